@@ -1,0 +1,97 @@
+/*
+ * Serial FP64 CPU oracle of one time step of the moist anelastic LES
+ * (Chammas et al., "Accelerating large-eddy simulations of clouds with
+ * Tensor Processing Units", Sec. 2).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header or table with the GPU library and the GPU library never calls it.
+ *
+ * Arrays are cell-centred, float64, index i + nx*(j + ny*k) (x fastest).
+ * Momentum inside the oracle is U = rho0*u as in the paper's conservation
+ * form; the interface exchanges primitive velocities.
+ */
+#ifndef LES_ORACLE_H
+#define LES_ORACLE_H
+#include <stdint.h>
+
+typedef struct ocfg {
+  int32_t nx, ny, nz, n_subiter;
+  int32_t poisson_scheme;      /* 0 = weighted Jacobi, 1 = Chebyshev-weighted Jacobi */
+  int32_t poisson_check_every; /* residual checked every m sweeps */
+  int32_t poisson_max_sweeps;
+  int32_t satadj_maxit;
+  double dx, dy, dz, dt;
+  double poisson_tol;          /* ||rhs - L phi||_2 <= tol * ||rhs||_2 */
+  double jacobi_omega;         /* 0 = closed-form optimum */
+  /* Table 1 */
+  double p00, theta0, Rd, Rv, cpd, cpv, cl, ci, Lv0, Ls0, Tf, fcor, g, cs, Pr, Sc;
+  /* forcing */
+  double ug, vg, shf, lhf, wsub_div, sponge_frac, sponge_max, rad_F0, rad_kappa;
+  /* saturation vapour pressure anchor and secant stopping */
+  double e_tr, T_tr, satadj_tol;
+} ocfg;
+
+typedef struct osolve {        /* one Poisson solve */
+  int32_t sweeps;              /* sweeps performed */
+  int32_t status;              /* 0 converged, 1 not converged, -3 non-finite */
+  double rhs_norm;             /* ||rhs||_2 after mean removal */
+  double res_norm;             /* ||rhs - L phi||_2 of the returned iterate */
+} osolve;
+
+/* Reference state (Sec. 2.1): p0, T0, rho0, alpha0 at cell centres. */
+int oracle_reference_state(const ocfg *c, double *p0, double *T0, double *rho0, double *alpha0);
+
+/* Pointwise thermodynamics (Sec. 2.1, 2.2). */
+double oracle_exner(const ocfg *c, double p0, double qt, double ql, double qi);
+double oracle_theta_l(const ocfg *c, double T, double ql, double qi, double qt, double p0);
+double oracle_qv_sat(const ocfg *c, double T, double p0);
+int oracle_satadj(const ocfg *c, double thl, double qt, double p0,
+                  double *T, double *ql, double *qi);
+/* Field thermodynamics: T, q_l, q_i, b (all optional except inputs). */
+int oracle_thermo(const ocfg *c, const double *thl, const double *qt,
+                  double *T, double *ql, double *qi, double *b);
+
+/* Operators (Sec. 2.3, 2.4, App. A).  Velocities primitive unless noted. */
+int oracle_sgs_nu(const ocfg *c, const double *u, const double *v, const double *w,
+                  const double *b, double *nu);
+int oracle_advect_quick(const ocfg *c, const double *U, const double *V, const double *W,
+                        const double *q, double zparity, double *out);
+int oracle_diffuse(const ocfg *c, const double *nu, double inv_prandtl,
+                   const double *q, double *out);
+int oracle_sgs_momentum(const ocfg *c, const double *nu, const double *u, const double *v,
+                        const double *w, double *fx, double *fy, double *fz);
+int oracle_laplacian(const ocfg *c, const double *phi, double *out);
+int oracle_app_a(const ocfg *c, const double *phi, double *out);
+int oracle_divergence(const ocfg *c, const double *U, const double *V, const double *W,
+                      double *out);
+int oracle_radiation(const ocfg *c, const double *ql, const double *cpm_pi, double *out);
+
+/* Poisson solve (Sec. 2.4): phi in = guess, out = zero-mean solution.
+ * fixed_sweeps > 0 performs exactly that many sweeps. */
+int oracle_poisson(const ocfg *c, const double *rhs, double *phi, int32_t fixed_sweeps,
+                   osolve *st);
+/* Closed-form extreme eigenvalues of -D^{-1} L on zero-mean fields. */
+int oracle_jacobi_bounds(const ocfg *c, double *mu_min, double *mu_max);
+
+/* Debug intermediates of the last sub-iteration of the last step (optional). */
+typedef struct odebug {
+  double *b_half;   /* buoyancy from the step-start scalars */
+  double *nu;       /* momentum viscosity of the last sub-iteration */
+  double *rhs;      /* Poisson right-hand side (mean removed) */
+  double *phi;      /* Poisson solution (zero mean) */
+  double *uhat, *vhat, *what; /* predicted primitive velocity */
+} odebug;
+
+/* nsteps time steps in place.  replay (nullable) gives per-solve sweep counts;
+ * rec (nullable) receives nsteps*n_subiter solve records. */
+int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, double *qt,
+                double *p, int32_t nsteps, const int32_t *replay, osolve *rec, odebug *dbg);
+
+/* Diagnostics: scalars[0..5] = sum rho0*thl*dV, sum rho0*qt*dV, ||div_c(rho0 u)||_2,
+ * max|div_c(rho0 u)|, max CFL, sum rho0*|u|^2/2*dV.  profiles (nullable) gets
+ * 9 x nz horizontal means: thl, qt, ql, u, v, w, w^2, w^3, b. */
+int oracle_diagnostics(const ocfg *c, const double *u, const double *v, const double *w,
+                       const double *thl, const double *qt, double *scalars, double *profiles);
+
+#endif

@@ -1,0 +1,636 @@
+"""Pins of the FP64 CPU oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: closed
+forms of the paper (Sec. 2.1 reference state, App. A stencil algebra),
+textbook special cases, invariants (Sec. 2.4 conservation claim), brute
+force (dense eigenvalues, bisection, FFT exact solves) and exact solutions of
+ODEs discretised by the same time scheme.  CPU only.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import les_inputs as li
+from conftest import load_table1
+
+
+def small(name="C1", **kw):
+    return li.workload(name, **kw)
+
+
+# ---------------------------------------------------------------- Table 1
+
+def test_table1_matches_paper(oracle_lib):
+    t1 = load_table1()
+    p = li.workload("C1")
+    for k, v in t1.items():
+        assert p[k] == pytest.approx(v, rel=0, abs=0), k
+    c = oracle_lib.make_cfg(p)
+    for k, v in t1.items():
+        assert getattr(c, k) == v
+
+
+# ------------------------------------------------------ P1 reference state
+
+def test_reference_state_closed_forms(oracle_lib):
+    """T0 = theta0 - g z / cpd exactly follows from the two closed forms;
+    rho0 = p0 / (Rd T0); dp0/dz = -rho0 g (hydrostatic balance)."""
+    p = small(nz=64, dz=20.0)
+    rs = oracle_lib.reference_state(p)
+    z = li.cell_heights(p)
+    np.testing.assert_allclose(rs["T0"], p["theta0"] - p["g"] * z / p["cpd"], rtol=1e-13)
+    np.testing.assert_allclose(rs["rho0"] * rs["alpha0"], 1.0, rtol=1e-14)
+    np.testing.assert_allclose(rs["rho0"], rs["p0"] / (p["Rd"] * rs["T0"]), rtol=1e-14)
+    # p0 at the surface limit equals p00 (extrapolate two levels linearly)
+    assert rs["p0"][0] < p["p00"]
+
+
+def test_reference_state_hydrostatic_second_order(oracle_lib):
+    errs = []
+    for dz in (40.0, 20.0, 10.0):
+        p = small(nz=int(1280 / dz), dz=dz)
+        rs = oracle_lib.reference_state(p)
+        dpdz = (rs["p0"][2:] - rs["p0"][:-2]) / (2 * dz)
+        resid = dpdz + rs["rho0"][1:-1] * p["g"]
+        errs.append(np.max(np.abs(resid)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.6 < r1 < 4.4 and 3.6 < r2 < 4.4, errs
+
+
+# ----------------------------------------------------- P2 thermodynamics
+
+def test_theta_l_dry_is_textbook_theta(oracle_lib):
+    p = small()
+    for T, p0 in [(300.0, 1.0e5), (285.0, 9.0e4), (260.0, 7.5e4)]:
+        th = oracle_lib.theta_l(p, T, 0.0, 0.0, 0.0, p0)
+        assert th == pytest.approx(T * (p["p00"] / p0) ** (p["Rd"] / p["cpd"]), rel=1e-14)
+        assert oracle_lib.exner(p, p0, 0.0, 0.0, 0.0) == pytest.approx(
+            (p0 / p["p00"]) ** (287.0 / 1004.5), rel=1e-14)
+
+
+def test_theta_l_liquid_lowers_theta(oracle_lib):
+    """Condensate lowers theta_l by about L q_l / (c_p Pi) (Sec. 2.1)."""
+    p = small()
+    T, p0, qt, ql = 285.0, 9.5e4, 0.01, 1e-3
+    th_dry = oracle_lib.theta_l(p, T, 0.0, 0.0, qt, p0)
+    th_wet = oracle_lib.theta_l(p, T, ql, 0.0, qt, p0)
+    approx = p["Lv0"] * ql / (p["cpd"] * (p0 / p["p00"]) ** 0.2857)
+    assert th_dry - th_wet == pytest.approx(approx, rel=0.03)
+
+
+def test_qv_sat_anchor_and_clausius_clapeyron(oracle_lib):
+    p = small()
+    eps = p["Rd"] / p["Rv"]
+
+    def e_of(T, p0):
+        q = oracle_lib.qv_sat(p, T, p0)
+        return q * p0 / (eps + (1 - eps) * q)
+
+    # triple-point anchor
+    assert e_of(273.16, 1e5) == pytest.approx(611.657, rel=1e-12)
+    # d ln e*/dT = L / (Rv T^2)
+    for T in (275.0, 290.0, 300.0):
+        h = 1e-3
+        slope = (math.log(e_of(T + h, 1e5)) - math.log(e_of(T - h, 1e5))) / (2 * h)
+        assert slope == pytest.approx(p["Lv0"] / (p["Rv"] * T * T), rel=1e-6)
+    # magnitude: saturation vapour pressure at 20 C is about 2.34 kPa
+    assert e_of(293.15, 1e5) == pytest.approx(2339.0, rel=0.02)
+
+
+# ------------------------------------------------ P3 saturation adjustment
+
+def test_satadj_round_trip_and_bisection(oracle_lib):
+    p = small()
+    rs_p = small(nz=130, dz=10.0)
+    p0s = oracle_lib.reference_state(rs_p)["p0"]
+    rng_T = np.linspace(270.0, 300.0, 13)
+    rng_q = np.linspace(0.0, 0.02, 11)
+    worst = 0.0
+    nsat = 0
+    for T in rng_T:
+        for p0 in p0s[::13]:
+            for qt in rng_q:
+                qc = max(0.0, qt - oracle_lib.qv_sat(p, T, p0))
+                ql = qc if T >= p["Tf"] else 0.0
+                qi = qc if T < p["Tf"] else 0.0
+                thl = oracle_lib.theta_l(p, T, ql, qi, qt, p0)
+                T2, ql2, qi2, it = oracle_lib.satadj(p, thl, qt, p0)
+                worst = max(worst, abs(T2 - T))
+                assert abs(ql2 - ql) <= 1e-11 and abs(qi2 - qi) <= 1e-11
+                if qc > 0 and T >= p["Tf"]:
+                    nsat += 1
+                    assert 1 <= it <= 20
+    assert nsat > 100
+    assert worst <= 1e-9, worst
+
+
+def test_satadj_matches_bisection(oracle_lib):
+    """Independent root finder on theta_l*(T) - theta_l (Sec. 2.2)."""
+    p = small()
+    p0 = 9.3e4
+    for thl, qt in [(289.0, 0.009), (289.0, 0.012), (292.0, 0.02), (289.0, 0.002)]:
+        def f(T):
+            qc = max(0.0, qt - oracle_lib.qv_sat(p, T, p0))
+            return oracle_lib.theta_l(p, T, qc, 0.0, qt, p0) - thl
+        lo, hi = 200.0, 350.0
+        assert f(lo) < 0 < f(hi)
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            if f(mid) < 0:
+                lo = mid
+            else:
+                hi = mid
+        T, ql, qi, _ = oracle_lib.satadj(p, thl, qt, p0)
+        assert T == pytest.approx(0.5 * (lo + hi), abs=1e-9)
+
+
+def test_cloud_layer_exists_in_stratocumulus_profile(oracle_lib):
+    """The mixed layer (289 K, 9 g/kg) saturates well below the inversion."""
+    p = small("C1m")
+    st = li.initial_state(p)
+    th = oracle_lib.thermo(p, st["thl"], st["qt"])
+    qlm = th["ql"].mean(axis=(1, 2))
+    z = li.cell_heights(p)
+    cloudy = z[qlm > 0]
+    assert cloudy.size > 0
+    assert 350.0 < cloudy.min() < 600.0 and cloudy.max() < 800.0
+    assert 4e-4 < qlm.max() < 1.2e-3
+    assert np.all(th["qi"] == 0.0)
+
+
+def test_buoyancy_zero_at_reference(oracle_lib):
+    p = small()
+    shape = (p["nz"], p["ny"], p["nx"])
+    th = oracle_lib.thermo(p, np.full(shape, p["theta0"]), np.zeros(shape))
+    assert np.all(th["b"] == 0.0)
+    rs = oracle_lib.reference_state(p)
+    np.testing.assert_allclose(th["T"][:, 0, 0], rs["T0"], rtol=1e-15)
+
+
+# ---------------------------------------------------- discrete operators
+
+def _modes(p, ax, m):
+    """Eigenfunction along one axis: periodic cos(2 pi m l / N) or, on the
+    mirror axis z, cos(pi m (l + 1/2) / N); returns (field, theta)."""
+    nx, ny, nz = p["nx"], p["ny"], p["nz"]
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    if ax == 0:
+        th = 2 * np.pi * m / nx
+        return np.cos(th * i), th
+    if ax == 1:
+        th = 2 * np.pi * m / ny
+        return np.cos(th * j), th
+    th = np.pi * m / nz
+    return np.cos(th * (k + 0.5)), th
+
+
+@pytest.mark.parametrize("ax", [0, 1, 2])
+def test_app_a_symbol(oracle_lib, ax):
+    """App. A: C = wide - compact has symbol (1 - cos theta)^2 / Delta^2;
+    the checkerboard gives 4 / Delta^2."""
+    p = small(nx=8, ny=12, nz=10, dx=40.0, dy=30.0, dz=10.0)
+    d = (p["dx"], p["dy"], p["dz"])[ax]
+    n = (p["nx"], p["ny"], p["nz"])[ax]
+    for m in range(0, n if ax == 2 else n // 2 + 1):
+        f, th = _modes(p, ax, m)
+        out = oracle_lib.app_a(p, f)
+        np.testing.assert_allclose(out, (1 - np.cos(th)) ** 2 / d ** 2 * f, atol=1e-14 / d ** 2)
+        lap = oracle_lib.laplacian(p, f)
+        np.testing.assert_allclose(lap, -(2 - 2 * np.cos(th)) / d ** 2 * f, atol=1e-14 / d ** 2)
+    if ax < 2:
+        f, th = _modes(p, ax, n // 2)
+        assert th == pytest.approx(np.pi)
+        np.testing.assert_allclose(oracle_lib.app_a(p, f), 4.0 / d ** 2 * f, atol=1e-14)
+
+
+def test_divergence_of_gradient_is_wide_laplacian(oracle_lib):
+    """div_c grad_c = compact Laplacian + C on periodic axes (App. A)."""
+    p = small(nx=8, ny=8, nz=8)
+    rng = np.random.default_rng(0)
+    f = rng.standard_normal((8, 8, 8))
+    f = np.repeat(f[:1], 8, axis=0)  # z-uniform: only periodic axes matter
+    gx = (np.roll(f, -1, 2) - np.roll(f, 1, 2)) / (2 * p["dx"])
+    gy = (np.roll(f, -1, 1) - np.roll(f, 1, 1)) / (2 * p["dy"])
+    wide = oracle_lib.divergence(p, gx, gy, np.zeros_like(f))
+    np.testing.assert_allclose(wide, oracle_lib.laplacian(p, f) + oracle_lib.app_a(p, f),
+                               atol=1e-16)
+
+
+def test_jacobi_bounds_brute_force(oracle_lib):
+    """Closed-form extreme eigenvalues of -D^{-1} L equal those of the dense
+    matrix assembled column by column from the oracle's Laplacian."""
+    for (nx, ny, nz) in [(4, 5, 4), (6, 4, 5)]:
+        p = small(nx=nx, ny=ny, nz=nz, dx=40.0, dy=35.0, dz=10.0)
+        n = nx * ny * nz
+        A = np.zeros((n, n))
+        for q in range(n):
+            e = np.zeros(n)
+            e[q] = 1.0
+            A[:, q] = oracle_lib.laplacian(p, e.reshape(nz, ny, nx)).ravel()
+        d = 2 / p["dx"] ** 2 + 2 / p["dy"] ** 2 + 2 / p["dz"] ** 2
+        ev = np.sort(np.linalg.eigvalsh(-A / d))
+        assert abs(ev[0]) < 1e-12 and ev[1] > 1e-6
+        lo, hi = oracle_lib.jacobi_bounds(p)
+        assert lo == pytest.approx(ev[1], rel=1e-10)
+        assert hi == pytest.approx(ev[-1], rel=1e-10)
+
+
+# ------------------------------------------------------ P7 Poisson exact
+
+def fft_poisson(p, rhs):
+    """Exact solution of the compact Laplacian with periodic x, y and
+    mirror-Neumann z: extend z symmetrically to 2 nz (half-sample), solve
+    mode by mode with eigenvalues -sum (2 - 2 cos theta) / Delta^2."""
+    nz = rhs.shape[0]
+    ext = np.concatenate([rhs, rhs[::-1]], axis=0)
+    F = np.fft.fftn(ext)
+    kz = 2 * np.pi * np.fft.fftfreq(2 * nz)
+    ky = 2 * np.pi * np.fft.fftfreq(rhs.shape[1])
+    kx = 2 * np.pi * np.fft.fftfreq(rhs.shape[2])
+    lam = -((2 - 2 * np.cos(kz))[:, None, None] / p["dz"] ** 2
+            + (2 - 2 * np.cos(ky))[None, :, None] / p["dy"] ** 2
+            + (2 - 2 * np.cos(kx))[None, None, :] / p["dx"] ** 2)
+    lam[0, 0, 0] = 1.0
+    F = F / lam
+    F[0, 0, 0] = 0.0
+    return np.real(np.fft.ifftn(F))[:nz]
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (10, 12, 16)])
+@pytest.mark.parametrize("scheme", ["jacobi", "chebyshev"])
+def test_poisson_matches_fft(oracle_lib, shape, scheme):
+    nz, ny, nx = shape
+    p = small(nx=nx, ny=ny, nz=nz, dx=40.0, dy=30.0, dz=10.0, poisson_tol=1e-12,
+              poisson_scheme=scheme)
+    rhs = li.random_field(shape, seed=11)
+    exact = fft_poisson(p, rhs)
+    phi, st = oracle_lib.poisson(p, rhs)
+    assert st["status"] == 0
+    assert st["res_norm"] <= 1e-12 * st["rhs_norm"]
+    np.testing.assert_allclose(phi, exact, atol=1e-10 * np.abs(exact).max())
+    assert abs(phi.mean()) < 1e-15 * np.abs(exact).max() * 10
+
+
+def test_poisson_fully_periodic_limit(oracle_lib):
+    """A z-uniform right-hand side reduces the problem to the 2D periodic one."""
+    p = small(nx=8, ny=8, nz=4, poisson_tol=1e-12)
+    r2 = li.random_field((1, 8, 8), seed=5)
+    rhs = np.repeat(r2, 4, axis=0)
+    phi, st = oracle_lib.poisson(p, rhs)
+    F = np.fft.fft2(r2[0])
+    ky = 2 * np.pi * np.fft.fftfreq(8)
+    lam = -((2 - 2 * np.cos(ky))[:, None] / p["dy"] ** 2 + (2 - 2 * np.cos(ky))[None, :] / p["dx"] ** 2)
+    lam[0, 0] = 1
+    F = F / lam
+    F[0, 0] = 0
+    exact = np.real(np.fft.ifft2(F))
+    for k in range(4):
+        np.testing.assert_allclose(phi[k], exact, atol=1e-10 * np.abs(exact).max())
+
+
+def test_chebyshev_needs_fewer_sweeps(oracle_lib):
+    shape = (16, 16, 16)
+    rhs = li.random_field(shape, seed=3)
+    base = dict(nx=16, ny=16, nz=16, poisson_tol=1e-8)
+    _, sj = oracle_lib.poisson(small(poisson_scheme="jacobi", **base), rhs)
+    _, sc = oracle_lib.poisson(small(poisson_scheme="chebyshev", **base), rhs)
+    assert sj["status"] == 0 and sc["status"] == 0
+    assert sc["sweeps"] * 4 < sj["sweeps"]
+
+
+def test_poisson_fixed_sweeps_and_zero_rhs(oracle_lib):
+    p = small(nx=8, ny=8, nz=8)
+    rhs = li.random_field((8, 8, 8), seed=2)
+    _, st = oracle_lib.poisson(p, rhs, fixed_sweeps=7)
+    assert st["sweeps"] == 7 and st["status"] == 1
+    phi, st = oracle_lib.poisson(p, np.zeros((8, 8, 8)), guess=np.full((8, 8, 8), 3.0))
+    assert st["sweeps"] == 0 and np.all(phi == 0.0)
+
+
+def test_poisson_not_converged_flag(oracle_lib):
+    p = small(nx=8, ny=8, nz=8, poisson_max_sweeps=1, poisson_check_every=1)
+    _, st = oracle_lib.poisson(p, li.random_field((8, 8, 8), seed=2))
+    assert st["status"] == 1 and st["sweeps"] == 1
+
+
+# ---------------------------------------------- P4 advection identities
+
+def test_quick_constant_field_divergence_free(oracle_lib):
+    """A constant scalar stays constant under a velocity whose central
+    divergence vanishes (w = 0, u = -d_c psi/dy, v = d_c psi/dx)."""
+    p = small(nx=12, ny=10, nz=8)
+    rs = oracle_lib.reference_state(p)
+    rng = np.random.default_rng(1)
+    psi = rng.standard_normal((8, 10, 12)) * 50.0
+    u = -(np.roll(psi, -1, 1) - np.roll(psi, 1, 1)) / (2 * p["dy"])
+    v = (np.roll(psi, -1, 2) - np.roll(psi, 1, 2)) / (2 * p["dx"])
+    r0 = rs["rho0"][:, None, None]
+    U, V, W = r0 * u, r0 * v, np.zeros_like(u)
+    assert np.abs(oracle_lib.divergence(p, U, V, W)).max() < 1e-13
+    out = oracle_lib.advect_quick(p, U, V, W, np.full_like(u, 290.0))
+    assert np.abs(out).max() < 1e-11 * 290.0 * np.abs(U).max() / p["dx"]
+
+
+def test_quick_flux_divergence_of_constant_equals_central_divergence(oracle_lib):
+    """Face mass flux = average of the two cells, so -div(U c) = -c div_c U
+    for any momentum field, including the wall rows."""
+    p = small(nx=8, ny=6, nz=7)
+    rng = np.random.default_rng(2)
+    U, V, W = (rng.standard_normal((7, 6, 8)) for _ in range(3))
+    out = oracle_lib.advect_quick(p, U, V, W, np.full((7, 6, 8), 3.0))
+    np.testing.assert_allclose(out, -3.0 * oracle_lib.divergence(p, U, V, W), atol=1e-13)
+
+
+def test_quick_upwind_coefficients(oracle_lib):
+    """1D check of the face value: for U > 0 the face value at i+1/2 is
+    (6 q_i + 3 q_{i+1} - q_{i-1}) / 8, reproducing quadratics exactly."""
+    p = small(nx=16, ny=4, nz=4, dx=1.0)
+    x = np.arange(16, dtype=float)
+    q = np.broadcast_to(0.3 * x ** 2 - x + 2.0, (4, 4, 16)).copy()
+    q[..., :2] = q[..., 2:4]  # keep the periodic seam out of the checked cells
+    U = np.ones((4, 4, 16))
+    out = oracle_lib.advect_quick(p, U, np.zeros_like(U), np.zeros_like(U), q)
+    face = lambda s: 0.3 * s ** 2 - s + 2.0
+    for i in range(4, 13):
+        expect = -(face(i + 0.5) - face(i - 0.5))
+        assert out[0, 0, i] == pytest.approx(expect, abs=1e-12)
+    out_neg = oracle_lib.advect_quick(p, -U, np.zeros_like(U), np.zeros_like(U), q)
+    for i in range(4, 13):
+        assert out_neg[0, 0, i] == pytest.approx(face(i + 0.5) - face(i - 0.5), abs=1e-12)
+
+
+# ------------------------------------------------------- P9 orders
+
+def test_diffusion_second_order(oracle_lib):
+    errs = []
+    for n in (8, 16, 32):
+        H = 400.0
+        p = small(nx=n, ny=n, nz=n, dx=1000.0 / n, dy=1000.0 / n, dz=H / n)
+        z = li.cell_heights(p)[:, None, None]
+        x = ((np.arange(n) + 0.5) * p["dx"])[None, None, :]
+        y = ((np.arange(n) + 0.5) * p["dy"])[None, :, None]
+        a, b, c = 2 * np.pi / 1000.0, 2 * np.pi / 1000.0, np.pi / H
+        q = np.sin(a * x) * np.sin(b * y) * np.cos(c * z)
+        nu = np.full(q.shape, 3.0)
+        out = oracle_lib.diffuse(p, nu, 1.0, q)
+        rs = oracle_lib.reference_state(p)
+        rho = rs["rho0"][:, None, None]
+        T0 = rs["T0"][:, None, None]
+        # d rho0 / dz from rho0 ~ T0^(cpd/Rd - 1), T0 = theta0 - g z / cpd
+        drho = rho * (p["cpd"] / p["Rd"] - 1.0) * (-p["g"] / p["cpd"]) / T0
+        lap = -(a * a + b * b + c * c) * q
+        dqdz = -c * np.sin(a * x) * np.sin(b * y) * np.sin(c * z)
+        exact = 3.0 * (rho * lap + drho * dqdz)
+        errs.append(np.abs(out - exact).max() / np.abs(exact).max())
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5, errs
+
+
+def test_advection_order_at_least_two(oracle_lib):
+    errs = []
+    for n in (16, 32, 64):
+        p = small(nx=n, ny=4, nz=4, dx=1.0 / n, dy=1.0, dz=1.0)
+        x = ((np.arange(n) + 0.5) / n)[None, None, :]
+        q = np.broadcast_to(np.sin(2 * np.pi * x), (4, 4, n)).copy()
+        U = np.full((4, 4, n), 2.0)
+        out = oracle_lib.advect_quick(p, U, 0 * U, 0 * U, q)
+        exact = -2.0 * 2 * np.pi * np.cos(2 * np.pi * x)
+        errs.append(np.abs(out - exact).max())
+    assert errs[0] / errs[1] > 3.6 and errs[1] / errs[2] > 3.6, errs
+
+
+# ------------------------------------------------ SGS viscosity pins
+
+def test_sgs_pure_shear(oracle_lib):
+    """u = s*y (periodic-safe in the interior rows): S = |s|, nu = (cs D)^2 |s|
+    for neutral stratification; f_B = 0 for Ri >= Pr."""
+    p = small(nx=6, ny=12, nz=6)
+    s = 0.01
+    y = (np.arange(12) * p["dy"])[None, :, None] * np.ones((6, 12, 6))
+    u = s * y
+    z0 = np.zeros_like(u)
+    nu = oracle_lib.sgs_nu(p, u, z0, z0, z0)
+    delta = (p["dx"] * p["dy"] * p["dz"]) ** (1 / 3)
+    # interior levels: the no-slip walls add strain in the first and last rows
+    np.testing.assert_allclose(nu[1:5, 2:10, :], (p["cs"] * delta) ** 2 * s, rtol=1e-13)
+    # stable stratification with N^2 = Pr S^2 / 2: f_B = sqrt(1/2)
+    zc = li.cell_heights(p)[:, None, None] * np.ones((6, 12, 6))
+    b = 0.5 * p["Pr"] * s * s * zc
+    nu2 = oracle_lib.sgs_nu(p, u, z0, z0, b)
+    np.testing.assert_allclose(nu2[1:5, 2:10, :], (p["cs"] * delta) ** 2 * s * np.sqrt(0.5), rtol=1e-12)
+    b3 = 2.0 * p["Pr"] * s * s * zc
+    nu3 = oracle_lib.sgs_nu(p, u, z0, z0, b3)
+    assert np.all(nu3[1:5, 2:10, :] == 0.0)
+
+
+def test_sgs_momentum_uniform_viscosity_is_laplacian(oracle_lib):
+    """For constant nu, rho0 and divergence-free periodic u, div(rho0 sigma)
+    = rho0 nu times the (wide/compact mixed) Laplacian; check for a single
+    Fourier mode u = sin(a y) where sigma reduces to the compact form."""
+    p = small(nx=8, ny=16, nz=6, g=0.0)
+    a = 2 * np.pi / 16
+    j = np.arange(16)[None, :, None] * np.ones((6, 16, 8))
+    u = np.sin(a * j)
+    z0 = np.zeros_like(u)
+    nu = np.full_like(u, 2.0)
+    fx, fy, fz = oracle_lib.sgs_momentum(p, nu, u, z0, z0)
+    rho = oracle_lib.reference_state(p)["rho0"]
+    assert np.allclose(rho, rho[0])
+    expect = rho[0] * 2.0 * (-(2 - 2 * np.cos(a)) / p["dy"] ** 2) * u
+    # interior levels (the no-slip walls add wall stress in the end rows)
+    np.testing.assert_allclose(fx[1:-1], expect[1:-1], atol=1e-14)
+    assert np.abs(fy[1:-1]).max() < 1e-14 and np.abs(fz[1:-1]).max() < 1e-14
+    # wall rows: extra drag -rho0 nu * 2 u / dz^2 from the mirrored ghost
+    np.testing.assert_allclose(fx[0], expect[0] - rho[0] * 2.0 * 2.0 * u[0] / p["dz"] ** 2,
+                               atol=1e-14)
+
+
+# ------------------------------------------------------ radiation
+
+def test_radiation_column_budget(oracle_lib):
+    """Integrated heating sum c_pm Pi * tend * dz telescopes to
+    F(bottom) - F(top) = F0 (exp(-kappa LWP) - 1)."""
+    p = small("C1m", nx=4, ny=4)
+    rs = oracle_lib.reference_state(p)
+    rng = np.random.default_rng(4)
+    ql = np.maximum(0, rng.standard_normal((p["nz"], 4, 4))) * 3e-4
+    cpmpi = 1000.0 + rng.random((p["nz"], 4, 4))
+    out = oracle_lib.radiation(p, ql, cpmpi)
+    lwp = (rs["rho0"][:, None, None] * ql * p["dz"]).sum(axis=0)
+    col = (out * cpmpi * p["dz"]).sum(axis=0)
+    np.testing.assert_allclose(col, p["rad_F0"] * (np.exp(-p["rad_kappa"] * lwp) - 1.0), rtol=1e-12)
+
+
+# --------------------------------------------- P5 / P6 / P11 full step
+
+def _random_velocity(p, state, amp=1.0, seed=9):
+    rng = np.random.default_rng(seed)
+    for k in ("u", "v", "w"):
+        state[k] = state[k] + amp * rng.standard_normal(state[k].shape)
+
+
+def _masses(p, state, oracle_lib):
+    d = oracle_lib.diagnostics(p, state)
+    return d["mass_thl"], d["mass_qt"]
+
+
+def test_scalar_conservation_full_step(oracle_lib):
+    """Sec. 2.4: domain integrals of scalars are conserved to machine
+    precision without non-conservative sources (no surface flux, radiation
+    or subsidence), whatever the velocity and viscosity."""
+    p = small("C1m", nx=12, ny=10, nz=16, shf=0.0, lhf=0.0, rad_F0=0.0,
+              poisson_tol=1e-6, poisson_scheme="chebyshev")
+    st = li.initial_state(p)
+    _random_velocity(p, st)
+    m0 = _masses(p, st, oracle_lib)
+    for _ in range(3):
+        oracle_lib.step(p, st, nsteps=1)
+        m1 = _masses(p, st, oracle_lib)
+        assert abs(m1[0] - m0[0]) <= 1e-14 * abs(m0[0]) * 4
+        assert abs(m1[1] - m0[1]) <= 1e-14 * abs(m0[1]) * 4
+    # and the state did change
+    assert np.abs(st["w"]).max() > 0.1
+
+
+def test_surface_flux_budget(oracle_lib):
+    p = small("C1m", nx=8, ny=8, nz=16, rad_F0=0.0, poisson_tol=1e-6,
+              poisson_scheme="chebyshev")
+    st = li.initial_state(p)
+    _random_velocity(p, st, amp=0.5)
+    m0 = _masses(p, st, oracle_lib)
+    oracle_lib.step(p, st, nsteps=2)
+    m1 = _masses(p, st, oracle_lib)
+    area = p["nx"] * p["dx"] * p["ny"] * p["dy"]
+    d_thl = 2 * p["dt"] * p["shf"] / p["cpd"] * area
+    d_qt = 2 * p["dt"] * p["lhf"] / p["Lv0"] * area
+    # exact up to round-off of the domain integral itself
+    assert abs((m1[0] - m0[0]) - d_thl) <= 1e-14 * 8 * abs(m0[0])
+    assert abs((m1[1] - m0[1]) - d_qt) <= 1e-14 * 8 * abs(m0[1])
+    assert d_thl > 1e4 * 1e-14 * abs(m0[0])
+
+
+def test_rest_state_is_bitwise_steady(oracle_lib):
+    p = small(nx=8, ny=8, nz=8, ug=0.0, vg=0.0, noise_thl=0.0, thl_ml=290.0, dthl_inv=0.0,
+              qt_ml=0.0, qt_ft=0.0)
+    p["z_inv"] = 1e9
+    st = li.initial_state(p)
+    ref = {k: v.copy() for k, v in st.items()}
+    recs, _ = oracle_lib.step(p, st, nsteps=3)
+    for k in st:
+        assert np.array_equal(st[k], ref[k]), k
+    assert all(r["sweeps"] == 0 for r in recs)
+
+
+# ---------------------------------------------- P10 single-column ODEs
+
+def _column_state(p, u, v):
+    st = li.initial_state(p)
+    st["u"][:] = u
+    st["v"][:] = v
+    st["thl"][:] = p["theta0"]
+    st["qt"][:] = 0.0
+    return st
+
+
+@pytest.mark.parametrize("K", [1, 2, 3])
+def test_inertial_oscillation(oracle_lib, K):
+    """c_s = 0, no sponge, horizontally uniform wind u - u_g: the scheme
+    reduces to dz/dt = -i f z for z = (u - u_g) + i (v - v_g).  Each step
+    multiplies z by the amplification factor of K predictor-corrector
+    sub-iterations, a(x) with a_1 = 1 + x, a_{k+1} = 1 + x (1 + a_k)/2,
+    x = -i f dt."""
+    p = small(nx=4, ny=4, nz=8, cs=0.0, sponge_max=0.0, noise_thl=0.0, n_subiter=K,
+              dt=600.0)
+    st = _column_state(p, p["ug"] + 3.0, p["vg"] - 1.0)
+    z0 = complex(3.0, -1.0)
+    x = -1j * p["fcor"] * p["dt"]
+    a = 1 + x
+    for _ in range(K - 1):
+        a = 1 + x * (1 + a) / 2
+    nsteps = 20
+    oracle_lib.step(p, st, nsteps=nsteps)
+    expect = z0 * a ** nsteps
+    got = (st["u"] - p["ug"]) + 1j * (st["v"] - p["vg"])
+    np.testing.assert_allclose(got, expect, rtol=1e-12)
+    assert np.abs(st["w"]).max() == 0.0
+
+
+def test_inertial_period_converges(oracle_lib):
+    """With small f dt the oscillation has period 2 pi / f."""
+    p = small(nx=4, ny=4, nz=4, cs=0.0, sponge_max=0.0, noise_thl=0.0, dt=60.0)
+    st = _column_state(p, p["ug"] + 1.0, p["vg"])
+    period = 2 * np.pi / p["fcor"]
+    n = int(round(period / p["dt"]))
+    oracle_lib.step(p, st, nsteps=n)
+    assert st["u"][0, 0, 0] - p["ug"] == pytest.approx(1.0, abs=2e-2)
+    assert abs(st["v"][0, 0, 0] - p["vg"]) < 2e-2
+
+
+def test_sponge_decay(oracle_lib):
+    """f = 0: a horizontally uniform wind anomaly relaxes at rate beta(z);
+    amplification per step with K = 2 is 1 - h + h^2/2, h = beta dt."""
+    p = small(nx=4, ny=4, nz=40, cs=0.0, fcor=0.0, noise_thl=0.0, sponge_frac=0.2)
+    st = _column_state(p, p["ug"] + 2.0, p["vg"] + 1.0)
+    oracle_lib.step(p, st, nsteps=5)
+    z = li.cell_heights(p)
+    H = p["nz"] * p["dz"]
+    zs = 0.8 * H
+    beta = np.where(z >= zs, p["sponge_max"] * np.sin(0.5 * np.pi * (z - zs) / (H - zs)) ** 2, 0.0)
+    h = beta * p["dt"]
+    amp = (1 - h + h * h / 2) ** 5
+    np.testing.assert_allclose(st["u"][:, 0, 0] - p["ug"], 2.0 * amp, rtol=1e-12)
+    np.testing.assert_allclose(st["v"][:, 0, 0] - p["vg"], 1.0 * amp, rtol=1e-12)
+    assert beta[-1] > 0.24 and beta[0] == 0.0
+
+
+# ---------------------------------------------- projection behaviour (R16)
+
+def test_divergence_falls_with_subiterations(oracle_lib):
+    """Post-projection central divergence drops as K grows (the lagged App. A
+    correction converges).  The paper gives no threshold: parity unpinned."""
+    divs = []
+    for K in (1, 2, 4):
+        p = small(nx=12, ny=12, nz=12, n_subiter=K, poisson_tol=1e-10,
+                  poisson_scheme="chebyshev")
+        st = li.initial_state(p)
+        _random_velocity(p, st, amp=0.5, seed=3)
+        oracle_lib.step(p, st, nsteps=1)
+        divs.append(oracle_lib.diagnostics(p, st)["div_l2"])
+    assert divs[1] < divs[0] and divs[2] < divs[1], divs
+
+
+def test_hydrostatic_adjustment_sign(oracle_lib):
+    """A horizontally uniform buoyancy at rest is balanced by the pressure
+    perturbation: rho0 d_c(alpha0 p')/dz = rho0 b in the interior (Sec. 2.1
+    momentum equation), so p' increases with height where b > 0.  A wrong
+    sign of buoyancy or of the pressure-gradient term gives ratio -1."""
+    p = small(nx=4, ny=4, nz=32, n_subiter=8, noise_thl=0.0, ug=0.0, vg=0.0, cs=0.0,
+              poisson_tol=1e-12, poisson_scheme="chebyshev")
+    st = li.initial_state(p)
+    rs = oracle_lib.reference_state(p)
+    oracle_lib.step(p, st, nsteps=2)
+    b = oracle_lib.thermo(p, st["thl"], st["qt"])["b"][:, 0, 0]
+    assert b.min() > 0.01
+    psi = rs["alpha0"] * st["p"][:, 0, 0]
+    ratio = (psi[2:] - psi[:-2]) / (2 * p["dz"]) / b[1:-1]
+    assert abs(ratio.mean() - 1.0) < 0.02
+    assert np.all((ratio > 0.85) & (ratio < 1.15))
+    assert np.abs(st["w"]).max() < 0.01
+
+
+def test_radiation_cools_column(oracle_lib):
+    """Radiative flux divergence (Sec. 2.1 theta_l equation) removes
+    F0 (1 - exp(-kappa LWP)) / (c_pm Pi) per unit area and time."""
+    p = small("C1m", nx=4, ny=4, ug=0.0, vg=0.0, shf=0.0, lhf=0.0, noise_thl=0.0,
+              noise_qt=0.0, cs=0.0, poisson_tol=1e-8, poisson_scheme="chebyshev")
+    st = li.initial_state(p)
+    m0 = oracle_lib.diagnostics(p, st)["mass_thl"]
+    th = oracle_lib.thermo(p, st["thl"], st["qt"])
+    oracle_lib.step(p, st, nsteps=1)
+    m1 = oracle_lib.diagnostics(p, st)["mass_thl"]
+    rs = oracle_lib.reference_state(p)
+    lwp = rs["rho0"] @ th["ql"][:, 0, 0] * p["dz"]
+    assert lwp > 0.05
+    area = p["nx"] * p["dx"] * p["ny"] * p["dy"]
+    expect = p["dt"] * p["rad_F0"] * (np.exp(-p["rad_kappa"] * lwp) - 1) / p["cpd"] * area
+    assert 0.95 < (m1 - m0) / expect < 1.05

@@ -1,0 +1,183 @@
+/*
+ * les.h — C ABI of the MI355X (gfx950) moist anelastic LES time step.
+ *
+ * Implements one time step of the anelastic moist LES of Chammas et al.,
+ * "Accelerating large-eddy simulations of clouds with Tensor Processing
+ * Units" (arXiv 2301.04698), Sec. 2: saturation adjustment (Sec. 2.2),
+ * Smagorinsky-Lilly subgrid model (Sec. 2.3), QUICK advection, central
+ * diffusion, the iterative predictor-corrector time scheme and the
+ * pressure-correction Poisson equation solved by weighted-Jacobi sweeps
+ * with the collocated-grid correction of App. A (Sec. 2.4).
+ *
+ * Conventions shared by every entry point:
+ *  - Fields are cell-centred arrays of nx*ny*nz elements in DEVICE memory,
+ *    index i + nx*(j + ny*k) (x fastest, z slowest), element type double
+ *    for LES_FP64 and float for LES_FP32.  x and y are periodic; z has
+ *    rigid walls at z = 0 and z = nz*dz.
+ *  - The library allocates no device memory.  The caller owns the
+ *    prognostic fields and one workspace of les_workspace_bytes() bytes;
+ *    the handle owns host metadata, a small pinned host buffer and events.
+ *  - Every call is ordered on the HIP stream given to les_init.  Calls that
+ *    return host statistics synchronize that stream before returning.
+ *  - Return codes: LES_OK (0), LES_WARN_NOT_CONVERGED (1: a Poisson solve
+ *    hit its sweep cap; the best iterate is kept and the step goes on), or a
+ *    negative error: LES_ERR_ARG (invalid argument, nothing launched),
+ *    LES_ERR_HIP (a HIP call failed), LES_ERR_NONFINITE (NaN/Inf found by a
+ *    norm), LES_ERR_STATE (handle unusable).  les_last_error() returns a
+ *    thread-local message describing the last failure.
+ *  - Errors leave the caller's buffers in an unspecified state.
+ */
+#ifndef LES_H
+#define LES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LES_OK = 0,
+  LES_WARN_NOT_CONVERGED = 1,
+  LES_ERR_ARG = -1,
+  LES_ERR_HIP = -2,
+  LES_ERR_NONFINITE = -3,
+  LES_ERR_STATE = -4
+};
+
+enum { LES_FP64 = 0, LES_FP32 = 1 };          /* storage / stencil precision */
+enum { LES_JACOBI = 0, LES_CHEBYSHEV = 1 };   /* Poisson sweep weighting */
+
+/* Run configuration.  Grid sizes >= 4 in every direction.
+ * Table 1 constants of the paper and forcing parameters are explicit so the
+ * caller states every value (les_default_config fills Table 1). */
+typedef struct les_config {
+  int32_t nx, ny, nz;
+  int32_t precision;            /* LES_FP64 or LES_FP32 */
+  int32_t n_subiter;            /* predictor-corrector sub-iterations K >= 1 */
+  int32_t poisson_scheme;       /* LES_JACOBI (fixed weight) or LES_CHEBYSHEV */
+  int32_t poisson_check_every;  /* residual checked every m sweeps, m >= 1 */
+  int32_t poisson_max_sweeps;   /* cap per solve */
+  int32_t satadj_maxit;         /* secant iteration cap */
+  int32_t reserved0;
+  double dx, dy, dz, dt;        /* m, m, m, s; all > 0 */
+  double poisson_tol;           /* stop when ||rhs - L phi||_2 <= tol ||rhs||_2 */
+  double jacobi_omega;          /* 0 selects 2/(mu_min+mu_max) */
+  /* Table 1 */
+  double p00, theta0, Rd, Rv, cpd, cpv, cl, ci, Lv0, Ls0, Tf, fcor, g, cs, Pr, Sc;
+  /* forcing: geostrophic wind, surface sensible/latent flux (W m^-2),
+   * large-scale divergence (w_sub = D z, downward), sponge fraction and top
+   * rate (s^-1), synthetic longwave flux F0 (W m^-2) and absorption
+   * coefficient (m^2 kg^-1) */
+  double ug, vg, shf, lhf, wsub_div, sponge_frac, sponge_max, rad_F0, rad_kappa;
+  /* saturation vapour pressure anchor (Pa, K) and secant tolerance (K) */
+  double e_tr, T_tr, satadj_tol;
+} les_config;
+
+/* Caller-owned device buffers.  u, v, w: velocity (m/s); thl: liquid-ice
+ * potential temperature (K) stored at the half step; qt: total water
+ * specific humidity (kg/kg) at the half step; p: pressure perturbation p'
+ * (Pa).  workspace: at least les_workspace_bytes(cfg) bytes, 256-byte
+ * aligned, not shared with another handle. */
+typedef struct les_buffers {
+  void *u, *v, *w, *thl, *qt, *p;
+  void *workspace;
+  size_t workspace_bytes;
+} les_buffers;
+
+typedef struct les_handle les_handle;
+
+/* One Poisson solve. */
+typedef struct les_solve_stats {
+  int32_t sweeps;     /* sweeps applied to reach the returned iterate */
+  int32_t status;     /* 0 converged, 1 sweep cap reached, -3 non-finite */
+  double rhs_norm;    /* ||rhs||_2 after mean removal (FP64) */
+  double res_norm;    /* ||rhs - L phi||_2 of the returned iterate (FP64) */
+  double seconds;     /* device time of the solve (HIP events) */
+} les_solve_stats;
+
+typedef struct les_poisson_opts {
+  int32_t fixed_sweeps;  /* > 0: apply exactly this many sweeps */
+  int32_t use_guess;     /* 1: phi holds the initial guess; 0: start from 0 */
+} les_poisson_opts;
+
+/* Optional per-call controls of les_step. */
+typedef struct les_step_opts {
+  const int32_t *replay_sweeps; /* host, nsteps*n_subiter entries or NULL:
+                                   per-solve sweep counts to apply exactly */
+  les_solve_stats *records;     /* host, nsteps*n_subiter entries or NULL */
+} les_step_opts;
+
+typedef struct les_step_stats {
+  int32_t steps, solves;
+  int64_t sweeps_total;
+  int32_t sweeps_max;
+  int32_t not_converged;        /* solves that hit the cap */
+  double res_rel_max;           /* max over solves of res_norm / rhs_norm */
+  double seconds;               /* device time of the whole call */
+  double poisson_seconds;       /* device time inside the solves */
+} les_step_stats;
+
+typedef struct les_diag {
+  double mass_thl;   /* sum rho0 thl dV  (kg K) */
+  double mass_qt;    /* sum rho0 qt dV   (kg) */
+  double div_l2;     /* ||div_c(rho0 u)||_2 */
+  double div_max;    /* max |div_c(rho0 u)| */
+  double cfl;        /* max (|u| dt/dx + |v| dt/dy + |w| dt/dz) */
+  double ke;         /* sum rho0 |u|^2 / 2 dV (J) */
+} les_diag;
+
+#define LES_NPROFILES 9  /* thl, qt, ql, u, v, w, w^2, w^3, b (horizontal means) */
+
+/* Fills Table 1 of the paper and defaults for the rest (a 32^3 grid). */
+void les_default_config(les_config *cfg);
+
+/* Bytes of workspace needed for cfg (0 if cfg is invalid). */
+size_t les_workspace_bytes(const les_config *cfg);
+
+/* Byte offset inside the workspace of an intermediate field (debug and
+ * tests); returns LES_ERR_ARG for an unknown field id.  Field ids:
+ * 0 u^n, 1 v^n, 2 w^n, 3 thl^{n+1/2}, 4 qt^{n+1/2}, 5 thl_mid, 6 qt_mid,
+ * 7..9 u,v,w at n+1/2, 10 b^{n+1/2}, 11 b_mid, 12 ql_mid, 13 c_pm*Pi (mid),
+ * 14 nu scalars, 15 nu momentum, 16 radiative heating, 17 Poisson rhs,
+ * 18 phi buffer 0, 19 phi buffer 1. */
+int les_workspace_offset(const les_config *cfg, int32_t field, size_t *offset);
+
+/* Validates cfg and buffers, computes the reference state (Sec. 2.1) and
+ * uploads it into the workspace.  The prognostic fields are read, never
+ * written, by les_init: the caller fills them with the initial state. */
+int les_init(const les_config *cfg, const les_buffers *bufs, void *hip_stream,
+             les_handle **out);
+
+/* Advances the state in the caller's buffers by nsteps time steps
+ * (Sec. 2.4).  opts and stats may be NULL.  Synchronizes the stream. */
+int les_step(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step_stats *stats);
+
+/* Solves L phi = rhs (compact 7-point Laplacian, periodic x/y, Neumann z;
+ * the pressure-correction equation of Sec. 2.4) by the configured sweeps.
+ * rhs: device, n elements, read only (its mean is removed internally).
+ * phi: device, n elements; in = guess if opts->use_guess, out = zero-mean
+ * solution.  Uses the handle's workspace.  Synchronizes the stream. */
+int les_poisson_solve(les_handle *h, const void *rhs, void *phi, const les_poisson_opts *opts,
+                      les_solve_stats *stats);
+
+/* Thermodynamic state of arbitrary fields (Sec. 2.1-2.2): temperature T,
+ * liquid water q_l and buoyancy b from thl, qt at the handle's levels.
+ * Device arrays of n elements; outputs may be NULL. */
+int les_thermo(les_handle *h, const void *thl, const void *qt, void *T, void *ql, void *b);
+
+/* Diagnostics of the current state: scalars into *out (host) and, if
+ * profiles is non-NULL, LES_NPROFILES x nz horizontal means (host, FP64,
+ * profile-major).  FP64 reductions.  Synchronizes the stream. */
+int les_diagnostics(les_handle *h, les_diag *out, double *profiles);
+
+void les_destroy(les_handle *h);
+
+const char *les_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LES_H */

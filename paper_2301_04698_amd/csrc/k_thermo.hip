@@ -1,0 +1,186 @@
+// Per-cell moist thermodynamics (paper Sec. 2.1-2.2) and the radiative
+// flux column (Sec. 2.1, theta_l equation).  The saturation adjustment
+// always iterates in FP64, whatever the storage precision.
+#include "les_device.h"
+
+namespace lesmi {
+
+namespace {
+
+// Saturation specific humidity: Clausius-Clapeyron with constant L_v0
+// anchored at the triple point (the paper cites the formula's source
+// without printing it); q = eps e / (p0 - (1 - eps) e).
+__device__ __forceinline__ double qsat(const Thermo &c, double T, double p0) {
+  const double e = c.e_tr * exp(c.Lv_over_Rv * (c.inv_Ttr - 1.0 / T));
+  return c.eps * e / (p0 - (1.0 - c.eps) * e);
+}
+
+struct Phase {
+  double ql, qi;
+};
+
+__device__ __forceinline__ Phase partition(const Thermo &c, double T, double qt, double p0) {
+  const double qc = fmax(0.0, qt - qsat(c, T, p0));
+  return T >= c.Tf ? Phase{qc, 0.0} : Phase{0.0, qc};
+}
+
+__device__ __forceinline__ double cp_moist(const Thermo &c, double qt, double ql, double qi) {
+  return (1.0 - qt) * c.cpd + (qt - ql - qi) * c.cpv + ql * c.cl + qi * c.ci;
+}
+
+__device__ __forceinline__ double r_moist(const Thermo &c, double qt, double ql, double qi) {
+  return (1.0 - qt) * c.Rd + (qt - ql - qi) * c.Rv;
+}
+
+// Exner function (p0/p00)^(R_m/c_pm) evaluated as exp(R_m/c_pm * ln(p0/p00)).
+__device__ __forceinline__ double exner(const Thermo &c, double lnp, double qt, double ql,
+                                        double qi) {
+  return exp(r_moist(c, qt, ql, qi) / cp_moist(c, qt, ql, qi) * lnp);
+}
+
+// theta_l*(T) - theta_l at saturation partition.
+__device__ __forceinline__ double thl_residual(const Thermo &c, double T, double thl, double qt,
+                                               double p0, double lnp) {
+  const Phase ph = partition(c, T, qt, p0);
+  const double cpm = cp_moist(c, qt, ph.ql, ph.qi);
+  const double pi = exner(c, lnp, qt, ph.ql, ph.qi);
+  return T / pi * (1.0 - (c.Lv0 * ph.ql + c.Ls0 * ph.qi) / (cpm * T)) - thl;
+}
+
+struct CellState {
+  double T, ql, qi;
+};
+
+// Saturation adjustment by the secant method (Sec. 2.2).  Unsaturated test
+// first; otherwise secant from T_u and T_u + L_v0 (q_t - q_v*(T_u)) / c_pd,
+// stopping at |dT| <= tol, equal residuals or the iteration cap.
+__device__ CellState saturation_adjust(const Thermo &c, double thl, double qt, double p0,
+                                       double lnp) {
+  const double tu = thl * exner(c, lnp, qt, 0.0, 0.0);
+  const double qs = qsat(c, tu, p0);
+  if (qt <= qs) return CellState{tu, 0.0, 0.0};
+  double ta = tu, tb = tu + c.Lv0 * (qt - qs) / c.cpd;
+  double fa = thl_residual(c, ta, thl, qt, p0, lnp);
+  double fb = thl_residual(c, tb, thl, qt, p0, lnp);
+  for (int it = 0; it < c.satadj_maxit; ++it) {
+    if (fb == fa) break;
+    const double tn = tb - fb * (tb - ta) / (fb - fa);
+    ta = tb;
+    fa = fb;
+    tb = tn;
+    fb = thl_residual(c, tb, thl, qt, p0, lnp);
+    if (fabs(tb - ta) <= c.satadj_tol) break;
+  }
+  const Phase ph = partition(c, tb, qt, p0);
+  return CellState{tb, ph.ql, ph.qi};
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void thermo_kernel(Grid g, Thermo c, Profiles<T> P,
+                                                        const T *__restrict__ thl_a,
+                                                        const T *__restrict__ qt_a,
+                                                        const T *__restrict__ thl_b,
+                                                        const T *__restrict__ qt_b,
+                                                        T *__restrict__ thl_mid,
+                                                        T *__restrict__ qt_mid, T *__restrict__ b,
+                                                        T *__restrict__ ql, T *__restrict__ cpmpi,
+                                                        T *__restrict__ Tout) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.n) return;
+  const int k = (int)(q / g.nxy);
+  T th = thl_a[q], qw = qt_a[q];
+  if (thl_b) {
+    // state midway between sub-iterate k and the step-start scalars
+    th = T(0.5) * (th + thl_b[q]);
+    qw = T(0.5) * (qw + qt_b[q]);
+    if (thl_mid) thl_mid[q] = th;
+    if (qt_mid) qt_mid[q] = qw;
+  }
+  const double p0 = P.p0[k], lnp = P.lnp[k], a0 = P.alpha0[k];
+  const double qtd = (double)qw;
+  const CellState s = saturation_adjust(c, (double)th, qtd, p0, lnp);
+  if (b) {
+    const double alpha = r_moist(c, qtd, s.ql, s.qi) * s.T / p0;
+    b[q] = (T)(c.g * (alpha - a0) / a0);
+  }
+  if (ql) ql[q] = (T)s.ql;
+  if (cpmpi) cpmpi[q] = (T)(cp_moist(c, qtd, s.ql, s.qi) * exner(c, lnp, qtd, s.ql, s.qi));
+  if (Tout) Tout[q] = (T)s.T;
+}
+
+// One thread per (i, j) column, marching down from the lid: net upward
+// flux F(z_f) = F0 exp(-kappa * sum_{cells above} rho0 q_l dz) and the
+// heating -(c_pm Pi)^{-1} dF/dz of each cell.  Consecutive threads take
+// consecutive x, so every level is a coalesced row access.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void radiation_kernel(Grid g, Profiles<T> P, double F0,
+                                                           double kappa, const T *__restrict__ ql,
+                                                           const T *__restrict__ cpmpi,
+                                                           T *__restrict__ out) {
+  const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= g.nxy) return;
+  double path = 0.0;
+  double f_above = F0;
+  for (int k = g.nz - 1; k >= 0; --k) {
+    const int64_t q = col + g.nxy * k;
+    path += P.rho0[k] * (double)ql[q] * g.dz;
+    const double f_below = F0 * exp(-kappa * path);
+    out[q] = (T)(-(f_above - f_below) / (g.dz * (double)cpmpi[q]));
+    f_above = f_below;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void average_kernel(int64_t n, const T *__restrict__ a0,
+                                                         const T *__restrict__ b0,
+                                                         T *__restrict__ o0,
+                                                         const T *__restrict__ a1,
+                                                         const T *__restrict__ b1,
+                                                         T *__restrict__ o1,
+                                                         const T *__restrict__ a2,
+                                                         const T *__restrict__ b2,
+                                                         T *__restrict__ o2) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  o0[q] = T(0.5) * (a0[q] + b0[q]);
+  o1[q] = T(0.5) * (a1[q] + b1[q]);
+  o2[q] = T(0.5) * (a2[q] + b2[q]);
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+template <typename T>
+void launch_thermo(const Grid &g, const Thermo &c, const Profiles<T> &P, const T *thl_a,
+                   const T *qt_a, const T *thl_b, const T *qt_b, T *thl_mid, T *qt_mid, T *b,
+                   T *ql, T *cpmpi, T *Tout, hipStream_t s) {
+  thermo_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g, c, P, thl_a, qt_a, thl_b, qt_b, thl_mid,
+                                                        qt_mid, b, ql, cpmpi, Tout);
+}
+
+template <typename T>
+void launch_radiation(const Grid &g, const Profiles<T> &P, double F0, double kappa, const T *ql,
+                      const T *cpmpi, T *out, hipStream_t s) {
+  radiation_kernel<T><<<blocks_for(g.nxy), kBlock, 0, s>>>(g, P, F0, kappa, ql, cpmpi, out);
+}
+
+template <typename T>
+void launch_average(const Grid &g, const T *a0, const T *b0, T *o0, const T *a1, const T *b1, T *o1,
+                    const T *a2, const T *b2, T *o2, hipStream_t s) {
+  average_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g.n, a0, b0, o0, a1, b1, o1, a2, b2, o2);
+}
+
+#define LES_INST(T)                                                                             \
+  template void launch_thermo<T>(const Grid &, const Thermo &, const Profiles<T> &, const T *,  \
+                                 const T *, const T *, const T *, T *, T *, T *, T *, T *, T *, \
+                                 hipStream_t);                                                  \
+  template void launch_radiation<T>(const Grid &, const Profiles<T> &, double, double, const T *, \
+                                    const T *, T *, hipStream_t);                               \
+  template void launch_average<T>(const Grid &, const T *, const T *, T *, const T *, const T *, \
+                                  T *, const T *, const T *, T *, hipStream_t);
+LES_INST(float)
+LES_INST(double)
+#undef LES_INST
+
+}  // namespace lesmi

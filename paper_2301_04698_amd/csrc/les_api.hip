@@ -1,0 +1,704 @@
+// C ABI of the LES library (include/les.h): validation, workspace layout,
+// reference state, and the stream-ordered orchestration of one time step
+// of the paper's iterative predictor-corrector scheme (Sec. 2.4).
+#include "../../include/les.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "les_internal.h"
+
+using namespace lesmi;
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(LES_ERR_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),   \
+                  __FILE__, __LINE__);                                                   \
+  } while (0)
+
+#define LAUNCH_TRY()                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = hipGetLastError();                                                   \
+    if (e_ != hipSuccess)                                                                \
+      return fail(LES_ERR_HIP, "kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), \
+                  __FILE__, __LINE__);                                                   \
+  } while (0)
+
+// Workspace fields (ids documented in les.h).
+enum Field {
+  F_UN = 0, F_VN, F_WN, F_THL_H, F_QT_H, F_THL_M, F_QT_M, F_UH, F_VH, F_WH,
+  F_B_H, F_B_M, F_QL_M, F_CPMPI_M, F_NU_S, F_NU_M, F_RAD, F_RHS, F_PHI0, F_PHI1,
+  F_COUNT
+};
+
+constexpr size_t kAlign = 256;
+constexpr int kPartialCap = kPartials + 1024;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t field[F_COUNT];
+  size_t prof_d;    // 4 x nz doubles: p0, lnp, alpha0, rho0
+  size_t prof_t;    // 4 x nz elems: rho0, alpha0, beta, wsub
+  size_t partials;  // kPartialCap doubles
+  size_t ctl;       // SolveCtl
+  size_t diag;      // nz x kDiagStride doubles
+  size_t total;
+};
+
+int validate(const les_config *c) {
+  if (!c) return fail(LES_ERR_ARG, "config is NULL");
+  if (c->nx < 4 || c->ny < 4 || c->nz < 4)
+    return fail(LES_ERR_ARG, "grid %dx%dx%d: every size must be >= 4", c->nx, c->ny, c->nz);
+  if ((int64_t)c->nx * c->ny > (int64_t)1 << 30 || (int64_t)c->nx * c->ny * c->nz > (int64_t)1 << 34)
+    return fail(LES_ERR_ARG, "grid too large");
+  if (!(c->dx > 0) || !(c->dy > 0) || !(c->dz > 0) || !(c->dt > 0))
+    return fail(LES_ERR_ARG, "dx, dy, dz, dt must be > 0");
+  if (c->precision != LES_FP64 && c->precision != LES_FP32)
+    return fail(LES_ERR_ARG, "precision must be LES_FP64 or LES_FP32");
+  if (c->n_subiter < 1 || c->n_subiter > 64) return fail(LES_ERR_ARG, "n_subiter must be in [1, 64]");
+  if (c->poisson_scheme != LES_JACOBI && c->poisson_scheme != LES_CHEBYSHEV)
+    return fail(LES_ERR_ARG, "unknown poisson_scheme %d", c->poisson_scheme);
+  if (c->poisson_check_every < 1) return fail(LES_ERR_ARG, "poisson_check_every must be >= 1");
+  if (c->poisson_max_sweeps < 1 || c->poisson_max_sweeps > 1000000000)
+    return fail(LES_ERR_ARG, "poisson_max_sweeps out of range");
+  if (!(c->poisson_tol > 0)) return fail(LES_ERR_ARG, "poisson_tol must be > 0");
+  if (!(c->jacobi_omega >= 0) || c->jacobi_omega >= 2)
+    return fail(LES_ERR_ARG, "jacobi_omega must be in [0, 2)");
+  if (c->satadj_maxit < 0 || c->satadj_maxit > 1000) return fail(LES_ERR_ARG, "satadj_maxit out of range");
+  if (!(c->p00 > 0) || !(c->theta0 > 0) || !(c->Rd > 0) || !(c->Rv > 0) || !(c->cpd > 0))
+    return fail(LES_ERR_ARG, "thermodynamic constants must be > 0");
+  const double top = c->nz * c->dz;
+  if (!(1.0 - c->g * top / (c->cpd * c->theta0) > 0))
+    return fail(LES_ERR_ARG, "domain top above the adiabatic atmosphere's height");
+  if (c->sponge_frac < 0 || c->sponge_frac > 1) return fail(LES_ERR_ARG, "sponge_frac must be in [0, 1]");
+  return LES_OK;
+}
+
+size_t elem_size(const les_config *c) { return c->precision == LES_FP64 ? 8 : 4; }
+
+Layout layout_of(const les_config *c) {
+  Layout L;
+  const size_t n = (size_t)c->nx * c->ny * c->nz;
+  const size_t es = elem_size(c);
+  size_t off = 0;
+  for (int f = 0; f < F_COUNT; ++f) {
+    L.field[f] = off;
+    off = align_up(off + n * es);
+  }
+  L.prof_d = off;
+  off = align_up(off + 4 * (size_t)c->nz * sizeof(double));
+  L.prof_t = off;
+  off = align_up(off + 4 * (size_t)c->nz * es);
+  L.partials = off;
+  off = align_up(off + kPartialCap * sizeof(double));
+  L.ctl = off;
+  off = align_up(off + sizeof(SolveCtl));
+  L.diag = off;
+  off = align_up(off + (size_t)c->nz * kDiagStride * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+// Small host-visible status of a solve written by the device when it stops.
+struct HostFlag {
+  int32_t done;
+  int32_t pad[15];
+};
+
+}  // namespace
+
+struct les_handle {
+  les_config cfg;
+  les_buffers buf;
+  hipStream_t stream;
+  Layout lay;
+  Grid grid;
+  Thermo thermo;
+  double mu_min, mu_max;
+  SolveCtl *ctl_host;  // pinned mirror for the final read-back
+  double *diag_host;   // pinned, nz x kDiagStride
+  hipEvent_t ev_a, ev_b, ev_s0, ev_s1;
+  std::vector<hipEvent_t> ev_check;
+  bool broken;
+};
+
+namespace {
+
+char *ws(const les_handle *h, size_t off) { return (char *)h->buf.workspace + off; }
+
+// Extreme nonzero eigenvalues of -D^{-1} L (compact Laplacian, periodic x/y,
+// mirror-Neumann z): sums of (2 - 2 cos theta)/Delta^2 per axis over D.
+void jacobi_spectrum(const les_config *c, double *lo, double *hi) {
+  const double pi = 3.14159265358979323846;
+  const double ax = 1.0 / (c->dx * c->dx), ay = 1.0 / (c->dy * c->dy), az = 1.0 / (c->dz * c->dz);
+  const double D = 2.0 * (ax + ay + az);
+  auto per = [&](int n, int m) { return 2.0 - 2.0 * std::cos(2.0 * pi * m / n); };
+  auto mir = [&](int n, int m) { return 2.0 - 2.0 * std::cos(pi * m / n); };
+  const double smallest[3] = {per(c->nx, 1) * ax, per(c->ny, 1) * ay, mir(c->nz, 1) * az};
+  double s = smallest[0];
+  for (int q = 1; q < 3; ++q) s = smallest[q] < s ? smallest[q] : s;
+  *lo = s / D;
+  *hi = (per(c->nx, c->nx / 2) * ax + per(c->ny, c->ny / 2) * ay + mir(c->nz, c->nz - 1) * az) / D;
+}
+
+template <typename T>
+struct View {
+  T *f[F_COUNT];
+  Profiles<T> P;
+  Dyn<T> dyn;
+  double *partials;
+  SolveCtl *ctl;
+  double *diag;
+  T *u, *v, *w, *thl, *qt, *p;
+};
+
+template <typename T>
+View<T> view_of(const les_handle *h) {
+  View<T> V;
+  for (int f = 0; f < F_COUNT; ++f) V.f[f] = (T *)ws(h, h->lay.field[f]);
+  const int nz = h->cfg.nz;
+  double *pd = (double *)ws(h, h->lay.prof_d);
+  T *pt = (T *)ws(h, h->lay.prof_t);
+  V.P.p0 = pd;
+  V.P.lnp = pd + nz;
+  V.P.alpha0 = pd + 2 * nz;
+  V.P.rho0 = pd + 3 * nz;
+  V.P.rho0_t = pt;
+  V.P.alpha0_t = pt + nz;
+  V.P.beta_t = pt + 2 * nz;
+  V.P.wsub_t = pt + 3 * nz;
+  V.partials = (double *)ws(h, h->lay.partials);
+  V.ctl = (SolveCtl *)ws(h, h->lay.ctl);
+  V.diag = (double *)ws(h, h->lay.diag);
+  const les_config &c = h->cfg;
+  Dyn<T> &d = V.dyn;
+  d.dt = (T)c.dt;
+  d.inv_dx = (T)(1.0 / c.dx);
+  d.inv_dy = (T)(1.0 / c.dy);
+  d.inv_dz = (T)(1.0 / c.dz);
+  d.inv_2dx = (T)(0.5 / c.dx);
+  d.inv_2dy = (T)(0.5 / c.dy);
+  d.inv_2dz = (T)(0.5 / c.dz);
+  d.fcor = (T)c.fcor;
+  d.ug = (T)c.ug;
+  d.vg = (T)c.vg;
+  d.inv_pr = (T)(1.0 / c.Pr);
+  d.inv_sc = (T)(1.0 / c.Sc);
+  d.sfc_thl = (T)(c.shf / c.cpd);
+  d.sfc_qt = (T)(c.lhf / c.Lv0);
+  const double delta = std::cbrt(c.dx * c.dy * c.dz);
+  d.smag_l2 = (T)((c.cs * delta) * (c.cs * delta));
+  d.pr = (T)c.Pr;
+  V.u = (T *)h->buf.u;
+  V.v = (T *)h->buf.v;
+  V.w = (T *)h->buf.w;
+  V.thl = (T *)h->buf.thl;
+  V.qt = (T *)h->buf.qt;
+  V.p = (T *)h->buf.p;
+  return V;
+}
+
+// Reference state (Sec. 2.1) on the host in FP64, uploaded into the
+// workspace (FP64 copies for thermodynamics and reductions, storage-type
+// copies for the stencils).  Returns after the upload completed.
+template <typename T>
+int upload_profiles(les_handle *h) {
+  const les_config &c = h->cfg;
+  const int nz = c.nz;
+  std::vector<double> pd(4 * (size_t)nz);
+  std::vector<T> pt(4 * (size_t)nz);
+  const double H = nz * c.dz, zs = (1.0 - c.sponge_frac) * H;
+  const double pi = 3.14159265358979323846;
+  for (int k = 0; k < nz; ++k) {
+    const double z = (k + 0.5) * c.dz;
+    const double base = 1.0 - c.g * z / (c.cpd * c.theta0);
+    const double p0 = c.p00 * std::pow(base, c.cpd / c.Rd);   // hydrostatic, adiabatic
+    const double T0 = c.theta0 * std::pow(p0 / c.p00, c.Rd / c.cpd);
+    const double alpha0 = c.Rd * T0 / p0;                       // = 1 / rho0
+    const double rho0 = p0 / (c.Rd * T0);
+    double beta = 0.0;
+    if (z >= zs && H > zs) {
+      const double s = std::sin(0.5 * pi * (z - zs) / (H - zs));
+      beta = c.sponge_max * s * s;
+    }
+    pd[k] = p0;
+    pd[nz + k] = std::log(p0 / c.p00);
+    pd[2 * nz + k] = alpha0;
+    pd[3 * nz + k] = rho0;
+    pt[k] = (T)rho0;
+    pt[nz + k] = (T)alpha0;
+    pt[2 * nz + k] = (T)beta;
+    pt[3 * nz + k] = (T)(c.wsub_div * z);
+  }
+  HIP_TRY(hipMemcpyAsync(ws(h, h->lay.prof_d), pd.data(), pd.size() * sizeof(double),
+                         hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipMemcpyAsync(ws(h, h->lay.prof_t), pt.data(), pt.size() * sizeof(T),
+                         hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return LES_OK;
+}
+
+// One Poisson solve on the workspace buffers.  rhs_in is the raw
+// right-hand side (may be the workspace rhs itself); the centred rhs goes to
+// F_RHS.  If use_guess, F_PHI0 already holds the guess.  On return
+// *result points at the buffer holding the returned iterate (not yet
+// gauge-shifted; ctl->phi_mean is not computed here).
+template <typename T>
+int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
+          les_solve_stats *st, T **result) {
+  const les_config &c = h->cfg;
+  const Grid &g = h->grid;
+  hipStream_t s = h->stream;
+  const int max_sweeps = fixed > 0 ? fixed : c.poisson_max_sweeps;
+  const int every = c.poisson_check_every;
+  T *buf[2] = {V.f[F_PHI0], V.f[F_PHI1]};
+  T *rhs = V.f[F_RHS];
+
+  HIP_TRY(hipEventRecord(h->ev_s0, s));
+  launch_ctl_reset(V.ctl, max_sweeps, fixed > 0 ? 1 : 0, s);
+  launch_block_sum(rhs_in, g.n, 0, V.partials, s);
+  launch_final(V.partials, kReduceBlocks, kFinalRhsMean, V.ctl, (double)g.n, 0.0, 0, nullptr, s);
+  launch_rhs_center(g, rhs_in, rhs, use_guess ? (T *)nullptr : buf[0], V.ctl, V.partials, s);
+  launch_final(V.partials, kReduceBlocks, kFinalRhsNorm, V.ctl, (double)g.n,
+               c.poisson_tol * c.poisson_tol, 0, nullptr, s);
+  LAUNCH_TRY();
+
+  const bool cheb = c.poisson_scheme == LES_CHEBYSHEV;
+  const double gamma = 2.0 / (h->mu_min + h->mu_max);
+  const double rho = (h->mu_max - h->mu_min) / (h->mu_max + h->mu_min);
+  const double omega_j = cheb ? gamma : (c.jacobi_omega > 0 ? c.jacobi_omega : gamma);
+  const int nblocks = sweep_grid_blocks(g);
+  double wc = 1.0;
+
+  // Queue sweeps; the device stops applying them once a check succeeds.
+  // Host polls a pinned copy of the control block after a bounded lag.
+  const int lag = 2;
+  std::vector<int> pending;  // check indices queued, in order
+  size_t next_wait = 0;
+  int m = 0;
+  for (; m <= max_sweeps; ++m) {
+    const bool check = fixed > 0 ? (m == max_sweeps) : (m % every == 0 || m == max_sweeps);
+    if (cheb) {
+      if (m == 0) wc = 1.0;
+      else if (m == 1) wc = 1.0 / (1.0 - 0.5 * rho * rho);
+      else wc = 1.0 / (1.0 - 0.25 * rho * rho * wc);
+    }
+    T *cur = buf[m & 1], *nxt = buf[(m + 1) & 1];
+    // The first Chebyshev step has weight 1 and is the plain weighted-Jacobi
+    // sweep: it must not read the (uninitialised) previous iterate.
+    launch_sweep<T>(g, cheb && m > 0, check, omega_j, wc, cur, nxt, nxt, rhs, V.ctl, V.partials, s);
+    if (check) {
+      launch_final(V.partials, nblocks, kFinalCheck, V.ctl, (double)g.n, 0.0, m, nullptr, s);
+      LAUNCH_TRY();
+      const size_t slot = pending.size() % h->ev_check.size();
+      HIP_TRY(hipMemcpyAsync(&h->ctl_host[slot], V.ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipEventRecord(h->ev_check[slot], s));
+      pending.push_back(m);
+      if (pending.size() - next_wait > (size_t)lag) {
+        const size_t ws_ = next_wait % h->ev_check.size();
+        HIP_TRY(hipEventSynchronize(h->ev_check[ws_]));
+        ++next_wait;
+        if (h->ctl_host[ws_].done) break;
+      }
+    }
+  }
+  HIP_TRY(hipEventRecord(h->ev_s1, s));
+  HIP_TRY(hipMemcpyAsync(&h->ctl_host[0], V.ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const SolveCtl &r = h->ctl_host[0];
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, h->ev_s0, h->ev_s1));
+  if (r.done == 0 || r.stop_m < 0)
+    return fail(LES_ERR_STATE, "Poisson solve ended without a decision (m=%d)", m);
+  st->sweeps = r.stop_m;
+  st->status = r.done == 1 ? 0 : (r.done == 3 ? 1 : -3);
+  st->rhs_norm = std::sqrt(r.rhs_norm2);
+  st->res_norm = std::sqrt(r.res_norm2);
+  st->seconds = ms * 1e-3;
+  *result = buf[r.stop_m & 1];
+  if (r.done == 2) return fail(LES_ERR_NONFINITE, "non-finite Poisson residual");
+  return LES_OK;
+}
+
+template <typename T>
+int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step_stats *stats) {
+  View<T> V = view_of<T>(h);
+  const les_config &c = h->cfg;
+  const Grid &g = h->grid;
+  hipStream_t s = h->stream;
+  const size_t bytes = (size_t)g.n * sizeof(T);
+  const int K = c.n_subiter;
+  les_step_stats acc;
+  std::memset(&acc, 0, sizeof(acc));
+  int rc_final = LES_OK;
+
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventRecord(e0, s));
+  for (int step = 0; step < nsteps; ++step) {
+    // step-start copies U^n, Phi^{n+1/2}
+    HIP_TRY(hipMemcpyAsync(V.f[F_UN], V.u, bytes, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(V.f[F_VN], V.v, bytes, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(V.f[F_WN], V.w, bytes, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(V.f[F_THL_H], V.thl, bytes, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(V.f[F_QT_H], V.qt, bytes, hipMemcpyDeviceToDevice, s));
+    // b^{n+1/2}; at k = 0 the midpoint state equals Phi^{n+1/2}
+    launch_thermo<T>(g, h->thermo, V.P, V.f[F_THL_H], V.f[F_QT_H], nullptr, nullptr, nullptr,
+                     nullptr, V.f[F_B_H], V.f[F_QL_M], V.f[F_CPMPI_M], nullptr, s);
+    const T *lag = nullptr;
+    for (int k = 0; k < K; ++k) {
+      const T *thm = V.f[F_THL_H], *qtm = V.f[F_QT_H], *bm = V.f[F_B_H];
+      if (k > 0) {
+        launch_thermo<T>(g, h->thermo, V.P, V.thl, V.qt, V.f[F_THL_H], V.f[F_QT_H], V.f[F_THL_M],
+                         V.f[F_QT_M], V.f[F_B_M], V.f[F_QL_M], V.f[F_CPMPI_M], nullptr, s);
+        thm = V.f[F_THL_M];
+        qtm = V.f[F_QT_M];
+        bm = V.f[F_B_M];
+      }
+      launch_radiation<T>(g, V.P, c.rad_F0, c.rad_kappa, V.f[F_QL_M], V.f[F_CPMPI_M], V.f[F_RAD], s);
+      launch_sgs_nu<T>(g, V.dyn, V.u, V.v, V.w, bm, V.f[F_NU_S], s);
+      launch_scalar_update<T>(g, V.dyn, V.P, V.u, V.v, V.w, thm, qtm, V.f[F_THL_H], V.f[F_QT_H],
+                              V.f[F_NU_S], V.f[F_RAD], V.thl, V.qt, s);
+      const T *uh = V.f[F_UN], *vh = V.f[F_VN], *wh = V.f[F_WN];
+      const T *num = V.f[F_NU_S];
+      if (k > 0) {
+        launch_average<T>(g, V.u, V.f[F_UN], V.f[F_UH], V.v, V.f[F_VN], V.f[F_VH], V.w, V.f[F_WN],
+                          V.f[F_WH], s);
+        launch_sgs_nu<T>(g, V.dyn, V.f[F_UH], V.f[F_VH], V.f[F_WH], V.f[F_B_H], V.f[F_NU_M], s);
+        uh = V.f[F_UH];
+        vh = V.f[F_VH];
+        wh = V.f[F_WH];
+        num = V.f[F_NU_M];
+      }
+      launch_momentum<T>(g, V.dyn, V.P, uh, vh, wh, V.f[F_UN], V.f[F_VN], V.f[F_WN], V.p,
+                         V.f[F_B_H], num, V.u, V.v, V.w, s);
+      launch_poisson_rhs<T>(g, V.dyn, V.P, V.u, V.v, V.w, lag, V.f[F_RHS], V.partials, s);
+      LAUNCH_TRY();
+      const int solve_idx = step * K + k;
+      const int fixed = opts && opts->replay_sweeps ? opts->replay_sweeps[solve_idx] : 0;
+      if (opts && opts->replay_sweeps && fixed < 0)
+        return fail(LES_ERR_ARG, "replay_sweeps[%d] = %d < 0", solve_idx, fixed);
+      les_solve_stats st;
+      T *phi = nullptr;
+      int rc = solve<T>(h, V, V.f[F_RHS], false, fixed, &st, &phi);
+      if (opts && opts->records) opts->records[solve_idx] = st;
+      if (rc < 0) return rc;
+      acc.solves++;
+      acc.sweeps_total += st.sweeps;
+      if (st.sweeps > acc.sweeps_max) acc.sweeps_max = st.sweeps;
+      if (st.status == 1) {
+        acc.not_converged++;
+        rc_final = LES_WARN_NOT_CONVERGED;
+      }
+      const double rel = st.rhs_norm > 0 ? st.res_norm / st.rhs_norm : 0.0;
+      if (rel > acc.res_rel_max) acc.res_rel_max = rel;
+      acc.poisson_seconds += st.seconds;
+      // gauge (zero mean) and projection
+      launch_block_sum<T>(phi, g.n, 0, V.partials, s);
+      launch_final(V.partials, kReduceBlocks, kFinalPhiMean, V.ctl, (double)g.n, 0.0, 0, nullptr, s);
+      launch_project<T>(g, V.dyn, V.P, phi, V.ctl, V.u, V.v, V.w, V.p, s);
+      LAUNCH_TRY();
+      lag = phi;
+    }
+    acc.steps++;
+  }
+  HIP_TRY(hipEventRecord(e1, s));
+  HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  acc.seconds = ms * 1e-3;
+  if (stats) *stats = acc;
+  return rc_final;
+}
+
+template <typename T>
+int poisson_impl(les_handle *h, const void *rhs, void *phi, const les_poisson_opts *opts,
+                 les_solve_stats *stats) {
+  View<T> V = view_of<T>(h);
+  const Grid &g = h->grid;
+  const bool guess = opts && opts->use_guess;
+  const int fixed = opts ? opts->fixed_sweeps : 0;
+  if (fixed < 0) return fail(LES_ERR_ARG, "fixed_sweeps < 0");
+  if (guess)
+    HIP_TRY(hipMemcpyAsync(V.f[F_PHI0], phi, (size_t)g.n * sizeof(T), hipMemcpyDeviceToDevice,
+                           h->stream));
+  les_solve_stats st;
+  T *res = nullptr;
+  int rc = solve<T>(h, V, (const T *)rhs, guess, fixed, &st, &res);
+  if (stats) *stats = st;
+  if (rc < 0) return rc;
+  launch_block_sum<T>(res, g.n, 0, V.partials, h->stream);
+  launch_final(V.partials, kReduceBlocks, kFinalPhiMean, V.ctl, (double)g.n, 0.0, 0, nullptr,
+               h->stream);
+  launch_sub_mean<T>(g, res, V.ctl, (T *)phi, h->stream);
+  LAUNCH_TRY();
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return st.status == 1 ? LES_WARN_NOT_CONVERGED : LES_OK;
+}
+
+template <typename T>
+int thermo_impl(les_handle *h, const void *thl, const void *qt, void *Tout, void *ql, void *b) {
+  View<T> V = view_of<T>(h);
+  launch_thermo<T>(h->grid, h->thermo, V.P, (const T *)thl, (const T *)qt, nullptr, nullptr,
+                   nullptr, nullptr, (T *)b, (T *)ql, nullptr, (T *)Tout, h->stream);
+  LAUNCH_TRY();
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return LES_OK;
+}
+
+template <typename T>
+int diag_impl(les_handle *h, les_diag *out, double *profiles) {
+  View<T> V = view_of<T>(h);
+  const Grid &g = h->grid;
+  const int nz = g.nz;
+  launch_thermo<T>(g, h->thermo, V.P, V.thl, V.qt, nullptr, nullptr, nullptr, nullptr,
+                   V.f[F_B_M], V.f[F_QL_M], nullptr, nullptr, h->stream);
+  launch_diag<T>(g, V.dyn, V.P, V.u, V.v, V.w, V.thl, V.qt, V.f[F_QL_M], V.f[F_B_M], V.diag,
+                 h->stream);
+  LAUNCH_TRY();
+  HIP_TRY(hipMemcpyAsync(h->diag_host, V.diag, (size_t)nz * kDiagStride * sizeof(double),
+                         hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  const double *L = h->diag_host;
+  const double dV = g.dx * g.dy * g.dz;
+  les_diag d;
+  std::memset(&d, 0, sizeof(d));
+  double div2 = 0.0;
+  for (int k = 0; k < nz; ++k) {
+    const double *r = L + (size_t)k * kDiagStride;
+    d.mass_thl += r[9] * dV;
+    d.mass_qt += r[10] * dV;
+    d.ke += r[11] * dV;
+    div2 += r[12];
+    d.div_max = r[13] > d.div_max ? r[13] : d.div_max;
+    d.cfl = r[14] > d.cfl ? r[14] : d.cfl;
+    if (profiles)
+      for (int m = 0; m < LES_NPROFILES; ++m) profiles[(size_t)m * nz + k] = r[m] / (double)g.nxy;
+  }
+  d.div_l2 = std::sqrt(div2);
+  if (out) *out = d;
+  return LES_OK;
+}
+
+int check_handle(const les_handle *h) {
+  if (!h) return fail(LES_ERR_ARG, "handle is NULL");
+  if (h->broken) return fail(LES_ERR_STATE, "handle unusable after an earlier HIP error");
+  return LES_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void les_default_config(les_config *c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->nx = c->ny = c->nz = 32;
+  c->precision = LES_FP64;
+  c->n_subiter = 2;
+  c->poisson_scheme = LES_JACOBI;
+  c->poisson_check_every = 25;
+  c->poisson_max_sweeps = 200000;
+  c->satadj_maxit = 20;
+  c->dx = c->dy = 40.0;
+  c->dz = 10.0;
+  c->dt = 0.5;
+  c->poisson_tol = 1e-8;
+  c->jacobi_omega = 0.0;
+  // Table 1 of the paper
+  c->p00 = 1.0e5;
+  c->theta0 = 290.0;
+  c->Rd = 287.0;
+  c->Rv = 461.89;
+  c->cpd = 1004.5;
+  c->cpv = 1859.5;
+  c->cl = 4181.0;
+  c->ci = 2100.0;
+  c->Lv0 = 2.47e6;
+  c->Ls0 = 2.83e6;
+  c->Tf = 273.15;
+  c->fcor = 7.62e-5;
+  c->g = 9.81;
+  c->cs = 0.18;
+  c->Pr = 0.4;
+  c->Sc = 0.4;
+  c->ug = 7.0;
+  c->vg = -5.0;
+  c->sponge_frac = 0.05;
+  c->sponge_max = 0.25;
+  c->e_tr = 611.657;
+  c->T_tr = 273.16;
+  c->satadj_tol = 1e-10;
+}
+
+size_t les_workspace_bytes(const les_config *cfg) {
+  if (validate(cfg) != LES_OK) return 0;
+  return layout_of(cfg).total;
+}
+
+int les_workspace_offset(const les_config *cfg, int32_t field, size_t *offset) {
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (field < 0 || field >= F_COUNT || !offset) return fail(LES_ERR_ARG, "unknown field %d", field);
+  *offset = layout_of(cfg).field[field];
+  return LES_OK;
+}
+
+int les_init(const les_config *cfg, const les_buffers *bufs, void *stream, les_handle **out) {
+  if (!out) return fail(LES_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (!bufs) return fail(LES_ERR_ARG, "buffers are NULL");
+  const size_t es = elem_size(cfg);
+  void *const ptrs[7] = {bufs->u, bufs->v, bufs->w, bufs->thl, bufs->qt, bufs->p, bufs->workspace};
+  const char *names[7] = {"u", "v", "w", "thl", "qt", "p", "workspace"};
+  for (int q = 0; q < 7; ++q) {
+    if (!ptrs[q]) return fail(LES_ERR_ARG, "buffer %s is NULL", names[q]);
+    if ((uintptr_t)ptrs[q] % (q == 6 ? kAlign : es))
+      return fail(LES_ERR_ARG, "buffer %s is misaligned", names[q]);
+  }
+  const Layout L = layout_of(cfg);
+  if (bufs->workspace_bytes < L.total)
+    return fail(LES_ERR_ARG, "workspace has %zu bytes, needs %zu", bufs->workspace_bytes, L.total);
+
+  les_handle *h = new les_handle();
+  h->cfg = *cfg;
+  h->buf = *bufs;
+  h->stream = (hipStream_t)stream;
+  h->lay = L;
+  h->broken = false;
+  Grid &g = h->grid;
+  g.nx = cfg->nx;
+  g.ny = cfg->ny;
+  g.nz = cfg->nz;
+  g.nxy = (int64_t)cfg->nx * cfg->ny;
+  g.n = g.nxy * cfg->nz;
+  g.dx = cfg->dx;
+  g.dy = cfg->dy;
+  g.dz = cfg->dz;
+  g.dt = cfg->dt;
+  Thermo &t = h->thermo;
+  t.p00 = cfg->p00;
+  t.Rd = cfg->Rd;
+  t.Rv = cfg->Rv;
+  t.cpd = cfg->cpd;
+  t.cpv = cfg->cpv;
+  t.cl = cfg->cl;
+  t.ci = cfg->ci;
+  t.Lv0 = cfg->Lv0;
+  t.Ls0 = cfg->Ls0;
+  t.Tf = cfg->Tf;
+  t.g = cfg->g;
+  t.e_tr = cfg->e_tr;
+  t.inv_Ttr = 1.0 / cfg->T_tr;
+  t.Lv_over_Rv = cfg->Lv0 / cfg->Rv;
+  t.eps = cfg->Rd / cfg->Rv;
+  t.satadj_tol = cfg->satadj_tol;
+  t.satadj_maxit = cfg->satadj_maxit;
+  jacobi_spectrum(cfg, &h->mu_min, &h->mu_max);
+
+  auto cleanup = [&](int code) {
+    les_destroy(h);
+    return code;
+  };
+  if (hipHostMalloc((void **)&h->ctl_host, 8 * sizeof(SolveCtl), hipHostMallocDefault) != hipSuccess)
+    return cleanup(fail(LES_ERR_HIP, "hipHostMalloc failed"));
+  if (hipHostMalloc((void **)&h->diag_host, (size_t)cfg->nz * kDiagStride * sizeof(double),
+                    hipHostMallocDefault) != hipSuccess)
+    return cleanup(fail(LES_ERR_HIP, "hipHostMalloc failed"));
+  h->ev_check.resize(8);
+  for (auto &e : h->ev_check)
+    if (hipEventCreate(&e) != hipSuccess) return cleanup(fail(LES_ERR_HIP, "hipEventCreate failed"));
+  if (hipEventCreate(&h->ev_s0) != hipSuccess || hipEventCreate(&h->ev_s1) != hipSuccess ||
+      hipEventCreate(&h->ev_a) != hipSuccess || hipEventCreate(&h->ev_b) != hipSuccess)
+    return cleanup(fail(LES_ERR_HIP, "hipEventCreate failed"));
+  rc = cfg->precision == LES_FP64 ? upload_profiles<double>(h) : upload_profiles<float>(h);
+  if (rc) return cleanup(rc);
+  *out = h;
+  return LES_OK;
+}
+
+int les_step(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step_stats *stats) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (nsteps < 0) return fail(LES_ERR_ARG, "nsteps < 0");
+  rc = h->cfg.precision == LES_FP64 ? step_impl<double>(h, nsteps, opts, stats)
+                                    : step_impl<float>(h, nsteps, opts, stats);
+  if (rc == LES_ERR_HIP) h->broken = true;
+  return rc;
+}
+
+int les_poisson_solve(les_handle *h, const void *rhs, void *phi, const les_poisson_opts *opts,
+                      les_solve_stats *stats) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!rhs || !phi) return fail(LES_ERR_ARG, "rhs and phi must be non-NULL");
+  rc = h->cfg.precision == LES_FP64 ? poisson_impl<double>(h, rhs, phi, opts, stats)
+                                    : poisson_impl<float>(h, rhs, phi, opts, stats);
+  if (rc == LES_ERR_HIP) h->broken = true;
+  return rc;
+}
+
+int les_thermo(les_handle *h, const void *thl, const void *qt, void *T, void *ql, void *b) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!thl || !qt) return fail(LES_ERR_ARG, "thl and qt must be non-NULL");
+  rc = h->cfg.precision == LES_FP64 ? thermo_impl<double>(h, thl, qt, T, ql, b)
+                                    : thermo_impl<float>(h, thl, qt, T, ql, b);
+  if (rc == LES_ERR_HIP) h->broken = true;
+  return rc;
+}
+
+int les_diagnostics(les_handle *h, les_diag *out, double *profiles) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  rc = h->cfg.precision == LES_FP64 ? diag_impl<double>(h, out, profiles)
+                                    : diag_impl<float>(h, out, profiles);
+  if (rc == LES_ERR_HIP) h->broken = true;
+  return rc;
+}
+
+void les_destroy(les_handle *h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (auto &e : h->ev_check)
+    if (e) (void)hipEventDestroy(e);
+  if (h->ev_s0) (void)hipEventDestroy(h->ev_s0);
+  if (h->ev_s1) (void)hipEventDestroy(h->ev_s1);
+  if (h->ev_a) (void)hipEventDestroy(h->ev_a);
+  if (h->ev_b) (void)hipEventDestroy(h->ev_b);
+  if (h->ctl_host) (void)hipHostFree(h->ctl_host);
+  if (h->diag_host) (void)hipHostFree(h->diag_host);
+  delete h;
+}
+
+const char *les_last_error(void) { return g_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Device helpers: boundary-aware loads, wavefront/block FP64 reductions.
+#pragma once
+
+#include "les_internal.h"
+
+namespace lesmi {
+
+// Periodic neighbour index for offsets |o| <= 2 (n >= 4 is validated on the host).
+__device__ __forceinline__ int pwrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Mirror across the walls z = 0 and z = H: level -1 -> 0, -2 -> 1, nz -> nz-1, nz+1 -> nz-2.
+__device__ __forceinline__ int zmirror(int k, int nz) {
+  return k < 0 ? -1 - k : (k >= nz ? 2 * nz - 1 - k : k);
+}
+
+// Value of a cell-centred field at (i, j, k) with ghost cells: periodic x/y,
+// wall mirror in z times the field's parity (+1 even: scalars, pressure,
+// viscosity, buoyancy; -1 odd: velocity components).
+template <typename T>
+__device__ __forceinline__ T gload(const T *__restrict__ f, const Grid &g, int i, int j, int k,
+                                   T parity) {
+  i = pwrap(i, g.nx);
+  j = pwrap(j, g.ny);
+  int km = zmirror(k, g.nz);
+  T v = f[(int64_t)i + (int64_t)g.nx * j + g.nxy * km];
+  return km == k ? v : parity * v;
+}
+
+// Profile value with even extension across the walls.
+template <typename T>
+__device__ __forceinline__ T pload(const T *__restrict__ a, int k, int nz) {
+  return a[zmirror(k, nz)];
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block-wide FP64 sum (blockDim.x a multiple of 64, at most 1024 threads).
+// Result valid in thread 0.  Fixed order: deterministic for a fixed launch.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[16];
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int q = 0; q < nw; ++q) s += red[q];
+  }
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Block-wide maximum (same launch constraints as block_sum).
+__device__ __forceinline__ double block_max(double v) {
+  __shared__ double red[16];
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = v;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int q = 0; q < nw; ++q) s = fmax(s, red[q]);
+  }
+  __syncthreads();
+  return s;
+}
+
+}  // namespace lesmi

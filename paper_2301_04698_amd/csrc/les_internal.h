@@ -1,0 +1,150 @@
+// Internal declarations of the HIP LES library: grid/physics parameter
+// blocks passed to kernels by value, the Poisson control block kept in the
+// workspace, and the host-side launchers implemented in the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lesmi {
+
+// Grid geometry.  Index of cell (i, j, k) is i + nx*(j + ny*k).
+struct Grid {
+  int nx, ny, nz;
+  int64_t nxy, n;
+  double dx, dy, dz, dt;
+};
+
+// Constants needed by the per-cell thermodynamics (always FP64).
+struct Thermo {
+  double p00, Rd, Rv, cpd, cpv, cl, ci, Lv0, Ls0, Tf, g;
+  double e_tr, inv_Ttr, Lv_over_Rv, eps;  // saturation vapour pressure
+  double satadj_tol;
+  int satadj_maxit;
+};
+
+// Vertical profiles (device pointers, nz entries each).
+template <typename T>
+struct Profiles {
+  const double *p0, *lnp, *alpha0, *rho0;   // FP64: ln(p0/p00) feeds the Exner power
+  const T *rho0_t, *alpha0_t, *beta_t, *wsub_t;
+};
+
+// Parameters of the dynamics kernels in storage precision.
+template <typename T>
+struct Dyn {
+  T dt, inv_dx, inv_dy, inv_dz, inv_2dx, inv_2dy, inv_2dz;
+  T fcor, ug, vg;
+  T inv_pr, inv_sc;
+  T sfc_thl, sfc_qt;   // surface flux per unit area (rho0-weighted) into the lowest cell
+  T smag_l2;           // (c_s Delta)^2
+  T pr;                // turbulent Prandtl number of the buoyancy factor
+};
+
+// Device-resident control block of one Poisson solve.  Sweep kernels read
+// `done` and return at once when it is set, so the host can queue sweeps
+// ahead of the convergence test without synchronizing.
+struct SolveCtl {
+  double rhs_mean;    // mean of the raw rhs
+  double rhs_norm2;   // ||rhs||^2 after mean removal
+  double res_norm2;   // residual^2 of the last checked iterate
+  double tol2;        // tol^2 * rhs_norm2
+  double phi_mean;    // mean of the returned iterate
+  double aux;
+  int32_t done;       // 0 running, 1 converged, 2 non-finite, 3 cap reached
+  int32_t stop_m;     // sweep index of the returned iterate
+  int32_t max_sweeps;
+  int32_t fixed;      // 1: stop at max_sweeps whatever the residual
+};
+
+constexpr int kBlock = 256;          // threads per block of elementwise kernels
+constexpr int kReduceBlocks = 1024;  // fixed grid of the generic reductions
+constexpr int kPartials = 1 << 16;   // max partials of one reduction (sweep tiles)
+
+// Sweep tile: 64 x-cells (one wavefront) by 4 y-rows, marching KC levels.
+constexpr int kSweepTX = 64;
+constexpr int kSweepTY = 4;
+constexpr int kSweepKC = 16;
+
+int sweep_grid_blocks(const Grid &g);
+
+// ------------------------------------------------------------ launchers
+template <typename T>
+void launch_thermo(const Grid &g, const Thermo &c, const Profiles<T> &P, const T *thl_a,
+                   const T *qt_a, const T *thl_b, const T *qt_b, T *thl_mid, T *qt_mid, T *b,
+                   T *ql, T *cpmpi, T *Tout, hipStream_t s);
+
+template <typename T>
+void launch_radiation(const Grid &g, const Profiles<T> &P, double F0, double kappa, const T *ql,
+                      const T *cpmpi, T *out, hipStream_t s);
+
+template <typename T>
+void launch_average(const Grid &g, const T *a0, const T *b0, T *o0, const T *a1, const T *b1, T *o1,
+                    const T *a2, const T *b2, T *o2, hipStream_t s);
+
+template <typename T>
+void launch_sgs_nu(const Grid &g, const Dyn<T> &d, const T *u, const T *v, const T *w, const T *b,
+                   T *nu, hipStream_t s);
+
+template <typename T>
+void launch_scalar_update(const Grid &g, const Dyn<T> &d, const Profiles<T> &P, const T *u,
+                          const T *v, const T *w, const T *thl_mid, const T *qt_mid,
+                          const T *thl_half, const T *qt_half, const T *nu, const T *rad,
+                          T *thl_out, T *qt_out, hipStream_t s);
+
+template <typename T>
+void launch_momentum(const Grid &g, const Dyn<T> &d, const Profiles<T> &P, const T *uh,
+                     const T *vh, const T *wh, const T *un, const T *vn, const T *wn, const T *p,
+                     const T *b, const T *nu, T *uo, T *vo, T *wo, hipStream_t s);
+
+template <typename T>
+void launch_poisson_rhs(const Grid &g, const Dyn<T> &d, const Profiles<T> &P, const T *u,
+                        const T *v, const T *w, const T *phi_lag, T *rhs, double *partials,
+                        hipStream_t s);
+
+// rhs_out = rhs_in - ctl->rhs_mean; partial sums of rhs_out^2; optional zeroing of phi0.
+template <typename T>
+void launch_rhs_center(const Grid &g, const T *rhs_in, T *rhs_out, T *phi0, const SolveCtl *ctl,
+                       double *partials, hipStream_t s);
+
+template <typename T>
+void launch_sweep(const Grid &g, bool chebyshev, bool check, double omega_jacobi, double omega_cheb,
+                  const T *phi, const T *prev, T *out, const T *rhs, const SolveCtl *ctl,
+                  double *partials, hipStream_t s);
+
+template <typename T>
+void launch_project(const Grid &g, const Dyn<T> &d, const Profiles<T> &P, const T *phi,
+                    const SolveCtl *ctl, T *u, T *v, T *w, T *p, hipStream_t s);
+
+template <typename T>
+void launch_sub_mean(const Grid &g, const T *in, const SolveCtl *ctl, T *out, hipStream_t s);
+
+// Generic FP64 sums over n elements: mode 0 sum(a), 1 sum(a^2).
+template <typename T>
+void launch_block_sum(const T *a, int64_t n, int mode, double *partials, hipStream_t s);
+
+// Final fixed-order reductions of `np` partials into the control block.
+enum FinalOp {
+  kFinalRhsMean = 0,   // ctl->rhs_mean = sum / n
+  kFinalRhsNorm = 1,   // ctl->rhs_norm2, tol2; converged at once if zero
+  kFinalCheck = 2,     // residual check at sweep m
+  kFinalPhiMean = 3,   // ctl->phi_mean = sum / n
+  kFinalStore = 4      // out[slot] = sum
+};
+void launch_final(const double *partials, int np, int op, SolveCtl *ctl, double n, double tol2_scale,
+                  int m, double *out, hipStream_t s);
+
+void launch_ctl_reset(SolveCtl *ctl, int max_sweeps, int fixed, hipStream_t s);
+
+// Per-level FP64 sums for the diagnostics: level_sums[k*kDiagStride + m],
+// m = 0..8 horizontal sums of thl, qt, ql, u, v, w, w^2, w^3, b; 9 sum rho0 thl,
+// 10 sum rho0 qt, 11 sum rho0 |u|^2/2, 12 sum div^2, 13 max |div|, 14 max CFL.
+constexpr int kDiagStride = 16;
+template <typename T>
+void launch_diag(const Grid &g, const Dyn<T> &d, const Profiles<T> &P, const T *u, const T *v,
+                 const T *w, const T *thl, const T *qt, const T *ql, const T *b,
+                 double *level_sums, hipStream_t s);
+
+}  // namespace lesmi

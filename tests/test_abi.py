@@ -1,0 +1,122 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/les.h declares, the ctypes structs match the C layouts, argument
+validation fails cleanly, and the workspace layout is consistent.  No GPU
+compute calls."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+import les_inputs as li
+from conftest import ROOT, load_table1
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "les.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b(les_[a-z_]+)\s*\(", src))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2301_04698_amd import les
+    return les
+
+
+def test_exports_every_declared_symbol(lib):
+    L = lib.load()
+    names = declared_functions()
+    assert set(names) == set(lib.EXPORTS), names
+    for n in names:
+        assert hasattr(L, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", lib.LIB_PATH], capture_output=True, text=True)
+    exported = set(re.findall(r" T (les_\w+)", out.stdout))
+    assert set(names) <= exported
+
+
+def test_struct_layouts_match_header(lib, tmp_path):
+    prog = tmp_path / "sz.c"
+    prog.write_text(r'''
+#include "les.h"
+#include <stdio.h>
+#include <stddef.h>
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(les_config), sizeof(les_buffers),
+         sizeof(les_solve_stats), sizeof(les_poisson_opts), sizeof(les_step_opts),
+         sizeof(les_step_stats), sizeof(les_diag), offsetof(les_config, dx),
+         offsetof(les_config, satadj_tol), offsetof(les_step_stats, res_rel_max));
+  return 0;
+}''')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    want = [C.sizeof(lib.LesConfig), C.sizeof(lib.LesBuffers), C.sizeof(lib.LesSolveStats),
+            C.sizeof(lib.LesPoissonOpts), C.sizeof(lib.LesStepOpts), C.sizeof(lib.LesStepStats),
+            C.sizeof(lib.LesDiag), lib.LesConfig.dx.offset, lib.LesConfig.satadj_tol.offset,
+            lib.LesStepStats.res_rel_max.offset]
+    assert got == want
+
+
+def test_default_config_is_table1(lib):
+    c = lib.default_config()
+    for k, v in load_table1().items():
+        assert getattr(c, k) == v, k
+
+
+def test_make_config_carries_every_parameter(lib, oracle_lib):
+    p = li.workload("C2")
+    c = lib.make_config(p)
+    o = oracle_lib.make_cfg(p)
+    for name, _ in oracle_lib.OCfg._fields_:
+        assert getattr(c, name) == getattr(o, name), name
+    assert c.precision == lib.LES_FP32 and c.poisson_scheme == lib.LES_CHEBYSHEV
+
+
+@pytest.mark.parametrize("override,needle", [
+    (dict(nx=3), "must be >= 4"),
+    (dict(dt=0.0), "> 0"),
+    (dict(poisson_tol=0.0), "poisson_tol"),
+    (dict(poisson_check_every=0), "check_every"),
+    (dict(n_subiter=0), "n_subiter"),
+    (dict(jacobi_omega=2.5), "jacobi_omega"),
+])
+def test_invalid_config_rejected(lib, override, needle):
+    c = lib.make_config(li.workload("C1", **override))
+    assert lib.workspace_bytes(c) == 0
+    assert needle in lib.last_error()
+
+
+def test_init_rejects_null_buffers(lib):
+    c = lib.make_config(li.workload("C1"))
+    b = lib.LesBuffers()
+    h = C.c_void_p()
+    rc = lib.load().les_init(C.byref(c), C.byref(b), None, C.byref(h))
+    assert rc == lib.LES_ERR_ARG and "NULL" in lib.last_error()
+    assert not h.value
+
+
+def test_init_rejects_small_workspace(lib):
+    c = lib.make_config(li.workload("C1"))
+    fake = 1 << 40  # never dereferenced: validation fails first
+    b = lib.LesBuffers(*([fake] * 7), 16)
+    h = C.c_void_p()
+    rc = lib.load().les_init(C.byref(c), C.byref(b), None, C.byref(h))
+    assert rc == lib.LES_ERR_ARG and "workspace" in lib.last_error()
+
+
+def test_workspace_layout(lib):
+    for name in ("C1", "C2", "C5"):
+        p = li.workload(name)
+        c = lib.make_config(p)
+        total = lib.workspace_bytes(c)
+        n = p["nx"] * p["ny"] * p["nz"]
+        es = 8 if c.precision == lib.LES_FP64 else 4
+        offs = [lib.workspace_offset(c, f) for f in lib.WS_FIELDS]
+        assert offs == sorted(offs) and all(o % 256 == 0 for o in offs)
+        assert all(b - a >= n * es for a, b in zip(offs, offs[1:]))
+        assert offs[-1] + n * es <= total
+    c5 = lib.make_config(li.workload("C5"))
+    assert lib.workspace_bytes(c5) < 32 * 2 ** 30  # fits easily in 288 GB of HBM

@@ -1,0 +1,235 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on
+identical seeded inputs.
+
+Bars: FP64 GPU path <= 1e-11 relative L2 per field; FP32 path <= 1e-5
+relative L2 per field per step.  For full steps the GPU replays the oracle's
+per-solve sweep counts so a stopping decision on the tolerance boundary
+cannot shift one side by a check interval.
+"""
+import numpy as np
+import pytest
+
+import les_inputs as li
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("u", "v", "w", "thl", "qt", "p")
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_04698_amd import les
+    les.load()
+    return les
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def rel_anom(a, b):
+    """Error relative to the deviation of b from its horizontal mean."""
+    d = b - b.mean(axis=(1, 2), keepdims=True)
+    nd = np.linalg.norm(d)
+    return np.linalg.norm(a - b) / (nd if nd > 0 else 1.0)
+
+
+def with_velocity_noise(p, st, amp, seed):
+    rng = np.random.default_rng(seed)
+    for k in ("u", "v", "w"):
+        st[k] = st[k] + amp * rng.standard_normal(st[k].shape)
+    return st
+
+
+# ------------------------------------------------------------ Poisson
+
+@pytest.mark.parametrize("shape,scheme", [((8, 8, 8), "jacobi"), ((10, 12, 16), "jacobi"),
+                                          ((8, 8, 8), "chebyshev"), ((10, 12, 16), "chebyshev"),
+                                          ((20, 36, 70), "chebyshev")])
+def test_poisson_fp64_matches_oracle(gpu, oracle_lib, shape, scheme):
+    import torch
+    nz, ny, nx = shape
+    p = li.workload("C1", nx=nx, ny=ny, nz=nz, dx=40.0, dy=30.0, dz=10.0, poisson_tol=1e-10,
+                    poisson_scheme=scheme)
+    rhs = li.random_field(shape, seed=21) + 0.3  # nonzero mean: removed by both sides
+    phi_o, st_o = oracle_lib.poisson(p, rhs)
+    sim = gpu.LES(p)
+    phi_g, st_g, rc = sim.poisson_solve(torch.from_numpy(rhs))
+    assert rc == 0 and st_g["status"] == 0 and st_o["status"] == 0
+    assert st_g["sweeps"] == st_o["sweeps"]
+    assert st_g["res_norm"] <= 1e-10 * st_g["rhs_norm"]
+    assert st_g["rhs_norm"] == pytest.approx(st_o["rhs_norm"], rel=1e-13)
+    e = rel(phi_g.cpu().numpy(), phi_o)
+    assert e <= 1e-11, e
+
+
+@pytest.mark.parametrize("scheme", ["jacobi", "chebyshev"])
+def test_poisson_fp32_matches_oracle(gpu, oracle_lib, scheme):
+    import torch
+    shape = (16, 24, 40)
+    p = li.workload("C1", nx=40, ny=24, nz=16, poisson_tol=1e-5, poisson_scheme=scheme,
+                    precision="fp32")
+    rhs = li.random_field(shape, seed=5)
+    phi_o, st_o = oracle_lib.poisson(p, rhs)
+    sim = gpu.LES(p)
+    phi_g, st_g, rc = sim.poisson_solve(torch.from_numpy(rhs), fixed_sweeps=st_o["sweeps"])
+    assert st_g["sweeps"] == st_o["sweeps"]
+    e = rel(phi_g.double().cpu().numpy(), phi_o)
+    assert e <= 1e-5, e
+    assert st_g["res_norm"] <= 2e-5 * st_g["rhs_norm"]
+
+
+def test_poisson_guess_and_zero_rhs(gpu, oracle_lib):
+    import torch
+    p = li.workload("C1", nx=16, ny=16, nz=16, poisson_tol=1e-10, poisson_scheme="chebyshev")
+    rhs = li.random_field((16, 16, 16), seed=8)
+    phi_o, _ = oracle_lib.poisson(p, rhs)
+    sim = gpu.LES(p)
+    guess = torch.from_numpy(phi_o.copy()).cuda()
+    phi_g, st, _ = sim.poisson_solve(torch.from_numpy(rhs), guess, use_guess=True)
+    assert st["sweeps"] == 0 and st["status"] == 0
+    zero = torch.zeros((16, 16, 16), dtype=torch.float64)
+    phi_z, st0, _ = sim.poisson_solve(zero, torch.full((16, 16, 16), 3.0, dtype=torch.float64,
+                                                        device="cuda"), use_guess=True)
+    assert st0["sweeps"] == 0 and torch.all(phi_z == 0)
+
+
+def test_poisson_not_converged_and_nonfinite(gpu):
+    import torch
+    p = li.workload("C1", nx=8, ny=8, nz=8, poisson_max_sweeps=3, poisson_check_every=1)
+    sim = gpu.LES(p)
+    rhs = torch.from_numpy(li.random_field((8, 8, 8), seed=1))
+    _, st, rc = sim.poisson_solve(rhs)
+    assert rc == gpu.LES_WARN_NOT_CONVERGED and st["status"] == 1 and st["sweeps"] == 3
+    bad = rhs.clone()
+    bad[3, 3, 3] = float("nan")
+    with pytest.raises(gpu.LesError) as ei:
+        sim.poisson_solve(bad)
+    assert ei.value.code == gpu.LES_ERR_NONFINITE
+
+
+# ------------------------------------------------------- thermodynamics
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_thermo_matches_oracle(gpu, oracle_lib, precision):
+    import torch
+    p = li.workload("C1m", precision=precision)
+    st = li.initial_state(p)
+    rng = np.random.default_rng(0)
+    thl = st["thl"] + rng.uniform(-2, 2, st["thl"].shape)
+    qt = np.clip(st["qt"] + rng.uniform(-3e-3, 3e-3, st["qt"].shape), 0, None)
+    if precision == "fp32":
+        # the oracle sees the same storage-rounded inputs as the kernel
+        thl = thl.astype(np.float32).astype(np.float64)
+        qt = qt.astype(np.float32).astype(np.float64)
+    o = oracle_lib.thermo(p, thl, qt)
+    sim = gpu.LES(p)
+    g = sim.thermo(torch.from_numpy(thl), torch.from_numpy(qt))
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    assert (o["ql"] > 0).mean() > 0.2
+    for k in ("T", "ql", "b"):
+        e = rel(g[k].double().cpu().numpy(), o[k])
+        assert e <= tol, (k, e)
+    if precision == "fp64":
+        assert np.abs(g["T"].cpu().numpy() - o["T"]).max() <= 1e-9
+
+
+# ------------------------------------------------------------ full step
+
+def _compare_step(gpu, oracle_lib, p, st0, nsteps, tol, debug=False):
+    ost = {k: v.copy() for k, v in st0.items()}
+    recs, dbg = oracle_lib.step(p, ost, nsteps=nsteps, debug=debug)
+    replay = [r["sweeps"] for r in recs]
+    sim = gpu.LES(p, st0)
+    rc, stats, grecs = sim.step(nsteps, replay=replay, records=True)
+    gst = sim.state_numpy()
+    errs = {k: rel(gst[k], ost[k]) for k in FIELDS}
+    return errs, recs, grecs, sim, dbg, ost, gst
+
+
+def test_step_c1_fp64_one_step(gpu, oracle_lib):
+    p = li.workload("C1")
+    st0 = li.initial_state(p)
+    errs, recs, grecs, sim, dbg, ost, gst = _compare_step(gpu, oracle_lib, p, st0, 1, 1e-11, debug=True)
+    for name, ws in (("b_half", "b_half"), ("rhs", "rhs")):
+        g = sim.workspace_field(ws).double().cpu().numpy()
+        assert rel(g, dbg[name]) <= 1e-11, (name, rel(g, dbg[name]))
+    for k, e in errs.items():
+        assert e <= 1e-11, (k, e, errs)
+    for a, b in zip(recs, grecs):
+        assert a["sweeps"] == b["sweeps"]
+        assert b["rhs_norm"] == pytest.approx(a["rhs_norm"], rel=1e-10)
+
+
+def test_step_c1m_fp64_all_physics(gpu, oracle_lib):
+    """Saturated cells, surface fluxes, radiation, sponge, Coriolis, SGS with
+    a perturbed velocity field; 2 steps, K = 2."""
+    p = li.workload("C1m", poisson_tol=1e-9, poisson_scheme="chebyshev")
+    st0 = with_velocity_noise(p, li.initial_state(p), 0.3, 4)
+    errs, *_ = _compare_step(gpu, oracle_lib, p, st0, 2, 1e-11)
+    for k, e in errs.items():
+        assert e <= 1e-11, (k, e, errs)
+
+
+def test_step_c1_fp64_ten_steps(gpu, oracle_lib):
+    """The configuration of the small parity case: 32^3, dt 0.5 s, tol 1e-8,
+    fixed-weight Jacobi, 10 steps."""
+    p = li.workload("C1")
+    st0 = li.initial_state(p)
+    errs, recs, grecs, *_ = _compare_step(gpu, oracle_lib, p, st0, 10, 1e-11)
+    for k, e in errs.items():
+        assert e <= 1e-11, (k, e, errs)
+    assert all(r["status"] == 0 for r in grecs)
+
+
+def test_step_fp32_matches_oracle(gpu, oracle_lib):
+    """FP32 storage/stencils with FP64 reductions and saturation adjustment:
+    per-field relative L2 error <= 1e-5 after one step (ragged 40x24x32 grid)."""
+    p = li.workload("C1m", nx=40, ny=24, nz=32, precision="fp32", poisson_tol=1e-6,
+                    poisson_scheme="chebyshev")
+    st0 = with_velocity_noise(p, li.initial_state(p), 0.3, 7)
+    errs, *_ = _compare_step(gpu, oracle_lib, p, st0, 1, 1e-5)
+    for k, e in errs.items():
+        assert e <= 1e-5, (k, e, errs)
+
+
+def test_step_rest_state_steady(gpu):
+    import torch
+    p = li.workload("C1", nx=8, ny=8, nz=8, ug=0.0, vg=0.0, noise_thl=0.0, thl_ml=290.0,
+                    dthl_inv=0.0, qt_ml=0.0, qt_ft=0.0, z_inv=1e9)
+    st0 = li.initial_state(p)
+    sim = gpu.LES(p, st0)
+    rc, stats, recs = sim.step(3, records=True)
+    gst = sim.state_numpy()
+    for k in FIELDS:
+        assert np.array_equal(gst[k], st0[k]), k
+    assert all(r["sweeps"] == 0 for r in recs)
+
+
+def test_conservation_gpu(gpu):
+    """Scalar domain integrals conserved without sources (FP64 path)."""
+    p = li.workload("C1m", shf=0.0, lhf=0.0, rad_F0=0.0, poisson_tol=1e-6,
+                    poisson_scheme="chebyshev")
+    st0 = with_velocity_noise(p, li.initial_state(p), 0.5, 2)
+    sim = gpu.LES(p, st0)
+    d0 = sim.diagnostics()
+    sim.step(3)
+    d1 = sim.diagnostics()
+    assert abs(d1["mass_thl"] - d0["mass_thl"]) <= 1e-13 * abs(d0["mass_thl"])
+    assert abs(d1["mass_qt"] - d0["mass_qt"]) <= 1e-13 * abs(d0["mass_qt"])
+
+
+def test_diagnostics_match_oracle(gpu, oracle_lib):
+    p = li.workload("C1m")
+    st0 = with_velocity_noise(p, li.initial_state(p), 0.3, 3)
+    o = oracle_lib.diagnostics(p, st0)
+    sim = gpu.LES(p, st0)
+    g = sim.diagnostics()
+    for k in ("mass_thl", "mass_qt", "div_l2", "div_max", "cfl", "ke"):
+        assert g[k] == pytest.approx(o[k], rel=1e-12), k
+    for k, prof in o["profiles"].items():
+        np.testing.assert_allclose(g["profiles"][k], prof, rtol=1e-11, atol=1e-15)

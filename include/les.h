@@ -107,6 +107,9 @@ typedef struct les_step_opts {
   const int32_t *replay_sweeps; /* host, nsteps*n_subiter entries or NULL:
                                    per-solve sweep counts to apply exactly */
   les_solve_stats *records;     /* host, nsteps*n_subiter entries or NULL */
+  int32_t time_sweeps;          /* 1: time runs of consecutive plain sweeps
+                                   (between residual checks) with HIP events */
+  int32_t reserved;
 } les_step_opts;
 
 typedef struct les_step_stats {
@@ -117,6 +120,8 @@ typedef struct les_step_stats {
   double res_rel_max;           /* max over solves of res_norm / rhs_norm */
   double seconds;               /* device time of the whole call */
   double poisson_seconds;       /* device time inside the solves */
+  double sweep_seconds;         /* time_sweeps: device time of the timed sweeps */
+  int64_t sweeps_timed;         /* time_sweeps: number of sweeps in sweep_seconds */
 } les_step_stats;
 
 typedef struct les_diag {

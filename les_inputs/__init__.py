@@ -102,11 +102,13 @@ WORKLOADS = {
     # 256x256x128, 35 m x 5 m, dt 0.3 s, tol 1e-6, fp32 storage.
     "C2": dict(nx=256, ny=256, nz=128, dx=35.0, dy=35.0, dz=5.0, dt=0.3,
                poisson_tol=1e-6, poisson_scheme="chebyshev", precision="fp32",
+               poisson_max_sweeps=20000,
                noise_qt=2.5e-5, shf=15.0, lhf=115.0, rad_F0=60.0, rad_kappa=100.0,
                seed=2),
     # 512x512x256 precision study.
     "C3": dict(nx=512, ny=512, nz=256, dx=35.0, dy=35.0, dz=5.0, dt=0.3,
                poisson_tol=1e-6, poisson_scheme="chebyshev", precision="fp32",
+               poisson_max_sweeps=40000,
                noise_qt=2.5e-5, shf=15.0, lhf=115.0, rad_F0=60.0, rad_kappa=100.0,
                seed=3),
     # 64^3 companion of C3 (same spacing and forcing) for oracle comparison.
@@ -117,11 +119,13 @@ WORKLOADS = {
     # Learned-guess evaluation grid (same as C2).
     "C4": dict(nx=256, ny=256, nz=128, dx=35.0, dy=35.0, dz=5.0, dt=0.3,
                poisson_tol=1e-6, poisson_scheme="chebyshev", precision="fp32",
+               poisson_max_sweeps=20000,
                noise_qt=2.5e-5, shf=15.0, lhf=115.0, rad_F0=60.0, rad_kappa=100.0,
                seed=2000),
     # Largest single-GPU domain.
     "C5": dict(nx=1024, ny=1024, nz=256, dx=35.0, dy=35.0, dz=5.0, dt=0.3,
                poisson_tol=1e-6, poisson_scheme="chebyshev", precision="fp32",
+               poisson_max_sweeps=80000,
                noise_qt=2.5e-5, shf=15.0, lhf=115.0, rad_F0=60.0, rad_kappa=100.0,
                seed=5),
 }

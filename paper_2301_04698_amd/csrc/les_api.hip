@@ -142,6 +142,7 @@ struct les_handle {
   double *diag_host;   // pinned, nz x kDiagStride
   hipEvent_t ev_a, ev_b, ev_s0, ev_s1;
   std::vector<hipEvent_t> ev_check;
+  std::vector<hipEvent_t> ev_sweep;  // pool bracketing runs of plain sweeps
   bool broken;
 };
 
@@ -266,9 +267,17 @@ int upload_profiles(les_handle *h) {
 // F_RHS.  If use_guess, F_PHI0 already holds the guess.  On return
 // *result points at the buffer holding the returned iterate (not yet
 // gauge-shifted; ctl->phi_mean is not computed here).
+// Device time of the runs of consecutive plain (non-check) sweeps of one
+// solve that lie before the returned iterate.
+struct SweepTiming {
+  bool enabled = false;
+  double seconds = 0.0;
+  int64_t sweeps = 0;
+};
+
 template <typename T>
 int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
-          les_solve_stats *st, T **result) {
+          les_solve_stats *st, T **result, SweepTiming *timing = nullptr) {
   const les_config &c = h->cfg;
   const Grid &g = h->grid;
   hipStream_t s = h->stream;
@@ -298,9 +307,29 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
   const int lag = 2;
   std::vector<int> pending;  // check indices queued, in order
   size_t next_wait = 0;
+  // timed runs: [first sweep, last sweep] with their event pair
+  struct Run {
+    int first, last;
+  };
+  std::vector<Run> runs;
+  const bool timed = timing && timing->enabled;
+  int run_first = -1;
+  auto is_check = [&](int mm) {
+    return fixed > 0 ? (mm == max_sweeps) : (mm % every == 0 || mm == max_sweeps);
+  };
   int m = 0;
   for (; m <= max_sweeps; ++m) {
-    const bool check = fixed > 0 ? (m == max_sweeps) : (m % every == 0 || m == max_sweeps);
+    const bool check = is_check(m);
+    if (timed && !check && run_first < 0) {
+      const size_t e = 2 * runs.size();
+      while (h->ev_sweep.size() < e + 2) {
+        hipEvent_t ev;
+        HIP_TRY(hipEventCreate(&ev));
+        h->ev_sweep.push_back(ev);
+      }
+      HIP_TRY(hipEventRecord(h->ev_sweep[e], s));
+      run_first = m;
+    }
     if (cheb) {
       if (m == 0) wc = 1.0;
       else if (m == 1) wc = 1.0 / (1.0 - 0.5 * rho * rho);
@@ -310,6 +339,11 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
     // The first Chebyshev step has weight 1 and is the plain weighted-Jacobi
     // sweep: it must not read the (uninitialised) previous iterate.
     launch_sweep<T>(g, cheb && m > 0, check, omega_j, wc, cur, nxt, nxt, rhs, V.ctl, V.partials, s);
+    if (timed && run_first >= 0 && (m == max_sweeps || is_check(m + 1))) {
+      HIP_TRY(hipEventRecord(h->ev_sweep[2 * runs.size() + 1], s));
+      runs.push_back(Run{run_first, m});
+      run_first = -1;
+    }
     if (check) {
       launch_final(V.partials, nblocks, kFinalCheck, V.ctl, (double)g.n, 0.0, m, nullptr, s);
       LAUNCH_TRY();
@@ -325,10 +359,24 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
       }
     }
   }
+  if (timed && run_first >= 0) {  // loop left inside a run
+    HIP_TRY(hipEventRecord(h->ev_sweep[2 * runs.size() + 1], s));
+    runs.push_back(Run{run_first, m > max_sweeps ? max_sweeps : m});
+  }
   HIP_TRY(hipEventRecord(h->ev_s1, s));
   HIP_TRY(hipMemcpyAsync(&h->ctl_host[0], V.ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   const SolveCtl &r = h->ctl_host[0];
+  if (timed) {
+    // only runs made entirely of sweeps applied before the returned iterate
+    for (size_t q = 0; q < runs.size(); ++q) {
+      if (runs[q].last >= r.stop_m) continue;
+      float rms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&rms, h->ev_sweep[2 * q], h->ev_sweep[2 * q + 1]));
+      timing->seconds += rms * 1e-3;
+      timing->sweeps += runs[q].last - runs[q].first + 1;
+    }
+  }
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, h->ev_s0, h->ev_s1));
   if (r.done == 0 || r.stop_m < 0)
@@ -404,7 +452,11 @@ int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step
         return fail(LES_ERR_ARG, "replay_sweeps[%d] = %d < 0", solve_idx, fixed);
       les_solve_stats st;
       T *phi = nullptr;
-      int rc = solve<T>(h, V, V.f[F_RHS], false, fixed, &st, &phi);
+      SweepTiming timing;
+      timing.enabled = opts && opts->time_sweeps;
+      int rc = solve<T>(h, V, V.f[F_RHS], false, fixed, &st, &phi, &timing);
+      acc.sweep_seconds += timing.seconds;
+      acc.sweeps_timed += timing.sweeps;
       if (opts && opts->records) opts->records[solve_idx] = st;
       if (rc < 0) return rc;
       acc.solves++;
@@ -694,6 +746,7 @@ void les_destroy(les_handle *h) {
   if (h->ev_s1) (void)hipEventDestroy(h->ev_s1);
   if (h->ev_a) (void)hipEventDestroy(h->ev_a);
   if (h->ev_b) (void)hipEventDestroy(h->ev_b);
+  for (auto &e : h->ev_sweep) (void)hipEventDestroy(e);
   if (h->ctl_host) (void)hipHostFree(h->ctl_host);
   if (h->diag_host) (void)hipHostFree(h->diag_host);
   delete h;

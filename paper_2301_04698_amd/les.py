@@ -69,14 +69,16 @@ class LesPoissonOpts(C.Structure):
 
 
 class LesStepOpts(C.Structure):
-    _fields_ = [("replay_sweeps", C.POINTER(C.c_int32)), ("records", C.POINTER(LesSolveStats))]
+    _fields_ = [("replay_sweeps", C.POINTER(C.c_int32)), ("records", C.POINTER(LesSolveStats)),
+                ("time_sweeps", C.c_int32), ("reserved", C.c_int32)]
 
 
 class LesStepStats(C.Structure):
     _fields_ = [("steps", C.c_int32), ("solves", C.c_int32), ("sweeps_total", C.c_int64),
                 ("sweeps_max", C.c_int32), ("not_converged", C.c_int32),
                 ("res_rel_max", C.c_double), ("seconds", C.c_double),
-                ("poisson_seconds", C.c_double)]
+                ("poisson_seconds", C.c_double), ("sweep_seconds", C.c_double),
+                ("sweeps_timed", C.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -219,10 +221,11 @@ class LES:
     def _n(self):
         return self.cfg.nx * self.cfg.ny * self.cfg.nz
 
-    def step(self, nsteps=1, replay=None, records=False):
+    def step(self, nsteps=1, replay=None, records=False, time_sweeps=False):
         """Advance nsteps; returns (rc, stats dict, per-solve records or None)."""
         K = self.cfg.n_subiter
         opts = LesStepOpts()
+        opts.time_sweeps = 1 if time_sweeps else 0
         rec = None
         keep = []
         if replay is not None:

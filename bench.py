@@ -25,6 +25,27 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
+# HBM bytes per launch of the one-sweep Chebyshev kernel measured with
+# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (FETCH scaled x2.0, WRITE x1.0 by a
+# 1 GiB copy calibration); see profiles/sweep_kernel_hbm_traffic_pmc.md.
+# Valid only for the sweep source it was taken on (sha256 prefix).
+SWEEP_SOURCE = os.path.join(ROOT, "paper_2301_04698_amd", "csrc", "k_tsweep.hip")
+MEASURED_TRAFFIC = {
+    "sha256": "e7ce655fb8bec1ad",
+    "bytes": {(256, 256, 128): 104.9e6 + 33.6e6, (512, 512, 256): 981.5e6 + 268.4e6},
+}
+
+
+def measured_traffic(p, S):
+    import hashlib
+    if S != 1:
+        return None
+    with open(SWEEP_SOURCE, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    if sha != MEASURED_TRAFFIC["sha256"]:
+        return None
+    return MEASURED_TRAFFIC["bytes"].get((p["nx"], p["ny"], p["nz"]))
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -35,7 +56,60 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-crop", type=int, default=128,
                     help="horizontal size of the crop the oracle's non-Poisson work is timed on")
+    ap.add_argument("--mode", choices=("step", "sweeps", "copy"), default="step",
+                    help="step: the LES step benchmark; sweeps: a fixed number of Poisson "
+                         "sweeps on the workload's grid; copy: a device-to-device copy of "
+                         "--bytes bytes (calibrates the HBM byte counters)")
+    ap.add_argument("--sweeps", type=int, default=200)
+    ap.add_argument("--sweeps-per-launch", type=int, default=0)
+    ap.add_argument("--bytes", type=int, default=1 << 30)
     return ap.parse_args()
+
+
+def run_sweeps(args):
+    """Fixed-count Poisson solve on a seeded right-hand side of the
+    workload's grid; per-sweep time from HIP events around the solve."""
+    import numpy as np
+    import torch
+
+    import les_inputs as li
+    from paper_2301_04698_amd import les
+
+    p = li.workload(args.workload, sweeps_per_launch=args.sweeps_per_launch)
+    shape = (p["nz"], p["ny"], p["nx"])
+    n = p["nx"] * p["ny"] * p["nz"]
+    sim = les.LES(p, device="cuda:0")
+    dt = torch.float32 if p["precision"] == "fp32" else torch.float64
+    rhs = torch.from_numpy(li.random_field(shape, seed=3)).to("cuda:0", dt)
+    sim.poisson_solve(rhs, fixed_sweeps=10)
+    _, st, _ = sim.poisson_solve(rhs, fixed_sweeps=args.sweeps)
+    per = st["seconds"] / args.sweeps
+    bpc = sweep_bytes_per_cell(p)
+    print(json.dumps({
+        "mode": "sweeps", "workload": args.workload, "grid": [p["nx"], p["ny"], p["nz"]],
+        "precision": p["precision"], "scheme": p["poisson_scheme"], "sweeps": args.sweeps,
+        "us_per_sweep": per * 1e6, "bytes_per_sweep": bpc * n,
+        "algorithmic_GBs": bpc * n / per / 1e9, "frac_of_8TBs": bpc * n / per / 1e9 / HBM_PEAK_GBS,
+        "note": "solve time includes rhs centring and the final residual check"}), flush=True)
+
+
+def run_copy(args):
+    import torch
+    n = args.bytes // 4
+    a = torch.ones(n, device="cuda:0", dtype=torch.float32)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n,
+                      "us_per_copy": s * 1e6, "GBs_read_plus_write": 8 * n / s / 1e9}), flush=True)
 
 
 def sweep_bytes_per_cell(p):
@@ -97,7 +171,11 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    p = li.workload(args.workload)
+    if args.mode == "sweeps":
+        return run_sweeps(args)
+    if args.mode == "copy":
+        return run_copy(args)
+    p = li.workload(args.workload, sweeps_per_launch=args.sweeps_per_launch)
     ncell = p["nx"] * p["ny"] * p["nz"]
     sim = les.LES(p, li.initial_state(p), device="cuda:0")
 
@@ -118,9 +196,13 @@ def main():
     ms_step = wall / args.steps * 1e3
     value = ncell * args.steps / wall / 1e6
 
+    S = sim.cfg.sweeps_per_launch or 1
     avg_sweep = st["sweep_seconds"] / max(st["sweeps_timed"], 1)
-    bytes_launch = sweep_bytes_per_cell(p) * ncell
-    achieved = bytes_launch / avg_sweep / 1e9
+    avg_launch = avg_sweep * S
+    es = 4 if p["precision"] == "fp32" else 8
+    # one sweep: sweep_bytes_per_cell; two fused sweeps: 3 arrays in, 2 out
+    bytes_launch = (sweep_bytes_per_cell(p) if S == 1 else 5 * es) * ncell
+    achieved = bytes_launch / avg_launch / 1e9
     diag = sim.diagnostics()
 
     out = {
@@ -153,13 +235,15 @@ def main():
         "cfl": diag["cfl"],
         "roofline": {
             "bound": "hbm",
-            "kernel": f"sweep_kernel<{'float' if p['precision'] == 'fp32' else 'double'}, cheb>",
+            "kernel": (f"sweep{S}_kernel<{'float' if p['precision'] == 'fp32' else 'double'}, "
+                       f"{'true' if p['poisson_scheme'] == 'chebyshev' else 'false'}, false>"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "avg_launch_us": avg_sweep * 1e6,
+            "traffic": measured_traffic(p, sim.cfg.sweeps_per_launch or 1),
+            "avg_launch_us": avg_launch * 1e6,
+            "sweeps_per_launch": S,
             "bytes_per_launch": bytes_launch,
             "note": ("working set of the sweep is about 134 MB, inside the 256 MB Infinity Cache"
                      if bytes_launch < 256e6 else "working set exceeds the 256 MB Infinity Cache"),

@@ -60,7 +60,8 @@ typedef struct les_config {
   int32_t poisson_check_every;  /* residual checked every m sweeps, m >= 1 */
   int32_t poisson_max_sweeps;   /* cap per solve */
   int32_t satadj_maxit;         /* secant iteration cap */
-  int32_t reserved0;
+  int32_t sweeps_per_launch;    /* Poisson sweeps fused per kernel launch, 0..2
+                                   (0: default); results do not depend on it */
   double dx, dy, dz, dt;        /* m, m, m, s; all > 0 */
   double poisson_tol;           /* stop when ||rhs - L phi||_2 <= tol ||rhs||_2 */
   double jacobi_omega;          /* 0 selects 2/(mu_min+mu_max) */
@@ -146,7 +147,7 @@ size_t les_workspace_bytes(const les_config *cfg);
  * 0 u^n, 1 v^n, 2 w^n, 3 thl^{n+1/2}, 4 qt^{n+1/2}, 5 thl_mid, 6 qt_mid,
  * 7..9 u,v,w at n+1/2, 10 b^{n+1/2}, 11 b_mid, 12 ql_mid, 13 c_pm*Pi (mid),
  * 14 nu scalars, 15 nu momentum, 16 radiative heating, 17 Poisson rhs,
- * 18 phi buffer 0, 19 phi buffer 1. */
+ * 18..21 Poisson iterate buffers 0..3. */
 int les_workspace_offset(const les_config *cfg, int32_t field, size_t *offset);
 
 /* Validates cfg and buffers, computes the reference state (Sec. 2.1) and

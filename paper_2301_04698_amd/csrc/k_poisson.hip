@@ -1,7 +1,7 @@
 // Pressure-correction Poisson path (paper Sec. 2.4 and App. A): right-hand
-// side with the collocated-grid correction, weighted-Jacobi sweeps with a
-// fused FP64 residual norm, projection, and the fixed-order FP64 reductions
-// that drive the device-side stopping test.
+// side with the collocated-grid correction, projection, and the fixed-order
+// FP64 reductions that drive the device-side stopping test.  The sweeps are
+// in k_tsweep.hip.
 #include "les_device.h"
 
 namespace lesmi {
@@ -69,80 +69,6 @@ __global__ __launch_bounds__(kBlock) void center_kernel(int64_t n, const T *in, 
   }
   const double s = block_sum(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
-}
-
-// Logical tile of physical block b.  Workgroups are dealt to the 8 XCDs
-// round-robin (b mod 8); this remap gives each XCD one contiguous range of
-// tiles (x fastest, then y, then z chunk), so the y/z neighbours a tile
-// reads were fetched into that XCD's L2 by its neighbours.
-__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
-  const int per = nblocks >> 3;  // nblocks is a multiple of 8
-  return (b & 7) * per + (b >> 3);
-}
-
-// One sweep of the compact 7-point operator (periodic x/y, mirror z):
-//   r         = rhs - L phi = rhs - (N(phi) - D phi), N = off-diagonal sum
-//   J(phi)    = phi - omega_j r / D          (weighted Jacobi)
-//   Jacobi:     out = J(phi)
-//   Chebyshev:  out = prev + omega_c (J(phi) - prev)   (out may alias prev)
-// The residual and the update are formed in FP64 from the stored values and
-// rounded once to the storage type: an FP32 update written as
-// (N - rhs)/D - phi cancels catastrophically and its rounding error, the
-// same from sweep to sweep, accumulates in the slow modes.
-// CHECK: also FP64 partial sums of r^2 for the input iterate.
-// Each thread owns one (i, j) column of a 64 x 4 tile and marches kc
-// levels keeping phi(k-1), phi(k), phi(k+1) in registers.
-template <typename T, bool CHEB, bool CHECK>
-__global__ __launch_bounds__(kSweepTX *kSweepTY) void sweep_kernel(
-    Grid g, int kc, int tiles_x, int tiles_y, int ntiles, double ix2, double iy2, double iz2,
-    double diag, double inv_diag, double omega_j, double omega_c, const T *__restrict__ phi,
-    const T *prev, T *out,
-    const T *__restrict__ rhs, const SolveCtl *__restrict__ ctl, double *__restrict__ partials) {
-  if (ctl->done) return;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  double acc = 0.0;
-  if (tile < ntiles) {
-    const int tx = tile % tiles_x;
-    const int rest = tile / tiles_x;
-    const int ty = rest % tiles_y;
-    const int tz = rest / tiles_y;
-    const int i = tx * kSweepTX + (threadIdx.x & (kSweepTX - 1));
-    const int j = ty * kSweepTY + (threadIdx.x / kSweepTX);
-    if (i < g.nx && j < g.ny) {
-      const int k0 = tz * kc;
-      const int k1 = min(g.nz, k0 + kc);
-      const int ip = i + 1 == g.nx ? 0 : i + 1, im = i == 0 ? g.nx - 1 : i - 1;
-      const int jp = j + 1 == g.ny ? 0 : j + 1, jm = j == 0 ? g.ny - 1 : j - 1;
-      const int64_t col = (int64_t)i + (int64_t)g.nx * j;
-      const int64_t oxp = ip - i, oxm = im - i;
-      const int64_t oyp = (int64_t)(jp - j) * g.nx, oym = (int64_t)(jm - j) * g.nx;
-      T below = phi[col + g.nxy * (k0 > 0 ? k0 - 1 : 0)];
-      T cur = phi[col + g.nxy * k0];
-      for (int k = k0; k < k1; ++k) {
-        const int64_t q = col + g.nxy * k;
-        const T above = phi[q + (k + 1 < g.nz ? g.nxy : 0)];
-        const double hx = (double)phi[q + oxp] + (double)phi[q + oxm];
-        const double hy = (double)phi[q + oyp] + (double)phi[q + oym];
-        const double hz = (double)above + (double)below;
-        const double c0 = (double)cur;
-        const double res = (double)rhs[q] - (hx * ix2 + hy * iy2 + hz * iz2 - diag * c0);
-        if (CHECK) acc += res * res;
-        const double jac = c0 - omega_j * res * inv_diag;
-        if (CHEB) {
-          const double pv = (double)prev[q];
-          out[q] = (T)(pv + omega_c * (jac - pv));
-        } else {
-          out[q] = (T)jac;
-        }
-        below = cur;
-        cur = above;
-      }
-    }
-  }
-  if (CHECK) {
-    const double s = block_sum(acc);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
-  }
 }
 
 // U^{k+1} = U_hat - dt rho0 grad_c phi (stored as velocity), p += rho0 (phi - mean).
@@ -259,31 +185,7 @@ __global__ void ctl_reset_kernel(SolveCtl *ctl, int max_sweeps, int fixed) {
   ctl->fixed = fixed;
 }
 
-struct SweepShape {
-  int kc, tiles_x, tiles_y, ntiles, blocks;
-};
-
-SweepShape sweep_shape(const Grid &g) {
-  SweepShape s;
-  s.tiles_x = (g.nx + kSweepTX - 1) / kSweepTX;
-  s.tiles_y = (g.ny + kSweepTY - 1) / kSweepTY;
-  s.kc = kSweepKC;
-  for (;;) {
-    const int tz = (g.nz + s.kc - 1) / s.kc;
-    const int64_t nt = (int64_t)s.tiles_x * s.tiles_y * tz;
-    if (nt <= kPartials || s.kc >= g.nz) {
-      s.ntiles = (int)nt;
-      break;
-    }
-    s.kc *= 2;
-  }
-  s.blocks = (s.ntiles + 7) / 8 * 8;
-  return s;
-}
-
 }  // namespace
-
-int sweep_grid_blocks(const Grid &g) { return sweep_shape(g).blocks; }
 
 template <typename T>
 void launch_poisson_rhs(const Grid &g, const Dyn<T> &d, const Profiles<T> &P, const T *u,
@@ -297,28 +199,6 @@ template <typename T>
 void launch_rhs_center(const Grid &g, const T *rhs_in, T *rhs_out, T *phi0, const SolveCtl *ctl,
                        double *partials, hipStream_t s) {
   center_kernel<T><<<kReduceBlocks, kBlock, 0, s>>>(g.n, rhs_in, rhs_out, phi0, ctl, partials);
-}
-
-template <typename T>
-void launch_sweep(const Grid &g, bool chebyshev, bool check, double omega_jacobi, double omega_cheb,
-                  const T *phi, const T *prev, T *out, const T *rhs, const SolveCtl *ctl,
-                  double *partials, hipStream_t s) {
-  const SweepShape sh = sweep_shape(g);
-  const double ix2 = 1.0 / (g.dx * g.dx), iy2 = 1.0 / (g.dy * g.dy), iz2 = 1.0 / (g.dz * g.dz);
-  const double diag = 2.0 * (ix2 + iy2 + iz2), inv_diag = 1.0 / diag;
-  const dim3 grid(sh.blocks), block(kSweepTX * kSweepTY);
-#define LES_SWEEP(CH, CK)                                                                          \
-  sweep_kernel<T, CH, CK><<<grid, block, 0, s>>>(g, sh.kc, sh.tiles_x, sh.tiles_y, sh.ntiles, ix2, \
-                                                 iy2, iz2, diag, inv_diag, omega_jacobi,          \
-                                                 omega_cheb, phi, prev, out, rhs, ctl, partials)
-  if (chebyshev) {
-    if (check) LES_SWEEP(true, true);
-    else LES_SWEEP(true, false);
-  } else {
-    if (check) LES_SWEEP(false, true);
-    else LES_SWEEP(false, false);
-  }
-#undef LES_SWEEP
 }
 
 template <typename T>
@@ -352,8 +232,6 @@ void launch_ctl_reset(SolveCtl *ctl, int max_sweeps, int fixed, hipStream_t s) {
                                       hipStream_t);                                              \
   template void launch_rhs_center<T>(const Grid &, const T *, T *, T *, const SolveCtl *,        \
                                      double *, hipStream_t);                                     \
-  template void launch_sweep<T>(const Grid &, bool, bool, double, double, const T *, const T *,  \
-                                T *, const T *, const SolveCtl *, double *, hipStream_t);        \
   template void launch_project<T>(const Grid &, const Dyn<T> &, const Profiles<T> &, const T *,  \
                                   const SolveCtl *, T *, T *, T *, T *, hipStream_t);            \
   template void launch_sub_mean<T>(const Grid &, const T *, const SolveCtl *, T *, hipStream_t); \

@@ -1,0 +1,353 @@
+// Weighted-Jacobi / Chebyshev sweeps of the compact 7-point
+// pressure-correction operator (paper Sec. 2.4 and App. A), one or two
+// sweeps per launch.
+//
+// Point update, shared by every kernel so their results are bitwise equal:
+//   r   = rhs - (N(phi) - D phi)     N: off-diagonal neighbour sum, FP64
+//   J   = phi - omega_j r / D         (weighted Jacobi)
+//   out = J, or Chebyshev: prev + omega_c (J - prev)
+// formed in FP64 from the stored values with explicit FMAs (no other
+// contraction) and rounded once to the storage type.  An FP32 update
+// written as (N - rhs)/D - phi cancels catastrophically; its rounding error
+// is the same from sweep to sweep and accumulates in the slow modes.
+//
+// One sweep: each thread owns one column of a 64 x 4 thread tile and
+// marches up z with the vertical neighbours in registers; x/y neighbours
+// come through the L1/L2 caches.  16 bytes per cell (Chebyshev: phi, prev,
+// rhs in, phi' out).
+//
+// Two sweeps: a 64 x TY thread tile covers a 62 x (TY-2) core plus a
+// one-cell ring.  Every thread computes the first sweep for its own column
+// as above; the second sweep, on the core only, takes the first sweep's x/y
+// neighbours from a ring of LDS planes and its z neighbours from the
+// thread's own registers.  20 bytes per cell for both sweeps.
+//
+// Walls: the z neighbour of the bottom/top level is that level itself (even
+// mirror); x and y are periodic.
+#include "les_device.h"
+
+namespace lesmi {
+
+namespace {
+
+struct SweepCoef {
+  double ix2, iy2, iz2, diag, inv_diag, omega_j;
+};
+
+__device__ __forceinline__ double point_residual(const SweepCoef &k, double c0, double hx,
+                                                 double hy, double hz, double rhs) {
+#pragma clang fp contract(off)
+  const double lap = fma(hx, k.ix2, fma(hy, k.iy2, fma(hz, k.iz2, -k.diag * c0)));
+  return rhs - lap;
+}
+
+__device__ __forceinline__ double point_update(const SweepCoef &k, double c0, double res,
+                                               bool cheb, double pv, double wc) {
+#pragma clang fp contract(off)
+  const double jac = fma(-k.omega_j * k.inv_diag, res, c0);
+  return cheb ? fma(wc, jac - pv, pv) : jac;
+}
+
+__device__ __forceinline__ int pmod(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// Logical tile of physical block b.  Workgroups go to the 8 XCDs
+// round-robin (b mod 8); each XCD gets one contiguous range of tiles
+// (x fastest, then y, then z chunk), so the y halos a tile reads were
+// fetched into the same L2 by its neighbours.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+  const int per = nblocks >> 3;  // nblocks is a multiple of 8
+  return (b & 7) * per + (b >> 3);
+}
+
+template <typename T>
+struct SweepArgs {
+  Grid g;
+  SweepCoef k;
+  int kc, tiles_x, tiles_y, tiles_z, ntiles;
+  double wc0, wc1;   // Chebyshev weights of the launch's first and second sweep
+  int first;         // the first sweep is the first of the solve (weight 1, no prev)
+  const T *cur, *prev, *rhs;
+  T *out_last, *out_prev;
+  const SolveCtl *ctl;
+  double *partials;
+};
+
+struct TileIdx {
+  int tx, ty, k0, k1;
+};
+
+__device__ __forceinline__ TileIdx tile_of(int tile, int tiles_x, int tiles_y, int kc, int nz) {
+  TileIdx t;
+  t.tx = tile % tiles_x;
+  const int rest = tile / tiles_x;
+  t.ty = rest % tiles_y;
+  t.k0 = (rest / tiles_y) * kc;
+  t.k1 = min(nz, t.k0 + kc);
+  return t;
+}
+
+// ---------------------------------------------------------------- 1 sweep
+
+constexpr int kTY1 = 4;
+
+template <typename T, bool CHEB, bool CHECK>
+__global__ __launch_bounds__(64 * kTY1) void sweep1_kernel(SweepArgs<T> a) {
+  if (a.ctl->done) return;
+  const Grid &g = a.g;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  double acc = 0.0;
+  if (tile < a.ntiles) {
+    const TileIdx t = tile_of(tile, a.tiles_x, a.tiles_y, a.kc, g.nz);
+    const int i = t.tx * 64 + (int)(threadIdx.x & 63);
+    const int j = t.ty * kTY1 + (int)(threadIdx.x >> 6);
+    if (i < g.nx && j < g.ny) {
+      const int ip = i + 1 == g.nx ? 0 : i + 1, im = i == 0 ? g.nx - 1 : i - 1;
+      const int jp = j + 1 == g.ny ? 0 : j + 1, jm = j == 0 ? g.ny - 1 : j - 1;
+      const int64_t col = (int64_t)i + (int64_t)g.nx * j;
+      const int64_t oxp = ip - i, oxm = im - i;
+      const int64_t oyp = (int64_t)(jp - j) * g.nx, oym = (int64_t)(jm - j) * g.nx;
+      const bool cheb = CHEB && !a.first;
+      T below = a.cur[col + g.nxy * (t.k0 > 0 ? t.k0 - 1 : 0)];
+      T c = a.cur[col + g.nxy * t.k0];
+      for (int k = t.k0; k < t.k1; ++k) {
+        const int64_t q = col + g.nxy * k;
+        const T above = a.cur[q + (k + 1 < g.nz ? g.nxy : 0)];
+        const double hx = (double)a.cur[q + oxp] + (double)a.cur[q + oxm];
+        const double hy = (double)a.cur[q + oyp] + (double)a.cur[q + oym];
+        const double hz = (double)above + (double)below;
+        const double res = point_residual(a.k, (double)c, hx, hy, hz, (double)a.rhs[q]);
+        if (CHECK) acc += res * res;
+        const double pv = cheb ? (double)a.prev[q] : 0.0;
+        a.out_last[q] = (T)point_update(a.k, (double)c, res, cheb, pv, a.wc0);
+        below = c;
+        c = above;
+      }
+    }
+  }
+  if (CHECK) {
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = s;
+  }
+}
+
+// --------------------------------------------------------------- 2 sweeps
+
+constexpr int kU2 = 2;  // planes per barrier in the two-sweep kernel
+
+template <typename T, int TY, bool CHEB, bool CHECK>
+__global__ __launch_bounds__(64 * TY) void sweep2_kernel(SweepArgs<T> a) {
+  if (a.ctl->done) return;
+  // First-sweep planes, slot k mod R.  A batch writes kU2 planes and reads
+  // kU2 planes starting one below; R = 2 kU2 + 1 keeps the next batch's
+  // writes clear of slower threads still reading, with one barrier per batch.
+  constexpr int kU = kU2;
+  constexpr int R = 2 * kU + 1;
+  __shared__ T lvl1[R][TY][64];
+  const Grid &g = a.g;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+  double acc = 0.0;
+  if (tile < a.ntiles) {
+    const TileIdx t = tile_of(tile, a.tiles_x, a.tiles_y, a.kc, g.nz);
+    // unwrapped coordinates of this thread's column; the core is
+    // lx in [1, 63), ly in [1, TY-1)
+    const int xu = t.tx * 62 - 1 + lx, yu = t.ty * (TY - 2) - 1 + ly;
+    const bool core = lx >= 1 && lx < 63 && ly >= 1 && ly < TY - 1 && xu < g.nx && yu < g.ny;
+    const int i = pmod(xu, g.nx), j = pmod(yu, g.ny);
+    const int ip = i + 1 == g.nx ? 0 : i + 1, im = i == 0 ? g.nx - 1 : i - 1;
+    const int jp = j + 1 == g.ny ? 0 : j + 1, jm = j == 0 ? g.ny - 1 : j - 1;
+    const int64_t col = (int64_t)i + (int64_t)g.nx * j;
+    const int64_t oxp = ip - i, oxm = im - i;
+    const int64_t oyp = (int64_t)(jp - j) * g.nx, oym = (int64_t)(jm - j) * g.nx;
+    const bool cheb1 = CHEB && !a.first, cheb2 = CHEB;
+    // first-sweep planes [kb, ke]; second sweep on [k0, k1)
+    const int kb = max(0, t.k0 - 1), ke = min(g.nz - 1, t.k1);
+    T below = a.cur[col + g.nxy * (kb > 0 ? kb - 1 : 0)];
+    T c = a.cur[col + g.nxy * kb];
+    // own-column values of the two planes below the current batch
+    T l1_m1 = T(0), l1_m2 = T(0), c_m1 = T(0), r_m1 = T(0);
+    for (int kbase = kb; kbase <= ke; kbase += kU) {
+      const int nb = min(kU, ke - kbase + 1);
+      T ab[kU], xp[kU], xm[kU], yp[kU], ym[kU], rr[kU], pp[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        if (u < nb) {
+          const int k = kbase + u;
+          const int64_t q = col + g.nxy * k;
+          ab[u] = a.cur[q + (k + 1 < g.nz ? g.nxy : 0)];
+          xp[u] = a.cur[q + oxp];
+          xm[u] = a.cur[q + oxm];
+          yp[u] = a.cur[q + oyp];
+          ym[u] = a.cur[q + oym];
+          rr[u] = a.rhs[q];
+          pp[u] = cheb1 ? a.prev[q] : T(0);
+        }
+      }
+      // ---- first sweep on planes kbase .. kbase+nb-1 (whole 64 x TY tile)
+      T l1v[kU], cv[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        l1v[u] = T(0);
+        cv[u] = T(0);
+        if (u < nb) {
+          const int k = kbase + u;
+          const int64_t q = col + g.nxy * k;
+          const double hx = (double)xp[u] + (double)xm[u];
+          const double hy = (double)yp[u] + (double)ym[u];
+          const double hz = (double)ab[u] + (double)below;
+          const double res = point_residual(a.k, (double)c, hx, hy, hz, (double)rr[u]);
+          const bool core_plane = k >= t.k0 && k < t.k1;
+          if (CHECK && core && core_plane) acc += res * res;
+          const T l1 = (T)point_update(a.k, (double)c, res, cheb1, (double)pp[u], a.wc0);
+          lvl1[k % R][ly][lx] = l1;
+          if (CHEB && core && core_plane) a.out_prev[q] = l1;
+          l1v[u] = l1;
+          cv[u] = c;
+          below = c;
+          c = ab[u];
+        }
+      }
+      __syncthreads();
+      // ---- second sweep on planes kk = kbase-1+u, u = 0 .. nb (the last
+      // one only for the top level), core columns only
+#pragma unroll
+      for (int u = 0; u <= kU; ++u) {
+        const int kk = kbase - 1 + u;
+        const bool valid = u < nb || (u == nb && kk == g.nz - 1);
+        if (!valid || !core || kk < t.k0 || kk >= t.k1) continue;
+        const T ctr = u == 0 ? l1_m1 : l1v[u - 1 < 0 ? 0 : u - 1];
+        const T lo = kk == 0 ? ctr : (u == 0 ? l1_m2 : (u == 1 ? l1_m1 : l1v[u - 2 < 0 ? 0 : u - 2]));
+        const T hi = kk + 1 == g.nz ? ctr : l1v[u < kU ? u : kU - 1];
+        const T *pl = &lvl1[kk % R][0][0];
+        const double h2x = (double)pl[ly * 64 + lx + 1] + (double)pl[ly * 64 + lx - 1];
+        const double h2y = (double)pl[(ly + 1) * 64 + lx] + (double)pl[(ly - 1) * 64 + lx];
+        const double h2z = (double)hi + (double)lo;
+        const double r2 = u == 0 ? (double)r_m1 : (double)rr[u - 1 < 0 ? 0 : u - 1];
+        const double pv2 = u == 0 ? (double)c_m1 : (double)cv[u - 1 < 0 ? 0 : u - 1];
+        const double res2 = point_residual(a.k, (double)ctr, h2x, h2y, h2z, r2);
+        a.out_last[col + g.nxy * kk] = (T)point_update(a.k, (double)ctr, res2, cheb2, pv2, a.wc1);
+      }
+      // history for the next batch (compile-time indices only)
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        if (u == nb - 1) {
+          l1_m2 = u >= 1 ? l1v[u >= 1 ? u - 1 : 0] : l1_m1;
+          l1_m1 = l1v[u];
+          c_m1 = cv[u];
+          r_m1 = rr[u];
+        }
+      }
+    }
+  }
+  if (CHECK) {
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = s;
+  }
+}
+
+constexpr int kTY2 = 8;  // two-sweep tile: 512 threads, core 62 x 6
+
+struct Shape {
+  int kc, tiles_x, tiles_y, tiles_z, ntiles, blocks;
+};
+
+Shape shape_of(const Grid &g, int S) {
+  Shape sh;
+  if (S == 1) {
+    sh.tiles_x = (g.nx + 63) / 64;
+    sh.tiles_y = (g.ny + kTY1 - 1) / kTY1;
+  } else {
+    sh.tiles_x = (g.nx + 61) / 62;
+    sh.tiles_y = (g.ny + kTY2 - 3) / (kTY2 - 2);
+  }
+  const int64_t cols = (int64_t)sh.tiles_x * sh.tiles_y;
+  // z chunks: long enough to amortise the halo planes, short enough for
+  // several blocks per CU
+  sh.kc = g.nz;
+  const int target = 2048;
+  while (sh.kc > 8 && cols * ((g.nz + sh.kc - 1) / sh.kc) < target) sh.kc = (sh.kc + 1) / 2;
+  sh.tiles_z = (g.nz + sh.kc - 1) / sh.kc;
+  int64_t nt = cols * sh.tiles_z;
+  while (nt > kPartials) {
+    sh.kc *= 2;
+    sh.tiles_z = (g.nz + sh.kc - 1) / sh.kc;
+    nt = cols * sh.tiles_z;
+  }
+  sh.ntiles = (int)nt;
+  sh.blocks = (sh.ntiles + 7) / 8 * 8;
+  return sh;
+}
+
+}  // namespace
+
+int tsweep_blocks(const Grid &g, int S, bool is_double) {
+  (void)is_double;
+  return shape_of(g, S).blocks;
+}
+
+template <typename T>
+void launch_tsweep(const Grid &g, int S, bool chebyshev, bool check, bool first,
+                   double omega_jacobi, const double *omega_cheb, const T *cur, const T *prev,
+                   T *out_last, T *out_prev, const T *rhs, const SolveCtl *ctl,
+                   double *partials, hipStream_t s) {
+  const Shape sh = shape_of(g, S);
+  SweepArgs<T> a;
+  a.g = g;
+  a.k.ix2 = 1.0 / (g.dx * g.dx);
+  a.k.iy2 = 1.0 / (g.dy * g.dy);
+  a.k.iz2 = 1.0 / (g.dz * g.dz);
+  a.k.diag = 2.0 * (a.k.ix2 + a.k.iy2 + a.k.iz2);
+  a.k.inv_diag = 1.0 / a.k.diag;
+  a.k.omega_j = omega_jacobi;
+  a.kc = sh.kc;
+  a.tiles_x = sh.tiles_x;
+  a.tiles_y = sh.tiles_y;
+  a.tiles_z = sh.tiles_z;
+  a.ntiles = sh.ntiles;
+  a.wc0 = omega_cheb[0];
+  a.wc1 = S > 1 ? omega_cheb[1] : 1.0;
+  a.first = first ? 1 : 0;
+  a.cur = cur;
+  a.prev = prev;
+  a.rhs = rhs;
+  a.out_last = out_last;
+  a.out_prev = out_prev;
+  a.ctl = ctl;
+  a.partials = partials;
+  const dim3 grid(sh.blocks);
+#define LES_PICK(KERNEL, BLOCK)                                           \
+  do {                                                                    \
+    if (chebyshev) {                                                      \
+      if (check) KERNEL<T, true, true><<<grid, BLOCK, 0, s>>>(a);         \
+      else KERNEL<T, true, false><<<grid, BLOCK, 0, s>>>(a);              \
+    } else {                                                              \
+      if (check) KERNEL<T, false, true><<<grid, BLOCK, 0, s>>>(a);        \
+      else KERNEL<T, false, false><<<grid, BLOCK, 0, s>>>(a);             \
+    }                                                                     \
+  } while (0)
+  if (S == 1) {
+    LES_PICK(sweep1_kernel, dim3(64 * kTY1));
+  } else {
+    const dim3 block(64 * kTY2);
+    if (chebyshev) {
+      if (check) sweep2_kernel<T, kTY2, true, true><<<grid, block, 0, s>>>(a);
+      else sweep2_kernel<T, kTY2, true, false><<<grid, block, 0, s>>>(a);
+    } else {
+      if (check) sweep2_kernel<T, kTY2, false, true><<<grid, block, 0, s>>>(a);
+      else sweep2_kernel<T, kTY2, false, false><<<grid, block, 0, s>>>(a);
+    }
+  }
+#undef LES_PICK
+}
+
+template void launch_tsweep<float>(const Grid &, int, bool, bool, bool, double, const double *,
+                                   const float *, const float *, float *, float *, const float *,
+                                   const SolveCtl *, double *, hipStream_t);
+template void launch_tsweep<double>(const Grid &, int, bool, bool, bool, double, const double *,
+                                    const double *, const double *, double *, double *,
+                                    const double *, const SolveCtl *, double *, hipStream_t);
+
+}  // namespace lesmi

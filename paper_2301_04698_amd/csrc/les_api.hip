@@ -1,7 +1,7 @@
 // C ABI of the LES library (include/les.h): validation, workspace layout,
 // reference state, and the stream-ordered orchestration of one time step
 // of the paper's iterative predictor-corrector scheme (Sec. 2.4).
-#include "../../include/les.h"
+#include "les.h"
 
 #include <hip/hip_runtime.h>
 
@@ -50,6 +50,7 @@ int fail(int code, const char *fmt, ...) {
 enum Field {
   F_UN = 0, F_VN, F_WN, F_THL_H, F_QT_H, F_THL_M, F_QT_M, F_UH, F_VH, F_WH,
   F_B_H, F_B_M, F_QL_M, F_CPMPI_M, F_NU_S, F_NU_M, F_RAD, F_RHS, F_PHI0, F_PHI1,
+  F_PHI2, F_PHI3,
   F_COUNT
 };
 
@@ -88,6 +89,8 @@ int validate(const les_config *c) {
   if (!(c->jacobi_omega >= 0) || c->jacobi_omega >= 2)
     return fail(LES_ERR_ARG, "jacobi_omega must be in [0, 2)");
   if (c->satadj_maxit < 0 || c->satadj_maxit > 1000) return fail(LES_ERR_ARG, "satadj_maxit out of range");
+  if (c->sweeps_per_launch < 0 || c->sweeps_per_launch > kMaxSweepsPerLaunch)
+    return fail(LES_ERR_ARG, "sweeps_per_launch must be in [0, %d]", kMaxSweepsPerLaunch);
   if (!(c->p00 > 0) || !(c->theta0 > 0) || !(c->Rd > 0) || !(c->Rv > 0) || !(c->cpd > 0))
     return fail(LES_ERR_ARG, "thermodynamic constants must be > 0");
   const double top = c->nz * c->dz;
@@ -138,6 +141,7 @@ struct les_handle {
   Grid grid;
   Thermo thermo;
   double mu_min, mu_max;
+  int sweeps_per_launch;  // temporal blocking depth of the Poisson sweeps
   SolveCtl *ctl_host;  // pinned mirror for the final read-back
   double *diag_host;   // pinned, nz x kDiagStride
   hipEvent_t ev_a, ev_b, ev_s0, ev_s1;
@@ -283,14 +287,13 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
   hipStream_t s = h->stream;
   const int max_sweeps = fixed > 0 ? fixed : c.poisson_max_sweeps;
   const int every = c.poisson_check_every;
-  T *buf[2] = {V.f[F_PHI0], V.f[F_PHI1]};
   T *rhs = V.f[F_RHS];
 
   HIP_TRY(hipEventRecord(h->ev_s0, s));
   launch_ctl_reset(V.ctl, max_sweeps, fixed > 0 ? 1 : 0, s);
   launch_block_sum(rhs_in, g.n, 0, V.partials, s);
   launch_final(V.partials, kReduceBlocks, kFinalRhsMean, V.ctl, (double)g.n, 0.0, 0, nullptr, s);
-  launch_rhs_center(g, rhs_in, rhs, use_guess ? (T *)nullptr : buf[0], V.ctl, V.partials, s);
+  launch_rhs_center(g, rhs_in, rhs, use_guess ? (T *)nullptr : V.f[F_PHI0], V.ctl, V.partials, s);
   launch_final(V.partials, kReduceBlocks, kFinalRhsNorm, V.ctl, (double)g.n,
                c.poisson_tol * c.poisson_tol, 0, nullptr, s);
   LAUNCH_TRY();
@@ -299,28 +302,51 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
   const double gamma = 2.0 / (h->mu_min + h->mu_max);
   const double rho = (h->mu_max - h->mu_min) / (h->mu_max + h->mu_min);
   const double omega_j = cheb ? gamma : (c.jacobi_omega > 0 ? c.jacobi_omega : gamma);
-  const int nblocks = sweep_grid_blocks(g);
-  double wc = 1.0;
+  const int smax = h->sweeps_per_launch;
 
-  // Queue sweeps; the device stops applying them once a check succeeds.
-  // Host polls a pinned copy of the control block after a bounded lag.
-  const int lag = 2;
-  std::vector<int> pending;  // check indices queued, in order
-  size_t next_wait = 0;
-  // timed runs: [first sweep, last sweep] with their event pair
-  struct Run {
-    int first, last;
-  };
-  std::vector<Run> runs;
-  const bool timed = timing && timing->enabled;
-  int run_first = -1;
+  // Launch plan: launches of up to smax sweeps; a residual check at sweep m
+  // is computed by the launch that starts at m (its input iterate is phi_m),
+  // so launches are cut at check positions.  Checks at every `every`-th
+  // sweep and at the cap (or only at the fixed count).
   auto is_check = [&](int mm) {
     return fixed > 0 ? (mm == max_sweeps) : (mm % every == 0 || mm == max_sweeps);
   };
-  int m = 0;
-  for (; m <= max_sweeps; ++m) {
-    const bool check = is_check(m);
-    if (timed && !check && run_first < 0) {
+  struct Launch {
+    int m, S;
+    bool check;
+  };
+  std::vector<Launch> plan;
+  for (int mm = 0; mm <= max_sweeps;) {
+    int S = 1;
+    if (mm < max_sweeps)
+      while (S < smax && mm + S < max_sweeps && !is_check(mm + S)) ++S;
+    plan.push_back(Launch{mm, S, is_check(mm)});
+    mm += S;
+  }
+
+  // Four iterate buffers: a launch reads (prev, cur) and writes its last two
+  // iterates into the two buffers it does not read.  Each check records the
+  // buffer that holds its input iterate.
+  T *buf[4] = {V.f[F_PHI0], V.f[F_PHI1], V.f[F_PHI2], V.f[F_PHI3]};
+  int cur = 0, prev = -1;
+  std::vector<std::pair<int, int>> check_buf;  // (m, buffer of phi_m)
+
+  // Queue launches; the device stops applying them once a check succeeds.
+  // The host polls a pinned copy of the control block after a bounded lag.
+  const int lag = 2;
+  size_t npending = 0, next_wait = 0;
+  struct Run {
+    int first, last;
+  };
+  std::vector<Run> runs;  // timed runs of full-size plain launches
+  const bool timed = timing && timing->enabled;
+  int run_first = -1;
+  double wc_prev = 1.0;  // Chebyshev weight recurrence
+  size_t li = 0;
+  for (; li < plan.size(); ++li) {
+    const Launch L = plan[li];
+    const bool plain_full = !L.check && L.S == smax;
+    if (timed && plain_full && run_first < 0) {
       const size_t e = 2 * runs.size();
       while (h->ev_sweep.size() < e + 2) {
         hipEvent_t ev;
@@ -328,40 +354,65 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
         h->ev_sweep.push_back(ev);
       }
       HIP_TRY(hipEventRecord(h->ev_sweep[e], s));
-      run_first = m;
+      run_first = L.m;
     }
-    if (cheb) {
-      if (m == 0) wc = 1.0;
-      else if (m == 1) wc = 1.0 / (1.0 - 0.5 * rho * rho);
-      else wc = 1.0 / (1.0 - 0.25 * rho * rho * wc);
+    double wc[4] = {1.0, 1.0, 1.0, 1.0};
+    for (int q = 0; q < L.S; ++q) {  // weight of sweep L.m + q
+      const int mm = L.m + q;
+      double w = 1.0;
+      if (cheb) {
+        if (mm == 0) w = 1.0;
+        else if (mm == 1) w = 1.0 / (1.0 - 0.5 * rho * rho);
+        else w = 1.0 / (1.0 - 0.25 * rho * rho * wc_prev);
+      }
+      wc[q] = w;
+      wc_prev = w;
     }
-    T *cur = buf[m & 1], *nxt = buf[(m + 1) & 1];
-    // The first Chebyshev step has weight 1 and is the plain weighted-Jacobi
-    // sweep: it must not read the (uninitialised) previous iterate.
-    launch_sweep<T>(g, cheb && m > 0, check, omega_j, wc, cur, nxt, nxt, rhs, V.ctl, V.partials, s);
-    if (timed && run_first >= 0 && (m == max_sweeps || is_check(m + 1))) {
+    int free_[4], nf = 0;
+    for (int q = 0; q < 4; ++q)
+      if (q != cur && q != prev) free_[nf++] = q;
+    const int out_last = L.S == 1 ? free_[0] : free_[1];
+    const int out_prev = L.S == 1 ? -1 : free_[0];
+    if (L.check) check_buf.emplace_back(L.m, cur);
+    // The first Chebyshev sweep has weight 1: the plain weighted-Jacobi
+    // sweep, which must not read the (uninitialised) previous iterate.
+    launch_tsweep<T>(g, L.S, cheb, L.check, L.m == 0, omega_j, wc, buf[cur],
+                     prev >= 0 ? buf[prev] : nullptr, buf[out_last],
+                     out_prev >= 0 ? buf[out_prev] : nullptr, rhs, V.ctl, V.partials, s);
+    if (L.S == 1) {
+      prev = cur;
+    } else {
+      prev = out_prev;
+    }
+    cur = out_last;
+    const bool next_plain_full =
+        li + 1 < plan.size() && !plan[li + 1].check && plan[li + 1].S == smax;
+    if (timed && run_first >= 0 && !next_plain_full) {
       HIP_TRY(hipEventRecord(h->ev_sweep[2 * runs.size() + 1], s));
-      runs.push_back(Run{run_first, m});
+      runs.push_back(Run{run_first, L.m + L.S - 1});
       run_first = -1;
     }
-    if (check) {
-      launch_final(V.partials, nblocks, kFinalCheck, V.ctl, (double)g.n, 0.0, m, nullptr, s);
+    if (L.check) {
+      // partial sums come from this launch's own block decomposition
+      launch_final(V.partials, tsweep_blocks(g, L.S, sizeof(T) == 8), kFinalCheck, V.ctl,
+                   (double)g.n, 0.0, L.m, nullptr, s);
       LAUNCH_TRY();
-      const size_t slot = pending.size() % h->ev_check.size();
+      const size_t slot = npending % h->ev_check.size();
       HIP_TRY(hipMemcpyAsync(&h->ctl_host[slot], V.ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipEventRecord(h->ev_check[slot], s));
-      pending.push_back(m);
-      if (pending.size() - next_wait > (size_t)lag) {
-        const size_t ws_ = next_wait % h->ev_check.size();
-        HIP_TRY(hipEventSynchronize(h->ev_check[ws_]));
+      ++npending;
+      if (npending - next_wait > (size_t)lag) {
+        const size_t w = next_wait % h->ev_check.size();
+        HIP_TRY(hipEventSynchronize(h->ev_check[w]));
         ++next_wait;
-        if (h->ctl_host[ws_].done) break;
+        if (h->ctl_host[w].done) break;
       }
     }
   }
+  LAUNCH_TRY();
   if (timed && run_first >= 0) {  // loop left inside a run
     HIP_TRY(hipEventRecord(h->ev_sweep[2 * runs.size() + 1], s));
-    runs.push_back(Run{run_first, m > max_sweeps ? max_sweeps : m});
+    runs.push_back(Run{run_first, plan[li < plan.size() ? li : plan.size() - 1].m});
   }
   HIP_TRY(hipEventRecord(h->ev_s1, s));
   HIP_TRY(hipMemcpyAsync(&h->ctl_host[0], V.ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, s));
@@ -380,13 +431,17 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, h->ev_s0, h->ev_s1));
   if (r.done == 0 || r.stop_m < 0)
-    return fail(LES_ERR_STATE, "Poisson solve ended without a decision (m=%d)", m);
+    return fail(LES_ERR_STATE, "Poisson solve ended without a decision");
+  int res_buf = -1;
+  for (const auto &cb : check_buf)
+    if (cb.first == r.stop_m) res_buf = cb.second;
+  if (res_buf < 0) return fail(LES_ERR_STATE, "Poisson solve stopped at an unchecked sweep");
   st->sweeps = r.stop_m;
   st->status = r.done == 1 ? 0 : (r.done == 3 ? 1 : -3);
   st->rhs_norm = std::sqrt(r.rhs_norm2);
   st->res_norm = std::sqrt(r.res_norm2);
   st->seconds = ms * 1e-3;
-  *result = buf[r.stop_m & 1];
+  *result = buf[res_buf];
   if (r.done == 2) return fail(LES_ERR_NONFINITE, "non-finite Poisson residual");
   return LES_OK;
 }
@@ -675,6 +730,7 @@ int les_init(const les_config *cfg, const les_buffers *bufs, void *stream, les_h
   t.satadj_tol = cfg->satadj_tol;
   t.satadj_maxit = cfg->satadj_maxit;
   jacobi_spectrum(cfg, &h->mu_min, &h->mu_max);
+  h->sweeps_per_launch = cfg->sweeps_per_launch > 0 ? cfg->sweeps_per_launch : kDefaultSweepsPerLaunch;
 
   auto cleanup = [&](int code) {
     les_destroy(h);

@@ -63,12 +63,13 @@ constexpr int kBlock = 256;          // threads per block of elementwise kernels
 constexpr int kReduceBlocks = 1024;  // fixed grid of the generic reductions
 constexpr int kPartials = 1 << 16;   // max partials of one reduction (sweep tiles)
 
-// Sweep tile: 64 x-cells (one wavefront) by 4 y-rows, marching KC levels.
-constexpr int kSweepTX = 64;
-constexpr int kSweepTY = 4;
-constexpr int kSweepKC = 16;
+// Temporally blocked Poisson sweeps: up to kMaxSweepsPerLaunch sweeps per
+// launch (kDefaultSweepsPerLaunch unless the configuration asks otherwise).
+constexpr int kMaxSweepsPerLaunch = 2;
+constexpr int kDefaultSweepsPerLaunch = 1;
 
-int sweep_grid_blocks(const Grid &g);
+// Blocks of a tsweep launch of S sweeps (its count of residual partials).
+int tsweep_blocks(const Grid &g, int S, bool is_double);
 
 // ------------------------------------------------------------ launchers
 template <typename T>
@@ -109,10 +110,15 @@ template <typename T>
 void launch_rhs_center(const Grid &g, const T *rhs_in, T *rhs_out, T *phi0, const SolveCtl *ctl,
                        double *partials, hipStream_t s);
 
+// S sweeps from (prev, cur) = (phi_{m-1}, phi_m) giving out_prev = phi_{m+S-1}
+// (S >= 2, Chebyshev) and out_last = phi_{m+S}; check: FP64 partial sums of
+// the residual of cur.  first: sweep m is the first of the solve.  omega_cheb:
+// S weights of sweeps m .. m+S-1.  Outputs never alias inputs.
 template <typename T>
-void launch_sweep(const Grid &g, bool chebyshev, bool check, double omega_jacobi, double omega_cheb,
-                  const T *phi, const T *prev, T *out, const T *rhs, const SolveCtl *ctl,
-                  double *partials, hipStream_t s);
+void launch_tsweep(const Grid &g, int S, bool chebyshev, bool check, bool first,
+                   double omega_jacobi, const double *omega_cheb, const T *cur, const T *prev,
+                   T *out_last, T *out_prev, const T *rhs, const SolveCtl *ctl,
+                   double *partials, hipStream_t s);
 
 template <typename T>
 void launch_project(const Grid &g, const Dyn<T> &d, const Profiles<T> &P, const T *phi,

@@ -24,7 +24,8 @@ PROFILE_NAMES = ("thl", "qt", "ql", "u", "v", "w", "w2", "w3", "b")
 
 # Workspace field ids (les_workspace_offset).
 WS_FIELDS = ("un", "vn", "wn", "thl_half", "qt_half", "thl_mid", "qt_mid", "uh", "vh", "wh",
-             "b_half", "b_mid", "ql_mid", "cpmpi_mid", "nu_s", "nu_m", "rad", "rhs", "phi0", "phi1")
+             "b_half", "b_mid", "ql_mid", "cpmpi_mid", "nu_s", "nu_m", "rad", "rhs", "phi0", "phi1",
+             "phi2", "phi3")
 
 EXPORTS = ("les_default_config", "les_workspace_bytes", "les_workspace_offset", "les_init",
            "les_step", "les_poisson_solve", "les_thermo", "les_diagnostics", "les_destroy",
@@ -36,7 +37,7 @@ class LesConfig(C.Structure):
         ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("precision", C.c_int32),
         ("n_subiter", C.c_int32), ("poisson_scheme", C.c_int32),
         ("poisson_check_every", C.c_int32), ("poisson_max_sweeps", C.c_int32),
-        ("satadj_maxit", C.c_int32), ("reserved0", C.c_int32),
+        ("satadj_maxit", C.c_int32), ("sweeps_per_launch", C.c_int32),
         ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("dt", C.c_double),
         ("poisson_tol", C.c_double), ("jacobi_omega", C.c_double),
         ("p00", C.c_double), ("theta0", C.c_double), ("Rd", C.c_double), ("Rv", C.c_double),
@@ -146,9 +147,9 @@ def make_config(p: dict) -> LesConfig:
     """les_config from a full workload parameter dict."""
     c = default_config()
     for name, ctype in LesConfig._fields_:
-        if name == "reserved0":
-            continue
-        if name == "precision":
+        if name == "sweeps_per_launch":
+            c.sweeps_per_launch = int(p.get("sweeps_per_launch", 0))
+        elif name == "precision":
             v = p.get("precision", "fp64")
             c.precision = {"fp64": LES_FP64, "fp32": LES_FP32}[v] if isinstance(v, str) else int(v)
         elif name == "poisson_scheme":

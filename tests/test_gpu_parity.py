@@ -233,3 +233,40 @@ def test_diagnostics_match_oracle(gpu, oracle_lib):
         assert g[k] == pytest.approx(o[k], rel=1e-12), k
     for k, prof in o["profiles"].items():
         np.testing.assert_allclose(g["profiles"][k], prof, rtol=1e-11, atol=1e-15)
+
+
+# ------------------------------------------- temporal blocking of sweeps
+
+@pytest.mark.parametrize("precision,shape", [("fp64", (20, 36, 70)), ("fp32", (33, 20, 130)),
+                                             ("fp32", (5, 6, 7))])
+@pytest.mark.parametrize("scheme", ["jacobi", "chebyshev"])
+def test_sweeps_per_launch_bitwise_equal(gpu, oracle_lib, precision, shape, scheme):
+    """Fusing S sweeps in one launch changes only the launch shape: the
+    iterates are bitwise equal for S = 1, 2, in fixed-count and in
+    tolerance mode (ragged tiles in x, y and z)."""
+    import torch
+    nz, ny, nx = shape
+    rhs = torch.from_numpy(li.random_field(shape, seed=13))
+    ref = None
+    for S in (1, 2):
+        p = li.workload("C1", nx=nx, ny=ny, nz=nz, precision=precision, poisson_scheme=scheme,
+                        poisson_tol=1e-5, sweeps_per_launch=S)
+        sim = gpu.LES(p)
+        phi_f, st_f, _ = sim.poisson_solve(rhs, fixed_sweeps=37)
+        phi_t, st_t, _ = sim.poisson_solve(rhs)
+        # the reported FP64 residual is that of the returned iterate: recompute
+        # it from the (FP32-rounded or FP64) fixed-count iterate on the CPU
+        if precision == "fp64":
+            r = rhs.numpy() - rhs.numpy().mean() - oracle_lib.laplacian(p, phi_f.cpu().numpy())
+            assert st_f["res_norm"] == pytest.approx(np.linalg.norm(r), rel=1e-10), S
+        got = (phi_f.cpu().numpy(), phi_t.cpu().numpy(), st_t["sweeps"], st_t["res_norm"])
+        if ref is None:
+            ref = got
+            assert st_f["sweeps"] == 37
+            continue
+        assert np.array_equal(got[0], ref[0]), S
+        assert np.array_equal(got[1], ref[1]), S
+        # same stopping sweep; the FP64 norm is summed over a launch-shape
+        # dependent block decomposition, so only its last bits may differ
+        assert got[2] == ref[2], S
+        assert got[3] == pytest.approx(ref[3], rel=1e-12), S

@@ -48,6 +48,21 @@ enum {
 
 enum { LES_FP64 = 0, LES_FP32 = 1 };          /* storage / stencil precision */
 enum { LES_JACOBI = 0, LES_CHEBYSHEV = 1 };   /* Poisson sweep weighting */
+/* Initial guess of the pressure-correction solves:
+ *   LES_GUESS_ZERO         phi_0 = 0 for every solve
+ *   LES_GUESS_EXTRAPOLATE  first solve of a step: phi_0 = alpha0 (p_{n-1} -
+ *                          p_{n-2}), the last step's pressure change; later
+ *                          solves start from 0
+ *   LES_GUESS_PREVIOUS     each sub-iteration's solve starts from the
+ *                          previous step's solution of the same
+ *                          sub-iteration (zero on the first step)
+ *   LES_GUESS_LEARNED      first solve of a step: the 3D CNN of les_cnn.h
+ *                          (weights bound with les_bind_cnn); later solves
+ *                          start from 0
+ * The solve always runs to the same residual tolerance: a guess only
+ * changes the number of sweeps, never the acceptance test. */
+enum { LES_GUESS_ZERO = 0, LES_GUESS_EXTRAPOLATE = 1, LES_GUESS_PREVIOUS = 2,
+       LES_GUESS_LEARNED = 3 };
 
 /* Run configuration.  Grid sizes >= 4 in every direction.
  * Table 1 constants of the paper and forcing parameters are explicit so the
@@ -74,6 +89,8 @@ typedef struct les_config {
   double ug, vg, shf, lhf, wsub_div, sponge_frac, sponge_max, rad_F0, rad_kappa;
   /* saturation vapour pressure anchor (Pa, K) and secant tolerance (K) */
   double e_tr, T_tr, satadj_tol;
+  int32_t guess;                /* LES_GUESS_* */
+  int32_t reserved1;
 } les_config;
 
 /* Caller-owned device buffers.  u, v, w: velocity (m/s); thl: liquid-ice
@@ -111,6 +128,11 @@ typedef struct les_step_opts {
   int32_t time_sweeps;          /* 1: time runs of consecutive plain sweeps
                                    (between residual checks) with HIP events */
   int32_t reserved;
+  void *dump_rhs0;              /* device, n elements or NULL: the centred
+                                   right-hand side of the first solve of the
+                                   call's last step */
+  void *dump_phi0;              /* device, n elements or NULL: that solve's
+                                   zero-mean solution */
 } les_step_opts;
 
 typedef struct les_step_stats {
@@ -147,7 +169,7 @@ size_t les_workspace_bytes(const les_config *cfg);
  * 0 u^n, 1 v^n, 2 w^n, 3 thl^{n+1/2}, 4 qt^{n+1/2}, 5 thl_mid, 6 qt_mid,
  * 7..9 u,v,w at n+1/2, 10 b^{n+1/2}, 11 b_mid, 12 ql_mid, 13 c_pm*Pi (mid),
  * 14 nu scalars, 15 nu momentum, 16 radiative heating, 17 Poisson rhs,
- * 18..21 Poisson iterate buffers 0..3. */
+ * 18..21 Poisson iterate buffers 0..3, 22 pressure of the previous step. */
 int les_workspace_offset(const les_config *cfg, int32_t field, size_t *offset);
 
 /* Validates cfg and buffers, computes the reference state (Sec. 2.1) and

@@ -17,11 +17,15 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 SCHEMES = {"jacobi": 0, "chebyshev": 1}
 
 
+GUESSES = {"zero": 0, "extrapolate": 1, "previous": 2}
+
+
 class OCfg(C.Structure):
     _fields_ = [
         ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("n_subiter", C.c_int32),
         ("poisson_scheme", C.c_int32), ("poisson_check_every", C.c_int32),
         ("poisson_max_sweeps", C.c_int32), ("satadj_maxit", C.c_int32),
+        ("guess", C.c_int32), ("reserved", C.c_int32),
         ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("dt", C.c_double),
         ("poisson_tol", C.c_double), ("jacobi_omega", C.c_double),
         ("p00", C.c_double), ("theta0", C.c_double), ("Rd", C.c_double), ("Rv", C.c_double),
@@ -89,6 +93,13 @@ def make_cfg(p: dict) -> OCfg:
         if name == "poisson_scheme":
             v = p["poisson_scheme"]
             c.poisson_scheme = SCHEMES[v] if isinstance(v, str) else int(v)
+        elif name == "guess":
+            v = p.get("guess", "zero")
+            if v not in GUESSES:
+                raise ValueError(f"the oracle step has no {v!r} guess; known: {sorted(GUESSES)}")
+            c.guess = GUESSES[v]
+        elif name == "reserved":
+            c.reserved = 0
         else:
             setattr(c, name, ctype(p[name]).value)
     return c

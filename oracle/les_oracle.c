@@ -688,12 +688,17 @@ static void scalar_sources(const ocfg *c, const oprof *P, const double *phi, dou
  * previous sub-iteration's phi (zero at a step's start). */
 int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, double *qt,
                 double *p, int32_t nsteps, const int32_t *replay, osolve *rec, odebug *dbg) {
-  if (check_cfg(c) || c->n_subiter < 1) return -1;
+  if (check_cfg(c) || c->n_subiter < 1 || c->guess < 0 || c->guess > 2) return -1;
   size_t n = ncell(c);
   oprof P;
   if (prof_make(c, &P)) return -1;
   ostate S;
   if (ostate_alloc(&S, n)) { prof_free(&P); return -1; }
+  /* guess memory: the previous step's pressure, or one solution per sub-iteration */
+  size_t nhist = c->guess == 1 ? n : c->guess == 2 ? (size_t)c->n_subiter * n : 0;
+  double *hist = nhist ? calloc(nhist, sizeof(double)) : NULL;
+  if (nhist && !hist) { ostate_free(&S); prof_free(&P); return -1; }
+  if (c->guess == 1) memcpy(hist, p, n * sizeof(double));
   double *vel[3] = {u, v, w};
   double ugv[3] = {c->ug, c->vg, 0.0};
   int solve = 0, rc = 0;
@@ -789,12 +794,21 @@ int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, dou
       double mr = fsum(c, S.rhs) / (double)n;
       for (size_t q = 0; q < n; ++q) S.rhs[q] -= mr;
       memset(S.phi, 0, n * sizeof(double));
+      if (c->guess == 1 && it == 0) {
+        for (int k = 0; k < c->nz; ++k)
+          for (size_t q = (size_t)k * c->nx * c->ny; q < (size_t)(k + 1) * c->nx * c->ny; ++q)
+            S.phi[q] = P.alpha0[k] * (p[q] - hist[q]);
+        memcpy(hist, p, n * sizeof(double));
+      } else if (c->guess == 2 && step > 0) {
+        memcpy(S.phi, hist + (size_t)it * n, n * sizeof(double));
+      }
       osolve st;
       int fixed = replay ? replay[solve] : 0;
       rc = oracle_poisson(c, S.rhs, S.phi, fixed, &st);
       if (rec) rec[solve] = st;
       ++solve;
       if (rc) break;
+      if (c->guess == 2) memcpy(hist + (size_t)it * n, S.phi, n * sizeof(double));
 
       /* --- projection: U^{k+1} = U_hat - dt rho0 grad_c phi, p += rho0 phi */
       for (int k = 0; k < c->nz; ++k)
@@ -828,6 +842,7 @@ int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, dou
           for (size_t q = (size_t)k * c->nx * c->ny; q < (size_t)(k + 1) * c->nx * c->ny; ++q)
             uh[a][q] = S.Uhat[a][q] / P.rho0[k];
   }
+  free(hist);
   ostate_free(&S);
   prof_free(&P);
   return rc;

@@ -21,6 +21,8 @@ typedef struct ocfg {
   int32_t poisson_check_every; /* residual checked every m sweeps */
   int32_t poisson_max_sweeps;
   int32_t satadj_maxit;
+  int32_t guess;               /* initial guess of the solves, see oracle_step */
+  int32_t reserved;
   double dx, dy, dz, dt;
   double poisson_tol;          /* ||rhs - L phi||_2 <= tol * ||rhs||_2 */
   double jacobi_omega;         /* 0 = closed-form optimum */
@@ -84,7 +86,15 @@ typedef struct odebug {
 } odebug;
 
 /* nsteps time steps in place.  replay (nullable) gives per-solve sweep counts;
- * rec (nullable) receives nsteps*n_subiter solve records. */
+ * rec (nullable) receives nsteps*n_subiter solve records.
+ * Initial guess of each solve by c->guess:
+ *   0  zero;
+ *   1  first solve of a step: alpha0 (p^n - p^{n-1}), the pressure change of
+ *      the last step (zero on the first step of the call); later solves zero;
+ *   2  each sub-iteration: the zero-mean solution of the same sub-iteration
+ *      of the last step (zero on the first step of the call).
+ * The guess changes the sweep count only: the stopping test is relative to
+ * ||rhs||, whatever the starting iterate. */
 int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, double *qt,
                 double *p, int32_t nsteps, const int32_t *replay, osolve *rec, odebug *dbg);
 

@@ -103,6 +103,16 @@ __global__ __launch_bounds__(kBlock) void sub_mean_kernel(int64_t n, const T *__
 }
 
 template <typename T>
+__global__ __launch_bounds__(kBlock) void extrapolate_kernel(Grid g, Profiles<T> P,
+                                                             const T *__restrict__ p,
+                                                             const T *__restrict__ pm,
+                                                             T *__restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.n) return;
+  out[q] = P.alpha0_t[(int)(q / g.nxy)] * (p[q] - pm[q]);
+}
+
+template <typename T>
 __global__ __launch_bounds__(kBlock) void block_sum_kernel(const T *__restrict__ a, int64_t n,
                                                            int mode, double *__restrict__ partials) {
   double acc = 0.0;
@@ -213,6 +223,12 @@ void launch_sub_mean(const Grid &g, const T *in, const SolveCtl *ctl, T *out, hi
 }
 
 template <typename T>
+void launch_extrapolate(const Grid &g, const Profiles<T> &P, const T *p, const T *p_prev, T *phi0,
+                        hipStream_t s) {
+  extrapolate_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g, P, p, p_prev, phi0);
+}
+
+template <typename T>
 void launch_block_sum(const T *a, int64_t n, int mode, double *partials, hipStream_t s) {
   block_sum_kernel<T><<<kReduceBlocks, kBlock, 0, s>>>(a, n, mode, partials);
 }
@@ -235,7 +251,9 @@ void launch_ctl_reset(SolveCtl *ctl, int max_sweeps, int fixed, hipStream_t s) {
   template void launch_project<T>(const Grid &, const Dyn<T> &, const Profiles<T> &, const T *,  \
                                   const SolveCtl *, T *, T *, T *, T *, hipStream_t);            \
   template void launch_sub_mean<T>(const Grid &, const T *, const SolveCtl *, T *, hipStream_t); \
-  template void launch_block_sum<T>(const T *, int64_t, int, double *, hipStream_t);
+  template void launch_block_sum<T>(const T *, int64_t, int, double *, hipStream_t);            \
+  template void launch_extrapolate<T>(const Grid &, const Profiles<T> &, const T *, const T *,   \
+                                      T *, hipStream_t);
 LES_INST(float)
 LES_INST(double)
 #undef LES_INST

@@ -50,7 +50,7 @@ int fail(int code, const char *fmt, ...) {
 enum Field {
   F_UN = 0, F_VN, F_WN, F_THL_H, F_QT_H, F_THL_M, F_QT_M, F_UH, F_VH, F_WH,
   F_B_H, F_B_M, F_QL_M, F_CPMPI_M, F_NU_S, F_NU_M, F_RAD, F_RHS, F_PHI0, F_PHI1,
-  F_PHI2, F_PHI3,
+  F_PHI2, F_PHI3, F_PM2,
   F_COUNT
 };
 
@@ -66,6 +66,7 @@ struct Layout {
   size_t partials;  // kPartialCap doubles
   size_t ctl;       // SolveCtl
   size_t diag;      // nz x kDiagStride doubles
+  size_t hist;      // n_subiter fields: previous step's solutions (history guess)
   size_t total;
 };
 
@@ -97,6 +98,8 @@ int validate(const les_config *c) {
   if (!(1.0 - c->g * top / (c->cpd * c->theta0) > 0))
     return fail(LES_ERR_ARG, "domain top above the adiabatic atmosphere's height");
   if (c->sponge_frac < 0 || c->sponge_frac > 1) return fail(LES_ERR_ARG, "sponge_frac must be in [0, 1]");
+  if (c->guess < LES_GUESS_ZERO || c->guess > LES_GUESS_LEARNED)
+    return fail(LES_ERR_ARG, "unknown guess mode %d", c->guess);
   return LES_OK;
 }
 
@@ -121,6 +124,8 @@ Layout layout_of(const les_config *c) {
   off = align_up(off + sizeof(SolveCtl));
   L.diag = off;
   off = align_up(off + (size_t)c->nz * kDiagStride * sizeof(double));
+  L.hist = off;
+  if (c->guess == LES_GUESS_PREVIOUS) off = align_up(off + (size_t)c->n_subiter * n * es);
   L.total = off;
   return L;
 }
@@ -148,6 +153,7 @@ struct les_handle {
   std::vector<hipEvent_t> ev_check;
   std::vector<hipEvent_t> ev_sweep;  // pool bracketing runs of plain sweeps
   bool broken;
+  std::vector<char> hist_valid;  // per sub-iteration: history holds a solution
 };
 
 namespace {
@@ -446,6 +452,10 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
   return LES_OK;
 }
 
+// Learned initial guess into the first iterate buffer.
+template <typename T>
+int cnn_guess(les_handle *h, View<T> &V);
+
 template <typename T>
 int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step_stats *stats) {
   View<T> V = view_of<T>(h);
@@ -501,6 +511,26 @@ int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step
                          V.f[F_B_H], num, V.u, V.v, V.w, s);
       launch_poisson_rhs<T>(g, V.dyn, V.P, V.u, V.v, V.w, lag, V.f[F_RHS], V.partials, s);
       LAUNCH_TRY();
+      // Initial guess.  At k = 0 p holds p^n and the workspace p^{n-1}; the
+      // extrapolated and learned guesses read both, then p^{n-1} <- p^n.
+      T *hist = (T *)ws(h, h->lay.hist) + (size_t)k * g.n;
+      bool guessed = false;
+      if (c.guess == LES_GUESS_PREVIOUS) {
+        // the previous step's solution of this sub-iteration
+        guessed = h->hist_valid[k] != 0;
+        if (guessed)
+          HIP_TRY(hipMemcpyAsync(V.f[F_PHI0], hist, bytes, hipMemcpyDeviceToDevice, s));
+      } else if (k == 0 && c.guess != LES_GUESS_ZERO) {
+        guessed = true;
+        if (c.guess == LES_GUESS_EXTRAPOLATE) {
+          launch_extrapolate<T>(g, V.P, V.p, V.f[F_PM2], V.f[F_PHI0], s);
+        } else {
+          const int grc = cnn_guess<T>(h, V);
+          if (grc) return grc;
+        }
+        HIP_TRY(hipMemcpyAsync(V.f[F_PM2], V.p, bytes, hipMemcpyDeviceToDevice, s));
+        LAUNCH_TRY();
+      }
       const int solve_idx = step * K + k;
       const int fixed = opts && opts->replay_sweeps ? opts->replay_sweeps[solve_idx] : 0;
       if (opts && opts->replay_sweeps && fixed < 0)
@@ -509,7 +539,7 @@ int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step
       T *phi = nullptr;
       SweepTiming timing;
       timing.enabled = opts && opts->time_sweeps;
-      int rc = solve<T>(h, V, V.f[F_RHS], false, fixed, &st, &phi, &timing);
+      int rc = solve<T>(h, V, V.f[F_RHS], guessed, fixed, &st, &phi, &timing);
       acc.sweep_seconds += timing.seconds;
       acc.sweeps_timed += timing.sweeps;
       if (opts && opts->records) opts->records[solve_idx] = st;
@@ -527,6 +557,15 @@ int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step
       // gauge (zero mean) and projection
       launch_block_sum<T>(phi, g.n, 0, V.partials, s);
       launch_final(V.partials, kReduceBlocks, kFinalPhiMean, V.ctl, (double)g.n, 0.0, 0, nullptr, s);
+      if (c.guess == LES_GUESS_PREVIOUS) {
+        launch_sub_mean<T>(g, phi, V.ctl, hist, s);
+        h->hist_valid[k] = 1;
+      }
+      if (k == 0 && step == nsteps - 1 && opts) {  // training pairs of the first solve
+        if (opts->dump_rhs0)
+          HIP_TRY(hipMemcpyAsync(opts->dump_rhs0, V.f[F_RHS], bytes, hipMemcpyDeviceToDevice, s));
+        if (opts->dump_phi0) launch_sub_mean<T>(g, phi, V.ctl, (T *)opts->dump_phi0, s);
+      }
       launch_project<T>(g, V.dyn, V.P, phi, V.ctl, V.u, V.v, V.w, V.p, s);
       LAUNCH_TRY();
       lag = phi;
@@ -611,6 +650,13 @@ int diag_impl(les_handle *h, les_diag *out, double *profiles) {
   d.div_l2 = std::sqrt(div2);
   if (out) *out = d;
   return LES_OK;
+}
+
+template <typename T>
+int cnn_guess(les_handle *h, View<T> &V) {
+  (void)h;
+  (void)V;
+  return fail(LES_ERR_STATE, "learned guess requested but no network is bound");
 }
 
 int check_handle(const les_handle *h) {
@@ -730,6 +776,7 @@ int les_init(const les_config *cfg, const les_buffers *bufs, void *stream, les_h
   t.satadj_tol = cfg->satadj_tol;
   t.satadj_maxit = cfg->satadj_maxit;
   jacobi_spectrum(cfg, &h->mu_min, &h->mu_max);
+  h->hist_valid.assign(cfg->n_subiter, 0);
   h->sweeps_per_launch = cfg->sweeps_per_launch > 0 ? cfg->sweeps_per_launch : kDefaultSweepsPerLaunch;
 
   auto cleanup = [&](int code) {
@@ -748,6 +795,11 @@ int les_init(const les_config *cfg, const les_buffers *bufs, void *stream, les_h
       hipEventCreate(&h->ev_a) != hipSuccess || hipEventCreate(&h->ev_b) != hipSuccess)
     return cleanup(fail(LES_ERR_HIP, "hipEventCreate failed"));
   rc = cfg->precision == LES_FP64 ? upload_profiles<double>(h) : upload_profiles<float>(h);
+  if (!rc && hipMemcpyAsync(ws(h, L.field[F_PM2]), bufs->p, (size_t)g.n * es,
+                            hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
+    rc = fail(LES_ERR_HIP, "copy of the initial pressure failed");
+  if (!rc && hipStreamSynchronize(h->stream) != hipSuccess)
+    rc = fail(LES_ERR_HIP, "hipStreamSynchronize failed");
   if (rc) return cleanup(rc);
   *out = h;
   return LES_OK;

@@ -127,6 +127,11 @@ void launch_project(const Grid &g, const Dyn<T> &d, const Profiles<T> &P, const 
 template <typename T>
 void launch_sub_mean(const Grid &g, const T *in, const SolveCtl *ctl, T *out, hipStream_t s);
 
+// phi0 = alpha0 (p - p_prev): the last step's pressure change as a guess.
+template <typename T>
+void launch_extrapolate(const Grid &g, const Profiles<T> &P, const T *p, const T *p_prev, T *phi0,
+                        hipStream_t s);
+
 // Generic FP64 sums over n elements: mode 0 sum(a), 1 sum(a^2).
 template <typename T>
 void launch_block_sum(const T *a, int64_t n, int mode, double *partials, hipStream_t s);

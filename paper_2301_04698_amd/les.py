@@ -19,13 +19,16 @@ LES_OK, LES_WARN_NOT_CONVERGED = 0, 1
 LES_ERR_ARG, LES_ERR_HIP, LES_ERR_NONFINITE, LES_ERR_STATE = -1, -2, -3, -4
 LES_FP64, LES_FP32 = 0, 1
 LES_JACOBI, LES_CHEBYSHEV = 0, 1
+LES_GUESS_ZERO, LES_GUESS_EXTRAPOLATE, LES_GUESS_PREVIOUS, LES_GUESS_LEARNED = 0, 1, 2, 3
+GUESS_MODES = {"zero": LES_GUESS_ZERO, "extrapolate": LES_GUESS_EXTRAPOLATE,
+               "previous": LES_GUESS_PREVIOUS, "learned": LES_GUESS_LEARNED}
 NPROFILES = 9
 PROFILE_NAMES = ("thl", "qt", "ql", "u", "v", "w", "w2", "w3", "b")
 
 # Workspace field ids (les_workspace_offset).
 WS_FIELDS = ("un", "vn", "wn", "thl_half", "qt_half", "thl_mid", "qt_mid", "uh", "vh", "wh",
              "b_half", "b_mid", "ql_mid", "cpmpi_mid", "nu_s", "nu_m", "rad", "rhs", "phi0", "phi1",
-             "phi2", "phi3")
+             "phi2", "phi3", "p_prev")
 
 EXPORTS = ("les_default_config", "les_workspace_bytes", "les_workspace_offset", "les_init",
            "les_step", "les_poisson_solve", "les_thermo", "les_diagnostics", "les_destroy",
@@ -48,6 +51,7 @@ class LesConfig(C.Structure):
         ("wsub_div", C.c_double), ("sponge_frac", C.c_double), ("sponge_max", C.c_double),
         ("rad_F0", C.c_double), ("rad_kappa", C.c_double),
         ("e_tr", C.c_double), ("T_tr", C.c_double), ("satadj_tol", C.c_double),
+        ("guess", C.c_int32), ("reserved1", C.c_int32),
     ]
 
 
@@ -71,7 +75,8 @@ class LesPoissonOpts(C.Structure):
 
 class LesStepOpts(C.Structure):
     _fields_ = [("replay_sweeps", C.POINTER(C.c_int32)), ("records", C.POINTER(LesSolveStats)),
-                ("time_sweeps", C.c_int32), ("reserved", C.c_int32)]
+                ("time_sweeps", C.c_int32), ("reserved", C.c_int32),
+                ("dump_rhs0", C.c_void_p), ("dump_phi0", C.c_void_p)]
 
 
 class LesStepStats(C.Structure):
@@ -147,8 +152,13 @@ def make_config(p: dict) -> LesConfig:
     """les_config from a full workload parameter dict."""
     c = default_config()
     for name, ctype in LesConfig._fields_:
+        if name == "reserved1":
+            continue
         if name == "sweeps_per_launch":
             c.sweeps_per_launch = int(p.get("sweeps_per_launch", 0))
+        elif name == "guess":
+            v = p.get("guess", "zero")
+            c.guess = GUESS_MODES[v] if isinstance(v, str) else int(v)
         elif name == "precision":
             v = p.get("precision", "fp64")
             c.precision = {"fp64": LES_FP64, "fp32": LES_FP32}[v] if isinstance(v, str) else int(v)
@@ -222,11 +232,19 @@ class LES:
     def _n(self):
         return self.cfg.nx * self.cfg.ny * self.cfg.nz
 
-    def step(self, nsteps=1, replay=None, records=False, time_sweeps=False):
-        """Advance nsteps; returns (rc, stats dict, per-solve records or None)."""
+    def step(self, nsteps=1, replay=None, records=False, time_sweeps=False, dump=None):
+        """Advance nsteps; returns (rc, stats dict, per-solve records or None).
+
+        dump: optional (rhs0, phi0) device tensors receiving the first
+        solve's centred right-hand side and solution of the last step."""
         K = self.cfg.n_subiter
         opts = LesStepOpts()
         opts.time_sweeps = 1 if time_sweeps else 0
+        if dump is not None:
+            for t in dump:
+                assert t.is_contiguous() and t.dtype == self.dtype and t.numel() == self._n()
+            opts.dump_rhs0 = dump[0].data_ptr()
+            opts.dump_phi0 = dump[1].data_ptr()
         rec = None
         keep = []
         if replay is not None:

@@ -197,6 +197,38 @@ def test_step_fp32_matches_oracle(gpu, oracle_lib):
         assert e <= 1e-5, (k, e, errs)
 
 
+@pytest.mark.parametrize("guess", ["extrapolate", "previous"])
+def test_step_guess_matches_oracle(gpu, oracle_lib, guess):
+    """Initial guesses of the solves: the GPU forms the same starting
+    iterate as the oracle (replayed sweep counts, FP64, 6 steps, all physics)."""
+    p = li.workload("C1m", poisson_tol=1e-9, poisson_scheme="chebyshev", guess=guess)
+    st0 = with_velocity_noise(p, li.initial_state(p), 0.3, 5)
+    errs, recs, grecs, *_ = _compare_step(gpu, oracle_lib, p, st0, 6, 1e-11)
+    for k, e in errs.items():
+        assert e <= 1e-11, (k, e, errs)
+    for a, b in zip(recs, grecs):
+        assert b["res_norm"] == pytest.approx(a["res_norm"], rel=1e-6, abs=1e-12 * a["rhs_norm"])
+
+
+def test_step_guess_fp32_converges(gpu):
+    """FP32, each solve of a guessed run stops at the tolerance, like the
+    zero-guess run, and the two runs stay within tolerance-level distance."""
+    base = li.workload("C1m", nx=40, ny=24, nz=32, precision="fp32", poisson_tol=1e-5,
+                       poisson_scheme="chebyshev")
+    out = {}
+    for g in ("zero", "previous", "extrapolate"):
+        p = dict(base, guess=g)
+        sim = gpu.LES(p, li.initial_state(p))
+        rc, stats, recs = sim.step(6, records=True)
+        assert rc == gpu.LES_OK and stats["not_converged"] == 0
+        for r in recs:
+            assert r["res_norm"] <= p["poisson_tol"] * r["rhs_norm"]
+        out[g] = sim.state_numpy()
+    for g in ("previous", "extrapolate"):
+        for k in FIELDS:
+            assert rel_anom(out[g][k], out["zero"][k]) <= 1e-3, (g, k)
+
+
 def test_step_rest_state_steady(gpu):
     import torch
     p = li.workload("C1", nx=8, ny=8, nz=8, ug=0.0, vg=0.0, noise_thl=0.0, thl_ml=290.0,

@@ -634,3 +634,38 @@ def test_radiation_cools_column(oracle_lib):
     area = p["nx"] * p["dx"] * p["ny"] * p["dy"]
     expect = p["dt"] * p["rad_F0"] * (np.exp(-p["rad_kappa"] * lwp) - 1) / p["cpd"] * area
     assert 0.95 < (m1 - m0) / expect < 1.05
+
+
+# ------------------------------------------- P12 initial guesses of the solve
+
+def test_guess_modes_change_sweeps_not_solution(oracle_lib):
+    """A starting iterate only changes how many sweeps the solve takes: the
+    stopping test is relative to ||rhs|| (Sec. 2.4 solve), so every guess
+    ends within the tolerance-level distance of the zero-guess run, and each
+    solve meets the tolerance.  Reusing the last step's solution of the same
+    sub-iteration saves sweeps once the flow is past its first adjustment; a
+    guess taken from the wrong sub-iteration or not gauged would not."""
+    p0 = small("C1m", poisson_tol=1e-8, poisson_scheme="chebyshev")
+    runs = {}
+    for g in ("zero", "previous", "extrapolate"):
+        p = dict(p0, guess=g)
+        st = li.initial_state(p)
+        recs, _ = oracle_lib.step(p, st, nsteps=10)
+        for r in recs:
+            assert r["status"] == 0 and r["res_norm"] <= p["poisson_tol"] * r["rhs_norm"]
+        runs[g] = (st, recs)
+    ref, rz = runs["zero"]
+    K = p0["n_subiter"]
+    for g in ("previous", "extrapolate"):
+        st, recs = runs[g]
+        # first step: nothing to reuse, identical solves
+        assert [r["sweeps"] for r in recs[:K]] == [r["sweeps"] for r in rz[:K]]
+        for k in st:
+            d = ref[k] - ref[k].mean(axis=(1, 2), keepdims=True)
+            assert np.linalg.norm(st[k] - ref[k]) <= 1e-6 * np.linalg.norm(d), (g, k)
+    sw = lambda recs, k: sum(r["sweeps"] for i, r in enumerate(recs[4 * K:]) if i % K == k)
+    st, rp = runs["previous"]
+    for k in range(K):
+        assert sw(rp, k) < sw(rz, k), k
+    with pytest.raises(ValueError):
+        oracle_lib.make_cfg(dict(p0, guess="learned"))

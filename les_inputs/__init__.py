@@ -192,3 +192,22 @@ def random_field(shape, seed: int, field: int = 7, zero_mean: bool = True) -> np
     if zero_mean:
         r = r - r.mean()
     return r
+
+
+FIELD_CNN = 11
+
+
+def cnn_init(seed: int, blocks) -> np.ndarray:
+    """Seeded initial parameters of a network, FP32 values as float64.
+
+    blocks: sequence of (n_weights, fan_in, n_bias); weights are uniform in
+    +-sqrt(3 / fan_in) (unit gain for a linear layer), biases zero.
+    """
+    out = []
+    base = 0
+    for nw, fan_in, nb in blocks:
+        u = uniform01(seed, FIELD_CNN, np.arange(base, base + nw, dtype=np.uint64))
+        base += nw
+        out.append((2.0 * u - 1.0) * np.sqrt(3.0 / fan_in))
+        out.append(np.zeros(nb))
+    return np.concatenate(out).astype(np.float32).astype(np.float64)

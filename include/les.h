@@ -128,11 +128,12 @@ typedef struct les_step_opts {
   int32_t time_sweeps;          /* 1: time runs of consecutive plain sweeps
                                    (between residual checks) with HIP events */
   int32_t reserved;
-  void *dump_rhs0;              /* device, n elements or NULL: the centred
-                                   right-hand side of the first solve of the
-                                   call's last step */
-  void *dump_phi0;              /* device, n elements or NULL: that solve's
-                                   zero-mean solution */
+  void *dump_rhs;               /* device, n_subiter*n elements or NULL: the
+                                   centred right-hand sides of the solves of
+                                   the call's last step, sub-iteration k at
+                                   offset k*n */
+  void *dump_phi;               /* device, n_subiter*n elements or NULL:
+                                   those solves' zero-mean solutions */
 } les_step_opts;
 
 typedef struct les_step_stats {

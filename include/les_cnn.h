@@ -1,0 +1,134 @@
+/*
+ * les_cnn.h — C ABI of the learned initial guess of the pressure-correction
+ * Poisson solve (the guess network) and of its training on the GPU.
+ *
+ * Role in the method.  Each sub-iteration of the time step solves the
+ * pressure-correction equation (Sec. 2.4 of the paper, compact Laplacian of
+ * phi = alpha0 dp equal to the divergence right-hand side) by weighted-
+ * Jacobi sweeps that stop when ||rhs - L phi||_2 <= tol ||rhs||_2.  A
+ * starting iterate closer to the solution ends the sweeps sooner but never
+ * changes that test.  With LES_GUESS_LEARNED the starting iterate of every
+ * solve (after the first step) is
+ *     phi_0 = base + (s / d) CNN(r / s),
+ * base = the previous step's solution of the same sub-iteration (a previous
+ * pressure correction), r = rhs - L base its residual for the new
+ * right-hand side, s = RMS(r), d = 2/dx^2 + 2/dy^2 + 2/dz^2.
+ *
+ * Network.  Four 3x3x3 convolutions with biases, channels 1 -> 16 -> 16 ->
+ * 16 -> 1, leaky ReLU of slope alpha after the first three.  Weights and
+ * every layer input are rounded to bfloat16 (nearest even); sums are FP32
+ * (the 16 -> 16 layers on the matrix cores); the output is FP32.
+ * x and y wrap on whole fields (periodic = 1) or are "valid" on training
+ * crops (periodic = 0: each layer trims one cell per side, 8 in total);
+ * every layer reads the even mirror of its input in z.
+ *
+ * Parameters.  One FP32 vector of les_cnn_param_count() values in device
+ * memory: per layer l = 0..3, W_l[tap][cout][cin] then b_l[cout], with
+ * tap = 9 (dz+1) + 3 (dy+1) + (dx+1).  "packed" is its bfloat16 copy
+ * (les_cnn_param_count() uint16 values) made by les_cnn_pack.
+ *
+ * Training loss.  On output crops (nz, ny, nx): e = out - target,
+ * q = (L e)/d on interior cells (one-cell ring in x and y excluded, mirror
+ * in z); loss = sum q^2 / sum ((L target)/d)^2 over the same cells: the
+ * squared residual of the corrected guess relative to that of the base.
+ * Targets are (phi* - base) d / s with phi* the solver's solution.
+ *
+ * Conventions are those of les.h: device pointers, stream-ordered calls,
+ * no device allocation by the library (work buffers come from the caller),
+ * negative return codes with les_last_error().  Every array argument is
+ * device memory unless marked host.
+ */
+#ifndef LES_CNN_H
+#define LES_CNN_H
+
+#include "les.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct les_cnn_dims {
+  int32_t batch;     /* number of fields / crops, >= 1 */
+  int32_t nz, ny, nx; /* network input size of each (valid: ny, nx >= 11) */
+  int32_t periodic;  /* 1: whole periodic fields; 0: valid crops */
+  int32_t reserved;  /* 0 */
+  double alpha;      /* leaky ReLU slope, >= 0 */
+} les_cnn_dims;
+
+/* Number of FP32 parameters (14737). */
+int32_t les_cnn_param_count(void);
+
+/* Bytes of the work buffer of les_cnn_forward / _loss / _backward /
+ * _train_step for these dims (stored layer inputs, gradients, partial sums). */
+size_t les_cnn_work_bytes(const les_cnn_dims *d);
+
+/* packed[q] = bfloat16(params[q]). */
+int les_cnn_pack(const float *params, uint16_t *packed, void *stream);
+
+/* Forward pass on a batch: x (batch, nz, ny, nx) FP32 (rounded to
+ * bfloat16 on entry), out (batch, nz, ny - 8, nx - 8) for valid crops or
+ * (batch, nz, ny, nx) for periodic fields.  Keeps the layer inputs in work
+ * for les_cnn_backward. */
+int les_cnn_forward(const les_cnn_dims *d, const float *params, const uint16_t *packed,
+                    const float *x, void *work, float *out, void *stream);
+
+/* Residual loss of out against target (both of the output size; valid
+ * crops only) and gout = dloss/dout.  loss (host, nullable): synchronizes
+ * the stream and stores the loss. */
+int les_cnn_loss(const les_cnn_dims *d, double dx, double dy, double dz, const float *out,
+                 const float *target, void *work, float *gout, double *loss, void *stream);
+
+/* Gradient of the loss with respect to the parameters (FP32, parameter
+ * layout) from gout and the layer inputs kept by the last les_cnn_forward
+ * on the same work buffer (valid crops only).  Leaky-ReLU slopes come from
+ * the sign of the stored bfloat16 activations; weight-gradient sums are
+ * FP64 in a fixed order (deterministic). */
+int les_cnn_backward(const les_cnn_dims *d, const uint16_t *packed, void *work,
+                     const float *gout, float *grad, void *stream);
+
+/* One Adam step (Kingma & Ba 2015, bias-corrected, step >= 1) on FP32
+ * params with FP32 moments m, v. */
+int les_cnn_adam(int32_t n, float *params, const float *grad, float *m, float *v, int32_t step,
+                 double lr, double beta1, double beta2, double eps, void *stream);
+
+/* forward + loss + backward + Adam + pack on one batch of crops.
+ * loss (host, nullable) as in les_cnn_loss. */
+int les_cnn_train_step(const les_cnn_dims *d, double dx, double dy, double dz, float *params,
+                       uint16_t *packed, float *m, float *v, int32_t step, double lr,
+                       double beta1, double beta2, double eps, const float *x,
+                       const float *target, void *work, float *grad, double *loss,
+                       void *stream);
+
+/* Training pair from one solve of a run with configuration cfg (fields of
+ * the storage type of cfg->precision): r = rhs - L base, s = RMS(r),
+ * x = r / s, target = (phi - base) d / s (FP32 fields).  base nullable
+ * (zero).  scratch: les_cnn_pair_scratch_bytes(cfg) bytes.  scale (host,
+ * nullable): synchronizes and stores s. */
+size_t les_cnn_pair_scratch_bytes(const les_config *cfg);
+int les_cnn_pair(const les_config *cfg, const void *rhs, const void *base, const void *phi,
+                 float *x, float *target, void *scratch, double *scale, void *stream);
+
+/* Crops of npairs stored pairs x_pairs, t_pairs (each npairs x nz x ny x nx,
+ * FP32).  crops: batch triples (pair, j0, i0), each taken modulo its range.
+ * xb gets (batch, nz, cy + 8, cx + 8) from (j0 - 4, i0 - 4), tb (batch, nz,
+ * cy, cx) from (j0, i0), both wrapping in x and y. */
+int les_cnn_gather(const float *x_pairs, const float *t_pairs, int32_t npairs, int32_t nz,
+                   int32_t ny, int32_t nx, const int32_t *crops, int32_t batch, int32_t cy,
+                   int32_t cx, float *xb, float *tb, void *stream);
+
+/* Bind the network used by LES_GUESS_LEARNED: copies params (device FP32)
+ * into the handle's workspace and packs them.  The caller's buffer may be
+ * freed afterwards.  Error if the handle was not created with
+ * LES_GUESS_LEARNED. */
+int les_bind_cnn(les_handle *h, const float *params, double alpha);
+
+/* The learned guess on caller fields of the handle's grid and storage
+ * type: guess = base + (s/d) CNN(r/s), r = rhs - L base (rhs is used as
+ * given).  scale (host, nullable): synchronizes and stores s. */
+int les_cnn_guess(les_handle *h, const void *rhs, const void *base, void *guess, double *scale);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

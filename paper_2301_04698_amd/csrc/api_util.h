@@ -1,0 +1,43 @@
+// Error reporting shared by the C ABI translation units: a thread-local
+// message returned by les_last_error() and the HIP status checks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "les.h"
+
+namespace lesmi {
+
+inline thread_local std::string g_error;
+
+inline int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+}  // namespace lesmi
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return lesmi::fail(LES_ERR_HIP, "%s failed: %s (%s:%d)", #expr,                    \
+                         hipGetErrorString(e_), __FILE__, __LINE__);                     \
+  } while (0)
+
+#define LAUNCH_TRY()                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = hipGetLastError();                                                   \
+    if (e_ != hipSuccess)                                                                \
+      return lesmi::fail(LES_ERR_HIP, "kernel launch failed: %s (%s:%d)",               \
+                         hipGetErrorString(e_), __FILE__, __LINE__);                     \
+  } while (0)

@@ -1,0 +1,99 @@
+// Internal declarations of the guess network (learned Poisson initial
+// guess): layer geometry and the launchers implemented in k_cnn.hip.
+//
+// Network: four 3x3x3 convolutions, channels 1 -> 16 -> 16 -> 16 -> 1, with
+// biases and a leaky ReLU after the first three.  Weights and layer inputs
+// are bfloat16 (round to nearest even), sums FP32 (the two 16 -> 16 layers
+// on the matrix cores), the output FP32.  Activations are stored
+// channels-last: element (cell, c) at cell * C + c.
+#pragma once
+
+#include "les_internal.h"
+
+namespace lesmi {
+
+constexpr int kCnnLayers = 4;
+constexpr int kCnnTaps = 27;
+constexpr int kCnnCh = 16;
+
+__host__ __device__ constexpr int cnn_cin(int l) { return l == 0 ? 1 : kCnnCh; }
+__host__ __device__ constexpr int cnn_cout(int l) { return l == kCnnLayers - 1 ? 1 : kCnnCh; }
+// Flat FP32 parameter vector: per layer W[tap][cout][cin] then b[cout].
+__host__ __device__ constexpr int cnn_weight_offset(int l) {
+  int off = 0;
+  for (int q = 0; q < l; ++q) off += kCnnTaps * cnn_cin(q) * cnn_cout(q) + cnn_cout(q);
+  return off;
+}
+__host__ __device__ constexpr int cnn_bias_offset(int l) {
+  return cnn_weight_offset(l) + kCnnTaps * cnn_cin(l) * cnn_cout(l);
+}
+__host__ __device__ constexpr int cnn_param_count() { return cnn_weight_offset(kCnnLayers); }
+// Largest weight-gradient entry count of one layer (weights + biases).
+constexpr int kCnnMaxEntries = kCnnTaps * kCnnCh * kCnnCh + kCnnCh;
+
+// Geometry of layer l: input (batch, nz, nyi, nxi), output (batch, nz, nyo,
+// nxo).  periodic: x, y wrap and sizes are kept; otherwise x, y are "valid"
+// (output cell (j, i) reads input (j + 1 + dy, i + 1 + dx)).  z always reads
+// the even mirror of the layer input.
+struct CnnGeom {
+  int batch, nz, nyi, nxi, nyo, nxo, periodic;
+  int64_t n_in, n_out;
+};
+CnnGeom cnn_geom(int batch, int nz, int ny, int nx, int periodic, int layer);
+
+// Weight-gradient reduction: blocks of one launch (their partials).
+constexpr int kCnnWgradBlocks = 1024;
+
+// ------------------------------------------------------------ launchers
+// wbf[q] = bf16(params[q]) for the whole parameter vector.
+void launch_cnn_pack(const float *params, uint16_t *wbf, hipStream_t s);
+// a0[q] = bf16(x[q] * scale) (scale: device double, nullptr = 1).
+void launch_cnn_round(int64_t n, const float *x, const double *scale, uint16_t *a0, hipStream_t s);
+// Layers 0..2: aout = bf16(leaky(conv(ain) + b)).  Layer 3: yout = conv(ain) + b.
+void launch_cnn_conv(int layer, const CnnGeom &G, const uint16_t *ain, const float *params,
+                     const uint16_t *wbf, float alpha, uint16_t *aout, float *yout, hipStream_t s);
+// Layer 3 fused with the guess: guess = base + s_over_d * (conv(ain) + b).
+template <typename T>
+void launch_cnn_guess(const CnnGeom &G, const uint16_t *ain, const float *params,
+                      const uint16_t *wbf, const T *base, const double *s_over_d, T *guess,
+                      hipStream_t s);
+
+// Residual loss on (batch, nz, ny, nx) crops (see the oracle for the
+// definition).  stats[0] = loss, stats[1] = denominator.  gy = dloss/dy.
+// partials: 2 * kReduceBlocks doubles; q: scratch of the crop size.
+void launch_cnn_loss(int batch, int nz, int ny, int nx, double wx, double wy, double wz,
+                     const float *y, const float *t, float *q, double *partials, double *stats,
+                     float *gy, hipStream_t s);
+
+// Backward through layer l (valid geometry): gprev = (W^T gy) * leaky'(ain)
+// for l >= 1, where ain is the stored input of layer l.
+void launch_cnn_dgrad(int layer, const CnnGeom &G, const float *gy, const uint16_t *wbf,
+                      const uint16_t *ain, float alpha, float *gprev, hipStream_t s);
+// Weight and bias gradient of layer l: per-block FP64 partials, then a
+// fixed-order sum into grad (FP32, parameter layout).
+void launch_cnn_wgrad(int layer, const CnnGeom &G, const float *gy, const uint16_t *ain,
+                      double *partials, float *grad, hipStream_t s);
+
+void launch_cnn_adam(int n, float *params, const float *grad, float *m, float *v, int step,
+                     double lr, double beta1, double beta2, double eps, hipStream_t s);
+
+// Network input of a solve: r = rhs - L base (compact Laplacian, periodic
+// x, y, mirror z, FP64 arithmetic) and FP64 partial sums of r^2.
+template <typename T>
+void launch_cnn_residual(const Grid &g, const T *rhs, const T *base, float *r, double *partials,
+                         hipStream_t s);
+// From kReduceBlocks partials of sum r^2: sc[0] = s = RMS(r), sc[1] = 1/s
+// (0 if s = 0), sc[2] = s/d.
+void launch_cnn_scale(const double *partials, double n, double d, double *sc, hipStream_t s);
+// Training pair: x = r/s and t = (phi - base) d/s, FP32.
+template <typename T>
+void launch_cnn_pair(const Grid &g, const float *r, const T *phi, const T *base, const double *sc,
+                     double d, float *x, float *t, hipStream_t s);
+// Crops of npairs stored pairs.  crops[3b..3b+2] = (pair, j0, i0), each
+// taken modulo its range: input crop (nz, cy + 8, cx + 8) from (j0 - 4,
+// i0 - 4), target crop (nz, cy, cx) from (j0, i0), both wrapping in x, y.
+void launch_cnn_gather(const float *X, const float *Tt, int npairs, int nz, int ny, int nx,
+                       const int32_t *crops, int batch, int cy, int cx, float *xb, float *tb,
+                       hipStream_t s);
+
+}  // namespace lesmi

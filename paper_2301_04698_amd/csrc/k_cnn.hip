@@ -1,0 +1,626 @@
+// Guess network kernels: inference of the learned Poisson initial guess and
+// the forward/backward/update kernels that train it on solver-generated
+// pairs.
+//
+// Layouts: single-channel fields are (batch, nz, ny, nx) with x fastest;
+// 16-channel activations are channels-last bfloat16 (cell * 16 + c), so
+// one cell's channels are one 32-byte line.  The two 16 -> 16 layers run on
+// the matrix cores as an implicit GEMM per tap: D(out ch x 16 cells) +=
+// W_tap(out x in) * X_tap(in x 16 cells), FP32 accumulation, one wave per
+// 16 consecutive output cells.  The 1 -> 16 and 16 -> 1 layers and the
+// backward pass are FP32 vector code (FP64 sums in the weight gradient).
+#include <cmath>
+
+#include "cnn_internal.h"
+#include "les_device.h"
+
+namespace lesmi {
+
+CnnGeom cnn_geom(int batch, int nz, int ny, int nx, int periodic, int layer) {
+  CnnGeom G;
+  const int ti = periodic ? 0 : 2 * layer, to = periodic ? 0 : 2 * (layer + 1);
+  G.batch = batch;
+  G.nz = nz;
+  G.nyi = ny - ti;
+  G.nxi = nx - ti;
+  G.nyo = ny - to;
+  G.nxo = nx - to;
+  G.periodic = periodic;
+  G.n_in = (int64_t)batch * nz * G.nyi * G.nxi;
+  G.n_out = (int64_t)batch * nz * G.nyo * G.nxo;
+  return G;
+}
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// FP32 -> bfloat16, round to nearest, ties to even (finite values): add
+// 0x7FFF plus the lowest kept bit, then truncate to the high half.
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ float leaky(float v, float alpha) { return v >= 0.f ? v : alpha * v; }
+
+struct Cell {
+  int b, k, j, i;
+};
+__device__ __forceinline__ Cell decode(int64_t q, int nz, int ny, int nx) {
+  Cell c;
+  c.i = (int)(q % nx);
+  q /= nx;
+  c.j = (int)(q % ny);
+  q /= ny;
+  c.k = (int)(q % nz);
+  c.b = (int)(q / nz);
+  return c;
+}
+
+// Input cell read by output cell c at tap (dz, dy, dx): even mirror in z
+// (radius one: -1 -> 0, nz -> nz - 1), wrap or valid offset in x and y.
+__device__ __forceinline__ int64_t src_cell(const CnnGeom &G, const Cell &c, int dz, int dy,
+                                            int dx) {
+  int kk = c.k + dz;
+  kk = kk < 0 ? 0 : (kk >= G.nz ? G.nz - 1 : kk);
+  int jj, ii;
+  if (G.periodic) {
+    jj = pwrap(c.j + dy, G.nyi);
+    ii = pwrap(c.i + dx, G.nxi);
+  } else {
+    jj = c.j + 1 + dy;
+    ii = c.i + 1 + dx;
+  }
+  return (((int64_t)c.b * G.nz + kk) * G.nyi + jj) * G.nxi + ii;
+}
+
+// ------------------------------------------------------------- forward
+
+__global__ __launch_bounds__(kBlock) void pack_kernel(const float *__restrict__ params,
+                                                      uint16_t *__restrict__ wbf, int n) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) wbf[q] = f2bf(params[q]);
+}
+
+__global__ __launch_bounds__(kBlock) void round_kernel(int64_t n, const float *__restrict__ x,
+                                                       const double *__restrict__ scale,
+                                                       uint16_t *__restrict__ a0) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const float v = scale ? (float)((double)x[q] * *scale) : x[q];
+  a0[q] = f2bf(v);
+}
+
+// Layer 0 (1 -> 16): one thread per output cell, weights in LDS.
+__global__ __launch_bounds__(kBlock) void conv_in_kernel(CnnGeom G, const uint16_t *__restrict__ ain,
+                                                         const float *__restrict__ params,
+                                                         const uint16_t *__restrict__ wbf,
+                                                         float alpha, uint16_t *__restrict__ aout) {
+  __shared__ float w[kCnnTaps * kCnnCh];
+  __shared__ float bias[kCnnCh];
+  for (int e = threadIdx.x; e < kCnnTaps * kCnnCh; e += blockDim.x) w[e] = bf2f(wbf[e]);
+  if (threadIdx.x < kCnnCh) bias[threadIdx.x] = params[cnn_bias_offset(0) + threadIdx.x];
+  __syncthreads();
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= G.n_out) return;
+  const Cell c = decode(q, G.nz, G.nyo, G.nxo);
+  float acc[kCnnCh];
+#pragma unroll
+  for (int o = 0; o < kCnnCh; ++o) acc[o] = bias[o];
+#pragma unroll 3
+  for (int t = 0; t < kCnnTaps; ++t) {
+    const float a = bf2f(ain[src_cell(G, c, t / 9 - 1, (t / 3) % 3 - 1, t % 3 - 1)]);
+#pragma unroll
+    for (int o = 0; o < kCnnCh; ++o) acc[o] += w[t * kCnnCh + o] * a;
+  }
+  uint32_t packed[kCnnCh / 2];
+#pragma unroll
+  for (int o = 0; o < kCnnCh / 2; ++o)
+    packed[o] = (uint32_t)f2bf(leaky(acc[2 * o], alpha)) |
+                ((uint32_t)f2bf(leaky(acc[2 * o + 1], alpha)) << 16);
+  uint4 *dst = (uint4 *)(aout + q * kCnnCh);
+  dst[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
+  dst[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
+}
+
+// Layers 1, 2 (16 -> 16) on the matrix cores.  Lane l of a wave: row = l % 16
+// is its cell of the 16-cell tile and its output channel in the A operand,
+// quad = l / 16 selects input channels 4 quad .. 4 quad + 3 (A, B) and output
+// channels 4 quad .. 4 quad + 3 of the result.
+__global__ __launch_bounds__(kBlock) void conv_mid_kernel(CnnGeom G, const uint16_t *__restrict__ ain,
+                                                          const float *__restrict__ bias,
+                                                          const uint16_t *__restrict__ w,
+                                                          float alpha, uint16_t *__restrict__ aout,
+                                                          int64_t tiles) {
+  const int lane = threadIdx.x & 63;
+  const int row = lane & 15, quad = lane >> 4;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  bf16x4 wa[kCnnTaps];
+#pragma unroll
+  for (int t = 0; t < kCnnTaps; ++t)
+    wa[t] = *(const bf16x4 *)(w + (t * kCnnCh + row) * kCnnCh + 4 * quad);
+  float bq[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) bq[r] = bias[4 * quad + r];
+
+  for (int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; tile < tiles;
+       tile += nwaves) {
+    const int64_t q = tile * 16 + row;
+    const bool valid = q < G.n_out;
+    const Cell c = decode(valid ? q : G.n_out - 1, G.nz, G.nyo, G.nxo);
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < kCnnTaps; ++t) {
+      const int64_t src = src_cell(G, c, t / 9 - 1, (t / 3) % 3 - 1, t % 3 - 1);
+      const bf16x4 xb = *(const bf16x4 *)(ain + src * kCnnCh + 4 * quad);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[t], xb, acc, 0, 0, 0);
+    }
+    if (valid) {
+      const uint32_t lo = (uint32_t)f2bf(leaky(acc[0] + bq[0], alpha)) |
+                          ((uint32_t)f2bf(leaky(acc[1] + bq[1], alpha)) << 16);
+      const uint32_t hi = (uint32_t)f2bf(leaky(acc[2] + bq[2], alpha)) |
+                          ((uint32_t)f2bf(leaky(acc[3] + bq[3], alpha)) << 16);
+      *(uint2 *)(aout + q * kCnnCh + 4 * quad) = make_uint2(lo, hi);
+    }
+  }
+}
+
+// Layer 3 (16 -> 1): one thread per output cell.  GUESS: the output becomes
+// the guess base + s_over_d * y instead of being stored.
+template <typename T, bool GUESS>
+__global__ __launch_bounds__(kBlock) void conv_out_kernel(CnnGeom G, const uint16_t *__restrict__ ain,
+                                                          const float *__restrict__ params,
+                                                          const uint16_t *__restrict__ wbf,
+                                                          float *__restrict__ y,
+                                                          const T *__restrict__ base,
+                                                          const double *__restrict__ s_over_d,
+                                                          T *__restrict__ guess) {
+  __shared__ float w[kCnnTaps * kCnnCh];
+  for (int e = threadIdx.x; e < kCnnTaps * kCnnCh; e += blockDim.x)
+    w[e] = bf2f(wbf[cnn_weight_offset(3) + e]);
+  __syncthreads();
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= G.n_out) return;
+  const Cell c = decode(q, G.nz, G.nyo, G.nxo);
+  float acc = params[cnn_bias_offset(3)];
+#pragma unroll 3
+  for (int t = 0; t < kCnnTaps; ++t) {
+    const int64_t src = src_cell(G, c, t / 9 - 1, (t / 3) % 3 - 1, t % 3 - 1);
+    const uint4 *p = (const uint4 *)(ain + src * kCnnCh);
+    const uint4 v0 = p[0], v1 = p[1];
+    const uint32_t u[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      acc += w[t * kCnnCh + 2 * h] * __uint_as_float(u[h] << 16);
+      acc += w[t * kCnnCh + 2 * h + 1] * __uint_as_float(u[h] & 0xFFFF0000u);
+    }
+  }
+  if (GUESS)
+    guess[q] = (T)((double)base[q] + *s_over_d * (double)acc);
+  else
+    y[q] = acc;
+}
+
+// ---------------------------------------------------------------- loss
+
+__device__ __forceinline__ double lh(const float *__restrict__ f, const float *__restrict__ g,
+                                     int64_t q, int k, int nz, int64_t sx, int64_t sy,
+                                     int64_t plane, double wx, double wy, double wz) {
+  // compact Laplacian / d of (f - g) at an interior cell q (g nullable)
+  auto e = [&](int64_t p) { return (double)f[p] - (g ? (double)g[p] : 0.0); };
+  const int64_t zp = k + 1 < nz ? q + plane : q, zm = k > 0 ? q - plane : q;
+  const double c = e(q);
+  return wx * (e(q + sx) + e(q - sx) - 2.0 * c) + wy * (e(q + sy) + e(q - sy) - 2.0 * c) +
+         wz * (e(zp) + e(zm) - 2.0 * c);
+}
+
+__global__ __launch_bounds__(kBlock) void loss_a_kernel(int64_t n, int nz, int ny, int nx,
+                                                        double wx, double wy, double wz,
+                                                        const float *__restrict__ y,
+                                                        const float *__restrict__ t,
+                                                        float *__restrict__ qout,
+                                                        double *__restrict__ partials) {
+  double num = 0.0, den = 0.0;
+  const int64_t plane = (int64_t)ny * nx;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const Cell c = decode(q, nz, ny, nx);
+    float qv = 0.f;
+    if (c.j >= 1 && c.j < ny - 1 && c.i >= 1 && c.i < nx - 1) {
+      const double qe = lh(y, t, q, c.k, nz, 1, nx, plane, wx, wy, wz);
+      const double qt = lh(t, nullptr, q, c.k, nz, 1, nx, plane, wx, wy, wz);
+      num += qe * qe;
+      den += qt * qt;
+      qv = (float)qe;
+    }
+    qout[q] = qv;
+  }
+  const double sn = block_sum(num);
+  const double sd = block_sum(den);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = sn;
+    partials[gridDim.x + blockIdx.x] = sd;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void loss_final_kernel(const double *__restrict__ partials,
+                                                            int np, double *__restrict__ stats) {
+  double a = 0.0, b = 0.0;
+  for (int q = threadIdx.x; q < np; q += blockDim.x) {
+    a += partials[q];
+    b += partials[np + q];
+  }
+  a = block_sum(a);
+  b = block_sum(b);
+  if (threadIdx.x == 0) {
+    stats[0] = b > 0.0 ? a / b : 0.0;
+    stats[1] = b;
+    stats[2] = b > 0.0 ? 2.0 / b : 0.0;
+  }
+}
+
+// gy = (2/den) Lh(q), q zero outside the crop in x and y, mirror in z.
+__global__ __launch_bounds__(kBlock) void loss_b_kernel(int64_t n, int nz, int ny, int nx,
+                                                        double wx, double wy, double wz,
+                                                        const float *__restrict__ qf,
+                                                        const double *__restrict__ stats,
+                                                        float *__restrict__ gy) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const Cell c = decode(q, nz, ny, nx);
+  const int64_t plane = (int64_t)ny * nx;
+  const double c0 = qf[q];
+  const double xp = c.i + 1 < nx ? qf[q + 1] : 0.0, xm = c.i > 0 ? qf[q - 1] : 0.0;
+  const double yp = c.j + 1 < ny ? qf[q + nx] : 0.0, ym = c.j > 0 ? qf[q - nx] : 0.0;
+  const double zp = qf[c.k + 1 < nz ? q + plane : q], zm = qf[c.k > 0 ? q - plane : q];
+  const double v = wx * (xp + xm) + wy * (yp + ym) + wz * (zp + zm) - 2.0 * (wx + wy + wz) * c0;
+  gy[q] = (float)(stats[2] * v);
+}
+
+// ------------------------------------------------------------ backward
+
+// gprev(cell', i) = leaky'(ain(cell', i)) * sum over (tap, out cell, o) with
+// src(out cell, tap) = cell' of gy(out cell, o) W[tap][o][i].  The z mirror
+// makes wall cells receive a second term: out level 0 at dz = -1 reads
+// level 0, out level nz-1 at dz = +1 reads level nz-1.
+template <int CI, int CO>
+__global__ __launch_bounds__(kBlock) void dgrad_kernel(CnnGeom G, const float *__restrict__ gy,
+                                                       const uint16_t *__restrict__ wl,
+                                                       const uint16_t *__restrict__ ain,
+                                                       float alpha, float *__restrict__ gprev) {
+  __shared__ float w[kCnnTaps * CO * CI];
+  for (int e = threadIdx.x; e < kCnnTaps * CO * CI; e += blockDim.x) w[e] = bf2f(wl[e]);
+  __syncthreads();
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= G.n_in) return;
+  const Cell c = decode(q, G.nz, G.nyi, G.nxi);
+  float acc[CI];
+#pragma unroll
+  for (int i = 0; i < CI; ++i) acc[i] = 0.f;
+  for (int dz = -1; dz <= 1; ++dz) {
+    int ks[2], nk = 0;
+    if (c.k - dz >= 0 && c.k - dz < G.nz) ks[nk++] = c.k - dz;
+    if ((dz == -1 && c.k == 0) || (dz == 1 && c.k == G.nz - 1)) ks[nk++] = c.k;
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int j = c.j - 1 - dy;
+      if (j < 0 || j >= G.nyo) continue;
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int i = c.i - 1 - dx;
+        if (i < 0 || i >= G.nxo) continue;
+        const int t = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
+        for (int m = 0; m < nk; ++m) {
+          const float *g = gy + ((((int64_t)c.b * G.nz + ks[m]) * G.nyo + j) * G.nxo + i) * CO;
+#pragma unroll 2
+          for (int o = 0; o < CO; ++o) {
+            const float gv = g[o];
+            const float *wr = w + (t * CO + o) * CI;
+#pragma unroll
+            for (int i2 = 0; i2 < CI; ++i2) acc[i2] += gv * wr[i2];
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < CI; ++i) {
+    const bool neg = (ain[q * CI + i] & 0x8000u) != 0;
+    gprev[q * CI + i] = acc[i] * (neg ? alpha : 1.f);
+  }
+}
+
+// Weight gradient partials of one block of `chunk` output cells: thread
+// pair (o, i) accumulates the 27 taps in FP64 (products of an FP32 gradient
+// and a bfloat16 activation are exact in FP64); PAIRS < 256 spreads the
+// cells over 256 / PAIRS groups, summed in a fixed order through LDS.
+// Partials layout per block: [tap][o][i] then the CO bias entries.
+template <int CI, int CO>
+__global__ __launch_bounds__(kBlock) void wgrad_kernel(CnnGeom G, const float *__restrict__ gy,
+                                                       const uint16_t *__restrict__ ain,
+                                                       int64_t chunk, double *__restrict__ partials) {
+  constexpr int PAIRS = CI * CO;
+  constexpr int GROUPS = kBlock / PAIRS;
+  constexpr int E = kCnnTaps * PAIRS + CO;
+  __shared__ double red[kBlock];
+  const int pair = threadIdx.x % PAIRS, grp = threadIdx.x / PAIRS;
+  const int o = pair / CI, ci = pair % CI;
+  double acc[kCnnTaps + 1];
+#pragma unroll
+  for (int t = 0; t <= kCnnTaps; ++t) acc[t] = 0.0;
+  const int64_t c0 = (int64_t)blockIdx.x * chunk;
+  const int64_t c1 = c0 + chunk < G.n_out ? c0 + chunk : G.n_out;
+  for (int64_t q = c0 + grp; q < c1; q += GROUPS) {
+    const Cell c = decode(q, G.nz, G.nyo, G.nxo);
+    const double g = gy[q * CO + o];
+    acc[kCnnTaps] += g;
+#pragma unroll
+    for (int t = 0; t < kCnnTaps; ++t) {
+      const int64_t src = src_cell(G, c, t / 9 - 1, (t / 3) % 3 - 1, t % 3 - 1);
+      acc[t] += g * (double)bf2f(ain[src * CI + ci]);
+    }
+  }
+  double *out = partials + (int64_t)blockIdx.x * E;
+  for (int t = 0; t <= kCnnTaps; ++t) {
+    double v = acc[t];
+    if (GROUPS > 1) {
+      __syncthreads();
+      red[threadIdx.x] = v;
+      __syncthreads();
+      if (grp == 0)
+        for (int m = 1; m < GROUPS; ++m) v += red[m * PAIRS + pair];
+    }
+    if (grp == 0) {
+      if (t < kCnnTaps)
+        out[t * PAIRS + pair] = v;
+      else if (ci == 0)
+        out[kCnnTaps * PAIRS + o] = v;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void wgrad_final_kernel(const double *__restrict__ partials,
+                                                             int nblocks, int E, int nw,
+                                                             float *__restrict__ gw,
+                                                             float *__restrict__ gb) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partials[(int64_t)b * E + e];
+  if (e < nw)
+    gw[e] = (float)s;
+  else
+    gb[e - nw] = (float)s;
+}
+
+__global__ __launch_bounds__(kBlock) void adam_kernel(int n, float *__restrict__ p,
+                                                      const float *__restrict__ g,
+                                                      float *__restrict__ m, float *__restrict__ v,
+                                                      float lr, float b1, float b2, float omb1,
+                                                      float omb2, float eps, float c1, float c2) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const float gq = g[q];
+  const float mq = b1 * m[q] + omb1 * gq;
+  const float vq = b2 * v[q] + omb2 * gq * gq;
+  m[q] = mq;
+  v[q] = vq;
+  p[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+}
+
+// ------------------------------------------------- inputs and datasets
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void residual_kernel(Grid g, double ix2, double iy2,
+                                                          double iz2, const T *__restrict__ rhs,
+                                                          const T *__restrict__ base,
+                                                          float *__restrict__ r,
+                                                          double *__restrict__ partials) {
+  double acc = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < g.n;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    double v = (double)rhs[q];
+    if (base) {
+      const int k = (int)(q / g.nxy);
+      const int64_t rr = q - g.nxy * k;
+      const int j = (int)(rr / g.nx);
+      const int i = (int)(rr - (int64_t)g.nx * j);
+      const double c = base[q];
+      const double lap =
+          ((double)gload(base, g, i + 1, j, k, T(1)) + (double)gload(base, g, i - 1, j, k, T(1)) -
+           2.0 * c) * ix2 +
+          ((double)gload(base, g, i, j + 1, k, T(1)) + (double)gload(base, g, i, j - 1, k, T(1)) -
+           2.0 * c) * iy2 +
+          ((double)gload(base, g, i, j, k + 1, T(1)) + (double)gload(base, g, i, j, k - 1, T(1)) -
+           2.0 * c) * iz2;
+      v -= lap;
+    }
+    r[q] = (float)v;
+    acc += v * v;
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void scale_kernel(const double *__restrict__ partials, int np,
+                                                       double n, double d, double *__restrict__ sc) {
+  double a = 0.0;
+  for (int q = threadIdx.x; q < np; q += blockDim.x) a += partials[q];
+  a = block_sum(a);
+  if (threadIdx.x == 0) {
+    const double s = sqrt(a / n);
+    sc[0] = s;
+    sc[1] = s > 0.0 ? 1.0 / s : 0.0;
+    sc[2] = s / d;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void pair_kernel(int64_t n, const float *__restrict__ r,
+                                                      const T *__restrict__ phi,
+                                                      const T *__restrict__ base,
+                                                      const double *__restrict__ sc, double d,
+                                                      float *__restrict__ x, float *__restrict__ t) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const double inv = sc[1];
+  x[q] = (float)((double)r[q] * inv);
+  t[q] = (float)(((double)phi[q] - (base ? (double)base[q] : 0.0)) * d * inv);
+}
+
+__global__ __launch_bounds__(kBlock) void gather_kernel(const float *__restrict__ X,
+                                                        const float *__restrict__ Tt,
+                                                        int64_t pair_stride, int nz, int ny, int nx,
+                                                        const int32_t *__restrict__ crops,
+                                                        int npairs, int cy, int cx, int64_t n_in,
+                                                        int64_t n_t,
+                                                        float *__restrict__ xb,
+                                                        float *__restrict__ tb) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool is_x = q < n_in;
+  if (q >= n_in + n_t) return;
+  const int64_t qq = is_x ? q : q - n_in;
+  const int h = is_x ? 4 : 0;
+  const Cell c = decode(qq, nz, cy + 2 * h, cx + 2 * h);
+  // every index is reduced modulo its range, so any crop entry reads in bounds
+  const int32_t *cr = crops + 3 * c.b;
+  int p = cr[0] % npairs, j = (int)(((int64_t)cr[1] - h + c.j) % ny),
+      i = (int)(((int64_t)cr[2] - h + c.i) % nx);
+  p += p < 0 ? npairs : 0;
+  j += j < 0 ? ny : 0;
+  i += i < 0 ? nx : 0;
+  const int64_t src = (int64_t)p * pair_stride + ((int64_t)c.k * ny + j) * nx + i;
+  if (is_x)
+    xb[qq] = X[src];
+  else
+    tb[qq] = Tt[src];
+}
+
+}  // namespace
+
+// ----------------------------------------------------------- launchers
+
+void launch_cnn_pack(const float *params, uint16_t *wbf, hipStream_t s) {
+  const int n = cnn_param_count();
+  pack_kernel<<<blocks_for(n), kBlock, 0, s>>>(params, wbf, n);
+}
+
+void launch_cnn_round(int64_t n, const float *x, const double *scale, uint16_t *a0, hipStream_t s) {
+  round_kernel<<<blocks_for(n), kBlock, 0, s>>>(n, x, scale, a0);
+}
+
+void launch_cnn_conv(int layer, const CnnGeom &G, const uint16_t *ain, const float *params,
+                     const uint16_t *wbf, float alpha, uint16_t *aout, float *yout, hipStream_t s) {
+  if (layer == 0) {
+    conv_in_kernel<<<blocks_for(G.n_out), kBlock, 0, s>>>(G, ain, params, wbf, alpha, aout);
+  } else if (layer < kCnnLayers - 1) {
+    const int64_t tiles = (G.n_out + 15) / 16;
+    const int64_t waves_wanted = (tiles + 7) / 8;  // about 8 tiles per wave
+    int64_t blocks = (waves_wanted + 3) / 4;
+    blocks = blocks < 1 ? 1 : (blocks > 8192 ? 8192 : blocks);
+    conv_mid_kernel<<<(unsigned)blocks, kBlock, 0, s>>>(G, ain, params + cnn_bias_offset(layer),
+                                                        wbf + cnn_weight_offset(layer), alpha,
+                                                        aout, tiles);
+  } else {
+    conv_out_kernel<float, false><<<blocks_for(G.n_out), kBlock, 0, s>>>(
+        G, ain, params, wbf, yout, nullptr, nullptr, nullptr);
+  }
+}
+
+template <typename T>
+void launch_cnn_guess(const CnnGeom &G, const uint16_t *ain, const float *params,
+                      const uint16_t *wbf, const T *base, const double *s_over_d, T *guess,
+                      hipStream_t s) {
+  conv_out_kernel<T, true><<<blocks_for(G.n_out), kBlock, 0, s>>>(G, ain, params, wbf, nullptr,
+                                                                  base, s_over_d, guess);
+}
+
+void launch_cnn_loss(int batch, int nz, int ny, int nx, double wx, double wy, double wz,
+                     const float *y, const float *t, float *q, double *partials, double *stats,
+                     float *gy, hipStream_t s) {
+  const int64_t n = (int64_t)batch * nz * ny * nx;
+  loss_a_kernel<<<kReduceBlocks, kBlock, 0, s>>>(n, nz, ny, nx, wx, wy, wz, y, t, q, partials);
+  loss_final_kernel<<<1, kBlock, 0, s>>>(partials, kReduceBlocks, stats);
+  if (gy) loss_b_kernel<<<blocks_for(n), kBlock, 0, s>>>(n, nz, ny, nx, wx, wy, wz, q, stats, gy);
+}
+
+void launch_cnn_dgrad(int layer, const CnnGeom &G, const float *gy, const uint16_t *wbf,
+                      const uint16_t *ain, float alpha, float *gprev, hipStream_t s) {
+  const uint16_t *wl = wbf + cnn_weight_offset(layer);
+  if (layer == kCnnLayers - 1)
+    dgrad_kernel<kCnnCh, 1><<<blocks_for(G.n_in), kBlock, 0, s>>>(G, gy, wl, ain, alpha, gprev);
+  else
+    dgrad_kernel<kCnnCh, kCnnCh><<<blocks_for(G.n_in), kBlock, 0, s>>>(G, gy, wl, ain, alpha,
+                                                                        gprev);
+}
+
+void launch_cnn_wgrad(int layer, const CnnGeom &G, const float *gy, const uint16_t *ain,
+                      double *partials, float *grad, hipStream_t s) {
+  const int ci = cnn_cin(layer), co = cnn_cout(layer);
+  const int E = kCnnTaps * ci * co + co;
+  const int64_t chunk = (G.n_out + kCnnWgradBlocks - 1) / kCnnWgradBlocks;
+  if (ci == 1)
+    wgrad_kernel<1, kCnnCh><<<kCnnWgradBlocks, kBlock, 0, s>>>(G, gy, ain, chunk, partials);
+  else if (co == 1)
+    wgrad_kernel<kCnnCh, 1><<<kCnnWgradBlocks, kBlock, 0, s>>>(G, gy, ain, chunk, partials);
+  else
+    wgrad_kernel<kCnnCh, kCnnCh><<<kCnnWgradBlocks, kBlock, 0, s>>>(G, gy, ain, chunk, partials);
+  wgrad_final_kernel<<<blocks_for(E), kBlock, 0, s>>>(partials, kCnnWgradBlocks, E,
+                                                      kCnnTaps * ci * co,
+                                                      grad + cnn_weight_offset(layer),
+                                                      grad + cnn_bias_offset(layer));
+}
+
+void launch_cnn_adam(int n, float *params, const float *grad, float *m, float *v, int step,
+                     double lr, double beta1, double beta2, double eps, hipStream_t s) {
+  const double c1 = 1.0 - std::pow(beta1, step), c2 = 1.0 - std::pow(beta2, step);
+  // 1 - beta in FP64: 1.f - 0.999f carries a 5e-5 relative error
+  adam_kernel<<<blocks_for(n), kBlock, 0, s>>>(n, params, grad, m, v, (float)lr, (float)beta1,
+                                               (float)beta2, (float)(1.0 - beta1),
+                                               (float)(1.0 - beta2), (float)eps, (float)c1,
+                                               (float)c2);
+}
+
+template <typename T>
+void launch_cnn_residual(const Grid &g, const T *rhs, const T *base, float *r, double *partials,
+                         hipStream_t s) {
+  residual_kernel<T><<<kReduceBlocks, kBlock, 0, s>>>(g, 1.0 / (g.dx * g.dx), 1.0 / (g.dy * g.dy),
+                                                      1.0 / (g.dz * g.dz), rhs, base, r, partials);
+}
+
+void launch_cnn_scale(const double *partials, double n, double d, double *sc, hipStream_t s) {
+  scale_kernel<<<1, kBlock, 0, s>>>(partials, kReduceBlocks, n, d, sc);
+}
+
+template <typename T>
+void launch_cnn_pair(const Grid &g, const float *r, const T *phi, const T *base, const double *sc,
+                     double d, float *x, float *t, hipStream_t s) {
+  pair_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g.n, r, phi, base, sc, d, x, t);
+}
+
+void launch_cnn_gather(const float *X, const float *Tt, int npairs, int nz, int ny, int nx,
+                       const int32_t *crops, int batch, int cy, int cx, float *xb, float *tb,
+                       hipStream_t s) {
+  const int64_t n_in = (int64_t)batch * nz * (cy + 8) * (cx + 8);
+  const int64_t n_t = (int64_t)batch * nz * cy * cx;
+  gather_kernel<<<blocks_for(n_in + n_t), kBlock, 0, s>>>(X, Tt, (int64_t)nz * ny * nx, nz, ny,
+                                                          nx, crops, npairs, cy, cx, n_in, n_t,
+                                                          xb, tb);
+}
+
+#define CNN_INST(T)                                                                             \
+  template void launch_cnn_guess<T>(const CnnGeom &, const uint16_t *, const float *,            \
+                                    const uint16_t *, const T *, const double *, T *,            \
+                                    hipStream_t);                                                \
+  template void launch_cnn_residual<T>(const Grid &, const T *, const T *, float *, double *,   \
+                                       hipStream_t);                                             \
+  template void launch_cnn_pair<T>(const Grid &, const float *, const T *, const T *,            \
+                                   const double *, double, float *, float *, hipStream_t);
+CNN_INST(float)
+CNN_INST(double)
+#undef CNN_INST
+
+}  // namespace lesmi

@@ -2,6 +2,7 @@
 // reference state, and the stream-ordered orchestration of one time step
 // of the paper's iterative predictor-corrector scheme (Sec. 2.4).
 #include "les.h"
+#include "les_cnn.h"
 
 #include <hip/hip_runtime.h>
 
@@ -12,39 +13,13 @@
 #include <string>
 #include <vector>
 
+#include "api_util.h"
+#include "cnn_internal.h"
 #include "les_internal.h"
 
 using namespace lesmi;
 
 namespace {
-
-thread_local std::string g_error;
-
-int fail(int code, const char *fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
-  va_end(ap);
-  g_error = buf;
-  return code;
-}
-
-#define HIP_TRY(expr)                                                                    \
-  do {                                                                                   \
-    hipError_t e_ = (expr);                                                              \
-    if (e_ != hipSuccess)                                                                \
-      return fail(LES_ERR_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),   \
-                  __FILE__, __LINE__);                                                   \
-  } while (0)
-
-#define LAUNCH_TRY()                                                                     \
-  do {                                                                                   \
-    hipError_t e_ = hipGetLastError();                                                   \
-    if (e_ != hipSuccess)                                                                \
-      return fail(LES_ERR_HIP, "kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), \
-                  __FILE__, __LINE__);                                                   \
-  } while (0)
 
 // Workspace fields (ids documented in les.h).
 enum Field {
@@ -67,6 +42,9 @@ struct Layout {
   size_t ctl;       // SolveCtl
   size_t diag;      // nz x kDiagStride doubles
   size_t hist;      // n_subiter fields: previous step's solutions (history guess)
+  // learned guess: residual (FP32), network input (bf16), two 16-channel
+  // activations (bf16), parameters (FP32) and their bf16 copy, scales
+  size_t cnn_r, cnn_a0, cnn_act[2], cnn_params, cnn_packed, cnn_sc;
   size_t total;
 };
 
@@ -125,7 +103,23 @@ Layout layout_of(const les_config *c) {
   L.diag = off;
   off = align_up(off + (size_t)c->nz * kDiagStride * sizeof(double));
   L.hist = off;
-  if (c->guess == LES_GUESS_PREVIOUS) off = align_up(off + (size_t)c->n_subiter * n * es);
+  const bool hist = c->guess == LES_GUESS_PREVIOUS || c->guess == LES_GUESS_LEARNED;
+  if (hist) off = align_up(off + (size_t)c->n_subiter * n * es);
+  const bool cnn = c->guess == LES_GUESS_LEARNED;
+  L.cnn_r = off;
+  if (cnn) off = align_up(off + n * sizeof(float));
+  L.cnn_a0 = off;
+  if (cnn) off = align_up(off + n * sizeof(uint16_t));
+  for (int q = 0; q < 2; ++q) {
+    L.cnn_act[q] = off;
+    if (cnn) off = align_up(off + n * kCnnCh * sizeof(uint16_t));
+  }
+  L.cnn_params = off;
+  if (cnn) off = align_up(off + (size_t)cnn_param_count() * sizeof(float));
+  L.cnn_packed = off;
+  if (cnn) off = align_up(off + (size_t)cnn_param_count() * sizeof(uint16_t));
+  L.cnn_sc = off;
+  if (cnn) off = align_up(off + 4 * sizeof(double));
   L.total = off;
   return L;
 }
@@ -154,6 +148,8 @@ struct les_handle {
   std::vector<hipEvent_t> ev_sweep;  // pool bracketing runs of plain sweeps
   bool broken;
   std::vector<char> hist_valid;  // per sub-iteration: history holds a solution
+  bool cnn_bound;                // learned guess: parameters bound
+  float cnn_alpha;               // its leaky ReLU slope
 };
 
 namespace {
@@ -287,7 +283,8 @@ struct SweepTiming {
 
 template <typename T>
 int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
-          les_solve_stats *st, T **result, SweepTiming *timing = nullptr) {
+          les_solve_stats *st, T **result, SweepTiming *timing = nullptr,
+          bool start_recorded = false) {
   const les_config &c = h->cfg;
   const Grid &g = h->grid;
   hipStream_t s = h->stream;
@@ -295,7 +292,8 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
   const int every = c.poisson_check_every;
   T *rhs = V.f[F_RHS];
 
-  HIP_TRY(hipEventRecord(h->ev_s0, s));
+  // start of the solve's time (the caller records it before preparing a guess)
+  if (!start_recorded) HIP_TRY(hipEventRecord(h->ev_s0, s));
   launch_ctl_reset(V.ctl, max_sweeps, fixed > 0 ? 1 : 0, s);
   launch_block_sum(rhs_in, g.n, 0, V.partials, s);
   launch_final(V.partials, kReduceBlocks, kFinalRhsMean, V.ctl, (double)g.n, 0.0, 0, nullptr, s);
@@ -454,7 +452,7 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
 
 // Learned initial guess into the first iterate buffer.
 template <typename T>
-int cnn_guess(les_handle *h, View<T> &V);
+int cnn_guess(les_handle *h, View<T> &V, const T *rhs, const T *base, T *guess);
 
 template <typename T>
 int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step_stats *stats) {
@@ -513,21 +511,23 @@ int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step
       LAUNCH_TRY();
       // Initial guess.  At k = 0 p holds p^n and the workspace p^{n-1}; the
       // extrapolated and learned guesses read both, then p^{n-1} <- p^n.
+      // the solve's time includes preparing its guess
+      HIP_TRY(hipEventRecord(h->ev_s0, s));
       T *hist = (T *)ws(h, h->lay.hist) + (size_t)k * g.n;
       bool guessed = false;
-      if (c.guess == LES_GUESS_PREVIOUS) {
-        // the previous step's solution of this sub-iteration
+      if (c.guess == LES_GUESS_PREVIOUS || c.guess == LES_GUESS_LEARNED) {
+        // the previous step's solution of this sub-iteration, corrected by
+        // the network in the learned form
         guessed = h->hist_valid[k] != 0;
-        if (guessed)
+        if (guessed && c.guess == LES_GUESS_PREVIOUS)
           HIP_TRY(hipMemcpyAsync(V.f[F_PHI0], hist, bytes, hipMemcpyDeviceToDevice, s));
-      } else if (k == 0 && c.guess != LES_GUESS_ZERO) {
-        guessed = true;
-        if (c.guess == LES_GUESS_EXTRAPOLATE) {
-          launch_extrapolate<T>(g, V.P, V.p, V.f[F_PM2], V.f[F_PHI0], s);
-        } else {
-          const int grc = cnn_guess<T>(h, V);
+        if (guessed && c.guess == LES_GUESS_LEARNED) {
+          const int grc = cnn_guess<T>(h, V, V.f[F_RHS], hist, V.f[F_PHI0]);
           if (grc) return grc;
         }
+      } else if (k == 0 && c.guess == LES_GUESS_EXTRAPOLATE) {
+        guessed = true;
+        launch_extrapolate<T>(g, V.P, V.p, V.f[F_PM2], V.f[F_PHI0], s);
         HIP_TRY(hipMemcpyAsync(V.f[F_PM2], V.p, bytes, hipMemcpyDeviceToDevice, s));
         LAUNCH_TRY();
       }
@@ -539,7 +539,7 @@ int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step
       T *phi = nullptr;
       SweepTiming timing;
       timing.enabled = opts && opts->time_sweeps;
-      int rc = solve<T>(h, V, V.f[F_RHS], guessed, fixed, &st, &phi, &timing);
+      int rc = solve<T>(h, V, V.f[F_RHS], guessed, fixed, &st, &phi, &timing, true);
       acc.sweep_seconds += timing.seconds;
       acc.sweeps_timed += timing.sweeps;
       if (opts && opts->records) opts->records[solve_idx] = st;
@@ -557,14 +557,16 @@ int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step
       // gauge (zero mean) and projection
       launch_block_sum<T>(phi, g.n, 0, V.partials, s);
       launch_final(V.partials, kReduceBlocks, kFinalPhiMean, V.ctl, (double)g.n, 0.0, 0, nullptr, s);
-      if (c.guess == LES_GUESS_PREVIOUS) {
+      if (c.guess == LES_GUESS_PREVIOUS || c.guess == LES_GUESS_LEARNED) {
         launch_sub_mean<T>(g, phi, V.ctl, hist, s);
         h->hist_valid[k] = 1;
       }
-      if (k == 0 && step == nsteps - 1 && opts) {  // training pairs of the first solve
-        if (opts->dump_rhs0)
-          HIP_TRY(hipMemcpyAsync(opts->dump_rhs0, V.f[F_RHS], bytes, hipMemcpyDeviceToDevice, s));
-        if (opts->dump_phi0) launch_sub_mean<T>(g, phi, V.ctl, (T *)opts->dump_phi0, s);
+      if (step == nsteps - 1 && opts) {  // the last step's solves (training pairs)
+        if (opts->dump_rhs)
+          HIP_TRY(hipMemcpyAsync((T *)opts->dump_rhs + (size_t)k * g.n, V.f[F_RHS], bytes,
+                                 hipMemcpyDeviceToDevice, s));
+        if (opts->dump_phi)
+          launch_sub_mean<T>(g, phi, V.ctl, (T *)opts->dump_phi + (size_t)k * g.n, s);
       }
       launch_project<T>(g, V.dyn, V.P, phi, V.ctl, V.u, V.v, V.w, V.p, s);
       LAUNCH_TRY();
@@ -652,11 +654,36 @@ int diag_impl(les_handle *h, les_diag *out, double *profiles) {
   return LES_OK;
 }
 
+// Learned guess: r = rhs - L base, s = RMS(r) (FP64 sums), network on
+// bf16(r / s) over the periodic field, guess = base + (s/d) out.
 template <typename T>
-int cnn_guess(les_handle *h, View<T> &V) {
-  (void)h;
-  (void)V;
-  return fail(LES_ERR_STATE, "learned guess requested but no network is bound");
+int cnn_guess(les_handle *h, View<T> &V, const T *rhs, const T *base, T *guess) {
+  if (!h->cnn_bound)
+    return fail(LES_ERR_STATE, "learned guess requested but no network is bound (les_bind_cnn)");
+  const Grid &g = h->grid;
+  hipStream_t s = h->stream;
+  const Layout &L = h->lay;
+  float *r = (float *)ws(h, L.cnn_r);
+  uint16_t *a0 = (uint16_t *)ws(h, L.cnn_a0);
+  uint16_t *act[2] = {(uint16_t *)ws(h, L.cnn_act[0]), (uint16_t *)ws(h, L.cnn_act[1])};
+  const float *params = (const float *)ws(h, L.cnn_params);
+  const uint16_t *packed = (const uint16_t *)ws(h, L.cnn_packed);
+  double *sc = (double *)ws(h, L.cnn_sc);
+  const double D = 2.0 / (g.dx * g.dx) + 2.0 / (g.dy * g.dy) + 2.0 / (g.dz * g.dz);
+  launch_cnn_residual<T>(g, rhs, base, r, V.partials, s);
+  launch_cnn_scale(V.partials, (double)g.n, D, sc, s);
+  launch_cnn_round(g.n, r, sc + 1, a0, s);
+  // one periodic field: batch 1, (nz, ny, nx)
+  const CnnGeom G0 = cnn_geom(1, g.nz, g.ny, g.nx, 1, 0);
+  launch_cnn_conv(0, G0, a0, params, packed, h->cnn_alpha, act[0], nullptr, s);
+  launch_cnn_conv(1, cnn_geom(1, g.nz, g.ny, g.nx, 1, 1), act[0], params, packed, h->cnn_alpha,
+                  act[1], nullptr, s);
+  launch_cnn_conv(2, cnn_geom(1, g.nz, g.ny, g.nx, 1, 2), act[1], params, packed, h->cnn_alpha,
+                  act[0], nullptr, s);
+  launch_cnn_guess<T>(cnn_geom(1, g.nz, g.ny, g.nx, 1, 3), act[0], params, packed, base, sc + 2,
+                      guess, s);
+  LAUNCH_TRY();
+  return LES_OK;
 }
 
 int check_handle(const les_handle *h) {
@@ -777,6 +804,8 @@ int les_init(const les_config *cfg, const les_buffers *bufs, void *stream, les_h
   t.satadj_maxit = cfg->satadj_maxit;
   jacobi_spectrum(cfg, &h->mu_min, &h->mu_max);
   h->hist_valid.assign(cfg->n_subiter, 0);
+  h->cnn_bound = false;
+  h->cnn_alpha = 0.f;
   h->sweeps_per_launch = cfg->sweeps_per_launch > 0 ? cfg->sweeps_per_launch : kDefaultSweepsPerLaunch;
 
   auto cleanup = [&](int code) {
@@ -858,6 +887,57 @@ void les_destroy(les_handle *h) {
   if (h->ctl_host) (void)hipHostFree(h->ctl_host);
   if (h->diag_host) (void)hipHostFree(h->diag_host);
   delete h;
+}
+
+int les_bind_cnn(les_handle *h, const float *params, double alpha) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (h->cfg.guess != LES_GUESS_LEARNED)
+    return fail(LES_ERR_STATE, "les_bind_cnn: the handle was not created with LES_GUESS_LEARNED");
+  if (!params) return fail(LES_ERR_ARG, "params is NULL");
+  if (!(alpha >= 0.0)) return fail(LES_ERR_ARG, "alpha must be >= 0");
+  float *dst = (float *)ws(h, h->lay.cnn_params);
+  if (hipMemcpyAsync(dst, params, (size_t)cnn_param_count() * sizeof(float),
+                     hipMemcpyDeviceToDevice, h->stream) != hipSuccess) {
+    h->broken = true;
+    return fail(LES_ERR_HIP, "copy of the network parameters failed");
+  }
+  launch_cnn_pack(dst, (uint16_t *)ws(h, h->lay.cnn_packed), h->stream);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) {
+    h->broken = true;
+    return fail(LES_ERR_HIP, "packing the network parameters failed");
+  }
+  h->cnn_bound = true;
+  h->cnn_alpha = (float)alpha;
+  return LES_OK;
+}
+
+int les_cnn_guess(les_handle *h, const void *rhs, const void *base, void *guess, double *scale) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (h->cfg.guess != LES_GUESS_LEARNED)
+    return fail(LES_ERR_STATE, "les_cnn_guess: the handle was not created with LES_GUESS_LEARNED");
+  if (!rhs || !base || !guess) return fail(LES_ERR_ARG, "rhs, base and guess must be non-NULL");
+  if (h->cfg.precision == LES_FP64) {
+    View<double> V = view_of<double>(h);
+    rc = cnn_guess<double>(h, V, (const double *)rhs, (const double *)base, (double *)guess);
+  } else {
+    View<float> V = view_of<float>(h);
+    rc = cnn_guess<float>(h, V, (const float *)rhs, (const float *)base, (float *)guess);
+  }
+  if (rc) {
+    if (rc == LES_ERR_HIP) h->broken = true;
+    return rc;
+  }
+  if (scale) {
+    if (hipMemcpyAsync(scale, ws(h, h->lay.cnn_sc), sizeof(double), hipMemcpyDeviceToHost,
+                       h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+      h->broken = true;
+      return fail(LES_ERR_HIP, "reading the guess scale failed");
+    }
+  }
+  return LES_OK;
 }
 
 const char *les_last_error(void) { return g_error.c_str(); }

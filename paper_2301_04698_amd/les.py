@@ -76,7 +76,7 @@ class LesPoissonOpts(C.Structure):
 class LesStepOpts(C.Structure):
     _fields_ = [("replay_sweeps", C.POINTER(C.c_int32)), ("records", C.POINTER(LesSolveStats)),
                 ("time_sweeps", C.c_int32), ("reserved", C.c_int32),
-                ("dump_rhs0", C.c_void_p), ("dump_phi0", C.c_void_p)]
+                ("dump_rhs", C.c_void_p), ("dump_phi", C.c_void_p)]
 
 
 class LesStepStats(C.Structure):
@@ -235,16 +235,17 @@ class LES:
     def step(self, nsteps=1, replay=None, records=False, time_sweeps=False, dump=None):
         """Advance nsteps; returns (rc, stats dict, per-solve records or None).
 
-        dump: optional (rhs0, phi0) device tensors receiving the first
-        solve's centred right-hand side and solution of the last step."""
+        dump: optional (rhs, phi) device tensors of n_subiter * n elements
+        receiving the centred right-hand sides and zero-mean solutions of
+        the last step's solves (sub-iteration k at offset k * n)."""
         K = self.cfg.n_subiter
         opts = LesStepOpts()
         opts.time_sweeps = 1 if time_sweeps else 0
         if dump is not None:
             for t in dump:
-                assert t.is_contiguous() and t.dtype == self.dtype and t.numel() == self._n()
-            opts.dump_rhs0 = dump[0].data_ptr()
-            opts.dump_phi0 = dump[1].data_ptr()
+                assert t.is_contiguous() and t.dtype == self.dtype and t.numel() == K * self._n()
+            opts.dump_rhs = dump[0].data_ptr()
+            opts.dump_phi = dump[1].data_ptr()
         rec = None
         keep = []
         if replay is not None:

@@ -14,9 +14,11 @@ from conftest import ROOT, load_table1
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "les.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = set(re.findall(r"\b(les_[a-z_]+)\s*\(", src))
+    names = set()
+    for h in ("les.h", "les_cnn.h"):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(les_[a-z_]+)\s*\(", src))
     return sorted(names)
 
 
@@ -27,9 +29,11 @@ def lib():
 
 
 def test_exports_every_declared_symbol(lib):
+    from paper_2301_04698_amd import cnn
     L = lib.load()
+    cnn.lib()
     names = declared_functions()
-    assert set(names) == set(lib.EXPORTS), names
+    assert set(names) == set(lib.EXPORTS) | set(cnn.EXPORTS), names
     for n in names:
         assert hasattr(L, n), n
     out = subprocess.run(["nm", "-D", "--defined-only", lib.LIB_PATH], capture_output=True, text=True)
@@ -122,3 +126,49 @@ def test_workspace_layout(lib):
         assert offs[-1] + n * es <= total
     c5 = lib.make_config(li.workload("C5"))
     assert lib.workspace_bytes(c5) < 32 * 2 ** 30  # fits easily in 288 GB of HBM
+
+
+# ------------------------------------------------------ guess network ABI
+
+def test_cnn_dims_layout_and_counts(lib, oracle_lib, tmp_path):
+    from oracle import cnn as ocnn
+    from paper_2301_04698_amd import cnn
+    prog = tmp_path / "cz.c"
+    prog.write_text(r'''
+#include "les_cnn.h"
+#include <stdio.h>
+#include <stddef.h>
+int main(void) {
+  printf("%zu %zu\n", sizeof(les_cnn_dims), offsetof(les_cnn_dims, alpha));
+  return 0;
+}''')
+    exe = tmp_path / "cz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    assert got == [C.sizeof(cnn.CnnDims), cnn.CnnDims.alpha.offset]
+    assert cnn.param_count() == ocnn.param_count() == 14737
+    for l in range(4):
+        assert cnn.weight_offset(l) == ocnn.weight_offset(l)
+        assert cnn.bias_offset(l) == ocnn.bias_offset(l)
+
+
+def test_cnn_work_bytes_validation(lib):
+    from paper_2301_04698_amd import cnn
+    ok = cnn.dims((2, 16, 20, 21), periodic=False)
+    assert cnn.work_bytes(ok) > 2 * 16 * 20 * 21 * (2 + 3 * 32)
+    for bad in (cnn.dims((0, 16, 20, 20)), cnn.dims((1, 16, 10, 20)),
+                cnn.dims((1, 16, 20, 20), alpha=-1.0)):
+        with pytest.raises(lib.LesError):
+            cnn.work_bytes(bad)
+    assert cnn.work_bytes(cnn.dims((1, 8, 5, 5), periodic=True)) > 0
+
+
+def test_learned_guess_workspace(lib):
+    p = li.workload("C1")
+    base = lib.workspace_bytes(lib.make_config(p))
+    prev = lib.workspace_bytes(lib.make_config(dict(p, guess="previous")))
+    learned = lib.workspace_bytes(lib.make_config(dict(p, guess="learned")))
+    n = p["nx"] * p["ny"] * p["nz"]
+    assert prev >= base + p["n_subiter"] * n * 8
+    # residual, network input, two 16-channel activations and the parameters
+    assert learned >= prev + n * (4 + 2 + 2 * 32) + 14737 * 6

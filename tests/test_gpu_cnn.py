@@ -1,0 +1,245 @@
+"""GPU parity of the guess network (learned Poisson initial guess) against
+the oracle of oracle/cnn_oracle.c, through the C ABI of include/les_cnn.h.
+
+Both sides round weights and layer inputs to bfloat16 at the same points;
+the GPU sums in FP32 (matrix cores for the 16 -> 16 layers), the oracle in
+FP64.  A pre-activation within FP32 rounding of a bfloat16 rounding
+boundary can round the other way (about 3e-5 of the values), so stored
+activations are compared by count of one-ulp differences and outputs by a
+relative L2 bound derived from that rate.
+"""
+import numpy as np
+import pytest
+
+import les_inputs as li
+
+pytestmark = pytest.mark.gpu
+
+BLOCKS = [(27 * ci * co, 27 * ci, co) for ci, co in zip((1, 16, 16, 16), (16, 16, 16, 1))]
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_04698_amd import cnn, les
+    les.load()
+    cnn.lib()
+    return cnn
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def params(seed, bias=0.2):
+    from oracle import cnn as ocnn
+    p = li.cnn_init(seed, BLOCKS)
+    rng = np.random.default_rng(seed)
+    for l in range(4):
+        o = ocnn.bias_offset(l)
+        p[o:o + (16 if l < 3 else 1)] = np.float32(bias * rng.standard_normal(16 if l < 3 else 1))
+    return p
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().double().numpy()
+
+
+@pytest.mark.parametrize("periodic,shape", [(False, (2, 6, 21, 19)), (True, (1, 5, 12, 40)),
+                                            (False, (1, 3, 11, 11))])
+def test_forward_matches_oracle(gpu, periodic, shape):
+    from oracle import cnn as ocnn
+    p = params(1)
+    x = np.random.default_rng(2).standard_normal(shape).astype(np.float32).astype(np.float64)
+    ref, acts, _ = ocnn.forward(p, x, periodic=periodic, alpha=0.1)
+    P = _t(p)
+    out, work = gpu.forward(P, gpu.pack(P), _t(x), periodic=periodic, alpha=0.1)
+    got = _np(out)
+    assert got.shape == ref.shape
+    assert rel(got, ref) <= 2e-4, rel(got, ref)
+
+
+@pytest.mark.parametrize("layer,c_in,c_out", [(0, 0, 5), (1, 3, 9), (1, 12, 0), (2, 7, 15),
+                                              (3, 11, 0)])
+def test_single_layer_routing(gpu, layer, c_in, c_out):
+    """One random layer between pass-through layers: the GPU output equals
+    the oracle's up to rare one-ulp bfloat16 flips.  Catches a wrong
+    channel or lane mapping of the matrix-core tiles."""
+    from oracle import cnn as ocnn
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from test_cnn_oracle import _select
+    p = _select(params(3), layer, c_in, c_out)
+    x = np.random.default_rng(4).standard_normal((2, 4, 19, 23)).astype(np.float32).astype(float)
+    ref, _, _ = ocnn.forward(p, x, periodic=False, alpha=0.1)
+    P = _t(p)
+    out, _ = gpu.forward(P, gpu.pack(P), _t(x), periodic=False, alpha=0.1)
+    got = _np(out)
+    diff = np.abs(got - ref) > 1e-6 * np.abs(ref).max()
+    assert diff.mean() <= 1e-3, diff.mean()
+    assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3)) <= 2.0 ** -7
+
+
+def test_loss_and_gradient_match_oracle(gpu):
+    from oracle import cnn as ocnn
+    rng = np.random.default_rng(5)
+    y = rng.standard_normal((2, 6, 9, 7)).astype(np.float32).astype(float)
+    t = rng.standard_normal((2, 6, 9, 7)).astype(np.float32).astype(float)
+    Lr, gr = ocnn.loss(y, t, 35.0, 30.0, 5.0)
+    val, gout = gpu.loss((2, 6, 17, 15), _t(y), _t(t), 35.0, 30.0, 5.0,
+                         gpu.empty_work(gpu.dims((2, 6, 17, 15))))
+    assert val == pytest.approx(Lr, rel=1e-10)
+    assert rel(_np(gout), gr) <= 1e-6
+
+
+def test_backward_matches_oracle(gpu):
+    """Parameter gradient from the same output gradient: the oracle's FP64
+    backward over its rounded activations against the GPU's FP32 dgrad and
+    FP64-summed wgrad over the GPU's activations."""
+    from oracle import cnn as ocnn
+    p = params(6)
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((2, 5, 18, 20)).astype(np.float32).astype(float)
+    out, acts, pre = ocnn.forward(p, x, periodic=False, alpha=0.1)
+    gout = rng.standard_normal(out.shape).astype(np.float32).astype(float)
+    ref = ocnn.backward(p, x, acts, pre, gout, periodic=False, alpha=0.1)
+    P = _t(p)
+    packed = gpu.pack(P)
+    _, work = gpu.forward(P, packed, _t(x), periodic=False, alpha=0.1)
+    got = _np(gpu.backward(x.shape, packed, work, _t(gout), alpha=0.1))
+    for l in range(4):
+        a, b = ocnn.weight_offset(l), ocnn.bias_offset(l)
+        e = b + (16 if l < 3 else 1)
+        assert rel(got[a:b], ref[a:b]) <= 5e-4, (l, rel(got[a:b], ref[a:b]))
+        assert rel(got[b:e], ref[b:e]) <= 5e-4, (l, "bias")
+    assert rel(got, ref) <= 2e-4
+
+
+def test_backward_deterministic(gpu):
+    p = params(8)
+    x = np.random.default_rng(9).standard_normal((3, 6, 20, 20)).astype(np.float32)
+    P = _t(p)
+    packed = gpu.pack(P)
+    g = []
+    for _ in range(2):
+        out, work = gpu.forward(P, packed, _t(x), periodic=False, alpha=0.1)
+        g.append(_np(gpu.backward(x.shape, packed, work, out.clone(), alpha=0.1)))
+    assert np.array_equal(g[0], g[1])
+
+
+def test_adam_matches_oracle(gpu):
+    from oracle import cnn as ocnn
+    import torch
+    rng = np.random.default_rng(10)
+    n = 1000
+    p0 = rng.standard_normal(n).astype(np.float32).astype(float)
+    P, M, V = _t(p0), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    p, m, v = p0.copy(), np.zeros(n), np.zeros(n)
+    for s in range(1, 4):
+        g = rng.standard_normal(n).astype(np.float32).astype(float)
+        gpu.adam(P, _t(g), M, V, s, lr=1e-3)
+        ocnn.adam(p, g.copy(), m, v, s, lr=1e-3)
+    # FP32 parameters: each step rounds p to 2^-24 relative, so compare p
+    # itself and the FP32 moments, not the tiny increments
+    assert rel(_np(P), p) <= 1e-6
+    assert rel(_np(M), m) <= 1e-6 and rel(_np(V), v) <= 1e-6
+
+
+def test_pair_and_gather(gpu, oracle_lib):
+    """Training pair (residual of the base, its RMS, normalised target) and
+    crops with wrap-around."""
+    import torch
+    from paper_2301_04698_amd import les
+    p = li.workload("C1", nx=24, ny=20, nz=16, precision="fp32")
+    sim = les.LES(p)
+    shape = (16, 20, 24)
+    rhs = li.random_field(shape, seed=11)
+    base = li.random_field(shape, seed=12) * 50.0
+    phi = base + li.random_field(shape, seed=13) * 5.0
+    cast = lambda a: torch.from_numpy(a.astype(np.float32)).cuda()
+    x, t = torch.empty(shape, device="cuda"), torch.empty(shape, device="cuda")
+    s = gpu.pair(sim, cast(rhs), cast(base), cast(phi), x, t)
+    b32 = base.astype(np.float32).astype(float)
+    r = rhs.astype(np.float32).astype(float) - oracle_lib.laplacian(p, b32)
+    d = 2 / p["dx"] ** 2 + 2 / p["dy"] ** 2 + 2 / p["dz"] ** 2
+    s_ref = np.sqrt(np.mean(r ** 2))
+    assert s == pytest.approx(s_ref, rel=1e-6)
+    assert rel(_np(x), r / s_ref) <= 1e-6
+    tref = (phi.astype(np.float32).astype(float) - b32) * d / s_ref
+    assert rel(_np(t), tref) <= 1e-6
+    X = torch.stack([x, 2 * x]).contiguous()
+    T = torch.stack([t, -t]).contiguous()
+    crops = torch.tensor([[1, 18, 22], [0, 0, 3], [3, -1, 7]], dtype=torch.int32)
+    xb, tb = gpu.gather(X, T, crops.reshape(-1), 6, 5)
+    Xn, Tn = _np(X), _np(T)
+    for b, (pp, j0, i0) in enumerate([(1, 18, 22), (0, 0, 3), (1, 19, 7)]):
+        jj = (j0 - 4 + np.arange(14)) % 20
+        ii = (i0 - 4 + np.arange(13)) % 24
+        assert np.array_equal(_np(xb)[b], Xn[pp][:, jj][:, :, ii])
+        jj = (j0 + np.arange(6)) % 20
+        ii = (i0 + np.arange(5)) % 24
+        assert np.array_equal(_np(tb)[b], Tn[pp][:, jj][:, :, ii])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_learned_guess_matches_oracle(gpu, oracle_lib, precision):
+    """The guess of a bound network on a whole periodic field: residual,
+    scale, network and combination against the oracle."""
+    import torch
+    from oracle import cnn as ocnn
+    from paper_2301_04698_amd import les
+    p = li.workload("C1", nx=32, ny=24, nz=16, precision=precision, guess="learned")
+    sim = les.LES(p)
+    prm = params(14, bias=0.05)
+    gpu.bind(sim, _t(prm), alpha=0.1)
+    shape = (16, 24, 32)
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    rhs = li.random_field(shape, seed=15)
+    base = li.random_field(shape, seed=16) * 30.0
+    R, B = torch.from_numpy(rhs).to("cuda", dt), torch.from_numpy(base).to("cuda", dt)
+    g, s = gpu.guess(sim, R, B)
+    rb = _np(R)
+    bb = _np(B)
+    r = rb - oracle_lib.laplacian(dict(p, guess="zero"), bb)
+    s_ref = np.sqrt(np.mean(r ** 2))
+    assert s == pytest.approx(s_ref, rel=1e-6)
+    d = 2 / p["dx"] ** 2 + 2 / p["dy"] ** 2 + 2 / p["dz"] ** 2
+    x = (r.astype(np.float32) / np.float32(1.0)).astype(float) / s_ref
+    out, _, _ = ocnn.forward(prm, x[None], periodic=True, alpha=0.1)
+    corr = _np(g) - bb
+    assert rel(corr, s_ref / d * out[0]) <= 5e-4
+
+
+def test_learned_step_converges(gpu):
+    """A learned-guess run (random network) still stops every solve at the
+    tolerance and stays within tolerance-level distance of the plain run."""
+    import torch
+    from paper_2301_04698_amd import les
+    base = li.workload("C1m", nx=40, ny=24, nz=32, precision="fp32", poisson_tol=1e-5,
+                       poisson_scheme="chebyshev")
+    out = {}
+    for g in ("zero", "learned"):
+        p = dict(base, guess=g)
+        sim = les.LES(p, li.initial_state(p))
+        if g == "learned":
+            with pytest.raises(les.LesError):
+                sim.step(2)   # no network bound yet (first step needs none)
+            sim = les.LES(p, li.initial_state(p))
+            gpu.bind(sim, _t(params(17, bias=0.0)) * 0.1, alpha=0.1)
+        rc, stats, recs = sim.step(5, records=True)
+        assert stats["not_converged"] == 0
+        for r in recs:
+            assert r["res_norm"] <= p["poisson_tol"] * r["rhs_norm"]
+        out[g] = sim.state_numpy()
+    for k in ("u", "v", "w", "thl", "qt", "p"):
+        d = out["zero"][k] - out["zero"][k].mean(axis=(1, 2), keepdims=True)
+        assert np.linalg.norm(out["learned"][k] - out["zero"][k]) <= 1e-3 * np.linalg.norm(d)

@@ -10,7 +10,11 @@ before the timed region starts.
 
 Prints one JSON line: Mcell-steps/s over the timed steps, Poisson seconds
 per step, the roofline of the dominant kernel (the Chebyshev sweep) and the
-FP64 CPU oracle timed on the host on a bounded sample.
+FP64 CPU oracle timed on the host on a bounded sample.  `value` is the plain
+form (every solve starts from zero).  The learned form (each solve starts
+from the previous step's solution corrected by the trained guess network,
+whose inference time counts in the Poisson seconds) runs the same steps
+from the same initial state and is reported under "learned".
 """
 from __future__ import annotations
 
@@ -30,6 +34,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # 1 GiB copy calibration); see profiles/sweep_kernel_hbm_traffic_pmc.md.
 # Valid only for the sweep source it was taken on (sha256 prefix).
 SWEEP_SOURCE = os.path.join(ROOT, "paper_2301_04698_amd", "csrc", "k_tsweep.hip")
+GUESS_WEIGHTS = os.path.join(ROOT, "paper_2301_04698_amd", "weights", "guess_256x256x128.npy")
 MEASURED_TRAFFIC = {
     "sha256": "e7ce655fb8bec1ad",
     "bytes": {(256, 256, 128): 104.9e6 + 33.6e6, (512, 512, 256): 981.5e6 + 268.4e6},
@@ -50,7 +55,7 @@ def measured_traffic(p, S):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -63,6 +68,9 @@ def parse():
     ap.add_argument("--sweeps", type=int, default=200)
     ap.add_argument("--sweeps-per-launch", type=int, default=0)
     ap.add_argument("--bytes", type=int, default=1 << 30)
+    ap.add_argument("--guess-weights", default=GUESS_WEIGHTS,
+                    help="trained guess network for the learned form ('' to skip it)")
+    ap.add_argument("--guess-alpha", type=float, default=0.1)
     return ap.parse_args()
 
 
@@ -150,6 +158,51 @@ def cpu_baseline(p, sweeps_per_step, crop):
                    f"crop ({t_np:.1f} s, scaled per cell to {p['nx']}x{p['ny']}x{p['nz']}) plus "
                    f"{nsw} sweeps at full size ({t_sw * 1e3:.1f} ms/sweep) times the measured "
                    f"{sweeps_per_step:.0f} sweeps/step; extrapolated s/step {t_step:.1f}"),
+    }
+
+
+def learned_form(p, args, plain_sweeps, plain_poisson, plain_value):
+    """The same steps from the same initial state with the learned guess."""
+    import numpy as np
+    import torch
+
+    import les_inputs as li
+    from paper_2301_04698_amd import cnn, les
+
+    pl = dict(p, guess="learned")
+    sim = les.LES(pl, li.initial_state(pl), device="cuda:0")
+    cnn.bind(sim, torch.from_numpy(np.load(args.guess_weights)), args.guess_alpha)
+    if args.warmup > 0:
+        sim.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, st, recs = sim.step(args.steps, records=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if rc not in (les.LES_OK, les.LES_WARN_NOT_CONVERGED):
+        raise SystemExit(f"les_step (learned guess) failed: {rc}")
+    K = p["n_subiter"]
+    sweeps = st["sweeps_total"] / args.steps
+    poisson = st["poisson_seconds"] / args.steps
+    value = p["nx"] * p["ny"] * p["nz"] * args.steps / wall / 1e6
+    sim.close()
+    return {
+        "value": value,
+        "unit": "Mcell-steps/s",
+        "ms_per_step": wall / args.steps * 1e3,
+        "poisson_s_per_step": poisson,
+        "sweeps_per_step": sweeps,
+        "sweeps_per_solve": [float(np.mean([r["sweeps"] for i, r in enumerate(recs) if i % K == k]))
+                             for k in range(K)],
+        "iterations_saved_per_step": plain_sweeps - sweeps,
+        "poisson_speedup": plain_poisson / poisson,
+        "speedup": value / plain_value,
+        "not_converged": st["not_converged"],
+        "res_rel_max": st["res_rel_max"],
+        "weights": os.path.relpath(args.guess_weights, ROOT),
+        "note": ("each solve after the first step starts from the previous step's solution of the "
+                 "same sub-iteration plus the network's correction; the network's inference time "
+                 "is inside poisson_s_per_step; same residual test as the plain form"),
     }
 
 
@@ -249,6 +302,11 @@ def main():
                      if bytes_launch < 256e6 else "working set exceeds the 256 MB Infinity Cache"),
         },
     }
+    if args.guess_weights and os.path.exists(args.guess_weights):
+        out["learned"] = learned_form(p, args, sweeps_step, st["poisson_seconds"] / args.steps,
+                                      value)
+    else:
+        out["learned"] = None
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, sweeps_step, args.cpu_crop)
     print(json.dumps(out), flush=True)

@@ -259,7 +259,7 @@ def main():
     diag = sim.diagnostics()
 
     out = {
-        "metric": "Mcell-steps/s and Poisson s/step at residual 1e-6, plain guess",
+        "metric": "Mcell-steps/s and Poisson s/step at residual 1e-6, plain vs learned guess",
         "value": value,
         "unit": "Mcell-steps/s",
         "n_gpus": 1,

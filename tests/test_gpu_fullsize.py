@@ -1,0 +1,127 @@
+"""Parity at the benchmark's full size, 256 x 256 x 128 FP32 (8.39 M cells),
+in the launch configuration bench.py times (one Chebyshev sweep per
+launch, default tiles).
+
+* One whole time step, all physics, element by element against the FP64
+  oracle, with both sides applying the same 40 sweeps per solve (the
+  oracle finishes a full-size step with few sweeps in seconds).
+* 60 full-size Chebyshev sweeps against the oracle's.
+* Every solve of a tolerance-controlled run meets the residual test when
+  the residual is recomputed on the host in FP64 from the returned field.
+* The learned guess on the full field against the oracle network on crops
+  (a crop with a four-cell halo gives the periodic output exactly).
+"""
+import numpy as np
+import pytest
+
+import les_inputs as li
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("u", "v", "w", "thl", "qt", "p")
+
+
+@pytest.fixture(scope="module")
+def les():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_04698_amd import les
+    les.load()
+    return les
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def c2(**kw):
+    return li.workload("C2", **kw)
+
+
+def test_full_size_step_matches_oracle(les, oracle_lib):
+    p = c2()
+    st0 = li.initial_state(p)
+    rng = np.random.default_rng(21)
+    for k in ("u", "v", "w"):
+        st0[k] = st0[k] + 0.3 * rng.standard_normal(st0[k].shape)
+    # both sides start from FP32 values
+    st0 = {k: v.astype(np.float32).astype(np.float64) for k, v in st0.items()}
+    replay = [40] * p["n_subiter"]
+    ost = {k: v.copy() for k, v in st0.items()}
+    oracle_lib.step(p, ost, nsteps=1, replay=replay)
+    sim = les.LES(p, st0)
+    sim.step(1, replay=replay)
+    gst = sim.state_numpy()
+    errs = {k: rel(gst[k], ost[k]) for k in FIELDS}
+    print("full-size step rel errors", errs)
+    for k, e in errs.items():
+        assert e <= 1e-5, (k, e)
+
+
+def test_full_size_sweeps_match_oracle(les, oracle_lib):
+    import torch
+    p = c2()
+    shape = (p["nz"], p["ny"], p["nx"])
+    rhs = li.random_field(shape, seed=22).astype(np.float32).astype(np.float64)
+    ref, _ = oracle_lib.poisson(p, rhs, fixed_sweeps=60)
+    sim = les.LES(p)
+    phi, st, _ = sim.poisson_solve(torch.from_numpy(rhs), fixed_sweeps=60)
+    got = phi.double().cpu().numpy()
+    assert st["sweeps"] == 60
+    assert rel(got, ref) <= 1e-5, rel(got, ref)
+
+
+def test_full_size_solves_meet_tolerance(les, oracle_lib):
+    """Recompute ||rhs - L phi|| in FP64 on the host for every solve of the
+    last of three steps (plain guess) and compare with tol ||rhs||."""
+    import torch
+    p = c2()
+    K = p["n_subiter"]
+    n = p["nx"] * p["ny"] * p["nz"]
+    shape = (p["nz"], p["ny"], p["nx"])
+    sim = les.LES(p, li.initial_state(p))
+    sim.step(2)
+    rhs = torch.empty(K * n, dtype=torch.float32, device="cuda")
+    phi = torch.empty_like(rhs)
+    rc, st, recs = sim.step(1, records=True, dump=(rhs, phi))
+    R = rhs.double().cpu().numpy().reshape(K, *shape)
+    P = phi.double().cpu().numpy().reshape(K, *shape)
+    for k in range(K):
+        r = R[k] - oracle_lib.laplacian(p, P[k])
+        ratio = np.linalg.norm(r) / np.linalg.norm(R[k])
+        print(f"solve {k}: {recs[k]['sweeps']} sweeps, host FP64 residual ratio {ratio:.3e}")
+        assert recs[k]["status"] == 0
+        # phi is stored in FP32 after the FP64 test: allow its rounding
+        assert ratio <= 1.05 * p["poisson_tol"], ratio
+        assert abs(P[k].mean()) <= 1e-6 * np.sqrt(np.mean(P[k] ** 2))
+
+
+def test_full_size_learned_guess_on_crops(les, oracle_lib):
+    import torch
+    from oracle import cnn as ocnn
+    from paper_2301_04698_amd import cnn
+    p = c2(guess="learned")
+    shape = (p["nz"], p["ny"], p["nx"])
+    blocks = [(27 * ci * co, 27 * ci, co) for ci, co in zip(cnn.CIN, cnn.COUT)]
+    prm = li.cnn_init(23, blocks)
+    sim = les.LES(p)
+    cnn.bind(sim, torch.from_numpy(prm.astype(np.float32)), alpha=0.1)
+    rhs = li.random_field(shape, seed=24)
+    base = li.random_field(shape, seed=25) * 40.0
+    R = torch.from_numpy(rhs.astype(np.float32)).cuda()
+    B = torch.from_numpy(base.astype(np.float32)).cuda()
+    g, s = cnn.guess(sim, R, B)
+    corr = (g.double() - B.double()).cpu().numpy()
+    b64 = B.double().cpu().numpy()
+    r = R.double().cpu().numpy() - oracle_lib.laplacian(dict(p, guess="zero"), b64)
+    assert s == pytest.approx(np.sqrt(np.mean(r ** 2)), rel=1e-6)
+    d = 2 / p["dx"] ** 2 + 2 / p["dy"] ** 2 + 2 / p["dz"] ** 2
+    x = r.astype(np.float32).astype(np.float64) / s
+    for (j0, i0) in ((0, 0), (100, 250), (251, 37)):
+        jj = (j0 - 4 + np.arange(24)) % p["ny"]
+        ii = (i0 - 4 + np.arange(24)) % p["nx"]
+        out, _, _ = ocnn.forward(prm, x[:, jj][:, :, ii][None], periodic=False, alpha=0.1)
+        got = corr[:, (j0 + np.arange(16)) % p["ny"]][:, :, (i0 + np.arange(16)) % p["nx"]]
+        e = rel(got, s / d * out[0])
+        assert e <= 5e-4, ((j0, i0), e)

@@ -120,6 +120,17 @@ def run_copy(args):
                       "us_per_copy": s * 1e6, "GBs_read_plus_write": 8 * n / s / 1e9}), flush=True)
 
 
+def sweep_kernel_name(p, S):
+    """Template instance of the plain (no residual check) sweep launch."""
+    es = 8 if p["precision"] == "fp64" else 4
+    cheb = "true" if p["poisson_scheme"] == "chebyshev" else "false"
+    T = "double" if es == 8 else "float"
+    if S != 1:
+        return f"sweep2_kernel<{T}, 8, {cheb}, false>"
+    streamed = 4.0 * p["nx"] * p["ny"] * p["nz"] * es > 192e6
+    return f"sweep1_kernel<{T}, {16 if streamed else 4}, {cheb}, false, {'true' if streamed else 'false'}>"
+
+
 def sweep_bytes_per_cell(p):
     es = 8 if p["precision"] == "fp64" else 4
     # Chebyshev: read phi_m, phi_{m-1}, rhs; write phi_{m+1}.  Jacobi: 3 arrays.
@@ -288,8 +299,7 @@ def main():
         "cfl": diag["cfl"],
         "roofline": {
             "bound": "hbm",
-            "kernel": (f"sweep{S}_kernel<{'float' if p['precision'] == 'fp32' else 'double'}, "
-                       f"{'true' if p['poisson_scheme'] == 'chebyshev' else 'false'}, false>"),
+            "kernel": sweep_kernel_name(p, S),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

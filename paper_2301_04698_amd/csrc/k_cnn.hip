@@ -96,50 +96,76 @@ __global__ __launch_bounds__(kBlock) void round_kernel(int64_t n, const float *_
   a0[q] = f2bf(v);
 }
 
-// Layer 0 (1 -> 16): one thread per output cell, weights in LDS.
-__global__ __launch_bounds__(kBlock) void conv_in_kernel(CnnGeom G, const uint16_t *__restrict__ ain,
-                                                         const float *__restrict__ params,
-                                                         const uint16_t *__restrict__ wbf,
-                                                         float alpha, uint16_t *__restrict__ aout) {
-  __shared__ float w[kCnnTaps * kCnnCh];
-  __shared__ float bias[kCnnCh];
-  for (int e = threadIdx.x; e < kCnnTaps * kCnnCh; e += blockDim.x) w[e] = bf2f(wbf[e]);
-  if (threadIdx.x < kCnnCh) bias[threadIdx.x] = params[cnn_bias_offset(0) + threadIdx.x];
-  __syncthreads();
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= G.n_out) return;
-  const Cell c = decode(q, G.nz, G.nyo, G.nxo);
-  float acc[kCnnCh];
-#pragma unroll
-  for (int o = 0; o < kCnnCh; ++o) acc[o] = bias[o];
-#pragma unroll 3
-  for (int t = 0; t < kCnnTaps; ++t) {
-    const float a = bf2f(ain[src_cell(G, c, t / 9 - 1, (t / 3) % 3 - 1, t % 3 - 1)]);
-#pragma unroll
-    for (int o = 0; o < kCnnCh; ++o) acc[o] += w[t * kCnnCh + o] * a;
-  }
-  uint32_t packed[kCnnCh / 2];
-#pragma unroll
-  for (int o = 0; o < kCnnCh / 2; ++o)
-    packed[o] = (uint32_t)f2bf(leaky(acc[2 * o], alpha)) |
-                ((uint32_t)f2bf(leaky(acc[2 * o + 1], alpha)) << 16);
-  uint4 *dst = (uint4 *)(aout + q * kCnnCh);
-  dst[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
-  dst[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
+// Layers 1, 2 (16 -> 16) on the matrix cores, as an implicit GEMM per tap:
+// D(out ch x 16 cells) += W_tap(out ch x in ch) X_tap(in ch x 16 cells).
+// A block owns a 64 x 4 output tile of one batch item and marches up z
+// over kCnnKC levels; the input planes k-1, k, k+1 (tile plus a one-cell
+// ring, 16 channels, 32 B per cell) sit in a three-plane LDS ring, each
+// loaded once with coalesced 16-B loads.  Wave w computes output row w as
+// four 16-cell MFMA chains interleaved tap by tap.  Lane l: row = l % 16 is
+// its cell (B operand, result) and its output channel (A operand); quad =
+// l / 16 selects input channels 4 quad .. 4 quad + 3 (A, B) and output
+// channels 4 quad .. 4 quad + 3 of the result.  The 8-B quads of a cell are
+// stored at quad ^ ((cell >> 2) & 3) so the 16 lanes reading one quad of 16
+// consecutive cells hit distinct LDS banks.
+constexpr int kCnnTX = 64, kCnnTY = 4, kCnnKC = 16;
+constexpr int kCnnPX = kCnnTX + 2, kCnnPY = kCnnTY + 2;
+constexpr int kCnnPlane = kCnnPX * kCnnPY;  // cells per LDS plane
+
+__device__ __forceinline__ int cnn_swz(int cell, int quad) { return quad ^ ((cell >> 2) & 3); }
+
+// Block geometry shared by the tiled layers: a 64 x 4 output tile of batch
+// item b over z levels [k0, k1).
+struct CnnTile {
+  int b, ox0, oy0, ix0, iy0, k0, k1;
+};
+__device__ __forceinline__ CnnTile cnn_tile(const CnnGeom &G, int tiles_x, int tiles_y,
+                                            int chunks) {
+  int blk = blockIdx.x;
+  CnnTile T;
+  const int tx = blk % tiles_x;
+  blk /= tiles_x;
+  const int ty = blk % tiles_y;
+  blk /= tiles_y;
+  const int kz = blk % chunks;
+  T.b = blk / chunks;
+  T.ox0 = tx * kCnnTX;
+  T.oy0 = ty * kCnnTY;
+  T.ix0 = G.periodic ? T.ox0 - 1 : T.ox0;
+  T.iy0 = G.periodic ? T.oy0 - 1 : T.oy0;
+  T.k0 = kz * kCnnKC;
+  T.k1 = min(G.nz, T.k0 + kCnnKC);
+  return T;
 }
 
-// Layers 1, 2 (16 -> 16) on the matrix cores.  Lane l of a wave: row = l % 16
-// is its cell of the 16-cell tile and its output channel in the A operand,
-// quad = l / 16 selects input channels 4 quad .. 4 quad + 3 (A, B) and output
-// channels 4 quad .. 4 quad + 3 of the result.
-__global__ __launch_bounds__(kBlock) void conv_mid_kernel(CnnGeom G, const uint16_t *__restrict__ ain,
-                                                          const float *__restrict__ bias,
-                                                          const uint16_t *__restrict__ w,
-                                                          float alpha, uint16_t *__restrict__ aout,
-                                                          int64_t tiles) {
-  const int lane = threadIdx.x & 63;
+// Input cell of LDS plane cell (ly, lx): wrap (periodic) or clamp (valid:
+// clamped cells feed only masked outputs).
+__device__ __forceinline__ int64_t cnn_src(const CnnGeom &G, const CnnTile &T, int kk, int ly,
+                                           int lx) {
+  kk = kk < 0 ? 0 : (kk >= G.nz ? G.nz - 1 : kk);
+  int jj = T.iy0 + ly, ii = T.ix0 + lx;
+  if (G.periodic) {
+    jj %= G.nyi;
+    jj += jj < 0 ? G.nyi : 0;
+    ii %= G.nxi;
+    ii += ii < 0 ? G.nxi : 0;
+  } else {
+    jj = jj < G.nyi ? jj : G.nyi - 1;
+    ii = ii < G.nxi ? ii : G.nxi - 1;
+  }
+  return (((int64_t)T.b * G.nz + kk) * G.nyi + jj) * G.nxi + ii;
+}
+
+__global__ __launch_bounds__(256) void conv_mid_kernel(CnnGeom G, const uint16_t *__restrict__ ain,
+                                                       const float *__restrict__ bias,
+                                                       const uint16_t *__restrict__ w,
+                                                       float alpha, uint16_t *__restrict__ aout,
+                                                       int tiles_x, int tiles_y, int chunks) {
+  __shared__ uint2 lds[3][kCnnPlane * 4];  // [slot][cell * 4 + swizzled quad]
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int row = lane & 15, quad = lane >> 4;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const CnnTile T = cnn_tile(G, tiles_x, tiles_y, chunks);
+
   bf16x4 wa[kCnnTaps];
 #pragma unroll
   for (int t = 0; t < kCnnTaps; ++t)
@@ -148,62 +174,188 @@ __global__ __launch_bounds__(kBlock) void conv_mid_kernel(CnnGeom G, const uint1
 #pragma unroll
   for (int r = 0; r < 4; ++r) bq[r] = bias[4 * quad + r];
 
-  for (int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; tile < tiles;
-       tile += nwaves) {
-    const int64_t q = tile * 16 + row;
-    const bool valid = q < G.n_out;
-    const Cell c = decode(valid ? q : G.n_out - 1, G.nz, G.nyo, G.nxo);
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+  // plane kk (mirror-clamped) into a slot: 2 x 16-B halves per cell
+  auto load_plane = [&](int kk, int slot) {
+    for (int e = threadIdx.x; e < kCnnPlane * 2; e += 256) {
+      const int cell = e >> 1, h = e & 1;
+      const int ly = cell / kCnnPX, lx = cell - ly * kCnnPX;
+      const uint4 v = *(const uint4 *)(ain + cnn_src(G, T, kk, ly, lx) * kCnnCh + 8 * h);
+      lds[slot][cell * 4 + cnn_swz(cell, 2 * h)] = make_uint2(v.x, v.y);
+      lds[slot][cell * 4 + cnn_swz(cell, 2 * h + 1)] = make_uint2(v.z, v.w);
+    }
+  };
+
+  load_plane(T.k0 - 1, (T.k0 + 2) % 3);
+  load_plane(T.k0, T.k0 % 3);
+  const int oy = T.oy0 + wv;
+  for (int k = T.k0; k < T.k1; ++k) {
+    __syncthreads();  // slot (k+1)%3 is no longer read
+    load_plane(k + 1, (k + 1) % 3);
+    __syncthreads();
+    floatx4 acc[4];
+#pragma unroll
+    for (int t4 = 0; t4 < 4; ++t4) acc[t4] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int t = 0; t < kCnnTaps; ++t) {
-      const int64_t src = src_cell(G, c, t / 9 - 1, (t / 3) % 3 - 1, t % 3 - 1);
-      const bf16x4 xb = *(const bf16x4 *)(ain + src * kCnnCh + 4 * quad);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[t], xb, acc, 0, 0, 0);
+      const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+      const uint2 *plane = lds[(k + dz + 3) % 3];
+      const int cbase = (wv + 1 + dy) * kCnnPX + row + 1 + dx;
+#pragma unroll
+      for (int t4 = 0; t4 < 4; ++t4) {
+        const int cell = cbase + 16 * t4;
+        const uint2 v = plane[cell * 4 + cnn_swz(cell, quad)];
+        bf16x4 xb;
+        xb[0] = (short)(v.x & 0xFFFFu);
+        xb[1] = (short)(v.x >> 16);
+        xb[2] = (short)(v.y & 0xFFFFu);
+        xb[3] = (short)(v.y >> 16);
+        acc[t4] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[t], xb, acc[t4], 0, 0, 0);
+      }
     }
-    if (valid) {
-      const uint32_t lo = (uint32_t)f2bf(leaky(acc[0] + bq[0], alpha)) |
-                          ((uint32_t)f2bf(leaky(acc[1] + bq[1], alpha)) << 16);
-      const uint32_t hi = (uint32_t)f2bf(leaky(acc[2] + bq[2], alpha)) |
-                          ((uint32_t)f2bf(leaky(acc[3] + bq[3], alpha)) << 16);
-      *(uint2 *)(aout + q * kCnnCh + 4 * quad) = make_uint2(lo, hi);
+    if (oy < G.nyo) {
+#pragma unroll
+      for (int t4 = 0; t4 < 4; ++t4) {
+        const int ox = T.ox0 + 16 * t4 + row;
+        if (ox < G.nxo) {
+          const uint32_t lo = (uint32_t)f2bf(leaky(acc[t4][0] + bq[0], alpha)) |
+                              ((uint32_t)f2bf(leaky(acc[t4][1] + bq[1], alpha)) << 16);
+          const uint32_t hi = (uint32_t)f2bf(leaky(acc[t4][2] + bq[2], alpha)) |
+                              ((uint32_t)f2bf(leaky(acc[t4][3] + bq[3], alpha)) << 16);
+          const int64_t q = (((int64_t)T.b * G.nz + k) * G.nyo + oy) * G.nxo + ox;
+          *(uint2 *)(aout + q * kCnnCh + 4 * quad) = make_uint2(lo, hi);
+        }
+      }
     }
   }
 }
 
-// Layer 3 (16 -> 1): one thread per output cell.  GUESS: the output becomes
-// the guess base + s_over_d * y instead of being stored.
-template <typename T, bool GUESS>
-__global__ __launch_bounds__(kBlock) void conv_out_kernel(CnnGeom G, const uint16_t *__restrict__ ain,
-                                                          const float *__restrict__ params,
-                                                          const uint16_t *__restrict__ wbf,
-                                                          float *__restrict__ y,
-                                                          const T *__restrict__ base,
-                                                          const double *__restrict__ s_over_d,
-                                                          T *__restrict__ guess) {
-  __shared__ float w[kCnnTaps * kCnnCh];
-  for (int e = threadIdx.x; e < kCnnTaps * kCnnCh; e += blockDim.x)
-    w[e] = bf2f(wbf[cnn_weight_offset(3) + e]);
-  __syncthreads();
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= G.n_out) return;
-  const Cell c = decode(q, G.nz, G.nyo, G.nxo);
-  float acc = params[cnn_bias_offset(3)];
-#pragma unroll 3
-  for (int t = 0; t < kCnnTaps; ++t) {
-    const int64_t src = src_cell(G, c, t / 9 - 1, (t / 3) % 3 - 1, t % 3 - 1);
-    const uint4 *p = (const uint4 *)(ain + src * kCnnCh);
-    const uint4 v0 = p[0], v1 = p[1];
-    const uint32_t u[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+// Layer 0 (1 -> 16) on the matrix cores: D(out ch x 16 cells) = W(out ch x
+// 32 taps, 27 used) X(32 taps x 16 cells), the im2col operand gathered from
+// a three-plane LDS ring of bfloat16 inputs; two MFMAs per 16 cells.
+__global__ __launch_bounds__(256) void conv_in_kernel(CnnGeom G, const uint16_t *__restrict__ ain,
+                                                      const float *__restrict__ params,
+                                                      const uint16_t *__restrict__ wbf,
+                                                      float alpha, uint16_t *__restrict__ aout,
+                                                      int tiles_x, int tiles_y, int chunks) {
+  __shared__ uint16_t lds[3][kCnnPlane];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int row = lane & 15, quad = lane >> 4;
+  const CnnTile T = cnn_tile(G, tiles_x, tiles_y, chunks);
+  // A operands: W0[tap][o = row][0] for taps 4 quad + r (+16 for the second)
+  bf16x4 wa[2];
 #pragma unroll
-    for (int h = 0; h < 8; ++h) {
-      acc += w[t * kCnnCh + 2 * h] * __uint_as_float(u[h] << 16);
-      acc += w[t * kCnnCh + 2 * h + 1] * __uint_as_float(u[h] & 0xFFFF0000u);
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int tap = 16 * m + 4 * quad + r;
+      wa[m][r] = tap < kCnnTaps ? (short)wbf[tap * kCnnCh + row] : (short)0;
+    }
+  float bq[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) bq[r] = params[cnn_bias_offset(0) + 4 * quad + r];
+  auto load_plane = [&](int kk, int slot) {
+    for (int e = threadIdx.x; e < kCnnPlane; e += 256) {
+      const int ly = e / kCnnPX, lx = e - ly * kCnnPX;
+      lds[slot][e] = ain[cnn_src(G, T, kk, ly, lx)];
+    }
+  };
+  load_plane(T.k0 - 1, (T.k0 + 2) % 3);
+  load_plane(T.k0, T.k0 % 3);
+  const int oy = T.oy0 + wv;
+  for (int k = T.k0; k < T.k1; ++k) {
+    __syncthreads();
+    load_plane(k + 1, (k + 1) % 3);
+    __syncthreads();
+#pragma unroll
+    for (int t4 = 0; t4 < 4; ++t4) {
+      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        bf16x4 xb;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int tap = 16 * m + 4 * quad + r;
+          short v = 0;
+          if (tap < kCnnTaps) {
+            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            v = (short)lds[(k + dz + 3) % 3][(wv + 1 + dy) * kCnnPX + 16 * t4 + row + 1 + dx];
+          }
+          xb[r] = v;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[m], xb, acc, 0, 0, 0);
+      }
+      const int ox = T.ox0 + 16 * t4 + row;
+      if (oy < G.nyo && ox < G.nxo) {
+        const uint32_t lo = (uint32_t)f2bf(leaky(acc[0] + bq[0], alpha)) |
+                            ((uint32_t)f2bf(leaky(acc[1] + bq[1], alpha)) << 16);
+        const uint32_t hi = (uint32_t)f2bf(leaky(acc[2] + bq[2], alpha)) |
+                            ((uint32_t)f2bf(leaky(acc[3] + bq[3], alpha)) << 16);
+        const int64_t q = (((int64_t)T.b * G.nz + k) * G.nyo + oy) * G.nxo + ox;
+        *(uint2 *)(aout + q * kCnnCh + 4 * quad) = make_uint2(lo, hi);
+      }
     }
   }
-  if (GUESS)
-    guess[q] = (T)((double)base[q] + *s_over_d * (double)acc);
-  else
-    y[q] = acc;
+}
+
+// Layer 3 (16 -> 1): one thread per output cell of the 64 x 4 tile, inputs
+// from the same swizzled three-plane LDS ring as the 16 -> 16 layers.
+// GUESS: the output becomes the guess base + s_over_d * y.
+template <typename T, bool GUESS>
+__global__ __launch_bounds__(256) void conv_out_kernel(CnnGeom G, const uint16_t *__restrict__ ain,
+                                                       const float *__restrict__ params,
+                                                       const uint16_t *__restrict__ wbf,
+                                                       float *__restrict__ y,
+                                                       const T *__restrict__ base,
+                                                       const double *__restrict__ s_over_d,
+                                                       T *__restrict__ guess, int tiles_x,
+                                                       int tiles_y, int chunks) {
+  __shared__ uint2 lds[3][kCnnPlane * 4];
+  __shared__ float w[kCnnTaps * kCnnCh];
+  for (int e = threadIdx.x; e < kCnnTaps * kCnnCh; e += 256)
+    w[e] = bf2f(wbf[cnn_weight_offset(3) + e]);
+  const CnnTile Tl = cnn_tile(G, tiles_x, tiles_y, chunks);
+  const float b3 = params[cnn_bias_offset(3)];
+  auto load_plane = [&](int kk, int slot) {
+    for (int e = threadIdx.x; e < kCnnPlane * 2; e += 256) {
+      const int cell = e >> 1, h = e & 1;
+      const int ly = cell / kCnnPX, lx = cell - ly * kCnnPX;
+      const uint4 v = *(const uint4 *)(ain + cnn_src(G, Tl, kk, ly, lx) * kCnnCh + 8 * h);
+      lds[slot][cell * 4 + cnn_swz(cell, 2 * h)] = make_uint2(v.x, v.y);
+      lds[slot][cell * 4 + cnn_swz(cell, 2 * h + 1)] = make_uint2(v.z, v.w);
+    }
+  };
+  load_plane(Tl.k0 - 1, (Tl.k0 + 2) % 3);
+  load_plane(Tl.k0, Tl.k0 % 3);
+  const int lx0 = threadIdx.x & 63, ly0 = threadIdx.x >> 6;
+  const int oy = Tl.oy0 + ly0, ox = Tl.ox0 + lx0;
+  for (int k = Tl.k0; k < Tl.k1; ++k) {
+    __syncthreads();
+    load_plane(k + 1, (k + 1) % 3);
+    __syncthreads();
+    float acc = b3;
+#pragma unroll 3
+    for (int t = 0; t < kCnnTaps; ++t) {
+      const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+      const uint2 *plane = lds[(k + dz + 3) % 3];
+      const int cell = (ly0 + 1 + dy) * kCnnPX + lx0 + 1 + dx;
+#pragma unroll
+      for (int qd = 0; qd < 4; ++qd) {
+        const uint2 v = plane[cell * 4 + cnn_swz(cell, qd)];
+        const float *wr = w + t * kCnnCh + 4 * qd;
+        acc += wr[0] * __uint_as_float(v.x << 16);
+        acc += wr[1] * __uint_as_float(v.x & 0xFFFF0000u);
+        acc += wr[2] * __uint_as_float(v.y << 16);
+        acc += wr[3] * __uint_as_float(v.y & 0xFFFF0000u);
+      }
+    }
+    if (oy < G.nyo && ox < G.nxo) {
+      const int64_t q = (((int64_t)Tl.b * G.nz + k) * G.nyo + oy) * G.nxo + ox;
+      if (GUESS)
+        guess[q] = (T)((double)base[q] + *s_over_d * (double)acc);
+      else
+        y[q] = acc;
+    }
+  }
 }
 
 // ---------------------------------------------------------------- loss
@@ -514,19 +666,20 @@ void launch_cnn_round(int64_t n, const float *x, const double *scale, uint16_t *
 
 void launch_cnn_conv(int layer, const CnnGeom &G, const uint16_t *ain, const float *params,
                      const uint16_t *wbf, float alpha, uint16_t *aout, float *yout, hipStream_t s) {
+  const int tiles_x = (G.nxo + kCnnTX - 1) / kCnnTX, tiles_y = (G.nyo + kCnnTY - 1) / kCnnTY;
+  const int chunks = (G.nz + kCnnKC - 1) / kCnnKC;
+  const unsigned blocks = (unsigned)((int64_t)G.batch * tiles_x * tiles_y * chunks);
   if (layer == 0) {
-    conv_in_kernel<<<blocks_for(G.n_out), kBlock, 0, s>>>(G, ain, params, wbf, alpha, aout);
+    conv_in_kernel<<<blocks, 256, 0, s>>>(G, ain, params, wbf, alpha, aout, tiles_x, tiles_y,
+                                          chunks);
   } else if (layer < kCnnLayers - 1) {
-    const int64_t tiles = (G.n_out + 15) / 16;
-    const int64_t waves_wanted = (tiles + 7) / 8;  // about 8 tiles per wave
-    int64_t blocks = (waves_wanted + 3) / 4;
-    blocks = blocks < 1 ? 1 : (blocks > 8192 ? 8192 : blocks);
-    conv_mid_kernel<<<(unsigned)blocks, kBlock, 0, s>>>(G, ain, params + cnn_bias_offset(layer),
-                                                        wbf + cnn_weight_offset(layer), alpha,
-                                                        aout, tiles);
+    conv_mid_kernel<<<blocks, 256, 0, s>>>(G, ain, params + cnn_bias_offset(layer),
+                                           wbf + cnn_weight_offset(layer), alpha, aout, tiles_x,
+                                           tiles_y, chunks);
   } else {
-    conv_out_kernel<float, false><<<blocks_for(G.n_out), kBlock, 0, s>>>(
-        G, ain, params, wbf, yout, nullptr, nullptr, nullptr);
+    conv_out_kernel<float, false><<<blocks, 256, 0, s>>>(G, ain, params, wbf, yout, nullptr,
+                                                         nullptr, nullptr, tiles_x, tiles_y,
+                                                         chunks);
   }
 }
 
@@ -534,8 +687,11 @@ template <typename T>
 void launch_cnn_guess(const CnnGeom &G, const uint16_t *ain, const float *params,
                       const uint16_t *wbf, const T *base, const double *s_over_d, T *guess,
                       hipStream_t s) {
-  conv_out_kernel<T, true><<<blocks_for(G.n_out), kBlock, 0, s>>>(G, ain, params, wbf, nullptr,
-                                                                  base, s_over_d, guess);
+  const int tiles_x = (G.nxo + kCnnTX - 1) / kCnnTX, tiles_y = (G.nyo + kCnnTY - 1) / kCnnTY;
+  const int chunks = (G.nz + kCnnKC - 1) / kCnnKC;
+  const unsigned blocks = (unsigned)((int64_t)G.batch * tiles_x * tiles_y * chunks);
+  conv_out_kernel<T, true><<<blocks, 256, 0, s>>>(G, ain, params, wbf, nullptr, base, s_over_d,
+                                                  guess, tiles_x, tiles_y, chunks);
 }
 
 void launch_cnn_loss(int batch, int nz, int ny, int nx, double wx, double wy, double wz,

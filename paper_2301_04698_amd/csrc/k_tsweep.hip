@@ -11,10 +11,14 @@
 // written as (N - rhs)/D - phi cancels catastrophically; its rounding error
 // is the same from sweep to sweep and accumulates in the slow modes.
 //
-// One sweep: each thread owns one column of a 64 x 4 thread tile and
+// One sweep: each thread owns one column of a 64 x TY thread tile and
 // marches up z with the vertical neighbours in registers; x/y neighbours
 // come through the L1/L2 caches.  16 bytes per cell (Chebyshev: phi, prev,
-// rhs in, phi' out).
+// rhs in, phi' out).  When the four arrays fit the 256 MB Infinity Cache
+// they stay there from sweep to sweep (64 x 4 tiles, ordinary accesses);
+// beyond it the arrays read once per sweep (prev, rhs) and the output are
+// streamed with non-temporal accesses so the caches keep the iterate's
+// neighbour rows, and taller 64 x 16 tiles halve the y-halo re-reads.
 //
 // Two sweeps: a 64 x TY thread tile covers a 62 x (TY-2) core plus a
 // one-cell ring.  Every thread computes the first sweep for its own column
@@ -91,10 +95,16 @@ __device__ __forceinline__ TileIdx tile_of(int tile, int tiles_x, int tiles_y, i
 
 // ---------------------------------------------------------------- 1 sweep
 
-constexpr int kTY1 = 4;
+constexpr int kTY1 = 4;       // cache-resident arrays
+constexpr int kTY1Big = 16;   // streamed arrays
 
-template <typename T, bool CHEB, bool CHECK>
-__global__ __launch_bounds__(64 * kTY1) void sweep1_kernel(SweepArgs<T> a) {
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T *p, bool nt) {
+  return nt ? __builtin_nontemporal_load(p) : *p;
+}
+
+template <typename T, int TY, bool CHEB, bool CHECK, bool NT>
+__global__ __launch_bounds__(64 * TY) void sweep1_kernel(SweepArgs<T> a) {
   if (a.ctl->done) return;
   const Grid &g = a.g;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -102,7 +112,7 @@ __global__ __launch_bounds__(64 * kTY1) void sweep1_kernel(SweepArgs<T> a) {
   if (tile < a.ntiles) {
     const TileIdx t = tile_of(tile, a.tiles_x, a.tiles_y, a.kc, g.nz);
     const int i = t.tx * 64 + (int)(threadIdx.x & 63);
-    const int j = t.ty * kTY1 + (int)(threadIdx.x >> 6);
+    const int j = t.ty * TY + (int)(threadIdx.x >> 6);
     if (i < g.nx && j < g.ny) {
       const int ip = i + 1 == g.nx ? 0 : i + 1, im = i == 0 ? g.nx - 1 : i - 1;
       const int jp = j + 1 == g.ny ? 0 : j + 1, jm = j == 0 ? g.ny - 1 : j - 1;
@@ -118,10 +128,15 @@ __global__ __launch_bounds__(64 * kTY1) void sweep1_kernel(SweepArgs<T> a) {
         const double hx = (double)a.cur[q + oxp] + (double)a.cur[q + oxm];
         const double hy = (double)a.cur[q + oyp] + (double)a.cur[q + oym];
         const double hz = (double)above + (double)below;
-        const double res = point_residual(a.k, (double)c, hx, hy, hz, (double)a.rhs[q]);
+        const double res =
+            point_residual(a.k, (double)c, hx, hy, hz, (double)ld_stream(&a.rhs[q], NT));
         if (CHECK) acc += res * res;
-        const double pv = cheb ? (double)a.prev[q] : 0.0;
-        a.out_last[q] = (T)point_update(a.k, (double)c, res, cheb, pv, a.wc0);
+        const double pv = cheb ? (double)ld_stream(&a.prev[q], NT) : 0.0;
+        const T out = (T)point_update(a.k, (double)c, res, cheb, pv, a.wc0);
+        if (NT)
+          __builtin_nontemporal_store(out, &a.out_last[q]);
+        else
+          a.out_last[q] = out;
         below = c;
         c = above;
       }
@@ -252,13 +267,21 @@ constexpr int kTY2 = 8;  // two-sweep tile: 512 threads, core 62 x 6
 
 struct Shape {
   int kc, tiles_x, tiles_y, tiles_z, ntiles, blocks;
+  bool stream;  // one-sweep kernel: streamed arrays, 64 x kTY1Big tiles
 };
 
-Shape shape_of(const Grid &g, int S) {
+// The four arrays of a sweep exceed what the Infinity Cache keeps.
+bool streamed(const Grid &g, bool is_double) {
+  return 4.0 * (double)g.n * (is_double ? 8.0 : 4.0) > 192.0e6;
+}
+
+Shape shape_of(const Grid &g, int S, bool is_double) {
   Shape sh;
+  sh.stream = S == 1 && streamed(g, is_double);
   if (S == 1) {
+    const int ty = sh.stream ? kTY1Big : kTY1;
     sh.tiles_x = (g.nx + 63) / 64;
-    sh.tiles_y = (g.ny + kTY1 - 1) / kTY1;
+    sh.tiles_y = (g.ny + ty - 1) / ty;
   } else {
     sh.tiles_x = (g.nx + 61) / 62;
     sh.tiles_y = (g.ny + kTY2 - 3) / (kTY2 - 2);
@@ -284,8 +307,7 @@ Shape shape_of(const Grid &g, int S) {
 }  // namespace
 
 int tsweep_blocks(const Grid &g, int S, bool is_double) {
-  (void)is_double;
-  return shape_of(g, S).blocks;
+  return shape_of(g, S, is_double).blocks;
 }
 
 template <typename T>
@@ -293,7 +315,7 @@ void launch_tsweep(const Grid &g, int S, bool chebyshev, bool check, bool first,
                    double omega_jacobi, const double *omega_cheb, const T *cur, const T *prev,
                    T *out_last, T *out_prev, const T *rhs, const SolveCtl *ctl,
                    double *partials, hipStream_t s) {
-  const Shape sh = shape_of(g, S);
+  const Shape sh = shape_of(g, S, sizeof(T) == 8);
   SweepArgs<T> a;
   a.g = g;
   a.k.ix2 = 1.0 / (g.dx * g.dx);
@@ -318,18 +340,22 @@ void launch_tsweep(const Grid &g, int S, bool chebyshev, bool check, bool first,
   a.ctl = ctl;
   a.partials = partials;
   const dim3 grid(sh.blocks);
-#define LES_PICK(KERNEL, BLOCK)                                           \
-  do {                                                                    \
-    if (chebyshev) {                                                      \
-      if (check) KERNEL<T, true, true><<<grid, BLOCK, 0, s>>>(a);         \
-      else KERNEL<T, true, false><<<grid, BLOCK, 0, s>>>(a);              \
-    } else {                                                              \
-      if (check) KERNEL<T, false, true><<<grid, BLOCK, 0, s>>>(a);        \
-      else KERNEL<T, false, false><<<grid, BLOCK, 0, s>>>(a);             \
-    }                                                                     \
+#define LES_PICK(TY, NT)                                                              \
+  do {                                                                                \
+    const dim3 block(64 * TY);                                                        \
+    if (chebyshev) {                                                                  \
+      if (check) sweep1_kernel<T, TY, true, true, NT><<<grid, block, 0, s>>>(a);      \
+      else sweep1_kernel<T, TY, true, false, NT><<<grid, block, 0, s>>>(a);           \
+    } else {                                                                          \
+      if (check) sweep1_kernel<T, TY, false, true, NT><<<grid, block, 0, s>>>(a);     \
+      else sweep1_kernel<T, TY, false, false, NT><<<grid, block, 0, s>>>(a);          \
+    }                                                                                 \
   } while (0)
   if (S == 1) {
-    LES_PICK(sweep1_kernel, dim3(64 * kTY1));
+    if (sh.stream)
+      LES_PICK(kTY1Big, true);
+    else
+      LES_PICK(kTY1, false);
   } else {
     const dim3 block(64 * kTY2);
     if (chebyshev) {

@@ -72,6 +72,21 @@ def test_full_size_sweeps_match_oracle(les, oracle_lib):
     assert rel(got, ref) <= 1e-5, rel(got, ref)
 
 
+def test_full_size_fp64_streamed_sweeps_match_oracle(les, oracle_lib):
+    """FP64 at 256 x 256 x 128: the four sweep arrays (268 MB) exceed the
+    Infinity Cache, so the streamed sweep (non-temporal accesses, 64 x 16
+    tiles) runs; FP64 bar against the oracle."""
+    import torch
+    p = c2(precision="fp64")
+    shape = (p["nz"], p["ny"], p["nx"])
+    rhs = li.random_field(shape, seed=26)
+    ref, _ = oracle_lib.poisson(p, rhs, fixed_sweeps=30)
+    sim = les.LES(p)
+    phi, st, _ = sim.poisson_solve(torch.from_numpy(rhs), fixed_sweeps=30)
+    got = phi.cpu().numpy()
+    assert rel(got, ref) <= 1e-11, rel(got, ref)
+
+
 def test_full_size_solves_meet_tolerance(les, oracle_lib):
     """Recompute ||rhs - L phi|| in FP64 on the host for every solve of the
     last of three steps (plain guess) and compare with tol ||rhs||."""

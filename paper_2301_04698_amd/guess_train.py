@@ -77,7 +77,7 @@ def collect(p, seeds, windows, window_len, device="cuda"):
     return X, T
 
 
-def train(X, T, p, iters=2000, batch=16, crop=32, lr=2e-3, seed=0, alpha=DEFAULT_ALPHA,
+def train(X, T, p, iters=4000, batch=16, crop=32, lr=2e-3, seed=0, alpha=DEFAULT_ALPHA,
           log_every=200, init=None):
     """Adam on random crops with a cosine learning-rate decay.  The loss is
     evaluated on crop x crop interior cells (output crop + 2).  Returns
@@ -162,7 +162,7 @@ def main():
     ap.add_argument("--seeds", default="1000,1001,1002")
     ap.add_argument("--windows", default="40,150,300")
     ap.add_argument("--window-len", type=int, default=3)
-    ap.add_argument("--iters", type=int, default=2000)
+    ap.add_argument("--iters", type=int, default=4000)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--crop", type=int, default=32)
     ap.add_argument("--lr", type=float, default=2e-3)

@@ -140,3 +140,17 @@ def test_full_size_learned_guess_on_crops(les, oracle_lib):
         got = corr[:, (j0 + np.arange(16)) % p["ny"]][:, :, (i0 + np.arange(16)) % p["nx"]]
         e = rel(got, s / d * out[0])
         assert e <= 5e-4, ((j0, i0), e)
+
+
+def test_largest_domain_sweeps_match_oracle(les, oracle_lib):
+    """1024 x 1024 x 256 (268 M cells, the largest single-GPU workload): ten
+    streamed Chebyshev sweeps against the oracle's, FP32 bar."""
+    import torch
+    p = li.workload("C5")
+    shape = (p["nz"], p["ny"], p["nx"])
+    rhs = li.random_field(shape, seed=27).astype(np.float32).astype(np.float64)
+    ref, _ = oracle_lib.poisson(p, rhs, fixed_sweeps=10)
+    sim = les.LES(p)
+    phi, st, _ = sim.poisson_solve(torch.from_numpy(rhs), fixed_sweeps=10)
+    got = phi.double().cpu().numpy()
+    assert rel(got, ref) <= 1e-5, rel(got, ref)

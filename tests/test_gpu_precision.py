@@ -62,20 +62,40 @@ def test_companion_64cubed_fp32_per_step(les, oracle_lib):
 
 def test_full_size_fp32_against_fp64_gpu(les):
     """512 x 512 x 256, three steps with 300 sweeps per solve on both paths
-    (both beyond the Infinity Cache: the streamed sweep kernel)."""
+    (both beyond the Infinity Cache: the streamed sweep kernel).  Each step
+    starts both paths from the FP64 path's state (rounded to FP32 for the
+    FP32 path), so the error is that of one step.  The velocity starts
+    perturbed: from rest, w after a few unconverged adjustment sweeps is
+    the small remainder of cancelling buoyancy and pressure-gradient terms,
+    and its relative error measures that cancellation, not the arithmetic.
+
+    Bar: 1e-5 per field per step, except w during this adjustment phase:
+    phi is stored in FP32 and its large smooth hydrostatic part gives its
+    vertical gradient an error of about ulp(phi) H / (2 dz) ~ 8e-6 of that
+    gradient here (H = 1280 m, dz = 5 m), which w, the small difference of
+    the predicted velocity and that gradient, inherits amplified; 2e-5."""
     p64 = li.workload("C3", precision="fp64")
     p32 = li.workload("C3")
-    st = f32(li.initial_state(p32))
-    replay = [300] * (3 * p32["n_subiter"])
-    s64 = les.LES(p64, st)
-    s64.step(3, replay=replay)
-    g64 = s64.state_numpy()
-    s64.close()
-    s32 = les.LES(p32, st)
-    s32.step(3, replay=replay)
-    g32 = s32.state_numpy()
-    errs = {k: rel(g32[k], g64[k]) for k in FIELDS}
-    print("512x512x256 after 3 steps, FP32 vs FP64 GPU: "
-          + " ".join(f"{k} {e:.2e}" for k, e in errs.items()))
-    for k, e in errs.items():
-        assert e <= 3e-5, (k, e)
+    st = li.initial_state(p32)
+    rng = np.random.default_rng(32)
+    for k in ("u", "v", "w"):
+        st[k] = st[k] + 0.2 * rng.standard_normal(st[k].shape)
+    replay = [300] * p32["n_subiter"]
+    worst = {k: 0.0 for k in FIELDS}
+    for n in range(3):
+        s64 = les.LES(p64, st)
+        s64.step(1, replay=replay)
+        g64 = s64.state_numpy()
+        s64.close()
+        s32 = les.LES(p32, f32(st))
+        s32.step(1, replay=replay)
+        g32 = s32.state_numpy()
+        s32.close()
+        errs = {k: rel(g32[k], g64[k]) for k in FIELDS}
+        print(f"512x512x256 step {n}, FP32 vs FP64 GPU: "
+              + " ".join(f"{k} {e:.2e}" for k, e in errs.items()))
+        for k, e in errs.items():
+            worst[k] = max(worst[k], e)
+        st = g64
+    for k, e in worst.items():
+        assert e <= (2e-5 if k == "w" else 1e-5), (k, e)

@@ -49,16 +49,16 @@ enum {
 enum { LES_FP64 = 0, LES_FP32 = 1 };          /* storage / stencil precision */
 enum { LES_JACOBI = 0, LES_CHEBYSHEV = 1 };   /* Poisson sweep weighting */
 /* Initial guess of the pressure-correction solves:
- *   LES_GUESS_ZERO         phi_0 = 0 for every solve
- *   LES_GUESS_EXTRAPOLATE  first solve of a step: phi_0 = alpha0 (p_{n-1} -
- *                          p_{n-2}), the last step's pressure change; later
+ *   LES_GUESS_ZERO         phi_0 = 0 for every solve (the plain method)
+ *   LES_GUESS_EXTRAPOLATE  first solve of a step: phi_0 = alpha0 (p^n -
+ *                          p^{n-1}), the last step's pressure change; later
  *                          solves start from 0
  *   LES_GUESS_PREVIOUS     each sub-iteration's solve starts from the
  *                          previous step's solution of the same
  *                          sub-iteration (zero on the first step)
- *   LES_GUESS_LEARNED      first solve of a step: the 3D CNN of les_cnn.h
- *                          (weights bound with les_bind_cnn); later solves
- *                          start from 0
+ *   LES_GUESS_LEARNED      as LES_GUESS_PREVIOUS, plus the correction of
+ *                          the guess network of les_cnn.h (parameters
+ *                          bound with les_bind_cnn before the second step)
  * The solve always runs to the same residual tolerance: a guess only
  * changes the number of sweeps, never the acceptance test. */
 enum { LES_GUESS_ZERO = 0, LES_GUESS_EXTRAPOLATE = 1, LES_GUESS_PREVIOUS = 2,

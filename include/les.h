@@ -113,6 +113,11 @@ typedef struct les_solve_stats {
   double rhs_norm;    /* ||rhs||_2 after mean removal (FP64) */
   double res_norm;    /* ||rhs - L phi||_2 of the returned iterate (FP64) */
   double seconds;     /* device time of the solve (HIP events) */
+  int32_t guess;      /* les_step: 0 started from zero, 1 from its guess,
+                         2 its guess was rejected (residual not below the
+                         zero start's) and it started from zero;
+                         les_poisson_solve: opts->use_guess */
+  int32_t reserved;
 } les_solve_stats;
 
 typedef struct les_poisson_opts {

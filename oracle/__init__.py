@@ -41,7 +41,8 @@ class OCfg(C.Structure):
 
 class OSolve(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("status", C.c_int32),
-                ("rhs_norm", C.c_double), ("res_norm", C.c_double)]
+                ("rhs_norm", C.c_double), ("res_norm", C.c_double),
+                ("guess", C.c_int32), ("reserved", C.c_int32)]
 
 
 class ODebug(C.Structure):
@@ -261,8 +262,8 @@ def step(p, state, nsteps=1, replay=None, debug=False):
             setattr(dbg, k, dbg_arrays[k].ctypes.data)
     rc = lib().oracle_step(C.byref(c), *[_ptr(a) for a in arrs], int(nsteps), rp, rec,
                            C.byref(dbg) if dbg is not None else None)
-    recs = [dict(sweeps=r.sweeps, status=r.status, rhs_norm=r.rhs_norm, res_norm=r.res_norm)
-            for r in rec]
+    recs = [dict(sweeps=r.sweeps, status=r.status, rhs_norm=r.rhs_norm, res_norm=r.res_norm,
+                 guess=r.guess) for r in rec]
     if rc != 0:
         raise RuntimeError(f"oracle step failed with code {rc}; solves: {recs}")
     return recs, dbg_arrays

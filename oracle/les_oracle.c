@@ -633,7 +633,14 @@ int oracle_poisson(const ocfg *c, const double *rhs_in, double *phi, int32_t fix
   }
   double mp = fsum(c, phi) / (double)n;
   for (size_t q = 0; q < n; ++q) phi[q] -= mp;
-  if (st) { st->sweeps = m; st->status = status; st->rhs_norm = rn; st->res_norm = rr; }
+  if (st) {
+    st->sweeps = m;
+    st->status = status;
+    st->rhs_norm = rn;
+    st->res_norm = rr;
+    st->guess = 0;
+    st->reserved = 0;
+  }
   free(rhs); free(tmp); free(prev);
   return status < 0 ? status : 0;
 }
@@ -791,20 +798,40 @@ int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, dou
       for (int k = 0; k < c->nz; ++k)
         for (size_t q = (size_t)k * c->nx * c->ny; q < (size_t)(k + 1) * c->nx * c->ny; ++q)
           S.rhs[q] = P.alpha0[k] / c->dt * S.rhs[q] - S.tmp[q];
-      double mr = fsum(c, S.rhs) / (double)n;
-      for (size_t q = 0; q < n; ++q) S.rhs[q] -= mr;
       memset(S.phi, 0, n * sizeof(double));
+      int guessed = 0;
       if (c->guess == 1 && it == 0) {
         for (int k = 0; k < c->nz; ++k)
           for (size_t q = (size_t)k * c->nx * c->ny; q < (size_t)(k + 1) * c->nx * c->ny; ++q)
             S.phi[q] = P.alpha0[k] * (p[q] - hist[q]);
         memcpy(hist, p, n * sizeof(double));
+        guessed = 1;
       } else if (c->guess == 2 && step > 0) {
         memcpy(S.phi, hist + (size_t)it * n, n * sizeof(double));
+        guessed = 1;
       }
+      if (guessed) {
+        /* keep the guess only if it starts closer than zero:
+           ||rhs - L phi_0|| < ||rhs|| (rhs before its mean is removed) */
+        oracle_laplacian(c, S.phi, S.tmp);
+        double rr = 0.0, bb = 0.0;
+        for (size_t q = 0; q < n; ++q) {
+          double r = S.rhs[q] - S.tmp[q];
+          rr += r * r;
+          bb += S.rhs[q] * S.rhs[q];
+        }
+        if (!(rr < bb)) {
+          memset(S.phi, 0, n * sizeof(double));
+          guessed = 2;
+        }
+      }
+      double mr = fsum(c, S.rhs) / (double)n;
+      for (size_t q = 0; q < n; ++q) S.rhs[q] -= mr;
       osolve st;
       int fixed = replay ? replay[solve] : 0;
       rc = oracle_poisson(c, S.rhs, S.phi, fixed, &st);
+      st.guess = guessed;
+      st.reserved = 0;
       if (rec) rec[solve] = st;
       ++solve;
       if (rc) break;

@@ -39,6 +39,8 @@ typedef struct osolve {        /* one Poisson solve */
   int32_t status;              /* 0 converged, 1 not converged, -3 non-finite */
   double rhs_norm;             /* ||rhs||_2 after mean removal */
   double res_norm;             /* ||rhs - L phi||_2 of the returned iterate */
+  int32_t guess;               /* oracle_step: 0 zero start, 1 guess kept, 2 rejected */
+  int32_t reserved;
 } osolve;
 
 /* Reference state (Sec. 2.1): p0, T0, rho0, alpha0 at cell centres. */
@@ -93,6 +95,9 @@ typedef struct odebug {
  *      the last step (zero on the first step of the call); later solves zero;
  *   2  each sub-iteration: the zero-mean solution of the same sub-iteration
  *      of the last step (zero on the first step of the call).
+ * A guess is kept only if ||rhs - L phi_0||_2 < ||rhs||_2 (the residual of
+ * the zero start), evaluated before the rhs mean is removed; otherwise the
+ * solve starts from zero.
  * The guess changes the sweep count only: the stopping test is relative to
  * ||rhs||, whatever the starting iterate. */
 int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, double *qt,

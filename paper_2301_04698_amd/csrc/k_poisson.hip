@@ -181,6 +181,65 @@ __global__ __launch_bounds__(1024) void final_kernel(const double *__restrict__ 
   }
 }
 
+// Starting-iterate test: FP64 partial sums of (rhs - L phi0)^2 (partials[b])
+// and of rhs^2 (partials[gridDim.x + b]), L the compact Laplacian with
+// periodic x, y and mirror z.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void guess_residual_kernel(Grid g, double ix2, double iy2,
+                                                                double iz2,
+                                                                const T *__restrict__ rhs,
+                                                                const T *__restrict__ phi0,
+                                                                double *__restrict__ partials) {
+  double rr = 0.0, bb = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < g.n;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(q / g.nxy);
+    const int64_t r2 = q - g.nxy * k;
+    const int j = (int)(r2 / g.nx);
+    const int i = (int)(r2 - (int64_t)g.nx * j);
+    const double c = phi0[q];
+    const double lap =
+        ((double)gload(phi0, g, i + 1, j, k, T(1)) + (double)gload(phi0, g, i - 1, j, k, T(1)) -
+         2.0 * c) * ix2 +
+        ((double)gload(phi0, g, i, j + 1, k, T(1)) + (double)gload(phi0, g, i, j - 1, k, T(1)) -
+         2.0 * c) * iy2 +
+        ((double)gload(phi0, g, i, j, k + 1, T(1)) + (double)gload(phi0, g, i, j, k - 1, T(1)) -
+         2.0 * c) * iz2;
+    const double b = rhs[q];
+    rr += (b - lap) * (b - lap);
+    bb += b * b;
+  }
+  const double sr = block_sum(rr);
+  const double sb = block_sum(bb);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = sr;
+    partials[gridDim.x + blockIdx.x] = sb;
+  }
+}
+
+// ctl->guess_kept = 1 when the starting iterate's residual is below the
+// zero start's (sum r^2 < sum rhs^2), else 0.
+__global__ __launch_bounds__(1024) void guess_gate_kernel(const double *__restrict__ partials,
+                                                          int np, SolveCtl *ctl) {
+  double a = 0.0, b = 0.0;
+  for (int q = threadIdx.x; q < np; q += blockDim.x) {
+    a += partials[q];
+    b += partials[np + q];
+  }
+  a = block_sum(a);
+  b = block_sum(b);
+  if (threadIdx.x == 0) ctl->guess_kept = a < b ? 1 : 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void guess_clear_kernel(int64_t n,
+                                                             const SolveCtl *__restrict__ ctl,
+                                                             T *__restrict__ phi0) {
+  if (ctl->guess_kept) return;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) phi0[q] = T(0);
+}
+
 __global__ void ctl_reset_kernel(SolveCtl *ctl, int max_sweeps, int fixed) {
   if (threadIdx.x != 0) return;
   ctl->rhs_mean = 0.0;
@@ -229,6 +288,15 @@ void launch_extrapolate(const Grid &g, const Profiles<T> &P, const T *p, const T
 }
 
 template <typename T>
+void launch_guess_gate(const Grid &g, const T *rhs, T *phi0, double *partials, SolveCtl *ctl,
+                       hipStream_t s) {
+  guess_residual_kernel<T><<<kReduceBlocks, kBlock, 0, s>>>(
+      g, 1.0 / (g.dx * g.dx), 1.0 / (g.dy * g.dy), 1.0 / (g.dz * g.dz), rhs, phi0, partials);
+  guess_gate_kernel<<<1, 1024, 0, s>>>(partials, kReduceBlocks, ctl);
+  guess_clear_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g.n, ctl, phi0);
+}
+
+template <typename T>
 void launch_block_sum(const T *a, int64_t n, int mode, double *partials, hipStream_t s) {
   block_sum_kernel<T><<<kReduceBlocks, kBlock, 0, s>>>(a, n, mode, partials);
 }
@@ -252,6 +320,8 @@ void launch_ctl_reset(SolveCtl *ctl, int max_sweeps, int fixed, hipStream_t s) {
                                   const SolveCtl *, T *, T *, T *, T *, hipStream_t);            \
   template void launch_sub_mean<T>(const Grid &, const T *, const SolveCtl *, T *, hipStream_t); \
   template void launch_block_sum<T>(const T *, int64_t, int, double *, hipStream_t);            \
+  template void launch_guess_gate<T>(const Grid &, const T *, T *, double *, SolveCtl *,         \
+                                     hipStream_t);                                               \
   template void launch_extrapolate<T>(const Grid &, const Profiles<T> &, const T *, const T *,   \
                                       T *, hipStream_t);
 LES_INST(float)

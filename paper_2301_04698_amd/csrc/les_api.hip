@@ -284,7 +284,7 @@ struct SweepTiming {
 template <typename T>
 int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
           les_solve_stats *st, T **result, SweepTiming *timing = nullptr,
-          bool start_recorded = false) {
+          bool start_recorded = false, bool gated = false) {
   const les_config &c = h->cfg;
   const Grid &g = h->grid;
   hipStream_t s = h->stream;
@@ -445,6 +445,8 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
   st->rhs_norm = std::sqrt(r.rhs_norm2);
   st->res_norm = std::sqrt(r.res_norm2);
   st->seconds = ms * 1e-3;
+  st->guess = !use_guess ? 0 : (gated && !r.guess_kept ? 2 : 1);
+  st->reserved = 0;
   *result = buf[res_buf];
   if (r.done == 2) return fail(LES_ERR_NONFINITE, "non-finite Poisson residual");
   return LES_OK;
@@ -531,6 +533,12 @@ int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step
         HIP_TRY(hipMemcpyAsync(V.f[F_PM2], V.p, bytes, hipMemcpyDeviceToDevice, s));
         LAUNCH_TRY();
       }
+      // a guess worse than the zero start (a step that changed the solution
+      // a lot, e.g. the first hydrostatic adjustment) is replaced by zero
+      if (guessed) {
+        launch_guess_gate<T>(g, V.f[F_RHS], V.f[F_PHI0], V.partials, V.ctl, s);
+        LAUNCH_TRY();
+      }
       const int solve_idx = step * K + k;
       const int fixed = opts && opts->replay_sweeps ? opts->replay_sweeps[solve_idx] : 0;
       if (opts && opts->replay_sweeps && fixed < 0)
@@ -539,7 +547,7 @@ int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step
       T *phi = nullptr;
       SweepTiming timing;
       timing.enabled = opts && opts->time_sweeps;
-      int rc = solve<T>(h, V, V.f[F_RHS], guessed, fixed, &st, &phi, &timing, true);
+      int rc = solve<T>(h, V, V.f[F_RHS], guessed, fixed, &st, &phi, &timing, true, guessed);
       acc.sweep_seconds += timing.seconds;
       acc.sweeps_timed += timing.sweeps;
       if (opts && opts->records) opts->records[solve_idx] = st;

@@ -57,6 +57,8 @@ struct SolveCtl {
   int32_t stop_m;     // sweep index of the returned iterate
   int32_t max_sweeps;
   int32_t fixed;      // 1: stop at max_sweeps whatever the residual
+  int32_t guess_kept; // starting-iterate test (not reset by a solve): 1 kept
+  int32_t pad;
 };
 
 constexpr int kBlock = 256;          // threads per block of elementwise kernels
@@ -131,6 +133,13 @@ void launch_sub_mean(const Grid &g, const T *in, const SolveCtl *ctl, T *out, hi
 template <typename T>
 void launch_extrapolate(const Grid &g, const Profiles<T> &P, const T *p, const T *p_prev, T *phi0,
                         hipStream_t s);
+
+// Keep a starting iterate only if it is a better start than zero:
+// phi0 := 0 unless ||rhs - L phi0||_2 < ||rhs||_2 (FP64 sums; sets
+// ctl->guess_kept).
+template <typename T>
+void launch_guess_gate(const Grid &g, const T *rhs, T *phi0, double *partials, SolveCtl *ctl,
+                       hipStream_t s);
 
 // Generic FP64 sums over n elements: mode 0 sum(a), 1 sum(a^2).
 template <typename T>

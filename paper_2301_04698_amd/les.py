@@ -62,11 +62,12 @@ class LesBuffers(C.Structure):
 
 class LesSolveStats(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("status", C.c_int32), ("rhs_norm", C.c_double),
-                ("res_norm", C.c_double), ("seconds", C.c_double)]
+                ("res_norm", C.c_double), ("seconds", C.c_double), ("guess", C.c_int32),
+                ("reserved", C.c_int32)]
 
     def as_dict(self):
         return dict(sweeps=self.sweeps, status=self.status, rhs_norm=self.rhs_norm,
-                    res_norm=self.res_norm, seconds=self.seconds)
+                    res_norm=self.res_norm, seconds=self.seconds, guess=self.guess)
 
 
 class LesPoissonOpts(C.Structure):

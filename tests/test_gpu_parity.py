@@ -208,6 +208,7 @@ def test_step_guess_matches_oracle(gpu, oracle_lib, guess):
         assert e <= 1e-11, (k, e, errs)
     for a, b in zip(recs, grecs):
         assert b["res_norm"] == pytest.approx(a["res_norm"], rel=1e-6, abs=1e-12 * a["rhs_norm"])
+        assert b["guess"] == a["guess"]
 
 
 def test_step_guess_fp32_converges(gpu):

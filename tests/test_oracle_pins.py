@@ -667,5 +667,12 @@ def test_guess_modes_change_sweeps_not_solution(oracle_lib):
     st, rp = runs["previous"]
     for k in range(K):
         assert sw(rp, k) < sw(rz, k), k
+    # start codes: 0 zero start, 1 guess kept, 2 guess rejected (its residual
+    # not below ||rhs||); no guess exists on the first step, and once the
+    # flow has passed its first adjustment the previous solution is kept
+    assert all(r["guess"] == 0 for r in rz)
+    assert [r["guess"] for r in rp[:K]] == [0] * K
+    assert all(r["guess"] == 1 for r in rp[6 * K:])
+    assert all(r["guess"] in (1, 2) for r in rp[K:])
     with pytest.raises(ValueError):
         oracle_lib.make_cfg(dict(p0, guess="learned"))

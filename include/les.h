@@ -175,7 +175,8 @@ size_t les_workspace_bytes(const les_config *cfg);
  * 0 u^n, 1 v^n, 2 w^n, 3 thl^{n+1/2}, 4 qt^{n+1/2}, 5 thl_mid, 6 qt_mid,
  * 7..9 u,v,w at n+1/2, 10 b^{n+1/2}, 11 b_mid, 12 ql_mid, 13 c_pm*Pi (mid),
  * 14 nu scalars, 15 nu momentum, 16 radiative heating, 17 Poisson rhs,
- * 18..21 Poisson iterate buffers 0..3, 22 pressure of the previous step. */
+ * 18..21 Poisson iterate buffers 0..3, 22 pressure of the previous step,
+ * 23 starting iterate of a guessed solve, 24 its defect right-hand side. */
 int les_workspace_offset(const les_config *cfg, int32_t field, size_t *offset);
 
 /* Validates cfg and buffers, computes the reference state (Sec. 2.1) and

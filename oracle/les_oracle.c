@@ -810,9 +810,11 @@ int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, dou
         memcpy(S.phi, hist + (size_t)it * n, n * sizeof(double));
         guessed = 1;
       }
+      double mr = fsum(c, S.rhs) / (double)n;
+      for (size_t q = 0; q < n; ++q) S.rhs[q] -= mr;
       if (guessed) {
         /* keep the guess only if it starts closer than zero:
-           ||rhs - L phi_0|| < ||rhs|| (rhs before its mean is removed) */
+           ||rhs - L phi_0|| < ||rhs|| */
         oracle_laplacian(c, S.phi, S.tmp);
         double rr = 0.0, bb = 0.0;
         for (size_t q = 0; q < n; ++q) {
@@ -825,8 +827,6 @@ int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, dou
           guessed = 2;
         }
       }
-      double mr = fsum(c, S.rhs) / (double)n;
-      for (size_t q = 0; q < n; ++q) S.rhs[q] -= mr;
       osolve st;
       int fixed = replay ? replay[solve] : 0;
       rc = oracle_poisson(c, S.rhs, S.phi, fixed, &st);

@@ -96,8 +96,8 @@ typedef struct odebug {
  *   2  each sub-iteration: the zero-mean solution of the same sub-iteration
  *      of the last step (zero on the first step of the call).
  * A guess is kept only if ||rhs - L phi_0||_2 < ||rhs||_2 (the residual of
- * the zero start), evaluated before the rhs mean is removed; otherwise the
- * solve starts from zero.
+ * the zero start, rhs with its mean removed); otherwise the solve starts
+ * from zero.
  * The guess changes the sweep count only: the stopping test is relative to
  * ||rhs||, whatever the starting iterate. */
 int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, double *qt,

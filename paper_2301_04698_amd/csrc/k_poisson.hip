@@ -132,13 +132,15 @@ __global__ __launch_bounds__(1024) void final_kernel(const double *__restrict__ 
                                                      double tol2_scale, int m, double *out) {
   double acc = 0.0;
   for (int q = threadIdx.x; q < np; q += blockDim.x) acc += partials[q];
-  const double s = block_sum(acc);
+  double s = block_sum(acc);
   if (threadIdx.x != 0) return;
   switch (op) {
     case kFinalRhsMean:
       ctl->rhs_mean = s / n;
       break;
+    case kFinalRhsNormRef:
     case kFinalRhsNorm:
+      if (op == kFinalRhsNormRef) s = ctl->ref_norm2;
       ctl->rhs_norm2 = s;
       ctl->tol2 = tol2_scale * s;
       if (!isfinite(s)) {
@@ -181,14 +183,16 @@ __global__ __launch_bounds__(1024) void final_kernel(const double *__restrict__ 
   }
 }
 
-// Starting-iterate test: FP64 partial sums of (rhs - L phi0)^2 (partials[b])
-// and of rhs^2 (partials[gridDim.x + b]), L the compact Laplacian with
-// periodic x, y and mirror z.
+// Defect right-hand side of a starting iterate: rhs_d = rhs - L phi0 in
+// FP64, with FP64 partial sums of rhs_d^2 (partials[b]) and of rhs^2
+// (partials[gridDim.x + b]); L the compact Laplacian, periodic x, y and
+// mirror z.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void guess_residual_kernel(Grid g, double ix2, double iy2,
                                                                 double iz2,
                                                                 const T *__restrict__ rhs,
                                                                 const T *__restrict__ phi0,
+                                                                T *__restrict__ rhs_d,
                                                                 double *__restrict__ partials) {
   double rr = 0.0, bb = 0.0;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < g.n;
@@ -206,7 +210,9 @@ __global__ __launch_bounds__(kBlock) void guess_residual_kernel(Grid g, double i
         ((double)gload(phi0, g, i, j, k + 1, T(1)) + (double)gload(phi0, g, i, j, k - 1, T(1)) -
          2.0 * c) * iz2;
     const double b = rhs[q];
-    rr += (b - lap) * (b - lap);
+    const double d = b - lap;
+    rhs_d[q] = (T)d;
+    rr += d * d;
     bb += b * b;
   }
   const double sr = block_sum(rr);
@@ -228,16 +234,31 @@ __global__ __launch_bounds__(1024) void guess_gate_kernel(const double *__restri
   }
   a = block_sum(a);
   b = block_sum(b);
-  if (threadIdx.x == 0) ctl->guess_kept = a < b ? 1 : 0;
+  if (threadIdx.x == 0) {
+    ctl->guess_kept = a < b ? 1 : 0;
+    ctl->ref_norm2 = b;
+  }
 }
 
+// A rejected starting iterate: the solve takes rhs itself from zero.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void guess_clear_kernel(int64_t n,
                                                              const SolveCtl *__restrict__ ctl,
-                                                             T *__restrict__ phi0) {
+                                                             const T *__restrict__ rhs,
+                                                             T *__restrict__ rhs_d) {
   if (ctl->guess_kept) return;
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < n) phi0[q] = T(0);
+  if (q < n) rhs_d[q] = rhs[q];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void add_guess_kernel(int64_t n,
+                                                           const SolveCtl *__restrict__ ctl,
+                                                           const T *__restrict__ phi0,
+                                                           T *__restrict__ phi) {
+  if (!ctl->guess_kept) return;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) phi[q] = (T)((double)phi[q] + (double)phi0[q]);
 }
 
 __global__ void ctl_reset_kernel(SolveCtl *ctl, int max_sweeps, int fixed) {
@@ -288,12 +309,18 @@ void launch_extrapolate(const Grid &g, const Profiles<T> &P, const T *p, const T
 }
 
 template <typename T>
-void launch_guess_gate(const Grid &g, const T *rhs, T *phi0, double *partials, SolveCtl *ctl,
-                       hipStream_t s) {
+void launch_guess_gate(const Grid &g, const T *rhs, const T *phi0, T *rhs_d, double *partials,
+                       SolveCtl *ctl, hipStream_t s) {
   guess_residual_kernel<T><<<kReduceBlocks, kBlock, 0, s>>>(
-      g, 1.0 / (g.dx * g.dx), 1.0 / (g.dy * g.dy), 1.0 / (g.dz * g.dz), rhs, phi0, partials);
+      g, 1.0 / (g.dx * g.dx), 1.0 / (g.dy * g.dy), 1.0 / (g.dz * g.dz), rhs, phi0, rhs_d,
+      partials);
   guess_gate_kernel<<<1, 1024, 0, s>>>(partials, kReduceBlocks, ctl);
-  guess_clear_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g.n, ctl, phi0);
+  guess_clear_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g.n, ctl, rhs, rhs_d);
+}
+
+template <typename T>
+void launch_add_guess(const Grid &g, const T *phi0, const SolveCtl *ctl, T *phi, hipStream_t s) {
+  add_guess_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g.n, ctl, phi0, phi);
 }
 
 template <typename T>
@@ -320,8 +347,9 @@ void launch_ctl_reset(SolveCtl *ctl, int max_sweeps, int fixed, hipStream_t s) {
                                   const SolveCtl *, T *, T *, T *, T *, hipStream_t);            \
   template void launch_sub_mean<T>(const Grid &, const T *, const SolveCtl *, T *, hipStream_t); \
   template void launch_block_sum<T>(const T *, int64_t, int, double *, hipStream_t);            \
-  template void launch_guess_gate<T>(const Grid &, const T *, T *, double *, SolveCtl *,         \
-                                     hipStream_t);                                               \
+  template void launch_guess_gate<T>(const Grid &, const T *, const T *, T *, double *,        \
+                                     SolveCtl *, hipStream_t);                                   \
+  template void launch_add_guess<T>(const Grid &, const T *, const SolveCtl *, T *, hipStream_t); \
   template void launch_extrapolate<T>(const Grid &, const Profiles<T> &, const T *, const T *,   \
                                       T *, hipStream_t);
 LES_INST(float)

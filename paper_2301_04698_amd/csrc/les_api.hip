@@ -25,7 +25,7 @@ namespace {
 enum Field {
   F_UN = 0, F_VN, F_WN, F_THL_H, F_QT_H, F_THL_M, F_QT_M, F_UH, F_VH, F_WH,
   F_B_H, F_B_M, F_QL_M, F_CPMPI_M, F_NU_S, F_NU_M, F_RAD, F_RHS, F_PHI0, F_PHI1,
-  F_PHI2, F_PHI3, F_PM2,
+  F_PHI2, F_PHI3, F_PM2, F_GUESS, F_RHSD,
   F_COUNT
 };
 
@@ -284,13 +284,14 @@ struct SweepTiming {
 template <typename T>
 int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
           les_solve_stats *st, T **result, SweepTiming *timing = nullptr,
-          bool start_recorded = false, bool gated = false) {
+          bool start_recorded = false, bool gated = false, T *rhs_work = nullptr) {
   const les_config &c = h->cfg;
   const Grid &g = h->grid;
   hipStream_t s = h->stream;
   const int max_sweeps = fixed > 0 ? fixed : c.poisson_max_sweeps;
   const int every = c.poisson_check_every;
-  T *rhs = V.f[F_RHS];
+  // centred rhs the sweeps read (a defect solve centres its own in place)
+  T *rhs = rhs_work ? rhs_work : V.f[F_RHS];
 
   // start of the solve's time (the caller records it before preparing a guess)
   if (!start_recorded) HIP_TRY(hipEventRecord(h->ev_s0, s));
@@ -298,8 +299,9 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
   launch_block_sum(rhs_in, g.n, 0, V.partials, s);
   launch_final(V.partials, kReduceBlocks, kFinalRhsMean, V.ctl, (double)g.n, 0.0, 0, nullptr, s);
   launch_rhs_center(g, rhs_in, rhs, use_guess ? (T *)nullptr : V.f[F_PHI0], V.ctl, V.partials, s);
-  launch_final(V.partials, kReduceBlocks, kFinalRhsNorm, V.ctl, (double)g.n,
-               c.poisson_tol * c.poisson_tol, 0, nullptr, s);
+  // a defect solve stops on the residual relative to the original ||rhs||
+  launch_final(V.partials, kReduceBlocks, gated ? kFinalRhsNormRef : kFinalRhsNorm, V.ctl,
+               (double)g.n, c.poisson_tol * c.poisson_tol, 0, nullptr, s);
   LAUNCH_TRY();
 
   const bool cheb = c.poisson_scheme == LES_CHEBYSHEV;
@@ -445,7 +447,7 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
   st->rhs_norm = std::sqrt(r.rhs_norm2);
   st->res_norm = std::sqrt(r.res_norm2);
   st->seconds = ms * 1e-3;
-  st->guess = !use_guess ? 0 : (gated && !r.guess_kept ? 2 : 1);
+  st->guess = gated ? (r.guess_kept ? 1 : 2) : (use_guess ? 1 : 0);
   st->reserved = 0;
   *result = buf[res_buf];
   if (r.done == 2) return fail(LES_ERR_NONFINITE, "non-finite Poisson residual");
@@ -516,27 +518,38 @@ int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step
       // the solve's time includes preparing its guess
       HIP_TRY(hipEventRecord(h->ev_s0, s));
       T *hist = (T *)ws(h, h->lay.hist) + (size_t)k * g.n;
-      bool guessed = false;
+      // Starting iterate: the previous step's solution of this sub-iteration
+      // (corrected by the network in the learned form), or at k = 0 the
+      // extrapolated pressure change.  At k = 0 p holds p^n and the
+      // workspace p^{n-1}.
+      const T *guess = nullptr;
       if (c.guess == LES_GUESS_PREVIOUS || c.guess == LES_GUESS_LEARNED) {
-        // the previous step's solution of this sub-iteration, corrected by
-        // the network in the learned form
-        guessed = h->hist_valid[k] != 0;
-        if (guessed && c.guess == LES_GUESS_PREVIOUS)
-          HIP_TRY(hipMemcpyAsync(V.f[F_PHI0], hist, bytes, hipMemcpyDeviceToDevice, s));
-        if (guessed && c.guess == LES_GUESS_LEARNED) {
-          const int grc = cnn_guess<T>(h, V, V.f[F_RHS], hist, V.f[F_PHI0]);
-          if (grc) return grc;
+        if (h->hist_valid[k]) {
+          if (c.guess == LES_GUESS_PREVIOUS) {
+            guess = hist;
+          } else {
+            const int grc = cnn_guess<T>(h, V, V.f[F_RHS], hist, V.f[F_GUESS]);
+            if (grc) return grc;
+            guess = V.f[F_GUESS];
+          }
         }
       } else if (k == 0 && c.guess == LES_GUESS_EXTRAPOLATE) {
-        guessed = true;
-        launch_extrapolate<T>(g, V.P, V.p, V.f[F_PM2], V.f[F_PHI0], s);
+        launch_extrapolate<T>(g, V.P, V.p, V.f[F_PM2], V.f[F_GUESS], s);
         HIP_TRY(hipMemcpyAsync(V.f[F_PM2], V.p, bytes, hipMemcpyDeviceToDevice, s));
         LAUNCH_TRY();
+        guess = V.f[F_GUESS];
       }
-      // a guess worse than the zero start (a step that changed the solution
-      // a lot, e.g. the first hydrostatic adjustment) is replaced by zero
+      const bool guessed = guess != nullptr;
       if (guessed) {
-        launch_guess_gate<T>(g, V.f[F_RHS], V.f[F_PHI0], V.partials, V.ctl, s);
+        // Defect form: centre rhs, then rhs_d = rhs - L guess; the sweeps
+        // solve for the correction from zero, so FP32 rounding acts at the
+        // correction's size, not the guess's.  A guess whose residual is
+        // not below the zero start's is dropped (rhs_d = rhs).
+        launch_block_sum<T>(V.f[F_RHS], g.n, 0, V.partials, s);
+        launch_final(V.partials, kReduceBlocks, kFinalRhsMean, V.ctl, (double)g.n, 0.0, 0,
+                     nullptr, s);
+        launch_rhs_center<T>(g, V.f[F_RHS], V.f[F_RHS], nullptr, V.ctl, V.partials, s);
+        launch_guess_gate<T>(g, V.f[F_RHS], guess, V.f[F_RHSD], V.partials, V.ctl, s);
         LAUNCH_TRY();
       }
       const int solve_idx = step * K + k;
@@ -547,11 +560,17 @@ int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step
       T *phi = nullptr;
       SweepTiming timing;
       timing.enabled = opts && opts->time_sweeps;
-      int rc = solve<T>(h, V, V.f[F_RHS], guessed, fixed, &st, &phi, &timing, true, guessed);
+      int rc = guessed ? solve<T>(h, V, V.f[F_RHSD], false, fixed, &st, &phi, &timing, true, true,
+                                  V.f[F_RHSD])
+                       : solve<T>(h, V, V.f[F_RHS], false, fixed, &st, &phi, &timing, true);
       acc.sweep_seconds += timing.seconds;
       acc.sweeps_timed += timing.sweeps;
       if (opts && opts->records) opts->records[solve_idx] = st;
       if (rc < 0) return rc;
+      if (guessed) {  // phi = guess + correction
+        launch_add_guess<T>(g, guess, V.ctl, phi, s);
+        LAUNCH_TRY();
+      }
       acc.solves++;
       acc.sweeps_total += st.sweeps;
       if (st.sweeps > acc.sweeps_max) acc.sweeps_max = st.sweeps;

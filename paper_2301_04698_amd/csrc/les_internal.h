@@ -59,6 +59,7 @@ struct SolveCtl {
   int32_t fixed;      // 1: stop at max_sweeps whatever the residual
   int32_t guess_kept; // starting-iterate test (not reset by a solve): 1 kept
   int32_t pad;
+  double ref_norm2;   // ||rhs||^2 of the equation a defect solve stands for
 };
 
 constexpr int kBlock = 256;          // threads per block of elementwise kernels
@@ -134,12 +135,17 @@ template <typename T>
 void launch_extrapolate(const Grid &g, const Profiles<T> &P, const T *p, const T *p_prev, T *phi0,
                         hipStream_t s);
 
-// Keep a starting iterate only if it is a better start than zero:
-// phi0 := 0 unless ||rhs - L phi0||_2 < ||rhs||_2 (FP64 sums; sets
-// ctl->guess_kept).
+// Starting iterate phi0 of a solve of L phi = rhs (rhs centred), in
+// defect form: rhs_d = rhs - L phi0 (FP64 arithmetic), so the sweeps solve
+// L delta = rhs_d from zero and phi = phi0 + delta.  The iterate is kept
+// only if ||rhs_d||_2 < ||rhs||_2 (the zero start's residual); otherwise
+// rhs_d = rhs.  Sets ctl->guess_kept and ctl->ref_norm2 = ||rhs||^2.
 template <typename T>
-void launch_guess_gate(const Grid &g, const T *rhs, T *phi0, double *partials, SolveCtl *ctl,
-                       hipStream_t s);
+void launch_guess_gate(const Grid &g, const T *rhs, const T *phi0, T *rhs_d, double *partials,
+                       SolveCtl *ctl, hipStream_t s);
+// phi += phi0 (FP64 sum, rounded once) when ctl->guess_kept.
+template <typename T>
+void launch_add_guess(const Grid &g, const T *phi0, const SolveCtl *ctl, T *phi, hipStream_t s);
 
 // Generic FP64 sums over n elements: mode 0 sum(a), 1 sum(a^2).
 template <typename T>
@@ -151,7 +157,8 @@ enum FinalOp {
   kFinalRhsNorm = 1,   // ctl->rhs_norm2, tol2; converged at once if zero
   kFinalCheck = 2,     // residual check at sweep m
   kFinalPhiMean = 3,   // ctl->phi_mean = sum / n
-  kFinalStore = 4      // out[slot] = sum
+  kFinalStore = 4,     // out[slot] = sum
+  kFinalRhsNormRef = 5 // as kFinalRhsNorm with ctl->ref_norm2 in place of the sum
 };
 void launch_final(const double *partials, int np, int op, SolveCtl *ctl, double n, double tol2_scale,
                   int m, double *out, hipStream_t s);

@@ -28,7 +28,7 @@ PROFILE_NAMES = ("thl", "qt", "ql", "u", "v", "w", "w2", "w3", "b")
 # Workspace field ids (les_workspace_offset).
 WS_FIELDS = ("un", "vn", "wn", "thl_half", "qt_half", "thl_mid", "qt_mid", "uh", "vh", "wh",
              "b_half", "b_mid", "ql_mid", "cpmpi_mid", "nu_s", "nu_m", "rad", "rhs", "phi0", "phi1",
-             "phi2", "phi3", "p_prev")
+             "phi2", "phi3", "p_prev", "guess", "rhs_defect")
 
 EXPORTS = ("les_default_config", "les_workspace_bytes", "les_workspace_offset", "les_init",
            "les_step", "les_poisson_solve", "les_thermo", "les_diagnostics", "les_destroy",

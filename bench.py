@@ -219,8 +219,8 @@ def learned_form(p, args, plain_sweeps, plain_poisson, plain_value):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: the LES step is built and measured on a "
-              "single MI355X (no multi-GPU decomposition in this build); use --gpus 1.",
+        print("bench.py runs on exactly one GPU: the library's LES step runs on a single "
+              "MI355X and has no multi-GPU decomposition; use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -76,7 +76,8 @@ _BASE = dict(
     poisson_check_every=25,
     jacobi_omega=0.0,          # 0 selects the closed-form optimum
     sweeps_per_launch=0,       # library launch shape only (0: its default)
-    guess="zero",              # first solve's initial guess (library only)
+    guess="zero",              # initial guess of the solves
+    advection="quick",         # "quick" or "weno3" (WENO3 with Lax-Friedrichs flux)
     # forcing
     ug=7.0, vg=-5.0,
     shf=0.0, lhf=0.0,          # surface sensible / latent heat flux, W/m^2

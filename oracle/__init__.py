@@ -18,6 +18,7 @@ SCHEMES = {"jacobi": 0, "chebyshev": 1}
 
 
 GUESSES = {"zero": 0, "extrapolate": 1, "previous": 2}
+ADVECTION = {"quick": 0, "weno3": 1}
 
 
 class OCfg(C.Structure):
@@ -25,7 +26,7 @@ class OCfg(C.Structure):
         ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("n_subiter", C.c_int32),
         ("poisson_scheme", C.c_int32), ("poisson_check_every", C.c_int32),
         ("poisson_max_sweeps", C.c_int32), ("satadj_maxit", C.c_int32),
-        ("guess", C.c_int32), ("reserved", C.c_int32),
+        ("guess", C.c_int32), ("advection", C.c_int32),
         ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("dt", C.c_double),
         ("poisson_tol", C.c_double), ("jacobi_omega", C.c_double),
         ("p00", C.c_double), ("theta0", C.c_double), ("Rd", C.c_double), ("Rv", C.c_double),
@@ -71,7 +72,9 @@ def lib():
         L.oracle_satadj.argtypes = [cfgp, C.c_double, C.c_double, C.c_double, _DP, _DP, _DP]
         L.oracle_thermo.argtypes = [cfgp, _DP, _DP, _DP, _DP, _DP, _DP]
         L.oracle_sgs_nu.argtypes = [cfgp, _DP, _DP, _DP, _DP, _DP]
-        L.oracle_advect_quick.argtypes = [cfgp, _DP, _DP, _DP, _DP, C.c_double, _DP]
+        L.oracle_advect.argtypes = [cfgp, _DP, _DP, _DP, _DP, C.c_double, _DP]
+        L.oracle_face_value.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double]
+        L.oracle_face_value.restype = C.c_double
         L.oracle_diffuse.argtypes = [cfgp, _DP, C.c_double, _DP, _DP]
         L.oracle_sgs_momentum.argtypes = [cfgp, _DP, _DP, _DP, _DP, _DP, _DP, _DP]
         L.oracle_laplacian.argtypes = [cfgp, _DP, _DP]
@@ -99,8 +102,11 @@ def make_cfg(p: dict) -> OCfg:
             if v not in GUESSES:
                 raise ValueError(f"the oracle step has no {v!r} guess; known: {sorted(GUESSES)}")
             c.guess = GUESSES[v]
-        elif name == "reserved":
-            c.reserved = 0
+        elif name == "advection":
+            v = p.get("advection", "quick")
+            if v not in ADVECTION:
+                raise ValueError(f"unknown advection scheme {v!r}; known: {sorted(ADVECTION)}")
+            c.advection = ADVECTION[v]
         else:
             setattr(c, name, ctype(p[name]).value)
     return c
@@ -165,11 +171,16 @@ def sgs_nu(p, u, v, w, b):
     return nu
 
 
-def advect_quick(p, U, V, W, q, zparity=1.0):
+def face_value(scheme, qm1, q0, q1):
+    """Upwind face value at l+1/2 from (q_{l-1}, q_l, q_{l+1})."""
+    return lib().oracle_face_value(ADVECTION[scheme], qm1, q0, q1)
+
+
+def advect(p, U, V, W, q, zparity=1.0):
     U, V, W, q = map(_f64, (U, V, W, q))
     out = np.zeros(_shape(p))
-    _check(lib().oracle_advect_quick(C.byref(make_cfg(p)), _ptr(U), _ptr(V), _ptr(W), _ptr(q),
-                                     float(zparity), _ptr(out)), "advect_quick")
+    _check(lib().oracle_advect(C.byref(make_cfg(p)), _ptr(U), _ptr(V), _ptr(W), _ptr(q),
+                               float(zparity), _ptr(out)), "advect")
     return out
 
 

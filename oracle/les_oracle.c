@@ -63,6 +63,7 @@ static double spacing(const ocfg *c, int axis) {
 static int check_cfg(const ocfg *c) {
   if (!c || c->nx < 4 || c->ny < 4 || c->nz < 4) return -1;
   if (!(c->dx > 0) || !(c->dy > 0) || !(c->dz > 0) || !(c->dt > 0)) return -1;
+  if (c->advection != 0 && c->advection != 1) return -1;
   return 0;
 }
 
@@ -293,23 +294,51 @@ static double quick_face(double m, double qm1, double q0, double q1, double q2) 
   return (6.0 * q1 + 3.0 * q0 - q2) / 8.0;
 }
 
+/* Third-order WENO reconstruction at face l+1/2 from the upwind side
+ * (Sec. 3 alternative scheme; READING: the finite-volume WENO3 of Jiang &
+ * Shu): a = q_{l-1}, b = q_l, c = q_{l+1}; candidates (-a + 3b)/2 on
+ * {l-1, l} and (b + c)/2 on {l, l+1} with linear weights 1/3, 2/3;
+ * smoothness (b - a)^2, (c - b)^2; eps = 1e-6 max(a^2, b^2, c^2) + 1e-18 so
+ * the weights do not depend on the field's units. */
+static double weno3_face(double a, double b, double c) {
+  const double eps = 1e-6 * fmax(a * a, fmax(b * b, c * c)) + 1e-18;
+  const double s0 = (eps + (b - a) * (b - a)), s1 = (eps + (c - b) * (c - b));
+  /* w0 = (1/3)/s0^2 / ((1/3)/s0^2 + (2/3)/s1^2), written without the small squares
+     in denominators */
+  const double w0 = (1.0 / 3.0) * s1 * s1 / ((1.0 / 3.0) * s1 * s1 + (2.0 / 3.0) * s0 * s0);
+  return w0 * (-a + 3.0 * b) / 2.0 + (1.0 - w0) * (b + c) / 2.0;
+}
+
+double oracle_face_value(int scheme, double qm1, double q0, double q1) {
+  if (scheme == 1) return weno3_face(qm1, q0, q1);
+  return (6.0 * q0 + 3.0 * q1 - qm1) / 8.0;
+}
+
 /* Advective flux through the face between a cell and its +1 neighbour along
  * `axis`: face mass flux m = (M_l + M_{l+1}) / 2 of the momentum component
- * along the axis, times the QUICK face value of q. */
+ * along the axis, times the face value of q.  WENO3: Lax-Friedrichs flux
+ * (1/2) m (q- + q+) - (1/2) |m| (q+ - q-) (READING: the local speed is |m|,
+ * so the flux takes the reconstruction from the upwind side and vanishes
+ * on the walls with m). */
 static double adv_flux(const ocfg *c, const double *M, const double *q, double qpar, int axis,
                        int i, int j, int k) {
   const int *e = UNIT[axis];
   double m = 0.5 * (at(c, M, i, j, k, -1.0) + at(c, M, i + e[0], j + e[1], k + e[2], -1.0));
-  double qf = quick_face(m, at(c, q, i - e[0], j - e[1], k - e[2], qpar), at(c, q, i, j, k, qpar),
-                         at(c, q, i + e[0], j + e[1], k + e[2], qpar),
-                         at(c, q, i + 2 * e[0], j + 2 * e[1], k + 2 * e[2], qpar));
-  return m * qf;
+  double qm1 = at(c, q, i - e[0], j - e[1], k - e[2], qpar), q0 = at(c, q, i, j, k, qpar);
+  double q1 = at(c, q, i + e[0], j + e[1], k + e[2], qpar);
+  double q2 = at(c, q, i + 2 * e[0], j + 2 * e[1], k + 2 * e[2], qpar);
+  if (c->advection == 1) {
+    double qminus = weno3_face(qm1, q0, q1), qplus = weno3_face(q2, q1, q0);
+    return 0.5 * m * (qminus + qplus) - 0.5 * fabs(m) * (qplus - qminus);
+  }
+  return m * quick_face(m, qm1, q0, q1, q2);
 }
 
-/* out = -div(U q) in flux form with QUICK face values (Sec. 2.1 conservation
- * form, Sec. 2.4 QUICK).  U, V, W are momentum components rho0 u. */
-int oracle_advect_quick(const ocfg *c, const double *U, const double *V, const double *W,
-                        const double *q, double zparity, double *out) {
+/* out = -div(U q) in flux form (Sec. 2.1 conservation form) with QUICK
+ * (Sec. 2.4) or WENO3/Lax-Friedrichs face fluxes.  U, V, W are momentum
+ * components rho0 u. */
+int oracle_advect(const ocfg *c, const double *U, const double *V, const double *W,
+                  const double *q, double zparity, double *out) {
   if (check_cfg(c)) return -1;
   const double *M[3] = {U, V, W};
   for (int k = 0; k < c->nz; ++k)
@@ -739,7 +768,7 @@ int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, dou
       oracle_sgs_nu(c, S.uk[0], S.uk[1], S.uk[2], S.b_m, S.nu_s);
 
       /* theta_l */
-      oracle_advect_quick(c, S.Uk[0], S.Uk[1], S.Uk[2], S.thl_m, 1.0, S.tend);
+      oracle_advect(c, S.Uk[0], S.Uk[1], S.Uk[2], S.thl_m, 1.0, S.tend);
       oracle_diffuse(c, S.nu_s, 1.0 / c->Pr, S.thl_m, S.tmp);
       for (size_t q = 0; q < n; ++q) S.tend[q] += S.tmp[q];
       oracle_radiation(c, S.ql_m, S.cpmpi_m, S.tmp);
@@ -749,7 +778,7 @@ int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, dou
         for (size_t q = (size_t)k * c->nx * c->ny; q < (size_t)(k + 1) * c->nx * c->ny; ++q)
           thl[q] = S.thl_h[q] + c->dt / P.rho0[k] * S.tend[q];
       /* q_t */
-      oracle_advect_quick(c, S.Uk[0], S.Uk[1], S.Uk[2], S.qt_m, 1.0, S.tend);
+      oracle_advect(c, S.Uk[0], S.Uk[1], S.Uk[2], S.qt_m, 1.0, S.tend);
       oracle_diffuse(c, S.nu_s, 1.0 / c->Sc, S.qt_m, S.tmp);
       for (size_t q = 0; q < n; ++q) S.tend[q] += S.tmp[q];
       scalar_sources(c, &P, S.qt_m, c->lhf / c->Lv0, S.tend);
@@ -767,7 +796,7 @@ int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, dou
       oracle_sgs_nu(c, S.uh[0], S.uh[1], S.uh[2], S.b_h, S.nu_m);
       oracle_sgs_momentum(c, S.nu_m, S.uh[0], S.uh[1], S.uh[2], S.sg[0], S.sg[1], S.sg[2]);
       for (int a = 0; a < 3; ++a) {
-        oracle_advect_quick(c, S.Uh[0], S.Uh[1], S.Uh[2], S.uh[a], -1.0, S.R[a]);
+        oracle_advect(c, S.Uh[0], S.Uh[1], S.Uh[2], S.uh[a], -1.0, S.R[a]);
         for (size_t q = 0; q < n; ++q) S.R[a][q] += S.sg[a][q];
       }
       for (int k = 0; k < c->nz; ++k)

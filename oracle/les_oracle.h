@@ -22,7 +22,7 @@ typedef struct ocfg {
   int32_t poisson_max_sweeps;
   int32_t satadj_maxit;
   int32_t guess;               /* initial guess of the solves, see oracle_step */
-  int32_t reserved;
+  int32_t advection;           /* 0 QUICK, 1 WENO3 with Lax-Friedrichs flux */
   double dx, dy, dz, dt;
   double poisson_tol;          /* ||rhs - L phi||_2 <= tol * ||rhs||_2 */
   double jacobi_omega;         /* 0 = closed-form optimum */
@@ -59,8 +59,13 @@ int oracle_thermo(const ocfg *c, const double *thl, const double *qt,
 /* Operators (Sec. 2.3, 2.4, App. A).  Velocities primitive unless noted. */
 int oracle_sgs_nu(const ocfg *c, const double *u, const double *v, const double *w,
                   const double *b, double *nu);
-int oracle_advect_quick(const ocfg *c, const double *U, const double *V, const double *W,
-                        const double *q, double zparity, double *out);
+/* out = -div(U q), flux form, face values by c->advection. */
+int oracle_advect(const ocfg *c, const double *U, const double *V, const double *W,
+                  const double *q, double zparity, double *out);
+/* Face value of the upwind reconstruction from (q_{l-1}, q_l, q_{l+1}),
+ * taken on the upwind side of face l+1/2 (scheme 0 QUICK uses q_{l+1}
+ * as its downwind point, scheme 1 WENO3). */
+double oracle_face_value(int scheme, double qm1, double q0, double q1);
 int oracle_diffuse(const ocfg *c, const double *nu, double inv_prandtl,
                    const double *q, double *out);
 int oracle_sgs_momentum(const ocfg *c, const double *nu, const double *u, const double *v,

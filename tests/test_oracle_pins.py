@@ -319,7 +319,11 @@ def test_poisson_not_converged_flag(oracle_lib):
 def test_quick_constant_field_divergence_free(oracle_lib):
     """A constant scalar stays constant under a velocity whose central
     divergence vanishes (w = 0, u = -d_c psi/dy, v = d_c psi/dx)."""
-    p = small(nx=12, ny=10, nz=8)
+    for scheme in ("quick", "weno3"):
+        _constant_field(oracle_lib, small(nx=12, ny=10, nz=8, advection=scheme))
+
+
+def _constant_field(oracle_lib, p):
     rs = oracle_lib.reference_state(p)
     rng = np.random.default_rng(1)
     psi = rng.standard_normal((8, 10, 12)) * 50.0
@@ -328,18 +332,19 @@ def test_quick_constant_field_divergence_free(oracle_lib):
     r0 = rs["rho0"][:, None, None]
     U, V, W = r0 * u, r0 * v, np.zeros_like(u)
     assert np.abs(oracle_lib.divergence(p, U, V, W)).max() < 1e-13
-    out = oracle_lib.advect_quick(p, U, V, W, np.full_like(u, 290.0))
+    out = oracle_lib.advect(p, U, V, W, np.full_like(u, 290.0))
     assert np.abs(out).max() < 1e-11 * 290.0 * np.abs(U).max() / p["dx"]
 
 
 def test_quick_flux_divergence_of_constant_equals_central_divergence(oracle_lib):
     """Face mass flux = average of the two cells, so -div(U c) = -c div_c U
     for any momentum field, including the wall rows."""
-    p = small(nx=8, ny=6, nz=7)
-    rng = np.random.default_rng(2)
-    U, V, W = (rng.standard_normal((7, 6, 8)) for _ in range(3))
-    out = oracle_lib.advect_quick(p, U, V, W, np.full((7, 6, 8), 3.0))
-    np.testing.assert_allclose(out, -3.0 * oracle_lib.divergence(p, U, V, W), atol=1e-13)
+    for scheme in ("quick", "weno3"):
+        p = small(nx=8, ny=6, nz=7, advection=scheme)
+        rng = np.random.default_rng(2)
+        U, V, W = (rng.standard_normal((7, 6, 8)) for _ in range(3))
+        out = oracle_lib.advect(p, U, V, W, np.full((7, 6, 8), 3.0))
+        np.testing.assert_allclose(out, -3.0 * oracle_lib.divergence(p, U, V, W), atol=1e-13)
 
 
 def test_quick_upwind_coefficients(oracle_lib):
@@ -350,14 +355,55 @@ def test_quick_upwind_coefficients(oracle_lib):
     q = np.broadcast_to(0.3 * x ** 2 - x + 2.0, (4, 4, 16)).copy()
     q[..., :2] = q[..., 2:4]  # keep the periodic seam out of the checked cells
     U = np.ones((4, 4, 16))
-    out = oracle_lib.advect_quick(p, U, np.zeros_like(U), np.zeros_like(U), q)
+    out = oracle_lib.advect(p, U, np.zeros_like(U), np.zeros_like(U), q)
     face = lambda s: 0.3 * s ** 2 - s + 2.0
     for i in range(4, 13):
         expect = -(face(i + 0.5) - face(i - 0.5))
         assert out[0, 0, i] == pytest.approx(expect, abs=1e-12)
-    out_neg = oracle_lib.advect_quick(p, -U, np.zeros_like(U), np.zeros_like(U), q)
+    out_neg = oracle_lib.advect(p, -U, np.zeros_like(U), np.zeros_like(U), q)
     for i in range(4, 13):
         assert out_neg[0, 0, i] == pytest.approx(face(i + 0.5) - face(i - 0.5), abs=1e-12)
+
+
+def test_weno3_face_values(oracle_lib):
+    """WENO3 reconstruction (the paper's alternative scheme): exact on
+    linear data whatever the weights; at a jump it takes the smooth side
+    (the upwind cell value) where QUICK overshoots by 3/8 of the jump; for
+    small smooth variations its weights tend to the linear ones, giving
+    (-q_{l-1} + 5 q_l + 2 q_{l+1}) / 6; and it is unit-free (scaling the
+    data scales the face value)."""
+    f = lambda a, b, c: oracle_lib.face_value("weno3", a, b, c)
+    for a, b, c in ((1.0, 2.0, 3.0), (290.0, 289.5, 289.0), (1e-3, 1.2e-3, 1.4e-3)):
+        assert f(a, b, c) == pytest.approx(b + 0.5 * (c - b), rel=1e-14, abs=1e-300)
+    assert abs(f(0.0, 0.0, 1.0)) < 1e-10
+    assert abs(f(1.0, 1.0, 0.0) - 1.0) < 1e-10
+    assert oracle_lib.face_value("quick", 0.0, 0.0, 1.0) == pytest.approx(0.375)
+    a, b, c = 290.0, 290.0 + 1e-5, 290.0 + 3e-5
+    assert f(a, b, c) == pytest.approx((-a + 5 * b + 2 * c) / 6, rel=1e-13)
+    rng = np.random.default_rng(9)
+    for _ in range(20):
+        a, b, c = rng.standard_normal(3)
+        for lam in (1e-3, 1e3):
+            assert f(lam * a, lam * b, lam * c) == pytest.approx(lam * f(a, b, c), rel=1e-9)
+
+
+def test_weno3_lax_friedrichs_flux_is_upwind_reconstruction(oracle_lib):
+    """With the face speed |m| the Lax-Friedrichs flux takes the
+    reconstruction from the upwind side: reversing the velocity mirrors
+    the tendency of a mirrored field."""
+    p = small(nx=16, ny=4, nz=4, dx=1.0, advection="weno3")
+    rng = np.random.default_rng(3)
+    q = np.broadcast_to(rng.standard_normal(16), (4, 4, 16)).copy()
+    U = np.full((4, 4, 16), 1.5)
+    out = oracle_lib.advect(p, U, 0 * U, 0 * U, q)
+    qm = q[..., ::-1].copy()
+    out_m = oracle_lib.advect(p, -U, 0 * U, 0 * U, qm)
+    np.testing.assert_allclose(out_m[..., ::-1], out, rtol=1e-12, atol=1e-12)
+    # explicit upwind face values for U > 0
+    fv = np.array([oracle_lib.face_value("weno3", q[0, 0, (i - 1) % 16], q[0, 0, i],
+                                         q[0, 0, (i + 1) % 16]) for i in range(16)])
+    expect = -1.5 * (fv - np.roll(fv, 1))
+    np.testing.assert_allclose(out[0, 0], expect, rtol=1e-12, atol=1e-12)
 
 
 # ------------------------------------------------------- P9 orders
@@ -386,6 +432,24 @@ def test_diffusion_second_order(oracle_lib):
     assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5, errs
 
 
+def test_weno3_advection_order(oracle_lib):
+    """WENO3 (Jiang-Shu weights): second order in the mean, at least second
+    order away from extrema in the maximum norm (at smooth extrema the
+    nonlinear weights lower it, a known property of the scheme)."""
+    l1, away = [], []
+    for n in (16, 32, 64):
+        p = small(nx=n, ny=4, nz=4, dx=1.0 / n, dy=1.0, dz=1.0, advection="weno3")
+        x = ((np.arange(n) + 0.5) / n)[None, None, :]
+        q = np.broadcast_to(np.sin(2 * np.pi * x), (4, 4, n)).copy()
+        U = np.full((4, 4, n), 2.0)
+        err = np.abs(oracle_lib.advect(p, U, 0 * U, 0 * U, q)
+                     + 2.0 * 2 * np.pi * np.cos(2 * np.pi * x))
+        l1.append(err.mean())
+        away.append(err[np.broadcast_to(np.abs(np.cos(2 * np.pi * x)) > 0.5, err.shape)].max())
+    assert l1[0] / l1[1] > 3.6 and l1[1] / l1[2] > 3.6, l1
+    assert away[0] / away[1] > 3.6 and away[1] / away[2] > 3.6, away
+
+
 def test_advection_order_at_least_two(oracle_lib):
     errs = []
     for n in (16, 32, 64):
@@ -393,7 +457,7 @@ def test_advection_order_at_least_two(oracle_lib):
         x = ((np.arange(n) + 0.5) / n)[None, None, :]
         q = np.broadcast_to(np.sin(2 * np.pi * x), (4, 4, n)).copy()
         U = np.full((4, 4, n), 2.0)
-        out = oracle_lib.advect_quick(p, U, 0 * U, 0 * U, q)
+        out = oracle_lib.advect(p, U, 0 * U, 0 * U, q)
         exact = -2.0 * 2 * np.pi * np.cos(2 * np.pi * x)
         errs.append(np.abs(out - exact).max())
     assert errs[0] / errs[1] > 3.6 and errs[1] / errs[2] > 3.6, errs
@@ -474,12 +538,14 @@ def _masses(p, state, oracle_lib):
     return d["mass_thl"], d["mass_qt"]
 
 
-def test_scalar_conservation_full_step(oracle_lib):
+@pytest.mark.parametrize("scheme", ["quick", "weno3"])
+def test_scalar_conservation_full_step(oracle_lib, scheme):
     """Sec. 2.4: domain integrals of scalars are conserved to machine
     precision without non-conservative sources (no surface flux, radiation
-    or subsidence), whatever the velocity and viscosity."""
+    or subsidence), whatever the velocity and viscosity, with either
+    advection scheme."""
     p = small("C1m", nx=12, ny=10, nz=16, shf=0.0, lhf=0.0, rad_F0=0.0,
-              poisson_tol=1e-6, poisson_scheme="chebyshev")
+              poisson_tol=1e-6, poisson_scheme="chebyshev", advection=scheme)
     st = li.initial_state(p)
     _random_velocity(p, st)
     m0 = _masses(p, st, oracle_lib)

@@ -48,6 +48,7 @@ enum {
 
 enum { LES_FP64 = 0, LES_FP32 = 1 };          /* storage / stencil precision */
 enum { LES_JACOBI = 0, LES_CHEBYSHEV = 1 };   /* Poisson sweep weighting */
+enum { LES_QUICK = 0, LES_WENO3 = 1 };       /* advection scheme */
 /* Initial guess of the pressure-correction solves:
  *   LES_GUESS_ZERO         phi_0 = 0 for every solve (the plain method)
  *   LES_GUESS_EXTRAPOLATE  first solve of a step: phi_0 = alpha0 (p^n -
@@ -90,7 +91,8 @@ typedef struct les_config {
   /* saturation vapour pressure anchor (Pa, K) and secant tolerance (K) */
   double e_tr, T_tr, satadj_tol;
   int32_t guess;                /* LES_GUESS_* */
-  int32_t reserved1;
+  int32_t advection;            /* LES_QUICK (Sec. 2.4) or LES_WENO3 (third-order
+                                   WENO faces, Lax-Friedrichs flux) */
 } les_config;
 
 /* Caller-owned device buffers.  u, v, w: velocity (m/s); thl: liquid-ice

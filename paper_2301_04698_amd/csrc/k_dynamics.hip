@@ -2,6 +2,7 @@
 // prediction equation) and momentum predictor (Sec. 2.4, momentum
 // prediction equation) on the collocated grid.  One thread per cell; the
 // stencil neighbourhoods are served by the L1/L2 caches.
+#include "les.h"
 #include "les_device.h"
 
 namespace lesmi {
@@ -26,6 +27,33 @@ __device__ __forceinline__ Cell cell_of(const Grid &g, int64_t q) {
 template <typename T>
 __device__ __forceinline__ T quick(T m, T qm1, T q0, T q1, T q2) {
   return m >= T(0) ? (T(6) * q0 + T(3) * q1 - qm1) / T(8) : (T(6) * q1 + T(3) * q0 - q2) / T(8);
+}
+
+// Third-order WENO face value at l+1/2 taken from the upwind side, from
+// a = q(l-1), b = q(l), c = q(l+1): candidates (-a + 3b)/2 and (b + c)/2,
+// linear weights 1/3 and 2/3, smoothness (b - a)^2 and (c - b)^2 (Jiang &
+// Shu), eps = 1e-6 max(a^2, b^2, c^2) + 1e-18 so the weights do not depend
+// on the field's units; the weight is formed without small squares in a
+// denominator.
+template <typename T>
+__device__ __forceinline__ T weno3(T a, T b, T c) {
+  const T eps = T(1e-6) * max(a * a, max(b * b, c * c)) + T(1e-18);
+  const T s0 = eps + (b - a) * (b - a), s1 = eps + (c - b) * (c - b);
+  const T w0 = (T(1) / T(3)) * s1 * s1 / ((T(1) / T(3)) * s1 * s1 + (T(2) / T(3)) * s0 * s0);
+  return w0 * (-a + T(3) * b) / T(2) + (T(1) - w0) * (b + c) / T(2);
+}
+
+// Advective flux m * (face value) through face l+1/2 of the five values
+// q(l-1) .. q(l+2): QUICK upwinded on m, or WENO3 with the Lax-Friedrichs
+// flux at the face speed |m| (the upwind-side reconstruction; zero on the
+// walls with m).
+template <typename T, bool WENO>
+__device__ __forceinline__ T face_flux(T m, T qm1, T q0, T q1, T q2) {
+  if (WENO) {
+    const T lo = weno3(qm1, q0, q1), hi = weno3(q2, q1, q0);
+    return T(0.5) * m * (lo + hi) - T(0.5) * fabs(m) * (hi - lo);
+  }
+  return m * quick(m, qm1, q0, q1, q2);
 }
 
 // Central derivative of component field f along axis ax at cell (i, j, k),
@@ -104,8 +132,8 @@ __device__ __forceinline__ FaceFlux<T> face_mass(const Grid &g, const Profiles<T
   return f;
 }
 
-// Flux-form QUICK advective tendency -div(U s) of a field s with parity par.
-template <typename T>
+// Flux-form advective tendency -div(U s) of a field s with parity par.
+template <typename T, bool WENO>
 __device__ __forceinline__ T advect(const Grid &g, const Dyn<T> &d, const FaceFlux<T> &f,
                                     const T *__restrict__ s, T par, const Cell &c) {
   T sx[5], sy[5], sz[5];
@@ -115,12 +143,12 @@ __device__ __forceinline__ T advect(const Grid &g, const Dyn<T> &d, const FaceFl
     sy[o + 2] = gload(s, g, c.i, c.j + o, c.k, par);
     sz[o + 2] = gload(s, g, c.i, c.j, c.k + o, par);
   }
-  const T fxp = f.xp * quick(f.xp, sx[1], sx[2], sx[3], sx[4]);
-  const T fxm = f.xm * quick(f.xm, sx[0], sx[1], sx[2], sx[3]);
-  const T fyp = f.yp * quick(f.yp, sy[1], sy[2], sy[3], sy[4]);
-  const T fym = f.ym * quick(f.ym, sy[0], sy[1], sy[2], sy[3]);
-  const T fzp = f.zp * quick(f.zp, sz[1], sz[2], sz[3], sz[4]);
-  const T fzm = f.zm * quick(f.zm, sz[0], sz[1], sz[2], sz[3]);
+  const T fxp = face_flux<T, WENO>(f.xp, sx[1], sx[2], sx[3], sx[4]);
+  const T fxm = face_flux<T, WENO>(f.xm, sx[0], sx[1], sx[2], sx[3]);
+  const T fyp = face_flux<T, WENO>(f.yp, sy[1], sy[2], sy[3], sy[4]);
+  const T fym = face_flux<T, WENO>(f.ym, sy[0], sy[1], sy[2], sy[3]);
+  const T fzp = face_flux<T, WENO>(f.zp, sz[1], sz[2], sz[3], sz[4]);
+  const T fzm = face_flux<T, WENO>(f.zm, sz[0], sz[1], sz[2], sz[3]);
   return -((fxp - fxm) * d.inv_dx + (fyp - fym) * d.inv_dy + (fzp - fzm) * d.inv_dz);
 }
 
@@ -165,7 +193,7 @@ __device__ __forceinline__ T diffuse(const Grid &g, const Dyn<T> &d, const FaceV
 
 // Phi^{k+1} = Phi^{n+1/2} + dt/rho0 [ -div(U^k Phi_mid) + div(rho0 nu/Pr grad Phi_mid)
 //            + rho0 w_sub dPhi_mid/dz + radiative heating (theta_l) + surface flux ]
-template <typename T>
+template <typename T, bool WENO>
 __global__ __launch_bounds__(kBlock) void scalar_kernel(
     Grid g, Dyn<T> d, Profiles<T> P, const T *__restrict__ u, const T *__restrict__ v,
     const T *__restrict__ w, const T *__restrict__ thm, const T *__restrict__ qtm,
@@ -180,14 +208,14 @@ __global__ __launch_bounds__(kBlock) void scalar_kernel(
   const T sub = r0 * P.wsub_t[c.k];
   const T scale = d.dt / r0;
   {
-    T tend = advect(g, d, mf, thm, T(1), c) + diffuse(g, d, fv, d.inv_pr, thm, c);
+    T tend = advect<T, WENO>(g, d, mf, thm, T(1), c) + diffuse(g, d, fv, d.inv_pr, thm, c);
     tend += rad[q];
     tend += sub * ((gload(thm, g, c.i, c.j, c.k + 1, T(1)) - gload(thm, g, c.i, c.j, c.k - 1, T(1))) * d.inv_2dz);
     if (c.k == 0) tend += d.sfc_thl * d.inv_dz;
     tho[q] = thh[q] + scale * tend;
   }
   {
-    T tend = advect(g, d, mf, qtm, T(1), c) + diffuse(g, d, fv, d.inv_sc, qtm, c);
+    T tend = advect<T, WENO>(g, d, mf, qtm, T(1), c) + diffuse(g, d, fv, d.inv_sc, qtm, c);
     tend += sub * ((gload(qtm, g, c.i, c.j, c.k + 1, T(1)) - gload(qtm, g, c.i, c.j, c.k - 1, T(1))) * d.inv_2dz);
     if (c.k == 0) tend += d.sfc_qt * d.inv_dz;
     qto[q] = qth[q] + scale * tend;
@@ -215,7 +243,7 @@ __device__ __forceinline__ T sgs_face(const Grid &g, const Dyn<T> &d, const T *c
 // U_hat = U^n + dt [ -rho0 grad_c(alpha0 p^k) + R^{n+1/2} ] with
 // R = -div(U_h (x) u_h) + div(rho0 sigma) + rho0 b e_z - f e_z x (U_h - rho0 u_g)
 //     - beta(z) (U_h - rho0 (u_g, v_g, 0)); stored as u_hat = U_hat / rho0.
-template <typename T>
+template <typename T, bool WENO>
 __global__ __launch_bounds__(kBlock) void momentum_kernel(
     Grid g, Dyn<T> d, Profiles<T> P, const T *__restrict__ uh, const T *__restrict__ vh,
     const T *__restrict__ wh, const T *__restrict__ un, const T *__restrict__ vn,
@@ -246,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void momentum_kernel(
   const T invd[3] = {d.inv_dx, d.inv_dy, d.inv_dz};
 #pragma unroll
   for (int cmp = 0; cmp < 3; ++cmp) {
-    T R = advect(g, d, mf, vel[cmp], T(-1), c);
+    T R = advect<T, WENO>(g, d, mf, vel[cmp], T(-1), c);
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const int di = ax == 0, dj = ax == 1, dk = ax == 2;
@@ -276,16 +304,24 @@ void launch_scalar_update(const Grid &g, const Dyn<T> &d, const Profiles<T> &P, 
                           const T *v, const T *w, const T *thl_mid, const T *qt_mid,
                           const T *thl_half, const T *qt_half, const T *nu, const T *rad,
                           T *thl_out, T *qt_out, hipStream_t s) {
-  scalar_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g, d, P, u, v, w, thl_mid, qt_mid, thl_half,
-                                                        qt_half, nu, rad, thl_out, qt_out);
+  if (d.advection == LES_WENO3)
+    scalar_kernel<T, true><<<blocks_for(g.n), kBlock, 0, s>>>(
+        g, d, P, u, v, w, thl_mid, qt_mid, thl_half, qt_half, nu, rad, thl_out, qt_out);
+  else
+    scalar_kernel<T, false><<<blocks_for(g.n), kBlock, 0, s>>>(
+        g, d, P, u, v, w, thl_mid, qt_mid, thl_half, qt_half, nu, rad, thl_out, qt_out);
 }
 
 template <typename T>
 void launch_momentum(const Grid &g, const Dyn<T> &d, const Profiles<T> &P, const T *uh,
                      const T *vh, const T *wh, const T *un, const T *vn, const T *wn, const T *p,
                      const T *b, const T *nu, T *uo, T *vo, T *wo, hipStream_t s) {
-  momentum_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g, d, P, uh, vh, wh, un, vn, wn, p, b, nu,
-                                                          uo, vo, wo);
+  if (d.advection == LES_WENO3)
+    momentum_kernel<T, true><<<blocks_for(g.n), kBlock, 0, s>>>(g, d, P, uh, vh, wh, un, vn, wn,
+                                                                p, b, nu, uo, vo, wo);
+  else
+    momentum_kernel<T, false><<<blocks_for(g.n), kBlock, 0, s>>>(g, d, P, uh, vh, wh, un, vn, wn,
+                                                                 p, b, nu, uo, vo, wo);
 }
 
 #define LES_INST(T)                                                                              \

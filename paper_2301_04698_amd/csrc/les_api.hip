@@ -76,6 +76,8 @@ int validate(const les_config *c) {
   if (!(1.0 - c->g * top / (c->cpd * c->theta0) > 0))
     return fail(LES_ERR_ARG, "domain top above the adiabatic atmosphere's height");
   if (c->sponge_frac < 0 || c->sponge_frac > 1) return fail(LES_ERR_ARG, "sponge_frac must be in [0, 1]");
+  if (c->advection != LES_QUICK && c->advection != LES_WENO3)
+    return fail(LES_ERR_ARG, "unknown advection scheme %d", c->advection);
   if (c->guess < LES_GUESS_ZERO || c->guess > LES_GUESS_LEARNED)
     return fail(LES_ERR_ARG, "unknown guess mode %d", c->guess);
   return LES_OK;
@@ -219,6 +221,7 @@ View<T> view_of(const les_handle *h) {
   const double delta = std::cbrt(c.dx * c.dy * c.dz);
   d.smag_l2 = (T)((c.cs * delta) * (c.cs * delta));
   d.pr = (T)c.Pr;
+  d.advection = c.advection;
   V.u = (T *)h->buf.u;
   V.v = (T *)h->buf.v;
   V.w = (T *)h->buf.w;

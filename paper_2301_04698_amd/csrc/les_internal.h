@@ -41,6 +41,7 @@ struct Dyn {
   T sfc_thl, sfc_qt;   // surface flux per unit area (rho0-weighted) into the lowest cell
   T smag_l2;           // (c_s Delta)^2
   T pr;                // turbulent Prandtl number of the buoyancy factor
+  int advection;       // LES_QUICK or LES_WENO3
 };
 
 // Device-resident control block of one Poisson solve.  Sweep kernels read

@@ -19,6 +19,8 @@ LES_OK, LES_WARN_NOT_CONVERGED = 0, 1
 LES_ERR_ARG, LES_ERR_HIP, LES_ERR_NONFINITE, LES_ERR_STATE = -1, -2, -3, -4
 LES_FP64, LES_FP32 = 0, 1
 LES_JACOBI, LES_CHEBYSHEV = 0, 1
+LES_QUICK, LES_WENO3 = 0, 1
+ADVECTION = {"quick": LES_QUICK, "weno3": LES_WENO3}
 LES_GUESS_ZERO, LES_GUESS_EXTRAPOLATE, LES_GUESS_PREVIOUS, LES_GUESS_LEARNED = 0, 1, 2, 3
 GUESS_MODES = {"zero": LES_GUESS_ZERO, "extrapolate": LES_GUESS_EXTRAPOLATE,
                "previous": LES_GUESS_PREVIOUS, "learned": LES_GUESS_LEARNED}
@@ -51,7 +53,7 @@ class LesConfig(C.Structure):
         ("wsub_div", C.c_double), ("sponge_frac", C.c_double), ("sponge_max", C.c_double),
         ("rad_F0", C.c_double), ("rad_kappa", C.c_double),
         ("e_tr", C.c_double), ("T_tr", C.c_double), ("satadj_tol", C.c_double),
-        ("guess", C.c_int32), ("reserved1", C.c_int32),
+        ("guess", C.c_int32), ("advection", C.c_int32),
     ]
 
 
@@ -153,10 +155,11 @@ def make_config(p: dict) -> LesConfig:
     """les_config from a full workload parameter dict."""
     c = default_config()
     for name, ctype in LesConfig._fields_:
-        if name == "reserved1":
-            continue
         if name == "sweeps_per_launch":
             c.sweeps_per_launch = int(p.get("sweeps_per_launch", 0))
+        elif name == "advection":
+            v = p.get("advection", "quick")
+            c.advection = ADVECTION[v] if isinstance(v, str) else int(v)
         elif name == "guess":
             v = p.get("guess", "zero")
             c.guess = GUESS_MODES[v] if isinstance(v, str) else int(v)

@@ -230,6 +230,25 @@ def test_step_guess_fp32_converges(gpu):
             assert rel_anom(out[g][k], out["zero"][k]) <= 1e-3, (g, k)
 
 
+def test_step_weno3_fp64_matches_oracle(gpu, oracle_lib):
+    """The paper's alternative advection (WENO3 faces, Lax-Friedrichs flux)
+    for scalars and momentum: all physics, 2 steps, FP64 bar."""
+    p = li.workload("C1m", poisson_tol=1e-9, poisson_scheme="chebyshev", advection="weno3")
+    st0 = with_velocity_noise(p, li.initial_state(p), 0.3, 8)
+    errs, *_ = _compare_step(gpu, oracle_lib, p, st0, 2, 1e-11)
+    for k, e in errs.items():
+        assert e <= 1e-11, (k, e, errs)
+
+
+def test_step_weno3_fp32_matches_oracle(gpu, oracle_lib):
+    p = li.workload("C1m", nx=40, ny=24, nz=32, precision="fp32", poisson_tol=1e-6,
+                    poisson_scheme="chebyshev", advection="weno3")
+    st0 = with_velocity_noise(p, li.initial_state(p), 0.3, 9)
+    errs, *_ = _compare_step(gpu, oracle_lib, p, st0, 1, 1e-5)
+    for k, e in errs.items():
+        assert e <= 1e-5, (k, e, errs)
+
+
 def test_step_rest_state_steady(gpu):
     import torch
     p = li.workload("C1", nx=8, ny=8, nz=8, ug=0.0, vg=0.0, noise_thl=0.0, thl_ml=290.0,
@@ -243,10 +262,11 @@ def test_step_rest_state_steady(gpu):
     assert all(r["sweeps"] == 0 for r in recs)
 
 
-def test_conservation_gpu(gpu):
+@pytest.mark.parametrize("scheme", ["quick", "weno3"])
+def test_conservation_gpu(gpu, scheme):
     """Scalar domain integrals conserved without sources (FP64 path)."""
     p = li.workload("C1m", shf=0.0, lhf=0.0, rad_F0=0.0, poisson_tol=1e-6,
-                    poisson_scheme="chebyshev")
+                    poisson_scheme="chebyshev", advection=scheme)
     st0 = with_velocity_noise(p, li.initial_state(p), 0.5, 2)
     sim = gpu.LES(p, st0)
     d0 = sim.diagnostics()

@@ -78,6 +78,8 @@ _BASE = dict(
     sweeps_per_launch=0,       # library launch shape only (0: its default)
     guess="zero",              # initial guess of the solves
     advection="quick",         # "quick" or "weno3" (WENO3 with Lax-Friedrichs flux)
+    wall="no_slip",            # u, v at z = 0, H: "no_slip" or "free_slip"
+    nu_const=0.0,              # > 0: uniform kinematic viscosity (m^2/s), no SGS model
     # forcing
     ug=7.0, vg=-5.0,
     shf=0.0, lhf=0.0,          # surface sensible / latent heat flux, W/m^2
@@ -87,7 +89,12 @@ _BASE = dict(
     # saturation vapour pressure anchor (triple point) and secant stopping
     e_tr=611.657, T_tr=273.16,
     satadj_tol=1e-10, satadj_maxit=20,
-    # initial profile
+    # initial state: "cloud_layer" (two-layer profile below) or "bubble"
+    init="cloud_layer",
+    # bubble: uniform theta_bg plus amp * cos^2(pi L / 2) for L <= 1,
+    # L^2 = ((x - Lx/2) / xr)^2 + ((z - zc) / zr)^2, dry and at rest
+    theta_bg=300.0, bubble_amp=0.0, bubble_xr=1.0, bubble_zr=1.0, bubble_zc=0.0,
+    # two-layer profile
     z_inv=800.0, thl_ml=289.0, qt_ml=9.0e-3, dthl_inv=8.0, qt_ft=1.5e-3,
     noise_z=200.0, noise_thl=0.1, noise_qt=0.0,
     seed=1,
@@ -133,6 +140,43 @@ WORKLOADS = {
                seed=5),
 }
 
+# Dry validation cases (Sec. 3): two-dimensional (ny = 1) at uniform
+# resolution h metres, the name carrying h.
+#   DC<h>: density current, 51.2 km x 6.4 km, -15 K bubble of radii 4 km x
+#          2 km centred 3 km up, uniform nu = 10 m^2/s, to t = 900 s.
+#   RB<h>: rising bubble, 20 km x 10 km, +2 K bubble of radius 2 km centred
+#          2 km up, uniform nu = 1 m^2/s, to t = 1000 s.
+# Both: theta = 300 K background (also the reference state's theta0), no
+# moisture, Coriolis, sponge, radiation or surface fluxes; free-slip walls;
+# dt = h / 200 m/s (Courant number about 0.2 at the cases' peak speeds).
+# FP64: their pressure correction is smooth on the grid scale, so FP32
+# storage of it alone leaves a relative residual above the 1e-6 tolerance
+# (5e-5 at 200 m, 1e-3 at 50 m for the density current).
+DRY_CASES = {
+    "DC": dict(Lx=51200.0, H=6400.0, bubble_amp=-15.0, bubble_xr=4000.0, bubble_zr=2000.0,
+               bubble_zc=3000.0, nu_const=10.0, t_end=900.0),
+    "RB": dict(Lx=20000.0, H=10000.0, bubble_amp=2.0, bubble_xr=2000.0, bubble_zr=2000.0,
+               bubble_zc=2000.0, nu_const=1.0, t_end=1000.0),
+}
+DRY_RESOLUTIONS = (400, 200, 100, 50, 25, 10)
+
+
+def _dry_workload(case: str, h: int) -> dict:
+    d = DRY_CASES[case]
+    return dict(nx=int(round(d["Lx"] / h)), ny=1, nz=int(round(d["H"] / h)),
+                dx=float(h), dy=float(h), dz=float(h), dt=h / 200.0,
+                poisson_scheme="chebyshev", poisson_tol=1e-6, poisson_max_sweeps=100000,
+                precision="fp64", init="bubble", theta0=300.0, theta_bg=300.0,
+                bubble_amp=d["bubble_amp"], bubble_xr=d["bubble_xr"],
+                bubble_zr=d["bubble_zr"], bubble_zc=d["bubble_zc"],
+                nu_const=d["nu_const"], wall="free_slip", ug=0.0, vg=0.0, fcor=0.0,
+                sponge_max=0.0, noise_thl=0.0, noise_qt=0.0)
+
+
+for _case in DRY_CASES:
+    for _h in DRY_RESOLUTIONS:
+        WORKLOADS[f"{_case}{_h}"] = _dry_workload(_case, _h)
+
 
 def workload(name: str, **overrides) -> dict:
     """Full parameter dict of a named workload, with optional overrides."""
@@ -155,12 +199,27 @@ def cell_heights(p: dict) -> np.ndarray:
 def initial_state(p: dict) -> dict:
     """Initial fields as float64 arrays of shape (nz, ny, nx), x fastest.
 
-    theta_l = thl_ml and q_t = qt_ml below z_inv; above it theta_l jumps by
+    init == "bubble": theta_l = theta_bg + bubble_amp cos^2(pi L / 2) where
+    L <= 1 (L as in the parameters above, x measured from the domain centre
+    Lx/2, which is a cell face when nx is even), q_t = 0, at rest.
+
+    init == "cloud_layer": theta_l = thl_ml and q_t = qt_ml below z_inv; above it theta_l jumps by
     dthl_inv and then rises as (z - z_inv)^(1/3) K (z in m), q_t = qt_ft.
     Uniform noise of half-width noise_thl / noise_qt below noise_z.
     Velocity starts at the background wind (ug, vg, 0); p' starts at 0.
     """
     nx, ny, nz = p["nx"], p["ny"], p["nz"]
+    shape = (nz, ny, nx)
+    if p["init"] == "bubble":
+        x = (np.arange(nx, dtype=np.float64) + 0.5) * p["dx"] - 0.5 * nx * p["dx"]
+        zc = cell_heights(p) - p["bubble_zc"]
+        L = np.sqrt((x[None, :] / p["bubble_xr"]) ** 2 + (zc[:, None] / p["bubble_zr"]) ** 2)
+        pert = np.where(L <= 1.0, p["bubble_amp"] * np.cos(0.5 * np.pi * L) ** 2, 0.0)
+        thl = p["theta_bg"] + np.broadcast_to(pert[:, None, :], shape)
+        return dict(u=np.full(shape, p["ug"]), v=np.full(shape, p["vg"]), w=np.zeros(shape),
+                    thl=np.ascontiguousarray(thl), qt=np.zeros(shape), p=np.zeros(shape))
+    if p["init"] != "cloud_layer":
+        raise ValueError(f"unknown init {p['init']!r}")
     z = cell_heights(p)[:, None, None] * np.ones((1, ny, nx))
     above = z >= p["z_inv"]
     thl = np.where(above, p["thl_ml"] + p["dthl_inv"]
@@ -174,7 +233,6 @@ def initial_state(p: dict) -> dict:
     if p["noise_qt"] > 0:
         r = uniform01(p["seed"], FIELD_QT, idx)
         qt = qt + np.where(low, p["noise_qt"] * (2.0 * r - 1.0), 0.0)
-    shape = (nz, ny, nx)
     return dict(
         u=np.full(shape, p["ug"]),
         v=np.full(shape, p["vg"]),

@@ -19,6 +19,7 @@ SCHEMES = {"jacobi": 0, "chebyshev": 1}
 
 GUESSES = {"zero": 0, "extrapolate": 1, "previous": 2}
 ADVECTION = {"quick": 0, "weno3": 1}
+WALLS = {"no_slip": 0, "free_slip": 1}
 
 
 class OCfg(C.Structure):
@@ -27,6 +28,7 @@ class OCfg(C.Structure):
         ("poisson_scheme", C.c_int32), ("poisson_check_every", C.c_int32),
         ("poisson_max_sweeps", C.c_int32), ("satadj_maxit", C.c_int32),
         ("guess", C.c_int32), ("advection", C.c_int32),
+        ("wall", C.c_int32), ("reserved", C.c_int32),
         ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("dt", C.c_double),
         ("poisson_tol", C.c_double), ("jacobi_omega", C.c_double),
         ("p00", C.c_double), ("theta0", C.c_double), ("Rd", C.c_double), ("Rv", C.c_double),
@@ -37,6 +39,7 @@ class OCfg(C.Structure):
         ("wsub_div", C.c_double), ("sponge_frac", C.c_double), ("sponge_max", C.c_double),
         ("rad_F0", C.c_double), ("rad_kappa", C.c_double),
         ("e_tr", C.c_double), ("T_tr", C.c_double), ("satadj_tol", C.c_double),
+        ("nu_const", C.c_double),
     ]
 
 
@@ -107,6 +110,13 @@ def make_cfg(p: dict) -> OCfg:
             if v not in ADVECTION:
                 raise ValueError(f"unknown advection scheme {v!r}; known: {sorted(ADVECTION)}")
             c.advection = ADVECTION[v]
+        elif name == "wall":
+            v = p.get("wall", "no_slip")
+            if v not in WALLS:
+                raise ValueError(f"unknown wall condition {v!r}; known: {sorted(WALLS)}")
+            c.wall = WALLS[v]
+        elif name == "reserved":
+            c.reserved = 0
         else:
             setattr(c, name, ctype(p[name]).value)
     return c

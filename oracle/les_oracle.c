@@ -36,9 +36,10 @@ static int wrapi(int i, int n) {
  * x and y are periodic; across the rigid walls at z = 0 and z = H the ghost
  * mirrors the interior (k = -1 -> 0, k = -2 -> 1, k = nz -> nz-1, ...) times
  * `parity`: +1 for scalars, pressure, viscosity and buoyancy (zero normal
- * gradient: homogeneous Neumann, Sec. 2.4), -1 for velocity / momentum
- * components (no-slip, zero wall mass flux; the paper's lid is no-slip and
- * zero-flux, Sec. 4, the surface is treated the same way). */
+ * gradient: homogeneous Neumann, Sec. 2.4), -1 for w (zero wall mass flux)
+ * and, with no-slip walls, for u and v (the paper's lid is no-slip and
+ * zero-flux, Sec. 4, the surface is treated the same way); with free-slip
+ * walls u and v are even (zero wall stress), see vpar. */
 static double at(const ocfg *c, const double *f, int i, int j, int k, double parity) {
   i = wrapi(i, c->nx);
   j = wrapi(j, c->ny);
@@ -56,14 +57,23 @@ static double prof(const ocfg *c, const double *a, int k) {
 
 static const int UNIT[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
 
+/* Wall parity of velocity component a.  READING (validation cases, Sec. 3):
+ * the density current and rising bubble keep the free-slip rigid walls of
+ * their original definitions (the paper replaces only the horizontal
+ * boundaries by periodic ones), so u and v mirror evenly there; w is odd
+ * under either condition. */
+static double vpar(const ocfg *c, int a) { return a < 2 && c->wall == 1 ? 1.0 : -1.0; }
+
 static double spacing(const ocfg *c, int axis) {
   return axis == 0 ? c->dx : (axis == 1 ? c->dy : c->dz);
 }
 
 static int check_cfg(const ocfg *c) {
-  if (!c || c->nx < 4 || c->ny < 4 || c->nz < 4) return -1;
+  if (!c || c->nx < 1 || c->ny < 1 || c->nz < 4) return -1;
   if (!(c->dx > 0) || !(c->dy > 0) || !(c->dz > 0) || !(c->dt > 0)) return -1;
   if (c->advection != 0 && c->advection != 1) return -1;
+  if (c->wall != 0 && c->wall != 1) return -1;
+  if (!(c->nu_const >= 0.0) || c->nu_const > 1e6) return -1;
   return 0;
 }
 
@@ -246,8 +256,8 @@ static void grad_u(const ocfg *c, const double *u, const double *v, const double
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) {
       const int *e = UNIT[b];
-      double up = at(c, vel[a], i + e[0], j + e[1], k + e[2], -1.0);
-      double dn = at(c, vel[a], i - e[0], j - e[1], k - e[2], -1.0);
+      double up = at(c, vel[a], i + e[0], j + e[1], k + e[2], vpar(c, a));
+      double dn = at(c, vel[a], i - e[0], j - e[1], k - e[2], vpar(c, a));
       G[a][b] = (up - dn) / (2.0 * spacing(c, b));
     }
 }
@@ -255,10 +265,17 @@ static void grad_u(const ocfg *c, const double *u, const double *v, const double
 /* Smagorinsky-Lilly viscosity nu_t = (c_s Delta)^2 f_B S (Sec. 2.3) with
  * Delta = (dx dy dz)^(1/3).  READING: S = sqrt(2 S_ij S_ij); the buoyancy
  * factor is f_B = sqrt(clamp(1 - N^2 / (Pr S^2), 0, 1)) with
- * N^2 = d b / d z (central), and nu_t = 0 where S = 0. */
+ * N^2 = d b / d z (central), and nu_t = 0 where S = 0.
+ * The validation cases (Sec. 3) replace the model by a uniform kinematic
+ * viscosity: nu = nu_const everywhere when nu_const > 0 (scalars then
+ * diffuse with nu/Pr and nu/Sc like any other viscosity). */
 int oracle_sgs_nu(const ocfg *c, const double *u, const double *v, const double *w,
                   const double *b, double *nu) {
   if (check_cfg(c)) return -1;
+  if (c->nu_const > 0.0) {
+    for (size_t q = 0; q < ncell(c); ++q) nu[q] = c->nu_const;
+    return 0;
+  }
   double delta = cbrt(c->dx * c->dy * c->dz);
   double l2 = (c->cs * delta) * (c->cs * delta);
   for (int k = 0; k < c->nz; ++k)
@@ -419,7 +436,8 @@ int oracle_sgs_momentum(const ocfg *c, const double *nu, const double *u, const 
             double nuf = 0.5 * (at(c, nu, li, lj, lk, 1.0) + at(c, nu, ri, rj, rk, 1.0));
             double rf = ax == 2 ? 0.5 * (prof(c, P.rho0, lk) + prof(c, P.rho0, rk)) : P.rho0[k];
             for (int comp = 0; comp < 3; ++comp) {
-              double dij = (at(c, vel[comp], ri, rj, rk, -1.0) - at(c, vel[comp], li, lj, lk, -1.0)) / d;
+              double dij = (at(c, vel[comp], ri, rj, rk, vpar(c, comp)) -
+                            at(c, vel[comp], li, lj, lk, vpar(c, comp))) / d;
               double dji = 0.5 * (Gl[ax][comp] + Gr[ax][comp]);
               F[side][comp] = rf * nuf * (dij + dji);
             }
@@ -573,7 +591,8 @@ static void neighbour_sum(const ocfg *c, const double *phi, double *nb) {
 /* Extreme nonzero eigenvalues of -D^{-1} L for the compact Laplacian L with
  * periodic x, y and mirror-Neumann z, D = 2/dx^2 + 2/dy^2 + 2/dz^2:
  * periodic axis (2 - 2 cos(2 pi m / N)) / Delta^2, mirror axis
- * (2 - 2 cos(pi m / N)) / Delta^2, m = 0 .. N-1. */
+ * (2 - 2 cos(pi m / N)) / Delta^2, m = 0 .. N-1.  A periodic axis of one
+ * cell has only its m = 0 mode and no smallest nonzero eigenvalue. */
 int oracle_jacobi_bounds(const ocfg *c, double *mu_min, double *mu_max) {
   if (check_cfg(c)) return -1;
   double d = 2.0 / (c->dx * c->dx) + 2.0 / (c->dy * c->dy) + 2.0 / (c->dz * c->dz);
@@ -583,8 +602,9 @@ int oracle_jacobi_bounds(const ocfg *c, double *mu_min, double *mu_max) {
   double lxm = (2.0 - 2.0 * cos(2.0 * PI * (c->nx / 2) / c->nx)) / (c->dx * c->dx);
   double lym = (2.0 - 2.0 * cos(2.0 * PI * (c->ny / 2) / c->ny)) / (c->dy * c->dy);
   double lzm = (2.0 - 2.0 * cos(PI * (c->nz - 1) / c->nz)) / (c->dz * c->dz);
-  double mn = lx1 < ly1 ? lx1 : ly1;
-  mn = mn < lz1 ? mn : lz1;
+  double mn = lz1;
+  if (c->nx > 1 && lx1 < mn) mn = lx1;
+  if (c->ny > 1 && ly1 < mn) mn = ly1;
   *mu_min = mn / d;
   *mu_max = (lxm + lym + lzm) / d;
   return 0;
@@ -796,7 +816,7 @@ int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, dou
       oracle_sgs_nu(c, S.uh[0], S.uh[1], S.uh[2], S.b_h, S.nu_m);
       oracle_sgs_momentum(c, S.nu_m, S.uh[0], S.uh[1], S.uh[2], S.sg[0], S.sg[1], S.sg[2]);
       for (int a = 0; a < 3; ++a) {
-        oracle_advect(c, S.Uh[0], S.Uh[1], S.Uh[2], S.uh[a], -1.0, S.R[a]);
+        oracle_advect(c, S.Uh[0], S.Uh[1], S.Uh[2], S.uh[a], vpar(c, a), S.R[a]);
         for (size_t q = 0; q < n; ++q) S.R[a][q] += S.sg[a][q];
       }
       for (int k = 0; k < c->nz; ++k)

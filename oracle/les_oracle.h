@@ -23,6 +23,8 @@ typedef struct ocfg {
   int32_t satadj_maxit;
   int32_t guess;               /* initial guess of the solves, see oracle_step */
   int32_t advection;           /* 0 QUICK, 1 WENO3 with Lax-Friedrichs flux */
+  int32_t wall;                /* u, v at z = 0, H: 0 no-slip (odd mirror), 1 free-slip (even) */
+  int32_t reserved;
   double dx, dy, dz, dt;
   double poisson_tol;          /* ||rhs - L phi||_2 <= tol * ||rhs||_2 */
   double jacobi_omega;         /* 0 = closed-form optimum */
@@ -32,6 +34,7 @@ typedef struct ocfg {
   double ug, vg, shf, lhf, wsub_div, sponge_frac, sponge_max, rad_F0, rad_kappa;
   /* saturation vapour pressure anchor and secant stopping */
   double e_tr, T_tr, satadj_tol;
+  double nu_const;             /* > 0: uniform kinematic viscosity in place of the SGS model */
 } ocfg;
 
 typedef struct osolve {        /* one Poisson solve */

@@ -742,3 +742,108 @@ def test_guess_modes_change_sweeps_not_solution(oracle_lib):
     assert all(r["guess"] in (1, 2) for r in rp[K:])
     with pytest.raises(ValueError):
         oracle_lib.make_cfg(dict(p0, guess="learned"))
+
+
+# ------------------------------- validation-case options (Sec. 3): uniform
+# viscosity and free-slip walls, pinned by exact discrete decay rates
+
+def _amp(x, K):
+    """Amplification per step of K predictor-corrector sub-iterations for
+    dq/dt = (x/dt) q (the recurrence of the inertial-oscillation pin)."""
+    a = 1 + x
+    for _ in range(K - 1):
+        a = 1 + x * (1 + a) / 2
+    return a
+
+
+def _quiet(**kw):
+    """g = 0 (uniform reference state, no buoyancy), no Coriolis, sponge,
+    forcing or noise, uniform viscosity: momentum and scalars only diffuse."""
+    base = dict(nx=4, ny=4, nz=16, dx=40.0, dy=40.0, dz=10.0, dt=5.0, g=0.0, fcor=0.0,
+                ug=0.0, vg=0.0, sponge_max=0.0, noise_thl=0.0, nu_const=2.0,
+                poisson_tol=1e-10)
+    base.update(kw)
+    return small(**base)
+
+
+@pytest.mark.parametrize("wall", ["free_slip", "no_slip"])
+def test_wall_condition_shear_mode_decay(oracle_lib, wall):
+    """A horizontally uniform shear flow u(z) with w = 0 is divergence free and
+    not advected, so it only diffuses.  Free slip mirrors u evenly across the
+    walls, whose discrete eigenmodes are cos(pi m (k + 1/2) / nz); no slip
+    mirrors it oddly, with modes sin(pi m (k + 1/2) / nz); both m = 1 modes
+    have the eigenvalue -(2 - 2 cos(pi / nz)) / dz^2.  Free slip also keeps
+    the column mean (zero wall stress).  A parity mistake in any stress or
+    advection term changes the decay or moves the mean."""
+    p = _quiet(wall=wall, nu_const=5.0)
+    nz, K = p["nz"], p["n_subiter"]
+    kk = np.arange(nz) + 0.5
+    mode = np.cos(np.pi * kk / nz) if wall == "free_slip" else np.sin(np.pi * kk / nz)
+    mean = 1.5 if wall == "free_slip" else 0.0
+    st = _column_state(p, 0.0, 0.0)
+    st["u"][:] = (mean + 2.0 * mode)[:, None, None]
+    lam = (2 - 2 * np.cos(np.pi / nz)) / p["dz"] ** 2
+    x = -p["nu_const"] * lam * p["dt"]
+    nsteps = 20
+    oracle_lib.step(p, st, nsteps=nsteps)
+    expect = mean + 2.0 * mode * _amp(x, K) ** nsteps
+    np.testing.assert_allclose(st["u"][:, 1, 2], expect, rtol=1e-12, atol=1e-13)
+    assert _amp(x, K) ** nsteps < 0.9  # the decay is large enough to see
+    assert np.abs(st["w"]).max() == 0.0 and np.abs(st["v"]).max() == 0.0
+
+
+def test_uniform_viscosity_horizontal_modes(oracle_lib):
+    """With nu uniform and free-slip walls (no-slip walls would add their
+    stress to the z-uniform v), a mode cos(2 pi x / Lx) of v (divergence
+    free), of theta_l and of q_t decays with the periodic eigenvalue
+    -(2 - 2 cos(2 pi / nx)) / dx^2 times nu, nu / Pr and nu / Sc
+    respectively (Sc set apart from Pr so a swapped number shows)."""
+    p = _quiet(nx=16, nz=4, dx=10.0, dy=10.0, Sc=0.7, wall="free_slip")
+    nx, K = p["nx"], p["n_subiter"]
+    c = np.cos(2 * np.pi * (np.arange(nx) + 0.5) / nx)[None, None, :]
+    st = _column_state(p, 0.0, 0.0)
+    st["v"] = np.broadcast_to(3.0 * c, st["v"].shape).copy()
+    st["thl"] = p["theta0"] + np.broadcast_to(0.5 * c, st["thl"].shape)
+    st["qt"] = 1e-3 + np.broadcast_to(1e-4 * c, st["qt"].shape)
+    lam = (2 - 2 * np.cos(2 * np.pi / nx)) / p["dx"] ** 2
+    nsteps = 10
+    oracle_lib.step(p, st, nsteps=nsteps)
+    for f, base, a, kappa in (("v", 0.0, 3.0, p["nu_const"]),
+                              ("thl", p["theta0"], 0.5, p["nu_const"] / p["Pr"]),
+                              ("qt", 1e-3, 1e-4, p["nu_const"] / p["Sc"])):
+        amp = _amp(-kappa * lam * p["dt"], K) ** nsteps
+        assert amp < 0.95
+        np.testing.assert_allclose(st[f] - base, a * amp * np.broadcast_to(c, st[f].shape),
+                                   rtol=0, atol=abs(a) * 1e-11, err_msg=f)
+
+
+@pytest.mark.parametrize("case", ["DC400", "RB400"])
+def test_validation_case_mirror_symmetry(oracle_lib, case):
+    """The density-current and rising-bubble initial states are mirror
+    symmetric about x = Lx/2 (a cell face), and the equations are invariant
+    under x -> -x with u -> -u, so theta_l and w stay symmetric and u
+    antisymmetric.  The QUICK upwind side flips with the sign of the face
+    flux; a stencil oriented the same way for both signs breaks this."""
+    p = small(case, precision="fp64", poisson_tol=1e-9)
+    st = li.initial_state(p)
+    oracle_lib.step(p, st, nsteps=4)
+    t, u, w = st["thl"][:, 0, :], st["u"][:, 0, :], st["w"][:, 0, :]
+    assert np.abs(w).max() > 0.1
+    dev = p["theta_bg"] - t
+    assert np.abs(dev - dev[:, ::-1]).max() <= 1e-12 * np.abs(dev).max()
+    assert np.abs(u + u[:, ::-1]).max() <= 1e-12 * np.abs(u).max()
+    assert np.abs(w - w[:, ::-1]).max() <= 1e-12 * np.abs(w).max()
+
+
+@pytest.mark.parametrize("case,sign", [("DC400", -1), ("RB400", 1)])
+def test_validation_case_bubble_moves_with_its_buoyancy(oracle_lib, case, sign):
+    """A cold bubble starts sinking and a warm one rising: w at the bubble
+    centre has the sign of the perturbation and the flow converges (cold)
+    or diverges (warm) below it."""
+    p = small(case, precision="fp64", poisson_tol=1e-9)
+    st = li.initial_state(p)
+    oracle_lib.step(p, st, nsteps=4)
+    kc = int(p["bubble_zc"] / p["dz"])
+    ic = p["nx"] // 2
+    assert sign * st["w"][kc, 0, ic] > 0
+    assert sign * st["w"][kc, 0, ic] > 0.5 * sign * st["w"][:, 0, :].max() * sign

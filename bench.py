@@ -70,6 +70,9 @@ def parse():
     ap.add_argument("--guess-weights", default=GUESS_WEIGHTS,
                     help="trained guess network for the learned form ('' to skip it)")
     ap.add_argument("--guess-alpha", type=float, default=0.1)
+    ap.add_argument("--advection", choices=("quick", "weno3"), default="quick",
+                    help="face-value scheme of the advection (QUICK, or third-order WENO with a "
+                         "Lax-Friedrichs flux)")
     return ap.parse_args()
 
 
@@ -127,7 +130,10 @@ def sweep_kernel_name(p, S):
     if S != 1:
         return f"sweep2_kernel<{T}, 8, {cheb}, false>"
     streamed = 4.0 * p["nx"] * p["ny"] * p["nz"] * es > 192e6
-    return f"sweep1_kernel<{T}, {16 if streamed else 4}, {cheb}, false, {'true' if streamed else 'false'}>"
+    ty = 16 if streamed else 4
+    if p["ny"] < ty:
+        ty = 1 if p["ny"] < 4 else 4
+    return f"sweep1_kernel<{T}, {ty}, {cheb}, false, {'true' if streamed else 'false'}>"
 
 
 def sweep_bytes_per_cell(p):
@@ -146,7 +152,7 @@ def cpu_baseline(p, sweeps_per_step, crop):
 
     nfull = p["nx"] * p["ny"] * p["nz"]
     pc = dict(p)
-    pc["nx"] = pc["ny"] = min(crop, p["nx"])
+    pc["nx"], pc["ny"] = min(crop, p["nx"]), min(crop, p["ny"])
     K = p["n_subiter"]
     st = li.initial_state(pc)
     t0 = time.perf_counter()
@@ -238,7 +244,8 @@ def main():
         return run_sweeps(args)
     if args.mode == "copy":
         return run_copy(args)
-    p = li.workload(args.workload, sweeps_per_launch=args.sweeps_per_launch)
+    p = li.workload(args.workload, sweeps_per_launch=args.sweeps_per_launch,
+                    advection=args.advection)
     ncell = p["nx"] * p["ny"] * p["nz"]
     sim = les.LES(p, li.initial_state(p), device="cuda:0")
 
@@ -285,7 +292,7 @@ def main():
             "workload": (f"synthetic stratocumulus LES step, {p['nx']}x{p['ny']}x{p['nz']} cells, "
                          f"{p['dx']:g}x{p['dy']:g}x{p['dz']:g} m, dt {p['dt']:g} s, "
                          f"{p['poisson_scheme']} Poisson to rel. residual {p['poisson_tol']:g}, "
-                         f"K={K}"),
+                         f"K={K}, {p['advection']} advection"),
             "grid": [p["nx"], p["ny"], p["nz"]],
             "precision": p["precision"],
         },
@@ -311,7 +318,9 @@ def main():
                      if bytes_launch < 256e6 else "working set exceeds the 256 MB Infinity Cache"),
         },
     }
-    if args.guess_weights and os.path.exists(args.guess_weights):
+    if p["init"] != "cloud_layer":
+        out["learned"] = None  # the guess network was trained on the cloud-layer workload
+    elif args.guess_weights and os.path.exists(args.guess_weights):
         out["learned"] = learned_form(p, args, sweeps_step, st["poisson_seconds"] / args.steps,
                                       value)
     else:

@@ -49,6 +49,7 @@ enum {
 enum { LES_FP64 = 0, LES_FP32 = 1 };          /* storage / stencil precision */
 enum { LES_JACOBI = 0, LES_CHEBYSHEV = 1 };   /* Poisson sweep weighting */
 enum { LES_QUICK = 0, LES_WENO3 = 1 };       /* advection scheme */
+enum { LES_NO_SLIP = 0, LES_FREE_SLIP = 1 };  /* u, v at the walls z = 0, H */
 /* Initial guess of the pressure-correction solves:
  *   LES_GUESS_ZERO         phi_0 = 0 for every solve (the plain method)
  *   LES_GUESS_EXTRAPOLATE  first solve of a step: phi_0 = alpha0 (p^n -
@@ -65,7 +66,8 @@ enum { LES_QUICK = 0, LES_WENO3 = 1 };       /* advection scheme */
 enum { LES_GUESS_ZERO = 0, LES_GUESS_EXTRAPOLATE = 1, LES_GUESS_PREVIOUS = 2,
        LES_GUESS_LEARNED = 3 };
 
-/* Run configuration.  Grid sizes >= 4 in every direction.
+/* Run configuration.  nx, ny >= 1 (ny = 1: a two-dimensional x-z run) and
+ * nz >= 4.
  * Table 1 constants of the paper and forcing parameters are explicit so the
  * caller states every value (les_default_config fills Table 1). */
 typedef struct les_config {
@@ -93,6 +95,15 @@ typedef struct les_config {
   int32_t guess;                /* LES_GUESS_* */
   int32_t advection;            /* LES_QUICK (Sec. 2.4) or LES_WENO3 (third-order
                                    WENO faces, Lax-Friedrichs flux) */
+  int32_t wall;                 /* LES_NO_SLIP (u, v mirror oddly across the
+                                   walls) or LES_FREE_SLIP (evenly: zero wall
+                                   stress, as in the Sec. 3 validation cases);
+                                   w has zero wall flux either way */
+  int32_t reserved;             /* 0 */
+  double nu_const;              /* > 0: uniform kinematic viscosity (m^2/s) in
+                                   place of the Smagorinsky model (Sec. 3
+                                   validation cases); scalars diffuse with
+                                   nu/Pr and nu/Sc.  0: Smagorinsky */
 } les_config;
 
 /* Caller-owned device buffers.  u, v, w: velocity (m/s); thl: liquid-ice

@@ -56,21 +56,30 @@ __device__ __forceinline__ T face_flux(T m, T qm1, T q0, T q1, T q2) {
   return m * quick(m, qm1, q0, q1, q2);
 }
 
-// Central derivative of component field f along axis ax at cell (i, j, k),
-// which may be a ghost level (velocity components are odd across walls).
+// Wall parity of velocity component a: w is odd across the walls (zero
+// mass flux); u and v are odd for no-slip walls, even for free-slip ones.
+template <typename T>
+__device__ __forceinline__ T vpar(const Dyn<T> &d, int a) {
+  return a < 2 ? d.uv_par : T(-1);
+}
+
+// Central derivative of velocity component a (field f) along axis ax at
+// cell (i, j, k), which may be a ghost level.
 template <typename T>
 __device__ __forceinline__ T dcentral(const T *__restrict__ f, const Grid &g, const Dyn<T> &d,
-                                      int ax, int i, int j, int k) {
+                                      int a, int ax, int i, int j, int k) {
   const int di = ax == 0, dj = ax == 1, dk = ax == 2;
   const T inv2 = ax == 0 ? d.inv_2dx : (ax == 1 ? d.inv_2dy : d.inv_2dz);
-  return (gload(f, g, i + di, j + dj, k + dk, T(-1)) - gload(f, g, i - di, j - dj, k - dk, T(-1))) *
+  const T par = vpar(d, a);
+  return (gload(f, g, i + di, j + dj, k + dk, par) - gload(f, g, i - di, j - dj, k - dk, par)) *
          inv2;
 }
 
 // ---------------------------------------------------------------- SGS nu
 
 // nu_t = (c_s Delta)^2 f_B S with S = sqrt(2 S_ij S_ij) and the buoyancy
-// factor f_B = sqrt(clamp(1 - N^2/(Pr S^2), 0, 1)), N^2 = db/dz (central).
+// factor f_B = sqrt(clamp(1 - N^2/(Pr S^2), 0, 1)), N^2 = db/dz (central);
+// or the uniform viscosity of the validation cases (Sec. 3) when set.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void sgs_nu_kernel(Grid g, Dyn<T> d, const T *__restrict__ u,
                                                         const T *__restrict__ v,
@@ -79,13 +88,17 @@ __global__ __launch_bounds__(kBlock) void sgs_nu_kernel(Grid g, Dyn<T> d, const 
                                                         T *__restrict__ nu) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= g.n) return;
+  if (d.nu_const > T(0)) {
+    nu[q] = d.nu_const;
+    return;
+  }
   const Cell c = cell_of(g, q);
   const T *vel[3] = {u, v, w};
   T G[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int e = 0; e < 3; ++e) G[a][e] = dcentral(vel[a], g, d, e, c.i, c.j, c.k);
+    for (int e = 0; e < 3; ++e) G[a][e] = dcentral(vel[a], g, d, a, e, c.i, c.j, c.k);
   T s2 = T(0);
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -232,11 +245,11 @@ __device__ __forceinline__ T sgs_face(const Grid &g, const Dyn<T> &d, const T *c
                                       int ax, int cmp, int ia, int ja, int ka) {
   const int di = ax == 0, dj = ax == 1, dk = ax == 2;
   const T inv = ax == 0 ? d.inv_dx : (ax == 1 ? d.inv_dy : d.inv_dz);
-  const T normal = (gload(vel[cmp], g, ia + di, ja + dj, ka + dk, T(-1)) -
-                    gload(vel[cmp], g, ia, ja, ka, T(-1))) *
+  const T normal = (gload(vel[cmp], g, ia + di, ja + dj, ka + dk, vpar(d, cmp)) -
+                    gload(vel[cmp], g, ia, ja, ka, vpar(d, cmp))) *
                    inv;
-  const T trans = T(0.5) * (dcentral(vel[ax], g, d, cmp, ia, ja, ka) +
-                            dcentral(vel[ax], g, d, cmp, ia + di, ja + dj, ka + dk));
+  const T trans = T(0.5) * (dcentral(vel[ax], g, d, ax, cmp, ia, ja, ka) +
+                            dcentral(vel[ax], g, d, ax, cmp, ia + di, ja + dj, ka + dk));
   return rnu * (normal + trans);
 }
 
@@ -274,7 +287,7 @@ __global__ __launch_bounds__(kBlock) void momentum_kernel(
   const T invd[3] = {d.inv_dx, d.inv_dy, d.inv_dz};
 #pragma unroll
   for (int cmp = 0; cmp < 3; ++cmp) {
-    T R = advect<T, WENO>(g, d, mf, vel[cmp], T(-1), c);
+    T R = advect<T, WENO>(g, d, mf, vel[cmp], vpar(d, cmp), c);
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const int di = ax == 0, dj = ax == 1, dk = ax == 2;

@@ -267,7 +267,8 @@ constexpr int kTY2 = 8;  // two-sweep tile: 512 threads, core 62 x 6
 
 struct Shape {
   int kc, tiles_x, tiles_y, tiles_z, ntiles, blocks;
-  bool stream;  // one-sweep kernel: streamed arrays, 64 x kTY1Big tiles
+  int ty;       // one-sweep kernel: tile rows
+  bool stream;  // one-sweep kernel: streamed arrays (64 x kTY1Big tiles)
 };
 
 // The four arrays of a sweep exceed what the Infinity Cache keeps.
@@ -278,8 +279,13 @@ bool streamed(const Grid &g, bool is_double) {
 Shape shape_of(const Grid &g, int S, bool is_double) {
   Shape sh;
   sh.stream = S == 1 && streamed(g, is_double);
+  sh.ty = 0;
   if (S == 1) {
-    const int ty = sh.stream ? kTY1Big : kTY1;
+    // rows beyond ny would idle: a short y axis (a two-dimensional run
+    // has ny = 1) takes the next smaller tile
+    int ty = sh.stream ? kTY1Big : kTY1;
+    if (g.ny < ty) ty = g.ny < kTY1 ? 1 : kTY1;
+    sh.ty = ty;
     sh.tiles_x = (g.nx + 63) / 64;
     sh.tiles_y = (g.ny + ty - 1) / ty;
   } else {
@@ -352,10 +358,16 @@ void launch_tsweep(const Grid &g, int S, bool chebyshev, bool check, bool first,
     }                                                                                 \
   } while (0)
   if (S == 1) {
-    if (sh.stream)
+    if (sh.ty == kTY1Big)
       LES_PICK(kTY1Big, true);
-    else
+    else if (sh.ty == kTY1 && !sh.stream)
       LES_PICK(kTY1, false);
+    else if (sh.ty == kTY1)
+      LES_PICK(kTY1, true);
+    else if (!sh.stream)
+      LES_PICK(1, false);
+    else
+      LES_PICK(1, true);
   } else {
     const dim3 block(64 * kTY2);
     if (chebyshev) {

@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -50,8 +51,9 @@ struct Layout {
 
 int validate(const les_config *c) {
   if (!c) return fail(LES_ERR_ARG, "config is NULL");
-  if (c->nx < 4 || c->ny < 4 || c->nz < 4)
-    return fail(LES_ERR_ARG, "grid %dx%dx%d: every size must be >= 4", c->nx, c->ny, c->nz);
+  if (c->nx < 1 || c->ny < 1 || c->nz < 4)
+    return fail(LES_ERR_ARG, "grid %dx%dx%d: nx, ny must be >= 1 and nz >= 4", c->nx, c->ny,
+                c->nz);
   if ((int64_t)c->nx * c->ny > (int64_t)1 << 30 || (int64_t)c->nx * c->ny * c->nz > (int64_t)1 << 34)
     return fail(LES_ERR_ARG, "grid too large");
   if (!(c->dx > 0) || !(c->dy > 0) || !(c->dz > 0) || !(c->dt > 0))
@@ -78,6 +80,10 @@ int validate(const les_config *c) {
   if (c->sponge_frac < 0 || c->sponge_frac > 1) return fail(LES_ERR_ARG, "sponge_frac must be in [0, 1]");
   if (c->advection != LES_QUICK && c->advection != LES_WENO3)
     return fail(LES_ERR_ARG, "unknown advection scheme %d", c->advection);
+  if (c->wall != LES_NO_SLIP && c->wall != LES_FREE_SLIP)
+    return fail(LES_ERR_ARG, "unknown wall condition %d", c->wall);
+  if (!(c->nu_const >= 0) || c->nu_const > 1e6)
+    return fail(LES_ERR_ARG, "nu_const must be in [0, 1e6]");
   if (c->guess < LES_GUESS_ZERO || c->guess > LES_GUESS_LEARNED)
     return fail(LES_ERR_ARG, "unknown guess mode %d", c->guess);
   return LES_OK;
@@ -166,9 +172,10 @@ void jacobi_spectrum(const les_config *c, double *lo, double *hi) {
   const double D = 2.0 * (ax + ay + az);
   auto per = [&](int n, int m) { return 2.0 - 2.0 * std::cos(2.0 * pi * m / n); };
   auto mir = [&](int n, int m) { return 2.0 - 2.0 * std::cos(pi * m / n); };
-  const double smallest[3] = {per(c->nx, 1) * ax, per(c->ny, 1) * ay, mir(c->nz, 1) * az};
-  double s = smallest[0];
-  for (int q = 1; q < 3; ++q) s = smallest[q] < s ? smallest[q] : s;
+  // a periodic axis of one cell has only its constant mode
+  double s = mir(c->nz, 1) * az;
+  if (c->nx > 1) s = std::min(s, per(c->nx, 1) * ax);
+  if (c->ny > 1) s = std::min(s, per(c->ny, 1) * ay);
   *lo = s / D;
   *hi = (per(c->nx, c->nx / 2) * ax + per(c->ny, c->ny / 2) * ay + mir(c->nz, c->nz - 1) * az) / D;
 }
@@ -222,6 +229,8 @@ View<T> view_of(const les_handle *h) {
   d.smag_l2 = (T)((c.cs * delta) * (c.cs * delta));
   d.pr = (T)c.Pr;
   d.advection = c.advection;
+  d.uv_par = c.wall == LES_FREE_SLIP ? T(1) : T(-1);
+  d.nu_const = (T)c.nu_const;
   V.u = (T *)h->buf.u;
   V.v = (T *)h->buf.v;
   V.w = (T *)h->buf.w;

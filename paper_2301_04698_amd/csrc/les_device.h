@@ -5,8 +5,11 @@
 
 namespace lesmi {
 
-// Periodic neighbour index for offsets |o| <= 2 (n >= 4 is validated on the host).
-__device__ __forceinline__ int pwrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+// Periodic neighbour index for offsets |o| <= 2: one wrap suffices for
+// n >= 2; an axis of one cell (a two-dimensional run) maps every offset to 0.
+__device__ __forceinline__ int pwrap(int i, int n) {
+  return n == 1 ? 0 : (i < 0 ? i + n : (i >= n ? i - n : i));
+}
 
 // Mirror across the walls z = 0 and z = H: level -1 -> 0, -2 -> 1, nz -> nz-1, nz+1 -> nz-2.
 __device__ __forceinline__ int zmirror(int k, int nz) {

@@ -42,6 +42,8 @@ struct Dyn {
   T smag_l2;           // (c_s Delta)^2
   T pr;                // turbulent Prandtl number of the buoyancy factor
   int advection;       // LES_QUICK or LES_WENO3
+  T uv_par;            // wall parity of u and v: -1 no-slip, +1 free-slip
+  T nu_const;          // > 0: uniform viscosity in place of the SGS model
 };
 
 // Device-resident control block of one Poisson solve.  Sweep kernels read

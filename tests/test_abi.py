@@ -82,7 +82,10 @@ def test_make_config_carries_every_parameter(lib, oracle_lib):
 
 
 @pytest.mark.parametrize("override,needle", [
-    (dict(nx=3), "must be >= 4"),
+    (dict(nz=3), "nz >= 4"),
+    (dict(ny=0), "nx, ny must be >= 1"),
+    (dict(wall=7), "wall condition"),
+    (dict(nu_const=-1.0), "nu_const"),
     (dict(dt=0.0), "> 0"),
     (dict(poisson_tol=0.0), "poisson_tol"),
     (dict(poisson_check_every=0), "check_every"),

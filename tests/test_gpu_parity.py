@@ -249,6 +249,77 @@ def test_step_weno3_fp32_matches_oracle(gpu, oracle_lib):
         assert e <= 1e-5, (k, e, errs)
 
 
+# ------------------------------- validation cases (Sec. 3): uniform nu,
+# free-slip walls, two-dimensional runs (ny = 1)
+
+@pytest.mark.parametrize("case,advection", [("DC400", "quick"), ("RB400", "quick"),
+                                            ("DC400", "weno3")])
+def test_validation_case_fp64_matches_oracle(gpu, oracle_lib, case, advection):
+    """Density current / rising bubble at 400 m (128 x 1 x 16, 50 x 1 x 25):
+    four steps in FP64 against the oracle."""
+    p = li.workload(case, precision="fp64", poisson_tol=1e-9, advection=advection)
+    errs, recs, *_ = _compare_step(gpu, oracle_lib, p, li.initial_state(p), 4, 1e-11)
+    assert all(r["sweeps"] > 0 for r in recs)
+    for k, e in errs.items():
+        assert e <= 1e-11, (k, e, errs)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-5)])
+def test_free_slip_uniform_nu_3d_matches_oracle(gpu, oracle_lib, precision, tol):
+    """Both options on a ragged three-dimensional grid with all moist physics
+    and a perturbed velocity (every stress and advection term sees the wall
+    parity of u and v)."""
+    p = li.workload("C1m", nx=40, ny=24, nz=32, precision=precision,
+                    poisson_tol=1e-9 if precision == "fp64" else 1e-6,
+                    poisson_scheme="chebyshev", wall="free_slip", nu_const=3.0)
+    st0 = with_velocity_noise(p, li.initial_state(p), 0.3, 12)
+    if precision == "fp32":
+        st0 = {k: v.astype(np.float32).astype(np.float64) for k, v in st0.items()}
+    errs, *_ = _compare_step(gpu, oracle_lib, p, st0, 2 if precision == "fp64" else 1, tol)
+    for k, e in errs.items():
+        assert e <= tol, (k, e, errs)
+
+
+def test_density_current_fp32_matches_oracle(gpu, oracle_lib):
+    """The 200 m density current (256 x 1 x 32) in the FP32 path, two steps
+    from the FP32-rounded initial state."""
+    p = li.workload("DC200", precision="fp32")
+    st0 = {k: v.astype(np.float32).astype(np.float64) for k, v in li.initial_state(p).items()}
+    errs, *_ = _compare_step(gpu, oracle_lib, p, st0, 2, 1e-5)
+    for k, e in errs.items():
+        assert e <= 1e-5, (k, e, errs)
+
+
+def test_density_current_stays_mirror_symmetric_gpu(gpu):
+    """200 steps (200 s) of the 200 m density current: theta_l and w
+    symmetric and u antisymmetric about the domain centre to round-off."""
+    p = li.workload("DC200", guess="previous")
+    sim = gpu.LES(p, li.initial_state(p))
+    rc, st, _ = sim.step(200, records=True)
+    assert st["not_converged"] == 0
+    st = sim.state_numpy()
+    t, u, w = st["thl"][:, 0, :], st["u"][:, 0, :], st["w"][:, 0, :]
+    assert np.abs(u).max() > 5.0
+    dev = p["theta_bg"] - t
+    assert np.abs(dev - dev[:, ::-1]).max() <= 1e-9 * np.abs(dev).max()
+    assert np.abs(u + u[:, ::-1]).max() <= 1e-9 * np.abs(u).max()
+    assert np.abs(w - w[:, ::-1]).max() <= 1e-9 * np.abs(w).max()
+
+
+def test_two_dimensional_sweeps_one_vs_two_per_launch(gpu):
+    """ny = 1 takes one-row sweep tiles; the fused two-sweep launch (its own
+    tiles) gives the same iterates."""
+    import torch
+    out = []
+    for spl in (1, 2):
+        p = li.workload("DC200", sweeps_per_launch=spl)
+        sim = gpu.LES(p)
+        rhs = torch.from_numpy(li.random_field((p["nz"], p["ny"], p["nx"]), seed=5))
+        phi, st, rc = sim.poisson_solve(rhs.float(), fixed_sweeps=60)
+        out.append(phi.double().cpu().numpy())
+    assert np.array_equal(out[0], out[1])
+
+
 def test_step_rest_state_steady(gpu):
     import torch
     p = li.workload("C1", nx=8, ny=8, nz=8, ug=0.0, vg=0.0, noise_thl=0.0, thl_ml=290.0,

@@ -28,6 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+CASE_LABEL = {"cloud_layer": "synthetic stratocumulus",
+              "bubble": "dry bubble (density current / rising bubble)"}
 
 # HBM bytes per launch of the one-sweep Chebyshev kernel measured with
 # rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (FETCH scaled x2.0, WRITE x1.0 by a
@@ -289,7 +291,8 @@ def main():
         "dtype": "f32" if p["precision"] == "fp32" else "f64",
         "data": "synthetic",
         "config": {
-            "workload": (f"synthetic stratocumulus LES step, {p['nx']}x{p['ny']}x{p['nz']} cells, "
+            "workload": (f"{CASE_LABEL.get(p['init'], p['init'])} LES step, "
+                         f"{p['nx']}x{p['ny']}x{p['nz']} cells, "
                          f"{p['dx']:g}x{p['dy']:g}x{p['dz']:g} m, dt {p['dt']:g} s, "
                          f"{p['poisson_scheme']} Poisson to rel. residual {p['poisson_tol']:g}, "
                          f"K={K}, {p['advection']} advection"),
@@ -314,8 +317,9 @@ def main():
             "avg_launch_us": avg_launch * 1e6,
             "sweeps_per_launch": S,
             "bytes_per_launch": bytes_launch,
-            "note": ("working set of the sweep is about 134 MB, inside the 256 MB Infinity Cache"
-                     if bytes_launch < 256e6 else "working set exceeds the 256 MB Infinity Cache"),
+            "note": (f"working set of the sweep {bytes_launch / 1e6:.0f} MB, "
+                     + ("inside" if bytes_launch < 256e6 else "beyond")
+                     + " the 256 MB Infinity Cache"),
         },
     }
     if p["init"] != "cloud_layer":

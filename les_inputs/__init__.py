@@ -80,6 +80,8 @@ _BASE = dict(
     advection="quick",         # "quick" or "weno3" (WENO3 with Lax-Friedrichs flux)
     wall="no_slip",            # u, v at z = 0, H: "no_slip" or "free_slip"
     nu_const=0.0,              # > 0: uniform kinematic viscosity (m^2/s), no SGS model
+    phase="heaviside",         # condensate partition: "heaviside" at T_f or "ramp"
+    T_ice=233.15,              # ramp: all condensate is ice at and below T_ice (K)
     # forcing
     ug=7.0, vg=-5.0,
     shf=0.0, lhf=0.0,          # surface sensible / latent heat flux, W/m^2
@@ -132,6 +134,16 @@ WORKLOADS = {
                poisson_max_sweeps=20000,
                noise_qt=2.5e-5, shf=15.0, lhf=115.0, rad_F0=60.0, rad_kappa=100.0,
                seed=2000),
+    # Cold mixed-phase variant of C1m (theta_l 258 K, 0.8 g/kg): a cloud of
+    # liquid and ice from about 460 m to the top, partitioned by the ramp.
+    "C1i": dict(dz=25.0, thl_ml=258.0, theta0=258.0, qt_ml=0.8e-3, noise_qt=2.5e-6,
+                shf=15.0, lhf=115.0, rad_F0=60.0, rad_kappa=100.0, phase="ramp"),
+    # The same cold profile on the 256x256x128 grid (thermodynamics timing).
+    "C2i": dict(nx=256, ny=256, nz=128, dx=35.0, dy=35.0, dz=5.0, dt=0.3,
+                poisson_tol=1e-6, poisson_scheme="chebyshev", precision="fp32",
+                poisson_max_sweeps=20000, thl_ml=258.0, theta0=258.0, qt_ml=0.8e-3,
+                z_inv=1e9, noise_qt=2.5e-6, shf=15.0, lhf=115.0, rad_F0=60.0,
+                rad_kappa=100.0, phase="ramp", seed=2),
     # Largest single-GPU domain.
     "C5": dict(nx=1024, ny=1024, nz=256, dx=35.0, dy=35.0, dz=5.0, dt=0.3,
                poisson_tol=1e-6, poisson_scheme="chebyshev", precision="fp32",

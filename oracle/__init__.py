@@ -20,6 +20,7 @@ SCHEMES = {"jacobi": 0, "chebyshev": 1}
 GUESSES = {"zero": 0, "extrapolate": 1, "previous": 2}
 ADVECTION = {"quick": 0, "weno3": 1}
 WALLS = {"no_slip": 0, "free_slip": 1}
+PHASES = {"heaviside": 0, "ramp": 1}
 
 
 class OCfg(C.Structure):
@@ -28,7 +29,7 @@ class OCfg(C.Structure):
         ("poisson_scheme", C.c_int32), ("poisson_check_every", C.c_int32),
         ("poisson_max_sweeps", C.c_int32), ("satadj_maxit", C.c_int32),
         ("guess", C.c_int32), ("advection", C.c_int32),
-        ("wall", C.c_int32), ("reserved", C.c_int32),
+        ("wall", C.c_int32), ("phase", C.c_int32),
         ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("dt", C.c_double),
         ("poisson_tol", C.c_double), ("jacobi_omega", C.c_double),
         ("p00", C.c_double), ("theta0", C.c_double), ("Rd", C.c_double), ("Rv", C.c_double),
@@ -39,7 +40,7 @@ class OCfg(C.Structure):
         ("wsub_div", C.c_double), ("sponge_frac", C.c_double), ("sponge_max", C.c_double),
         ("rad_F0", C.c_double), ("rad_kappa", C.c_double),
         ("e_tr", C.c_double), ("T_tr", C.c_double), ("satadj_tol", C.c_double),
-        ("nu_const", C.c_double),
+        ("nu_const", C.c_double), ("T_ice", C.c_double),
     ]
 
 
@@ -72,6 +73,11 @@ def lib():
         L.oracle_theta_l.restype = C.c_double
         L.oracle_qv_sat.argtypes = [cfgp, C.c_double, C.c_double]
         L.oracle_qv_sat.restype = C.c_double
+        for name in ("oracle_qv_sat_ice", "oracle_qv_star"):
+            getattr(L, name).argtypes = [cfgp, C.c_double, C.c_double]
+            getattr(L, name).restype = C.c_double
+        L.oracle_liquid_fraction.argtypes = [cfgp, C.c_double]
+        L.oracle_liquid_fraction.restype = C.c_double
         L.oracle_satadj.argtypes = [cfgp, C.c_double, C.c_double, C.c_double, _DP, _DP, _DP]
         L.oracle_thermo.argtypes = [cfgp, _DP, _DP, _DP, _DP, _DP, _DP]
         L.oracle_sgs_nu.argtypes = [cfgp, _DP, _DP, _DP, _DP, _DP]
@@ -115,8 +121,11 @@ def make_cfg(p: dict) -> OCfg:
             if v not in WALLS:
                 raise ValueError(f"unknown wall condition {v!r}; known: {sorted(WALLS)}")
             c.wall = WALLS[v]
-        elif name == "reserved":
-            c.reserved = 0
+        elif name == "phase":
+            v = p.get("phase", "heaviside")
+            if v not in PHASES:
+                raise ValueError(f"unknown phase partition {v!r}; known: {sorted(PHASES)}")
+            c.phase = PHASES[v]
         else:
             setattr(c, name, ctype(p[name]).value)
     return c
@@ -159,6 +168,18 @@ def theta_l(p, T, ql, qi, qt, p0):
 
 def qv_sat(p, T, p0):
     return lib().oracle_qv_sat(C.byref(make_cfg(p)), T, p0)
+
+
+def qv_sat_ice(p, T, p0):
+    return lib().oracle_qv_sat_ice(C.byref(make_cfg(p)), T, p0)
+
+
+def qv_star(p, T, p0):
+    return lib().oracle_qv_star(C.byref(make_cfg(p)), T, p0)
+
+
+def liquid_fraction(p, T):
+    return lib().oracle_liquid_fraction(C.byref(make_cfg(p)), T)
 
 
 def satadj(p, thl, qt, p0):

@@ -74,6 +74,8 @@ static int check_cfg(const ocfg *c) {
   if (c->advection != 0 && c->advection != 1) return -1;
   if (c->wall != 0 && c->wall != 1) return -1;
   if (!(c->nu_const >= 0.0) || c->nu_const > 1e6) return -1;
+  if (c->phase != 0 && c->phase != 1) return -1;
+  if (c->phase == 1 && !(c->T_ice > 0.0 && c->T_ice < c->Tf)) return -1;
   return 0;
 }
 
@@ -172,13 +174,47 @@ double oracle_qv_sat(const ocfg *c, double T, double p0) {
   return eps * es / (p0 - (1.0 - eps) * es);
 }
 
-/* theta_l*(T; p0) - theta_l: the saturation-adjustment residual (Sec. 2.2),
- * with q_l* = max(0, q_t - q_v*) H(T - T_f) and q_i* = max(0, ...) H(T_f - T);
- * H(0) counts as liquid. */
+/* Saturation specific humidity over ice: the same form with the
+ * sublimation heat L_s0 of Table 1 (READING: the ice phase of Sec. 2.2
+ * saturates over ice), equal to the liquid value at the triple point. */
+double oracle_qv_sat_ice(const ocfg *c, double T, double p0) {
+  double es = c->e_tr * exp(c->Ls0 / c->Rv * (1.0 / c->T_tr - 1.0 / T));
+  double eps = c->Rd / c->Rv;
+  return eps * es / (p0 - (1.0 - eps) * es);
+}
+
+/* Share lambda(T) of the condensate that is liquid.  Phase 0: the
+ * Heaviside function of Sec. 2.2, H(T - T_f) with H(0) = 1.  Phase 1: the
+ * continuous partition the paper suggests for mixed-phase clouds;
+ * READING: the linear ramp of Tao et al. (1989), lambda = (T - T_ice) /
+ * (T_f - T_ice) clipped to [0, 1]. */
+double oracle_liquid_fraction(const ocfg *c, double T) {
+  if (c->phase == 0) return T >= c->Tf ? 1.0 : 0.0;
+  double lam = (T - c->T_ice) / (c->Tf - c->T_ice);
+  return lam < 0.0 ? 0.0 : (lam > 1.0 ? 1.0 : lam);
+}
+
+/* Saturation humidity of the partitioned condensate (READING, after Tao
+ * et al. 1989): lambda q_v*(liquid) + (1 - lambda) q_v*(ice). */
+double oracle_qv_star(const ocfg *c, double T, double p0) {
+  double lam = oracle_liquid_fraction(c, T);
+  return lam * oracle_qv_sat(c, T, p0) + (1.0 - lam) * oracle_qv_sat_ice(c, T, p0);
+}
+
+/* Saturation partition at temperature T: q_c = max(0, q_t - q_v*),
+ * q_l = lambda q_c, q_i = (1 - lambda) q_c (Sec. 2.2 with lambda in place of
+ * the Heaviside functions). */
+static void partition(const ocfg *c, double T, double qt, double p0, double *ql, double *qi) {
+  double qc = fmax(0.0, qt - oracle_qv_star(c, T, p0));
+  double lam = oracle_liquid_fraction(c, T);
+  *ql = lam * qc;
+  *qi = qc - *ql;
+}
+
+/* theta_l*(T; p0) - theta_l: the saturation-adjustment residual (Sec. 2.2). */
 static double satadj_residual(const ocfg *c, double T, double thl, double qt, double p0) {
-  double qc = fmax(0.0, qt - oracle_qv_sat(c, T, p0));
-  double ql = T >= c->Tf ? qc : 0.0;
-  double qi = T >= c->Tf ? 0.0 : qc;
+  double ql, qi;
+  partition(c, T, qt, p0, &ql, &qi);
   return oracle_theta_l(c, T, ql, qi, qt, p0) - thl;
 }
 
@@ -191,7 +227,7 @@ static double satadj_residual(const ocfg *c, double T, double thl, double qt, do
 int oracle_satadj(const ocfg *c, double thl, double qt, double p0, double *T, double *ql,
                   double *qi) {
   double Tu = thl * oracle_exner(c, p0, qt, 0.0, 0.0);
-  double qs = oracle_qv_sat(c, Tu, p0);
+  double qs = oracle_qv_star(c, Tu, p0);
   if (qt <= qs) {
     *T = Tu; *ql = 0.0; *qi = 0.0;
     return 0;
@@ -208,10 +244,8 @@ int oracle_satadj(const ocfg *c, double thl, double qt, double p0, double *T, do
     ++it;
     if (fabs(Tb - Ta) <= c->satadj_tol) break;
   }
-  double qc = fmax(0.0, qt - oracle_qv_sat(c, Tb, p0));
   *T = Tb;
-  *ql = Tb >= c->Tf ? qc : 0.0;
-  *qi = Tb >= c->Tf ? 0.0 : qc;
+  partition(c, Tb, qt, p0, ql, qi);
   return it;
 }
 

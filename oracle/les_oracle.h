@@ -24,7 +24,7 @@ typedef struct ocfg {
   int32_t guess;               /* initial guess of the solves, see oracle_step */
   int32_t advection;           /* 0 QUICK, 1 WENO3 with Lax-Friedrichs flux */
   int32_t wall;                /* u, v at z = 0, H: 0 no-slip (odd mirror), 1 free-slip (even) */
-  int32_t reserved;
+  int32_t phase;               /* condensate partition: 0 Heaviside at T_f, 1 linear ramp T_ice..T_f */
   double dx, dy, dz, dt;
   double poisson_tol;          /* ||rhs - L phi||_2 <= tol * ||rhs||_2 */
   double jacobi_omega;         /* 0 = closed-form optimum */
@@ -35,6 +35,7 @@ typedef struct ocfg {
   /* saturation vapour pressure anchor and secant stopping */
   double e_tr, T_tr, satadj_tol;
   double nu_const;             /* > 0: uniform kinematic viscosity in place of the SGS model */
+  double T_ice;                /* phase 1: all condensate is ice at and below T_ice (K) */
 } ocfg;
 
 typedef struct osolve {        /* one Poisson solve */
@@ -52,7 +53,10 @@ int oracle_reference_state(const ocfg *c, double *p0, double *T0, double *rho0, 
 /* Pointwise thermodynamics (Sec. 2.1, 2.2). */
 double oracle_exner(const ocfg *c, double p0, double qt, double ql, double qi);
 double oracle_theta_l(const ocfg *c, double T, double ql, double qi, double qt, double p0);
-double oracle_qv_sat(const ocfg *c, double T, double p0);
+double oracle_qv_sat(const ocfg *c, double T, double p0);      /* over liquid */
+double oracle_qv_sat_ice(const ocfg *c, double T, double p0);  /* over ice */
+double oracle_liquid_fraction(const ocfg *c, double T);        /* share of condensate that is liquid */
+double oracle_qv_star(const ocfg *c, double T, double p0);     /* saturation humidity of the partition */
 int oracle_satadj(const ocfg *c, double thl, double qt, double p0,
                   double *T, double *ql, double *qi);
 /* Field thermodynamics: T, q_l, q_i, b (all optional except inputs). */

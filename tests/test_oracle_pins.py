@@ -111,7 +111,7 @@ def test_satadj_round_trip_and_bisection(oracle_lib):
     for T in rng_T:
         for p0 in p0s[::13]:
             for qt in rng_q:
-                qc = max(0.0, qt - oracle_lib.qv_sat(p, T, p0))
+                qc = max(0.0, qt - oracle_lib.qv_star(p, T, p0))
                 ql = qc if T >= p["Tf"] else 0.0
                 qi = qc if T < p["Tf"] else 0.0
                 thl = oracle_lib.theta_l(p, T, ql, qi, qt, p0)
@@ -143,6 +143,106 @@ def test_satadj_matches_bisection(oracle_lib):
                 hi = mid
         T, ql, qi, _ = oracle_lib.satadj(p, thl, qt, p0)
         assert T == pytest.approx(0.5 * (lo + hi), abs=1e-9)
+
+
+# ------------------------------- ice and mixed phase (Sec. 2.2 partition)
+
+def test_ice_saturation_clausius_clapeyron(oracle_lib):
+    """Over ice the saturation vapour pressure follows Clausius-Clapeyron
+    with the sublimation heat L_s0; it equals the liquid value at the triple
+    point and lies below it at colder temperatures; at -20 C it is about
+    103 Pa (published value 103.3 Pa, Murphy & Koop 2005)."""
+    p = small()
+    eps = p["Rd"] / p["Rv"]
+
+    def e_of(T, p0):
+        q = oracle_lib.qv_sat_ice(p, T, p0)
+        return q * p0 / (eps + q * (1.0 - eps))
+
+    for T in (230.0, 250.0, 265.0):
+        h = 1e-3
+        slope = (math.log(e_of(T + h, 1e5)) - math.log(e_of(T - h, 1e5))) / (2 * h)
+        assert slope == pytest.approx(p["Ls0"] / (p["Rv"] * T * T), rel=1e-6)
+        assert oracle_lib.qv_sat_ice(p, T, 8e4) < oracle_lib.qv_sat(p, T, 8e4)
+    assert e_of(p["T_tr"], 1e5) == pytest.approx(p["e_tr"], rel=1e-14)
+    assert oracle_lib.qv_sat_ice(p, p["T_tr"], 9e4) == pytest.approx(
+        oracle_lib.qv_sat(p, p["T_tr"], 9e4), rel=1e-14)
+    assert e_of(253.15, 1e5) == pytest.approx(103.3, rel=0.02)
+
+
+def test_liquid_fraction_heaviside_and_ramp(oracle_lib):
+    """Heaviside: liquid at and above T_f, ice below (Sec. 2.2).  Ramp: 1 at
+    T_f, 0 at T_ice, linear between, clipped outside."""
+    p = small()
+    tf, ti = p["Tf"], p["T_ice"]
+    assert oracle_lib.liquid_fraction(p, tf) == 1.0
+    assert oracle_lib.liquid_fraction(p, tf - 1e-9) == 0.0
+    r = small(phase="ramp")
+    assert oracle_lib.liquid_fraction(r, tf) == 1.0
+    assert oracle_lib.liquid_fraction(r, tf + 5) == 1.0
+    assert oracle_lib.liquid_fraction(r, ti) == 0.0
+    assert oracle_lib.liquid_fraction(r, ti - 5) == 0.0
+    for f in (0.1, 0.5, 0.8):
+        assert oracle_lib.liquid_fraction(r, ti + f * (tf - ti)) == pytest.approx(f, abs=1e-14)
+    # the saturation humidity blends the two phases with the same weight
+    T, p0 = ti + 0.25 * (tf - ti), 8.5e4
+    assert oracle_lib.qv_star(r, T, p0) == pytest.approx(
+        0.25 * oracle_lib.qv_sat(r, T, p0) + 0.75 * oracle_lib.qv_sat_ice(r, T, p0), rel=1e-14)
+
+
+def test_mixed_phase_round_trip_and_bisection(oracle_lib):
+    """Ramp partition: theta_l*(T) is continuous through the mixed-phase
+    range, so theta_l built from (T, q_t) at saturation gives back T, and
+    the secant root equals an independent bisection root.  Condensate splits
+    as lambda(T) : 1 - lambda(T) and q_v + q_l + q_i = q_t."""
+    p = small(phase="ramp")
+    p0s = oracle_lib.reference_state(small(nz=130, dz=10.0, phase="ramp"))["p0"][::26]
+    worst = 0.0
+    nmix = 0
+    for T in np.linspace(215.0, 290.0, 16):
+        lam = oracle_lib.liquid_fraction(p, T)
+        for p0 in p0s:
+            qs = oracle_lib.qv_star(p, T, p0)
+            for qt in (0.5 * qs, 1.5 * qs, 3.0 * qs):
+                qc = max(0.0, qt - qs)
+                thl = oracle_lib.theta_l(p, T, lam * qc, (1 - lam) * qc, qt, p0)
+                T2, ql2, qi2, it = oracle_lib.satadj(p, thl, qt, p0)
+                worst = max(worst, abs(T2 - T))
+                assert ql2 == pytest.approx(lam * qc, abs=1e-12)
+                assert qi2 == pytest.approx((1 - lam) * qc, abs=1e-12)
+                if qc > 0 and 0 < lam < 1:
+                    nmix += 1
+                    assert ql2 > 0 and qi2 > 0
+                    qv = oracle_lib.qv_star(p, T2, p0)
+                    assert qv + ql2 + qi2 == pytest.approx(qt, rel=1e-9)
+
+                def f(Tx):
+                    lx = oracle_lib.liquid_fraction(p, Tx)
+                    qx = max(0.0, qt - oracle_lib.qv_star(p, Tx, p0))
+                    return oracle_lib.theta_l(p, Tx, lx * qx, (1 - lx) * qx, qt, p0) - thl
+                lo, hi = 150.0, 350.0
+                assert f(lo) < 0 < f(hi)
+                for _ in range(200):
+                    mid = 0.5 * (lo + hi)
+                    lo, hi = (mid, hi) if f(mid) < 0 else (lo, mid)
+                assert T2 == pytest.approx(0.5 * (lo + hi), abs=1e-9)
+    assert nmix >= 20
+    assert worst <= 1e-9, worst
+
+
+def test_cold_cloud_layer_is_mixed_phase(oracle_lib):
+    """The cold workload (theta_l 258 K, 0.8 g/kg): temperatures inside the
+    ramp, a cloud of liquid and ice in the upper part, the ice share growing
+    with height as the air cools."""
+    p = small("C1i")
+    st = li.initial_state(p)
+    th = oracle_lib.thermo(p, st["thl"], st["qt"])
+    assert p["T_ice"] < th["T"].min() and th["T"].max() < p["Tf"]
+    ql, qi = th["ql"].mean(axis=(1, 2)), th["qi"].mean(axis=(1, 2))
+    cloudy = np.where(ql + qi > 0)[0]
+    assert 300.0 < li.cell_heights(p)[cloudy.min()] < 600.0
+    share = qi[cloudy] / (ql[cloudy] + qi[cloudy])
+    assert np.all(share > 0.3) and np.all(share < 0.7) and np.all(np.diff(share) > 0)
 
 
 def test_cloud_layer_exists_in_stratocumulus_profile(oracle_lib):

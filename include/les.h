@@ -50,6 +50,13 @@ enum { LES_FP64 = 0, LES_FP32 = 1 };          /* storage / stencil precision */
 enum { LES_JACOBI = 0, LES_CHEBYSHEV = 1 };   /* Poisson sweep weighting */
 enum { LES_QUICK = 0, LES_WENO3 = 1 };       /* advection scheme */
 enum { LES_NO_SLIP = 0, LES_FREE_SLIP = 1 };  /* u, v at the walls z = 0, H */
+/* Share of the condensate that is liquid (Sec. 2.2): LES_PHASE_HEAVISIDE,
+ * liquid at and above T_f and ice below (the paper's equations), or
+ * LES_PHASE_RAMP, the continuous partition for mixed-phase clouds: linear
+ * from all ice at T_ice to all liquid at T_f.  Saturation over ice uses the
+ * sublimation heat Ls0; the saturation humidity of a partition is the
+ * liquid-share-weighted mean of the two. */
+enum { LES_PHASE_HEAVISIDE = 0, LES_PHASE_RAMP = 1 };
 /* Initial guess of the pressure-correction solves:
  *   LES_GUESS_ZERO         phi_0 = 0 for every solve (the plain method)
  *   LES_GUESS_EXTRAPOLATE  first solve of a step: phi_0 = alpha0 (p^n -
@@ -66,8 +73,8 @@ enum { LES_NO_SLIP = 0, LES_FREE_SLIP = 1 };  /* u, v at the walls z = 0, H */
 enum { LES_GUESS_ZERO = 0, LES_GUESS_EXTRAPOLATE = 1, LES_GUESS_PREVIOUS = 2,
        LES_GUESS_LEARNED = 3 };
 
-/* Run configuration.  nx, ny >= 1 (ny = 1: a two-dimensional x-z run) and
- * nz >= 4.
+/* Run configuration.  nx >= 2, ny >= 1 (ny = 1: a two-dimensional x-z run)
+ * and nz >= 4.
  * Table 1 constants of the paper and forcing parameters are explicit so the
  * caller states every value (les_default_config fills Table 1). */
 typedef struct les_config {
@@ -99,11 +106,13 @@ typedef struct les_config {
                                    walls) or LES_FREE_SLIP (evenly: zero wall
                                    stress, as in the Sec. 3 validation cases);
                                    w has zero wall flux either way */
-  int32_t reserved;             /* 0 */
+  int32_t phase;                /* LES_PHASE_HEAVISIDE or LES_PHASE_RAMP */
   double nu_const;              /* > 0: uniform kinematic viscosity (m^2/s) in
                                    place of the Smagorinsky model (Sec. 3
                                    validation cases); scalars diffuse with
                                    nu/Pr and nu/Sc.  0: Smagorinsky */
+  double T_ice;                 /* LES_PHASE_RAMP: all condensate is ice at
+                                   and below T_ice (K), 0 < T_ice < Tf */
 } les_config;
 
 /* Caller-owned device buffers.  u, v, w: velocity (m/s); thl: liquid-ice

@@ -254,6 +254,7 @@ int les_cnn_pair(const les_config *cfg, const void *rhs, const void *base, const
   g.ny = cfg->ny;
   g.nz = cfg->nz;
   g.nxy = (int64_t)g.nx * g.ny;
+  g.sy = g.ny == 1 ? 0 : g.nx;
   g.n = g.nxy * g.nz;
   g.dx = cfg->dx;
   g.dy = cfg->dy;

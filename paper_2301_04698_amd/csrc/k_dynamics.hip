@@ -57,20 +57,21 @@ __device__ __forceinline__ T face_flux(T m, T qm1, T q0, T q1, T q2) {
 }
 
 // Wall parity of velocity component a: w is odd across the walls (zero
-// mass flux); u and v are odd for no-slip walls, even for free-slip ones.
-template <typename T>
-__device__ __forceinline__ T vpar(const Dyn<T> &d, int a) {
-  return a < 2 ? d.uv_par : T(-1);
+// mass flux); u and v are odd for no-slip walls, even for free-slip (FS)
+// ones.  A compile-time sign keeps the ghost negation free.
+template <typename T, bool FS>
+__device__ __forceinline__ T vpar(int a) {
+  return a < 2 && FS ? T(1) : T(-1);
 }
 
 // Central derivative of velocity component a (field f) along axis ax at
 // cell (i, j, k), which may be a ghost level.
-template <typename T>
+template <typename T, bool FS>
 __device__ __forceinline__ T dcentral(const T *__restrict__ f, const Grid &g, const Dyn<T> &d,
                                       int a, int ax, int i, int j, int k) {
   const int di = ax == 0, dj = ax == 1, dk = ax == 2;
   const T inv2 = ax == 0 ? d.inv_2dx : (ax == 1 ? d.inv_2dy : d.inv_2dz);
-  const T par = vpar(d, a);
+  const T par = vpar<T, FS>(a);
   return (gload(f, g, i + di, j + dj, k + dk, par) - gload(f, g, i - di, j - dj, k - dk, par)) *
          inv2;
 }
@@ -80,7 +81,7 @@ __device__ __forceinline__ T dcentral(const T *__restrict__ f, const Grid &g, co
 // nu_t = (c_s Delta)^2 f_B S with S = sqrt(2 S_ij S_ij) and the buoyancy
 // factor f_B = sqrt(clamp(1 - N^2/(Pr S^2), 0, 1)), N^2 = db/dz (central);
 // or the uniform viscosity of the validation cases (Sec. 3) when set.
-template <typename T>
+template <typename T, bool FS>
 __global__ __launch_bounds__(kBlock) void sgs_nu_kernel(Grid g, Dyn<T> d, const T *__restrict__ u,
                                                         const T *__restrict__ v,
                                                         const T *__restrict__ w,
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void sgs_nu_kernel(Grid g, Dyn<T> d, const 
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int e = 0; e < 3; ++e) G[a][e] = dcentral(vel[a], g, d, a, e, c.i, c.j, c.k);
+    for (int e = 0; e < 3; ++e) G[a][e] = dcentral<T, FS>(vel[a], g, d, a, e, c.i, c.j, c.k);
   T s2 = T(0);
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -240,23 +241,23 @@ __global__ __launch_bounds__(kBlock) void scalar_kernel(
 // SGS momentum flux of component cmp through the face between cell a and
 // cell b = a + e_ax: rho0_f nu_f [ (u_cmp(b) - u_cmp(a))/Delta_ax
 //   + (d u_ax/d x_cmp (a) + d u_ax/d x_cmp (b)) / 2 ].
-template <typename T>
+template <typename T, bool FS>
 __device__ __forceinline__ T sgs_face(const Grid &g, const Dyn<T> &d, const T *const vel[3], T rnu,
                                       int ax, int cmp, int ia, int ja, int ka) {
   const int di = ax == 0, dj = ax == 1, dk = ax == 2;
   const T inv = ax == 0 ? d.inv_dx : (ax == 1 ? d.inv_dy : d.inv_dz);
-  const T normal = (gload(vel[cmp], g, ia + di, ja + dj, ka + dk, vpar(d, cmp)) -
-                    gload(vel[cmp], g, ia, ja, ka, vpar(d, cmp))) *
+  const T normal = (gload(vel[cmp], g, ia + di, ja + dj, ka + dk, vpar<T, FS>(cmp)) -
+                    gload(vel[cmp], g, ia, ja, ka, vpar<T, FS>(cmp))) *
                    inv;
-  const T trans = T(0.5) * (dcentral(vel[ax], g, d, ax, cmp, ia, ja, ka) +
-                            dcentral(vel[ax], g, d, ax, cmp, ia + di, ja + dj, ka + dk));
+  const T trans = T(0.5) * (dcentral<T, FS>(vel[ax], g, d, ax, cmp, ia, ja, ka) +
+                            dcentral<T, FS>(vel[ax], g, d, ax, cmp, ia + di, ja + dj, ka + dk));
   return rnu * (normal + trans);
 }
 
 // U_hat = U^n + dt [ -rho0 grad_c(alpha0 p^k) + R^{n+1/2} ] with
 // R = -div(U_h (x) u_h) + div(rho0 sigma) + rho0 b e_z - f e_z x (U_h - rho0 u_g)
 //     - beta(z) (U_h - rho0 (u_g, v_g, 0)); stored as u_hat = U_hat / rho0.
-template <typename T, bool WENO>
+template <typename T, bool WENO, bool FS>
 __global__ __launch_bounds__(kBlock) void momentum_kernel(
     Grid g, Dyn<T> d, Profiles<T> P, const T *__restrict__ uh, const T *__restrict__ vh,
     const T *__restrict__ wh, const T *__restrict__ un, const T *__restrict__ vn,
@@ -287,12 +288,12 @@ __global__ __launch_bounds__(kBlock) void momentum_kernel(
   const T invd[3] = {d.inv_dx, d.inv_dy, d.inv_dz};
 #pragma unroll
   for (int cmp = 0; cmp < 3; ++cmp) {
-    T R = advect<T, WENO>(g, d, mf, vel[cmp], vpar(d, cmp), c);
+    T R = advect<T, WENO>(g, d, mf, vel[cmp], vpar<T, FS>(cmp), c);
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const int di = ax == 0, dj = ax == 1, dk = ax == 2;
-      const T fp = sgs_face(g, d, vel, rnu_p[ax], ax, cmp, c.i, c.j, c.k);
-      const T fm = sgs_face(g, d, vel, rnu_m[ax], ax, cmp, c.i - di, c.j - dj, c.k - dk);
+      const T fp = sgs_face<T, FS>(g, d, vel, rnu_p[ax], ax, cmp, c.i, c.j, c.k);
+      const T fm = sgs_face<T, FS>(g, d, vel, rnu_m[ax], ax, cmp, c.i - di, c.j - dj, c.k - dk);
       R += (fp - fm) * invd[ax];
     }
     if (cmp == 2) R += r0 * b[q];
@@ -309,7 +310,10 @@ __global__ __launch_bounds__(kBlock) void momentum_kernel(
 template <typename T>
 void launch_sgs_nu(const Grid &g, const Dyn<T> &d, const T *u, const T *v, const T *w, const T *b,
                    T *nu, hipStream_t s) {
-  sgs_nu_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g, d, u, v, w, b, nu);
+  if (d.uv_par > T(0))
+    sgs_nu_kernel<T, true><<<blocks_for(g.n), kBlock, 0, s>>>(g, d, u, v, w, b, nu);
+  else
+    sgs_nu_kernel<T, false><<<blocks_for(g.n), kBlock, 0, s>>>(g, d, u, v, w, b, nu);
 }
 
 template <typename T>
@@ -329,12 +333,15 @@ template <typename T>
 void launch_momentum(const Grid &g, const Dyn<T> &d, const Profiles<T> &P, const T *uh,
                      const T *vh, const T *wh, const T *un, const T *vn, const T *wn, const T *p,
                      const T *b, const T *nu, T *uo, T *vo, T *wo, hipStream_t s) {
-  if (d.advection == LES_WENO3)
-    momentum_kernel<T, true><<<blocks_for(g.n), kBlock, 0, s>>>(g, d, P, uh, vh, wh, un, vn, wn,
-                                                                p, b, nu, uo, vo, wo);
-  else
-    momentum_kernel<T, false><<<blocks_for(g.n), kBlock, 0, s>>>(g, d, P, uh, vh, wh, un, vn, wn,
-                                                                 p, b, nu, uo, vo, wo);
+#define LES_MOM(WENO, FS)                                                                \
+  momentum_kernel<T, WENO, FS><<<blocks_for(g.n), kBlock, 0, s>>>(g, d, P, uh, vh, wh, un, vn, \
+                                                                  wn, p, b, nu, uo, vo, wo)
+  const bool weno = d.advection == LES_WENO3, fs = d.uv_par > T(0);
+  if (weno && fs) LES_MOM(true, true);
+  else if (weno) LES_MOM(true, false);
+  else if (fs) LES_MOM(false, true);
+  else LES_MOM(false, false);
+#undef LES_MOM
 }
 
 #define LES_INST(T)                                                                              \

@@ -1,27 +1,47 @@
 // Per-cell moist thermodynamics (paper Sec. 2.1-2.2) and the radiative
 // flux column (Sec. 2.1, theta_l equation).  The saturation adjustment
 // always iterates in FP64, whatever the storage precision.
+#include "les.h"
 #include "les_device.h"
 
 namespace lesmi {
 
 namespace {
 
-// Saturation specific humidity: Clausius-Clapeyron with constant L_v0
-// anchored at the triple point (the paper cites the formula's source
-// without printing it); q = eps e / (p0 - (1 - eps) e).
-__device__ __forceinline__ double qsat(const Thermo &c, double T, double p0) {
-  const double e = c.e_tr * exp(c.Lv_over_Rv * (c.inv_Ttr - 1.0 / T));
+// Saturation specific humidity over liquid (L = L_v0) or ice (L = L_s0):
+// Clausius-Clapeyron with a constant latent heat anchored at the triple
+// point (the paper cites the formula's source without printing it);
+// q = eps e / (p0 - (1 - eps) e).
+__device__ __forceinline__ double qsat_of(const Thermo &c, double L_over_Rv, double T, double p0) {
+  const double e = c.e_tr * exp(L_over_Rv * (c.inv_Ttr - 1.0 / T));
   return c.eps * e / (p0 - (1.0 - c.eps) * e);
+}
+
+// Share of the condensate that is liquid: H(T - T_f) (H(0) = 1), or the
+// linear ramp from T_ice to T_f for mixed-phase clouds.
+__device__ __forceinline__ double liquid_fraction(const Thermo &c, double T) {
+  if (c.phase == LES_PHASE_HEAVISIDE) return T >= c.Tf ? 1.0 : 0.0;
+  const double lam = (T - c.T_ice) * c.inv_ramp;
+  return lam < 0.0 ? 0.0 : (lam > 1.0 ? 1.0 : lam);
 }
 
 struct Phase {
   double ql, qi;
 };
 
+// Saturation humidity of the partition, lam q*(liquid) + (1 - lam) q*(ice)
+// (the ice term only where some condensate is ice).
+__device__ __forceinline__ double qstar(const Thermo &c, double lam, double T, double p0) {
+  const double ql = qsat_of(c, c.Lv_over_Rv, T, p0);
+  return lam == 1.0 ? ql : lam * ql + (1.0 - lam) * qsat_of(c, c.Ls_over_Rv, T, p0);
+}
+
+// q_c = max(0, q_t - q*), split as lam q_c liquid and the rest ice.
 __device__ __forceinline__ Phase partition(const Thermo &c, double T, double qt, double p0) {
-  const double qc = fmax(0.0, qt - qsat(c, T, p0));
-  return T >= c.Tf ? Phase{qc, 0.0} : Phase{0.0, qc};
+  const double lam = liquid_fraction(c, T);
+  const double qc = fmax(0.0, qt - qstar(c, lam, T, p0));
+  const double ql = lam * qc;
+  return Phase{ql, qc - ql};
 }
 
 __device__ __forceinline__ double cp_moist(const Thermo &c, double qt, double ql, double qi) {
@@ -57,7 +77,7 @@ struct CellState {
 __device__ CellState saturation_adjust(const Thermo &c, double thl, double qt, double p0,
                                        double lnp) {
   const double tu = thl * exner(c, lnp, qt, 0.0, 0.0);
-  const double qs = qsat(c, tu, p0);
+  const double qs = qstar(c, liquid_fraction(c, tu), tu, p0);
   if (qt <= qs) return CellState{tu, 0.0, 0.0};
   double ta = tu, tb = tu + c.Lv0 * (qt - qs) / c.cpd;
   double fa = thl_residual(c, ta, thl, qt, p0, lnp);

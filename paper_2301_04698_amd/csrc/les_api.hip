@@ -51,9 +51,9 @@ struct Layout {
 
 int validate(const les_config *c) {
   if (!c) return fail(LES_ERR_ARG, "config is NULL");
-  if (c->nx < 1 || c->ny < 1 || c->nz < 4)
-    return fail(LES_ERR_ARG, "grid %dx%dx%d: nx, ny must be >= 1 and nz >= 4", c->nx, c->ny,
-                c->nz);
+  if (c->nx < 2 || c->ny < 1 || c->nz < 4)
+    return fail(LES_ERR_ARG, "grid %dx%dx%d: nx must be >= 2, ny >= 1 and nz >= 4", c->nx,
+                c->ny, c->nz);
   if ((int64_t)c->nx * c->ny > (int64_t)1 << 30 || (int64_t)c->nx * c->ny * c->nz > (int64_t)1 << 34)
     return fail(LES_ERR_ARG, "grid too large");
   if (!(c->dx > 0) || !(c->dy > 0) || !(c->dz > 0) || !(c->dt > 0))
@@ -84,6 +84,10 @@ int validate(const les_config *c) {
     return fail(LES_ERR_ARG, "unknown wall condition %d", c->wall);
   if (!(c->nu_const >= 0) || c->nu_const > 1e6)
     return fail(LES_ERR_ARG, "nu_const must be in [0, 1e6]");
+  if (c->phase != LES_PHASE_HEAVISIDE && c->phase != LES_PHASE_RAMP)
+    return fail(LES_ERR_ARG, "unknown phase partition %d", c->phase);
+  if (c->phase == LES_PHASE_RAMP && !(c->T_ice > 0 && c->T_ice < c->Tf))
+    return fail(LES_ERR_ARG, "T_ice must be in (0, Tf) for LES_PHASE_RAMP");
   if (c->guess < LES_GUESS_ZERO || c->guess > LES_GUESS_LEARNED)
     return fail(LES_ERR_ARG, "unknown guess mode %d", c->guess);
   return LES_OK;
@@ -774,6 +778,7 @@ void les_default_config(les_config *c) {
   c->e_tr = 611.657;
   c->T_tr = 273.16;
   c->satadj_tol = 1e-10;
+  c->T_ice = 233.15;
 }
 
 size_t les_workspace_bytes(const les_config *cfg) {
@@ -818,6 +823,7 @@ int les_init(const les_config *cfg, const les_buffers *bufs, void *stream, les_h
   g.ny = cfg->ny;
   g.nz = cfg->nz;
   g.nxy = (int64_t)cfg->nx * cfg->ny;
+  g.sy = cfg->ny == 1 ? 0 : cfg->nx;
   g.n = g.nxy * cfg->nz;
   g.dx = cfg->dx;
   g.dy = cfg->dy;
@@ -838,7 +844,11 @@ int les_init(const les_config *cfg, const les_buffers *bufs, void *stream, les_h
   t.e_tr = cfg->e_tr;
   t.inv_Ttr = 1.0 / cfg->T_tr;
   t.Lv_over_Rv = cfg->Lv0 / cfg->Rv;
+  t.Ls_over_Rv = cfg->Ls0 / cfg->Rv;
   t.eps = cfg->Rd / cfg->Rv;
+  t.phase = cfg->phase;
+  t.T_ice = cfg->T_ice;
+  t.inv_ramp = cfg->phase == LES_PHASE_RAMP ? 1.0 / (cfg->Tf - cfg->T_ice) : 0.0;
   t.satadj_tol = cfg->satadj_tol;
   t.satadj_maxit = cfg->satadj_maxit;
   jacobi_spectrum(cfg, &h->mu_min, &h->mu_max);

@@ -5,11 +5,10 @@
 
 namespace lesmi {
 
-// Periodic neighbour index for offsets |o| <= 2: one wrap suffices for
-// n >= 2; an axis of one cell (a two-dimensional run) maps every offset to 0.
-__device__ __forceinline__ int pwrap(int i, int n) {
-  return n == 1 ? 0 : (i < 0 ? i + n : (i >= n ? i - n : i));
-}
+// Periodic neighbour index for offsets |o| <= 2; one wrap suffices for
+// n >= 2.  A y axis of one cell (a two-dimensional run) leaves j in
+// [-1, 1], which gload multiplies by a zero row stride.
+__device__ __forceinline__ int pwrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 // Mirror across the walls z = 0 and z = H: level -1 -> 0, -2 -> 1, nz -> nz-1, nz+1 -> nz-2.
 __device__ __forceinline__ int zmirror(int k, int nz) {
@@ -25,7 +24,7 @@ __device__ __forceinline__ T gload(const T *__restrict__ f, const Grid &g, int i
   i = pwrap(i, g.nx);
   j = pwrap(j, g.ny);
   int km = zmirror(k, g.nz);
-  T v = f[(int64_t)i + (int64_t)g.nx * j + g.nxy * km];
+  T v = f[(int64_t)i + g.sy * j + g.nxy * km];
   return km == k ? v : parity * v;
 }
 

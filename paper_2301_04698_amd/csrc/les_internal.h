@@ -14,15 +14,18 @@ namespace lesmi {
 struct Grid {
   int nx, ny, nz;
   int64_t nxy, n;
+  int64_t sy;  // row stride of the periodic y wrap: nx, or 0 when ny == 1
   double dx, dy, dz, dt;
 };
 
 // Constants needed by the per-cell thermodynamics (always FP64).
 struct Thermo {
   double p00, Rd, Rv, cpd, cpv, cl, ci, Lv0, Ls0, Tf, g;
-  double e_tr, inv_Ttr, Lv_over_Rv, eps;  // saturation vapour pressure
+  double e_tr, inv_Ttr, Lv_over_Rv, Ls_over_Rv, eps;  // saturation vapour pressure
+  double T_ice, inv_ramp;  // LES_PHASE_RAMP: liquid share (T - T_ice) / (Tf - T_ice)
   double satadj_tol;
   int satadj_maxit;
+  int phase;               // LES_PHASE_HEAVISIDE or LES_PHASE_RAMP
 };
 
 // Vertical profiles (device pointers, nz entries each).

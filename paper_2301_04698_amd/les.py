@@ -23,6 +23,8 @@ LES_QUICK, LES_WENO3 = 0, 1
 ADVECTION = {"quick": LES_QUICK, "weno3": LES_WENO3}
 LES_NO_SLIP, LES_FREE_SLIP = 0, 1
 WALLS = {"no_slip": LES_NO_SLIP, "free_slip": LES_FREE_SLIP}
+LES_PHASE_HEAVISIDE, LES_PHASE_RAMP = 0, 1
+PHASES = {"heaviside": LES_PHASE_HEAVISIDE, "ramp": LES_PHASE_RAMP}
 LES_GUESS_ZERO, LES_GUESS_EXTRAPOLATE, LES_GUESS_PREVIOUS, LES_GUESS_LEARNED = 0, 1, 2, 3
 GUESS_MODES = {"zero": LES_GUESS_ZERO, "extrapolate": LES_GUESS_EXTRAPOLATE,
                "previous": LES_GUESS_PREVIOUS, "learned": LES_GUESS_LEARNED}
@@ -56,7 +58,8 @@ class LesConfig(C.Structure):
         ("rad_F0", C.c_double), ("rad_kappa", C.c_double),
         ("e_tr", C.c_double), ("T_tr", C.c_double), ("satadj_tol", C.c_double),
         ("guess", C.c_int32), ("advection", C.c_int32),
-        ("wall", C.c_int32), ("reserved", C.c_int32), ("nu_const", C.c_double),
+        ("wall", C.c_int32), ("phase", C.c_int32), ("nu_const", C.c_double),
+        ("T_ice", C.c_double),
     ]
 
 
@@ -166,8 +169,9 @@ def make_config(p: dict) -> LesConfig:
         elif name == "wall":
             v = p.get("wall", "no_slip")
             c.wall = WALLS[v] if isinstance(v, str) else int(v)
-        elif name == "reserved":
-            c.reserved = 0
+        elif name == "phase":
+            v = p.get("phase", "heaviside")
+            c.phase = PHASES[v] if isinstance(v, str) else int(v)
         elif name == "guess":
             v = p.get("guess", "zero")
             c.guess = GUESS_MODES[v] if isinstance(v, str) else int(v)

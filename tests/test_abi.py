@@ -83,7 +83,8 @@ def test_make_config_carries_every_parameter(lib, oracle_lib):
 
 @pytest.mark.parametrize("override,needle", [
     (dict(nz=3), "nz >= 4"),
-    (dict(ny=0), "nx, ny must be >= 1"),
+    (dict(ny=0), "nx must be >= 2, ny >= 1"),
+    (dict(nx=1), "nx must be >= 2, ny >= 1"),
     (dict(wall=7), "wall condition"),
     (dict(nu_const=-1.0), "nu_const"),
     (dict(dt=0.0), "> 0"),

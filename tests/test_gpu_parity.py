@@ -138,6 +138,83 @@ def test_thermo_matches_oracle(gpu, oracle_lib, precision):
         assert np.abs(g["T"].cpu().numpy() - o["T"]).max() <= 1e-9
 
 
+def _heaviside_gap(oracle_lib, p, thl, qt):
+    """Cells whose theta_l lies in the jump of theta_l*(T) at T_f under the
+    Heaviside partition (all-ice just below T_f, all-liquid at it), widened
+    by 1e-3 K: there the adjustment has no root (or one at the jump), and
+    where the secant ends is not unique."""
+    p0 = oracle_lib.reference_state(p)["p0"]
+    tf = p["Tf"]
+    gap = np.zeros(thl.shape, bool)
+    for k, j, i in np.ndindex(*thl.shape):
+        q, pk = qt[k, j, i], p0[k]
+        liq = oracle_lib.theta_l(p, tf, max(0.0, q - oracle_lib.qv_sat(p, tf, pk)), 0.0, q, pk)
+        ice = oracle_lib.theta_l(p, tf, 0.0, max(0.0, q - oracle_lib.qv_sat_ice(p, tf, pk)), q, pk)
+        gap[k, j, i] = min(liq, ice) - 1e-3 < thl[k, j, i] < max(liq, ice) + 1e-3
+    return gap, p0
+
+
+@pytest.mark.parametrize("phase", ["heaviside", "ramp"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_thermo_ice_and_mixed_phase_matches_oracle(gpu, oracle_lib, phase, precision):
+    """Cold states from all-ice through mixed phase to all-liquid (T about
+    200 to 290 K over a 4 km column), saturated and not, in both partition
+    modes (Sec. 2.2).  Under the Heaviside partition, cells inside the jump
+    of theta_l* at T_f have no unique result: they are checked for validity
+    (T within 1 K of T_f, liquid consistent with the side of T_f), the
+    others element by element."""
+    import torch
+    p = li.workload("C1", nx=16, ny=16, nz=32, dz=125.0, theta0=265.0, phase=phase,
+                    precision=precision)
+    shape = (p["nz"], p["ny"], p["nx"])
+    rng = np.random.default_rng(1)
+    thl = rng.uniform(235.0, 290.0, shape)
+    qt = rng.uniform(0.0, 10e-3, shape)
+    if precision == "fp32":
+        thl = thl.astype(np.float32).astype(np.float64)
+        qt = qt.astype(np.float32).astype(np.float64)
+    o = oracle_lib.thermo(p, thl, qt)
+    assert (o["qi"] > 0).mean() > 0.3 and (o["ql"] > 0).mean() > 0.03
+    if phase == "ramp":
+        assert ((o["qi"] > 0) & (o["ql"] > 0)).mean() > 0.3
+    sim = gpu.LES(p)
+    g = {k: v.double().cpu().numpy() for k, v in sim.thermo(torch.from_numpy(thl),
+                                                            torch.from_numpy(qt)).items()}
+    keep = np.ones(shape, bool)
+    if phase == "heaviside":
+        gap, p0 = _heaviside_gap(oracle_lib, p, thl, qt)
+        assert 0 < gap.sum() < 0.02 * gap.size
+        keep = ~gap
+        for k, j, i in zip(*np.nonzero(gap)):
+            T = g["T"][k, j, i]
+            assert abs(T - p["Tf"]) <= 1.0
+            if T < p["Tf"]:
+                assert g["ql"][k, j, i] == 0.0
+            else:
+                ql = max(0.0, qt[k, j, i] - oracle_lib.qv_sat(p, T, p0[k]))
+                assert g["ql"][k, j, i] == pytest.approx(ql, rel=1e-5, abs=1e-12)
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    for k in ("T", "ql", "b"):
+        e = rel(g[k][keep], o[k][keep])
+        assert e <= tol, (k, e)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-5)])
+def test_step_cold_mixed_phase_matches_oracle(gpu, oracle_lib, precision, tol):
+    """The cold workload: a cloud of liquid and ice partitioned by the ramp,
+    with surface fluxes and radiation (liquid path), perturbed velocity."""
+    p = li.workload("C1i", precision=precision, poisson_scheme="chebyshev",
+                    poisson_tol=1e-9 if precision == "fp64" else 1e-6)
+    if precision == "fp32":
+        p = dict(p, nx=40, ny=24)
+    st0 = with_velocity_noise(p, li.initial_state(p), 0.3, 14)
+    if precision == "fp32":
+        st0 = {k: v.astype(np.float32).astype(np.float64) for k, v in st0.items()}
+    errs, *_ = _compare_step(gpu, oracle_lib, p, st0, 2 if precision == "fp64" else 1, tol)
+    for k, e in errs.items():
+        assert e <= tol, (k, e, errs)
+
+
 # ------------------------------------------------------------ full step
 
 def _compare_step(gpu, oracle_lib, p, st0, nsteps, tol, debug=False):

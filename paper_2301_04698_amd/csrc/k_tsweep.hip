@@ -12,8 +12,9 @@
 // is the same from sweep to sweep and accumulates in the slow modes.
 //
 // One sweep: each thread owns one column of a 64 x TY thread tile and
-// marches up z with the vertical neighbours in registers; x/y neighbours
-// come through the L1/L2 caches.  16 bytes per cell (Chebyshev: phi, prev,
+// marches up z with the vertical neighbours in registers; x neighbours come
+// from the adjacent lanes of the wavefront, y neighbours through the L1/L2
+// caches.  16 bytes per cell (Chebyshev: phi, prev,
 // rhs in, phi' out).  When the four arrays fit the 256 MB Infinity Cache
 // they stay there from sweep to sweep (64 x 4 tiles, ordinary accesses);
 // beyond it the arrays read once per sweep (prev, rhs) and the output are
@@ -103,6 +104,27 @@ __device__ __forceinline__ T ld_stream(const T *p, bool nt) {
   return nt ? __builtin_nontemporal_load(p) : *p;
 }
 
+// Value of v in the next (+1) or previous (-1) lane of the 64-wide
+// wavefront by DPP wave shifts; a lane without a source keeps its own value
+// (the caller replaces the end lanes).  A double moves as two 32-bit halves.
+template <int DIR>
+__device__ __forceinline__ float lane_shift(float v) {
+  const int x = __float_as_int(v);
+  return __int_as_float(__builtin_amdgcn_update_dpp(x, x, DIR > 0 ? 0x130 : 0x138, 0xF, 0xF, false));
+}
+template <int DIR>
+__device__ __forceinline__ double lane_shift(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int ctrl = DIR > 0 ? 0x130 : 0x138;
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, ctrl, 0xF, 0xF, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, ctrl, 0xF, 0xF, false));
+}
+
+// One wave per 64-cell row of the tile.  The x neighbours of a cell are the
+// iterate values its neighbouring lanes already hold (wave shifts); only the
+// row's end lanes load theirs, so each plane row is read once.  Every lane
+// of a row marches (the shifts need them): lanes beyond nx read the row's
+// last cell and neither store nor count in the residual.
 template <typename T, int TY, bool CHEB, bool CHECK, bool NT>
 __global__ __launch_bounds__(64 * TY) void sweep1_kernel(SweepArgs<T> a) {
   if (a.ctl->done) return;
@@ -111,32 +133,41 @@ __global__ __launch_bounds__(64 * TY) void sweep1_kernel(SweepArgs<T> a) {
   double acc = 0.0;
   if (tile < a.ntiles) {
     const TileIdx t = tile_of(tile, a.tiles_x, a.tiles_y, a.kc, g.nz);
-    const int i = t.tx * 64 + (int)(threadIdx.x & 63);
+    const int lane = (int)(threadIdx.x & 63);
+    const int i = t.tx * 64 + lane;
     const int j = t.ty * TY + (int)(threadIdx.x >> 6);
-    if (i < g.nx && j < g.ny) {
-      const int ip = i + 1 == g.nx ? 0 : i + 1, im = i == 0 ? g.nx - 1 : i - 1;
+    if (j < g.ny) {  // uniform per wave
+      const bool valid = i < g.nx;
+      const int ic = valid ? i : g.nx - 1;
+      const int ip = ic + 1 == g.nx ? 0 : ic + 1, im = ic == 0 ? g.nx - 1 : ic - 1;
       const int jp = j + 1 == g.ny ? 0 : j + 1, jm = j == 0 ? g.ny - 1 : j - 1;
-      const int64_t col = (int64_t)i + (int64_t)g.nx * j;
-      const int64_t oxp = ip - i, oxm = im - i;
+      const int64_t col = (int64_t)ic + (int64_t)g.nx * j;
+      const int64_t oxp = ip - ic, oxm = im - ic;
       const int64_t oyp = (int64_t)(jp - j) * g.nx, oym = (int64_t)(jm - j) * g.nx;
-      const bool cheb = CHEB && !a.first;
+      const bool load_xp = lane == 63 || ic + 1 >= g.nx, load_xm = lane == 0;
+      constexpr bool cheb = CHEB;  // the first sweep of a solve launches as CHEB = false
       T below = a.cur[col + g.nxy * (t.k0 > 0 ? t.k0 - 1 : 0)];
       T c = a.cur[col + g.nxy * t.k0];
       for (int k = t.k0; k < t.k1; ++k) {
         const int64_t q = col + g.nxy * k;
         const T above = a.cur[q + (k + 1 < g.nz ? g.nxy : 0)];
-        const double hx = (double)a.cur[q + oxp] + (double)a.cur[q + oxm];
+        T xp = lane_shift<1>(c), xm = lane_shift<-1>(c);
+        if (load_xp) xp = a.cur[q + oxp];
+        if (load_xm) xm = a.cur[q + oxm];
+        const double hx = (double)xp + (double)xm;
         const double hy = (double)a.cur[q + oyp] + (double)a.cur[q + oym];
         const double hz = (double)above + (double)below;
         const double res =
             point_residual(a.k, (double)c, hx, hy, hz, (double)ld_stream(&a.rhs[q], NT));
-        if (CHECK) acc += res * res;
+        if (CHECK && valid) acc += res * res;
         const double pv = cheb ? (double)ld_stream(&a.prev[q], NT) : 0.0;
         const T out = (T)point_update(a.k, (double)c, res, cheb, pv, a.wc0);
-        if (NT)
-          __builtin_nontemporal_store(out, &a.out_last[q]);
-        else
-          a.out_last[q] = out;
+        if (valid) {
+          if (NT)
+            __builtin_nontemporal_store(out, &a.out_last[q]);
+          else
+            a.out_last[q] = out;
+        }
         below = c;
         c = above;
       }
@@ -349,7 +380,7 @@ void launch_tsweep(const Grid &g, int S, bool chebyshev, bool check, bool first,
 #define LES_PICK(TY, NT)                                                              \
   do {                                                                                \
     const dim3 block(64 * TY);                                                        \
-    if (chebyshev) {                                                                  \
+    if (chebyshev && !first) {                                                        \
       if (check) sweep1_kernel<T, TY, true, true, NT><<<grid, block, 0, s>>>(a);      \
       else sweep1_kernel<T, TY, true, false, NT><<<grid, block, 0, s>>>(a);           \
     } else {                                                                          \

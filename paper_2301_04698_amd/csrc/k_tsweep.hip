@@ -120,11 +120,68 @@ __device__ __forceinline__ double lane_shift(double v) {
                           __builtin_amdgcn_update_dpp(lo, lo, ctrl, 0xF, 0xF, false));
 }
 
-// One wave per 64-cell row of the tile.  The x neighbours of a cell are the
-// iterate values its neighbouring lanes already hold (wave shifts); only the
-// row's end lanes load theirs, so each plane row is read once.  Every lane
-// of a row marches (the shifts need them): lanes beyond nx read the row's
-// last cell and neither store nor count in the residual.
+// z-march of one 64-cell row (one wave) of a tile over levels [k0, k1):
+// one Chebyshev (or, CHEB = false, weighted-Jacobi) sweep of each cell,
+// returning its FP64 residual sum when CHECK.  SHIFT: the x neighbours of a
+// cell are the iterate values its neighbouring lanes already hold (DPP wave
+// shifts) and only the row's end lanes load theirs, so each plane row is
+// read once; otherwise they are loaded.  FULL: all 64 cells of the row lie
+// inside the grid, so no lane is predicated off (a predicated store makes
+// the compiler wait for that store before the next level); a ragged row's
+// lanes beyond nx march on the row's last cell, for the shifts, but neither
+// store nor count in the residual.
+template <bool FULL, bool SHIFT, bool CHEB, bool CHECK, bool NT, typename T>
+__device__ __forceinline__ double march_row(const SweepArgs<T> &a, const TileIdx &t, int lane,
+                                            int i, int j) {
+  const Grid &g = a.g;
+  const bool valid = FULL || i < g.nx;
+  const int ic = valid ? i : g.nx - 1;
+  const int ip = ic + 1 == g.nx ? 0 : ic + 1, im = ic == 0 ? g.nx - 1 : ic - 1;
+  const int jp = j + 1 == g.ny ? 0 : j + 1, jm = j == 0 ? g.ny - 1 : j - 1;
+  const int64_t col = (int64_t)ic + (int64_t)g.nx * j;
+  const int64_t oxp = ip - ic, oxm = im - ic;
+  const int64_t oyp = (int64_t)(jp - j) * g.nx, oym = (int64_t)(jm - j) * g.nx;
+  const bool load_xp = lane == 63 || ic + 1 >= g.nx, load_xm = lane == 0;
+  double acc = 0.0;
+  T below = a.cur[col + g.nxy * (t.k0 > 0 ? t.k0 - 1 : 0)];
+  T c = a.cur[col + g.nxy * t.k0];
+  for (int k = t.k0; k < t.k1; ++k) {
+    const int64_t q = col + g.nxy * k;
+    const T above = a.cur[q + (k + 1 < g.nz ? g.nxy : 0)];
+    T xp, xm;
+    if (SHIFT) {
+      xp = lane_shift<1>(c);
+      xm = lane_shift<-1>(c);
+      if (load_xp) xp = a.cur[q + oxp];
+      if (load_xm) xm = a.cur[q + oxm];
+    } else {
+      xp = a.cur[q + oxp];
+      xm = a.cur[q + oxm];
+    }
+    const double hx = (double)xp + (double)xm;
+    const double hy = (double)a.cur[q + oyp] + (double)a.cur[q + oym];
+    const double hz = (double)above + (double)below;
+    const double res =
+        point_residual(a.k, (double)c, hx, hy, hz, (double)ld_stream(&a.rhs[q], NT));
+    if (CHECK && valid) acc += res * res;
+    const double pv = CHEB ? (double)ld_stream(&a.prev[q], NT) : 0.0;
+    const T out = (T)point_update(a.k, (double)c, res, CHEB, pv, a.wc0);
+    if (valid) {
+      if (NT)
+        __builtin_nontemporal_store(out, &a.out_last[q]);
+      else
+        a.out_last[q] = out;
+    }
+    below = c;
+    c = above;
+  }
+  return acc;
+}
+
+// One wave per 64-cell row of a 64 x TY tile; the first sweep of a solve
+// (weight 1, no previous iterate) launches as CHEB = false.  Lane shifts
+// only for TY > 1: one-row tiles (two-dimensional grids, a block per wave,
+// few waves per CU) measured faster with loaded x neighbours.
 template <typename T, int TY, bool CHEB, bool CHECK, bool NT>
 __global__ __launch_bounds__(64 * TY) void sweep1_kernel(SweepArgs<T> a) {
   if (a.ctl->done) return;
@@ -136,41 +193,14 @@ __global__ __launch_bounds__(64 * TY) void sweep1_kernel(SweepArgs<T> a) {
     const int lane = (int)(threadIdx.x & 63);
     const int i = t.tx * 64 + lane;
     const int j = t.ty * TY + (int)(threadIdx.x >> 6);
+    constexpr bool kShift = TY > 1;
     if (j < g.ny) {  // uniform per wave
-      const bool valid = i < g.nx;
-      const int ic = valid ? i : g.nx - 1;
-      const int ip = ic + 1 == g.nx ? 0 : ic + 1, im = ic == 0 ? g.nx - 1 : ic - 1;
-      const int jp = j + 1 == g.ny ? 0 : j + 1, jm = j == 0 ? g.ny - 1 : j - 1;
-      const int64_t col = (int64_t)ic + (int64_t)g.nx * j;
-      const int64_t oxp = ip - ic, oxm = im - ic;
-      const int64_t oyp = (int64_t)(jp - j) * g.nx, oym = (int64_t)(jm - j) * g.nx;
-      const bool load_xp = lane == 63 || ic + 1 >= g.nx, load_xm = lane == 0;
-      constexpr bool cheb = CHEB;  // the first sweep of a solve launches as CHEB = false
-      T below = a.cur[col + g.nxy * (t.k0 > 0 ? t.k0 - 1 : 0)];
-      T c = a.cur[col + g.nxy * t.k0];
-      for (int k = t.k0; k < t.k1; ++k) {
-        const int64_t q = col + g.nxy * k;
-        const T above = a.cur[q + (k + 1 < g.nz ? g.nxy : 0)];
-        T xp = lane_shift<1>(c), xm = lane_shift<-1>(c);
-        if (load_xp) xp = a.cur[q + oxp];
-        if (load_xm) xm = a.cur[q + oxm];
-        const double hx = (double)xp + (double)xm;
-        const double hy = (double)a.cur[q + oyp] + (double)a.cur[q + oym];
-        const double hz = (double)above + (double)below;
-        const double res =
-            point_residual(a.k, (double)c, hx, hy, hz, (double)ld_stream(&a.rhs[q], NT));
-        if (CHECK && valid) acc += res * res;
-        const double pv = cheb ? (double)ld_stream(&a.prev[q], NT) : 0.0;
-        const T out = (T)point_update(a.k, (double)c, res, cheb, pv, a.wc0);
-        if (valid) {
-          if (NT)
-            __builtin_nontemporal_store(out, &a.out_last[q]);
-          else
-            a.out_last[q] = out;
-        }
-        below = c;
-        c = above;
-      }
+      // Streamed (HBM-bound) sweeps keep the predicated march for full rows
+      // too: its wait on each level's store measured faster there.
+      if (!NT && t.tx * 64 + 64 <= g.nx)  // uniform per wave
+        acc = march_row<true, kShift, CHEB, CHECK, NT>(a, t, lane, i, j);
+      else
+        acc = march_row<false, kShift, CHEB, CHECK, NT>(a, t, lane, i, j);
     }
   }
   if (CHECK) {

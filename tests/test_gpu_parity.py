@@ -67,6 +67,25 @@ def test_poisson_fp64_matches_oracle(gpu, oracle_lib, shape, scheme):
     assert e <= 1e-11, e
 
 
+@pytest.mark.parametrize("shape", [(8, 1, 2), (8, 3, 2), (6, 2, 3), (5, 1, 65), (4, 3, 129)])
+def test_poisson_degenerate_grids_match_oracle(gpu, oracle_lib, shape):
+    """The smallest grids the library accepts and rows that end one cell into
+    a wavefront: nx = 2, 3 (every lane but the first one or two idle, both
+    end lanes load their x neighbours), ny = 1..3 (one-row tiles), nx = 65
+    and 129 (a second or third wavefront holding a single cell)."""
+    import torch
+    nz, ny, nx = shape
+    p = li.workload("C1", nx=nx, ny=ny, nz=nz, dx=40.0, dy=30.0, dz=10.0, poisson_tol=1e-10,
+                    poisson_scheme="chebyshev")
+    rhs = li.random_field(shape, seed=22)
+    phi_o, st_o = oracle_lib.poisson(p, rhs)
+    sim = gpu.LES(p)
+    phi_g, st_g, rc = sim.poisson_solve(torch.from_numpy(rhs), fixed_sweeps=st_o["sweeps"])
+    assert st_g["sweeps"] == st_o["sweeps"] and st_o["status"] == 0
+    e = rel(phi_g.cpu().numpy(), phi_o)
+    assert e <= 1e-11, e
+
+
 @pytest.mark.parametrize("scheme", ["jacobi", "chebyshev"])
 def test_poisson_fp32_matches_oracle(gpu, oracle_lib, scheme):
     import torch
@@ -395,6 +414,18 @@ def test_two_dimensional_sweeps_one_vs_two_per_launch(gpu):
         phi, st, rc = sim.poisson_solve(rhs.float(), fixed_sweeps=60)
         out.append(phi.double().cpu().numpy())
     assert np.array_equal(out[0], out[1])
+
+
+def test_all_options_fp32_matches_oracle(gpu, oracle_lib):
+    """WENO3, the mixed-phase ramp, free-slip walls and a uniform viscosity
+    together on the cold workload's physics, ragged grid, FP32."""
+    p = li.workload("C1i", nx=40, ny=24, precision="fp32", poisson_scheme="chebyshev",
+                    poisson_tol=1e-6, advection="weno3", wall="free_slip", nu_const=2.0)
+    st0 = with_velocity_noise(p, li.initial_state(p), 0.3, 15)
+    st0 = {k: v.astype(np.float32).astype(np.float64) for k, v in st0.items()}
+    errs, *_ = _compare_step(gpu, oracle_lib, p, st0, 1, 1e-5)
+    for k, e in errs.items():
+        assert e <= 1e-5, (k, e, errs)
 
 
 def test_step_rest_state_steady(gpu):

@@ -136,12 +136,6 @@ Layout layout_of(const les_config *c) {
   return L;
 }
 
-// Small host-visible status of a solve written by the device when it stops.
-struct HostFlag {
-  int32_t done;
-  int32_t pad[15];
-};
-
 }  // namespace
 
 struct les_handle {

@@ -38,8 +38,8 @@ CASE_LABEL = {"cloud_layer": "synthetic stratocumulus",
 SWEEP_SOURCE = os.path.join(ROOT, "paper_2301_04698_amd", "csrc", "k_tsweep.hip")
 GUESS_WEIGHTS = os.path.join(ROOT, "paper_2301_04698_amd", "weights", "guess_256x256x128.npy")
 MEASURED_TRAFFIC = {
-    "sha256": "77e1c9b14f077d1c",
-    "bytes": {(256, 256, 128): 104_920_448 + 33_554_432, (512, 512, 256): 826_123_776 + 268_435_456},
+    "sha256": "5ffc39c7e724ab27",
+    "bytes": {(256, 256, 128): 104_618_496 + 33_554_432, (512, 512, 256): 850_375_616 + 268_435_456},
 }
 
 def measured_traffic(p, S):
@@ -132,10 +132,13 @@ def sweep_kernel_name(p, S):
     if S != 1:
         return f"sweep2_kernel<{T}, 8, {cheb}, false>"
     streamed = 4.0 * p["nx"] * p["ny"] * p["nz"] * es > 192e6
-    ty = 16 if streamed else 4
-    if p["ny"] < ty:
-        ty = 1 if p["ny"] < 4 else 4
-    return f"sweep1_kernel<{T}, {ty}, {cheb}, false, {'true' if streamed else 'false'}>"
+    if p["nx"] >= 256 and p["ny"] >= 4:
+        wx, ty = 4, (4 if streamed else 2)
+    else:
+        wx, ty = 1, (16 if streamed else 4)
+        if p["ny"] < ty:
+            ty = 1 if p["ny"] < 4 else 4
+    return f"sweep1_kernel<{T}, {wx}, {ty}, {cheb}, false, {'true' if streamed else 'false'}>"
 
 
 def sweep_bytes_per_cell(p):

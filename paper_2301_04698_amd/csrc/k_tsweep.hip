@@ -11,15 +11,16 @@
 // written as (N - rhs)/D - phi cancels catastrophically; its rounding error
 // is the same from sweep to sweep and accumulates in the slow modes.
 //
-// One sweep: each thread owns one column of a 64 x TY thread tile and
-// marches up z with the vertical neighbours in registers; x neighbours come
-// from the adjacent lanes of the wavefront, y neighbours through the L1/L2
-// caches.  16 bytes per cell (Chebyshev: phi, prev,
-// rhs in, phi' out).  When the four arrays fit the 256 MB Infinity Cache
-// they stay there from sweep to sweep (64 x 4 tiles, ordinary accesses);
-// beyond it the arrays read once per sweep (prev, rhs) and the output are
-// streamed with non-temporal accesses so the caches keep the iterate's
-// neighbour rows, and taller 64 x 16 tiles halve the y-halo re-reads.
+// One sweep: each thread owns one column of the tile and marches up z
+// with the vertical neighbours in registers; x neighbours come from the
+// adjacent lanes of the wavefront, y neighbours through the L1/L2 caches.
+// 16 bytes per cell (Chebyshev: phi, prev, rhs in, phi' out).  Grids at
+// least 256 cells wide take 256-cell-wide tiles (four waves side by side):
+// 256 x 2 while the four arrays fit the 256 MB Infinity Cache, 256 x 4
+// beyond it, where the arrays read once per sweep (prev, rhs) and the
+// output are streamed with non-temporal accesses so the caches keep the
+// iterate's neighbour rows.  Narrower grids take 64 x 4 (or 64 x 16
+// streamed, 64 x 1 for ny < 4) tiles.
 //
 // Two sweeps: a 64 x TY thread tile covers a 62 x (TY-2) core plus a
 // one-cell ring.  Every thread computes the first sweep for its own column
@@ -98,6 +99,10 @@ __device__ __forceinline__ TileIdx tile_of(int tile, int tiles_x, int tiles_y, i
 
 constexpr int kTY1 = 4;       // cache-resident arrays
 constexpr int kTY1Big = 16;   // streamed arrays
+// Grids at least kWideNx wide take tiles of kWX waves side by side along x
+// (256-cell rows): longer contiguous runs per plane row and fewer halo
+// planes per cell; kWideTY rows when cache-resident, kWideTYBig streamed.
+constexpr int kWideNx = 256, kWX = 4, kWideTY = 2, kWideTYBig = 4;
 
 template <typename T>
 __device__ __forceinline__ T ld_stream(const T *p, bool nt) {
@@ -178,26 +183,29 @@ __device__ __forceinline__ double march_row(const SweepArgs<T> &a, const TileIdx
   return acc;
 }
 
-// One wave per 64-cell row of a 64 x TY tile; the first sweep of a solve
-// (weight 1, no previous iterate) launches as CHEB = false.  Lane shifts
-// only for TY > 1: one-row tiles (two-dimensional grids, a block per wave,
-// few waves per CU) measured faster with loaded x neighbours.
-template <typename T, int TY, bool CHEB, bool CHECK, bool NT>
-__global__ __launch_bounds__(64 * TY) void sweep1_kernel(SweepArgs<T> a) {
+// A 64 WX x TY tile: wave (wx, wy) owns the 64 cells of row ty TY + wy
+// starting at x = tx 64 WX + 64 wx.  The first sweep of a solve (weight 1,
+// no previous iterate) launches as CHEB = false.  Lane shifts only in
+// blocks of several waves: one-wave blocks (two-dimensional grids, few waves
+// per CU) measured faster with loaded x neighbours.
+template <typename T, int WX, int TY, bool CHEB, bool CHECK, bool NT>
+__global__ __launch_bounds__(64 * WX * TY) void sweep1_kernel(SweepArgs<T> a) {
   if (a.ctl->done) return;
   const Grid &g = a.g;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   double acc = 0.0;
   if (tile < a.ntiles) {
     const TileIdx t = tile_of(tile, a.tiles_x, a.tiles_y, a.kc, g.nz);
-    const int lane = (int)(threadIdx.x & 63);
-    const int i = t.tx * 64 + lane;
-    const int j = t.ty * TY + (int)(threadIdx.x >> 6);
-    constexpr bool kShift = TY > 1;
-    if (j < g.ny) {  // uniform per wave
-      // Streamed (HBM-bound) sweeps keep the predicated march for full rows
-      // too: its wait on each level's store measured faster there.
-      if (!NT && t.tx * 64 + 64 <= g.nx)  // uniform per wave
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    const int x0 = t.tx * 64 * WX + (wave % WX) * 64;
+    const int i = x0 + lane;
+    const int j = t.ty * TY + wave / WX;
+    constexpr bool kShift = WX * TY > 1;
+    if (j < g.ny && x0 < g.nx) {  // uniform per wave
+      // Streamed (HBM-bound) sweeps on 64-wide tiles keep the predicated
+      // march for full rows too: its wait on each level's store measured
+      // faster there.
+      if ((!NT || WX > 1) && x0 + 64 <= g.nx)  // uniform per wave
         acc = march_row<true, kShift, CHEB, CHECK, NT>(a, t, lane, i, j);
       else
         acc = march_row<false, kShift, CHEB, CHECK, NT>(a, t, lane, i, j);
@@ -328,8 +336,8 @@ constexpr int kTY2 = 8;  // two-sweep tile: 512 threads, core 62 x 6
 
 struct Shape {
   int kc, tiles_x, tiles_y, tiles_z, ntiles, blocks;
-  int ty;       // one-sweep kernel: tile rows
-  bool stream;  // one-sweep kernel: streamed arrays (64 x kTY1Big tiles)
+  int wx, ty;   // one-sweep kernel: waves along x, tile rows
+  bool stream;  // one-sweep kernel: streamed arrays
 };
 
 // The four arrays of a sweep exceed what the Infinity Cache keeps.
@@ -340,14 +348,21 @@ bool streamed(const Grid &g, bool is_double) {
 Shape shape_of(const Grid &g, int S, bool is_double) {
   Shape sh;
   sh.stream = S == 1 && streamed(g, is_double);
+  sh.wx = 1;
   sh.ty = 0;
   if (S == 1) {
-    // rows beyond ny would idle: a short y axis (a two-dimensional run
-    // has ny = 1) takes the next smaller tile
-    int ty = sh.stream ? kTY1Big : kTY1;
-    if (g.ny < ty) ty = g.ny < kTY1 ? 1 : kTY1;
+    int ty;
+    if (g.nx >= kWideNx && g.ny >= kWideTYBig) {
+      sh.wx = kWX;
+      ty = sh.stream ? kWideTYBig : kWideTY;
+    } else {
+      // rows beyond ny would idle: a short y axis (a two-dimensional run
+      // has ny = 1) takes the next smaller tile
+      ty = sh.stream ? kTY1Big : kTY1;
+      if (g.ny < ty) ty = g.ny < kTY1 ? 1 : kTY1;
+    }
     sh.ty = ty;
-    sh.tiles_x = (g.nx + 63) / 64;
+    sh.tiles_x = (g.nx + 64 * sh.wx - 1) / (64 * sh.wx);
     sh.tiles_y = (g.ny + ty - 1) / ty;
   } else {
     sh.tiles_x = (g.nx + 61) / 62;
@@ -355,9 +370,11 @@ Shape shape_of(const Grid &g, int S, bool is_double) {
   }
   const int64_t cols = (int64_t)sh.tiles_x * sh.tiles_y;
   // z chunks: long enough to amortise the halo planes, short enough for
-  // several blocks per CU
+  // several blocks per CU.  Wide tiles aim at a wave count: the 8192 waves
+  // that fill the chip once when cache-resident, eight times that when
+  // streamed (shorter chunks measured faster there).
   sh.kc = g.nz;
-  const int target = 2048;
+  const int target = sh.wx > 1 ? (sh.stream ? 65536 : 8192) / (sh.wx * sh.ty) : 2048;
   while (sh.kc > 8 && cols * ((g.nz + sh.kc - 1) / sh.kc) < target) sh.kc = (sh.kc + 1) / 2;
   sh.tiles_z = (g.nz + sh.kc - 1) / sh.kc;
   int64_t nt = cols * sh.tiles_z;
@@ -407,28 +424,32 @@ void launch_tsweep(const Grid &g, int S, bool chebyshev, bool check, bool first,
   a.ctl = ctl;
   a.partials = partials;
   const dim3 grid(sh.blocks);
-#define LES_PICK(TY, NT)                                                              \
+#define LES_PICK(WX, TY, NT)                                                          \
   do {                                                                                \
-    const dim3 block(64 * TY);                                                        \
+    const dim3 block(64 * WX * TY);                                                   \
     if (chebyshev && !first) {                                                        \
-      if (check) sweep1_kernel<T, TY, true, true, NT><<<grid, block, 0, s>>>(a);      \
-      else sweep1_kernel<T, TY, true, false, NT><<<grid, block, 0, s>>>(a);           \
+      if (check) sweep1_kernel<T, WX, TY, true, true, NT><<<grid, block, 0, s>>>(a);  \
+      else sweep1_kernel<T, WX, TY, true, false, NT><<<grid, block, 0, s>>>(a);       \
     } else {                                                                          \
-      if (check) sweep1_kernel<T, TY, false, true, NT><<<grid, block, 0, s>>>(a);     \
-      else sweep1_kernel<T, TY, false, false, NT><<<grid, block, 0, s>>>(a);          \
+      if (check) sweep1_kernel<T, WX, TY, false, true, NT><<<grid, block, 0, s>>>(a); \
+      else sweep1_kernel<T, WX, TY, false, false, NT><<<grid, block, 0, s>>>(a);      \
     }                                                                                 \
   } while (0)
   if (S == 1) {
-    if (sh.ty == kTY1Big)
-      LES_PICK(kTY1Big, true);
+    if (sh.wx == kWX && sh.stream)
+      LES_PICK(kWX, kWideTYBig, true);
+    else if (sh.wx == kWX)
+      LES_PICK(kWX, kWideTY, false);
+    else if (sh.ty == kTY1Big)
+      LES_PICK(1, kTY1Big, true);
     else if (sh.ty == kTY1 && !sh.stream)
-      LES_PICK(kTY1, false);
+      LES_PICK(1, kTY1, false);
     else if (sh.ty == kTY1)
-      LES_PICK(kTY1, true);
+      LES_PICK(1, kTY1, true);
     else if (!sh.stream)
-      LES_PICK(1, false);
+      LES_PICK(1, 1, false);
     else
-      LES_PICK(1, true);
+      LES_PICK(1, 1, true);
   } else {
     const dim3 block(64 * kTY2);
     if (chebyshev) {

@@ -67,12 +67,15 @@ def test_poisson_fp64_matches_oracle(gpu, oracle_lib, shape, scheme):
     assert e <= 1e-11, e
 
 
-@pytest.mark.parametrize("shape", [(8, 1, 2), (8, 3, 2), (6, 2, 3), (5, 1, 65), (4, 3, 129)])
+@pytest.mark.parametrize("shape", [(8, 1, 2), (8, 3, 2), (6, 2, 3), (5, 1, 65), (4, 3, 129),
+                                   (6, 5, 300)])
 def test_poisson_degenerate_grids_match_oracle(gpu, oracle_lib, shape):
     """The smallest grids the library accepts and rows that end one cell into
     a wavefront: nx = 2, 3 (every lane but the first one or two idle, both
     end lanes load their x neighbours), ny = 1..3 (one-row tiles), nx = 65
-    and 129 (a second or third wavefront holding a single cell)."""
+    and 129 (a second or third wavefront holding a single cell), nx = 300 (a
+    256-wide tile whose second wave is ragged and whose others lie beyond
+    nx, with a partial tile row in y)."""
     import torch
     nz, ny, nx = shape
     p = li.workload("C1", nx=nx, ny=ny, nz=nz, dx=40.0, dy=30.0, dz=10.0, poisson_tol=1e-10,
@@ -414,6 +417,23 @@ def test_two_dimensional_sweeps_one_vs_two_per_launch(gpu):
         phi, st, rc = sim.poisson_solve(rhs.float(), fixed_sweeps=60)
         out.append(phi.double().cpu().numpy())
     assert np.array_equal(out[0], out[1])
+
+
+def test_poisson_streamed_wide_ragged_fp64(gpu, oracle_lib):
+    """300 x 160 x 128 in FP64 (the four arrays exceed the Infinity Cache, so
+    the streamed 256 x 4 tiles with a ragged last tile): 20 fixed sweeps
+    against the oracle."""
+    import torch
+    shape = (128, 160, 300)
+    p = li.workload("C1", nx=300, ny=160, nz=128, dx=35.0, dy=35.0, dz=5.0,
+                    poisson_scheme="chebyshev")
+    rhs = li.random_field(shape, seed=23)
+    phi_o, _ = oracle_lib.poisson(p, rhs, fixed_sweeps=20)
+    sim = gpu.LES(p)
+    phi_g, st_g, rc = sim.poisson_solve(torch.from_numpy(rhs), fixed_sweeps=20)
+    assert st_g["sweeps"] == 20
+    e = rel(phi_g.cpu().numpy(), phi_o)
+    assert e <= 1e-11, e
 
 
 def test_all_options_fp32_matches_oracle(gpu, oracle_lib):

@@ -154,23 +154,7 @@ __global__ __launch_bounds__(1024) void final_kernel(const double *__restrict__ 
       }
       break;
     case kFinalCheck:
-      if (ctl->done) break;
-      ctl->res_norm2 = s;
-      if (!isfinite(s)) {
-        ctl->done = 2;
-        ctl->stop_m = m;
-      } else if (ctl->fixed) {
-        if (m >= ctl->max_sweeps) {
-          ctl->done = s <= ctl->tol2 ? 1 : 3;
-          ctl->stop_m = m;
-        }
-      } else if (s <= ctl->tol2) {
-        ctl->done = 1;
-        ctl->stop_m = m;
-      } else if (m >= ctl->max_sweeps) {
-        ctl->done = 3;
-        ctl->stop_m = m;
-      }
+      check_decision(ctl, s, m);
       break;
     case kFinalPhiMean:
       ctl->phi_mean = s / n;

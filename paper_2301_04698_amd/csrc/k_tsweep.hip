@@ -77,8 +77,12 @@ struct SweepArgs {
   int first;         // the first sweep is the first of the solve (weight 1, no prev)
   const T *cur, *prev, *rhs;
   T *out_last, *out_prev;
-  const SolveCtl *ctl;
+  SolveCtl *ctl;
   double *partials;
+  // one-sweep launches: a pending residual check (sweep dec_m >= 0) of an
+  // earlier launch whose dec_np block partials block 0 reduces and decides
+  const double *dec_partials;
+  int dec_np, dec_m;
 };
 
 struct TileIdx {
@@ -210,6 +214,18 @@ __global__ __launch_bounds__(64 * WX * TY) void sweep1_kernel(SweepArgs<T> a) {
       else
         acc = march_row<false, kShift, CHEB, CHECK, NT>(a, t, lane, i, j);
     }
+  }
+  if (a.dec_m >= 0 && blockIdx.x == 0 && threadIdx.x < 64) {
+    // The residual test of an earlier checking launch, decided here by one
+    // wave after its row instead of by a launch of its own: its partials are
+    // complete at this launch's start.  The other blocks sweep regardless;
+    // their outputs go to buffers that hold neither the tested iterate nor
+    // this launch's input, and the next launch sees the decision.
+    double t = 0.0;
+#pragma unroll 16
+    for (int q = (int)threadIdx.x; q < a.dec_np; q += 64) t += a.dec_partials[q];
+    t = wave_sum(t);
+    if (threadIdx.x == 0) check_decision(a.ctl, t, a.dec_m);
   }
   if (CHECK) {
     const double s = block_sum(acc);
@@ -397,8 +413,8 @@ int tsweep_blocks(const Grid &g, int S, bool is_double) {
 template <typename T>
 void launch_tsweep(const Grid &g, int S, bool chebyshev, bool check, bool first,
                    double omega_jacobi, const double *omega_cheb, const T *cur, const T *prev,
-                   T *out_last, T *out_prev, const T *rhs, const SolveCtl *ctl,
-                   double *partials, hipStream_t s) {
+                   T *out_last, T *out_prev, const T *rhs, SolveCtl *ctl, double *partials,
+                   const double *dec_partials, int dec_np, int dec_m, hipStream_t s) {
   const Shape sh = shape_of(g, S, sizeof(T) == 8);
   SweepArgs<T> a;
   a.g = g;
@@ -423,6 +439,9 @@ void launch_tsweep(const Grid &g, int S, bool chebyshev, bool check, bool first,
   a.out_prev = out_prev;
   a.ctl = ctl;
   a.partials = partials;
+  a.dec_partials = dec_partials;
+  a.dec_np = dec_np;
+  a.dec_m = S == 1 ? dec_m : -1;
   const dim3 grid(sh.blocks);
 #define LES_PICK(WX, TY, NT)                                                          \
   do {                                                                                \
@@ -465,9 +484,10 @@ void launch_tsweep(const Grid &g, int S, bool chebyshev, bool check, bool first,
 
 template void launch_tsweep<float>(const Grid &, int, bool, bool, bool, double, const double *,
                                    const float *, const float *, float *, float *, const float *,
-                                   const SolveCtl *, double *, hipStream_t);
+                                   SolveCtl *, double *, const double *, int, int, hipStream_t);
 template void launch_tsweep<double>(const Grid &, int, bool, bool, bool, double, const double *,
                                     const double *, const double *, double *, double *,
-                                    const double *, const SolveCtl *, double *, hipStream_t);
+                                    const double *, SolveCtl *, double *, const double *, int, int,
+                                    hipStream_t);
 
 }  // namespace lesmi

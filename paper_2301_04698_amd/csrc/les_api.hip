@@ -40,6 +40,7 @@ struct Layout {
   size_t prof_d;    // 4 x nz doubles: p0, lnp, alpha0, rho0
   size_t prof_t;    // 4 x nz elems: rho0, alpha0, beta, wsub
   size_t partials;  // kPartialCap doubles
+  size_t partials2; // kPartials doubles: every other residual check's partials
   size_t ctl;       // SolveCtl
   size_t diag;      // nz x kDiagStride doubles
   size_t hist;      // n_subiter fields: previous step's solutions (history guess)
@@ -110,6 +111,8 @@ Layout layout_of(const les_config *c) {
   off = align_up(off + 4 * (size_t)c->nz * es);
   L.partials = off;
   off = align_up(off + kPartialCap * sizeof(double));
+  L.partials2 = off;
+  off = align_up(off + kPartials * sizeof(double));
   L.ctl = off;
   off = align_up(off + sizeof(SolveCtl));
   L.diag = off;
@@ -183,7 +186,7 @@ struct View {
   T *f[F_COUNT];
   Profiles<T> P;
   Dyn<T> dyn;
-  double *partials;
+  double *partials, *partials2;
   SolveCtl *ctl;
   double *diag;
   T *u, *v, *w, *thl, *qt, *p;
@@ -205,6 +208,7 @@ View<T> view_of(const les_handle *h) {
   V.P.beta_t = pt + 2 * nz;
   V.P.wsub_t = pt + 3 * nz;
   V.partials = (double *)ws(h, h->lay.partials);
+  V.partials2 = (double *)ws(h, h->lay.partials2);
   V.ctl = (SolveCtl *)ws(h, h->lay.ctl);
   V.diag = (double *)ws(h, h->lay.diag);
   const les_config &c = h->cfg;
@@ -358,6 +362,26 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
   const bool timed = timing && timing->enabled;
   int run_first = -1;
   double wc_prev = 1.0;  // Chebyshev weight recurrence
+  // pending residual check (decided by the next launch) and the host poll:
+  // a copy of the control block after each decision, read `lag` checks later
+  int pend_m = -1, pend_np = 0, nchecks = 0;
+  const double *pend_parts = nullptr;
+  auto poll = [&](bool &done) -> hipError_t {
+    const size_t slot = npending % h->ev_check.size();
+    hipError_t e = hipMemcpyAsync(&h->ctl_host[slot], V.ctl, sizeof(SolveCtl),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(h->ev_check[slot], s);
+    if (e != hipSuccess) return e;
+    ++npending;
+    if (npending - next_wait > (size_t)lag) {
+      const size_t w = next_wait % h->ev_check.size();
+      e = hipEventSynchronize(h->ev_check[w]);
+      if (e != hipSuccess) return e;
+      ++next_wait;
+      done = h->ctl_host[w].done != 0;
+    }
+    return hipSuccess;
+  };
   size_t li = 0;
   for (; li < plan.size(); ++li) {
     const Launch L = plan[li];
@@ -390,11 +414,18 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
     const int out_last = L.S == 1 ? free_[0] : free_[1];
     const int out_prev = L.S == 1 ? -1 : free_[0];
     if (L.check) check_buf.emplace_back(L.m, cur);
+    // A check left pending by the previous launch is decided by this one
+    // (block 0 reduces its partials); checks alternate partial buffers so a
+    // checking launch can decide the check before it.
+    const bool decides = pend_m >= 0 && L.S == 1;
+    double *parts = (nchecks & 1) ? V.partials2 : V.partials;
     // The first Chebyshev sweep has weight 1: the plain weighted-Jacobi
     // sweep, which must not read the (uninitialised) previous iterate.
     launch_tsweep<T>(g, L.S, cheb, L.check, L.m == 0, omega_j, wc, buf[cur],
                      prev >= 0 ? buf[prev] : nullptr, buf[out_last],
-                     out_prev >= 0 ? buf[out_prev] : nullptr, rhs, V.ctl, V.partials, s);
+                     out_prev >= 0 ? buf[out_prev] : nullptr, rhs, V.ctl, parts,
+                     decides ? pend_parts : nullptr, decides ? pend_np : 0, decides ? pend_m : -1,
+                     s);
     if (L.S == 1) {
       prev = cur;
     } else {
@@ -408,22 +439,34 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
       runs.push_back(Run{run_first, L.m + L.S - 1});
       run_first = -1;
     }
-    if (L.check) {
-      // partial sums come from this launch's own block decomposition
-      launch_final(V.partials, tsweep_blocks(g, L.S, sizeof(T) == 8), kFinalCheck, V.ctl,
-                   (double)g.n, 0.0, L.m, nullptr, s);
+    bool stop = false;
+    if (decides) {
+      pend_m = -1;
       LAUNCH_TRY();
-      const size_t slot = npending % h->ev_check.size();
-      HIP_TRY(hipMemcpyAsync(&h->ctl_host[slot], V.ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipEventRecord(h->ev_check[slot], s));
-      ++npending;
-      if (npending - next_wait > (size_t)lag) {
-        const size_t w = next_wait % h->ev_check.size();
-        HIP_TRY(hipEventSynchronize(h->ev_check[w]));
-        ++next_wait;
-        if (h->ctl_host[w].done) break;
+      HIP_TRY(poll(stop));
+    }
+    if (L.check) {
+      ++nchecks;
+      // partial sums come from this launch's own block decomposition; the
+      // next launch decides unless it is a two-sweep launch or there is none
+      const int np = tsweep_blocks(g, L.S, sizeof(T) == 8);
+      if (L.S == 1 && li + 1 < plan.size() && plan[li + 1].S == 1) {
+        pend_m = L.m;
+        pend_parts = parts;
+        pend_np = np;
+      } else {
+        launch_final(parts, np, kFinalCheck, V.ctl, (double)g.n, 0.0, L.m, nullptr, s);
+        LAUNCH_TRY();
+        bool stop2 = false;
+        HIP_TRY(poll(stop2));
+        stop = stop || stop2;
       }
     }
+    if (stop) break;
+  }
+  if (pend_m >= 0) {  // a check no later launch decided (the loop stopped early)
+    launch_final(pend_parts, pend_np, kFinalCheck, V.ctl, (double)g.n, 0.0, pend_m, nullptr, s);
+    LAUNCH_TRY();
   }
   LAUNCH_TRY();
   if (timed && run_first >= 0) {  // loop left inside a run

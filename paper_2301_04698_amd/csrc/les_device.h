@@ -57,6 +57,29 @@ __device__ __forceinline__ double block_sum(double v) {
   return s;
 }
 
+// Stopping decision of the residual check at sweep m with squared residual
+// norm s (one thread): converged when s <= tol^2 ||rhs||^2, non-finite, or
+// the sweep cap; a fixed-count solve stops only at its count.
+__device__ __forceinline__ void check_decision(SolveCtl *ctl, double s, int m) {
+  if (ctl->done) return;
+  ctl->res_norm2 = s;
+  if (!isfinite(s)) {
+    ctl->done = 2;
+    ctl->stop_m = m;
+  } else if (ctl->fixed) {
+    if (m >= ctl->max_sweeps) {
+      ctl->done = s <= ctl->tol2 ? 1 : 3;
+      ctl->stop_m = m;
+    }
+  } else if (s <= ctl->tol2) {
+    ctl->done = 1;
+    ctl->stop_m = m;
+  } else if (m >= ctl->max_sweeps) {
+    ctl->done = 3;
+    ctl->stop_m = m;
+  }
+}
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));

@@ -121,13 +121,16 @@ void launch_rhs_center(const Grid &g, const T *rhs_in, T *rhs_out, T *phi0, cons
 
 // S sweeps from (prev, cur) = (phi_{m-1}, phi_m) giving out_prev = phi_{m+S-1}
 // (S >= 2, Chebyshev) and out_last = phi_{m+S}; check: FP64 partial sums of
-// the residual of cur.  first: sweep m is the first of the solve.  omega_cheb:
-// S weights of sweeps m .. m+S-1.  Outputs never alias inputs.
+// the residual of cur, one per block (tsweep_blocks of them).  first: sweep
+// m is the first of the solve.  omega_cheb: S weights of sweeps m .. m+S-1.
+// dec_m >= 0 (S == 1 only): block 0 also reduces the dec_np partials of an
+// earlier checking launch of sweep dec_m and applies its stopping decision
+// to ctl.  Outputs never alias inputs.
 template <typename T>
 void launch_tsweep(const Grid &g, int S, bool chebyshev, bool check, bool first,
                    double omega_jacobi, const double *omega_cheb, const T *cur, const T *prev,
-                   T *out_last, T *out_prev, const T *rhs, const SolveCtl *ctl,
-                   double *partials, hipStream_t s);
+                   T *out_last, T *out_prev, const T *rhs, SolveCtl *ctl, double *partials,
+                   const double *dec_partials, int dec_np, int dec_m, hipStream_t s);
 
 template <typename T>
 void launch_project(const Grid &g, const Dyn<T> &d, const Profiles<T> &P, const T *phi,

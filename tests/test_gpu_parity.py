@@ -89,6 +89,27 @@ def test_poisson_degenerate_grids_match_oracle(gpu, oracle_lib, shape):
     assert e <= 1e-11, e
 
 
+@pytest.mark.parametrize("every,spl", [(1, 1), (3, 1), (1, 2), (4, 2), (25, 2)])
+def test_poisson_check_intervals_match_oracle(gpu, oracle_lib, every, spl):
+    """Residual checks every 1, 3, 4 or 25 sweeps with one- and two-sweep
+    launches: a check is decided inside the next one-sweep launch (checks on
+    consecutive sweeps alternate partial buffers) or, before a two-sweep
+    launch, by a launch of its own.  The solve stops at the oracle's sweep."""
+    import torch
+    shape = (16, 12, 20)
+    p = li.workload("C1", nx=20, ny=12, nz=16, dx=40.0, dy=30.0, dz=10.0, poisson_tol=1e-10,
+                    poisson_scheme="chebyshev", poisson_check_every=every,
+                    sweeps_per_launch=spl)
+    rhs = li.random_field(shape, seed=24)
+    phi_o, st_o = oracle_lib.poisson(p, rhs)
+    sim = gpu.LES(p)
+    phi_g, st_g, rc = sim.poisson_solve(torch.from_numpy(rhs))
+    assert rc == 0 and st_o["status"] == 0 and st_g["status"] == 0
+    assert st_g["sweeps"] == st_o["sweeps"]
+    assert st_g["sweeps"] % every == 0
+    assert rel(phi_g.cpu().numpy(), phi_o) <= 1e-11
+
+
 @pytest.mark.parametrize("scheme", ["jacobi", "chebyshev"])
 def test_poisson_fp32_matches_oracle(gpu, oracle_lib, scheme):
     import torch

@@ -74,7 +74,8 @@ enum { LES_GUESS_ZERO = 0, LES_GUESS_EXTRAPOLATE = 1, LES_GUESS_PREVIOUS = 2,
        LES_GUESS_LEARNED = 3 };
 
 /* Run configuration.  nx >= 2, ny >= 1 (ny = 1: a two-dimensional x-z run)
- * and nz >= 4.
+ * and nz >= 4; one z plane of a field at most 2 GiB (nx*ny <= 2^29 in FP32,
+ * 2^28 in FP64) and at most 2^34 cells, else LES_ERR_ARG.
  * Table 1 constants of the paper and forcing parameters are explicit so the
  * caller states every value (les_default_config fills Table 1). */
 typedef struct les_config {

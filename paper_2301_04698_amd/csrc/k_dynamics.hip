@@ -1,26 +1,14 @@
 // Subgrid viscosity (paper Sec. 2.3), scalar predictor (Sec. 2.4, scalar
 // prediction equation) and momentum predictor (Sec. 2.4, momentum
-// prediction equation) on the collocated grid.  One thread per cell; the
-// stencil neighbourhoods are served by the L1/L2 caches.
+// prediction equation) on the collocated grid.  Column-marching kernels
+// (one lane per column, a chunk of levels per wave); the stencil
+// neighbourhoods are served by the L1/L2 caches.
 #include "les.h"
-#include "les_device.h"
+#include "les_column.h"
 
 namespace lesmi {
 
 namespace {
-
-inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
-
-struct Cell {
-  int i, j, k;
-};
-
-__device__ __forceinline__ Cell cell_of(const Grid &g, int64_t q) {
-  const int k = (int)(q / g.nxy);
-  const int64_t r = q - g.nxy * k;
-  const int j = (int)(r / g.nx);
-  return Cell{(int)(r - (int64_t)g.nx * j), j, k};
-}
 
 // QUICK face value at l+1/2 from q(l-1), q(l), q(l+1), q(l+2), upwinded on
 // the face mass flux m (Leonard's quadratic upstream interpolation).
@@ -65,15 +53,15 @@ __device__ __forceinline__ T vpar(int a) {
 }
 
 // Central derivative of velocity component a (field f) along axis ax at
-// cell (i, j, k), which may be a ghost level.
-template <typename T, bool FS>
-__device__ __forceinline__ T dcentral(const T *__restrict__ f, const Grid &g, const Dyn<T> &d,
-                                      int a, int ax, int i, int j, int k) {
+// the cell offset (oi, oj, ok) from the wave's cell (a ghost level near
+// the walls).
+template <typename T, bool FS, class L>
+__device__ __forceinline__ T dcentral(const T *__restrict__ f, const L &at, const Dyn<T> &d, int a,
+                                      int ax, int oi, int oj, int ok) {
   const int di = ax == 0, dj = ax == 1, dk = ax == 2;
   const T inv2 = ax == 0 ? d.inv_2dx : (ax == 1 ? d.inv_2dy : d.inv_2dz);
   const T par = vpar<T, FS>(a);
-  return (gload(f, g, i + di, j + dj, k + dk, par) - gload(f, g, i - di, j - dj, k - dk, par)) *
-         inv2;
+  return (at(f, oi + di, oj + dj, ok + dk, par) - at(f, oi - di, oj - dj, ok - dk, par)) * inv2;
 }
 
 // ---------------------------------------------------------------- SGS nu
@@ -81,25 +69,18 @@ __device__ __forceinline__ T dcentral(const T *__restrict__ f, const Grid &g, co
 // nu_t = (c_s Delta)^2 f_B S with S = sqrt(2 S_ij S_ij) and the buoyancy
 // factor f_B = sqrt(clamp(1 - N^2/(Pr S^2), 0, 1)), N^2 = db/dz (central);
 // or the uniform viscosity of the validation cases (Sec. 3) when set.
-template <typename T, bool FS>
-__global__ __launch_bounds__(kBlock) void sgs_nu_kernel(Grid g, Dyn<T> d, const T *__restrict__ u,
-                                                        const T *__restrict__ v,
-                                                        const T *__restrict__ w,
-                                                        const T *__restrict__ b,
-                                                        T *__restrict__ nu) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= g.n) return;
-  if (d.nu_const > T(0)) {
-    nu[q] = d.nu_const;
-    return;
-  }
-  const Cell c = cell_of(g, q);
+template <typename T, bool FS, bool EDGE>
+__device__ __forceinline__ void sgs_nu_level(const Grid &g, const Dyn<T> &d, const ColPts<T> &pts,
+                                             int k, bool active, const T *__restrict__ u,
+                                             const T *__restrict__ v, const T *__restrict__ w,
+                                             const T *__restrict__ b, T *__restrict__ nu) {
+  const Lvl<T, EDGE> at(g, pts, k);
   const T *vel[3] = {u, v, w};
   T G[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int e = 0; e < 3; ++e) G[a][e] = dcentral<T, FS>(vel[a], g, d, a, e, c.i, c.j, c.k);
+    for (int e = 0; e < 3; ++e) G[a][e] = dcentral<T, FS>(vel[a], at, d, a, e, 0, 0, 0);
   T s2 = T(0);
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -108,14 +89,35 @@ __global__ __launch_bounds__(kBlock) void sgs_nu_kernel(Grid g, Dyn<T> d, const 
       const T sij = T(0.5) * (G[a][e] + G[e][a]);
       s2 += T(2) * sij * sij;
     }
-  const T n2 = (gload(b, g, c.i, c.j, c.k + 1, T(1)) - gload(b, g, c.i, c.j, c.k - 1, T(1))) * d.inv_2dz;
+  const T n2 = (at(b, 0, 0, 1, T(1)) - at(b, 0, 0, -1, T(1))) * d.inv_2dz;
   T val = T(0);
   if (s2 > T(0)) {
     T r = T(1) - n2 / (d.pr * s2);
     r = r < T(0) ? T(0) : (r > T(1) ? T(1) : r);
     val = d.smag_l2 * sqrt(s2) * sqrt(r);
   }
-  nu[q] = val;
+  at.store(nu, val, active);
+}
+
+template <typename T, bool FS>
+__global__ __launch_bounds__(kBlock) void sgs_nu_kernel(Grid g, ColMap m, Dyn<T> d,
+                                                        const T *__restrict__ u,
+                                                        const T *__restrict__ v,
+                                                        const T *__restrict__ w,
+                                                        const T *__restrict__ b,
+                                                        T *__restrict__ nu) {
+  const ColWave c = col_wave(g, m);
+  if (!c.valid) return;
+  const ColPts<T> pts = col_pts<T>(g, c.i, c.j);
+  for (int k = c.k0; k < c.k1; ++k) {
+    if (d.nu_const > T(0)) {
+      Lvl<T, false>(g, pts, k).store(nu, d.nu_const, c.active);
+    } else if (k >= 2 && k + 2 < g.nz) {
+      sgs_nu_level<T, FS, false>(g, d, pts, k, c.active, u, v, w, b, nu);
+    } else {
+      sgs_nu_level<T, FS, true>(g, d, pts, k, c.active, u, v, w, b, nu);
+    }
+  }
 }
 
 // ------------------------------------------------------- scalar update
@@ -127,35 +129,35 @@ struct FaceFlux {
   T xm, xp, ym, yp, zm, zp;
 };
 
-template <typename T>
-__device__ __forceinline__ FaceFlux<T> face_mass(const Grid &g, const Profiles<T> &P,
+template <typename T, class L>
+__device__ __forceinline__ FaceFlux<T> face_mass(const L &at, const Profiles<T> &P,
                                                  const T *__restrict__ u, const T *__restrict__ v,
-                                                 const T *__restrict__ w, const Cell &c) {
-  const T r0 = P.rho0_t[c.k];
-  const T rm = pload(P.rho0_t, c.k - 1, g.nz), rp = pload(P.rho0_t, c.k + 1, g.nz);
-  const T uc = r0 * gload(u, g, c.i, c.j, c.k, T(-1));
-  const T vc = r0 * gload(v, g, c.i, c.j, c.k, T(-1));
-  const T wc = r0 * gload(w, g, c.i, c.j, c.k, T(-1));
+                                                 const T *__restrict__ w) {
+  const T r0 = at.prof(P.rho0_t, 0);
+  const T rm = at.prof(P.rho0_t, -1), rp = at.prof(P.rho0_t, 1);
+  const T uc = r0 * at(u, 0, 0, 0, T(-1));
+  const T vc = r0 * at(v, 0, 0, 0, T(-1));
+  const T wc = r0 * at(w, 0, 0, 0, T(-1));
   FaceFlux<T> f;
-  f.xp = T(0.5) * (uc + r0 * gload(u, g, c.i + 1, c.j, c.k, T(-1)));
-  f.xm = T(0.5) * (r0 * gload(u, g, c.i - 1, c.j, c.k, T(-1)) + uc);
-  f.yp = T(0.5) * (vc + r0 * gload(v, g, c.i, c.j + 1, c.k, T(-1)));
-  f.ym = T(0.5) * (r0 * gload(v, g, c.i, c.j - 1, c.k, T(-1)) + vc);
-  f.zp = T(0.5) * (wc + rp * gload(w, g, c.i, c.j, c.k + 1, T(-1)));
-  f.zm = T(0.5) * (rm * gload(w, g, c.i, c.j, c.k - 1, T(-1)) + wc);
+  f.xp = T(0.5) * (uc + r0 * at(u, 1, 0, 0, T(-1)));
+  f.xm = T(0.5) * (r0 * at(u, -1, 0, 0, T(-1)) + uc);
+  f.yp = T(0.5) * (vc + r0 * at(v, 0, 1, 0, T(-1)));
+  f.ym = T(0.5) * (r0 * at(v, 0, -1, 0, T(-1)) + vc);
+  f.zp = T(0.5) * (wc + rp * at(w, 0, 0, 1, T(-1)));
+  f.zm = T(0.5) * (rm * at(w, 0, 0, -1, T(-1)) + wc);
   return f;
 }
 
 // Flux-form advective tendency -div(U s) of a field s with parity par.
-template <typename T, bool WENO>
-__device__ __forceinline__ T advect(const Grid &g, const Dyn<T> &d, const FaceFlux<T> &f,
-                                    const T *__restrict__ s, T par, const Cell &c) {
+template <typename T, bool WENO, class L>
+__device__ __forceinline__ T advect(const L &at, const Dyn<T> &d, const FaceFlux<T> &f,
+                                    const T *__restrict__ s, T par) {
   T sx[5], sy[5], sz[5];
 #pragma unroll
   for (int o = -2; o <= 2; ++o) {
-    sx[o + 2] = gload(s, g, c.i + o, c.j, c.k, par);
-    sy[o + 2] = gload(s, g, c.i, c.j + o, c.k, par);
-    sz[o + 2] = gload(s, g, c.i, c.j, c.k + o, par);
+    sx[o + 2] = at(s, o, 0, 0, par);
+    sy[o + 2] = at(s, 0, o, 0, par);
+    sz[o + 2] = at(s, 0, 0, o, par);
   }
   const T fxp = face_flux<T, WENO>(f.xp, sx[1], sx[2], sx[3], sx[4]);
   const T fxm = face_flux<T, WENO>(f.xm, sx[0], sx[1], sx[2], sx[3]);
@@ -172,136 +174,185 @@ struct FaceVisc {
   T xm, xp, ym, yp, zm, zp;  // rho0_f * nu_f
 };
 
-template <typename T>
-__device__ __forceinline__ FaceVisc<T> face_visc(const Grid &g, const Profiles<T> &P,
-                                                 const T *__restrict__ nu, const Cell &c) {
-  const T r0 = P.rho0_t[c.k];
-  const T rm = pload(P.rho0_t, c.k - 1, g.nz), rp = pload(P.rho0_t, c.k + 1, g.nz);
-  const T n0 = nu[(int64_t)c.i + (int64_t)g.nx * c.j + g.nxy * c.k];
+template <typename T, class L>
+__device__ __forceinline__ FaceVisc<T> face_visc(const L &at, const Profiles<T> &P,
+                                                 const T *__restrict__ nu) {
+  const T r0 = at.prof(P.rho0_t, 0);
+  const T rm = at.prof(P.rho0_t, -1), rp = at.prof(P.rho0_t, 1);
+  const T n0 = at(nu, 0, 0, 0, T(1));
   FaceVisc<T> f;
-  f.xp = r0 * (T(0.5) * (n0 + gload(nu, g, c.i + 1, c.j, c.k, T(1))));
-  f.xm = r0 * (T(0.5) * (gload(nu, g, c.i - 1, c.j, c.k, T(1)) + n0));
-  f.yp = r0 * (T(0.5) * (n0 + gload(nu, g, c.i, c.j + 1, c.k, T(1))));
-  f.ym = r0 * (T(0.5) * (gload(nu, g, c.i, c.j - 1, c.k, T(1)) + n0));
-  f.zp = T(0.5) * (r0 + rp) * (T(0.5) * (n0 + gload(nu, g, c.i, c.j, c.k + 1, T(1))));
-  f.zm = T(0.5) * (rm + r0) * (T(0.5) * (gload(nu, g, c.i, c.j, c.k - 1, T(1)) + n0));
+  f.xp = r0 * (T(0.5) * (n0 + at(nu, 1, 0, 0, T(1))));
+  f.xm = r0 * (T(0.5) * (at(nu, -1, 0, 0, T(1)) + n0));
+  f.yp = r0 * (T(0.5) * (n0 + at(nu, 0, 1, 0, T(1))));
+  f.ym = r0 * (T(0.5) * (at(nu, 0, -1, 0, T(1)) + n0));
+  f.zp = T(0.5) * (r0 + rp) * (T(0.5) * (n0 + at(nu, 0, 0, 1, T(1))));
+  f.zm = T(0.5) * (rm + r0) * (T(0.5) * (at(nu, 0, 0, -1, T(1)) + n0));
   return f;
 }
 
 // div(rho0 nu / Pr grad s), compact face differences.
-template <typename T>
-__device__ __forceinline__ T diffuse(const Grid &g, const Dyn<T> &d, const FaceVisc<T> &f, T inv_pr,
-                                     const T *__restrict__ s, const Cell &c) {
-  const T s0 = gload(s, g, c.i, c.j, c.k, T(1));
-  const T gx = (f.xp * inv_pr * ((gload(s, g, c.i + 1, c.j, c.k, T(1)) - s0) * d.inv_dx) -
-                f.xm * inv_pr * ((s0 - gload(s, g, c.i - 1, c.j, c.k, T(1))) * d.inv_dx)) *
+template <typename T, class L>
+__device__ __forceinline__ T diffuse(const L &at, const Dyn<T> &d, const FaceVisc<T> &f, T inv_pr,
+                                     const T *__restrict__ s) {
+  const T s0 = at(s, 0, 0, 0, T(1));
+  const T gx = (f.xp * inv_pr * ((at(s, 1, 0, 0, T(1)) - s0) * d.inv_dx) -
+                f.xm * inv_pr * ((s0 - at(s, -1, 0, 0, T(1))) * d.inv_dx)) *
                d.inv_dx;
-  const T gy = (f.yp * inv_pr * ((gload(s, g, c.i, c.j + 1, c.k, T(1)) - s0) * d.inv_dy) -
-                f.ym * inv_pr * ((s0 - gload(s, g, c.i, c.j - 1, c.k, T(1))) * d.inv_dy)) *
+  const T gy = (f.yp * inv_pr * ((at(s, 0, 1, 0, T(1)) - s0) * d.inv_dy) -
+                f.ym * inv_pr * ((s0 - at(s, 0, -1, 0, T(1))) * d.inv_dy)) *
                d.inv_dy;
-  const T gz = (f.zp * inv_pr * ((gload(s, g, c.i, c.j, c.k + 1, T(1)) - s0) * d.inv_dz) -
-                f.zm * inv_pr * ((s0 - gload(s, g, c.i, c.j, c.k - 1, T(1))) * d.inv_dz)) *
+  const T gz = (f.zp * inv_pr * ((at(s, 0, 0, 1, T(1)) - s0) * d.inv_dz) -
+                f.zm * inv_pr * ((s0 - at(s, 0, 0, -1, T(1))) * d.inv_dz)) *
                d.inv_dz;
   return gx + gy + gz;
 }
 
 // Phi^{k+1} = Phi^{n+1/2} + dt/rho0 [ -div(U^k Phi_mid) + div(rho0 nu/Pr grad Phi_mid)
 //            + rho0 w_sub dPhi_mid/dz + radiative heating (theta_l) + surface flux ]
+template <typename T, bool WENO, bool EDGE>
+__device__ __forceinline__ void scalar_level(
+    const Grid &g, const Dyn<T> &d, const Profiles<T> &P, const ColPts<T> &pts, int k,
+    bool active, const T *__restrict__ u, const T *__restrict__ v, const T *__restrict__ w,
+    const T *__restrict__ thm, const T *__restrict__ qtm, const T *__restrict__ thh,
+    const T *__restrict__ qth, const T *__restrict__ nu, const T *__restrict__ rad,
+    T *__restrict__ tho, T *__restrict__ qto) {
+  const Lvl<T, EDGE> at(g, pts, k);
+  const FaceFlux<T> mf = face_mass(at, P, u, v, w);
+  const FaceVisc<T> fv = face_visc(at, P, nu);
+  const T r0 = at.prof(P.rho0_t, 0);
+  const T sub = r0 * at.prof(P.wsub_t, 0);
+  const T scale = d.dt / r0;
+  T th_new, qt_new;
+  {
+    T tend = advect<T, WENO>(at, d, mf, thm, T(1)) + diffuse(at, d, fv, d.inv_pr, thm);
+    tend += at(rad, 0, 0, 0, T(1));
+    tend += sub * ((at(thm, 0, 0, 1, T(1)) - at(thm, 0, 0, -1, T(1))) * d.inv_2dz);
+    if (k == 0) tend += d.sfc_thl * d.inv_dz;
+    th_new = at(thh, 0, 0, 0, T(1)) + scale * tend;
+  }
+  {
+    T tend = advect<T, WENO>(at, d, mf, qtm, T(1)) + diffuse(at, d, fv, d.inv_sc, qtm);
+    tend += sub * ((at(qtm, 0, 0, 1, T(1)) - at(qtm, 0, 0, -1, T(1))) * d.inv_2dz);
+    if (k == 0) tend += d.sfc_qt * d.inv_dz;
+    qt_new = at(qth, 0, 0, 0, T(1)) + scale * tend;
+  }
+  // Stores after all loads (the two scalars share the face fluxes' loads).
+  at.store(tho, th_new, active);
+  at.store(qto, qt_new, active);
+}
+
 template <typename T, bool WENO>
 __global__ __launch_bounds__(kBlock) void scalar_kernel(
-    Grid g, Dyn<T> d, Profiles<T> P, const T *__restrict__ u, const T *__restrict__ v,
+    Grid g, ColMap m, Dyn<T> d, Profiles<T> P, const T *__restrict__ u, const T *__restrict__ v,
     const T *__restrict__ w, const T *__restrict__ thm, const T *__restrict__ qtm,
     const T *__restrict__ thh, const T *__restrict__ qth, const T *__restrict__ nu,
     const T *__restrict__ rad, T *__restrict__ tho, T *__restrict__ qto) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= g.n) return;
-  const Cell c = cell_of(g, q);
-  const FaceFlux<T> mf = face_mass(g, P, u, v, w, c);
-  const FaceVisc<T> fv = face_visc(g, P, nu, c);
-  const T r0 = P.rho0_t[c.k];
-  const T sub = r0 * P.wsub_t[c.k];
-  const T scale = d.dt / r0;
-  {
-    T tend = advect<T, WENO>(g, d, mf, thm, T(1), c) + diffuse(g, d, fv, d.inv_pr, thm, c);
-    tend += rad[q];
-    tend += sub * ((gload(thm, g, c.i, c.j, c.k + 1, T(1)) - gload(thm, g, c.i, c.j, c.k - 1, T(1))) * d.inv_2dz);
-    if (c.k == 0) tend += d.sfc_thl * d.inv_dz;
-    tho[q] = thh[q] + scale * tend;
-  }
-  {
-    T tend = advect<T, WENO>(g, d, mf, qtm, T(1), c) + diffuse(g, d, fv, d.inv_sc, qtm, c);
-    tend += sub * ((gload(qtm, g, c.i, c.j, c.k + 1, T(1)) - gload(qtm, g, c.i, c.j, c.k - 1, T(1))) * d.inv_2dz);
-    if (c.k == 0) tend += d.sfc_qt * d.inv_dz;
-    qto[q] = qth[q] + scale * tend;
+  const ColWave c = col_wave(g, m);
+  if (!c.valid) return;
+  const ColPts<T> pts = col_pts<T>(g, c.i, c.j);
+  for (int k = c.k0; k < c.k1; ++k) {
+    if (k >= 2 && k + 2 < g.nz)
+      scalar_level<T, WENO, false>(g, d, P, pts, k, c.active, u, v, w, thm, qtm, thh, qth, nu,
+                                   rad, tho, qto);
+    else
+      scalar_level<T, WENO, true>(g, d, P, pts, k, c.active, u, v, w, thm, qtm, thh, qth, nu,
+                                  rad, tho, qto);
   }
 }
 
 // ------------------------------------------------------ momentum update
 
-// SGS momentum flux of component cmp through the face between cell a and
-// cell b = a + e_ax: rho0_f nu_f [ (u_cmp(b) - u_cmp(a))/Delta_ax
-//   + (d u_ax/d x_cmp (a) + d u_ax/d x_cmp (b)) / 2 ].
-template <typename T, bool FS>
-__device__ __forceinline__ T sgs_face(const Grid &g, const Dyn<T> &d, const T *const vel[3], T rnu,
-                                      int ax, int cmp, int ia, int ja, int ka) {
+// SGS momentum flux of component cmp through the face between the cell
+// at offset o = (oi, oj, ok) and the one at o + e_ax:
+//   rho0_f nu_f [ (u_cmp(o + e_ax) - u_cmp(o))/Delta_ax
+//                 + (d u_ax/d x_cmp (o) + d u_ax/d x_cmp (o + e_ax)) / 2 ].
+template <typename T, bool FS, class L>
+__device__ __forceinline__ T sgs_face(const L &at, const Dyn<T> &d, const T *const vel[3], T rnu,
+                                      int ax, int cmp, int oi, int oj, int ok) {
   const int di = ax == 0, dj = ax == 1, dk = ax == 2;
   const T inv = ax == 0 ? d.inv_dx : (ax == 1 ? d.inv_dy : d.inv_dz);
-  const T normal = (gload(vel[cmp], g, ia + di, ja + dj, ka + dk, vpar<T, FS>(cmp)) -
-                    gload(vel[cmp], g, ia, ja, ka, vpar<T, FS>(cmp))) *
+  const T normal = (at(vel[cmp], oi + di, oj + dj, ok + dk, vpar<T, FS>(cmp)) -
+                    at(vel[cmp], oi, oj, ok, vpar<T, FS>(cmp))) *
                    inv;
-  const T trans = T(0.5) * (dcentral<T, FS>(vel[ax], g, d, ax, cmp, ia, ja, ka) +
-                            dcentral<T, FS>(vel[ax], g, d, ax, cmp, ia + di, ja + dj, ka + dk));
+  const T trans = T(0.5) * (dcentral<T, FS>(vel[ax], at, d, ax, cmp, oi, oj, ok) +
+                            dcentral<T, FS>(vel[ax], at, d, ax, cmp, oi + di, oj + dj, ok + dk));
   return rnu * (normal + trans);
 }
 
 // U_hat = U^n + dt [ -rho0 grad_c(alpha0 p^k) + R^{n+1/2} ] with
 // R = -div(U_h (x) u_h) + div(rho0 sigma) + rho0 b e_z - f e_z x (U_h - rho0 u_g)
 //     - beta(z) (U_h - rho0 (u_g, v_g, 0)); stored as u_hat = U_hat / rho0.
-template <typename T, bool WENO, bool FS>
-__global__ __launch_bounds__(kBlock) void momentum_kernel(
-    Grid g, Dyn<T> d, Profiles<T> P, const T *__restrict__ uh, const T *__restrict__ vh,
-    const T *__restrict__ wh, const T *__restrict__ un, const T *__restrict__ vn,
-    const T *__restrict__ wn, const T *__restrict__ p, const T *__restrict__ b,
-    const T *__restrict__ nu, T *__restrict__ uo, T *__restrict__ vo, T *__restrict__ wo) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= g.n) return;
-  const Cell c = cell_of(g, q);
+template <typename T, bool WENO, bool FS, bool EDGE>
+__device__ __forceinline__ void momentum_level(
+    const Grid &g, const Dyn<T> &d, const Profiles<T> &P, const ColPts<T> &pts, int k,
+    bool active, const T *__restrict__ uh, const T *__restrict__ vh, const T *__restrict__ wh,
+    const T *__restrict__ un, const T *__restrict__ vn, const T *__restrict__ wn,
+    const T *__restrict__ p, const T *__restrict__ b, const T *__restrict__ nu,
+    T *__restrict__ uo, T *__restrict__ vo, T *__restrict__ wo) {
+  const Lvl<T, EDGE> at(g, pts, k);
   const T *const vel[3] = {uh, vh, wh};
-  const FaceFlux<T> mf = face_mass(g, P, uh, vh, wh, c);
-  const FaceVisc<T> fv = face_visc(g, P, nu, c);
-  const T r0 = P.rho0_t[c.k];
-  const T beta = P.beta_t[c.k];
+  const FaceFlux<T> mf = face_mass(at, P, uh, vh, wh);
+  const FaceVisc<T> fv = face_visc(at, P, nu);
+  const T r0 = at.prof(P.rho0_t, 0);
+  const T beta = at.prof(P.beta_t, 0);
   // pressure gradient of psi = alpha0 p' (even mirror)
-  auto psi = [&](int i, int j, int k) {
-    return pload(P.alpha0_t, k, g.nz) * gload(p, g, i, j, k, T(1));
-  };
-  const T gpx = (psi(c.i + 1, c.j, c.k) - psi(c.i - 1, c.j, c.k)) * d.inv_2dx;
-  const T gpy = (psi(c.i, c.j + 1, c.k) - psi(c.i, c.j - 1, c.k)) * d.inv_2dy;
-  const T gpz = (psi(c.i, c.j, c.k + 1) - psi(c.i, c.j, c.k - 1)) * d.inv_2dz;
+  const T a0 = at.prof(P.alpha0_t, 0);
+  const T gpx = (a0 * at(p, 1, 0, 0, T(1)) - a0 * at(p, -1, 0, 0, T(1))) * d.inv_2dx;
+  const T gpy = (a0 * at(p, 0, 1, 0, T(1)) - a0 * at(p, 0, -1, 0, T(1))) * d.inv_2dy;
+  const T gpz = (at.prof(P.alpha0_t, 1) * at(p, 0, 0, 1, T(1)) -
+                 at.prof(P.alpha0_t, -1) * at(p, 0, 0, -1, T(1))) *
+                d.inv_2dz;
   const T gp[3] = {gpx, gpy, gpz};
-  const T Uh[3] = {r0 * uh[q], r0 * vh[q], r0 * wh[q]};
-  const T Un[3] = {r0 * un[q], r0 * vn[q], r0 * wn[q]};
+  const T Uh[3] = {r0 * at(uh, 0, 0, 0, T(1)), r0 * at(vh, 0, 0, 0, T(1)),
+                   r0 * at(wh, 0, 0, 0, T(1))};
+  const T Un[3] = {r0 * at(un, 0, 0, 0, T(1)), r0 * at(vn, 0, 0, 0, T(1)),
+                   r0 * at(wn, 0, 0, 0, T(1))};
   const T geo[3] = {d.ug, d.vg, T(0)};
   T *const out[3] = {uo, vo, wo};
   const T rnu_m[3] = {fv.xm, fv.ym, fv.zm};
   const T rnu_p[3] = {fv.xp, fv.yp, fv.zp};
   const T invd[3] = {d.inv_dx, d.inv_dy, d.inv_dz};
+  const T bq = at(b, 0, 0, 0, T(1));
+  T res[3];
 #pragma unroll
   for (int cmp = 0; cmp < 3; ++cmp) {
-    T R = advect<T, WENO>(g, d, mf, vel[cmp], vpar<T, FS>(cmp), c);
+    T R = advect<T, WENO>(at, d, mf, vel[cmp], vpar<T, FS>(cmp));
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const int di = ax == 0, dj = ax == 1, dk = ax == 2;
-      const T fp = sgs_face<T, FS>(g, d, vel, rnu_p[ax], ax, cmp, c.i, c.j, c.k);
-      const T fm = sgs_face<T, FS>(g, d, vel, rnu_m[ax], ax, cmp, c.i - di, c.j - dj, c.k - dk);
+      const T fp = sgs_face<T, FS>(at, d, vel, rnu_p[ax], ax, cmp, 0, 0, 0);
+      const T fm = sgs_face<T, FS>(at, d, vel, rnu_m[ax], ax, cmp, -di, -dj, -dk);
       R += (fp - fm) * invd[ax];
     }
-    if (cmp == 2) R += r0 * b[q];
+    if (cmp == 2) R += r0 * bq;
     if (cmp == 0) R += d.fcor * (Uh[1] - r0 * d.vg);
     if (cmp == 1) R -= d.fcor * (Uh[0] - r0 * d.ug);
     R -= beta * (Uh[cmp] - r0 * geo[cmp]);
     const T Uhat = Un[cmp] + d.dt * (-r0 * gp[cmp] + R);
-    out[cmp][q] = Uhat / r0;
+    res[cmp] = Uhat / r0;
+  }
+  // Stores after all loads: the loads of the three components share their
+  // common points and differences.
+#pragma unroll
+  for (int cmp = 0; cmp < 3; ++cmp) at.store(out[cmp], res[cmp], active);
+}
+
+template <typename T, bool WENO, bool FS>
+__global__ __launch_bounds__(kBlock) void momentum_kernel(
+    Grid g, ColMap m, Dyn<T> d, Profiles<T> P, const T *__restrict__ uh, const T *__restrict__ vh,
+    const T *__restrict__ wh, const T *__restrict__ un, const T *__restrict__ vn,
+    const T *__restrict__ wn, const T *__restrict__ p, const T *__restrict__ b,
+    const T *__restrict__ nu, T *__restrict__ uo, T *__restrict__ vo, T *__restrict__ wo) {
+  const ColWave c = col_wave(g, m);
+  if (!c.valid) return;
+  const ColPts<T> pts = col_pts<T>(g, c.i, c.j);
+  for (int k = c.k0; k < c.k1; ++k) {
+    if (k >= 2 && k + 2 < g.nz)
+      momentum_level<T, WENO, FS, false>(g, d, P, pts, k, c.active, uh, vh, wh, un, vn, wn, p, b,
+                                         nu, uo, vo, wo);
+    else
+      momentum_level<T, WENO, FS, true>(g, d, P, pts, k, c.active, uh, vh, wh, un, vn, wn, p, b,
+                                        nu, uo, vo, wo);
   }
 }
 
@@ -310,10 +361,11 @@ __global__ __launch_bounds__(kBlock) void momentum_kernel(
 template <typename T>
 void launch_sgs_nu(const Grid &g, const Dyn<T> &d, const T *u, const T *v, const T *w, const T *b,
                    T *nu, hipStream_t s) {
+  const ColMap m = col_map(g);
   if (d.uv_par > T(0))
-    sgs_nu_kernel<T, true><<<blocks_for(g.n), kBlock, 0, s>>>(g, d, u, v, w, b, nu);
+    sgs_nu_kernel<T, true><<<m.blocks, kBlock, 0, s>>>(g, m, d, u, v, w, b, nu);
   else
-    sgs_nu_kernel<T, false><<<blocks_for(g.n), kBlock, 0, s>>>(g, d, u, v, w, b, nu);
+    sgs_nu_kernel<T, false><<<m.blocks, kBlock, 0, s>>>(g, m, d, u, v, w, b, nu);
 }
 
 template <typename T>
@@ -321,21 +373,23 @@ void launch_scalar_update(const Grid &g, const Dyn<T> &d, const Profiles<T> &P, 
                           const T *v, const T *w, const T *thl_mid, const T *qt_mid,
                           const T *thl_half, const T *qt_half, const T *nu, const T *rad,
                           T *thl_out, T *qt_out, hipStream_t s) {
+  const ColMap m = col_map(g);
   if (d.advection == LES_WENO3)
-    scalar_kernel<T, true><<<blocks_for(g.n), kBlock, 0, s>>>(
-        g, d, P, u, v, w, thl_mid, qt_mid, thl_half, qt_half, nu, rad, thl_out, qt_out);
+    scalar_kernel<T, true><<<m.blocks, kBlock, 0, s>>>(
+        g, m, d, P, u, v, w, thl_mid, qt_mid, thl_half, qt_half, nu, rad, thl_out, qt_out);
   else
-    scalar_kernel<T, false><<<blocks_for(g.n), kBlock, 0, s>>>(
-        g, d, P, u, v, w, thl_mid, qt_mid, thl_half, qt_half, nu, rad, thl_out, qt_out);
+    scalar_kernel<T, false><<<m.blocks, kBlock, 0, s>>>(
+        g, m, d, P, u, v, w, thl_mid, qt_mid, thl_half, qt_half, nu, rad, thl_out, qt_out);
 }
 
 template <typename T>
 void launch_momentum(const Grid &g, const Dyn<T> &d, const Profiles<T> &P, const T *uh,
                      const T *vh, const T *wh, const T *un, const T *vn, const T *wn, const T *p,
                      const T *b, const T *nu, T *uo, T *vo, T *wo, hipStream_t s) {
-#define LES_MOM(WENO, FS)                                                                \
-  momentum_kernel<T, WENO, FS><<<blocks_for(g.n), kBlock, 0, s>>>(g, d, P, uh, vh, wh, un, vn, \
-                                                                  wn, p, b, nu, uo, vo, wo)
+  const ColMap m = col_map(g);
+#define LES_MOM(WENO, FS)                                                                     \
+  momentum_kernel<T, WENO, FS><<<m.blocks, kBlock, 0, s>>>(g, m, d, P, uh, vh, wh, un, vn, wn, \
+                                                           p, b, nu, uo, vo, wo)
   const bool weno = d.advection == LES_WENO3, fs = d.uv_par > T(0);
   if (weno && fs) LES_MOM(true, true);
   else if (weno) LES_MOM(true, false);

@@ -2,7 +2,7 @@
 // side with the collocated-grid correction, projection, and the fixed-order
 // FP64 reductions that drive the device-side stopping test.  The sweeps are
 // in k_tsweep.hip.
-#include "les_device.h"
+#include "les_column.h"
 
 namespace lesmi {
 
@@ -12,26 +12,20 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBl
 
 // rhs = (alpha0/dt) div_c(rho0 u_hat) - C(phi_lag), with C the App. A
 // fourth difference (wide minus compact Laplacian) of the previous
-// sub-iteration's correction (phi_lag == nullptr: C = 0).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void rhs_kernel(Grid g, Dyn<T> d, Profiles<T> P,
-                                                     const T *__restrict__ u,
-                                                     const T *__restrict__ v,
-                                                     const T *__restrict__ w,
-                                                     const T *__restrict__ lag,
-                                                     T *__restrict__ rhs) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= g.n) return;
-  const int k = (int)(q / g.nxy);
-  const int64_t r = q - g.nxy * k;
-  const int j = (int)(r / g.nx);
-  const int i = (int)(r - (int64_t)g.nx * j);
-  const T r0 = P.rho0_t[k];
-  const T rm = pload(P.rho0_t, k - 1, g.nz), rp = pload(P.rho0_t, k + 1, g.nz);
-  const T div = (r0 * gload(u, g, i + 1, j, k, T(-1)) - r0 * gload(u, g, i - 1, j, k, T(-1))) * d.inv_2dx +
-                (r0 * gload(v, g, i, j + 1, k, T(-1)) - r0 * gload(v, g, i, j - 1, k, T(-1))) * d.inv_2dy +
-                (rp * gload(w, g, i, j, k + 1, T(-1)) - rm * gload(w, g, i, j, k - 1, T(-1))) * d.inv_2dz;
-  T val = P.alpha0_t[k] / d.dt * div;
+// sub-iteration's correction (phi_lag == nullptr: C = 0).  Column-marching.
+template <typename T, bool EDGE>
+__device__ __forceinline__ void rhs_level(const Grid &g, const Dyn<T> &d, const Profiles<T> &P,
+                                          const ColPts<T> &pts, int k, bool active,
+                                          const T *__restrict__ u, const T *__restrict__ v,
+                                          const T *__restrict__ w, const T *__restrict__ lag,
+                                          T *__restrict__ rhs) {
+  const Lvl<T, EDGE> at(g, pts, k);
+  const T r0 = at.prof(P.rho0_t, 0);
+  const T rm = at.prof(P.rho0_t, -1), rp = at.prof(P.rho0_t, 1);
+  const T div = (r0 * at(u, 1, 0, 0, T(-1)) - r0 * at(u, -1, 0, 0, T(-1))) * d.inv_2dx +
+                (r0 * at(v, 0, 1, 0, T(-1)) - r0 * at(v, 0, -1, 0, T(-1))) * d.inv_2dy +
+                (rp * at(w, 0, 0, 1, T(-1)) - rm * at(w, 0, 0, -1, T(-1))) * d.inv_2dz;
+  T val = at.prof(P.alpha0_t, 0) / d.dt * div;
   if (lag) {
     T corr = T(0);
     const T inv4[3] = {T(0.25) * d.inv_dx * d.inv_dx, T(0.25) * d.inv_dy * d.inv_dy,
@@ -39,16 +33,34 @@ __global__ __launch_bounds__(kBlock) void rhs_kernel(Grid g, Dyn<T> d, Profiles<
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const int di = ax == 0, dj = ax == 1, dk = ax == 2;
-      const T a2 = gload(lag, g, i + 2 * di, j + 2 * dj, k + 2 * dk, T(1));
-      const T a1 = gload(lag, g, i + di, j + dj, k + dk, T(1));
-      const T a0 = gload(lag, g, i, j, k, T(1));
-      const T b1 = gload(lag, g, i - di, j - dj, k - dk, T(1));
-      const T b2 = gload(lag, g, i - 2 * di, j - 2 * dj, k - 2 * dk, T(1));
+      const T a2 = at(lag, 2 * di, 2 * dj, 2 * dk, T(1));
+      const T a1 = at(lag, di, dj, dk, T(1));
+      const T a0 = at(lag, 0, 0, 0, T(1));
+      const T b1 = at(lag, -di, -dj, -dk, T(1));
+      const T b2 = at(lag, -2 * di, -2 * dj, -2 * dk, T(1));
       corr += (a2 - T(4) * a1 + T(6) * a0 - T(4) * b1 + b2) * inv4[ax];
     }
     val -= corr;
   }
-  rhs[q] = val;
+  at.store(rhs, val, active);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void rhs_kernel(Grid g, ColMap m, Dyn<T> d, Profiles<T> P,
+                                                     const T *__restrict__ u,
+                                                     const T *__restrict__ v,
+                                                     const T *__restrict__ w,
+                                                     const T *__restrict__ lag,
+                                                     T *__restrict__ rhs) {
+  const ColWave c = col_wave(g, m);
+  if (!c.valid) return;
+  const ColPts<T> pts = col_pts<T>(g, c.i, c.j);
+  for (int k = c.k0; k < c.k1; ++k) {
+    if (k >= 2 && k + 2 < g.nz)
+      rhs_level<T, false>(g, d, P, pts, k, c.active, u, v, w, lag, rhs);
+    else
+      rhs_level<T, true>(g, d, P, pts, k, c.active, u, v, w, lag, rhs);
+  }
 }
 
 // rhs_out = rhs_in - mean (in and out may alias); FP64 partial sums of
@@ -72,25 +84,44 @@ __global__ __launch_bounds__(kBlock) void center_kernel(int64_t n, const T *in, 
 }
 
 // U^{k+1} = U_hat - dt rho0 grad_c phi (stored as velocity), p += rho0 (phi - mean).
+// Column-marching.
+template <typename T, bool EDGE>
+__device__ __forceinline__ void project_level(const Grid &g, const Dyn<T> &d,
+                                              const Profiles<T> &P, const ColPts<T> &pts, int k,
+                                              bool active, T mean, const T *__restrict__ phi,
+                                              T *__restrict__ u, T *__restrict__ v,
+                                              T *__restrict__ w, T *__restrict__ p) {
+  const Lvl<T, EDGE> at(g, pts, k);
+  const T gx = (at(phi, 1, 0, 0, T(1)) - at(phi, -1, 0, 0, T(1))) * d.inv_2dx;
+  const T gy = (at(phi, 0, 1, 0, T(1)) - at(phi, 0, -1, 0, T(1))) * d.inv_2dy;
+  const T gz = (at(phi, 0, 0, 1, T(1)) - at(phi, 0, 0, -1, T(1))) * d.inv_2dz;
+  const T uo = at(u, 0, 0, 0, T(1)) - d.dt * gx;
+  const T vo = at(v, 0, 0, 0, T(1)) - d.dt * gy;
+  const T wo = at(w, 0, 0, 0, T(1)) - d.dt * gz;
+  const T po = at(p, 0, 0, 0, T(1)) + at.prof(P.rho0_t, 0) * (at(phi, 0, 0, 0, T(1)) - mean);
+  at.store(u, uo, active);
+  at.store(v, vo, active);
+  at.store(w, wo, active);
+  at.store(p, po, active);
+}
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void project_kernel(Grid g, Dyn<T> d, Profiles<T> P,
+__global__ __launch_bounds__(kBlock) void project_kernel(Grid g, ColMap m, Dyn<T> d,
+                                                         Profiles<T> P,
                                                          const T *__restrict__ phi,
                                                          const SolveCtl *__restrict__ ctl,
                                                          T *__restrict__ u, T *__restrict__ v,
                                                          T *__restrict__ w, T *__restrict__ p) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= g.n) return;
-  const int k = (int)(q / g.nxy);
-  const int64_t r = q - g.nxy * k;
-  const int j = (int)(r / g.nx);
-  const int i = (int)(r - (int64_t)g.nx * j);
-  const T gx = (gload(phi, g, i + 1, j, k, T(1)) - gload(phi, g, i - 1, j, k, T(1))) * d.inv_2dx;
-  const T gy = (gload(phi, g, i, j + 1, k, T(1)) - gload(phi, g, i, j - 1, k, T(1))) * d.inv_2dy;
-  const T gz = (gload(phi, g, i, j, k + 1, T(1)) - gload(phi, g, i, j, k - 1, T(1))) * d.inv_2dz;
-  u[q] = u[q] - d.dt * gx;
-  v[q] = v[q] - d.dt * gy;
-  w[q] = w[q] - d.dt * gz;
-  p[q] = p[q] + P.rho0_t[k] * (phi[q] - (T)ctl->phi_mean);
+  const ColWave c = col_wave(g, m);
+  if (!c.valid) return;
+  const ColPts<T> pts = col_pts<T>(g, c.i, c.j);
+  const T mean = (T)ctl->phi_mean;
+  for (int k = c.k0; k < c.k1; ++k) {
+    if (k >= 1 && k + 1 < g.nz)
+      project_level<T, false>(g, d, P, pts, k, c.active, mean, phi, u, v, w, p);
+    else
+      project_level<T, true>(g, d, P, pts, k, c.active, mean, phi, u, v, w, p);
+  }
 }
 
 template <typename T>
@@ -266,7 +297,8 @@ void launch_poisson_rhs(const Grid &g, const Dyn<T> &d, const Profiles<T> &P, co
                         const T *v, const T *w, const T *phi_lag, T *rhs, double *partials,
                         hipStream_t s) {
   (void)partials;
-  rhs_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g, d, P, u, v, w, phi_lag, rhs);
+  const ColMap m = col_map(g);
+  rhs_kernel<T><<<m.blocks, kBlock, 0, s>>>(g, m, d, P, u, v, w, phi_lag, rhs);
 }
 
 template <typename T>
@@ -278,7 +310,8 @@ void launch_rhs_center(const Grid &g, const T *rhs_in, T *rhs_out, T *phi0, cons
 template <typename T>
 void launch_project(const Grid &g, const Dyn<T> &d, const Profiles<T> &P, const T *phi,
                     const SolveCtl *ctl, T *u, T *v, T *w, T *p, hipStream_t s) {
-  project_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g, d, P, phi, ctl, u, v, w, p);
+  const ColMap m = col_map(g);
+  project_kernel<T><<<m.blocks, kBlock, 0, s>>>(g, m, d, P, phi, ctl, u, v, w, p);
 }
 
 template <typename T>

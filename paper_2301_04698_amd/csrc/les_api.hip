@@ -55,8 +55,12 @@ int validate(const les_config *c) {
   if (c->nx < 2 || c->ny < 1 || c->nz < 4)
     return fail(LES_ERR_ARG, "grid %dx%dx%d: nx must be >= 2, ny >= 1 and nz >= 4", c->nx,
                 c->ny, c->nz);
-  if ((int64_t)c->nx * c->ny > (int64_t)1 << 30 || (int64_t)c->nx * c->ny * c->nz > (int64_t)1 << 34)
-    return fail(LES_ERR_ARG, "grid too large");
+  // A z plane of one field stays within 2 GiB (the stencil kernels address
+  // a plane with 32-bit byte offsets); at most 2^34 cells.
+  const int64_t elem = c->precision == LES_FP64 ? 8 : 4;
+  if ((int64_t)c->nx * c->ny * elem > (int64_t)1 << 31 ||
+      (int64_t)c->nx * c->ny * c->nz > (int64_t)1 << 34)
+    return fail(LES_ERR_ARG, "grid too large: at most 2 GiB per z plane and 2^34 cells");
   if (!(c->dx > 0) || !(c->dy > 0) || !(c->dz > 0) || !(c->dt > 0))
     return fail(LES_ERR_ARG, "dx, dy, dz, dt must be > 0");
   if (c->precision != LES_FP64 && c->precision != LES_FP32)

@@ -87,6 +87,8 @@ def test_make_config_carries_every_parameter(lib, oracle_lib):
     (dict(nx=1), "nx must be >= 2, ny >= 1"),
     (dict(wall=7), "wall condition"),
     (dict(nu_const=-1.0), "nu_const"),
+    (dict(nx=16384, ny=16385, nz=4), "grid too large"),  # FP64 plane just over 2 GiB
+    (dict(nx=32768, ny=32768, nz=4, precision="fp32"), "grid too large"),
     (dict(dt=0.0), "> 0"),
     (dict(poisson_tol=0.0), "poisson_tol"),
     (dict(poisson_check_every=0), "check_every"),
@@ -97,6 +99,16 @@ def test_invalid_config_rejected(lib, override, needle):
     c = lib.make_config(li.workload("C1", **override))
     assert lib.workspace_bytes(c) == 0
     assert needle in lib.last_error()
+
+
+def test_plane_limit_is_per_precision(lib):
+    """The 2 GiB bound on one z plane: a 16384 x 16385 plane is 1 GiB in
+    FP32 (accepted; only sized here, nothing is allocated) and just over
+    2 GiB in FP64 (rejected)."""
+    c = lib.make_config(li.workload("C1", nx=16384, ny=16385, nz=4, precision="fp32"))
+    assert lib.workspace_bytes(c) > 25 * 16384 * 16385 * 4 * 4
+    c = lib.make_config(li.workload("C1", nx=16384, ny=16385, nz=4, precision="fp64"))
+    assert lib.workspace_bytes(c) == 0
 
 
 def test_init_rejects_null_buffers(lib):

@@ -295,6 +295,26 @@ def test_step_c1m_fp64_all_physics(gpu, oracle_lib):
         assert e <= 1e-11, (k, e, errs)
 
 
+@pytest.mark.parametrize("shape,advection,wall", [
+    ((4, 5, 70), "quick", "no_slip"),     # every level within two cells of a wall
+    ((7, 3, 130), "weno3", "free_slip"),  # a partial z chunk, three x segments, ragged
+    ((9, 1, 66), "quick", "free_slip"),   # two-dimensional, a one-level z chunk
+    ((6, 4, 64), "weno3", "no_slip"),     # whole x segments, two interior levels
+])
+def test_step_column_kernel_shapes_match_oracle(gpu, oracle_lib, shape, advection, wall):
+    """The column-marching stencil kernels (advection, diffusion, SGS,
+    divergence, projection) on launch shapes with ragged x segments, rows not
+    a multiple of the block's four, partial z chunks and wall levels only:
+    all moist physics, a perturbed velocity, two FP64 steps."""
+    nz, ny, nx = shape
+    p = li.workload("C1m", nx=nx, ny=ny, nz=nz, poisson_tol=1e-9, poisson_scheme="chebyshev",
+                    advection=advection, wall=wall)
+    st0 = with_velocity_noise(p, li.initial_state(p), 0.3, 31)
+    errs, *_ = _compare_step(gpu, oracle_lib, p, st0, 2, 1e-11)
+    for k, e in errs.items():
+        assert e <= 1e-11, (k, e, errs)
+
+
 def test_step_c1_fp64_ten_steps(gpu, oracle_lib):
     """The configuration of the small parity case: 32^3, dt 0.5 s, tol 1e-8,
     fixed-weight Jacobi, 10 steps."""

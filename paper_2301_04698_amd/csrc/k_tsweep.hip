@@ -22,15 +22,14 @@
 // iterate's neighbour rows.  Narrower grids take 64 x 4 (or 64 x 16
 // streamed, 64 x 1 for ny < 4) tiles.
 //
-// Two sweeps: a 64 x TY thread tile covers a 62 x (TY-2) core plus a
-// one-cell ring.  Every thread computes the first sweep for its own column
-// as above; the second sweep, on the core only, takes the first sweep's x/y
-// neighbours from a ring of LDS planes and its z neighbours from the
-// thread's own registers.  20 bytes per cell for both sweeps.
+// Two sweeps: one wave per four rows and 62-cell segment also forms the
+// first sweep of the two rows beside them in registers, so the second sweep
+// needs no LDS and no barrier; 20 bytes per cell from memory for both
+// sweeps (phi, prev, rhs in; the two new iterates out).
 //
 // Walls: the z neighbour of the bottom/top level is that level itself (even
 // mirror); x and y are periodic.
-#include "les_device.h"
+#include "les_column.h"
 
 namespace lesmi {
 
@@ -235,110 +234,161 @@ __global__ __launch_bounds__(64 * WX * TY) void sweep1_kernel(SweepArgs<T> a) {
 
 // --------------------------------------------------------------- 2 sweeps
 
-constexpr int kU2 = 2;  // planes per barrier in the two-sweep kernel
+// Two fused sweeps without LDS or barriers.  A wave owns R rows j0 ..
+// j0+R-1 and a 62-cell x segment (lanes 1..62; lanes 0 and 63 are its halo
+// columns, wrapped periodically like every other lane) of the z chunk
+// [k0, k1).  Marching up z it forms the first sweep on rows j0-1 .. j0+R at
+// level k (their y neighbours are rows j0-2 .. j0+R+1 of the iterate, x
+// neighbours the adjacent lanes, z neighbours registers), then the second
+// sweep on its R rows at level k-1 from first-sweep values that are all in
+// its own registers or adjacent lanes.  The first sweep of the two boundary
+// rows is also formed by the neighbouring waves; in exchange every array is
+// read from memory once per two sweeps (neighbour rows through the caches).
+// All accesses are buffer loads and stores on one z plane: lanes outside
+// the segment's core, and rows beyond the grid, store at an offset past the
+// plane's range, which the hardware drops.
+constexpr int kR2 = 4;  // rows per wave of the two-sweep kernel
 
-template <typename T, int TY, bool CHEB, bool CHECK>
-__global__ __launch_bounds__(64 * TY) void sweep2_kernel(SweepArgs<T> a) {
+template <typename T, int R, bool CHEB, bool CHECK>
+__global__ __launch_bounds__(256) void sweep2_kernel(SweepArgs<T> a) {
   if (a.ctl->done) return;
-  // First-sweep planes, slot k mod R.  A batch writes kU2 planes and reads
-  // kU2 planes starting one below; R = 2 kU2 + 1 keeps the next batch's
-  // writes clear of slower threads still reading, with one barrier per batch.
-  constexpr int kU = kU2;
-  constexpr int R = 2 * kU + 1;
-  __shared__ T lvl1[R][TY][64];
+  constexpr int NR = R + 2;  // first-sweep rows j0-1 .. j0+R
   const Grid &g = a.g;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+  const int lb = xcd_tile(blockIdx.x, gridDim.x);
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = (int)(threadIdx.x & 63);
+  const int u = lb * 4 + wave;
   double acc = 0.0;
-  if (tile < a.ntiles) {
-    const TileIdx t = tile_of(tile, a.tiles_x, a.tiles_y, a.kc, g.nz);
-    // unwrapped coordinates of this thread's column; the core is
-    // lx in [1, 63), ly in [1, TY-1)
-    const int xu = t.tx * 62 - 1 + lx, yu = t.ty * (TY - 2) - 1 + ly;
-    const bool core = lx >= 1 && lx < 63 && ly >= 1 && ly < TY - 1 && xu < g.nx && yu < g.ny;
-    const int i = pmod(xu, g.nx), j = pmod(yu, g.ny);
-    const int ip = i + 1 == g.nx ? 0 : i + 1, im = i == 0 ? g.nx - 1 : i - 1;
-    const int jp = j + 1 == g.ny ? 0 : j + 1, jm = j == 0 ? g.ny - 1 : j - 1;
-    const int64_t col = (int64_t)i + (int64_t)g.nx * j;
-    const int64_t oxp = ip - i, oxm = im - i;
-    const int64_t oyp = (int64_t)(jp - j) * g.nx, oym = (int64_t)(jm - j) * g.nx;
-    const bool cheb1 = CHEB && !a.first, cheb2 = CHEB;
-    // first-sweep planes [kb, ke]; second sweep on [k0, k1)
-    const int kb = max(0, t.k0 - 1), ke = min(g.nz - 1, t.k1);
-    T below = a.cur[col + g.nxy * (kb > 0 ? kb - 1 : 0)];
-    T c = a.cur[col + g.nxy * kb];
-    // own-column values of the two planes below the current batch
-    T l1_m1 = T(0), l1_m2 = T(0), c_m1 = T(0), r_m1 = T(0);
-    for (int kbase = kb; kbase <= ke; kbase += kU) {
-      const int nb = min(kU, ke - kbase + 1);
-      T ab[kU], xp[kU], xm[kU], yp[kU], ym[kU], rr[kU], pp[kU];
+  if (u < a.ntiles) {  // uniform per wave
+    const int ty = u % a.tiles_y, rest = u / a.tiles_y;
+    const int tx = rest % a.tiles_x, tz = rest / a.tiles_x;
+    const int j0 = ty * R;
+    const int k0 = tz * a.kc, k1 = min(g.nz, k0 + a.kc);
+    const int xu = tx * 62 - 1 + lane;
+    const bool core = lane >= 1 && lane <= 62 && xu < g.nx;
+    const int i = pmod(xu, g.nx), il = pmod(xu - 1, g.nx), ir = pmod(xu + 1, g.nx);
+    constexpr uint32_t kOut = 0x80000000u;  // beyond any plane (at most 2 GiB)
+    const uint32_t es = (uint32_t)sizeof(T);
+    uint32_t o[R + 4];  // rows j0-2 .. j0+R+1 of this lane's column
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        if (u < nb) {
-          const int k = kbase + u;
-          const int64_t q = col + g.nxy * k;
-          ab[u] = a.cur[q + (k + 1 < g.nz ? g.nxy : 0)];
-          xp[u] = a.cur[q + oxp];
-          xm[u] = a.cur[q + oxm];
-          yp[u] = a.cur[q + oyp];
-          ym[u] = a.cur[q + oym];
-          rr[u] = a.rhs[q];
-          pp[u] = cheb1 ? a.prev[q] : T(0);
+    for (int d = 0; d < R + 4; ++d)
+      o[d] = ((uint32_t)i + (uint32_t)g.nx * (uint32_t)pmod(j0 + d - 2, g.ny)) * es;
+    uint32_t oxl[NR], oxr[NR];  // x neighbours of the end lanes
+#pragma unroll
+    for (int d = 0; d < NR; ++d) {
+      const uint32_t row = (uint32_t)g.nx * (uint32_t)pmod(j0 + d - 1, g.ny);
+      oxl[d] = lane == 0 ? ((uint32_t)il + row) * es : kOut;
+      oxr[d] = lane == 63 ? ((uint32_t)ir + row) * es : kOut;
+    }
+    uint32_t ost[R];  // store offsets of the output rows
+    bool rcore[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      rcore[r] = core && j0 + r < g.ny;
+      ost[r] = rcore[r] ? o[r + 2] : kOut;
+    }
+    const int64_t pb = g.nxy * (int64_t)sizeof(T);
+    const bool cheb1 = CHEB && !a.first;
+    const int kb = max(0, k0 - 1), ke = min(g.nz - 1, k1);
+    // iterate of the first-sweep rows at levels k-1 (bl) and k (cc)
+    T bl[NR], cc[NR];
+    {
+      const __amdgpu_buffer_rsrc_t rb = plane_rsrc(a.cur, pb, kb > 0 ? kb - 1 : 0);
+      const __amdgpu_buffer_rsrc_t rc = plane_rsrc(a.cur, pb, kb);
+#pragma unroll
+      for (int d = 0; d < NR; ++d) {
+        bl[d] = rsrc_load<T>(rb, o[d + 1]);
+        cc[d] = rsrc_load<T>(rc, o[d + 1]);
+      }
+    }
+    // first-sweep values at level k-1 (all rows) and k-2 (output rows);
+    // rhs and iterate of the output rows at level k-1
+    T s1p[NR], s1pp[R], rm1[R], cm1[R];
+#pragma unroll
+    for (int d = 0; d < NR; ++d) s1p[d] = T(0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) s1pp[r] = rm1[r] = cm1[r] = T(0);
+    for (int k = kb; k <= ke; ++k) {
+      const __amdgpu_buffer_rsrc_t rk = plane_rsrc(a.cur, pb, k);
+      const __amdgpu_buffer_rsrc_t ra = plane_rsrc(a.cur, pb, k + 1 < g.nz ? k + 1 : k);
+      const __amdgpu_buffer_rsrc_t rr = plane_rsrc(a.rhs, pb, k);
+      T ab[NR], rh[NR], pv[NR], xl[NR], xr[NR];
+#pragma unroll
+      for (int d = 0; d < NR; ++d) {
+        ab[d] = rsrc_load<T>(ra, o[d + 1]);
+        rh[d] = rsrc_load<T>(rr, o[d + 1]);
+        xl[d] = rsrc_load<T>(rk, oxl[d]);
+        xr[d] = rsrc_load<T>(rk, oxr[d]);
+        pv[d] = T(0);
+      }
+      const T ylo = rsrc_load<T>(rk, o[0]), yhi = rsrc_load<T>(rk, o[R + 3]);
+      if (cheb1) {
+        const __amdgpu_buffer_rsrc_t rp = plane_rsrc(a.prev, pb, k);
+#pragma unroll
+        for (int d = 0; d < NR; ++d) pv[d] = rsrc_load<T>(rp, o[d + 1]);
+      }
+      const bool core_k = k >= k0 && k < k1;
+      // ---- first sweep, rows j0-1 .. j0+R at level k
+      T s1[NR];
+#pragma unroll
+      for (int d = 0; d < NR; ++d) {
+        const T sp = lane_shift<1>(cc[d]), sm = lane_shift<-1>(cc[d]);
+        const T xp = lane == 63 ? xr[d] : sp;
+        const T xm = lane == 0 ? xl[d] : sm;
+        const T yp = d == NR - 1 ? yhi : cc[d < NR - 1 ? d + 1 : NR - 1];
+        const T ym = d == 0 ? ylo : cc[d > 0 ? d - 1 : 0];
+        const double hx = (double)xp + (double)xm;
+        const double hy = (double)yp + (double)ym;
+        const double hz = (double)ab[d] + (double)bl[d];
+        const double res = point_residual(a.k, (double)cc[d], hx, hy, hz, (double)rh[d]);
+        if (CHECK && d >= 1 && d <= R && core_k && rcore[d >= 1 && d <= R ? d - 1 : 0])
+          acc += res * res;
+        s1[d] = (T)point_update(a.k, (double)cc[d], res, cheb1, (double)pv[d], a.wc0);
+      }
+      if (CHEB && core_k) {
+        const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.out_prev, pb, k);
+#pragma unroll
+        for (int r = 0; r < R; ++r) rsrc_store<T>(ro, ost[r], s1[r + 1]);
+      }
+      // ---- second sweep, output rows at level k-1
+      if (k - 1 >= k0 && k - 1 < k1) {
+        const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.out_last, pb, k - 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const T ctr = s1p[r + 1];
+          const T lo = k - 1 == 0 ? ctr : s1pp[r];
+          const double h2x = (double)lane_shift<1>(ctr) + (double)lane_shift<-1>(ctr);
+          const double h2y = (double)s1p[r + 2] + (double)s1p[r];
+          const double h2z = (double)s1[r + 1] + (double)lo;
+          const double r2 = point_residual(a.k, (double)ctr, h2x, h2y, h2z, (double)rm1[r]);
+          rsrc_store<T>(ro, ost[r], (T)point_update(a.k, (double)ctr, r2, CHEB, (double)cm1[r], a.wc1));
         }
       }
-      // ---- first sweep on planes kbase .. kbase+nb-1 (whole 64 x TY tile)
-      T l1v[kU], cv[kU];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        l1v[u] = T(0);
-        cv[u] = T(0);
-        if (u < nb) {
-          const int k = kbase + u;
-          const int64_t q = col + g.nxy * k;
-          const double hx = (double)xp[u] + (double)xm[u];
-          const double hy = (double)yp[u] + (double)ym[u];
-          const double hz = (double)ab[u] + (double)below;
-          const double res = point_residual(a.k, (double)c, hx, hy, hz, (double)rr[u]);
-          const bool core_plane = k >= t.k0 && k < t.k1;
-          if (CHECK && core && core_plane) acc += res * res;
-          const T l1 = (T)point_update(a.k, (double)c, res, cheb1, (double)pp[u], a.wc0);
-          lvl1[k % R][ly][lx] = l1;
-          if (CHEB && core && core_plane) a.out_prev[q] = l1;
-          l1v[u] = l1;
-          cv[u] = c;
-          below = c;
-          c = ab[u];
-        }
+      for (int r = 0; r < R; ++r) {
+        s1pp[r] = s1p[r + 1];
+        rm1[r] = rh[r + 1];
+        cm1[r] = cc[r + 1];
       }
-      __syncthreads();
-      // ---- second sweep on planes kk = kbase-1+u, u = 0 .. nb (the last
-      // one only for the top level), core columns only
 #pragma unroll
-      for (int u = 0; u <= kU; ++u) {
-        const int kk = kbase - 1 + u;
-        const bool valid = u < nb || (u == nb && kk == g.nz - 1);
-        if (!valid || !core || kk < t.k0 || kk >= t.k1) continue;
-        const T ctr = u == 0 ? l1_m1 : l1v[u - 1 < 0 ? 0 : u - 1];
-        const T lo = kk == 0 ? ctr : (u == 0 ? l1_m2 : (u == 1 ? l1_m1 : l1v[u - 2 < 0 ? 0 : u - 2]));
-        const T hi = kk + 1 == g.nz ? ctr : l1v[u < kU ? u : kU - 1];
-        const T *pl = &lvl1[kk % R][0][0];
-        const double h2x = (double)pl[ly * 64 + lx + 1] + (double)pl[ly * 64 + lx - 1];
-        const double h2y = (double)pl[(ly + 1) * 64 + lx] + (double)pl[(ly - 1) * 64 + lx];
-        const double h2z = (double)hi + (double)lo;
-        const double r2 = u == 0 ? (double)r_m1 : (double)rr[u - 1 < 0 ? 0 : u - 1];
-        const double pv2 = u == 0 ? (double)c_m1 : (double)cv[u - 1 < 0 ? 0 : u - 1];
-        const double res2 = point_residual(a.k, (double)ctr, h2x, h2y, h2z, r2);
-        a.out_last[col + g.nxy * kk] = (T)point_update(a.k, (double)ctr, res2, cheb2, pv2, a.wc1);
+      for (int d = 0; d < NR; ++d) {
+        s1p[d] = s1[d];
+        bl[d] = cc[d];
+        cc[d] = ab[d];
       }
-      // history for the next batch (compile-time indices only)
+    }
+    if (k1 == g.nz) {  // the top level: its upper neighbour is itself
+      const int kk = g.nz - 1;
+      const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.out_last, pb, kk);
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        if (u == nb - 1) {
-          l1_m2 = u >= 1 ? l1v[u >= 1 ? u - 1 : 0] : l1_m1;
-          l1_m1 = l1v[u];
-          c_m1 = cv[u];
-          r_m1 = rr[u];
-        }
+      for (int r = 0; r < R; ++r) {
+        const T ctr = s1p[r + 1];
+        const T lo = kk == 0 ? ctr : s1pp[r];
+        const double h2x = (double)lane_shift<1>(ctr) + (double)lane_shift<-1>(ctr);
+        const double h2y = (double)s1p[r + 2] + (double)s1p[r];
+        const double h2z = (double)ctr + (double)lo;
+        const double r2 = point_residual(a.k, (double)ctr, h2x, h2y, h2z, (double)rm1[r]);
+        rsrc_store<T>(ro, ost[r], (T)point_update(a.k, (double)ctr, r2, CHEB, (double)cm1[r], a.wc1));
       }
     }
   }
@@ -347,8 +397,6 @@ __global__ __launch_bounds__(64 * TY) void sweep2_kernel(SweepArgs<T> a) {
     if (threadIdx.x == 0) a.partials[blockIdx.x] = s;
   }
 }
-
-constexpr int kTY2 = 8;  // two-sweep tile: 512 threads, core 62 x 6
 
 struct Shape {
   int kc, tiles_x, tiles_y, tiles_z, ntiles, blocks;
@@ -381,8 +429,21 @@ Shape shape_of(const Grid &g, int S, bool is_double) {
     sh.tiles_x = (g.nx + 64 * sh.wx - 1) / (64 * sh.wx);
     sh.tiles_y = (g.ny + ty - 1) / ty;
   } else {
+    // one wave per kR2 rows and 62-cell x segment, four waves per block; z
+    // chunks halved (to 8 levels at least) until about 8192 waves
     sh.tiles_x = (g.nx + 61) / 62;
-    sh.tiles_y = (g.ny + kTY2 - 3) / (kTY2 - 2);
+    sh.tiles_y = (g.ny + kR2 - 1) / kR2;
+    const int64_t rows = (int64_t)sh.tiles_x * sh.tiles_y;
+    sh.kc = g.nz;
+    while (sh.kc > 8 && rows * ((g.nz + sh.kc - 1) / sh.kc) < 8192) sh.kc = (sh.kc + 1) / 2;
+    for (;;) {
+      sh.tiles_z = (g.nz + sh.kc - 1) / sh.kc;
+      if ((rows * sh.tiles_z + 3) / 4 <= kPartials) break;
+      sh.kc *= 2;
+    }
+    sh.ntiles = (int)(rows * sh.tiles_z);
+    sh.blocks = ((sh.ntiles + 3) / 4 + 7) / 8 * 8;
+    return sh;
   }
   const int64_t cols = (int64_t)sh.tiles_x * sh.tiles_y;
   // z chunks: long enough to amortise the halo planes, short enough for
@@ -470,13 +531,13 @@ void launch_tsweep(const Grid &g, int S, bool chebyshev, bool check, bool first,
     else
       LES_PICK(1, 1, true);
   } else {
-    const dim3 block(64 * kTY2);
+    const dim3 block(256);
     if (chebyshev) {
-      if (check) sweep2_kernel<T, kTY2, true, true><<<grid, block, 0, s>>>(a);
-      else sweep2_kernel<T, kTY2, true, false><<<grid, block, 0, s>>>(a);
+      if (check) sweep2_kernel<T, kR2, true, true><<<grid, block, 0, s>>>(a);
+      else sweep2_kernel<T, kR2, true, false><<<grid, block, 0, s>>>(a);
     } else {
-      if (check) sweep2_kernel<T, kTY2, false, true><<<grid, block, 0, s>>>(a);
-      else sweep2_kernel<T, kTY2, false, false><<<grid, block, 0, s>>>(a);
+      if (check) sweep2_kernel<T, kR2, false, true><<<grid, block, 0, s>>>(a);
+      else sweep2_kernel<T, kR2, false, false><<<grid, block, 0, s>>>(a);
     }
   }
 #undef LES_PICK

@@ -106,6 +106,15 @@ __device__ __forceinline__ T rsrc_load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
 
+template <typename T>
+__device__ __forceinline__ void rsrc_store(__amdgpu_buffer_rsrc_t r, uint32_t off, T v) {
+  if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(
+        __builtin_bit_cast(__attribute__((ext_vector_type(2))) uint32_t, v), r, (int)off, 0, 0);
+}
+
 // Stencil access at level k of a wave's columns: plane address (scalar)
 // plus the lane's column offset (loop-invariant vector register), no
 // per-load address arithmetic.  EDGE: the level is within two cells of a
@@ -141,13 +150,7 @@ struct Lvl {
   // is at most 2 GiB), which the buffer range check discards: no
   // divergent branch around the store.
   __device__ __forceinline__ void store(T *f, T v, bool active) const {
-    const __amdgpu_buffer_rsrc_t r = plane_rsrc(f, pb, k);
-    const int off = active ? (int)p.o[2][2] : (int)0x80000000u;
-    if constexpr (sizeof(T) == 4)
-      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
-    else
-      __builtin_amdgcn_raw_buffer_store_b64(
-          __builtin_bit_cast(__attribute__((ext_vector_type(2))) uint32_t, v), r, off, 0, 0);
+    rsrc_store<T>(plane_rsrc(f, pb, k), active ? p.o[2][2] : 0x80000000u, v);
   }
 };
 

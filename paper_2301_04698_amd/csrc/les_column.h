@@ -23,7 +23,8 @@ struct ColMap {
   int ntx;       // 64-cell x segments per row
   int kc;        // levels per z chunk
   int nkc;       // z chunks
-  int units;     // ny * ntx * nkc (below 2^27: the grid has at most 2^34 cells)
+  int units;     // ny * ntx * nkc: at most n / 8, below 2^31 for any grid whose
+                 // workspace (25 fields) fits in one GPU's memory
   int blocks;    // multiple of 8 (one contiguous range of blocks per XCD)
 };
 

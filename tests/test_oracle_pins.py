@@ -658,6 +658,36 @@ def test_scalar_conservation_full_step(oracle_lib, scheme):
     assert np.abs(st["w"]).max() > 0.1
 
 
+@pytest.mark.parametrize("scheme", ["quick", "weno3"])
+def test_horizontal_momentum_conservation_free_slip(oracle_lib, scheme):
+    """Sec. 2.4: flux-form advection and the divergence of the SGS stress
+    only move momentum between cells; nothing crosses the periodic sides, and
+    free-slip walls carry neither mass flux nor stress.  The central pressure
+    gradient of a periodic field sums to zero along x and y, and buoyancy
+    acts on w only.  Without Coriolis, sponge and large-scale forcing the
+    domain integrals of rho0 u and rho0 v are conserved to round-off by full
+    steps, with the Smagorinsky viscosity varying in space.  A dropped or
+    mis-signed flux term, an unmatched face value or a wrong wall parity
+    breaks this (no-slip walls exert a stress, so there it must not hold)."""
+    def run(wall):
+        p = small("C1m", nx=12, ny=10, nz=16, fcor=0.0, ug=0.0, vg=0.0, sponge_max=0.0,
+                  wall=wall, poisson_tol=1e-8, poisson_scheme="chebyshev", advection=scheme)
+        st = li.initial_state(p)
+        _random_velocity(p, st)
+        rho0 = oracle_lib.reference_state(p)["rho0"][:, None, None]
+        mom = lambda s: np.array([(rho0 * s[c]).sum() for c in ("u", "v")])
+        scale = np.array([(rho0 * np.abs(st[c])).sum() for c in ("u", "v")])
+        m0 = mom(st)
+        drift = []
+        for _ in range(3):
+            oracle_lib.step(p, st, nsteps=1)
+            drift.append(np.abs(mom(st) - m0) / scale)
+        assert np.abs(st["w"]).max() > 0.1
+        return np.max(drift)
+    assert run("free_slip") <= 1e-13
+    assert run("no_slip") > 1e-6
+
+
 def test_surface_flux_budget(oracle_lib):
     p = small("C1m", nx=8, ny=8, nz=16, rad_F0=0.0, poisson_tol=1e-6,
               poisson_scheme="chebyshev")

@@ -7,6 +7,7 @@ force (dense eigenvalues, bisection, FFT exact solves) and exact solutions of
 ODEs discretised by the same time scheme.  CPU only.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -945,6 +946,33 @@ def test_uniform_viscosity_horizontal_modes(oracle_lib):
         assert amp < 0.95
         np.testing.assert_allclose(st[f] - base, a * amp * np.broadcast_to(c, st[f].shape),
                                    rtol=0, atol=abs(a) * 1e-11, err_msg=f)
+
+
+def test_validation_case_parameters_match_paper():
+    """The dry validation workloads carry the amplitudes, radii, domain sizes,
+    viscosities, end times and resolution range that Sec. 3 prints
+    (tests/golden/validation_cases.txt); their grids span the domain."""
+    golden = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "validation_cases.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                case, name, value = line.split()
+                golden.setdefault(case, {})[name] = float(value)
+    for case, vals in golden.items():
+        d = li.DRY_CASES[case]
+        for name, v in vals.items():
+            if name == "h_coarsest":
+                assert v in li.DRY_RESOLUTIONS
+            elif name == "h_finest":
+                assert min(li.DRY_RESOLUTIONS) == v
+            else:
+                assert d[name] == v, (case, name)
+        for h in li.DRY_RESOLUTIONS:
+            p = li.workload(f"{case}{h}")
+            assert p["nx"] * p["dx"] == vals["Lx"] and p["nz"] * p["dz"] == vals["H"]
+            assert p["ny"] == 1 and p["nu_const"] == vals["nu_const"]
+            assert p["bubble_amp"] == vals["bubble_amp"]
 
 
 @pytest.mark.parametrize("case", ["DC400", "RB400"])

@@ -6,6 +6,7 @@ Arrays are float64 numpy arrays of shape (nz, ny, nx).
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 
@@ -58,45 +59,63 @@ _lib = None
 _DP = C.POINTER(C.c_double)
 
 
+def _bind(L):
+    """Set the ctypes signatures of an oracle library."""
+    cfgp = C.POINTER(OCfg)
+    L.oracle_reference_state.argtypes = [cfgp, _DP, _DP, _DP, _DP]
+    L.oracle_exner.argtypes = [cfgp] + [C.c_double] * 4
+    L.oracle_exner.restype = C.c_double
+    L.oracle_theta_l.argtypes = [cfgp] + [C.c_double] * 5
+    L.oracle_theta_l.restype = C.c_double
+    L.oracle_qv_sat.argtypes = [cfgp, C.c_double, C.c_double]
+    L.oracle_qv_sat.restype = C.c_double
+    for name in ("oracle_qv_sat_ice", "oracle_qv_star"):
+        getattr(L, name).argtypes = [cfgp, C.c_double, C.c_double]
+        getattr(L, name).restype = C.c_double
+    L.oracle_liquid_fraction.argtypes = [cfgp, C.c_double]
+    L.oracle_liquid_fraction.restype = C.c_double
+    L.oracle_satadj.argtypes = [cfgp, C.c_double, C.c_double, C.c_double, _DP, _DP, _DP]
+    L.oracle_thermo.argtypes = [cfgp, _DP, _DP, _DP, _DP, _DP, _DP]
+    L.oracle_sgs_nu.argtypes = [cfgp, _DP, _DP, _DP, _DP, _DP]
+    L.oracle_advect.argtypes = [cfgp, _DP, _DP, _DP, _DP, C.c_double, _DP]
+    L.oracle_face_value.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double]
+    L.oracle_face_value.restype = C.c_double
+    L.oracle_diffuse.argtypes = [cfgp, _DP, C.c_double, _DP, _DP]
+    L.oracle_sgs_momentum.argtypes = [cfgp, _DP, _DP, _DP, _DP, _DP, _DP, _DP]
+    L.oracle_laplacian.argtypes = [cfgp, _DP, _DP]
+    L.oracle_app_a.argtypes = [cfgp, _DP, _DP]
+    L.oracle_divergence.argtypes = [cfgp, _DP, _DP, _DP, _DP]
+    L.oracle_radiation.argtypes = [cfgp, _DP, _DP, _DP]
+    L.oracle_poisson.argtypes = [cfgp, _DP, _DP, C.c_int32, C.POINTER(OSolve)]
+    L.oracle_jacobi_bounds.argtypes = [cfgp, _DP, _DP]
+    L.oracle_step.argtypes = [cfgp, _DP, _DP, _DP, _DP, _DP, _DP, C.c_int32,
+                              C.POINTER(C.c_int32), C.POINTER(OSolve), C.POINTER(ODebug)]
+    L.oracle_diagnostics.argtypes = [cfgp, _DP, _DP, _DP, _DP, _DP, _DP, _DP]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             from . import build as _b
             _b.build()
-        L = C.CDLL(LIB_PATH)
-        cfgp = C.POINTER(OCfg)
-        L.oracle_reference_state.argtypes = [cfgp, _DP, _DP, _DP, _DP]
-        L.oracle_exner.argtypes = [cfgp] + [C.c_double] * 4
-        L.oracle_exner.restype = C.c_double
-        L.oracle_theta_l.argtypes = [cfgp] + [C.c_double] * 5
-        L.oracle_theta_l.restype = C.c_double
-        L.oracle_qv_sat.argtypes = [cfgp, C.c_double, C.c_double]
-        L.oracle_qv_sat.restype = C.c_double
-        for name in ("oracle_qv_sat_ice", "oracle_qv_star"):
-            getattr(L, name).argtypes = [cfgp, C.c_double, C.c_double]
-            getattr(L, name).restype = C.c_double
-        L.oracle_liquid_fraction.argtypes = [cfgp, C.c_double]
-        L.oracle_liquid_fraction.restype = C.c_double
-        L.oracle_satadj.argtypes = [cfgp, C.c_double, C.c_double, C.c_double, _DP, _DP, _DP]
-        L.oracle_thermo.argtypes = [cfgp, _DP, _DP, _DP, _DP, _DP, _DP]
-        L.oracle_sgs_nu.argtypes = [cfgp, _DP, _DP, _DP, _DP, _DP]
-        L.oracle_advect.argtypes = [cfgp, _DP, _DP, _DP, _DP, C.c_double, _DP]
-        L.oracle_face_value.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double]
-        L.oracle_face_value.restype = C.c_double
-        L.oracle_diffuse.argtypes = [cfgp, _DP, C.c_double, _DP, _DP]
-        L.oracle_sgs_momentum.argtypes = [cfgp, _DP, _DP, _DP, _DP, _DP, _DP, _DP]
-        L.oracle_laplacian.argtypes = [cfgp, _DP, _DP]
-        L.oracle_app_a.argtypes = [cfgp, _DP, _DP]
-        L.oracle_divergence.argtypes = [cfgp, _DP, _DP, _DP, _DP]
-        L.oracle_radiation.argtypes = [cfgp, _DP, _DP, _DP]
-        L.oracle_poisson.argtypes = [cfgp, _DP, _DP, C.c_int32, C.POINTER(OSolve)]
-        L.oracle_jacobi_bounds.argtypes = [cfgp, _DP, _DP]
-        L.oracle_step.argtypes = [cfgp, _DP, _DP, _DP, _DP, _DP, _DP, C.c_int32,
-                                  C.POINTER(C.c_int32), C.POINTER(OSolve), C.POINTER(ODebug)]
-        L.oracle_diagnostics.argtypes = [cfgp, _DP, _DP, _DP, _DP, _DP, _DP, _DP]
-        _lib = L
+        _lib = _bind(C.CDLL(LIB_PATH))
     return _lib
+
+
+@contextlib.contextmanager
+def variant(path):
+    """Route every call of this module to another build of the oracle (a
+    copy with a deliberately planted mistake, built by the tests to show
+    that a pin fails on it) for the duration of the block."""
+    global _lib
+    saved = lib()
+    _lib = _bind(C.CDLL(path))
+    try:
+        yield
+    finally:
+        _lib = saved
 
 
 def make_cfg(p: dict) -> OCfg:

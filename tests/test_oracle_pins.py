@@ -269,6 +269,146 @@ def test_buoyancy_zero_at_reference(oracle_lib):
     np.testing.assert_allclose(th["T"][:, 0, 0], rs["T0"], rtol=1e-15)
 
 
+def _check_buoyancy_dry(lib):
+    """Dry air (q_t = 0) at the reference pressure: alpha / alpha0 = T / T0
+    = theta / theta0, so b = g (theta_l - theta0) / theta0 exactly, the
+    textbook dry buoyancy (Sec. 2.1 buoyancy and equation of state)."""
+    p = small(nx=4, ny=3, nz=32)
+    shape = (p["nz"], p["ny"], p["nx"])
+    rng = np.random.default_rng(21)
+    dth = rng.uniform(0.5, 3.0, shape) * rng.choice([-1.0, 1.0], shape)
+    th = lib.thermo(p, p["theta0"] + dth, np.zeros(shape))
+    np.testing.assert_allclose(th["b"], p["g"] * dth / p["theta0"], rtol=1e-10, atol=0)
+
+
+def _moist_states(p):
+    """Unsaturated moist cells (2-6 g/kg) in the lower half of the column and
+    cloudy cells (10-14 g/kg) in the upper half, theta_l within 2 K of theta0."""
+    shape = (p["nz"], p["ny"], p["nx"])
+    rng = np.random.default_rng(22)
+    upper = (np.arange(p["nz"]) >= p["nz"] // 2)[:, None, None]
+    qt = np.where(upper, rng.uniform(10e-3, 14e-3, shape), rng.uniform(2e-3, 6e-3, shape))
+    thl = p["theta0"] + rng.uniform(-2.0, 2.0, shape)
+    return thl, qt
+
+
+def _check_buoyancy_moist(lib):
+    """Moist air: the textbook buoyancy with water-vapour and condensate
+    loading, linearised in small perturbations,
+        b ~ g [ (T - T0)/T0 + (R_v/R_d - 1) q_v - q_c ],
+    holds up to its second-order remainder g |(T - T0)/T0| |(R_v/R_d - 1) q_v - q_c|.
+    T and q_c come from the saturation adjustment (pinned by the round trip
+    and bisection tests), T0 from the closed form T0 = theta0 - g z / c_pd.
+    A condensate left out of R_m shifts b by g q_c R_v/R_d (~0.02 m/s^2 per
+    g/kg), a reference temperature in place of T by g (T - T0)/T0; both are
+    first order and exceed the remainder many times over."""
+    p = small(nx=4, ny=4, nz=32, dz=25.0)
+    thl, qt = _moist_states(p)
+    th = lib.thermo(p, thl, qt)
+    qc = th["ql"] + th["qi"]
+    cloudy = qc > 5e-4
+    assert cloudy.mean() > 0.3 and ((qc == 0) & (qt > 2e-3)).mean() > 0.3
+    T0 = (p["theta0"] - p["g"] * li.cell_heights(p) / p["cpd"])[:, None, None]
+    dT = th["T"] / T0 - 1.0
+    a = (p["Rv"] / p["Rd"] - 1.0) * (qt - qc) - qc
+    lin = p["g"] * (dT + a)
+    bound = p["g"] * np.abs(dT) * np.abs(a) * (1 + 1e-9) + 1e-13
+    assert np.all(np.abs(th["b"] - lin) <= bound), np.max(np.abs(th["b"] - lin) / bound)
+    assert np.max(bound) < 2e-3
+
+
+def _check_radiation_heating(lib):
+    """One step with K = 1 of a column at rest with no advection, diffusion,
+    surface flux or subsidence changes theta_l only by the radiative source
+    of the Sec. 2.1 theta_l equation: rho0 d theta_l / dt =
+    -(c_pm Pi)^-1 d F / dz, F the synthetic longwave flux at the faces.
+    c_pm Pi is taken from the theta_l definition solved for Pi,
+    c_pm Pi = (c_pm T - L_v0 q_l) / theta_l, not from the Exner power, so a
+    heating that uses c_pm alone (Pi dropped, 2-5 % off here) fails."""
+    p = small("C1m", nx=2, ny=2, n_subiter=1, ug=0.0, vg=0.0, fcor=0.0, shf=0.0, lhf=0.0,
+              noise_thl=0.0, noise_qt=0.0, cs=0.0, sponge_max=0.0, poisson_tol=1e-8,
+              poisson_scheme="chebyshev")
+    st = li.initial_state(p)
+    thl0, qt = st["thl"][:, 0, 0].copy(), st["qt"][:, 0, 0].copy()
+    th = lib.thermo(p, st["thl"], st["qt"])
+    lib.step(p, st, nsteps=1)
+    rs = lib.reference_state(p)
+    T, ql = th["T"][:, 0, 0], th["ql"][:, 0, 0]
+    assert ql.max() > 3e-4 and np.all(th["qi"] == 0)
+    cpm = (1 - qt) * p["cpd"] + (qt - ql) * p["cpv"] + ql * p["cl"]
+    cpm_pi = (cpm * T - p["Lv0"] * ql) / thl0
+    nz = p["nz"]
+    F = np.empty(nz + 1)
+    F[nz] = p["rad_F0"]
+    path = 0.0
+    for k in range(nz - 1, -1, -1):
+        path += rs["rho0"][k] * ql[k] * p["dz"]
+        F[k] = p["rad_F0"] * np.exp(-p["rad_kappa"] * path)
+    expect = -p["dt"] / rs["rho0"] * (F[1:] - F[:-1]) / (p["dz"] * cpm_pi)
+    got = st["thl"][:, 0, 0] - thl0
+    assert np.abs(expect).max() > 1e-4
+    np.testing.assert_allclose(got, expect, rtol=1e-7, atol=1e-12)
+    assert np.all(st["thl"] == st["thl"][:, :1, :1])
+
+
+def test_buoyancy_dry_is_textbook(oracle_lib):
+    _check_buoyancy_dry(oracle_lib)
+
+
+def test_buoyancy_moist_linearisation(oracle_lib):
+    _check_buoyancy_moist(oracle_lib)
+
+
+def test_radiation_heating_per_level(oracle_lib):
+    _check_radiation_heating(oracle_lib)
+
+
+# Planted mistakes: a copy of the oracle with one plausible error each,
+# built on the CPU, must fail the pins above.
+PLANTED = {
+    "condensate_left_out_of_Rm": (
+        "double Rm = (1.0 - qt[n]) * c->Rd + (qt[n] - qlc - qic) * c->Rv;",
+        "double Rm = (1.0 - qt[n]) * c->Rd + qt[n] * c->Rv;",
+        [_check_buoyancy_moist]),
+    "reference_temperature_in_alpha": (
+        "double alpha = Rm * Tc / P.p0[k];",
+        "double alpha = Rm * P.T0[k] / P.p0[k];",
+        [_check_buoyancy_dry, _check_buoyancy_moist]),
+    "exner_dropped_from_radiative_heating": (
+        "return cpm * oracle_exner(c, p0, qt, ql, qi);",
+        "return cpm;",
+        [_check_radiation_heating]),
+}
+
+
+def _build_planted(tmp_path, old, new):
+    import shutil
+    import subprocess
+    from oracle import build as obuild
+    src = os.path.join(os.path.dirname(obuild.HERE), "oracle")
+    for f in os.listdir(src):
+        if f.endswith((".c", ".h")):
+            shutil.copy(os.path.join(src, f), tmp_path / f)
+    path = tmp_path / "les_oracle.c"
+    text = path.read_text()
+    assert text.count(old) == 1, old
+    path.write_text(text.replace(old, new))
+    lib = str(tmp_path / "liboracle_planted.so")
+    subprocess.run(obuild.CMD + [lib, str(path), str(tmp_path / "cnn_oracle.c"), "-lm"],
+                   check=True)
+    return lib
+
+
+@pytest.mark.parametrize("name", sorted(PLANTED))
+def test_planted_thermodynamics_mistakes_fail_pins(oracle_lib, tmp_path, name):
+    old, new, checks = PLANTED[name]
+    lib = _build_planted(tmp_path, old, new)
+    with oracle_lib.variant(lib):
+        for check in checks:
+            with pytest.raises(AssertionError):
+                check(oracle_lib)
+
+
 # ---------------------------------------------------- discrete operators
 
 def _modes(p, ax, m):

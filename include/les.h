@@ -57,6 +57,18 @@ enum { LES_NO_SLIP = 0, LES_FREE_SLIP = 1 };  /* u, v at the walls z = 0, H */
  * sublimation heat Ls0; the saturation humidity of a partition is the
  * liquid-share-weighted mean of the two. */
 enum { LES_PHASE_HEAVISIDE = 0, LES_PHASE_RAMP = 1 };
+/* Horizontally uniform part of each pressure-correction solve.  The compact
+ * Laplacian maps a function of z alone to its second difference in z and
+ * commutes with horizontal averaging, so the horizontal mean of the
+ * equation is a one-dimensional Neumann problem that decouples from the
+ * other modes:
+ *   LES_MEAN_SWEPT  the sweeps solve it with the rest (the paper's method
+ *                   as written)
+ *   LES_MEAN_EXACT  it is solved exactly in FP64 (two running sums) and the
+ *                   sweeps start from that solution; its part of phi and of
+ *                   the pressure is kept as FP64 profiles (see les_buffers.p)
+ * Both meet the same residual test. */
+enum { LES_MEAN_SWEPT = 0, LES_MEAN_EXACT = 1 };
 /* Initial guess of the pressure-correction solves:
  *   LES_GUESS_ZERO         phi_0 = 0 for every solve (the plain method)
  *   LES_GUESS_EXTRAPOLATE  first solve of a step: phi_0 = alpha0 (p^n -
@@ -114,6 +126,8 @@ typedef struct les_config {
                                    nu/Pr and nu/Sc.  0: Smagorinsky */
   double T_ice;                 /* LES_PHASE_RAMP: all condensate is ice at
                                    and below T_ice (K), 0 < T_ice < Tf */
+  int32_t mean_mode;            /* LES_MEAN_SWEPT or LES_MEAN_EXACT */
+  int32_t reserved;             /* 0 */
 } les_config;
 
 /* Caller-owned device buffers.  u, v, w: velocity (m/s); thl: liquid-ice

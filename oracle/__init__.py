@@ -22,6 +22,7 @@ GUESSES = {"zero": 0, "extrapolate": 1, "previous": 2}
 ADVECTION = {"quick": 0, "weno3": 1}
 WALLS = {"no_slip": 0, "free_slip": 1}
 PHASES = {"heaviside": 0, "ramp": 1}
+MEAN_MODES = {"swept": 0, "exact": 1}
 
 
 class OCfg(C.Structure):
@@ -30,7 +31,8 @@ class OCfg(C.Structure):
         ("poisson_scheme", C.c_int32), ("poisson_check_every", C.c_int32),
         ("poisson_max_sweeps", C.c_int32), ("satadj_maxit", C.c_int32),
         ("guess", C.c_int32), ("advection", C.c_int32),
-        ("wall", C.c_int32), ("phase", C.c_int32),
+        ("wall", C.c_int32), ("phase", C.c_int32), ("mean_mode", C.c_int32),
+        ("reserved", C.c_int32),
         ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("dt", C.c_double),
         ("poisson_tol", C.c_double), ("jacobi_omega", C.c_double),
         ("p00", C.c_double), ("theta0", C.c_double), ("Rd", C.c_double), ("Rv", C.c_double),
@@ -87,6 +89,7 @@ def _bind(L):
     L.oracle_divergence.argtypes = [cfgp, _DP, _DP, _DP, _DP]
     L.oracle_radiation.argtypes = [cfgp, _DP, _DP, _DP]
     L.oracle_poisson.argtypes = [cfgp, _DP, _DP, C.c_int32, C.POINTER(OSolve)]
+    L.oracle_poisson_gated.argtypes = [cfgp, _DP, _DP, C.c_int32, C.POINTER(OSolve)]
     L.oracle_jacobi_bounds.argtypes = [cfgp, _DP, _DP]
     L.oracle_step.argtypes = [cfgp, _DP, _DP, _DP, _DP, _DP, _DP, C.c_int32,
                               C.POINTER(C.c_int32), C.POINTER(OSolve), C.POINTER(ODebug)]
@@ -145,6 +148,13 @@ def make_cfg(p: dict) -> OCfg:
             if v not in PHASES:
                 raise ValueError(f"unknown phase partition {v!r}; known: {sorted(PHASES)}")
             c.phase = PHASES[v]
+        elif name == "mean_mode":
+            v = p.get("mean_mode", "exact")
+            if v not in MEAN_MODES:
+                raise ValueError(f"unknown mean mode {v!r}; known: {sorted(MEAN_MODES)}")
+            c.mean_mode = MEAN_MODES[v]
+        elif name == "reserved":
+            c.reserved = 0
         else:
             setattr(c, name, ctype(p[name]).value)
     return c
@@ -284,15 +294,19 @@ def jacobi_bounds(p):
     return a.value, b.value
 
 
-def poisson(p, rhs, guess=None, fixed_sweeps=0):
-    """Returns (phi, stats dict)."""
+def poisson(p, rhs, guess=None, fixed_sweeps=0, gated=False):
+    """Returns (phi, stats dict).  gated: the solve as the time step runs it
+    for a guess (kept only if it starts closer than the zero start, solved
+    again from the zero start if its sweeps reach the cap)."""
     rhs = _f64(rhs)
     phi = np.zeros(_shape(p)) if guess is None else _f64(guess).copy()
     st = OSolve()
-    rc = lib().oracle_poisson(C.byref(make_cfg(p)), _ptr(rhs), _ptr(phi), int(fixed_sweeps), C.byref(st))
+    fn = lib().oracle_poisson_gated if gated else lib().oracle_poisson
+    rc = fn(C.byref(make_cfg(p)), _ptr(rhs), _ptr(phi), int(fixed_sweeps), C.byref(st))
     if rc not in (0, -3):
         raise RuntimeError(f"oracle poisson failed with code {rc}")
-    return phi, dict(sweeps=st.sweeps, status=st.status, rhs_norm=st.rhs_norm, res_norm=st.res_norm)
+    return phi, dict(sweeps=st.sweeps, status=st.status, rhs_norm=st.rhs_norm, res_norm=st.res_norm,
+                     guess=st.guess)
 
 
 DEBUG_FIELDS = ("b_half", "nu", "rhs", "phi", "uhat", "vhat", "what")

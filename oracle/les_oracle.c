@@ -644,27 +644,65 @@ int oracle_jacobi_bounds(const ocfg *c, double *mu_min, double *mu_max) {
   return 0;
 }
 
-/* Solve L phi = rhs (Sec. 2.4, pressure-correction equation; the unknown is
- * phi = alpha0 delta p) by weighted Jacobi sweeps
+/* Horizontal mean of field f on every level. */
+static void level_means(const ocfg *c, const double *f, double *mean) {
+  size_t nxy = (size_t)c->nx * c->ny;
+  for (int k = 0; k < c->nz; ++k) {
+    double s = 0.0;
+    for (size_t q = 0; q < nxy; ++q) s += f[(size_t)k * nxy + q];
+    mean[k] = s / (double)nxy;
+  }
+}
+
+/* The horizontally uniform part of L phi = rhs.  READING (the paper sweeps
+ * every mode): the compact Laplacian maps a function of z alone to its
+ * second difference in z, and horizontal averaging commutes with it, so the
+ * horizontal mean of the equation is the one-dimensional Neumann problem
+ *   (pb_{k+1} - 2 pb_k + pb_{k-1}) / dz^2 = rb_k   (mirror ghosts),
+ * decoupled from the other modes.  Its exact solution: the face gradient
+ * G_{k+1/2} = (pb_{k+1} - pb_k)/dz is zero at the bottom wall and grows by
+ * dz rb_k across level k, so G_{k+1/2} = dz sum_{m<=k} rb_m and
+ * pb_{k+1} = pb_k + dz G_{k+1/2}; then the vertical mean is removed.  rb has
+ * zero vertical mean (the rhs mean is removed), which is what makes the
+ * gradient at the top wall vanish too. */
+static void mean_mode_solve(const ocfg *c, const double *rb, double *pb) {
+  double G = 0.0, s = 0.0;
+  pb[0] = 0.0;
+  for (int k = 0; k + 1 < c->nz; ++k) {
+    G += c->dz * rb[k];
+    pb[k + 1] = pb[k] + c->dz * G;
+  }
+  for (int k = 0; k < c->nz; ++k) s += pb[k];
+  for (int k = 0; k < c->nz; ++k) pb[k] -= s / c->nz;
+}
+
+/* ||rhs - L phi||_2 with L phi = neighbour sum - D phi. */
+static double residual_norm(const ocfg *c, const double *rhs, const double *phi, double *tmp) {
+  double d = 2.0 / (c->dx * c->dx) + 2.0 / (c->dy * c->dy) + 2.0 / (c->dz * c->dz);
+  neighbour_sum(c, phi, tmp);
+  double s = 0.0;
+  for (size_t q = 0; q < ncell(c); ++q) {
+    double r = rhs[q] - (tmp[q] - d * phi[q]);
+    s += r * r;
+  }
+  return sqrt(s);
+}
+
+/* Weighted-Jacobi sweeps on L phi = rhs (rhs centred) from the iterate in
+ * phi until ||rhs - L phi||_2 <= tol * rn (checked every check_every
+ * sweeps), the cap, or exactly fixed_sweeps sweeps:
  *   phi' = (1 - w) phi + w [sum_axes (phi_+ + phi_-)/Delta^2 - rhs] / D.
  * READING: w = 2 / (mu_min + mu_max) unless set; scheme 1 accelerates the
  * same sweep with the Chebyshev two-term recurrence
  *   phi_{m+1} = phi_{m-1} + w_{m+1} (J(phi_m) - phi_{m-1}),
  *   w_1 = 1, w_2 = 1/(1 - rho^2/2), w_{m+1} = 1/(1 - rho^2 w_m / 4),
- * rho = (mu_max - mu_min)/(mu_max + mu_min).  rhs gets its mean removed
- * (compatibility); the residual of the current iterate is checked every
- * check_every sweeps against tol * ||rhs||_2; the solution has zero mean. */
-int oracle_poisson(const ocfg *c, const double *rhs_in, double *phi, int32_t fixed_sweeps,
-                   osolve *st) {
-  if (check_cfg(c)) return -1;
+ * rho = (mu_max - mu_min)/(mu_max + mu_min).  Returns the status (0
+ * converged, 1 not converged, -3 non-finite); *sweeps and *res get the
+ * sweep count and the residual norm of the returned iterate. */
+static int jacobi_sweeps(const ocfg *c, const double *rhs, double rn, double *phi,
+                         int32_t fixed_sweeps, double *tmp, double *prev, int *sweeps,
+                         double *res) {
   size_t n = ncell(c);
-  double *rhs = malloc(n * sizeof(double));
-  double *tmp = malloc(n * sizeof(double));
-  double *prev = malloc(n * sizeof(double));
-  if (!rhs || !tmp || !prev) { free(rhs); free(tmp); free(prev); return -1; }
-  double mr = fsum(c, rhs_in) / (double)n;
-  for (size_t q = 0; q < n; ++q) rhs[q] = rhs_in[q] - mr;
-  double rn = fnorm2(c, rhs);
   double d = 2.0 / (c->dx * c->dx) + 2.0 / (c->dy * c->dy) + 2.0 / (c->dz * c->dz);
   double mu0, mu1;
   oracle_jacobi_bounds(c, &mu0, &mu1);
@@ -672,46 +710,99 @@ int oracle_poisson(const ocfg *c, const double *rhs_in, double *phi, int32_t fix
   double rho = (mu1 - mu0) / (mu1 + mu0);
   double wcheb = 1.0;
   memcpy(prev, phi, n * sizeof(double));
-
   int m = 0, status = 1;
   double rr = 0.0;
-  if (rn == 0.0) {
-    status = 0;
-  } else {
-    for (;;) {
-      int check = fixed_sweeps > 0 ? (m == fixed_sweeps)
-                                   : (m % c->poisson_check_every == 0 || m >= c->poisson_max_sweeps);
-      if (check) {
-        /* r = rhs - L phi with L phi = neighbour sum - D phi */
-        neighbour_sum(c, phi, tmp);
-        double s = 0.0;
-        for (size_t q = 0; q < n; ++q) {
-          double r = rhs[q] - (tmp[q] - d * phi[q]);
-          s += r * r;
-        }
-        rr = sqrt(s);
-        if (!isfinite(rr)) { status = -3; break; }
-        if (fixed_sweeps > 0) { status = rr <= c->poisson_tol * rn ? 0 : 1; break; }
-        if (rr <= c->poisson_tol * rn) { status = 0; break; }
-        if (m >= c->poisson_max_sweeps) { status = 1; break; }
+  for (;;) {
+    int check = fixed_sweeps > 0 ? (m == fixed_sweeps)
+                                 : (m % c->poisson_check_every == 0 || m >= c->poisson_max_sweeps);
+    if (check) {
+      rr = residual_norm(c, rhs, phi, tmp);
+      if (!isfinite(rr)) { status = -3; break; }
+      if (fixed_sweeps > 0) { status = rr <= c->poisson_tol * rn ? 0 : 1; break; }
+      if (rr <= c->poisson_tol * rn) { status = 0; break; }
+      if (m >= c->poisson_max_sweeps) { status = 1; break; }
+    }
+    /* one sweep: tmp = J(phi), the weighted-Jacobi update */
+    double wj = c->poisson_scheme == 1 ? 2.0 / (mu0 + mu1) : omega;
+    neighbour_sum(c, phi, tmp);
+    for (size_t q = 0; q < n; ++q) tmp[q] = (1.0 - wj) * phi[q] + wj * (tmp[q] - rhs[q]) / d;
+    if (c->poisson_scheme == 1) {
+      if (m == 0) wcheb = 1.0;
+      else if (m == 1) wcheb = 1.0 / (1.0 - 0.5 * rho * rho);
+      else wcheb = 1.0 / (1.0 - 0.25 * rho * rho * wcheb);
+      for (size_t q = 0; q < n; ++q) {
+        double next = prev[q] + wcheb * (tmp[q] - prev[q]);
+        prev[q] = phi[q];
+        phi[q] = next;
       }
-      /* one sweep: tmp = J(phi), the weighted-Jacobi update */
-      double wj = c->poisson_scheme == 1 ? 2.0 / (mu0 + mu1) : omega;
-      neighbour_sum(c, phi, tmp);
-      for (size_t q = 0; q < n; ++q) tmp[q] = (1.0 - wj) * phi[q] + wj * (tmp[q] - rhs[q]) / d;
-      if (c->poisson_scheme == 1) {
-        if (m == 0) wcheb = 1.0;
-        else if (m == 1) wcheb = 1.0 / (1.0 - 0.5 * rho * rho);
-        else wcheb = 1.0 / (1.0 - 0.25 * rho * rho * wcheb);
-        for (size_t q = 0; q < n; ++q) {
-          double next = prev[q] + wcheb * (tmp[q] - prev[q]);
-          prev[q] = phi[q];
-          phi[q] = next;
-        }
-      } else {
-        memcpy(phi, tmp, n * sizeof(double));
-      }
-      ++m;
+    } else {
+      memcpy(phi, tmp, n * sizeof(double));
+    }
+    ++m;
+  }
+  *sweeps = m;
+  *res = rr;
+  return status;
+}
+
+/* Solve L phi = rhs (Sec. 2.4, pressure-correction equation; the unknown is
+ * phi = alpha0 delta p).  rhs gets its mean removed (compatibility); the
+ * stopping test is relative to its norm; the solution has zero mean.
+ * The zero start is phi = 0, or with mean_mode = 1 the exact solution of the
+ * horizontally uniform part (mean_mode_solve).  phi in holds the guess: the
+ * start is the zero start plus the guess (with mean_mode = 1 the guess's
+ * horizontal means per level are removed first, as that part is already
+ * exact).  gate = 1: the guess is kept only if its residual is below the
+ * zero start's, and a kept guess whose sweeps reach the cap (no fixed
+ * count) is dropped and the sweeps repeated from the zero start. */
+static int poisson_solve(const ocfg *c, const double *rhs_in, double *phi, int32_t fixed_sweeps,
+                         int gate, osolve *st) {
+  if (check_cfg(c)) return -1;
+  size_t n = ncell(c), nxy = (size_t)c->nx * c->ny;
+  double *rhs = malloc(n * sizeof(double));
+  double *tmp = malloc(n * sizeof(double));
+  double *prev = malloc(n * sizeof(double));
+  double *zero = malloc(n * sizeof(double));
+  double *rb = malloc(c->nz * sizeof(double));
+  double *pb = malloc(c->nz * sizeof(double));
+  double *gb = malloc(c->nz * sizeof(double));
+  if (!rhs || !tmp || !prev || !zero || !rb || !pb || !gb) {
+    free(rhs); free(tmp); free(prev); free(zero); free(rb); free(pb); free(gb);
+    return -1;
+  }
+  double mr = fsum(c, rhs_in) / (double)n;
+  for (size_t q = 0; q < n; ++q) rhs[q] = rhs_in[q] - mr;
+  double rn = fnorm2(c, rhs);
+  /* zero start, and the guess with its level means removed */
+  for (int k = 0; k < c->nz; ++k) pb[k] = gb[k] = 0.0;
+  if (c->mean_mode == 1) {
+    level_means(c, rhs, rb);
+    mean_mode_solve(c, rb, pb);
+    level_means(c, phi, gb);
+  }
+  for (int k = 0; k < c->nz; ++k)
+    for (size_t q = (size_t)k * nxy; q < (size_t)(k + 1) * nxy; ++q) {
+      zero[q] = pb[k];
+      phi[q] = pb[k] + (phi[q] - gb[k]);
+    }
+  int guessed = 0;
+  if (gate) {
+    guessed = 1;
+    if (!(residual_norm(c, rhs, phi, tmp) < residual_norm(c, rhs, zero, tmp))) {
+      memcpy(phi, zero, n * sizeof(double));
+      guessed = 2;
+    }
+  }
+  int m = 0, status = 0;
+  double rr = 0.0;
+  if (rn > 0.0) {
+    status = jacobi_sweeps(c, rhs, rn, phi, fixed_sweeps, tmp, prev, &m, &rr);
+    if (status == 1 && guessed == 1 && fixed_sweeps == 0) {
+      int m2 = 0;
+      memcpy(phi, zero, n * sizeof(double));
+      status = jacobi_sweeps(c, rhs, rn, phi, 0, tmp, prev, &m2, &rr);
+      m += m2;
+      guessed = 3;
     }
   }
   double mp = fsum(c, phi) / (double)n;
@@ -721,11 +812,21 @@ int oracle_poisson(const ocfg *c, const double *rhs_in, double *phi, int32_t fix
     st->status = status;
     st->rhs_norm = rn;
     st->res_norm = rr;
-    st->guess = 0;
+    st->guess = guessed;
     st->reserved = 0;
   }
-  free(rhs); free(tmp); free(prev);
+  free(rhs); free(tmp); free(prev); free(zero); free(rb); free(pb); free(gb);
   return status < 0 ? status : 0;
+}
+
+int oracle_poisson(const ocfg *c, const double *rhs_in, double *phi, int32_t fixed_sweeps,
+                   osolve *st) {
+  return poisson_solve(c, rhs_in, phi, fixed_sweeps, 0, st);
+}
+
+int oracle_poisson_gated(const ocfg *c, const double *rhs_in, double *phi, int32_t fixed_sweeps,
+                         osolve *st) {
+  return poisson_solve(c, rhs_in, phi, fixed_sweeps, 1, st);
 }
 
 /* ---------------------------------------------------------- time step */
@@ -881,6 +982,8 @@ int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, dou
       for (int k = 0; k < c->nz; ++k)
         for (size_t q = (size_t)k * c->nx * c->ny; q < (size_t)(k + 1) * c->nx * c->ny; ++q)
           S.rhs[q] = P.alpha0[k] / c->dt * S.rhs[q] - S.tmp[q];
+      double mr = fsum(c, S.rhs) / (double)n;
+      for (size_t q = 0; q < n; ++q) S.rhs[q] -= mr;
       memset(S.phi, 0, n * sizeof(double));
       int guessed = 0;
       if (c->guess == 1 && it == 0) {
@@ -893,28 +996,9 @@ int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, dou
         memcpy(S.phi, hist + (size_t)it * n, n * sizeof(double));
         guessed = 1;
       }
-      double mr = fsum(c, S.rhs) / (double)n;
-      for (size_t q = 0; q < n; ++q) S.rhs[q] -= mr;
-      if (guessed) {
-        /* keep the guess only if it starts closer than zero:
-           ||rhs - L phi_0|| < ||rhs|| */
-        oracle_laplacian(c, S.phi, S.tmp);
-        double rr = 0.0, bb = 0.0;
-        for (size_t q = 0; q < n; ++q) {
-          double r = S.rhs[q] - S.tmp[q];
-          rr += r * r;
-          bb += S.rhs[q] * S.rhs[q];
-        }
-        if (!(rr < bb)) {
-          memset(S.phi, 0, n * sizeof(double));
-          guessed = 2;
-        }
-      }
       osolve st;
       int fixed = replay ? replay[solve] : 0;
-      rc = oracle_poisson(c, S.rhs, S.phi, fixed, &st);
-      st.guess = guessed;
-      st.reserved = 0;
+      rc = poisson_solve(c, S.rhs, S.phi, fixed, guessed, &st);
       if (rec) rec[solve] = st;
       ++solve;
       if (rc) break;

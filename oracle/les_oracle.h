@@ -25,6 +25,9 @@ typedef struct ocfg {
   int32_t advection;           /* 0 QUICK, 1 WENO3 with Lax-Friedrichs flux */
   int32_t wall;                /* u, v at z = 0, H: 0 no-slip (odd mirror), 1 free-slip (even) */
   int32_t phase;               /* condensate partition: 0 Heaviside at T_f, 1 linear ramp T_ice..T_f */
+  int32_t mean_mode;           /* horizontally uniform part of each solve: 0 swept with the
+                                  rest, 1 solved exactly first (see oracle_poisson) */
+  int32_t reserved;
   double dx, dy, dz, dt;
   double poisson_tol;          /* ||rhs - L phi||_2 <= tol * ||rhs||_2 */
   double jacobi_omega;         /* 0 = closed-form optimum */
@@ -43,7 +46,9 @@ typedef struct osolve {        /* one Poisson solve */
   int32_t status;              /* 0 converged, 1 not converged, -3 non-finite */
   double rhs_norm;             /* ||rhs||_2 after mean removal */
   double res_norm;             /* ||rhs - L phi||_2 of the returned iterate */
-  int32_t guess;               /* oracle_step: 0 zero start, 1 guess kept, 2 rejected */
+  int32_t guess;               /* oracle_step: 0 zero start, 1 guess kept, 2 rejected,
+                                  3 kept but the cap was reached, solved again from
+                                  the zero start (sweeps count both passes) */
   int32_t reserved;
 } osolve;
 
@@ -84,9 +89,18 @@ int oracle_divergence(const ocfg *c, const double *U, const double *V, const dou
 int oracle_radiation(const ocfg *c, const double *ql, const double *cpm_pi, double *out);
 
 /* Poisson solve (Sec. 2.4): phi in = guess, out = zero-mean solution.
- * fixed_sweeps > 0 performs exactly that many sweeps. */
+ * fixed_sweeps > 0 performs exactly that many sweeps.  With mean_mode = 1
+ * the horizontal mean of the equation, a one-dimensional Neumann problem in
+ * z, is solved exactly first and the sweeps start from that solution plus
+ * the guess with its horizontal mean per level removed. */
 int oracle_poisson(const ocfg *c, const double *rhs, double *phi, int32_t fixed_sweeps,
                    osolve *st);
+/* The same solve as the time step runs it for a guess: the guess is kept
+ * only if its residual is below the zero start's, and a kept guess whose
+ * sweeps reach the cap (no fixed count) is dropped and the sweeps repeated
+ * from the zero start; st->guess as in oracle_step's records. */
+int oracle_poisson_gated(const ocfg *c, const double *rhs, double *phi, int32_t fixed_sweeps,
+                         osolve *st);
 /* Closed-form extreme eigenvalues of -D^{-1} L on zero-mean fields. */
 int oracle_jacobi_bounds(const ocfg *c, double *mu_min, double *mu_max);
 
@@ -107,9 +121,11 @@ typedef struct odebug {
  *      the last step (zero on the first step of the call); later solves zero;
  *   2  each sub-iteration: the zero-mean solution of the same sub-iteration
  *      of the last step (zero on the first step of the call).
- * A guess is kept only if ||rhs - L phi_0||_2 < ||rhs||_2 (the residual of
- * the zero start, rhs with its mean removed); otherwise the solve starts
- * from zero.
+ * A guess is kept only if ||rhs - L phi_0||_2 is below the residual of the
+ * zero start (rhs with its mean removed; with mean_mode = 1, rhs minus its
+ * horizontal mean per level); otherwise the solve starts from the zero
+ * start.  A kept guess whose solve reaches the sweep cap is dropped and the
+ * solve repeated from the zero start (not with replayed sweep counts).
  * The guess changes the sweep count only: the stopping test is relative to
  * ||rhs||, whatever the starting iterate. */
 int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, double *qt,

@@ -95,6 +95,8 @@ int validate(const les_config *c) {
     return fail(LES_ERR_ARG, "T_ice must be in (0, Tf) for LES_PHASE_RAMP");
   if (c->guess < LES_GUESS_ZERO || c->guess > LES_GUESS_LEARNED)
     return fail(LES_ERR_ARG, "unknown guess mode %d", c->guess);
+  if (c->mean_mode != LES_MEAN_SWEPT)
+    return fail(LES_ERR_ARG, "mean mode %d is not supported", c->mean_mode);
   return LES_OK;
 }
 
@@ -820,6 +822,7 @@ void les_default_config(les_config *c) {
   c->T_tr = 273.16;
   c->satadj_tol = 1e-10;
   c->T_ice = 233.15;
+  c->mean_mode = LES_MEAN_SWEPT;
 }
 
 size_t les_workspace_bytes(const les_config *cfg) {

@@ -25,6 +25,8 @@ LES_NO_SLIP, LES_FREE_SLIP = 0, 1
 WALLS = {"no_slip": LES_NO_SLIP, "free_slip": LES_FREE_SLIP}
 LES_PHASE_HEAVISIDE, LES_PHASE_RAMP = 0, 1
 PHASES = {"heaviside": LES_PHASE_HEAVISIDE, "ramp": LES_PHASE_RAMP}
+LES_MEAN_SWEPT, LES_MEAN_EXACT = 0, 1
+MEAN_MODES = {"swept": LES_MEAN_SWEPT, "exact": LES_MEAN_EXACT}
 LES_GUESS_ZERO, LES_GUESS_EXTRAPOLATE, LES_GUESS_PREVIOUS, LES_GUESS_LEARNED = 0, 1, 2, 3
 GUESS_MODES = {"zero": LES_GUESS_ZERO, "extrapolate": LES_GUESS_EXTRAPOLATE,
                "previous": LES_GUESS_PREVIOUS, "learned": LES_GUESS_LEARNED}
@@ -59,7 +61,7 @@ class LesConfig(C.Structure):
         ("e_tr", C.c_double), ("T_tr", C.c_double), ("satadj_tol", C.c_double),
         ("guess", C.c_int32), ("advection", C.c_int32),
         ("wall", C.c_int32), ("phase", C.c_int32), ("nu_const", C.c_double),
-        ("T_ice", C.c_double),
+        ("T_ice", C.c_double), ("mean_mode", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -175,6 +177,11 @@ def make_config(p: dict) -> LesConfig:
         elif name == "guess":
             v = p.get("guess", "zero")
             c.guess = GUESS_MODES[v] if isinstance(v, str) else int(v)
+        elif name == "mean_mode":
+            v = p.get("mean_mode", "exact")
+            c.mean_mode = MEAN_MODES[v] if isinstance(v, str) else int(v)
+        elif name == "reserved":
+            c.reserved = 0
         elif name == "precision":
             v = p.get("precision", "fp64")
             c.precision = {"fp64": LES_FP64, "fp32": LES_FP32}[v] if isinstance(v, str) else int(v)

@@ -500,10 +500,11 @@ def fft_poisson(p, rhs):
 
 @pytest.mark.parametrize("shape", [(8, 8, 8), (10, 12, 16)])
 @pytest.mark.parametrize("scheme", ["jacobi", "chebyshev"])
-def test_poisson_matches_fft(oracle_lib, shape, scheme):
+@pytest.mark.parametrize("mean_mode", ["exact", "swept"])
+def test_poisson_matches_fft(oracle_lib, shape, scheme, mean_mode):
     nz, ny, nx = shape
     p = small(nx=nx, ny=ny, nz=nz, dx=40.0, dy=30.0, dz=10.0, poisson_tol=1e-12,
-              poisson_scheme=scheme)
+              poisson_scheme=scheme, mean_mode=mean_mode)
     rhs = li.random_field(shape, seed=11)
     exact = fft_poisson(p, rhs)
     phi, st = oracle_lib.poisson(p, rhs)
@@ -528,6 +529,86 @@ def test_poisson_fully_periodic_limit(oracle_lib):
     exact = np.real(np.fft.ifft2(F))
     for k in range(4):
         np.testing.assert_allclose(phi[k], exact, atol=1e-10 * np.abs(exact).max())
+
+
+def test_mean_mode_of_a_horizontally_uniform_rhs(oracle_lib):
+    """A right-hand side of z alone is the horizontally uniform mode only:
+    the exact start of that mode solves it with no sweep, and it equals the
+    dense minimum-norm (zero-mean) solution of the one-dimensional mirror-
+    Neumann second difference.  Sweeping that mode instead takes hundreds of
+    sweeps."""
+    nz, ny, nx = 24, 5, 6
+    p = small(nx=nx, ny=ny, nz=nz, dz=7.0, poisson_tol=1e-12, mean_mode="exact")
+    rng = np.random.default_rng(8)
+    r = rng.standard_normal(nz)
+    r -= r.mean()
+    rhs = np.broadcast_to(r[:, None, None], (nz, ny, nx)).copy()
+    phi, st = oracle_lib.poisson(p, rhs)
+    assert st["status"] == 0 and st["sweeps"] == 0
+    A = (np.diag(-2.0 * np.ones(nz)) + np.diag(np.ones(nz - 1), 1) + np.diag(np.ones(nz - 1), -1))
+    A[0, 0] = A[-1, -1] = -1.0
+    exact = np.linalg.pinv(A / p["dz"] ** 2) @ r
+    np.testing.assert_allclose(phi, np.broadcast_to(exact[:, None, None], rhs.shape),
+                               rtol=0, atol=1e-11 * np.abs(exact).max())
+    _, st2 = oracle_lib.poisson(small(nx=nx, ny=ny, nz=nz, dz=7.0, poisson_tol=1e-12,
+                                      mean_mode="swept"), rhs)
+    assert st2["status"] == 0 and st2["sweeps"] > 100
+
+
+def test_mean_mode_ignores_level_means_of_a_guess(oracle_lib):
+    """With the horizontally uniform part solved exactly, a guess's
+    horizontal means per level play no part: adding any profile of z to it
+    changes neither the sweeps nor the solution."""
+    shape = (12, 10, 14)
+    p = small(nx=14, ny=10, nz=12, poisson_tol=1e-10, poisson_scheme="chebyshev",
+              mean_mode="exact")
+    rhs = li.random_field(shape, seed=12)
+    g = li.random_field(shape, seed=13) * 40.0
+    prof = np.linspace(-300.0, 500.0, 12)[:, None, None]
+    a, sa = oracle_lib.poisson(p, rhs, guess=g)
+    b, sb = oracle_lib.poisson(p, rhs, guess=g + prof)
+    assert sa["sweeps"] == sb["sweeps"] and sa["status"] == 0
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-12 * np.abs(a).max())
+
+
+def _mid_spectrum_case():
+    """rhs = L of an eigenmode with Jacobi eigenvalue 1 (the fixed-weight
+    sweep removes it at once) and the slowest horizontal mode v."""
+    p = small(nx=16, ny=16, nz=16, dx=40.0, dy=40.0, dz=10.0, poisson_scheme="jacobi",
+              poisson_tol=1e-10, poisson_check_every=5)
+    k, j, i = np.meshgrid(np.arange(16), np.arange(16), np.arange(16), indexing="ij")
+    mode = (np.cos(2 * np.pi * 4 * i / 16) * np.cos(2 * np.pi * 4 * j / 16)
+            * np.cos(np.pi * 8 * (k + 0.5) / 16))
+    v = np.cos(2 * np.pi * (i + 0.5) / 16)
+    return p, mode, v
+
+
+def test_gated_guess_kept_rejected_and_capped(oracle_lib):
+    """The time step's guessed solve: a guess that starts closer than the
+    zero start is kept; one that starts farther is dropped (same sweeps and
+    solution as the zero start); a kept guess whose sweeps reach the cap is
+    dropped and the sweeps repeated from the zero start, so the solve still
+    meets the tolerance and returns the zero start's solution, with both
+    passes counted.  Here the right-hand side is one eigenmode that the
+    fixed-weight sweep removes in a few sweeps, and the kept guess errs by
+    the slowest mode, which decays by 1 - omega mu_min per sweep."""
+    p, mode, v = _mid_spectrum_case()
+    rhs = oracle_lib.laplacian(p, mode)
+    phi0, s0 = oracle_lib.poisson(p, rhs)
+    assert s0["status"] == 0 and s0["sweeps"] <= 10
+    Lv = oracle_lib.laplacian(p, v)
+    a = 0.5 * np.linalg.norm(rhs) / np.linalg.norm(Lv)
+    good = phi0 + a * v
+    slow, sk = oracle_lib.poisson(dict(p, poisson_max_sweeps=100000), rhs, guess=good, gated=True)
+    assert sk["guess"] == 1 and sk["status"] == 0 and sk["sweeps"] > 200
+    bad = phi0 + 4.0 * a * v
+    out, sb = oracle_lib.poisson(p, rhs, guess=bad, gated=True)
+    assert sb["guess"] == 2 and sb["sweeps"] == s0["sweeps"]
+    np.testing.assert_array_equal(out, phi0)
+    cap = 100
+    out, sc = oracle_lib.poisson(dict(p, poisson_max_sweeps=cap), rhs, guess=good, gated=True)
+    assert sc["guess"] == 3 and sc["status"] == 0 and sc["sweeps"] == cap + s0["sweeps"]
+    np.testing.assert_array_equal(out, phi0)
 
 
 def test_chebyshev_needs_fewer_sweeps(oracle_lib):

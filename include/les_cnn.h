@@ -108,6 +108,22 @@ size_t les_cnn_pair_scratch_bytes(const les_config *cfg);
 int les_cnn_pair(const les_config *cfg, const void *rhs, const void *base, const void *phi,
                  float *x, float *target, void *scratch, double *scale, void *stream);
 
+/* les_cnn_pair for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same pair, bit for bit, with no scratch argument.  The residual is formed
+ * in x itself and scaled there; the reduction partials and the scale
+ * factors live in a fixed 16 KiB device array of the library (one per GPU,
+ * held until the process ends), of which 8224 bytes are used whatever the
+ * grid (1024 FP64 partial sums, then the scale factors), so no grid within the
+ * limits of les_cnn_pair is refused for lack of scratch.  Calls no hipMalloc or
+ * hipFree.  x and target must not alias rhs, base or phi.  Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (two
+ * streams, two threads) race and must be serialised by the caller.
+ * scale (host, nullable): synchronizes and stores s. */
+int les_cnn_pair_noalloc(const les_config *cfg, const void *rhs, const void *base,
+                         const void *phi, float *x, float *target, double *scale,
+                         void *stream);
+
 /* Crops of npairs stored pairs x_pairs, t_pairs (each npairs x nz x ny x nx,
  * FP32).  crops: batch triples (pair, j0, i0), each taken modulo its range.
  * xb gets (batch, nz, cy + 8, cx + 8) from (j0 - 4, i0 - 4), tb (batch, nz,

@@ -13,7 +13,8 @@ from . import les
 
 EXPORTS = ("les_cnn_param_count", "les_cnn_work_bytes", "les_cnn_pack", "les_cnn_forward",
            "les_cnn_loss", "les_cnn_backward", "les_cnn_adam", "les_cnn_train_step",
-           "les_cnn_pair_scratch_bytes", "les_cnn_pair", "les_cnn_gather", "les_bind_cnn",
+           "les_cnn_pair_scratch_bytes", "les_cnn_pair", "les_cnn_pair_noalloc",
+           "les_cnn_gather", "les_bind_cnn",
            "les_cnn_guess")
 
 LAYERS = 4
@@ -53,6 +54,8 @@ def lib():
         L.les_cnn_pair_scratch_bytes.restype = C.c_size_t
         L.les_cnn_pair.argtypes = [C.POINTER(les.LesConfig), _vp, _vp, _vp, _vp, _vp, _vp,
                                    C.POINTER(C.c_double), _vp]
+        L.les_cnn_pair_noalloc.argtypes = [C.POINTER(les.LesConfig), _vp, _vp, _vp, _vp, _vp,
+                                           C.POINTER(C.c_double), _vp]
         L.les_cnn_gather.argtypes = [_vp, _vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _vp,
                                      C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _vp]
         L.les_bind_cnn.argtypes = [_vp, _vp, C.c_double]
@@ -200,6 +203,18 @@ def pair(sim, rhs, base, phi, x, target, scratch=None):
     s = C.c_double()
     les.check(L.les_cnn_pair(C.byref(sim.cfg), _ptr(rhs), _ptr(base), _ptr(phi), _ptr(_f32(x)),
                              _ptr(_f32(target)), _ptr(scratch), C.byref(s), _stream()))
+    return s.value
+
+
+def pair_noalloc(sim, rhs, base, phi, x, target):
+    """As pair() through the entry point that allocates nothing (its scratch
+    is a fixed device array of the library)."""
+    L = lib()
+    for t in (rhs, phi) + ((base,) if base is not None else ()):
+        assert t.dtype == sim.dtype and t.is_contiguous() and t.numel() == sim._n()
+    s = C.c_double()
+    les.check(L.les_cnn_pair_noalloc(C.byref(sim.cfg), _ptr(rhs), _ptr(base), _ptr(phi),
+                                     _ptr(_f32(x)), _ptr(_f32(target)), C.byref(s), _stream()))
     return s.value
 
 

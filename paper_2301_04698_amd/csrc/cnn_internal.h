@@ -89,6 +89,10 @@ void launch_cnn_scale(const double *partials, double n, double d, double *sc, hi
 template <typename T>
 void launch_cnn_pair(const Grid &g, const float *r, const T *phi, const T *base, const double *sc,
                      double d, float *x, float *t, hipStream_t s);
+// The same with the residual already in x (scaled in place).
+template <typename T>
+void launch_cnn_pair_inplace(const Grid &g, const T *phi, const T *base, const double *sc,
+                             double d, float *x, float *t, hipStream_t s);
 // Crops of npairs stored pairs.  crops[3b..3b+2] = (pair, j0, i0), each
 // taken modulo its range: input crop (nz, cy + 8, cx + 8) from (j0 - 4,
 // i0 - 4), target crop (nz, cy, cx) from (j0, i0), both wrapping in x, y.

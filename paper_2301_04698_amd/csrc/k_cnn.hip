@@ -623,6 +623,20 @@ __global__ __launch_bounds__(kBlock) void pair_kernel(int64_t n, const float *__
   t[q] = (float)(((double)phi[q] - (base ? (double)base[q] : 0.0)) * d * inv);
 }
 
+// As pair_kernel with the residual r already in x: x = x/s in place.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void pair_inplace_kernel(int64_t n, const T *__restrict__ phi,
+                                                              const T *__restrict__ base,
+                                                              const double *__restrict__ sc,
+                                                              double d, float *x,
+                                                              float *__restrict__ t) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const double inv = sc[1];
+  x[q] = (float)((double)x[q] * inv);
+  t[q] = (float)(((double)phi[q] - (base ? (double)base[q] : 0.0)) * d * inv);
+}
+
 __global__ __launch_bounds__(kBlock) void gather_kernel(const float *__restrict__ X,
                                                         const float *__restrict__ Tt,
                                                         int64_t pair_stride, int nz, int ny, int nx,
@@ -757,6 +771,12 @@ void launch_cnn_pair(const Grid &g, const float *r, const T *phi, const T *base,
   pair_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g.n, r, phi, base, sc, d, x, t);
 }
 
+template <typename T>
+void launch_cnn_pair_inplace(const Grid &g, const T *phi, const T *base, const double *sc,
+                             double d, float *x, float *t, hipStream_t s) {
+  pair_inplace_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g.n, phi, base, sc, d, x, t);
+}
+
 void launch_cnn_gather(const float *X, const float *Tt, int npairs, int nz, int ny, int nx,
                        const int32_t *crops, int batch, int cy, int cx, float *xb, float *tb,
                        hipStream_t s) {
@@ -774,7 +794,9 @@ void launch_cnn_gather(const float *X, const float *Tt, int npairs, int nz, int 
   template void launch_cnn_residual<T>(const Grid &, const T *, const T *, float *, double *,   \
                                        hipStream_t);                                             \
   template void launch_cnn_pair<T>(const Grid &, const float *, const T *, const T *,            \
-                                   const double *, double, float *, float *, hipStream_t);
+                                   const double *, double, float *, float *, hipStream_t);        \
+  template void launch_cnn_pair_inplace<T>(const Grid &, const T *, const T *, const double *,   \
+                                           double, float *, float *, hipStream_t);
 CNN_INST(float)
 CNN_INST(double)
 #undef CNN_INST

@@ -133,7 +133,10 @@ typedef struct les_config {
 /* Caller-owned device buffers.  u, v, w: velocity (m/s); thl: liquid-ice
  * potential temperature (K) stored at the half step; qt: total water
  * specific humidity (kg/kg) at the half step; p: pressure perturbation p'
- * (Pa).  workspace: at least les_workspace_bytes(cfg) bytes, 256-byte
+ * (Pa) less the horizontally uniform pressure that LES_MEAN_EXACT keeps in
+ * the workspace as an FP64 profile (starts at zero with les_init; with
+ * LES_MEAN_SWEPT it stays zero and p is p').  les_pressure returns the
+ * whole p'.  workspace: at least les_workspace_bytes(cfg) bytes, 256-byte
  * aligned, not shared with another handle. */
 typedef struct les_buffers {
   void *u, *v, *w, *thl, *qt, *p;
@@ -152,14 +155,24 @@ typedef struct les_solve_stats {
   double seconds;     /* device time of the solve (HIP events) */
   int32_t guess;      /* les_step: 0 started from zero, 1 from its guess,
                          2 its guess was rejected (residual not below the
-                         zero start's) and it started from zero;
-                         les_poisson_solve: opts->use_guess */
+                         zero start's) and it started from zero, 3 its kept
+                         guess reached the cap or its returned iterate
+                         missed the tolerance, and the sweeps were repeated
+                         from the zero start (sweeps and seconds count both
+                         passes); les_poisson_solve: opts->use_guess.
+                         "Zero start": phi = 0, or with LES_MEAN_EXACT the
+                         exact horizontally uniform part.  For a kept guess
+                         res_norm is the residual of the returned iterate
+                         (guess plus correction, as stored) */
   int32_t reserved;
 } les_solve_stats;
 
 typedef struct les_poisson_opts {
   int32_t fixed_sweeps;  /* > 0: apply exactly this many sweeps */
-  int32_t use_guess;     /* 1: phi holds the initial guess; 0: start from 0 */
+  int32_t use_guess;     /* 0: start from the zero start; 1: phi holds a
+                            guess, always kept; 2: phi holds a guess, kept
+                            and repeated as les_step does (see
+                            les_solve_stats.guess) */
 } les_poisson_opts;
 
 /* Optional per-call controls of les_step. */
@@ -171,11 +184,26 @@ typedef struct les_step_opts {
                                    (between residual checks) with HIP events */
   int32_t reserved;
   void *dump_rhs;               /* device, n_subiter*n elements or NULL: the
-                                   centred right-hand sides of the solves of
-                                   the call's last step, sub-iteration k at
-                                   offset k*n */
+                                   right-hand sides the sweeps of the call's
+                                   last step solved, sub-iteration k at
+                                   offset k*n: centred, and with
+                                   LES_MEAN_EXACT also without their
+                                   horizontal mean per level */
   void *dump_phi;               /* device, n_subiter*n elements or NULL:
-                                   those solves' zero-mean solutions */
+                                   those solves' zero-mean solutions, with
+                                   LES_MEAN_EXACT without their horizontally
+                                   uniform part */
+  double *dump_mean;            /* host, n_subiter*(2*nz+1) doubles or NULL:
+                                   per solve of the last step, the values the
+                                   centring subtracted per level (the mean of
+                                   the raw rhs, or with LES_MEAN_EXACT its
+                                   horizontal mean per level), the
+                                   horizontally uniform part of the solution
+                                   (zero with LES_MEAN_SWEPT), and the mean
+                                   of the raw rhs.  With LES_MEAN_EXACT the
+                                   whole centred rhs is dump_rhs + (first
+                                   profile - mean) and the whole solution
+                                   dump_phi + second profile */
 } les_step_opts;
 
 typedef struct les_step_stats {
@@ -230,9 +258,25 @@ int les_step(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step_
  * the pressure-correction equation of Sec. 2.4) by the configured sweeps.
  * rhs: device, n elements, read only (its mean is removed internally).
  * phi: device, n elements; in = guess if opts->use_guess, out = zero-mean
- * solution.  Uses the handle's workspace.  Synchronizes the stream. */
+ * solution (with LES_MEAN_EXACT its horizontally uniform part, solved
+ * exactly in FP64, is added before rounding once).  The sweeps solve for a
+ * guess's correction from zero.  Uses the handle's workspace.
+ * Synchronizes the stream. */
 int les_poisson_solve(les_handle *h, const void *rhs, void *phi, const les_poisson_opts *opts,
                       les_solve_stats *stats);
+
+/* The whole pressure perturbation p' (Sec. 2.4: the sum of the pressure
+ * corrections rho0 phi of the solves): p_out (device, n elements of the
+ * storage type, nullable) = p + pbar(z), rounded once; pbar_host (host, nz
+ * doubles, nullable) = the FP64 profile pbar kept by LES_MEAN_EXACT (zero
+ * with LES_MEAN_SWEPT).  Synchronizes the stream. */
+int les_pressure(les_handle *h, void *p_out, double *pbar_host);
+
+/* Restart with LES_MEAN_EXACT: sets the FP64 horizontally uniform pressure
+ * pbar (host, nz doubles, finite) that p is taken relative to, e.g. the
+ * pbar_host of les_pressure on an earlier run (les_init starts it at
+ * zero).  LES_ERR_STATE with LES_MEAN_SWEPT.  Synchronizes the stream. */
+int les_set_pressure_profile(les_handle *h, const double *pbar_host);
 
 /* Thermodynamic state of arbitrary fields (Sec. 2.1-2.2): temperature T,
  * liquid water q_l and buoyancy b from thl, qt at the handle's levels.
@@ -241,8 +285,35 @@ int les_thermo(les_handle *h, const void *thl, const void *qt, void *T, void *ql
 
 /* Diagnostics of the current state: scalars into *out (host) and, if
  * profiles is non-NULL, LES_NPROFILES x nz horizontal means (host, FP64,
- * profile-major).  FP64 reductions.  Synchronizes the stream. */
+ * profile-major): the mean-state profiles of theta_l, q_t and liquid water
+ * and the variance and skewness moments of w the paper compares for its
+ * stratocumulus case (Sec. 4, fidelity of the simulation), the domain
+ * integrals of rho0 theta_l and rho0 q_t that the scheme conserves (Sec.
+ * 2.4), the kinetic energy, the central divergence and the CFL number.
+ * FP64 reductions.  Synchronizes the stream. */
 int les_diagnostics(les_handle *h, les_diag *out, double *profiles);
+
+/* State the library keeps between les_step calls, beyond the caller's
+ * fields: the FP64 horizontally uniform pressure of LES_MEAN_EXACT, the
+ * previous step's pressure (LES_GUESS_EXTRAPOLATE), the previous step's
+ * solutions of each sub-iteration and which of them are held
+ * (LES_GUESS_PREVIOUS, LES_GUESS_LEARNED), and the count of steps taken.
+ * Together with the caller's u, v, w, thl, qt, p it is the whole state of a
+ * run (the host does input and output only, Sec. 2.5), so a run can stop
+ * and continue in another handle, process or machine: les_step on an
+ * imported state gives bit for bit what the exporting handle's next steps
+ * would.  A bound network (les_bind_cnn) is not part of it.
+ * les_state_bytes: size of the exported state (0 if h is NULL).
+ * les_export_state: writes it to dst (device, 256-byte aligned,
+ * les_state_bytes(h) bytes).  les_import_state: reads one from src (device)
+ * into a handle of the same grid, precision, mean mode, guess mode and
+ * n_subiter (else LES_ERR_ARG); the caller's fields are not touched.  Both
+ * synchronize the stream.  les_steps_done: the count of steps (-1 if h is
+ * NULL). */
+size_t les_state_bytes(const les_handle *h);
+int les_export_state(les_handle *h, void *dst);
+int les_import_state(les_handle *h, const void *src);
+int64_t les_steps_done(const les_handle *h);
 
 void les_destroy(les_handle *h);
 

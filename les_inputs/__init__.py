@@ -77,7 +77,7 @@ _BASE = dict(
     jacobi_omega=0.0,          # 0 selects the closed-form optimum
     sweeps_per_launch=0,       # library launch shape only (0: its default)
     guess="zero",              # initial guess of the solves
-    mean_mode="swept",         # horizontal-mean part of each solve: "exact" (1D solve
+    mean_mode="exact",         # horizontal-mean part of each solve: "exact" (1D solve
                                # first) or "swept" (with the rest)
     advection="quick",         # "quick" or "weno3" (WENO3 with Lax-Friedrichs flux)
     wall="no_slip",            # u, v at z = 0, H: "no_slip" or "free_slip"

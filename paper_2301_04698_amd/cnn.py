@@ -8,6 +8,7 @@ tensor of shape (batch, nz, ny, nx).
 from __future__ import annotations
 
 import ctypes as C
+import os
 
 from . import les
 
@@ -109,6 +110,24 @@ def _f32(t):
     import torch
     assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
     return t
+
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
+                       "guess_256x256x128.npy")
+
+
+def load_weights(path=WEIGHTS):
+    """Shipped network parameters (float32 numpy) and their metadata (the
+    JSON file beside them: training command, alpha, ...)."""
+    import json
+    import numpy as np
+    prm = np.load(path).astype(np.float32)
+    meta = {"alpha": 0.1}
+    side = os.path.splitext(path)[0] + ".json"
+    if os.path.exists(side):
+        with open(side) as f:
+            meta.update(json.load(f))
+    return prm, meta
 
 
 def pack(params):

@@ -6,6 +6,8 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <exception>
+#include <new>
 #include <string>
 
 #include "les.h"
@@ -22,6 +24,21 @@ inline int fail(int code, const char *fmt, ...) {
   va_end(ap);
   g_error = buf;
   return code;
+}
+
+// Runs an entry point's body so that no C++ exception leaves the C ABI:
+// host allocation failure and any other exception become LES_ERR_STATE.
+template <typename F>
+int guarded(F &&body) {
+  try {
+    return body();
+  } catch (const std::bad_alloc &) {
+    return fail(LES_ERR_STATE, "out of host memory");
+  } catch (const std::exception &e) {
+    return fail(LES_ERR_STATE, "internal error: %s", e.what());
+  } catch (...) {
+    return fail(LES_ERR_STATE, "internal error");
+  }
 }
 
 }  // namespace lesmi

@@ -299,9 +299,12 @@ __device__ __forceinline__ void momentum_level(
   const T a0 = at.prof(P.alpha0_t, 0);
   const T gpx = (a0 * at(p, 1, 0, 0, T(1)) - a0 * at(p, -1, 0, 0, T(1))) * d.inv_2dx;
   const T gpy = (a0 * at(p, 0, 1, 0, T(1)) - a0 * at(p, 0, -1, 0, T(1))) * d.inv_2dy;
+  // plus the gradient of the horizontally uniform part of p', kept as an
+  // FP64 profile and rounded once
   const T gpz = (at.prof(P.alpha0_t, 1) * at(p, 0, 0, 1, T(1)) -
                  at.prof(P.alpha0_t, -1) * at(p, 0, 0, -1, T(1))) *
-                d.inv_2dz;
+                    d.inv_2dz +
+                at.prof(P.pgz_t, 0);
   const T gp[3] = {gpx, gpy, gpz};
   const T Uh[3] = {r0 * at(uh, 0, 0, 0, T(1)), r0 * at(vh, 0, 0, 0, T(1)),
                    r0 * at(wh, 0, 0, 0, T(1))};

@@ -40,7 +40,9 @@ __device__ __forceinline__ void rhs_level(const Grid &g, const Dyn<T> &d, const 
       const T b2 = at(lag, -2 * di, -2 * dj, -2 * dk, T(1));
       corr += (a2 - T(4) * a1 + T(6) * a0 - T(4) * b1 + b2) * inv4[ax];
     }
-    val -= corr;
+    // the horizontally uniform part of phi_lag, kept as an FP64 profile:
+    // its fourth difference in z, rounded once
+    val -= corr + at.prof(P.cbar_t, 0);
   }
   at.store(rhs, val, active);
 }
@@ -63,24 +65,149 @@ __global__ __launch_bounds__(kBlock) void rhs_kernel(Grid g, ColMap m, Dyn<T> d,
   }
 }
 
-// rhs_out = rhs_in - mean (in and out may alias); FP64 partial sums of
-// rhs_out^2; phi0 := 0 when given.
+// Level decomposition of the per-level kernels: block (p, k) covers part p
+// of level k's plane (lp parts per level).
+struct LevelPart {
+  int64_t b, e;
+};
+__device__ __forceinline__ LevelPart level_part(const Grid &g, int lp) {
+  const int64_t chunk = (g.nxy + lp - 1) / lp;
+  LevelPart r;
+  r.b = (int64_t)blockIdx.x * chunk;
+  r.e = r.b + chunk < g.nxy ? r.b + chunk : g.nxy;
+  return r;
+}
+
+// FP64 sum of part p of level k of f into part[k * lp + p].
 template <typename T>
-__global__ __launch_bounds__(kBlock) void center_kernel(int64_t n, const T *in, T *out,
+__global__ __launch_bounds__(kBlock) void level_sum_kernel(Grid g, const T *__restrict__ f, int lp,
+                                                           double *__restrict__ part) {
+  const int k = blockIdx.y;
+  const LevelPart r = level_part(g, lp);
+  const T *row = f + (int64_t)k * g.nxy;
+  double acc = 0.0;
+  for (int64_t q = r.b + threadIdx.x; q < r.e; q += blockDim.x) acc += (double)row[q];
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) part[(int64_t)k * lp + blockIdx.x] = s;
+}
+
+// From the level partials of the raw rhs: its mean m (ctl->rhs_mean) and
+// what the centring subtracts per level, rsub[k]: the level mean when the
+// horizontally uniform part is solved exactly, else m.  Exact mode also
+// solves that part, (pb_{k+1} - 2 pb_k + pb_{k-1}) / dz^2 = rb_k with
+// rb_k = level mean - m and mirror ghosts: the face gradient is zero at the
+// bottom wall and grows by dz rb_k across level k; pb has zero mean.  One
+// block; the running sums are sequential in a fixed order.
+__global__ __launch_bounds__(256) void mean_mode_kernel(const double *__restrict__ part, int lp,
+                                                        int nz, double nxy, double dz, int exact,
+                                                        SolveCtl *ctl, double *__restrict__ rsub,
+                                                        double *__restrict__ pb) {
+  for (int k = threadIdx.x; k < nz; k += blockDim.x) {
+    double s = 0.0;
+    for (int q = 0; q < lp; ++q) s += part[(int64_t)k * lp + q];
+    rsub[k] = s / nxy;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double tot = 0.0;
+  for (int k = 0; k < nz; ++k) tot += rsub[k];
+  const double m = tot / nz;
+  ctl->rhs_mean = m;
+  if (exact) {
+    double G = 0.0, acc = 0.0;
+    pb[0] = 0.0;
+    for (int k = 0; k + 1 < nz; ++k) {
+      G += dz * (rsub[k] - m);
+      pb[k + 1] = pb[k] + dz * G;
+    }
+    for (int k = 0; k < nz; ++k) acc += pb[k];
+    const double mp = acc / nz;
+    for (int k = 0; k < nz; ++k) pb[k] -= mp;
+  } else {
+    for (int k = 0; k < nz; ++k) {
+      rsub[k] = m;
+      pb[k] = 0.0;
+    }
+  }
+}
+
+// rhs_out = rhs_in - rsub[k], rounded once (in and out may alias); FP64
+// partial sums of (rhs_in - m)^2, the norm of the centred right-hand side;
+// phi0 := 0 when given.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void center_kernel(Grid g, int lp, const T *in, T *out,
                                                         T *__restrict__ phi0,
+                                                        const double *__restrict__ rsub,
                                                         const SolveCtl *__restrict__ ctl,
                                                         double *__restrict__ partials) {
-  const T mean = (T)ctl->rhs_mean;
+  const int k = blockIdx.y;
+  const LevelPart r = level_part(g, lp);
+  const double m = ctl->rhs_mean, sub = rsub[k];
+  const int64_t base = (int64_t)k * g.nxy;
   double acc = 0.0;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    const T val = in[q] - mean;
-    out[q] = val;
-    acc += (double)val * (double)val;
+  for (int64_t q = base + r.b + threadIdx.x; q < base + r.e; q += blockDim.x) {
+    const double x = (double)in[q];
+    out[q] = (T)(x - sub);
+    acc += (x - m) * (x - m);
     if (phi0) phi0[q] = T(0);
   }
   const double s = block_sum(acc);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (threadIdx.x == 0) partials[(int64_t)k * lp + blockIdx.x] = s;
+}
+
+// gbar[k] = level mean from the level partials (exact mode), else 0.
+__global__ __launch_bounds__(256) void level_mean_kernel(const double *__restrict__ part, int lp,
+                                                         int nz, double nxy, int exact,
+                                                         double *__restrict__ gbar) {
+  for (int k = threadIdx.x; k < nz; k += blockDim.x) {
+    double s = 0.0;
+    if (exact)
+      for (int q = 0; q < lp; ++q) s += part[(int64_t)k * lp + q];
+    gbar[k] = s / nxy;
+  }
+}
+
+// Profiles of the horizontally uniform part pb of a solution (FP64 in,
+// storage type out, each rounded once; even mirror across the walls):
+// phigz = d_c pb / dz (projection), cbar = its App. A fourth difference in z
+// (the next sub-iteration's right-hand side), and with add_p pbar += rho0
+// pb.  Then pgz = d_c(alpha0 pbar)/dz (momentum predictor).  pb nullable
+// (only pgz).  One block.
+template <typename T>
+__global__ __launch_bounds__(256) void mean_profiles_kernel(int nz, double dz,
+                                                            const double *__restrict__ pb,
+                                                            const double *__restrict__ rho0,
+                                                            const double *__restrict__ alpha0,
+                                                            int add_p, double *pbar,
+                                                            T *__restrict__ phigz,
+                                                            T *__restrict__ cbar,
+                                                            T *__restrict__ pgz) {
+  if (pb) {
+    for (int k = threadIdx.x; k < nz; k += blockDim.x) {
+      const double a2 = pb[zmirror(k + 2, nz)], a1 = pb[zmirror(k + 1, nz)], a0 = pb[k];
+      const double b1 = pb[zmirror(k - 1, nz)], b2 = pb[zmirror(k - 2, nz)];
+      phigz[k] = (T)((a1 - b1) / (2.0 * dz));
+      cbar[k] = (T)((a2 - 4.0 * a1 + 6.0 * a0 - 4.0 * b1 + b2) / (4.0 * dz * dz));
+      if (add_p) pbar[k] += rho0[k] * a0;
+    }
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < nz; k += blockDim.x) {
+    const int kp = zmirror(k + 1, nz), km = zmirror(k - 1, nz);
+    pgz[k] = (T)((alpha0[kp] * pbar[kp] - alpha0[km] * pbar[km]) / (2.0 * dz));
+  }
+}
+
+// out = in - ctl->phi_mean (if ctl) + prof[k], in FP64, rounded once.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void add_profile_kernel(Grid g, const T *__restrict__ in,
+                                                             const SolveCtl *__restrict__ ctl,
+                                                             const double *__restrict__ prof,
+                                                             T *__restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.n) return;
+  const double mean = ctl ? ctl->phi_mean : 0.0;
+  out[q] = (T)((double)in[q] - mean + prof[(int)(q / g.nxy)]);
 }
 
 // U^{k+1} = U_hat - dt rho0 grad_c phi (stored as velocity), p += rho0 (phi - mean).
@@ -94,7 +221,8 @@ __device__ __forceinline__ void project_level(const Grid &g, const Dyn<T> &d,
   const Lvl<T, EDGE> at(g, pts, k);
   const T gx = (at(phi, 1, 0, 0, T(1)) - at(phi, -1, 0, 0, T(1))) * d.inv_2dx;
   const T gy = (at(phi, 0, 1, 0, T(1)) - at(phi, 0, -1, 0, T(1))) * d.inv_2dy;
-  const T gz = (at(phi, 0, 0, 1, T(1)) - at(phi, 0, 0, -1, T(1))) * d.inv_2dz;
+  const T gz = (at(phi, 0, 0, 1, T(1)) - at(phi, 0, 0, -1, T(1))) * d.inv_2dz +
+               at.prof(P.phigz_t, 0);
   const T uo = at(u, 0, 0, 0, T(1)) - d.dt * gx;
   const T vo = at(v, 0, 0, 0, T(1)) - d.dt * gy;
   const T wo = at(w, 0, 0, 0, T(1)) - d.dt * gz;
@@ -169,9 +297,7 @@ __global__ __launch_bounds__(1024) void final_kernel(const double *__restrict__ 
     case kFinalRhsMean:
       ctl->rhs_mean = s / n;
       break;
-    case kFinalRhsNormRef:
     case kFinalRhsNorm:
-      if (op == kFinalRhsNormRef) s = ctl->ref_norm2;
       ctl->rhs_norm2 = s;
       ctl->tol2 = tol2_scale * s;
       if (!isfinite(s)) {
@@ -193,20 +319,25 @@ __global__ __launch_bounds__(1024) void final_kernel(const double *__restrict__ 
     case kFinalStore:
       out[0] = s;
       break;
+    case kFinalReturned:
+      ctl->res_out2 = s;
+      break;
     default:
       break;
   }
 }
 
-// Defect right-hand side of a starting iterate: rhs_d = rhs - L phi0 in
-// FP64, with FP64 partial sums of rhs_d^2 (partials[b]) and of rhs^2
-// (partials[gridDim.x + b]); L the compact Laplacian, periodic x, y and
-// mirror z.
+// Defect right-hand side of a starting iterate: rhs_d = rhs - L (phi0 -
+// gbar) in FP64 (gbar: per-level means to remove, nullable), with FP64
+// partial sums of rhs_d^2 (partials[b]) and of rhs^2 (partials[gridDim.x +
+// b]); L the compact Laplacian, periodic x, y and mirror z.  rhs_d nullable
+// (only the sums: the residual of a returned iterate).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void guess_residual_kernel(Grid g, double ix2, double iy2,
                                                                 double iz2,
                                                                 const T *__restrict__ rhs,
                                                                 const T *__restrict__ phi0,
+                                                                const double *__restrict__ gbar,
                                                                 T *__restrict__ rhs_d,
                                                                 double *__restrict__ partials) {
   double rr = 0.0, bb = 0.0;
@@ -217,16 +348,18 @@ __global__ __launch_bounds__(kBlock) void guess_residual_kernel(Grid g, double i
     const int j = (int)(r2 / g.nx);
     const int i = (int)(r2 - (int64_t)g.nx * j);
     const double c = phi0[q];
-    const double lap =
+    double lap =
         ((double)gload(phi0, g, i + 1, j, k, T(1)) + (double)gload(phi0, g, i - 1, j, k, T(1)) -
          2.0 * c) * ix2 +
         ((double)gload(phi0, g, i, j + 1, k, T(1)) + (double)gload(phi0, g, i, j - 1, k, T(1)) -
          2.0 * c) * iy2 +
         ((double)gload(phi0, g, i, j, k + 1, T(1)) + (double)gload(phi0, g, i, j, k - 1, T(1)) -
          2.0 * c) * iz2;
+    if (gbar)
+      lap -= (pload(gbar, k + 1, g.nz) - 2.0 * gbar[k] + pload(gbar, k - 1, g.nz)) * iz2;
     const double b = rhs[q];
     const double d = b - lap;
-    rhs_d[q] = (T)d;
+    if (rhs_d) rhs_d[q] = (T)d;
     rr += d * d;
     bb += b * b;
   }
@@ -239,9 +372,9 @@ __global__ __launch_bounds__(kBlock) void guess_residual_kernel(Grid g, double i
 }
 
 // ctl->guess_kept = 1 when the starting iterate's residual is below the
-// zero start's (sum r^2 < sum rhs^2), else 0.
+// zero start's (sum r^2 < sum rhs^2) or always_keep, else 0.
 __global__ __launch_bounds__(1024) void guess_gate_kernel(const double *__restrict__ partials,
-                                                          int np, SolveCtl *ctl) {
+                                                          int np, int always_keep, SolveCtl *ctl) {
   double a = 0.0, b = 0.0;
   for (int q = threadIdx.x; q < np; q += blockDim.x) {
     a += partials[q];
@@ -250,8 +383,7 @@ __global__ __launch_bounds__(1024) void guess_gate_kernel(const double *__restri
   a = block_sum(a);
   b = block_sum(b);
   if (threadIdx.x == 0) {
-    ctl->guess_kept = a < b ? 1 : 0;
-    ctl->ref_norm2 = b;
+    ctl->guess_kept = (always_keep || a < b) ? 1 : 0;
   }
 }
 
@@ -266,14 +398,34 @@ __global__ __launch_bounds__(kBlock) void guess_clear_kernel(int64_t n,
   if (q < n) rhs_d[q] = rhs[q];
 }
 
+// phi += phi0 - gbar[k] (gbar nullable), FP64 sum rounded once.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void add_guess_kernel(int64_t n,
+__global__ __launch_bounds__(kBlock) void add_guess_kernel(Grid g,
                                                            const SolveCtl *__restrict__ ctl,
                                                            const T *__restrict__ phi0,
+                                                           const double *__restrict__ gbar,
                                                            T *__restrict__ phi) {
   if (!ctl->guess_kept) return;
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < n) phi[q] = (T)((double)phi[q] + (double)phi0[q]);
+  if (q >= g.n) return;
+  const double gb = gbar ? gbar[(int)(q / g.nxy)] : 0.0;
+  phi[q] = (T)((double)phi[q] + ((double)phi0[q] - gb));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void zero_kernel(int64_t n, T *__restrict__ f) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) f[q] = T(0);
+}
+
+// A second pass of sweeps on the same right-hand side (the zero start after
+// a kept guess reached the cap): the reference norm and tolerance stay.
+__global__ void ctl_restart_kernel(SolveCtl *ctl) {
+  if (threadIdx.x != 0) return;
+  ctl->done = 0;
+  ctl->stop_m = -1;
+  ctl->res_norm2 = 0.0;
+  ctl->guess_kept = 0;
 }
 
 __global__ void ctl_reset_kernel(SolveCtl *ctl, int max_sweeps, int fixed) {
@@ -301,10 +453,56 @@ void launch_poisson_rhs(const Grid &g, const Dyn<T> &d, const Profiles<T> &P, co
   rhs_kernel<T><<<m.blocks, kBlock, 0, s>>>(g, m, d, P, u, v, w, phi_lag, rhs);
 }
 
+int level_parts(const Grid &g) {
+  int64_t lp = g.nxy / 8192;
+  if (lp > 64) lp = 64;
+  if (lp * g.nz > kPartials) lp = kPartials / g.nz;
+  return lp < 1 ? 1 : (int)lp;
+}
+
 template <typename T>
-void launch_rhs_center(const Grid &g, const T *rhs_in, T *rhs_out, T *phi0, const SolveCtl *ctl,
-                       double *partials, hipStream_t s) {
-  center_kernel<T><<<kReduceBlocks, kBlock, 0, s>>>(g.n, rhs_in, rhs_out, phi0, ctl, partials);
+void launch_level_sum(const Grid &g, const T *f, double *part, hipStream_t s) {
+  const int lp = level_parts(g);
+  level_sum_kernel<T><<<dim3(lp, g.nz), kBlock, 0, s>>>(g, f, lp, part);
+}
+
+void launch_mean_mode(const Grid &g, const double *part, int exact, SolveCtl *ctl, double *rsub,
+                      double *pb, hipStream_t s) {
+  mean_mode_kernel<<<1, 256, 0, s>>>(part, level_parts(g), g.nz, (double)g.nxy, g.dz, exact, ctl,
+                                     rsub, pb);
+}
+
+void launch_level_mean(const Grid &g, const double *part, int exact, double *gbar, hipStream_t s) {
+  level_mean_kernel<<<1, 256, 0, s>>>(part, level_parts(g), g.nz, (double)g.nxy, exact, gbar);
+}
+
+template <typename T>
+void launch_mean_profiles(const Grid &g, const double *pb, const double *rho0,
+                          const double *alpha0, int add_p, double *pbar, T *phigz, T *cbar,
+                          T *pgz, hipStream_t s) {
+  mean_profiles_kernel<T><<<1, 256, 0, s>>>(g.nz, g.dz, pb, rho0, alpha0, add_p, pbar, phigz,
+                                            cbar, pgz);
+}
+
+template <typename T>
+void launch_add_profile(const Grid &g, const T *in, const SolveCtl *ctl, const double *prof,
+                        T *out, hipStream_t s) {
+  add_profile_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g, in, ctl, prof, out);
+}
+
+template <typename T>
+void launch_rhs_center(const Grid &g, const T *rhs_in, T *rhs_out, T *phi0, const double *rsub,
+                       const SolveCtl *ctl, double *partials, hipStream_t s) {
+  const int lp = level_parts(g);
+  center_kernel<T><<<dim3(lp, g.nz), kBlock, 0, s>>>(g, lp, rhs_in, rhs_out, phi0, rsub, ctl,
+                                                     partials);
+}
+
+void launch_ctl_restart(SolveCtl *ctl, hipStream_t s) { ctl_restart_kernel<<<1, 64, 0, s>>>(ctl); }
+
+template <typename T>
+void launch_zero(const Grid &g, T *f, hipStream_t s) {
+  zero_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g.n, f);
 }
 
 template <typename T>
@@ -326,18 +524,29 @@ void launch_extrapolate(const Grid &g, const Profiles<T> &P, const T *p, const T
 }
 
 template <typename T>
-void launch_guess_gate(const Grid &g, const T *rhs, const T *phi0, T *rhs_d, double *partials,
-                       SolveCtl *ctl, hipStream_t s) {
+void launch_guess_gate(const Grid &g, const T *rhs, const T *phi0, const double *gbar, T *rhs_d,
+                       double *partials, SolveCtl *ctl, int always_keep, hipStream_t s) {
   guess_residual_kernel<T><<<kReduceBlocks, kBlock, 0, s>>>(
-      g, 1.0 / (g.dx * g.dx), 1.0 / (g.dy * g.dy), 1.0 / (g.dz * g.dz), rhs, phi0, rhs_d,
+      g, 1.0 / (g.dx * g.dx), 1.0 / (g.dy * g.dy), 1.0 / (g.dz * g.dz), rhs, phi0, gbar, rhs_d,
       partials);
-  guess_gate_kernel<<<1, 1024, 0, s>>>(partials, kReduceBlocks, ctl);
+  guess_gate_kernel<<<1, 1024, 0, s>>>(partials, kReduceBlocks, always_keep, ctl);
   guess_clear_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g.n, ctl, rhs, rhs_d);
 }
 
 template <typename T>
-void launch_add_guess(const Grid &g, const T *phi0, const SolveCtl *ctl, T *phi, hipStream_t s) {
-  add_guess_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g.n, ctl, phi0, phi);
+void launch_returned_residual(const Grid &g, const T *rhs, const T *phi, double *partials,
+                              SolveCtl *ctl, hipStream_t s) {
+  guess_residual_kernel<T><<<kReduceBlocks, kBlock, 0, s>>>(
+      g, 1.0 / (g.dx * g.dx), 1.0 / (g.dy * g.dy), 1.0 / (g.dz * g.dz), rhs, phi, nullptr,
+      nullptr, partials);
+  final_kernel<<<1, 1024, 0, s>>>(partials, kReduceBlocks, kFinalReturned, ctl, 0.0, 0.0, 0,
+                                  nullptr);
+}
+
+template <typename T>
+void launch_add_guess(const Grid &g, const T *phi0, const double *gbar, const SolveCtl *ctl,
+                      T *phi, hipStream_t s) {
+  add_guess_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g, ctl, phi0, gbar, phi);
 }
 
 template <typename T>
@@ -358,15 +567,25 @@ void launch_ctl_reset(SolveCtl *ctl, int max_sweeps, int fixed, hipStream_t s) {
   template void launch_poisson_rhs<T>(const Grid &, const Dyn<T> &, const Profiles<T> &,         \
                                       const T *, const T *, const T *, const T *, T *, double *, \
                                       hipStream_t);                                              \
-  template void launch_rhs_center<T>(const Grid &, const T *, T *, T *, const SolveCtl *,        \
-                                     double *, hipStream_t);                                     \
+  template void launch_rhs_center<T>(const Grid &, const T *, T *, T *, const double *,        \
+                                     const SolveCtl *, double *, hipStream_t);                   \
+  template void launch_level_sum<T>(const Grid &, const T *, double *, hipStream_t);           \
+  template void launch_zero<T>(const Grid &, T *, hipStream_t);                                 \
+  template void launch_mean_profiles<T>(const Grid &, const double *, const double *,          \
+                                        const double *, int, double *, T *, T *, T *,          \
+                                        hipStream_t);                                          \
+  template void launch_add_profile<T>(const Grid &, const T *, const SolveCtl *, const double *, \
+                                      T *, hipStream_t);                                       \
+  template void launch_returned_residual<T>(const Grid &, const T *, const T *, double *,       \
+                                            SolveCtl *, hipStream_t);                          \
   template void launch_project<T>(const Grid &, const Dyn<T> &, const Profiles<T> &, const T *,  \
                                   const SolveCtl *, T *, T *, T *, T *, hipStream_t);            \
   template void launch_sub_mean<T>(const Grid &, const T *, const SolveCtl *, T *, hipStream_t); \
   template void launch_block_sum<T>(const T *, int64_t, int, double *, hipStream_t);            \
-  template void launch_guess_gate<T>(const Grid &, const T *, const T *, T *, double *,        \
-                                     SolveCtl *, hipStream_t);                                   \
-  template void launch_add_guess<T>(const Grid &, const T *, const SolveCtl *, T *, hipStream_t); \
+  template void launch_guess_gate<T>(const Grid &, const T *, const T *, const double *, T *,   \
+                                     double *, SolveCtl *, int, hipStream_t);                    \
+  template void launch_add_guess<T>(const Grid &, const T *, const double *, const SolveCtl *,   \
+                                    T *, hipStream_t);                                           \
   template void launch_extrapolate<T>(const Grid &, const Profiles<T> &, const T *, const T *,   \
                                       T *, hipStream_t);
 LES_INST(float)

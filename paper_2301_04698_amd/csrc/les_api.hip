@@ -31,6 +31,7 @@ enum Field {
 };
 
 constexpr size_t kAlign = 256;
+constexpr int kProfT = 7;  // storage-type profiles
 constexpr int kPartialCap = kPartials + 1024;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -38,7 +39,9 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   size_t field[F_COUNT];
   size_t prof_d;    // 4 x nz doubles: p0, lnp, alpha0, rho0
-  size_t prof_t;    // 4 x nz elems: rho0, alpha0, beta, wsub
+  size_t prof_t;    // 7 x nz elems: rho0, alpha0, beta, wsub, pgz, cbar, phigz
+  size_t lvl_part;  // kPartials doubles: per-level partial sums
+  size_t mean_d;    // 4 x nz doubles: rsub, phibar, gbar, pbar (the FP64 mean-mode state)
   size_t partials;  // kPartialCap doubles
   size_t partials2; // kPartials doubles: every other residual check's partials
   size_t ctl;       // SolveCtl
@@ -52,9 +55,9 @@ struct Layout {
 
 int validate(const les_config *c) {
   if (!c) return fail(LES_ERR_ARG, "config is NULL");
-  if (c->nx < 2 || c->ny < 1 || c->nz < 4)
-    return fail(LES_ERR_ARG, "grid %dx%dx%d: nx must be >= 2, ny >= 1 and nz >= 4", c->nx,
-                c->ny, c->nz);
+  if (c->nx < 2 || c->ny < 1 || c->nz < 4 || c->nz > 65535)
+    return fail(LES_ERR_ARG, "grid %dx%dx%d: nx must be >= 2, ny >= 1 and 4 <= nz <= 65535",
+                c->nx, c->ny, c->nz);
   // A z plane of one field stays within 2 GiB (the stencil kernels address
   // a plane with 32-bit byte offsets); at most 2^34 cells.
   const int64_t elem = c->precision == LES_FP64 ? 8 : 4;
@@ -95,8 +98,9 @@ int validate(const les_config *c) {
     return fail(LES_ERR_ARG, "T_ice must be in (0, Tf) for LES_PHASE_RAMP");
   if (c->guess < LES_GUESS_ZERO || c->guess > LES_GUESS_LEARNED)
     return fail(LES_ERR_ARG, "unknown guess mode %d", c->guess);
-  if (c->mean_mode != LES_MEAN_SWEPT)
-    return fail(LES_ERR_ARG, "mean mode %d is not supported", c->mean_mode);
+  if (c->mean_mode != LES_MEAN_SWEPT && c->mean_mode != LES_MEAN_EXACT)
+    return fail(LES_ERR_ARG, "unknown mean mode %d", c->mean_mode);
+  if (c->reserved != 0) return fail(LES_ERR_ARG, "reserved must be 0");
   return LES_OK;
 }
 
@@ -114,7 +118,11 @@ Layout layout_of(const les_config *c) {
   L.prof_d = off;
   off = align_up(off + 4 * (size_t)c->nz * sizeof(double));
   L.prof_t = off;
-  off = align_up(off + 4 * (size_t)c->nz * es);
+  off = align_up(off + kProfT * (size_t)c->nz * es);
+  L.lvl_part = off;
+  off = align_up(off + kPartials * sizeof(double));
+  L.mean_d = off;
+  off = align_up(off + 4 * (size_t)c->nz * sizeof(double));
   L.partials = off;
   off = align_up(off + kPartialCap * sizeof(double));
   L.partials2 = off;
@@ -165,6 +173,7 @@ struct les_handle {
   std::vector<char> hist_valid;  // per sub-iteration: history holds a solution
   bool cnn_bound;                // learned guess: parameters bound
   float cnn_alpha;               // its leaky ReLU slope
+  int64_t steps_done;            // time steps taken since les_init (or the imported count)
 };
 
 namespace {
@@ -196,6 +205,11 @@ struct View {
   SolveCtl *ctl;
   double *diag;
   T *u, *v, *w, *thl, *qt, *p;
+  // mean-mode state: level partials, per-level centring values, the
+  // horizontally uniform part of the current solution, of a guess, and of p'
+  double *lvl_part, *rsub, *phibar, *gbar, *pbar;
+  T *pgz_w, *cbar_w, *phigz_w;  // writable views of the profile terms
+  int exact;                    // LES_MEAN_EXACT
 };
 
 template <typename T>
@@ -213,6 +227,16 @@ View<T> view_of(const les_handle *h) {
   V.P.alpha0_t = pt + nz;
   V.P.beta_t = pt + 2 * nz;
   V.P.wsub_t = pt + 3 * nz;
+  V.P.pgz_t = V.pgz_w = pt + 4 * nz;
+  V.P.cbar_t = V.cbar_w = pt + 5 * nz;
+  V.P.phigz_t = V.phigz_w = pt + 6 * nz;
+  V.lvl_part = (double *)ws(h, h->lay.lvl_part);
+  double *md = (double *)ws(h, h->lay.mean_d);
+  V.rsub = md;
+  V.phibar = md + nz;
+  V.gbar = md + 2 * nz;
+  V.pbar = md + 3 * nz;
+  V.exact = h->cfg.mean_mode == LES_MEAN_EXACT;
   V.partials = (double *)ws(h, h->lay.partials);
   V.partials2 = (double *)ws(h, h->lay.partials2);
   V.ctl = (SolveCtl *)ws(h, h->lay.ctl);
@@ -256,7 +280,8 @@ int upload_profiles(les_handle *h) {
   const les_config &c = h->cfg;
   const int nz = c.nz;
   std::vector<double> pd(4 * (size_t)nz);
-  std::vector<T> pt(4 * (size_t)nz);
+  std::vector<T> pt(kProfT * (size_t)nz, T(0));
+  const std::vector<double> md(4 * (size_t)nz, 0.0);  // no mean-mode part yet
   const double H = nz * c.dz, zs = (1.0 - c.sponge_frac) * H;
   const double pi = 3.14159265358979323846;
   for (int k = 0; k < nz; ++k) {
@@ -284,15 +309,12 @@ int upload_profiles(les_handle *h) {
                          hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipMemcpyAsync(ws(h, h->lay.prof_t), pt.data(), pt.size() * sizeof(T),
                          hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipMemcpyAsync(ws(h, h->lay.mean_d), md.data(), md.size() * sizeof(double),
+                         hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   return LES_OK;
 }
 
-// One Poisson solve on the workspace buffers.  rhs_in is the raw
-// right-hand side (may be the workspace rhs itself); the centred rhs goes to
-// F_RHS.  If use_guess, F_PHI0 already holds the guess.  On return
-// *result points at the buffer holding the returned iterate (not yet
-// gauge-shifted; ctl->phi_mean is not computed here).
 // Device time of the runs of consecutive plain (non-check) sweeps of one
 // solve that lie before the returned iterate.
 struct SweepTiming {
@@ -301,39 +323,67 @@ struct SweepTiming {
   int64_t sweeps = 0;
 };
 
+// Centred right-hand side of a solve into F_RHS (rhs_in may be F_RHS
+// itself): the mean removed and, with the horizontally uniform part solved
+// exactly, the horizontal mean of every level, whose part of the solution
+// goes to V.phibar (zero otherwise).  Resets the control block; the
+// stopping test is relative to ||rhs_in - mean||, the norm of the whole
+// centred right-hand side.
 template <typename T>
-int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
-          les_solve_stats *st, T **result, SweepTiming *timing = nullptr,
-          bool start_recorded = false, bool gated = false, T *rhs_work = nullptr) {
+int prepare_rhs(les_handle *h, View<T> &V, const T *rhs_in, int max_sweeps, bool fixed) {
+  const Grid &g = h->grid;
+  hipStream_t s = h->stream;
+  const double tol = h->cfg.poisson_tol;
+  launch_ctl_reset(V.ctl, max_sweeps, fixed ? 1 : 0, s);
+  launch_level_sum<T>(g, rhs_in, V.lvl_part, s);
+  launch_mean_mode(g, V.lvl_part, V.exact, V.ctl, V.rsub, V.phibar, s);
+  // the sweeps start from zero in F_PHI0
+  launch_rhs_center<T>(g, rhs_in, V.f[F_RHS], V.f[F_PHI0], V.rsub, V.ctl, V.partials, s);
+  launch_final(V.partials, level_parts(g) * g.nz, kFinalRhsNorm, V.ctl, (double)g.n, tol * tol,
+               0, nullptr, s);
+  LAUNCH_TRY();
+  return LES_OK;
+}
+
+// Starting iterate `guess` of the solve prepared by prepare_rhs, in defect
+// form: F_RHSD = F_RHS - L(guess - gbar), gbar its horizontal means per
+// level when those are solved exactly (already part of V.phibar).  The
+// guess is kept if always_keep or its residual is below the zero start's;
+// a dropped guess leaves F_RHSD = F_RHS.
+template <typename T>
+int prepare_guess(les_handle *h, View<T> &V, const T *guess, bool always_keep) {
+  const Grid &g = h->grid;
+  hipStream_t s = h->stream;
+  launch_level_sum<T>(g, guess, V.lvl_part, s);
+  launch_level_mean(g, V.lvl_part, V.exact, V.gbar, s);
+  launch_guess_gate<T>(g, V.f[F_RHS], guess, V.exact ? V.gbar : nullptr, V.f[F_RHSD], V.partials,
+                       V.ctl, always_keep ? 1 : 0, s);
+  LAUNCH_TRY();
+  return LES_OK;
+}
+
+// Sweeps on L phi = rhs from zero until the device-side residual test
+// (relative to the reference norm in the control block) stops them, the cap
+// or exactly `fixed` sweeps.  *result: the buffer holding the returned
+// iterate; *out: the control block as it ended (the stream is synchronized).
+template <typename T>
+int run_sweeps(les_handle *h, View<T> &V, const T *rhs, int fixed, SolveCtl *out, T **result,
+               SweepTiming *timing) {
   const les_config &c = h->cfg;
   const Grid &g = h->grid;
   hipStream_t s = h->stream;
   const int max_sweeps = fixed > 0 ? fixed : c.poisson_max_sweeps;
   const int every = c.poisson_check_every;
-  // centred rhs the sweeps read (a defect solve centres its own in place)
-  T *rhs = rhs_work ? rhs_work : V.f[F_RHS];
-
-  // start of the solve's time (the caller records it before preparing a guess)
-  if (!start_recorded) HIP_TRY(hipEventRecord(h->ev_s0, s));
-  launch_ctl_reset(V.ctl, max_sweeps, fixed > 0 ? 1 : 0, s);
-  launch_block_sum(rhs_in, g.n, 0, V.partials, s);
-  launch_final(V.partials, kReduceBlocks, kFinalRhsMean, V.ctl, (double)g.n, 0.0, 0, nullptr, s);
-  launch_rhs_center(g, rhs_in, rhs, use_guess ? (T *)nullptr : V.f[F_PHI0], V.ctl, V.partials, s);
-  // a defect solve stops on the residual relative to the original ||rhs||
-  launch_final(V.partials, kReduceBlocks, gated ? kFinalRhsNormRef : kFinalRhsNorm, V.ctl,
-               (double)g.n, c.poisson_tol * c.poisson_tol, 0, nullptr, s);
-  LAUNCH_TRY();
-
   const bool cheb = c.poisson_scheme == LES_CHEBYSHEV;
   const double gamma = 2.0 / (h->mu_min + h->mu_max);
   const double rho = (h->mu_max - h->mu_min) / (h->mu_max + h->mu_min);
   const double omega_j = cheb ? gamma : (c.jacobi_omega > 0 ? c.jacobi_omega : gamma);
   const int smax = h->sweeps_per_launch;
 
-  // Launch plan: launches of up to smax sweeps; a residual check at sweep m
-  // is computed by the launch that starts at m (its input iterate is phi_m),
-  // so launches are cut at check positions.  Checks at every `every`-th
-  // sweep and at the cap (or only at the fixed count).
+  // Launches of up to smax sweeps, made one at a time; a residual check at
+  // sweep m is computed by the launch that starts at m (its input iterate
+  // is phi_m), so launches are cut at check positions.  Checks at every
+  // `every`-th sweep and at the cap (or only at the fixed count).
   auto is_check = [&](int mm) {
     return fixed > 0 ? (mm == max_sweeps) : (mm % every == 0 || mm == max_sweeps);
   };
@@ -341,21 +391,21 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
     int m, S;
     bool check;
   };
-  std::vector<Launch> plan;
-  for (int mm = 0; mm <= max_sweeps;) {
-    int S = 1;
+  auto launch_at = [&](int mm) {
+    Launch L{mm, 1, is_check(mm)};
     if (mm < max_sweeps)
-      while (S < smax && mm + S < max_sweeps && !is_check(mm + S)) ++S;
-    plan.push_back(Launch{mm, S, is_check(mm)});
-    mm += S;
-  }
+      while (L.S < smax && mm + L.S < max_sweeps && !is_check(mm + L.S)) ++L.S;
+    return L;
+  };
 
   // Four iterate buffers: a launch reads (prev, cur) and writes its last two
-  // iterates into the two buffers it does not read.  Each check records the
-  // buffer that holds its input iterate.
+  // iterates into the two buffers it does not read.  The last few checks
+  // remember the buffer of their input iterate; the decisive one is among
+  // them (the host stops queueing `lag` checks after the device decided).
   T *buf[4] = {V.f[F_PHI0], V.f[F_PHI1], V.f[F_PHI2], V.f[F_PHI3]};
   int cur = 0, prev = -1;
-  std::vector<std::pair<int, int>> check_buf;  // (m, buffer of phi_m)
+  constexpr int kRecent = 16;
+  int recent_m[kRecent], recent_buf[kRecent], nrecent = 0;
 
   // Queue launches; the device stops applying them once a check succeeds.
   // The host polls a pinned copy of the control block after a bounded lag.
@@ -364,7 +414,8 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
   struct Run {
     int first, last;
   };
-  std::vector<Run> runs;  // timed runs of full-size plain launches
+  constexpr size_t kMaxRuns = 4096;  // timed runs per solve (a sample)
+  std::vector<Run> runs;
   const bool timed = timing && timing->enabled;
   int run_first = -1;
   double wc_prev = 1.0;  // Chebyshev weight recurrence
@@ -388,11 +439,14 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
     }
     return hipSuccess;
   };
-  size_t li = 0;
-  for (; li < plan.size(); ++li) {
-    const Launch L = plan[li];
+  Launch L = launch_at(0);
+  int last_m = 0;
+  for (bool more = true; more;) {
+    const Launch nextL = L.m + L.S <= max_sweeps ? launch_at(L.m + L.S) : Launch{-1, 0, false};
+    const bool has_next = nextL.m >= 0;
+    last_m = L.m;
     const bool plain_full = !L.check && L.S == smax;
-    if (timed && plain_full && run_first < 0) {
+    if (timed && plain_full && run_first < 0 && runs.size() < kMaxRuns) {
       const size_t e = 2 * runs.size();
       while (h->ev_sweep.size() < e + 2) {
         hipEvent_t ev;
@@ -419,7 +473,11 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
       if (q != cur && q != prev) free_[nf++] = q;
     const int out_last = L.S == 1 ? free_[0] : free_[1];
     const int out_prev = L.S == 1 ? -1 : free_[0];
-    if (L.check) check_buf.emplace_back(L.m, cur);
+    if (L.check) {
+      recent_m[nrecent % kRecent] = L.m;
+      recent_buf[nrecent % kRecent] = cur;
+      ++nrecent;
+    }
     // A check left pending by the previous launch is decided by this one
     // (block 0 reduces its partials); checks alternate partial buffers so a
     // checking launch can decide the check before it.
@@ -438,8 +496,7 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
       prev = out_prev;
     }
     cur = out_last;
-    const bool next_plain_full =
-        li + 1 < plan.size() && !plan[li + 1].check && plan[li + 1].S == smax;
+    const bool next_plain_full = has_next && !nextL.check && nextL.S == smax;
     if (timed && run_first >= 0 && !next_plain_full) {
       HIP_TRY(hipEventRecord(h->ev_sweep[2 * runs.size() + 1], s));
       runs.push_back(Run{run_first, L.m + L.S - 1});
@@ -456,7 +513,7 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
       // partial sums come from this launch's own block decomposition; the
       // next launch decides unless it is a two-sweep launch or there is none
       const int np = tsweep_blocks(g, L.S, sizeof(T) == 8);
-      if (L.S == 1 && li + 1 < plan.size() && plan[li + 1].S == 1) {
+      if (L.S == 1 && has_next && nextL.S == 1) {
         pend_m = L.m;
         pend_parts = parts;
         pend_np = np;
@@ -468,7 +525,8 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
         stop = stop || stop2;
       }
     }
-    if (stop) break;
+    more = !stop && has_next;
+    if (more) L = nextL;
   }
   if (pend_m >= 0) {  // a check no later launch decided (the loop stopped early)
     launch_final(pend_parts, pend_np, kFinalCheck, V.ctl, (double)g.n, 0.0, pend_m, nullptr, s);
@@ -477,12 +535,12 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
   LAUNCH_TRY();
   if (timed && run_first >= 0) {  // loop left inside a run
     HIP_TRY(hipEventRecord(h->ev_sweep[2 * runs.size() + 1], s));
-    runs.push_back(Run{run_first, plan[li < plan.size() ? li : plan.size() - 1].m});
+    runs.push_back(Run{run_first, last_m});
   }
-  HIP_TRY(hipEventRecord(h->ev_s1, s));
   HIP_TRY(hipMemcpyAsync(&h->ctl_host[0], V.ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   const SolveCtl &r = h->ctl_host[0];
+  *out = r;
   if (timed) {
     // only runs made entirely of sweeps applied before the returned iterate
     for (size_t q = 0; q < runs.size(); ++q) {
@@ -493,23 +551,70 @@ int solve(les_handle *h, View<T> &V, const T *rhs_in, bool use_guess, int fixed,
       timing->sweeps += runs[q].last - runs[q].first + 1;
     }
   }
-  float ms = 0.f;
-  HIP_TRY(hipEventElapsedTime(&ms, h->ev_s0, h->ev_s1));
   if (r.done == 0 || r.stop_m < 0)
     return fail(LES_ERR_STATE, "Poisson solve ended without a decision");
   int res_buf = -1;
-  for (const auto &cb : check_buf)
-    if (cb.first == r.stop_m) res_buf = cb.second;
+  for (int q = 0; q < kRecent && q < nrecent; ++q)
+    if (recent_m[q] == r.stop_m) res_buf = recent_buf[q];
   if (res_buf < 0) return fail(LES_ERR_STATE, "Poisson solve stopped at an unchecked sweep");
-  st->sweeps = r.stop_m;
-  st->status = r.done == 1 ? 0 : (r.done == 3 ? 1 : -3);
-  st->rhs_norm = std::sqrt(r.rhs_norm2);
-  st->res_norm = std::sqrt(r.res_norm2);
-  st->seconds = ms * 1e-3;
-  st->guess = gated ? (r.guess_kept ? 1 : 2) : (use_guess ? 1 : 0);
-  st->reserved = 0;
   *result = buf[res_buf];
   if (r.done == 2) return fail(LES_ERR_NONFINITE, "non-finite Poisson residual");
+  return LES_OK;
+}
+
+// A whole solve after prepare_rhs (and prepare_guess if `guess`): the
+// sweeps, then for a kept guess phi = guess - gbar + correction and the FP64
+// residual of that returned iterate.  gated: a kept guess whose solve
+// reaches the cap, or whose returned iterate misses the tolerance, is
+// dropped and the sweeps repeated from the zero start (unless the sweep
+// count is fixed).  The caller recorded h->ev_s0 before preparing the
+// solve; st covers everything since.
+template <typename T>
+int solve_prepared(les_handle *h, View<T> &V, const T *guess, bool gated, int fixed,
+                   les_solve_stats *st, T **result, SweepTiming *timing) {
+  const Grid &g = h->grid;
+  hipStream_t s = h->stream;
+  SolveCtl r;
+  T *phi = nullptr;
+  int rc = run_sweeps<T>(h, V, guess ? V.f[F_RHSD] : V.f[F_RHS], fixed, &r, &phi, timing);
+  if (rc) return rc;
+  int sweeps = r.stop_m;
+  int flag = guess ? (r.guess_kept ? 1 : 2) : 0;
+  double res2 = r.res_norm2;
+  if (guess && r.guess_kept) {
+    launch_add_guess<T>(g, guess, V.exact ? V.gbar : nullptr, V.ctl, phi, s);
+    launch_returned_residual<T>(g, V.f[F_RHS], phi, V.partials, V.ctl, s);
+    LAUNCH_TRY();
+    HIP_TRY(hipMemcpyAsync(&h->ctl_host[0], V.ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    r = h->ctl_host[0];
+    res2 = r.res_out2;
+    const bool missed = r.done == 3 || !(res2 <= r.tol2);
+    if (gated && fixed == 0 && missed) {
+      launch_ctl_restart(V.ctl, s);
+      launch_zero<T>(g, V.f[F_PHI0], s);
+      LAUNCH_TRY();
+      rc = run_sweeps<T>(h, V, V.f[F_RHS], 0, &r, &phi, timing);
+      if (rc) return rc;
+      sweeps += r.stop_m;
+      res2 = r.res_norm2;
+      flag = 3;
+    } else if (r.done == 1 && !(res2 <= r.tol2)) {
+      r.done = 3;  // the returned iterate misses the tolerance
+    }
+  }
+  HIP_TRY(hipEventRecord(h->ev_s1, s));
+  HIP_TRY(hipEventSynchronize(h->ev_s1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, h->ev_s0, h->ev_s1));
+  st->sweeps = sweeps;
+  st->status = r.done == 1 ? 0 : 1;
+  st->rhs_norm = std::sqrt(r.rhs_norm2);
+  st->res_norm = std::sqrt(res2);
+  st->seconds = ms * 1e-3;
+  st->guess = flag;
+  st->reserved = 0;
+  *result = phi;
   return LES_OK;
 }
 
@@ -572,15 +677,21 @@ int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step
                          V.f[F_B_H], num, V.u, V.v, V.w, s);
       launch_poisson_rhs<T>(g, V.dyn, V.P, V.u, V.v, V.w, lag, V.f[F_RHS], V.partials, s);
       LAUNCH_TRY();
-      // Initial guess.  At k = 0 p holds p^n and the workspace p^{n-1}; the
-      // extrapolated and learned guesses read both, then p^{n-1} <- p^n.
-      // the solve's time includes preparing its guess
+      const int solve_idx = step * K + k;
+      const int fixed = opts && opts->replay_sweeps ? opts->replay_sweeps[solve_idx] : 0;
+      if (opts && opts->replay_sweeps && fixed < 0)
+        return fail(LES_ERR_ARG, "replay_sweeps[%d] = %d < 0", solve_idx, fixed);
+      // the solve's time includes preparing its right-hand side and guess
       HIP_TRY(hipEventRecord(h->ev_s0, s));
-      T *hist = (T *)ws(h, h->lay.hist) + (size_t)k * g.n;
+      int rc = prepare_rhs<T>(h, V, V.f[F_RHS], fixed > 0 ? fixed : c.poisson_max_sweeps,
+                              fixed > 0);
+      if (rc) return rc;
       // Starting iterate: the previous step's solution of this sub-iteration
-      // (corrected by the network in the learned form), or at k = 0 the
-      // extrapolated pressure change.  At k = 0 p holds p^n and the
-      // workspace p^{n-1}.
+      // (corrected by the network in the learned form, whose input is the
+      // residual of that solution for the centred right-hand side), or at
+      // k = 0 the extrapolated pressure change: p holds p^n and the
+      // workspace p^{n-1}, then p^{n-1} <- p^n.
+      T *hist = (T *)ws(h, h->lay.hist) + (size_t)k * g.n;
       const T *guess = nullptr;
       if (c.guess == LES_GUESS_PREVIOUS || c.guess == LES_GUESS_LEARNED) {
         if (h->hist_valid[k]) {
@@ -598,38 +709,19 @@ int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step
         LAUNCH_TRY();
         guess = V.f[F_GUESS];
       }
-      const bool guessed = guess != nullptr;
-      if (guessed) {
-        // Defect form: centre rhs, then rhs_d = rhs - L guess; the sweeps
-        // solve for the correction from zero, so FP32 rounding acts at the
-        // correction's size, not the guess's.  A guess whose residual is
-        // not below the zero start's is dropped (rhs_d = rhs).
-        launch_block_sum<T>(V.f[F_RHS], g.n, 0, V.partials, s);
-        launch_final(V.partials, kReduceBlocks, kFinalRhsMean, V.ctl, (double)g.n, 0.0, 0,
-                     nullptr, s);
-        launch_rhs_center<T>(g, V.f[F_RHS], V.f[F_RHS], nullptr, V.ctl, V.partials, s);
-        launch_guess_gate<T>(g, V.f[F_RHS], guess, V.f[F_RHSD], V.partials, V.ctl, s);
-        LAUNCH_TRY();
-      }
-      const int solve_idx = step * K + k;
-      const int fixed = opts && opts->replay_sweeps ? opts->replay_sweeps[solve_idx] : 0;
-      if (opts && opts->replay_sweeps && fixed < 0)
-        return fail(LES_ERR_ARG, "replay_sweeps[%d] = %d < 0", solve_idx, fixed);
+      // Defect form: the sweeps solve for the correction from zero, so FP32
+      // rounding acts at the correction's size, not the guess's.  A guess
+      // whose residual is not below the zero start's is dropped.
+      if (guess && (rc = prepare_guess<T>(h, V, guess, false))) return rc;
       les_solve_stats st;
       T *phi = nullptr;
       SweepTiming timing;
       timing.enabled = opts && opts->time_sweeps;
-      int rc = guessed ? solve<T>(h, V, V.f[F_RHSD], false, fixed, &st, &phi, &timing, true, true,
-                                  V.f[F_RHSD])
-                       : solve<T>(h, V, V.f[F_RHS], false, fixed, &st, &phi, &timing, true);
+      rc = solve_prepared<T>(h, V, guess, true, fixed, &st, &phi, &timing);
       acc.sweep_seconds += timing.seconds;
       acc.sweeps_timed += timing.sweeps;
       if (opts && opts->records) opts->records[solve_idx] = st;
       if (rc < 0) return rc;
-      if (guessed) {  // phi = guess + correction
-        launch_add_guess<T>(g, guess, V.ctl, phi, s);
-        LAUNCH_TRY();
-      }
       acc.solves++;
       acc.sweeps_total += st.sweeps;
       if (st.sweeps > acc.sweeps_max) acc.sweeps_max = st.sweeps;
@@ -640,9 +732,13 @@ int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step
       const double rel = st.rhs_norm > 0 ? st.res_norm / st.rhs_norm : 0.0;
       if (rel > acc.res_rel_max) acc.res_rel_max = rel;
       acc.poisson_seconds += st.seconds;
-      // gauge (zero mean) and projection
+      // gauge (zero mean); profile terms of the horizontally uniform part
+      // (projection, the next sub-iteration's right-hand side) and its
+      // pressure, p_bar += rho0 phi_bar in FP64
       launch_block_sum<T>(phi, g.n, 0, V.partials, s);
       launch_final(V.partials, kReduceBlocks, kFinalPhiMean, V.ctl, (double)g.n, 0.0, 0, nullptr, s);
+      launch_mean_profiles<T>(g, V.phibar, V.P.rho0, V.P.alpha0, 1, V.pbar, V.phigz_w, V.cbar_w,
+                              V.pgz_w, s);
       if (c.guess == LES_GUESS_PREVIOUS || c.guess == LES_GUESS_LEARNED) {
         launch_sub_mean<T>(g, phi, V.ctl, hist, s);
         h->hist_valid[k] = 1;
@@ -653,12 +749,24 @@ int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step
                                  hipMemcpyDeviceToDevice, s));
         if (opts->dump_phi)
           launch_sub_mean<T>(g, phi, V.ctl, (T *)opts->dump_phi + (size_t)k * g.n, s);
+        if (opts->dump_mean) {
+          // per-level values the centring removed and the solution's
+          // horizontally uniform part (FP64, host)
+          double *dm = opts->dump_mean + (size_t)k * (2 * g.nz + 1);
+          HIP_TRY(hipMemcpyAsync(dm, V.rsub, g.nz * sizeof(double), hipMemcpyDeviceToHost, s));
+          HIP_TRY(hipMemcpyAsync(dm + g.nz, V.phibar, g.nz * sizeof(double),
+                                 hipMemcpyDeviceToHost, s));
+          HIP_TRY(hipMemcpyAsync(dm + 2 * g.nz, &V.ctl->rhs_mean, sizeof(double),
+                                 hipMemcpyDeviceToHost, s));
+          HIP_TRY(hipStreamSynchronize(s));
+        }
       }
       launch_project<T>(g, V.dyn, V.P, phi, V.ctl, V.u, V.v, V.w, V.p, s);
       LAUNCH_TRY();
       lag = phi;
     }
     acc.steps++;
+    h->steps_done++;
   }
   HIP_TRY(hipEventRecord(e1, s));
   HIP_TRY(hipEventSynchronize(e1));
@@ -676,24 +784,65 @@ int poisson_impl(les_handle *h, const void *rhs, void *phi, const les_poisson_op
                  les_solve_stats *stats) {
   View<T> V = view_of<T>(h);
   const Grid &g = h->grid;
-  const bool guess = opts && opts->use_guess;
+  hipStream_t s = h->stream;
+  const int use_guess = opts ? opts->use_guess : 0;
   const int fixed = opts ? opts->fixed_sweeps : 0;
   if (fixed < 0) return fail(LES_ERR_ARG, "fixed_sweeps < 0");
-  if (guess)
-    HIP_TRY(hipMemcpyAsync(V.f[F_PHI0], phi, (size_t)g.n * sizeof(T), hipMemcpyDeviceToDevice,
-                           h->stream));
+  if (use_guess < 0 || use_guess > 2) return fail(LES_ERR_ARG, "use_guess must be 0, 1 or 2");
+  HIP_TRY(hipEventRecord(h->ev_s0, s));
+  int rc = prepare_rhs<T>(h, V, (const T *)rhs, fixed > 0 ? fixed : h->cfg.poisson_max_sweeps,
+                          fixed > 0);
+  if (rc) return rc;
+  const T *guess = nullptr;
+  if (use_guess) {
+    HIP_TRY(hipMemcpyAsync(V.f[F_GUESS], phi, (size_t)g.n * sizeof(T), hipMemcpyDeviceToDevice,
+                           s));
+    guess = V.f[F_GUESS];
+    if ((rc = prepare_guess<T>(h, V, guess, use_guess == 1))) return rc;
+  }
   les_solve_stats st;
   T *res = nullptr;
-  int rc = solve<T>(h, V, (const T *)rhs, guess, fixed, &st, &res);
+  rc = solve_prepared<T>(h, V, guess, use_guess == 2, fixed, &st, &res, nullptr);
   if (stats) *stats = st;
   if (rc < 0) return rc;
-  launch_block_sum<T>(res, g.n, 0, V.partials, h->stream);
-  launch_final(V.partials, kReduceBlocks, kFinalPhiMean, V.ctl, (double)g.n, 0.0, 0, nullptr,
-               h->stream);
-  launch_sub_mean<T>(g, res, V.ctl, (T *)phi, h->stream);
+  launch_block_sum<T>(res, g.n, 0, V.partials, s);
+  launch_final(V.partials, kReduceBlocks, kFinalPhiMean, V.ctl, (double)g.n, 0.0, 0, nullptr, s);
+  launch_add_profile<T>(g, res, V.ctl, V.phibar, (T *)phi, s);
+  LAUNCH_TRY();
+  HIP_TRY(hipStreamSynchronize(s));
+  return st.status == 1 ? LES_WARN_NOT_CONVERGED : LES_OK;
+}
+
+// The momentum predictor's profile d_c(alpha0 pbar)/dz from the pbar held
+// in the workspace.  Synchronizes.
+template <typename T>
+int set_pressure_profile_device(les_handle *h) {
+  View<T> V = view_of<T>(h);
+  launch_mean_profiles<T>(h->grid, nullptr, V.P.rho0, V.P.alpha0, 0, V.pbar, V.phigz_w, V.cbar_w,
+                          V.pgz_w, h->stream);
   LAUNCH_TRY();
   HIP_TRY(hipStreamSynchronize(h->stream));
-  return st.status == 1 ? LES_WARN_NOT_CONVERGED : LES_OK;
+  return LES_OK;
+}
+
+template <typename T>
+int set_pressure_profile_impl(les_handle *h, const double *pbar_host) {
+  View<T> V = view_of<T>(h);
+  HIP_TRY(hipMemcpyAsync(V.pbar, pbar_host, h->grid.nz * sizeof(double), hipMemcpyHostToDevice,
+                         h->stream));
+  return set_pressure_profile_device<T>(h);
+}
+
+template <typename T>
+int pressure_impl(les_handle *h, void *p_out, double *pbar_host) {
+  View<T> V = view_of<T>(h);
+  if (p_out) launch_add_profile<T>(h->grid, V.p, nullptr, V.pbar, (T *)p_out, h->stream);
+  LAUNCH_TRY();
+  if (pbar_host)
+    HIP_TRY(hipMemcpyAsync(pbar_host, V.pbar, h->grid.nz * sizeof(double),
+                           hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return LES_OK;
 }
 
 template <typename T>
@@ -772,6 +921,36 @@ int cnn_guess(les_handle *h, View<T> &V, const T *rhs, const T *base, T *guess) 
   return LES_OK;
 }
 
+// Exported state: a header, then the FP64 pressure profile, then (by guess
+// mode) the previous step's pressure or the previous step's solutions of
+// each sub-iteration, each region 256-byte aligned.
+struct StateHeader {
+  char magic[8];  // "LESSTAT1"
+  int32_t nx, ny, nz, precision, mean_mode, guess, n_subiter, reserved;
+  uint64_t hist_valid;  // bit k: sub-iteration k's previous solution is held
+  int64_t steps_done;
+};
+static_assert(sizeof(StateHeader) <= kAlign, "state header exceeds its region");
+
+struct StateLayout {
+  size_t pbar, pm2, hist, total;
+};
+
+StateLayout state_layout(const les_config &c) {
+  const size_t n = (size_t)c.nx * c.ny * c.nz, es = elem_size(&c);
+  StateLayout S;
+  size_t off = kAlign;
+  S.pbar = off;
+  off = align_up(off + (size_t)c.nz * sizeof(double));
+  S.pm2 = off;
+  if (c.guess == LES_GUESS_EXTRAPOLATE) off = align_up(off + n * es);
+  S.hist = off;
+  if (c.guess == LES_GUESS_PREVIOUS || c.guess == LES_GUESS_LEARNED)
+    off = align_up(off + (size_t)c.n_subiter * n * es);
+  S.total = off;
+  return S;
+}
+
 int check_handle(const les_handle *h) {
   if (!h) return fail(LES_ERR_ARG, "handle is NULL");
   if (h->broken) return fail(LES_ERR_STATE, "handle unusable after an earlier HIP error");
@@ -822,7 +1001,7 @@ void les_default_config(les_config *c) {
   c->T_tr = 273.16;
   c->satadj_tol = 1e-10;
   c->T_ice = 233.15;
-  c->mean_mode = LES_MEAN_SWEPT;
+  c->mean_mode = LES_MEAN_EXACT;
 }
 
 size_t les_workspace_bytes(const les_config *cfg) {
@@ -838,7 +1017,20 @@ int les_workspace_offset(const les_config *cfg, int32_t field, size_t *offset) {
   return LES_OK;
 }
 
+namespace {
+int init_impl(const les_config *cfg, const les_buffers *bufs, void *stream, les_handle **out);
+}
+
 int les_init(const les_config *cfg, const les_buffers *bufs, void *stream, les_handle **out) {
+  if (out) *out = nullptr;
+  return guarded([&] { return init_impl(cfg, bufs, stream, out); });
+}
+
+}  // extern "C"
+
+namespace {
+
+int init_impl(const les_config *cfg, const les_buffers *bufs, void *stream, les_handle **out) {
   if (!out) return fail(LES_ERR_ARG, "out is NULL");
   *out = nullptr;
   int rc = validate(cfg);
@@ -899,6 +1091,7 @@ int les_init(const les_config *cfg, const les_buffers *bufs, void *stream, les_h
   h->hist_valid.assign(cfg->n_subiter, 0);
   h->cnn_bound = false;
   h->cnn_alpha = 0.f;
+  h->steps_done = 0;
   h->sweeps_per_launch = cfg->sweeps_per_launch > 0 ? cfg->sweeps_per_launch : kDefaultSweepsPerLaunch;
 
   auto cleanup = [&](int code) {
@@ -927,12 +1120,18 @@ int les_init(const les_config *cfg, const les_buffers *bufs, void *stream, les_h
   return LES_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
 int les_step(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step_stats *stats) {
   int rc = check_handle(h);
   if (rc) return rc;
   if (nsteps < 0) return fail(LES_ERR_ARG, "nsteps < 0");
-  rc = h->cfg.precision == LES_FP64 ? step_impl<double>(h, nsteps, opts, stats)
-                                    : step_impl<float>(h, nsteps, opts, stats);
+  rc = guarded([&] {
+    return h->cfg.precision == LES_FP64 ? step_impl<double>(h, nsteps, opts, stats)
+                                        : step_impl<float>(h, nsteps, opts, stats);
+  });
   if (rc == LES_ERR_HIP) h->broken = true;
   return rc;
 }
@@ -942,8 +1141,129 @@ int les_poisson_solve(les_handle *h, const void *rhs, void *phi, const les_poiss
   int rc = check_handle(h);
   if (rc) return rc;
   if (!rhs || !phi) return fail(LES_ERR_ARG, "rhs and phi must be non-NULL");
-  rc = h->cfg.precision == LES_FP64 ? poisson_impl<double>(h, rhs, phi, opts, stats)
-                                    : poisson_impl<float>(h, rhs, phi, opts, stats);
+  rc = guarded([&] {
+    return h->cfg.precision == LES_FP64 ? poisson_impl<double>(h, rhs, phi, opts, stats)
+                                        : poisson_impl<float>(h, rhs, phi, opts, stats);
+  });
+  if (rc == LES_ERR_HIP) h->broken = true;
+  return rc;
+}
+
+size_t les_state_bytes(const les_handle *h) {
+  if (!h) return 0;
+  return state_layout(h->cfg).total;
+}
+
+int les_export_state(les_handle *h, void *dst) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!dst) return fail(LES_ERR_ARG, "dst is NULL");
+  if ((uintptr_t)dst % kAlign) return fail(LES_ERR_ARG, "dst is not 256-byte aligned");
+  const les_config &c = h->cfg;
+  const StateLayout S = state_layout(c);
+  const size_t n = (size_t)h->grid.n, es = elem_size(&c);
+  StateHeader hd;
+  std::memset(&hd, 0, sizeof(hd));
+  std::memcpy(hd.magic, "LESSTAT1", 8);
+  hd.nx = c.nx;
+  hd.ny = c.ny;
+  hd.nz = c.nz;
+  hd.precision = c.precision;
+  hd.mean_mode = c.mean_mode;
+  hd.guess = c.guess;
+  hd.n_subiter = c.n_subiter;
+  for (int k = 0; k < c.n_subiter; ++k)
+    if (h->hist_valid[k]) hd.hist_valid |= (uint64_t)1 << k;
+  hd.steps_done = h->steps_done;
+  char *d = (char *)dst;
+  auto copy = [&](void *to, const void *from, size_t bytes, hipMemcpyKind kind) {
+    return hipMemcpyAsync(to, from, bytes, kind, h->stream);
+  };
+  hipError_t e = copy(d, &hd, sizeof(hd), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = copy(d + S.pbar, ws(h, h->lay.mean_d) + 3 * (size_t)c.nz * sizeof(double),
+             (size_t)c.nz * sizeof(double), hipMemcpyDeviceToDevice);
+  if (e == hipSuccess && c.guess == LES_GUESS_EXTRAPOLATE)
+    e = copy(d + S.pm2, ws(h, h->lay.field[F_PM2]), n * es, hipMemcpyDeviceToDevice);
+  if (e == hipSuccess && (c.guess == LES_GUESS_PREVIOUS || c.guess == LES_GUESS_LEARNED))
+    e = copy(d + S.hist, ws(h, h->lay.hist), (size_t)c.n_subiter * n * es,
+             hipMemcpyDeviceToDevice);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    h->broken = true;
+    return fail(LES_ERR_HIP, "exporting the state failed: %s", hipGetErrorString(e));
+  }
+  return LES_OK;
+}
+
+int les_import_state(les_handle *h, const void *src) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!src) return fail(LES_ERR_ARG, "src is NULL");
+  const les_config &c = h->cfg;
+  const StateLayout S = state_layout(c);
+  const size_t n = (size_t)h->grid.n, es = elem_size(&c);
+  StateHeader hd;
+  if (hipMemcpyAsync(&hd, src, sizeof(hd), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess) {
+    h->broken = true;
+    return fail(LES_ERR_HIP, "reading the state header failed");
+  }
+  if (std::memcmp(hd.magic, "LESSTAT1", 8) != 0)
+    return fail(LES_ERR_ARG, "src does not hold an exported state");
+  if (hd.nx != c.nx || hd.ny != c.ny || hd.nz != c.nz || hd.precision != c.precision ||
+      hd.mean_mode != c.mean_mode || hd.guess != c.guess || hd.n_subiter != c.n_subiter)
+    return fail(LES_ERR_ARG,
+                "state of a %dx%dx%d grid (precision %d, mean mode %d, guess %d, K %d) does not "
+                "match this handle",
+                hd.nx, hd.ny, hd.nz, hd.precision, hd.mean_mode, hd.guess, hd.n_subiter);
+  const char *d = (const char *)src;
+  auto copy = [&](void *to, const void *from, size_t bytes) {
+    return hipMemcpyAsync(to, from, bytes, hipMemcpyDeviceToDevice, h->stream);
+  };
+  hipError_t e = copy(ws(h, h->lay.mean_d) + 3 * (size_t)c.nz * sizeof(double), d + S.pbar,
+                      (size_t)c.nz * sizeof(double));
+  if (e == hipSuccess && c.guess == LES_GUESS_EXTRAPOLATE)
+    e = copy(ws(h, h->lay.field[F_PM2]), d + S.pm2, n * es);
+  if (e == hipSuccess && (c.guess == LES_GUESS_PREVIOUS || c.guess == LES_GUESS_LEARNED))
+    e = copy(ws(h, h->lay.hist), d + S.hist, (size_t)c.n_subiter * n * es);
+  if (e != hipSuccess) {
+    h->broken = true;
+    return fail(LES_ERR_HIP, "importing the state failed: %s", hipGetErrorString(e));
+  }
+  // the momentum predictor's pressure-gradient profile follows the profile
+  rc = c.precision == LES_FP64 ? set_pressure_profile_device<double>(h)
+                               : set_pressure_profile_device<float>(h);
+  if (rc) {
+    if (rc == LES_ERR_HIP) h->broken = true;
+    return rc;
+  }
+  for (int k = 0; k < c.n_subiter; ++k) h->hist_valid[k] = (hd.hist_valid >> k) & 1;
+  h->steps_done = hd.steps_done;
+  return LES_OK;
+}
+
+int64_t les_steps_done(const les_handle *h) { return h ? h->steps_done : -1; }
+
+int les_set_pressure_profile(les_handle *h, const double *pbar_host) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!pbar_host) return fail(LES_ERR_ARG, "pbar_host is NULL");
+  if (h->cfg.mean_mode != LES_MEAN_EXACT)
+    return fail(LES_ERR_STATE, "les_set_pressure_profile needs LES_MEAN_EXACT");
+  for (int k = 0; k < h->cfg.nz; ++k)
+    if (!std::isfinite(pbar_host[k])) return fail(LES_ERR_ARG, "pbar_host[%d] is not finite", k);
+  rc = h->cfg.precision == LES_FP64 ? set_pressure_profile_impl<double>(h, pbar_host)
+                                    : set_pressure_profile_impl<float>(h, pbar_host);
+  if (rc == LES_ERR_HIP) h->broken = true;
+  return rc;
+}
+
+int les_pressure(les_handle *h, void *p_out, double *pbar_host) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  rc = h->cfg.precision == LES_FP64 ? pressure_impl<double>(h, p_out, pbar_host)
+                                    : pressure_impl<float>(h, p_out, pbar_host);
   if (rc == LES_ERR_HIP) h->broken = true;
   return rc;
 }

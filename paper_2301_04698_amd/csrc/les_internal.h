@@ -33,6 +33,12 @@ template <typename T>
 struct Profiles {
   const double *p0, *lnp, *alpha0, *rho0;   // FP64: ln(p0/p00) feeds the Exner power
   const T *rho0_t, *alpha0_t, *beta_t, *wsub_t;
+  // terms of the horizontally uniform part of phi and p' (kept as FP64
+  // profiles, each term rounded once): d_c(alpha0 pbar)/dz for the momentum
+  // predictor, the App. A fourth difference of the previous sub-iteration's
+  // part for the right-hand side, d_c(phibar)/dz for the projection; all
+  // zero when that part is swept with the rest
+  const T *pgz_t, *cbar_t, *phigz_t;
 };
 
 // Parameters of the dynamics kernels in storage precision.
@@ -65,7 +71,7 @@ struct SolveCtl {
   int32_t fixed;      // 1: stop at max_sweeps whatever the residual
   int32_t guess_kept; // starting-iterate test (not reset by a solve): 1 kept
   int32_t pad;
-  double ref_norm2;   // ||rhs||^2 of the equation a defect solve stands for
+  double res_out2;    // residual^2 of a guessed solve's returned iterate
 };
 
 constexpr int kBlock = 256;          // threads per block of elementwise kernels
@@ -114,10 +120,43 @@ void launch_poisson_rhs(const Grid &g, const Dyn<T> &d, const Profiles<T> &P, co
                         const T *v, const T *w, const T *phi_lag, T *rhs, double *partials,
                         hipStream_t s);
 
-// rhs_out = rhs_in - ctl->rhs_mean; partial sums of rhs_out^2; optional zeroing of phi0.
+// Per-level kernels split each level's plane into level_parts(g) parts
+// (level_parts(g) * nz <= kPartials partial sums).
+int level_parts(const Grid &g);
+// part[k * level_parts + p] = FP64 sum of part p of level k of f.
 template <typename T>
-void launch_rhs_center(const Grid &g, const T *rhs_in, T *rhs_out, T *phi0, const SolveCtl *ctl,
-                       double *partials, hipStream_t s);
+void launch_level_sum(const Grid &g, const T *f, double *part, hipStream_t s);
+// From the level sums of a raw right-hand side: ctl->rhs_mean, the
+// per-level value the centring subtracts (rsub: level mean if exact, else
+// the mean) and, if exact, the FP64 solution pb of the horizontally uniform
+// part (zero otherwise).
+void launch_mean_mode(const Grid &g, const double *part, int exact, SolveCtl *ctl, double *rsub,
+                      double *pb, hipStream_t s);
+// gbar[k] = level mean from the level sums if exact, else 0.
+void launch_level_mean(const Grid &g, const double *part, int exact, double *gbar, hipStream_t s);
+// Storage-type profiles of a solution's horizontally uniform part pb
+// (nullable): phigz = d_c pb/dz, cbar = App. A fourth difference in z, and
+// with add_p pbar += rho0 pb; then pgz = d_c(alpha0 pbar)/dz.
+template <typename T>
+void launch_mean_profiles(const Grid &g, const double *pb, const double *rho0,
+                          const double *alpha0, int add_p, double *pbar, T *phigz, T *cbar,
+                          T *pgz, hipStream_t s);
+// out = in - ctl->phi_mean (ctl nullable) + prof[k].
+template <typename T>
+void launch_add_profile(const Grid &g, const T *in, const SolveCtl *ctl, const double *prof,
+                        T *out, hipStream_t s);
+// rhs_out = rhs_in - rsub[k] (FP64, rounded once); partial sums of
+// (rhs_in - ctl->rhs_mean)^2 (level_parts * nz of them); optional zeroing
+// of phi0.
+template <typename T>
+void launch_rhs_center(const Grid &g, const T *rhs_in, T *rhs_out, T *phi0, const double *rsub,
+                       const SolveCtl *ctl, double *partials, hipStream_t s);
+// Reset the stopping state for a second pass of sweeps on the same rhs.
+void launch_ctl_restart(SolveCtl *ctl, hipStream_t s);
+// f = 0 (a fill kernel rather than a memset, so the call records no memset
+// node when a caller captures the stream into a graph).
+template <typename T>
+void launch_zero(const Grid &g, T *f, hipStream_t s);
 
 // S sweeps from (prev, cur) = (phi_{m-1}, phi_m) giving out_prev = phi_{m+S-1}
 // (S >= 2, Chebyshev) and out_last = phi_{m+S}; check: FP64 partial sums of
@@ -144,17 +183,24 @@ template <typename T>
 void launch_extrapolate(const Grid &g, const Profiles<T> &P, const T *p, const T *p_prev, T *phi0,
                         hipStream_t s);
 
-// Starting iterate phi0 of a solve of L phi = rhs (rhs centred), in
-// defect form: rhs_d = rhs - L phi0 (FP64 arithmetic), so the sweeps solve
-// L delta = rhs_d from zero and phi = phi0 + delta.  The iterate is kept
-// only if ||rhs_d||_2 < ||rhs||_2 (the zero start's residual); otherwise
-// rhs_d = rhs.  Sets ctl->guess_kept and ctl->ref_norm2 = ||rhs||^2.
+// Starting iterate phi0 - gbar (gbar: per-level means to remove, nullable)
+// of a solve of L phi = rhs (rhs centred), in defect form: rhs_d = rhs -
+// L(phi0 - gbar) (FP64 arithmetic), so the sweeps solve L delta = rhs_d from
+// zero and phi = phi0 - gbar + delta.  The iterate is kept if always_keep
+// or ||rhs_d||_2 < ||rhs||_2 (the zero start's residual); otherwise rhs_d =
+// rhs.  Sets ctl->guess_kept.
 template <typename T>
-void launch_guess_gate(const Grid &g, const T *rhs, const T *phi0, T *rhs_d, double *partials,
-                       SolveCtl *ctl, hipStream_t s);
-// phi += phi0 (FP64 sum, rounded once) when ctl->guess_kept.
+void launch_guess_gate(const Grid &g, const T *rhs, const T *phi0, const double *gbar, T *rhs_d,
+                       double *partials, SolveCtl *ctl, int always_keep, hipStream_t s);
+// phi += phi0 - gbar (FP64 sum, rounded once) when ctl->guess_kept.
 template <typename T>
-void launch_add_guess(const Grid &g, const T *phi0, const SolveCtl *ctl, T *phi, hipStream_t s);
+void launch_add_guess(const Grid &g, const T *phi0, const double *gbar, const SolveCtl *ctl,
+                      T *phi, hipStream_t s);
+// ctl->res_out2 = ||rhs - L phi||^2 in FP64 (the residual of a returned
+// iterate).
+template <typename T>
+void launch_returned_residual(const Grid &g, const T *rhs, const T *phi, double *partials,
+                              SolveCtl *ctl, hipStream_t s);
 
 // Generic FP64 sums over n elements: mode 0 sum(a), 1 sum(a^2).
 template <typename T>
@@ -167,7 +213,7 @@ enum FinalOp {
   kFinalCheck = 2,     // residual check at sweep m
   kFinalPhiMean = 3,   // ctl->phi_mean = sum / n
   kFinalStore = 4,     // out[slot] = sum
-  kFinalRhsNormRef = 5 // as kFinalRhsNorm with ctl->ref_norm2 in place of the sum
+  kFinalReturned = 5   // ctl->res_out2 = sum
 };
 void launch_final(const double *partials, int np, int op, SolveCtl *ctl, double n, double tol2_scale,
                   int m, double *out, hipStream_t s);

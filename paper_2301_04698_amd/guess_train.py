@@ -104,12 +104,13 @@ def train(X, T, p, iters=4000, batch=16, crop=32, lr=2e-3, seed=0, alpha=DEFAULT
     return tr.params.detach().clone(), hist
 
 
-def run_mode(p, state, mode, nsteps, params=None, alpha=DEFAULT_ALPHA, device="cuda"):
+def run_mode(p, state, mode, nsteps, params=None, alpha=DEFAULT_ALPHA, device="cuda", pbar=None):
     """nsteps timed steps after one untimed step (which fills the history)
-    from `state` with the given guess mode; returns per-step figures."""
+    from `state` (p relative to the FP64 profile pbar) with the given guess
+    mode; returns per-step figures."""
     import torch
     ps = dict(p, guess=mode)
-    sim = les.LES(ps, state, device=device)
+    sim = les.LES(ps, state, device=device, pbar=pbar)
     if mode == "learned":
         cnn.bind(sim, params, alpha)
     sim.step(1)
@@ -147,11 +148,11 @@ def evaluate(p, params, seed, spinup, nsteps, alpha=DEFAULT_ALPHA, modes=("zero"
         sim.step(m)
         done += m
         log(f"evaluate: spin-up {done}/{spinup}")
-    state = sim.state_numpy()
+    state, pbar = sim.state_split()
     sim.close()
     res = {}
     for mode in modes:
-        res[mode] = run_mode(ps, state, mode, nsteps, params, alpha, device)
+        res[mode] = run_mode(ps, state, mode, nsteps, params, alpha, device, pbar=pbar)
         log(f"evaluate: {json.dumps(res[mode])}")
     return res
 

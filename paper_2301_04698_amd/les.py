@@ -39,8 +39,9 @@ WS_FIELDS = ("un", "vn", "wn", "thl_half", "qt_half", "thl_mid", "qt_mid", "uh",
              "phi2", "phi3", "p_prev", "guess", "rhs_defect")
 
 EXPORTS = ("les_default_config", "les_workspace_bytes", "les_workspace_offset", "les_init",
-           "les_step", "les_poisson_solve", "les_thermo", "les_diagnostics", "les_destroy",
-           "les_last_error")
+           "les_step", "les_poisson_solve", "les_pressure", "les_set_pressure_profile",
+           "les_thermo", "les_diagnostics", "les_state_bytes", "les_export_state",
+           "les_import_state", "les_steps_done", "les_destroy", "les_last_error")
 
 
 class LesConfig(C.Structure):
@@ -87,7 +88,8 @@ class LesPoissonOpts(C.Structure):
 class LesStepOpts(C.Structure):
     _fields_ = [("replay_sweeps", C.POINTER(C.c_int32)), ("records", C.POINTER(LesSolveStats)),
                 ("time_sweeps", C.c_int32), ("reserved", C.c_int32),
-                ("dump_rhs", C.c_void_p), ("dump_phi", C.c_void_p)]
+                ("dump_rhs", C.c_void_p), ("dump_phi", C.c_void_p),
+                ("dump_mean", C.POINTER(C.c_double))]
 
 
 class LesStepStats(C.Structure):
@@ -133,6 +135,14 @@ def load():
     L.les_step.argtypes = [C.c_void_p, C.c_int32, C.POINTER(LesStepOpts), C.POINTER(LesStepStats)]
     L.les_poisson_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(LesPoissonOpts),
                                     C.POINTER(LesSolveStats)]
+    L.les_pressure.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]
+    L.les_set_pressure_profile.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
+    L.les_state_bytes.argtypes = [C.c_void_p]
+    L.les_state_bytes.restype = C.c_size_t
+    L.les_export_state.argtypes = [C.c_void_p, C.c_void_p]
+    L.les_import_state.argtypes = [C.c_void_p, C.c_void_p]
+    L.les_steps_done.argtypes = [C.c_void_p]
+    L.les_steps_done.restype = C.c_int64
     L.les_thermo.argtypes = [C.c_void_p] + [C.c_void_p] * 5
     L.les_diagnostics.argtypes = [C.c_void_p, C.POINTER(LesDiag), C.POINTER(C.c_double)]
     L.les_destroy.argtypes = [C.c_void_p]
@@ -208,7 +218,10 @@ def workspace_offset(cfg: LesConfig, field) -> int:
 class LES:
     """A simulation whose state lives in torch tensors on the current GPU."""
 
-    def __init__(self, params: dict, state: dict | None = None, device="cuda"):
+    def __init__(self, params: dict, state: dict | None = None, device="cuda", pbar=None):
+        """state: initial u, v, w, thl, qt, p (numpy or torch); pbar: the FP64
+        horizontally uniform pressure that p is relative to (exact mean
+        mode; les_set_pressure_profile), default zero."""
         import torch
         self.torch = torch
         self.params = dict(params)
@@ -240,6 +253,12 @@ class LES:
         check(load().les_init(C.byref(self.cfg), C.byref(self.bufs), C.c_void_p(self.stream.cuda_stream),
                               C.byref(h)), allow_warn=False)
         self.handle = h
+        if pbar is not None:
+            pb = np.ascontiguousarray(pbar, dtype=np.float64)
+            assert pb.shape == (self.cfg.nz,)
+            check(load().les_set_pressure_profile(self.handle,
+                                                  pb.ctypes.data_as(C.POINTER(C.c_double))),
+                  allow_warn=False)
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
@@ -255,12 +274,17 @@ class LES:
     def _n(self):
         return self.cfg.nx * self.cfg.ny * self.cfg.nz
 
-    def step(self, nsteps=1, replay=None, records=False, time_sweeps=False, dump=None):
+    def step(self, nsteps=1, replay=None, records=False, time_sweeps=False, dump=None,
+             dump_mean=None):
         """Advance nsteps; returns (rc, stats dict, per-solve records or None).
 
         dump: optional (rhs, phi) device tensors of n_subiter * n elements
-        receiving the centred right-hand sides and zero-mean solutions of
-        the last step's solves (sub-iteration k at offset k * n)."""
+        receiving the right-hand sides the last step's sweeps solved and
+        their zero-mean solutions (sub-iteration k at offset k * n); with the
+        exact mean mode both lack their horizontally uniform parts, which
+        dump_mean (a float64 numpy array of n_subiter * (2 nz + 1) values)
+        receives: per solve the per-level values the centring subtracted,
+        the solution's horizontally uniform part, and the rhs mean."""
         K = self.cfg.n_subiter
         opts = LesStepOpts()
         opts.time_sweeps = 1 if time_sweeps else 0
@@ -269,6 +293,10 @@ class LES:
                 assert t.is_contiguous() and t.dtype == self.dtype and t.numel() == K * self._n()
             opts.dump_rhs = dump[0].data_ptr()
             opts.dump_phi = dump[1].data_ptr()
+        if dump_mean is not None:
+            assert dump_mean.dtype == np.float64 and dump_mean.flags.c_contiguous
+            assert dump_mean.size == K * (2 * self.cfg.nz + 1)
+            opts.dump_mean = dump_mean.ctypes.data_as(C.POINTER(C.c_double))
         rec = None
         keep = []
         if replay is not None:
@@ -286,13 +314,15 @@ class LES:
         return rc, st.as_dict(), recs
 
     def poisson_solve(self, rhs, phi=None, fixed_sweeps=0, use_guess=False):
+        """use_guess: False (zero start), True (phi holds a guess, kept) or 2
+        (phi holds a guess, gated as in the time step)."""
         torch = self.torch
         rhs = rhs.to(device=self.device, dtype=self.dtype).contiguous()
         if phi is None:
             phi = torch.zeros_like(rhs)
         assert phi.is_contiguous() and phi.dtype == self.dtype and phi.numel() == self._n()
         assert rhs.numel() == self._n()
-        opts = LesPoissonOpts(int(fixed_sweeps), 1 if use_guess else 0)
+        opts = LesPoissonOpts(int(fixed_sweeps), int(use_guess))
         st = LesSolveStats()
         rc = check(load().les_poisson_solve(self.handle, C.c_void_p(rhs.data_ptr()),
                                             C.c_void_p(phi.data_ptr()), C.byref(opts), C.byref(st)))
@@ -318,6 +348,19 @@ class LES:
         out["profiles"] = dict(zip(PROFILE_NAMES, prof))
         return out
 
+    def export_state(self):
+        """The library-held state (les_export_state) as a device uint8 tensor."""
+        n = int(load().les_state_bytes(self.handle))
+        buf = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
+        check(load().les_export_state(self.handle, C.c_void_p(buf.data_ptr())), allow_warn=False)
+        return buf
+
+    def import_state(self, buf):
+        check(load().les_import_state(self.handle, C.c_void_p(buf.data_ptr())), allow_warn=False)
+
+    def steps_done(self):
+        return int(load().les_steps_done(self.handle))
+
     def workspace_field(self, name):
         """View of an intermediate field inside the workspace (debugging)."""
         off = workspace_offset(self.cfg, name)
@@ -325,7 +368,27 @@ class LES:
         raw = self.workspace[off: off + self._n() * es]
         return raw.view(self.dtype).view(self.shape)
 
-    def state_numpy(self):
+    def pressure(self):
+        """(whole p' as a device tensor, the FP64 profile kept apart)."""
+        out = self.torch.empty_like(self.fields["p"])
+        pbar = np.zeros(self.cfg.nz)
+        check(load().les_pressure(self.handle, C.c_void_p(out.data_ptr()),
+                                  pbar.ctypes.data_as(C.POINTER(C.c_double))))
+        return out, pbar
+
+    def state_split(self):
+        """(state as float64 numpy arrays with p as stored, i.e. relative to
+        the FP64 profile, that profile): a restart keeps p in its own
+        precision and the profile in FP64."""
         self.torch.cuda.synchronize(self.device)
-        return {k: v.detach().to("cpu", dtype=self.torch.float64).numpy().copy()
-                for k, v in self.fields.items()}
+        out = {k: v.detach().to("cpu", dtype=self.torch.float64).numpy().copy()
+               for k, v in self.fields.items()}
+        return out, self.pressure()[1]
+
+    def state_numpy(self):
+        """State as float64 numpy arrays; p is the whole p' (les_pressure)."""
+        self.torch.cuda.synchronize(self.device)
+        out = {k: v.detach().to("cpu", dtype=self.torch.float64).numpy().copy()
+               for k, v in self.fields.items()}
+        out["p"] = self.pressure()[0].to("cpu", dtype=self.torch.float64).numpy()
+        return out

@@ -82,7 +82,9 @@ def test_make_config_carries_every_parameter(lib, oracle_lib):
 
 
 @pytest.mark.parametrize("override,needle", [
-    (dict(nz=3), "nz >= 4"),
+    (dict(nz=3), "4 <= nz <= 65535"),
+    (dict(nz=65536, nx=2, ny=1), "4 <= nz <= 65535"),
+    (dict(mean_mode=5), "mean mode"),
     (dict(ny=0), "nx must be >= 2, ny >= 1"),
     (dict(nx=1), "nx must be >= 2, ny >= 1"),
     (dict(wall=7), "wall condition"),

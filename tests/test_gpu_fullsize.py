@@ -87,29 +87,50 @@ def test_full_size_fp64_streamed_sweeps_match_oracle(les, oracle_lib):
     assert rel(got, ref) <= 1e-11, rel(got, ref)
 
 
-def test_full_size_solves_meet_tolerance(les, oracle_lib):
+@pytest.mark.parametrize("guess", ["zero", "previous", "learned"])
+def test_full_size_solves_meet_tolerance(les, oracle_lib, guess):
     """Recompute ||rhs - L phi|| in FP64 on the host for every solve of the
-    last of three steps (plain guess) and compare with tol ||rhs||."""
+    third step (each form from the initial state; the guessed forms' solves
+    start from the last step's solution, plus the shipped network's
+    correction) and compare with tol ||rhs||: the returned field (guess plus
+    correction as stored, with its FP64 horizontally uniform part) meets
+    the same test as the plain form's."""
     import torch
-    p = c2()
+    from paper_2301_04698_amd import cnn
+    p = c2(guess=guess)
     K = p["n_subiter"]
     n = p["nx"] * p["ny"] * p["nz"]
+    nz = p["nz"]
     shape = (p["nz"], p["ny"], p["nx"])
     sim = les.LES(p, li.initial_state(p))
+    if guess == "learned":
+        prm, meta = cnn.load_weights()
+        cnn.bind(sim, torch.from_numpy(prm).cuda(), alpha=meta["alpha"])
     sim.step(2)
     rhs = torch.empty(K * n, dtype=torch.float32, device="cuda")
     phi = torch.empty_like(rhs)
-    rc, st, recs = sim.step(1, records=True, dump=(rhs, phi))
+    dm = np.zeros(K * (2 * nz + 1))
+    rc, st, recs = sim.step(1, records=True, dump=(rhs, phi), dump_mean=dm)
     R = rhs.double().cpu().numpy().reshape(K, *shape)
     P = phi.double().cpu().numpy().reshape(K, *shape)
     for k in range(K):
-        r = R[k] - oracle_lib.laplacian(p, P[k])
-        ratio = np.linalg.norm(r) / np.linalg.norm(R[k])
-        print(f"solve {k}: {recs[k]['sweeps']} sweeps, host FP64 residual ratio {ratio:.3e}")
+        m = dm[k * (2 * nz + 1):(k + 1) * (2 * nz + 1)]
+        rsub, phibar, mean = m[:nz], m[nz:2 * nz], m[2 * nz]
+        Rk = R[k] + (rsub - mean)[:, None, None]   # the whole centred rhs
+        Pk = P[k] + phibar[:, None, None]          # the whole solution
+        r = Rk - oracle_lib.laplacian(dict(p, guess="zero"), Pk)
+        ratio = np.linalg.norm(r) / np.linalg.norm(Rk)
+        print(f"{guess} solve {k}: {recs[k]['sweeps']} sweeps, start {recs[k]['guess']}, "
+              f"host FP64 residual ratio {ratio:.3e}, reported "
+              f"{recs[k]['res_norm'] / recs[k]['rhs_norm']:.3e}")
         assert recs[k]["status"] == 0
-        # phi is stored in FP32 after the FP64 test: allow its rounding
-        assert ratio <= 1.05 * p["poisson_tol"], ratio
-        assert abs(P[k].mean()) <= 1e-6 * np.sqrt(np.mean(P[k] ** 2))
+        assert recs[k]["rhs_norm"] == pytest.approx(np.linalg.norm(Rk), rel=1e-6)
+        # the sum of the FP32 field and the FP64 profile, formed on the
+        # host, rounds differently from the device's FP64 sums: 1 %
+        assert ratio <= 1.01 * p["poisson_tol"], ratio
+        assert abs(Pk.mean()) <= 1e-6 * np.sqrt(np.mean(Pk ** 2))
+        if guess != "zero":
+            assert recs[k]["guess"] in (1, 3)
 
 
 def test_full_size_learned_guess_on_crops(les, oracle_lib):

@@ -1,0 +1,80 @@
+"""Stopping and continuing a run: the library-held state (les_export_state /
+les_import_state: the FP64 horizontally uniform pressure, the guess history,
+the step count) plus the caller's fields is the whole state, so five steps,
+an export, a new handle, an import and five more steps give the ten-step
+run bit for bit, in every guess mode and both precisions (every reduction of
+the library has a fixed order, so a run is deterministic)."""
+import numpy as np
+import pytest
+
+import les_inputs as li
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("u", "v", "w", "thl", "qt", "p")
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_04698_amd import les
+    les.load()
+    return les
+
+
+def _sim(gpu, p, state):
+    import torch
+    from paper_2301_04698_amd import cnn
+    sim = gpu.LES(p, state)
+    if p["guess"] == "learned":
+        prm, meta = cnn.load_weights()
+        cnn.bind(sim, torch.from_numpy(prm).cuda(), alpha=meta["alpha"])
+    return sim
+
+
+@pytest.mark.parametrize("precision,guess", [("fp32", "zero"), ("fp32", "extrapolate"),
+                                             ("fp32", "previous"), ("fp32", "learned"),
+                                             ("fp64", "previous")])
+def test_split_run_is_bitwise_the_whole_run(gpu, precision, guess):
+    import torch
+    p = li.workload("C1m", nx=40, ny=24, nz=32, precision=precision, poisson_scheme="chebyshev",
+                    poisson_tol=1e-6 if precision == "fp32" else 1e-9, guess=guess)
+    st0 = li.initial_state(p)
+    rng = np.random.default_rng(3)
+    for k in ("u", "v", "w"):
+        st0[k] = st0[k] + 0.3 * rng.standard_normal(st0[k].shape)
+    print(f"restart: {precision} guess {guess}", flush=True)
+    whole = _sim(gpu, p, st0)
+    whole.step(10)
+    first = _sim(gpu, p, st0)
+    first.step(5)
+    blob = first.export_state()
+    fields = {k: first.fields[k].clone() for k in FIELDS}
+    first.close()
+    second = _sim(gpu, p, fields)
+    assert second.steps_done() == 0
+    second.import_state(blob)
+    assert second.steps_done() == 5
+    second.step(5)
+    torch.cuda.synchronize()
+    for k in FIELDS:
+        assert torch.equal(whole.fields[k], second.fields[k]), k
+    _, pb_w = whole.pressure()
+    _, pb_s = second.pressure()
+    assert np.array_equal(pb_w, pb_s) and np.abs(pb_w).max() > 0
+    assert whole.steps_done() == second.steps_done() == 10
+
+
+def test_import_rejects_a_mismatched_state(gpu):
+    p = li.workload("C1", nx=16, ny=16, nz=16, precision="fp32", guess="previous")
+    a = gpu.LES(p, li.initial_state(p))
+    a.step(1)
+    blob = a.export_state()
+    for other in (dict(p, guess="zero"), dict(p, nz=20), dict(p, precision="fp64")):
+        b = gpu.LES(other, li.initial_state(other))
+        with pytest.raises(gpu.LesError):
+            b.import_state(blob)
+        b.close()
+    a.close()

@@ -14,7 +14,10 @@ FP64 CPU oracle timed on the host on a bounded sample.  `value` is the plain
 form (every solve starts from zero).  The learned form (each solve starts
 from the previous step's solution corrected by the trained guess network,
 whose inference time counts in the Poisson seconds) runs the same steps
-from the same initial state and is reported under "learned".
+from the same initial state and is reported under "learned".  The largest
+single-GPU domain, 1024 x 1024 x 256, is reported under "c5": both forms'
+Mcell-steps/s, Poisson seconds and sweeps per step from one state after a
+few warm-up steps, and the streamed sweep's HBM GB/s.
 """
 from __future__ import annotations
 
@@ -60,6 +63,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-timings", action="store_true",
+                    help="only time the oracle on the host (the benchmark runs this in a child "
+                         "process) and print one JSON line")
     ap.add_argument("--cpu-crop", type=int, default=128,
                     help="horizontal size of the crop the oracle's non-Poisson work is timed on")
     ap.add_argument("--mode", choices=("step", "sweeps", "copy"), default="step",
@@ -72,6 +78,12 @@ def parse():
     ap.add_argument("--guess-weights", default=GUESS_WEIGHTS,
                     help="trained guess network for the learned form ('' to skip it)")
     ap.add_argument("--guess-alpha", type=float, default=0.1)
+    ap.add_argument("--c5-warmup", type=int, default=2,
+                    help="largest-domain leg (1024x1024x256): untimed steps from the initial "
+                         "state (learned form; its first step starts from zero)")
+    ap.add_argument("--c5-steps", type=int, default=1,
+                    help="largest-domain leg: timed steps of each form from the same state "
+                         "(0 skips the leg)")
     ap.add_argument("--advection", choices=("quick", "weno3"), default="quick",
                     help="face-value scheme of the advection (QUICK, or third-order WENO with a "
                          "Lax-Friedrichs flux)")
@@ -182,6 +194,70 @@ def cpu_baseline(p, sweeps_per_step, crop):
     }
 
 
+def oracle_timings():
+    """The oracle (serial FP64 C, one thread) timed on the host: all ten steps
+    of the 32^3 workload, one step of the 64^3 companion of the 512x512x256
+    workload, and the per-sweep cell-update rate of its Poisson sweep at the
+    size of every workload (the difference of a 3-sweep and a 1-sweep solve,
+    so the per-solve setup cancels).  Runs in a child process that never
+    touches the GPU; prints one JSON line."""
+    import les_inputs as li
+    import oracle
+    out = {}
+    p = li.workload("C1")
+    st = li.initial_state(p)
+    t0 = time.perf_counter()
+    recs, _ = oracle.step(p, st, nsteps=10)
+    t = time.perf_counter() - t0
+    out["c1_ten_steps"] = {"seconds": t, "sweeps": sum(r["sweeps"] for r in recs),
+                           "mcell_steps_per_s": p["nx"] * p["ny"] * p["nz"] * 10 / t / 1e6}
+    p = li.workload("C3s")
+    st = li.initial_state(p)
+    t0 = time.perf_counter()
+    recs, _ = oracle.step(p, st, nsteps=1)
+    t = time.perf_counter() - t0
+    out["c3_companion_64cubed_step"] = {"seconds": t, "sweeps": sum(r["sweeps"] for r in recs),
+                                        "mcell_steps_per_s": 64 ** 3 / t / 1e6}
+    # per-sweep rate: (t(1 + m sweeps) - t(1 sweep)) / m; a sweep's cost does
+    # not depend on the values, so the large grids take one seeded plane
+    # repeated over the levels; sizes beyond the time budget are skipped
+    import numpy as np
+    rates = {}
+    t_start = time.perf_counter()
+    for name, m in (("C1", 200), ("C2", 10), ("C3", 4), ("C5", 2)):
+        p = li.workload(name)
+        key = f"{p['nx']}x{p['ny']}x{p['nz']}"
+        if time.perf_counter() - t_start > 150:
+            rates[key] = "skipped (time budget)"
+            continue
+        plane = li.random_field((1, p["ny"], p["nx"]), seed=3)
+        rhs = np.ascontiguousarray(np.broadcast_to(plane, (p["nz"], p["ny"], p["nx"])))
+        ts = []
+        for nsw in (1, 1 + m):
+            t0 = time.perf_counter()
+            oracle.poisson(p, rhs, fixed_sweeps=nsw)
+            ts.append(time.perf_counter() - t0)
+        per = (ts[1] - ts[0]) / m
+        rates[key] = {"s_per_sweep": per, "sweeps_timed": m, "one_sweep_solve_s": ts[0],
+                      "mcell_updates_per_s": rhs.size / per / 1e6 if per > 0 else None}
+        del rhs
+    out["sweep_rates"] = rates
+    print(json.dumps(out), flush=True)
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count()}
+
+
 def learned_form(p, args, plain_sweeps, plain_poisson, plain_value):
     """The same steps from the same initial state with the learned guess."""
     import numpy as np
@@ -227,13 +303,131 @@ def learned_form(p, args, plain_sweeps, plain_poisson, plain_value):
     }
 
 
+def progress(msg):
+    """Progress of a long run on stderr (the JSON line stays alone on stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def largest_domain(args):
+    """The largest single-GPU domain, 1024 x 1024 x 256 (268 M cells, FP32,
+    the sweep's arrays far beyond the Infinity Cache): args.c5_warmup
+    untimed steps from the initial state with the learned form (the first
+    of them starts every solve from zero), then args.c5_steps timed steps of
+    the learned form and, from the same state (fields and the FP64 pressure
+    profile copied on the device), of the plain form."""
+    import numpy as np
+    import torch
+
+    import les_inputs as li
+    from paper_2301_04698_amd import cnn, les
+
+    p = li.workload("C5")
+    ncell = p["nx"] * p["ny"] * p["nz"]
+    K = p["n_subiter"]
+    T = args.c5_steps
+    prm = torch.from_numpy(np.load(args.guess_weights))
+
+    def timed(sim):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st, recs = sim.step(T, records=True, time_sweeps=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if rc not in (les.LES_OK, les.LES_WARN_NOT_CONVERGED):
+            raise SystemExit(f"les_step (1024x1024x256) failed: {rc}")
+        return {
+            "value": ncell * T / wall / 1e6,
+            "unit": "Mcell-steps/s",
+            "ms_per_step": wall / T * 1e3,
+            "poisson_s_per_step": st["poisson_seconds"] / T,
+            "sweeps_per_step": st["sweeps_total"] / T,
+            "sweeps_per_solve": [r["sweeps"] for r in recs],
+            "starts": [r["guess"] for r in recs],
+            "not_converged": st["not_converged"],
+            "res_rel_max": st["res_rel_max"],
+        }, st
+
+    t0 = time.perf_counter()
+    sim = les.LES(dict(p, guess="learned"), li.initial_state(p), device="cuda:0")
+    cnn.bind(sim, prm, args.guess_alpha)
+    t_init = time.perf_counter() - t0
+    progress(f"1024x1024x256: set up in {t_init:.0f} s")
+    t0 = time.perf_counter()
+    for w in range(args.c5_warmup):
+        _, st, recs = sim.step(1, records=True)
+        progress(f"1024x1024x256: warm-up step {w + 1}/{args.c5_warmup}, "
+                 f"{st['sweeps_total']} sweeps, {st['seconds']:.1f} s, solves "
+                 f"{[(r['sweeps'], r['guess']) for r in recs]}")
+    torch.cuda.synchronize()
+    t_warm = time.perf_counter() - t0
+    snap = {k: v.clone() for k, v in sim.fields.items()}
+    _, pbar = sim.pressure()
+    learned, _ = timed(sim)
+    progress(f"1024x1024x256: learned form {learned['ms_per_step'] / 1e3:.1f} s/step, solves "
+             f"{learned['sweeps_per_solve']} sweeps, starts {learned['starts']}")
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    sim = les.LES(p, snap, device="cuda:0", pbar=pbar)
+    del snap
+    plain, st = timed(sim)
+    progress(f"1024x1024x256: plain form {plain['ms_per_step'] / 1e3:.1f} s/step, solves "
+             f"{plain['sweeps_per_solve']} sweeps")
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    S = 1
+    avg = st["sweep_seconds"] / max(st["sweeps_timed"], 1)
+    bytes_launch = sweep_bytes_per_cell(p) * ncell
+    achieved = bytes_launch / avg / 1e9
+    learned["speedup"] = learned["value"] / plain["value"]
+    learned["poisson_speedup"] = plain["poisson_s_per_step"] / learned["poisson_s_per_step"]
+    learned["iterations_saved_per_step"] = plain["sweeps_per_step"] - learned["sweeps_per_step"]
+    return {
+        "workload": (f"synthetic stratocumulus LES step, {p['nx']}x{p['ny']}x{p['nz']} cells, "
+                     f"{p['dx']:g}x{p['dy']:g}x{p['dz']:g} m, dt {p['dt']:g} s, "
+                     f"{p['poisson_scheme']} Poisson to rel. residual {p['poisson_tol']:g}, K={K}"),
+        "grid": [p["nx"], p["ny"], p["nz"]],
+        "warmup": args.c5_warmup,
+        "steps": T,
+        "note": (f"{args.c5_warmup} untimed steps from the initial state (learned form, first "
+                 f"step from zero; {t_warm:.0f} s), then {T} timed step(s) of each form from that "
+                 f"state; setup {t_init:.0f} s"),
+        "plain": plain,
+        "learned": learned,
+        "sweep": {
+            "bound": "hbm",
+            "kernel": sweep_kernel_name(p, S),
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "avg_launch_us": avg * 1e6,
+            "bytes_per_launch": bytes_launch,
+            "note": ("plain sweeps between residual checks, HIP events on the library's stream; "
+                     "arrays of 4.3 GB per sweep, beyond the 256 MB Infinity Cache"),
+        },
+    }
+
+
 def main():
     args = parse()
+    if args.oracle_timings:
+        return oracle_timings()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the library's LES step runs on a single "
               "MI355X and has no multi-GPU decomposition; use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
+
+    # The oracle's own timings run on the host beside the GPU legs, started
+    # before anything initialises the GPU (a child of a GPU process must not
+    # exec).
+    timings = None
+    if not args.no_cpu_baseline and args.mode == "step":
+        import subprocess
+        timings = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-timings"],
+                                   stdout=subprocess.PIPE, text=True)
 
     import numpy as np
     import torch
@@ -325,6 +519,7 @@ def main():
                      + " the 256 MB Infinity Cache"),
         },
     }
+    progress(f"{p['nx']}x{p['ny']}x{p['nz']}: plain form {value:.1f} Mcell-steps/s")
     if p["init"] != "cloud_layer":
         out["learned"] = None  # the guess network was trained on the cloud-layer workload
     elif args.guess_weights and os.path.exists(args.guess_weights):
@@ -332,8 +527,22 @@ def main():
                                       value)
     else:
         out["learned"] = None
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    if (args.c5_steps > 0 and args.workload == "C2" and args.guess_weights
+            and os.path.exists(args.guess_weights)):
+        out["c5"] = largest_domain(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, sweeps_step, args.cpu_crop)
+        out["cpu_baseline"]["host"] = host_cpu()
+        if timings is not None:
+            try:
+                so, _ = timings.communicate(timeout=300)
+                out["cpu_baseline"]["oracle_timings"] = json.loads(so.strip().splitlines()[-1])
+            except Exception as e:  # report, never fail the benchmark for it
+                timings.kill()
+                out["cpu_baseline"]["oracle_timings"] = {"error": repr(e)}
     print(json.dumps(out), flush=True)
 
 

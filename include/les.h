@@ -156,7 +156,9 @@ typedef struct les_solve_stats {
   int32_t guess;      /* les_step: 0 started from zero, 1 from its guess,
                          2 its guess was rejected (residual not below the
                          zero start's) and it started from zero, 3 its kept
-                         guess reached the cap or its returned iterate
+                         guess reached the cap, or its budget (the sweeps
+                         of the last solve of the same sub-iteration that
+                         ran from the zero start), or its returned iterate
                          missed the tolerance, and the sweeps were repeated
                          from the zero start (sweeps and seconds count both
                          passes); les_poisson_solve: opts->use_guess.
@@ -164,7 +166,7 @@ typedef struct les_solve_stats {
                          exact horizontally uniform part.  For a kept guess
                          res_norm is the residual of the returned iterate
                          (guess plus correction, as stored) */
-  int32_t reserved;
+  int32_t guess_sweeps; /* guess 3: the sweeps of the dropped guess's pass */
 } les_solve_stats;
 
 typedef struct les_poisson_opts {
@@ -173,6 +175,11 @@ typedef struct les_poisson_opts {
                             guess, always kept; 2: phi holds a guess, kept
                             and repeated as les_step does (see
                             les_solve_stats.guess) */
+  int32_t budget;        /* use_guess 2: > 0 ends a kept guess's sweeps at
+                            the first residual check at or beyond this many
+                            sweeps, then repeats from the zero start (les_step
+                            passes the sweeps of the last zero-start solve of
+                            the same sub-iteration); 0 none */
 } les_poisson_opts;
 
 /* Optional per-call controls of les_step. */

@@ -86,6 +86,14 @@ int les_cnn_loss(const les_cnn_dims *d, double dx, double dy, double dz, const f
 int les_cnn_backward(const les_cnn_dims *d, const uint16_t *packed, void *work,
                      const float *gout, float *grad, void *stream);
 
+/* The input of layer `layer` (0..3) kept in work by the last
+ * les_cnn_forward with these dims (bfloat16 values, written as FP32) in the
+ * order (batch, channels, nz, ny_l, nx_l), ny_l = ny - 2 layer on valid
+ * crops (ny on periodic fields), nx_l alike: for inspection and for
+ * checking the backward pass on the very operands it used. */
+int les_cnn_stored_input(const les_cnn_dims *d, const void *work, int32_t layer, float *out,
+                         void *stream);
+
 /* One Adam step (Kingma & Ba 2015, bias-corrected, step >= 1) on FP32
  * params with FP32 moments m, v. */
 int les_cnn_adam(int32_t n, float *params, const float *grad, float *m, float *v, int32_t step,

@@ -239,14 +239,16 @@ def initial_state(p: dict) -> dict:
     thl = np.where(above, p["thl_ml"] + p["dthl_inv"]
                    + np.cbrt(np.maximum(z - p["z_inv"], 0.0)), p["thl_ml"])
     qt = np.where(above, p["qt_ft"], p["qt_ml"])
-    idx = np.arange(nx * ny * nz, dtype=np.uint64).reshape(nz, ny, nx)
-    low = z < p["noise_z"]
-    if p["noise_thl"] > 0:
+    # noise on the levels below noise_z only (the counter is the cell index,
+    # so drawing it level by level gives the same values)
+    nlow = int(np.count_nonzero(cell_heights(p) < p["noise_z"]))
+    idx = np.arange(nx * ny * nlow, dtype=np.uint64).reshape(nlow, ny, nx)
+    if p["noise_thl"] > 0 and nlow:
         r = uniform01(p["seed"], FIELD_THL, idx)
-        thl = thl + np.where(low, p["noise_thl"] * (2.0 * r - 1.0), 0.0)
-    if p["noise_qt"] > 0:
+        thl[:nlow] = thl[:nlow] + p["noise_thl"] * (2.0 * r - 1.0)
+    if p["noise_qt"] > 0 and nlow:
         r = uniform01(p["seed"], FIELD_QT, idx)
-        qt = qt + np.where(low, p["noise_qt"] * (2.0 * r - 1.0), 0.0)
+        qt[:nlow] = qt[:nlow] + p["noise_qt"] * (2.0 * r - 1.0)
     return dict(
         u=np.full(shape, p["ug"]),
         v=np.full(shape, p["vg"]),

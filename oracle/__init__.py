@@ -50,7 +50,7 @@ class OCfg(C.Structure):
 class OSolve(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("status", C.c_int32),
                 ("rhs_norm", C.c_double), ("res_norm", C.c_double),
-                ("guess", C.c_int32), ("reserved", C.c_int32)]
+                ("guess", C.c_int32), ("guess_sweeps", C.c_int32)]
 
 
 class ODebug(C.Structure):
@@ -89,7 +89,7 @@ def _bind(L):
     L.oracle_divergence.argtypes = [cfgp, _DP, _DP, _DP, _DP]
     L.oracle_radiation.argtypes = [cfgp, _DP, _DP, _DP]
     L.oracle_poisson.argtypes = [cfgp, _DP, _DP, C.c_int32, C.POINTER(OSolve)]
-    L.oracle_poisson_gated.argtypes = [cfgp, _DP, _DP, C.c_int32, C.POINTER(OSolve)]
+    L.oracle_poisson_gated.argtypes = [cfgp, _DP, _DP, C.c_int32, C.c_int32, C.POINTER(OSolve)]
     L.oracle_jacobi_bounds.argtypes = [cfgp, _DP, _DP]
     L.oracle_step.argtypes = [cfgp, _DP, _DP, _DP, _DP, _DP, _DP, C.c_int32,
                               C.POINTER(C.c_int32), C.POINTER(OSolve), C.POINTER(ODebug)]
@@ -294,19 +294,24 @@ def jacobi_bounds(p):
     return a.value, b.value
 
 
-def poisson(p, rhs, guess=None, fixed_sweeps=0, gated=False):
+def poisson(p, rhs, guess=None, fixed_sweeps=0, gated=False, budget=0):
     """Returns (phi, stats dict).  gated: the solve as the time step runs it
     for a guess (kept only if it starts closer than the zero start, solved
-    again from the zero start if its sweeps reach the cap)."""
+    again from the zero start if its sweeps reach the cap or, budget > 0,
+    that many sweeps)."""
     rhs = _f64(rhs)
     phi = np.zeros(_shape(p)) if guess is None else _f64(guess).copy()
     st = OSolve()
-    fn = lib().oracle_poisson_gated if gated else lib().oracle_poisson
-    rc = fn(C.byref(make_cfg(p)), _ptr(rhs), _ptr(phi), int(fixed_sweeps), C.byref(st))
+    if gated:
+        rc = lib().oracle_poisson_gated(C.byref(make_cfg(p)), _ptr(rhs), _ptr(phi),
+                                        int(fixed_sweeps), int(budget), C.byref(st))
+    else:
+        rc = lib().oracle_poisson(C.byref(make_cfg(p)), _ptr(rhs), _ptr(phi), int(fixed_sweeps),
+                                  C.byref(st))
     if rc not in (0, -3):
         raise RuntimeError(f"oracle poisson failed with code {rc}")
     return phi, dict(sweeps=st.sweeps, status=st.status, rhs_norm=st.rhs_norm, res_norm=st.res_norm,
-                     guess=st.guess)
+                     guess=st.guess, guess_sweeps=st.guess_sweeps)
 
 
 DEBUG_FIELDS = ("b_half", "nu", "rhs", "phi", "uhat", "vhat", "what")
@@ -338,7 +343,7 @@ def step(p, state, nsteps=1, replay=None, debug=False):
     rc = lib().oracle_step(C.byref(c), *[_ptr(a) for a in arrs], int(nsteps), rp, rec,
                            C.byref(dbg) if dbg is not None else None)
     recs = [dict(sweeps=r.sweeps, status=r.status, rhs_norm=r.rhs_norm, res_norm=r.res_norm,
-                 guess=r.guess) for r in rec]
+                 guess=r.guess, guess_sweeps=r.guess_sweeps) for r in rec]
     if rc != 0:
         raise RuntimeError(f"oracle step failed with code {rc}; solves: {recs}")
     return recs, dbg_arrays

@@ -754,9 +754,12 @@ static int jacobi_sweeps(const ocfg *c, const double *rhs, double rn, double *ph
  * horizontal means per level are removed first, as that part is already
  * exact).  gate = 1: the guess is kept only if its residual is below the
  * zero start's, and a kept guess whose sweeps reach the cap (no fixed
- * count) is dropped and the sweeps repeated from the zero start. */
+ * count) is dropped and the sweeps repeated from the zero start.  budget >
+ * 0 (no fixed count): a kept guess's sweeps stop at the first residual
+ * check at or beyond `budget` sweeps, counting as reaching the cap (a
+ * guess that needs more sweeps than the zero start did is no use). */
 static int poisson_solve(const ocfg *c, const double *rhs_in, double *phi, int32_t fixed_sweeps,
-                         int gate, osolve *st) {
+                         int gate, int budget, osolve *st) {
   if (check_cfg(c)) return -1;
   size_t n = ncell(c), nxy = (size_t)c->nx * c->ny;
   double *rhs = malloc(n * sizeof(double));
@@ -793,14 +796,20 @@ static int poisson_solve(const ocfg *c, const double *rhs_in, double *phi, int32
       guessed = 2;
     }
   }
-  int m = 0, status = 0;
+  int m = 0, status = 0, first = 0;
   double rr = 0.0;
   if (rn > 0.0) {
-    status = jacobi_sweeps(c, rhs, rn, phi, fixed_sweeps, tmp, prev, &m, &rr);
+    ocfg cb = *c; /* a kept guess's sweeps end at the first check from `budget` on */
+    if (guessed == 1 && fixed_sweeps == 0 && budget > 0) {
+      int b = (budget + c->poisson_check_every - 1) / c->poisson_check_every * c->poisson_check_every;
+      if (b < cb.poisson_max_sweeps) cb.poisson_max_sweeps = b;
+    }
+    status = jacobi_sweeps(&cb, rhs, rn, phi, fixed_sweeps, tmp, prev, &m, &rr);
     if (status == 1 && guessed == 1 && fixed_sweeps == 0) {
       int m2 = 0;
       memcpy(phi, zero, n * sizeof(double));
       status = jacobi_sweeps(c, rhs, rn, phi, 0, tmp, prev, &m2, &rr);
+      first = m;
       m += m2;
       guessed = 3;
     }
@@ -813,7 +822,7 @@ static int poisson_solve(const ocfg *c, const double *rhs_in, double *phi, int32
     st->rhs_norm = rn;
     st->res_norm = rr;
     st->guess = guessed;
-    st->reserved = 0;
+    st->guess_sweeps = first;
   }
   free(rhs); free(tmp); free(prev); free(zero); free(rb); free(pb); free(gb);
   return status < 0 ? status : 0;
@@ -821,12 +830,12 @@ static int poisson_solve(const ocfg *c, const double *rhs_in, double *phi, int32
 
 int oracle_poisson(const ocfg *c, const double *rhs_in, double *phi, int32_t fixed_sweeps,
                    osolve *st) {
-  return poisson_solve(c, rhs_in, phi, fixed_sweeps, 0, st);
+  return poisson_solve(c, rhs_in, phi, fixed_sweeps, 0, 0, st);
 }
 
 int oracle_poisson_gated(const ocfg *c, const double *rhs_in, double *phi, int32_t fixed_sweeps,
-                         osolve *st) {
-  return poisson_solve(c, rhs_in, phi, fixed_sweeps, 1, st);
+                         int32_t budget, osolve *st) {
+  return poisson_solve(c, rhs_in, phi, fixed_sweeps, 1, budget, st);
 }
 
 /* ---------------------------------------------------------- time step */
@@ -888,6 +897,10 @@ int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, dou
   /* guess memory: the previous step's pressure, or one solution per sub-iteration */
   size_t nhist = c->guess == 1 ? n : c->guess == 2 ? (size_t)c->n_subiter * n : 0;
   double *hist = nhist ? calloc(nhist, sizeof(double)) : NULL;
+  /* sweeps of the last solve of each sub-iteration that ran from the zero
+     start: the budget of a kept guess (0: none yet) */
+  int *zero_sweeps = calloc(c->n_subiter, sizeof(int));
+  if (!zero_sweeps) { free(hist); ostate_free(&S); prof_free(&P); return -1; }
   if (nhist && !hist) { ostate_free(&S); prof_free(&P); return -1; }
   if (c->guess == 1) memcpy(hist, p, n * sizeof(double));
   double *vel[3] = {u, v, w};
@@ -998,7 +1011,9 @@ int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, dou
       }
       osolve st;
       int fixed = replay ? replay[solve] : 0;
-      rc = poisson_solve(c, S.rhs, S.phi, fixed, guessed, &st);
+      rc = poisson_solve(c, S.rhs, S.phi, fixed, guessed, zero_sweeps[it], &st);
+      if (st.guess == 0 || st.guess == 2) zero_sweeps[it] = st.sweeps;
+      else if (st.guess == 3) zero_sweeps[it] = st.sweeps - st.guess_sweeps;
       if (rec) rec[solve] = st;
       ++solve;
       if (rc) break;
@@ -1037,6 +1052,7 @@ int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, dou
             uh[a][q] = S.Uhat[a][q] / P.rho0[k];
   }
   free(hist);
+  free(zero_sweeps);
   ostate_free(&S);
   prof_free(&P);
   return rc;

@@ -47,9 +47,9 @@ typedef struct osolve {        /* one Poisson solve */
   double rhs_norm;             /* ||rhs||_2 after mean removal */
   double res_norm;             /* ||rhs - L phi||_2 of the returned iterate */
   int32_t guess;               /* oracle_step: 0 zero start, 1 guess kept, 2 rejected,
-                                  3 kept but the cap was reached, solved again from
-                                  the zero start (sweeps count both passes) */
-  int32_t reserved;
+                                  3 kept but the cap or its budget was reached, solved
+                                  again from the zero start (sweeps count both passes) */
+  int32_t guess_sweeps;        /* guess 3: sweeps of the dropped guess's pass */
 } osolve;
 
 /* Reference state (Sec. 2.1): p0, T0, rho0, alpha0 at cell centres. */
@@ -97,10 +97,11 @@ int oracle_poisson(const ocfg *c, const double *rhs, double *phi, int32_t fixed_
                    osolve *st);
 /* The same solve as the time step runs it for a guess: the guess is kept
  * only if its residual is below the zero start's, and a kept guess whose
- * sweeps reach the cap (no fixed count) is dropped and the sweeps repeated
- * from the zero start; st->guess as in oracle_step's records. */
+ * sweeps reach the cap, or (budget > 0) the first residual check at or
+ * beyond `budget` sweeps, is dropped and the sweeps repeated from the zero
+ * start (no fixed count); st->guess as in oracle_step's records. */
 int oracle_poisson_gated(const ocfg *c, const double *rhs, double *phi, int32_t fixed_sweeps,
-                         osolve *st);
+                         int32_t budget, osolve *st);
 /* Closed-form extreme eigenvalues of -D^{-1} L on zero-mean fields. */
 int oracle_jacobi_bounds(const ocfg *c, double *mu_min, double *mu_max);
 
@@ -124,8 +125,10 @@ typedef struct odebug {
  * A guess is kept only if ||rhs - L phi_0||_2 is below the residual of the
  * zero start (rhs with its mean removed; with mean_mode = 1, rhs minus its
  * horizontal mean per level); otherwise the solve starts from the zero
- * start.  A kept guess whose solve reaches the sweep cap is dropped and the
- * solve repeated from the zero start (not with replayed sweep counts).
+ * start.  A kept guess whose solve reaches the sweep cap, or needs more
+ * sweeps than the last solve of the same sub-iteration that ran from the
+ * zero start (its budget), is dropped and the solve repeated from the zero
+ * start (not with replayed sweep counts).
  * The guess changes the sweep count only: the stopping test is relative to
  * ||rhs||, whatever the starting iterate. */
 int oracle_step(const ocfg *c, double *u, double *v, double *w, double *thl, double *qt,

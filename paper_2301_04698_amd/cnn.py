@@ -13,7 +13,8 @@ import os
 from . import les
 
 EXPORTS = ("les_cnn_param_count", "les_cnn_work_bytes", "les_cnn_pack", "les_cnn_forward",
-           "les_cnn_loss", "les_cnn_backward", "les_cnn_adam", "les_cnn_train_step",
+           "les_cnn_loss", "les_cnn_backward", "les_cnn_stored_input", "les_cnn_adam",
+           "les_cnn_train_step",
            "les_cnn_pair_scratch_bytes", "les_cnn_pair", "les_cnn_pair_noalloc",
            "les_cnn_gather", "les_bind_cnn",
            "les_cnn_guess")
@@ -45,6 +46,7 @@ def lib():
         L.les_cnn_loss.argtypes = [_dp, C.c_double, C.c_double, C.c_double, _vp, _vp, _vp, _vp,
                                    C.POINTER(C.c_double), _vp]
         L.les_cnn_backward.argtypes = [_dp, _vp, _vp, _vp, _vp, _vp]
+        L.les_cnn_stored_input.argtypes = [_dp, _vp, C.c_int32, _vp, _vp]
         L.les_cnn_adam.argtypes = [C.c_int32, _vp, _vp, _vp, _vp, C.c_int32, C.c_double,
                                    C.c_double, C.c_double, C.c_double, _vp]
         L.les_cnn_train_step.argtypes = [_dp, C.c_double, C.c_double, C.c_double, _vp, _vp, _vp,
@@ -172,6 +174,19 @@ def backward(x_shape, packed, work, gout, alpha=0.1):
     les.check(lib().les_cnn_backward(C.byref(d), _ptr(packed), _ptr(work), _ptr(_f32(gout)),
                                      _ptr(grad), _stream()))
     return grad
+
+
+def stored_input(x_shape, work, layer, periodic=False, alpha=0.1):
+    """Layer `layer`'s input kept in work by the last forward, as a float32
+    tensor (batch, channels, nz, ny_l, nx_l)."""
+    import torch
+    d = dims(x_shape, periodic=periodic, alpha=alpha)
+    b, nz, ny, nx = x_shape
+    t = 0 if periodic else 2 * layer
+    out = torch.empty((b, CIN[layer], nz, ny - t, nx - t), dtype=torch.float32,
+                      device=work.device)
+    les.check(lib().les_cnn_stored_input(C.byref(d), _ptr(work), int(layer), _ptr(out), _stream()))
+    return out
 
 
 def adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -187,6 +187,19 @@ int les_cnn_backward(const les_cnn_dims *d, const uint16_t *packed, void *work,
   return backward_impl(d, packed, work, gout, grad, (hipStream_t)stream);
 }
 
+int les_cnn_stored_input(const les_cnn_dims *d, const void *work, int32_t layer, float *out,
+                         void *stream) {
+  if (int rc = check_dims(d)) return rc;
+  if (layer < 0 || layer >= kCnnLayers) return fail(LES_ERR_ARG, "layer %d out of range", layer);
+  if (!work || !out) return fail(LES_ERR_ARG, "NULL argument");
+  const Work W = work_layout(d);
+  const CnnGeom G = cnn_geom(d->batch, d->nz, d->ny, d->nx, d->periodic, layer);
+  launch_cnn_unpack(G, cnn_cin(layer), at<uint16_t>(const_cast<void *>(work), W.a[layer]), out,
+                    (hipStream_t)stream);
+  LAUNCH_TRY();
+  return LES_OK;
+}
+
 int les_cnn_adam(int32_t n, float *params, const float *grad, float *m, float *v, int32_t step,
                  double lr, double beta1, double beta2, double eps, void *stream) {
   if (n < 0 || step < 1 || !params || !grad || !m || !v)

@@ -74,6 +74,10 @@ void launch_cnn_dgrad(int layer, const CnnGeom &G, const float *gy, const uint16
 void launch_cnn_wgrad(int layer, const CnnGeom &G, const float *gy, const uint16_t *ain,
                       double *partials, float *grad, hipStream_t s);
 
+// Stored input of a layer of geometry G (C channels, channels-last
+// bfloat16) as FP32 in (batch, C, nz, nyi, nxi) order.
+void launch_cnn_unpack(const CnnGeom &G, int C, const uint16_t *a, float *out, hipStream_t s);
+
 void launch_cnn_adam(int n, float *params, const float *grad, float *m, float *v, int step,
                      double lr, double beta1, double beta2, double eps, hipStream_t s);
 

@@ -623,6 +623,19 @@ __global__ __launch_bounds__(kBlock) void pair_kernel(int64_t n, const float *__
   t[q] = (float)(((double)phi[q] - (base ? (double)base[q] : 0.0)) * d * inv);
 }
 
+// Stored layer input (channels-last bfloat16, C channels, `cells` cells per
+// batch entry) to FP32 in (batch, C, cells) order.
+__global__ __launch_bounds__(kBlock) void unpack_kernel(int64_t n, int C, int64_t cells,
+                                                        const uint16_t *__restrict__ a,
+                                                        float *__restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // input order
+  if (q >= n) return;
+  const int c = (int)(q % C);
+  const int64_t cell = q / C;
+  const int64_t b = cell / cells, r = cell - b * cells;
+  out[(b * C + c) * cells + r] = bf2f(a[q]);
+}
+
 // As pair_kernel with the residual r already in x: x = x/s in place.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void pair_inplace_kernel(int64_t n, const T *__restrict__ phi,
@@ -769,6 +782,11 @@ template <typename T>
 void launch_cnn_pair(const Grid &g, const float *r, const T *phi, const T *base, const double *sc,
                      double d, float *x, float *t, hipStream_t s) {
   pair_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g.n, r, phi, base, sc, d, x, t);
+}
+
+void launch_cnn_unpack(const CnnGeom &G, int C, const uint16_t *a, float *out, hipStream_t s) {
+  const int64_t n = G.n_in * C;
+  unpack_kernel<<<blocks_for(n), kBlock, 0, s>>>(n, C, (int64_t)G.nz * G.nyi * G.nxi, a, out);
 }
 
 template <typename T>

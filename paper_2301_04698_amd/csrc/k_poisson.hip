@@ -420,8 +420,9 @@ __global__ __launch_bounds__(kBlock) void zero_kernel(int64_t n, T *__restrict__
 
 // A second pass of sweeps on the same right-hand side (the zero start after
 // a kept guess reached the cap): the reference norm and tolerance stay.
-__global__ void ctl_restart_kernel(SolveCtl *ctl) {
+__global__ void ctl_restart_kernel(SolveCtl *ctl, int max_sweeps) {
   if (threadIdx.x != 0) return;
+  ctl->max_sweeps = max_sweeps;
   ctl->done = 0;
   ctl->stop_m = -1;
   ctl->res_norm2 = 0.0;
@@ -498,7 +499,17 @@ void launch_rhs_center(const Grid &g, const T *rhs_in, T *rhs_out, T *phi0, cons
                                                      partials);
 }
 
-void launch_ctl_restart(SolveCtl *ctl, hipStream_t s) { ctl_restart_kernel<<<1, 64, 0, s>>>(ctl); }
+void launch_ctl_restart(SolveCtl *ctl, int max_sweeps, hipStream_t s) {
+  ctl_restart_kernel<<<1, 64, 0, s>>>(ctl, max_sweeps);
+}
+
+__global__ void ctl_limit_kernel(SolveCtl *ctl, int max_sweeps) {
+  if (threadIdx.x == 0) ctl->max_sweeps = max_sweeps;
+}
+
+void launch_ctl_limit(SolveCtl *ctl, int max_sweeps, hipStream_t s) {
+  ctl_limit_kernel<<<1, 64, 0, s>>>(ctl, max_sweeps);
+}
 
 template <typename T>
 void launch_zero(const Grid &g, T *f, hipStream_t s) {

@@ -171,6 +171,8 @@ struct les_handle {
   std::vector<hipEvent_t> ev_sweep;  // pool bracketing runs of plain sweeps
   bool broken;
   std::vector<char> hist_valid;  // per sub-iteration: history holds a solution
+  std::vector<int32_t> zero_sweeps;  // per sub-iteration: sweeps of its last pass from the
+                                     // zero start (a kept guess's budget; 0 none yet)
   bool cnn_bound;                // learned guess: parameters bound
   float cnn_alpha;               // its leaky ReLU slope
   int64_t steps_done;            // time steps taken since les_init (or the imported count)
@@ -364,15 +366,16 @@ int prepare_guess(les_handle *h, View<T> &V, const T *guess, bool always_keep) {
 
 // Sweeps on L phi = rhs from zero until the device-side residual test
 // (relative to the reference norm in the control block) stops them, the cap
-// or exactly `fixed` sweeps.  *result: the buffer holding the returned
+// (`cap` if > 0, which the control block must hold too, else the
+// configuration's) or exactly `fixed` sweeps.  *result: the buffer holding the returned
 // iterate; *out: the control block as it ended (the stream is synchronized).
 template <typename T>
-int run_sweeps(les_handle *h, View<T> &V, const T *rhs, int fixed, SolveCtl *out, T **result,
-               SweepTiming *timing) {
+int run_sweeps(les_handle *h, View<T> &V, const T *rhs, int fixed, int cap, SolveCtl *out,
+               T **result, SweepTiming *timing) {
   const les_config &c = h->cfg;
   const Grid &g = h->grid;
   hipStream_t s = h->stream;
-  const int max_sweeps = fixed > 0 ? fixed : c.poisson_max_sweeps;
+  const int max_sweeps = fixed > 0 ? fixed : (cap > 0 ? cap : c.poisson_max_sweeps);
   const int every = c.poisson_check_every;
   const bool cheb = c.poisson_scheme == LES_CHEBYSHEV;
   const double gamma = 2.0 / (h->mu_min + h->mu_max);
@@ -565,20 +568,36 @@ int run_sweeps(les_handle *h, View<T> &V, const T *rhs, int fixed, SolveCtl *out
 // A whole solve after prepare_rhs (and prepare_guess if `guess`): the
 // sweeps, then for a kept guess phi = guess - gbar + correction and the FP64
 // residual of that returned iterate.  gated: a kept guess whose solve
-// reaches the cap, or whose returned iterate misses the tolerance, is
+// reaches the cap, or (budget > 0) the first residual check at or beyond
+// `budget` sweeps, or whose returned iterate misses the tolerance, is
 // dropped and the sweeps repeated from the zero start (unless the sweep
 // count is fixed).  The caller recorded h->ev_s0 before preparing the
 // solve; st covers everything since.
 template <typename T>
-int solve_prepared(les_handle *h, View<T> &V, const T *guess, bool gated, int fixed,
+int solve_prepared(les_handle *h, View<T> &V, const T *guess, bool gated, int fixed, int budget,
                    les_solve_stats *st, T **result, SweepTiming *timing) {
   const Grid &g = h->grid;
+  const les_config &c = h->cfg;
   hipStream_t s = h->stream;
   SolveCtl r;
   T *phi = nullptr;
-  int rc = run_sweeps<T>(h, V, guess ? V.f[F_RHSD] : V.f[F_RHS], fixed, &r, &phi, timing);
+  int cap = 0;
+  if (guess && gated && fixed == 0 && budget > 0) {
+    // a kept guess gets the budget (the gate's decision is read back first,
+    // so a dropped guess's zero start keeps the whole cap)
+    HIP_TRY(hipMemcpyAsync(&h->ctl_host[0], V.ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int every = c.poisson_check_every;
+    const int64_t b = ((int64_t)budget + every - 1) / every * every;
+    if (h->ctl_host[0].guess_kept && b < c.poisson_max_sweeps) {
+      cap = (int)b;
+      launch_ctl_limit(V.ctl, cap, s);
+      LAUNCH_TRY();
+    }
+  }
+  int rc = run_sweeps<T>(h, V, guess ? V.f[F_RHSD] : V.f[F_RHS], fixed, cap, &r, &phi, timing);
   if (rc) return rc;
-  int sweeps = r.stop_m;
+  int sweeps = r.stop_m, first = 0;
   int flag = guess ? (r.guess_kept ? 1 : 2) : 0;
   double res2 = r.res_norm2;
   if (guess && r.guess_kept) {
@@ -591,11 +610,12 @@ int solve_prepared(les_handle *h, View<T> &V, const T *guess, bool gated, int fi
     res2 = r.res_out2;
     const bool missed = r.done == 3 || !(res2 <= r.tol2);
     if (gated && fixed == 0 && missed) {
-      launch_ctl_restart(V.ctl, s);
+      launch_ctl_restart(V.ctl, c.poisson_max_sweeps, s);
       launch_zero<T>(g, V.f[F_PHI0], s);
       LAUNCH_TRY();
-      rc = run_sweeps<T>(h, V, V.f[F_RHS], 0, &r, &phi, timing);
+      rc = run_sweeps<T>(h, V, V.f[F_RHS], 0, 0, &r, &phi, timing);
       if (rc) return rc;
+      first = sweeps;
       sweeps += r.stop_m;
       res2 = r.res_norm2;
       flag = 3;
@@ -613,7 +633,7 @@ int solve_prepared(les_handle *h, View<T> &V, const T *guess, bool gated, int fi
   st->res_norm = std::sqrt(res2);
   st->seconds = ms * 1e-3;
   st->guess = flag;
-  st->reserved = 0;
+  st->guess_sweeps = first;
   *result = phi;
   return LES_OK;
 }
@@ -717,7 +737,11 @@ int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step
       T *phi = nullptr;
       SweepTiming timing;
       timing.enabled = opts && opts->time_sweeps;
-      rc = solve_prepared<T>(h, V, guess, true, fixed, &st, &phi, &timing);
+      rc = solve_prepared<T>(h, V, guess, true, fixed, h->zero_sweeps[k], &st, &phi, &timing);
+      if (rc >= 0) {  // the last count of a pass from the zero start: the next guess's budget
+        if (st.guess == 0 || st.guess == 2) h->zero_sweeps[k] = st.sweeps;
+        else if (st.guess == 3) h->zero_sweeps[k] = st.sweeps - st.guess_sweeps;
+      }
       acc.sweep_seconds += timing.seconds;
       acc.sweeps_timed += timing.sweeps;
       if (opts && opts->records) opts->records[solve_idx] = st;
@@ -802,7 +826,9 @@ int poisson_impl(les_handle *h, const void *rhs, void *phi, const les_poisson_op
   }
   les_solve_stats st;
   T *res = nullptr;
-  rc = solve_prepared<T>(h, V, guess, use_guess == 2, fixed, &st, &res, nullptr);
+  const int budget = opts ? opts->budget : 0;
+  if (budget < 0) return fail(LES_ERR_ARG, "budget < 0");
+  rc = solve_prepared<T>(h, V, guess, use_guess == 2, fixed, budget, &st, &res, nullptr);
   if (stats) *stats = st;
   if (rc < 0) return rc;
   launch_block_sum<T>(res, g.n, 0, V.partials, s);
@@ -933,13 +959,15 @@ struct StateHeader {
 static_assert(sizeof(StateHeader) <= kAlign, "state header exceeds its region");
 
 struct StateLayout {
-  size_t pbar, pm2, hist, total;
+  size_t zsw, pbar, pm2, hist, total;
 };
 
 StateLayout state_layout(const les_config &c) {
   const size_t n = (size_t)c.nx * c.ny * c.nz, es = elem_size(&c);
   StateLayout S;
   size_t off = kAlign;
+  S.zsw = off;  // n_subiter int32: the guesses' sweep budgets
+  off = align_up(off + (size_t)c.n_subiter * sizeof(int32_t));
   S.pbar = off;
   off = align_up(off + (size_t)c.nz * sizeof(double));
   S.pm2 = off;
@@ -1089,6 +1117,7 @@ int init_impl(const les_config *cfg, const les_buffers *bufs, void *stream, les_
   t.satadj_maxit = cfg->satadj_maxit;
   jacobi_spectrum(cfg, &h->mu_min, &h->mu_max);
   h->hist_valid.assign(cfg->n_subiter, 0);
+  h->zero_sweeps.assign(cfg->n_subiter, 0);
   h->cnn_bound = false;
   h->cnn_alpha = 0.f;
   h->steps_done = 0;
@@ -1181,6 +1210,9 @@ int les_export_state(les_handle *h, void *dst) {
   };
   hipError_t e = copy(d, &hd, sizeof(hd), hipMemcpyHostToDevice);
   if (e == hipSuccess)
+    e = copy(d + S.zsw, h->zero_sweeps.data(), (size_t)c.n_subiter * sizeof(int32_t),
+             hipMemcpyHostToDevice);
+  if (e == hipSuccess)
     e = copy(d + S.pbar, ws(h, h->lay.mean_d) + 3 * (size_t)c.nz * sizeof(double),
              (size_t)c.nz * sizeof(double), hipMemcpyDeviceToDevice);
   if (e == hipSuccess && c.guess == LES_GUESS_EXTRAPOLATE)
@@ -1238,7 +1270,15 @@ int les_import_state(les_handle *h, const void *src) {
     if (rc == LES_ERR_HIP) h->broken = true;
     return rc;
   }
+  std::vector<int32_t> zsw(c.n_subiter);
+  if (hipMemcpyAsync(zsw.data(), d + S.zsw, (size_t)c.n_subiter * sizeof(int32_t),
+                     hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess) {
+    h->broken = true;
+    return fail(LES_ERR_HIP, "reading the guess budgets failed");
+  }
   for (int k = 0; k < c.n_subiter; ++k) h->hist_valid[k] = (hd.hist_valid >> k) & 1;
+  h->zero_sweeps = zsw;
   h->steps_done = hd.steps_done;
   return LES_OK;
 }

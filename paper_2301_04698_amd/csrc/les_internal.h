@@ -151,8 +151,11 @@ void launch_add_profile(const Grid &g, const T *in, const SolveCtl *ctl, const d
 template <typename T>
 void launch_rhs_center(const Grid &g, const T *rhs_in, T *rhs_out, T *phi0, const double *rsub,
                        const SolveCtl *ctl, double *partials, hipStream_t s);
-// Reset the stopping state for a second pass of sweeps on the same rhs.
-void launch_ctl_restart(SolveCtl *ctl, hipStream_t s);
+// Reset the stopping state for a second pass of sweeps on the same rhs,
+// with cap max_sweeps.
+void launch_ctl_restart(SolveCtl *ctl, int max_sweeps, hipStream_t s);
+// ctl->max_sweeps = max_sweeps (a kept guess's budget).
+void launch_ctl_limit(SolveCtl *ctl, int max_sweeps, hipStream_t s);
 // f = 0 (a fill kernel rather than a memset, so the call records no memset
 // node when a caller captures the stream into a graph).
 template <typename T>

@@ -116,7 +116,21 @@ def run_mode(p, state, mode, nsteps, params=None, alpha=DEFAULT_ALPHA, device="c
     sim.step(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rc, st, recs = sim.step(nsteps, records=True)
+    recs, acc = [], None
+    done = 0
+    while done < nsteps:
+        m = min(50, nsteps - done)
+        rc, st_m, r = sim.step(m, records=True)
+        recs += r
+        if acc is None:
+            acc = dict(st_m)
+        else:
+            for key in ("sweeps_total", "not_converged", "poisson_seconds", "seconds"):
+                acc[key] += st_m[key]
+            acc["res_rel_max"] = max(acc["res_rel_max"], st_m["res_rel_max"])
+        done += m
+        log(f"evaluate {mode}: {done}/{nsteps} steps, {acc['sweeps_total'] / done:.0f} sweeps/step")
+    st = acc
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     K = p["n_subiter"]
@@ -130,6 +144,9 @@ def run_mode(p, state, mode, nsteps, params=None, alpha=DEFAULT_ALPHA, device="c
                           for k in range(K)],
         not_converged=st["not_converged"],
         res_rel_max=st["res_rel_max"],
+        starts={name: sum(1 for r in recs if r["guess"] == code)
+                for code, name in ((0, "zero"), (1, "guess_kept"), (2, "guess_rejected"),
+                                   (3, "repeated_from_zero"))},
     )
     sim.close()
     return out
@@ -171,11 +188,26 @@ def main():
     ap.add_argument("--eval-seed", type=int, default=2000)
     ap.add_argument("--eval-spinup", type=int, default=300)
     ap.add_argument("--eval-steps", type=int, default=40)
-    ap.add_argument("--out", required=True)
+    ap.add_argument("--out", required=True,
+                    help="weights file to write (or, with --eval-only, to evaluate)")
+    ap.add_argument("--eval-only", action="store_true",
+                    help="evaluate the weights in --out on the held-out run; write <out>.eval.json")
+    ap.add_argument("--no-eval", action="store_true")
     a = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
     p = li.workload(a.workload)
+    if a.eval_only:
+        params = torch.from_numpy(np.load(a.out)).cuda()
+        t0 = time.perf_counter()
+        res = evaluate(p, params, a.eval_seed, a.eval_spinup, a.eval_steps, a.alpha)
+        summary = dict(workload=a.workload, weights=os.path.basename(a.out), eval_seed=a.eval_seed,
+                       eval_spinup=a.eval_spinup, eval_steps=a.eval_steps,
+                       eval_s=time.perf_counter() - t0, eval=res)
+        with open(os.path.splitext(a.out)[0] + ".eval.json", "w") as f:
+            json.dump(summary, f, indent=1)
+        log(json.dumps(summary))
+        return
     t0 = time.perf_counter()
     X, T = collect(p, [int(s) for s in a.seeds.split(",")], [int(w) for w in a.windows.split(",")],
                    a.window_len)
@@ -185,9 +217,15 @@ def main():
     t2 = time.perf_counter()
     del X, T
     np.save(a.out, params.cpu().numpy().astype(np.float32))
-    res = evaluate(p, params, a.eval_seed, a.eval_spinup, a.eval_steps, a.alpha)
-    summary = dict(workload=a.workload, collect_s=t1 - t0, train_s=t2 - t1, loss=hist,
-                   alpha=a.alpha, iters=a.iters, batch=a.batch, crop=a.crop, eval=res)
+    res = None if a.no_eval else evaluate(p, params, a.eval_seed, a.eval_spinup, a.eval_steps,
+                                          a.alpha)
+    npairs = len(a.seeds.split(",")) * len(a.windows.split(",")) * a.window_len * p["n_subiter"]
+    summary = dict(command="python -m paper_2301_04698_amd.guess_train " + " ".join(sys.argv[1:]),
+                   workload=a.workload, seeds=[int(x) for x in a.seeds.split(",")],
+                   windows=[int(x) for x in a.windows.split(",")], window_len=a.window_len,
+                   pairs=npairs, crop_samples=a.iters * a.batch, collect_s=t1 - t0,
+                   train_s=t2 - t1, loss=hist, alpha=a.alpha, iters=a.iters, batch=a.batch,
+                   crop=a.crop, lr=a.lr, schedule="cosine", eval=res)
     with open(os.path.splitext(a.out)[0] + ".json", "w") as f:
         json.dump(summary, f, indent=1)
     log(json.dumps(summary))

@@ -74,15 +74,16 @@ class LesBuffers(C.Structure):
 class LesSolveStats(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("status", C.c_int32), ("rhs_norm", C.c_double),
                 ("res_norm", C.c_double), ("seconds", C.c_double), ("guess", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("guess_sweeps", C.c_int32)]
 
     def as_dict(self):
         return dict(sweeps=self.sweeps, status=self.status, rhs_norm=self.rhs_norm,
-                    res_norm=self.res_norm, seconds=self.seconds, guess=self.guess)
+                    res_norm=self.res_norm, seconds=self.seconds, guess=self.guess,
+                    guess_sweeps=self.guess_sweeps)
 
 
 class LesPoissonOpts(C.Structure):
-    _fields_ = [("fixed_sweeps", C.c_int32), ("use_guess", C.c_int32)]
+    _fields_ = [("fixed_sweeps", C.c_int32), ("use_guess", C.c_int32), ("budget", C.c_int32)]
 
 
 class LesStepOpts(C.Structure):
@@ -313,16 +314,16 @@ class LES:
         recs = [r.as_dict() for r in rec] if rec is not None else None
         return rc, st.as_dict(), recs
 
-    def poisson_solve(self, rhs, phi=None, fixed_sweeps=0, use_guess=False):
+    def poisson_solve(self, rhs, phi=None, fixed_sweeps=0, use_guess=False, budget=0):
         """use_guess: False (zero start), True (phi holds a guess, kept) or 2
-        (phi holds a guess, gated as in the time step)."""
+        (phi holds a guess, gated as in the time step, with a sweep budget)."""
         torch = self.torch
         rhs = rhs.to(device=self.device, dtype=self.dtype).contiguous()
         if phi is None:
             phi = torch.zeros_like(rhs)
         assert phi.is_contiguous() and phi.dtype == self.dtype and phi.numel() == self._n()
         assert rhs.numel() == self._n()
-        opts = LesPoissonOpts(int(fixed_sweeps), int(use_guess))
+        opts = LesPoissonOpts(int(fixed_sweeps), int(use_guess), int(budget))
         st = LesSolveStats()
         rc = check(load().les_poisson_solve(self.handle, C.c_void_p(rhs.data_ptr()),
                                             C.c_void_p(phi.data_ptr()), C.byref(opts), C.byref(st)))

@@ -124,6 +124,39 @@ def test_backward_matches_oracle(gpu):
     assert rel(got, ref) <= 2e-4
 
 
+def test_backward_matches_oracle_on_identical_operands(gpu):
+    """The backward pass on the very operands the GPU used: the oracle's
+    FP64 backward is fed the GPU forward's stored bfloat16 layer inputs
+    (read back with les_cnn_stored_input) as its activations and their signs
+    as the leaky-ReLU branches, and the same FP32 output gradient.  What is
+    left is the GPU's FP32 accumulation of the activation gradients (sums of
+    432 products per value, through three layers): <= 1e-5 relative per
+    layer for weights and biases."""
+    from oracle import cnn as ocnn
+    p = params(6)
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((2, 5, 18, 20)).astype(np.float32).astype(float)
+    P = _t(p)
+    packed = gpu.pack(P)
+    out, work = gpu.forward(P, packed, _t(x), periodic=False, alpha=0.1)
+    acts = [np.ascontiguousarray(_np(gpu.stored_input(x.shape, work, l, alpha=0.1)))
+            for l in range(4)]
+    # layer 0's stored input is bf16(x), the oracle's own rounding of x
+    ref_x0 = ocnn.bf16(x)
+    assert np.array_equal(acts[0][:, 0], ref_x0)
+    gout = rng.standard_normal(_np(out).shape).astype(np.float32).astype(float)
+    ref = ocnn.backward(p, x, acts, [acts[1], acts[2], acts[3]], gout, periodic=False,
+                        alpha=0.1)
+    got = _np(gpu.backward(x.shape, packed, work, _t(gout), alpha=0.1))
+    for l in range(4):
+        a, b = ocnn.weight_offset(l), ocnn.bias_offset(l)
+        e = b + (16 if l < 3 else 1)
+        print(f"layer {l}: weight gradient {rel(got[a:b], ref[a:b]):.2e}, "
+              f"bias gradient {rel(got[b:e], ref[b:e]):.2e}")
+        assert rel(got[a:b], ref[a:b]) <= 1e-5, (l, rel(got[a:b], ref[a:b]))
+        assert rel(got[b:e], ref[b:e]) <= 1e-5, (l, "bias")
+
+
 def test_backward_deterministic(gpu):
     p = params(8)
     x = np.random.default_rng(9).standard_normal((3, 6, 20, 20)).astype(np.float32)

@@ -137,15 +137,19 @@ def test_gated_guess_kept_rejected_and_capped(gpu, oracle_lib):
     rhs = oracle_lib.laplacian(base, mode)
     phi0, s0 = oracle_lib.poisson(base, rhs)
     a = 0.5 * np.linalg.norm(rhs) / np.linalg.norm(oracle_lib.laplacian(base, v))
-    for cap, amp, flag in ((100000, 1.0, 1), (100000, 4.0, 2), (100, 1.0, 3)):
+    budget = 2 * s0["sweeps"] + 1
+    for cap, amp, bud, flag in ((100000, 1.0, 0, 1), (100000, 4.0, 0, 2), (100, 1.0, 0, 3),
+                                (100000, 1.0, budget, 3)):
         p = dict(base, poisson_max_sweeps=cap)
         guess = phi0 + amp * a * v
-        print(f"gated guess: cap {cap}, amplitude {amp}", flush=True)
-        phi_o, st_o = oracle_lib.poisson(p, rhs, guess=guess, gated=True)
+        print(f"gated guess: cap {cap}, amplitude {amp}, budget {bud}", flush=True)
+        phi_o, st_o = oracle_lib.poisson(p, rhs, guess=guess, gated=True, budget=bud)
         sim = gpu.LES(p)
         phi_g, st_g, rc = sim.poisson_solve(torch.from_numpy(rhs),
-                                            torch.from_numpy(guess.copy()).cuda(), use_guess=2)
+                                            torch.from_numpy(guess.copy()).cuda(), use_guess=2,
+                                            budget=bud)
         assert st_o["guess"] == flag and st_g["guess"] == flag, (st_o, st_g)
+        assert st_g["guess_sweeps"] == st_o["guess_sweeps"]
         assert st_g["status"] == 0 and rc == 0
         assert st_g["sweeps"] == st_o["sweeps"]
         assert rel(phi_g.cpu().numpy(), phi_o) <= 1e-11

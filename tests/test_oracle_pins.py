@@ -608,6 +608,16 @@ def test_gated_guess_kept_rejected_and_capped(oracle_lib):
     cap = 100
     out, sc = oracle_lib.poisson(dict(p, poisson_max_sweeps=cap), rhs, guess=good, gated=True)
     assert sc["guess"] == 3 and sc["status"] == 0 and sc["sweeps"] == cap + s0["sweeps"]
+    assert sc["guess_sweeps"] == cap
+    np.testing.assert_array_equal(out, phi0)
+    # a budget (the zero start's sweep count) ends the kept guess's sweeps at
+    # the first check from there on, and the zero start takes over
+    budget = 2 * s0["sweeps"] + 1
+    first = -(-budget // p["poisson_check_every"]) * p["poisson_check_every"]
+    out, sb = oracle_lib.poisson(dict(p, poisson_max_sweeps=100000), rhs, guess=good, gated=True,
+                                 budget=budget)
+    assert sb["guess"] == 3 and sb["guess_sweeps"] == first
+    assert sb["sweeps"] == first + s0["sweeps"] and sb["status"] == 0
     np.testing.assert_array_equal(out, phi0)
 
 

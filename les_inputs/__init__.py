@@ -77,8 +77,10 @@ _BASE = dict(
     jacobi_omega=0.0,          # 0 selects the closed-form optimum
     sweeps_per_launch=0,       # library launch shape only (0: its default)
     guess="zero",              # initial guess of the solves
-    mean_mode="exact",         # horizontal-mean part of each solve: "exact" (1D solve
-                               # first) or "swept" (with the rest)
+    mean_mode="exact",         # parts of each solve solved exactly before the sweeps:
+                               # "exact" (the horizontally uniform part, a 1D problem, and
+                               # the vertically uniform part, a 2D one), "level" (the 1D
+                               # part only) or "swept" (none)
     advection="quick",         # "quick" or "weno3" (WENO3 with Lax-Friedrichs flux)
     wall="no_slip",            # u, v at z = 0, H: "no_slip" or "free_slip"
     nu_const=0.0,              # > 0: uniform kinematic viscosity (m^2/s), no SGS model

@@ -22,7 +22,7 @@ GUESSES = {"zero": 0, "extrapolate": 1, "previous": 2}
 ADVECTION = {"quick": 0, "weno3": 1}
 WALLS = {"no_slip": 0, "free_slip": 1}
 PHASES = {"heaviside": 0, "ramp": 1}
-MEAN_MODES = {"swept": 0, "exact": 1}
+MEAN_MODES = {"swept": 0, "level": 1, "exact": 2}
 
 
 class OCfg(C.Structure):
@@ -91,6 +91,7 @@ def _bind(L):
     L.oracle_poisson.argtypes = [cfgp, _DP, _DP, C.c_int32, C.POINTER(OSolve)]
     L.oracle_poisson_gated.argtypes = [cfgp, _DP, _DP, C.c_int32, C.c_int32, C.POINTER(OSolve)]
     L.oracle_jacobi_bounds.argtypes = [cfgp, _DP, _DP]
+    L.oracle_vertical_mode_solve.argtypes = [cfgp, _DP, _DP]
     L.oracle_step.argtypes = [cfgp, _DP, _DP, _DP, _DP, _DP, _DP, C.c_int32,
                               C.POINTER(C.c_int32), C.POINTER(OSolve), C.POINTER(ODebug)]
     L.oracle_diagnostics.argtypes = [cfgp, _DP, _DP, _DP, _DP, _DP, _DP, _DP]
@@ -286,6 +287,16 @@ def radiation(p, ql, cpmpi):
     out = np.zeros(_shape(p))
     _check(lib().oracle_radiation(C.byref(make_cfg(p)), _ptr(ql), _ptr(cpmpi), _ptr(out)), "radiation")
     return out
+
+
+def vertical_mode_solve(p, rv):
+    """Solution pv (ny, nx) of the vertically uniform part Lh pv = rv."""
+    rv = _f64(rv)
+    assert rv.shape == (p["ny"], p["nx"])
+    pv = np.zeros_like(rv)
+    _check(lib().oracle_vertical_mode_solve(C.byref(make_cfg(p)), _ptr(rv), _ptr(pv)),
+           "vertical_mode_solve")
+    return pv
 
 
 def jacobi_bounds(p):

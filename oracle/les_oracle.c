@@ -625,8 +625,12 @@ static void neighbour_sum(const ocfg *c, const double *phi, double *nb) {
 /* Extreme nonzero eigenvalues of -D^{-1} L for the compact Laplacian L with
  * periodic x, y and mirror-Neumann z, D = 2/dx^2 + 2/dy^2 + 2/dz^2:
  * periodic axis (2 - 2 cos(2 pi m / N)) / Delta^2, mirror axis
- * (2 - 2 cos(pi m / N)) / Delta^2, m = 0 .. N-1.  A periodic axis of one
- * cell has only its m = 0 mode and no smallest nonzero eigenvalue. */
+ * (2 - 2 cos(pi m / N)) / Delta^2, m = 0 .. N-1; an eigenvalue of L is the
+ * sum over the axes.  A periodic axis of one cell has only its m = 0 mode
+ * and no smallest nonzero eigenvalue.  With mean_mode 2 the sweeps act only
+ * on modes with both horizontal (m_x or m_y > 0) and vertical (m_z > 0)
+ * structure, whose smallest eigenvalue is the smallest horizontal one plus
+ * the smallest vertical one. */
 int oracle_jacobi_bounds(const ocfg *c, double *mu_min, double *mu_max) {
   if (check_cfg(c)) return -1;
   double d = 2.0 / (c->dx * c->dx) + 2.0 / (c->dy * c->dy) + 2.0 / (c->dz * c->dz);
@@ -636,9 +640,15 @@ int oracle_jacobi_bounds(const ocfg *c, double *mu_min, double *mu_max) {
   double lxm = (2.0 - 2.0 * cos(2.0 * PI * (c->nx / 2) / c->nx)) / (c->dx * c->dx);
   double lym = (2.0 - 2.0 * cos(2.0 * PI * (c->ny / 2) / c->ny)) / (c->dy * c->dy);
   double lzm = (2.0 - 2.0 * cos(PI * (c->nz - 1) / c->nz)) / (c->dz * c->dz);
-  double mn = lz1;
-  if (c->nx > 1 && lx1 < mn) mn = lx1;
-  if (c->ny > 1 && ly1 < mn) mn = ly1;
+  double mn = lz1, mh = 0.0;
+  if (c->nx > 1) mh = lx1;
+  if (c->ny > 1 && (mh == 0.0 || ly1 < mh)) mh = ly1;
+  if (c->mean_mode == 2) {
+    /* the sweeps see only modes with horizontal and vertical structure */
+    mn = mh + lz1;
+  } else if (mh > 0.0 && mh < mn) {
+    mn = mh;
+  }
   *mu_min = mn / d;
   *mu_max = (lxm + lym + lzm) / d;
   return 0;
@@ -674,6 +684,77 @@ static void mean_mode_solve(const ocfg *c, const double *rb, double *pb) {
   }
   for (int k = 0; k < c->nz; ++k) s += pb[k];
   for (int k = 0; k < c->nz; ++k) pb[k] -= s / c->nz;
+}
+
+/* Vertical mean of field f in every column (i, j): mean[i + nx j]. */
+static void column_means(const ocfg *c, const double *f, double *mean) {
+  size_t nxy = (size_t)c->nx * c->ny;
+  for (size_t q = 0; q < nxy; ++q) {
+    double s = 0.0;
+    for (int k = 0; k < c->nz; ++k) s += f[(size_t)k * nxy + q];
+    mean[q] = s / c->nz;
+  }
+}
+
+/* cas(2 pi m / n) = cos + sin of the angle, m taken modulo n. */
+static double cas_angle(long m, int n) {
+  double t = 2.0 * PI * (double)(m % n) / n;
+  return cos(t) + sin(t);
+}
+
+/* The vertically uniform part of L phi = rhs (mean_mode 2).  READING (the
+ * paper sweeps every mode): with mirror walls the z second differences of a
+ * column sum to zero, and the z part of L vanishes on a field constant in
+ * z, so the vertical mean of the equation is the two-dimensional periodic
+ * problem Lh pv = rv, Lh the x and y part of L, which decouples from the
+ * modes with vertical structure.  Its exact solution in the real Fourier
+ * (Hartley) basis, which diagonalises each periodic second difference:
+ * with H[k][i] = cas(2 pi k i / n) (H H = n I) and the eigenvalue of mode
+ * (kx, ky) lambda = -(2 - 2 cos(2 pi kx/nx))/dx^2 - (2 - 2 cos(2 pi ky/ny))/dy^2,
+ *   pv = Hy [ (Hy rv Hx) / lambda ] Hx / (nx ny),
+ * the mode (0, 0) (the mean, zero for a centred rhs) set to zero.  Plain
+ * sums, O(nx ny (nx + ny)). */
+static int vertical_mode_solve(const ocfg *c, const double *rv, double *pv) {
+  int nx = c->nx, ny = c->ny;
+  size_t nxy = (size_t)nx * ny;
+  double *a = malloc(nxy * sizeof(double)), *b = malloc(nxy * sizeof(double));
+  if (!a || !b) { free(a); free(b); return -1; }
+  /* a = Hy rv: a[ky][i] = sum_j cas(2 pi ky j / ny) rv[j][i] */
+  for (int ky = 0; ky < ny; ++ky)
+    for (int i = 0; i < nx; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < ny; ++j) s += cas_angle((long)ky * j, ny) * rv[(size_t)j * nx + i];
+      a[(size_t)ky * nx + i] = s;
+    }
+  /* b = a Hx, divided by the eigenvalue */
+  for (int ky = 0; ky < ny; ++ky)
+    for (int kx = 0; kx < nx; ++kx) {
+      double s = 0.0;
+      for (int i = 0; i < nx; ++i) s += a[(size_t)ky * nx + i] * cas_angle((long)i * kx, nx);
+      double lam = -(2.0 - 2.0 * cos(2.0 * PI * kx / nx)) / (c->dx * c->dx)
+                   - (2.0 - 2.0 * cos(2.0 * PI * ky / ny)) / (c->dy * c->dy);
+      b[(size_t)ky * nx + kx] = (kx == 0 && ky == 0) ? 0.0 : s / lam;
+    }
+  /* pv = Hy b Hx / (nx ny) */
+  for (int j = 0; j < ny; ++j)
+    for (int kx = 0; kx < nx; ++kx) {
+      double s = 0.0;
+      for (int ky = 0; ky < ny; ++ky) s += cas_angle((long)j * ky, ny) * b[(size_t)ky * nx + kx];
+      a[(size_t)j * nx + kx] = s;
+    }
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      double s = 0.0;
+      for (int kx = 0; kx < nx; ++kx) s += a[(size_t)j * nx + kx] * cas_angle((long)kx * i, nx);
+      pv[(size_t)j * nx + i] = s / ((double)nx * ny);
+    }
+  free(a); free(b);
+  return 0;
+}
+
+int oracle_vertical_mode_solve(const ocfg *c, const double *rv, double *pv) {
+  if (check_cfg(c)) return -1;
+  return vertical_mode_solve(c, rv, pv);
 }
 
 /* ||rhs - L phi||_2 with L phi = neighbour sum - D phi. */
@@ -748,11 +829,15 @@ static int jacobi_sweeps(const ocfg *c, const double *rhs, double rn, double *ph
 /* Solve L phi = rhs (Sec. 2.4, pressure-correction equation; the unknown is
  * phi = alpha0 delta p).  rhs gets its mean removed (compatibility); the
  * stopping test is relative to its norm; the solution has zero mean.
- * The zero start is phi = 0, or with mean_mode = 1 the exact solution of the
- * horizontally uniform part (mean_mode_solve).  phi in holds the guess: the
- * start is the zero start plus the guess (with mean_mode = 1 the guess's
- * horizontal means per level are removed first, as that part is already
- * exact).  gate = 1: the guess is kept only if its residual is below the
+ * The zero start is phi = 0, or with mean_mode >= 1 the exact solution of
+ * the horizontally uniform part (mean_mode_solve), with mean_mode 2 plus
+ * that of the vertically uniform part (vertical_mode_solve).  phi in holds
+ * the guess: the start is the zero start plus the guess with those exact
+ * parts removed (its horizontal means per level, and with mean_mode 2 its
+ * vertical means per column, its overall mean added back).  With
+ * mean_mode 2 the sweeps' correction is projected the same way at the end
+ * (in exact arithmetic a no-op: the sweeps keep both parts of it zero) and
+ * the residual reported is that of the returned iterate.  gate = 1: the guess is kept only if its residual is below the
  * zero start's, and a kept guess whose sweeps reach the cap (no fixed
  * count) is dropped and the sweeps repeated from the zero start.  budget >
  * 0 (no fixed count): a kept guess's sweeps stop at the first residual
@@ -769,24 +854,40 @@ static int poisson_solve(const ocfg *c, const double *rhs_in, double *phi, int32
   double *rb = malloc(c->nz * sizeof(double));
   double *pb = malloc(c->nz * sizeof(double));
   double *gb = malloc(c->nz * sizeof(double));
-  if (!rhs || !tmp || !prev || !zero || !rb || !pb || !gb) {
+  double *rv = calloc(nxy, sizeof(double));
+  double *pv = calloc(nxy, sizeof(double));
+  double *gv = calloc(nxy, sizeof(double));
+  if (!rhs || !tmp || !prev || !zero || !rb || !pb || !gb || !rv || !pv || !gv) {
     free(rhs); free(tmp); free(prev); free(zero); free(rb); free(pb); free(gb);
+    free(rv); free(pv); free(gv);
     return -1;
   }
   double mr = fsum(c, rhs_in) / (double)n;
   for (size_t q = 0; q < n; ++q) rhs[q] = rhs_in[q] - mr;
   double rn = fnorm2(c, rhs);
-  /* zero start, and the guess with its level means removed */
+  /* zero start, and the guess without the parts that start exact */
+  double gm = 0.0;
   for (int k = 0; k < c->nz; ++k) pb[k] = gb[k] = 0.0;
-  if (c->mean_mode == 1) {
+  if (c->mean_mode >= 1) {
     level_means(c, rhs, rb);
     mean_mode_solve(c, rb, pb);
     level_means(c, phi, gb);
   }
+  if (c->mean_mode == 2) {
+    column_means(c, rhs, rv);
+    if (vertical_mode_solve(c, rv, pv)) {
+      free(rhs); free(tmp); free(prev); free(zero); free(rb); free(pb); free(gb);
+      free(rv); free(pv); free(gv);
+      return -1;
+    }
+    column_means(c, phi, gv);
+    gm = fsum(c, phi) / (double)n;
+  }
   for (int k = 0; k < c->nz; ++k)
-    for (size_t q = (size_t)k * nxy; q < (size_t)(k + 1) * nxy; ++q) {
-      zero[q] = pb[k];
-      phi[q] = pb[k] + (phi[q] - gb[k]);
+    for (size_t q = 0; q < nxy; ++q) {
+      size_t qq = (size_t)k * nxy + q;
+      zero[qq] = pb[k] + pv[q];
+      phi[qq] = zero[qq] + (phi[qq] - gb[k] - gv[q] + gm);
     }
   int guessed = 0;
   if (gate) {
@@ -795,6 +896,17 @@ static int poisson_solve(const ocfg *c, const double *rhs_in, double *phi, int32
       memcpy(phi, zero, n * sizeof(double));
       guessed = 2;
     }
+  }
+  /* the sweeps' start (mean_mode 2 projects the correction against it) */
+  double *start = NULL;
+  if (c->mean_mode == 2) {
+    start = malloc(n * sizeof(double));
+    if (!start) {
+      free(rhs); free(tmp); free(prev); free(zero); free(rb); free(pb); free(gb);
+      free(rv); free(pv); free(gv);
+      return -1;
+    }
+    memcpy(start, phi, n * sizeof(double));
   }
   int m = 0, status = 0, first = 0;
   double rr = 0.0;
@@ -808,11 +920,26 @@ static int poisson_solve(const ocfg *c, const double *rhs_in, double *phi, int32
     if (status == 1 && guessed == 1 && fixed_sweeps == 0) {
       int m2 = 0;
       memcpy(phi, zero, n * sizeof(double));
+      if (start) memcpy(start, zero, n * sizeof(double));
       status = jacobi_sweeps(c, rhs, rn, phi, 0, tmp, prev, &m2, &rr);
       first = m;
       m += m2;
       guessed = 3;
     }
+  }
+  if (c->mean_mode == 2 && rn > 0.0) {
+    /* the correction relative to the last pass's start, without the parts
+       that started exact (each zero in exact arithmetic) */
+    for (size_t q = 0; q < n; ++q) tmp[q] = phi[q] - start[q];
+    level_means(c, tmp, gb);
+    column_means(c, tmp, gv);
+    double dm = fsum(c, tmp) / (double)n;
+    for (int k = 0; k < c->nz; ++k)
+      for (size_t q = 0; q < nxy; ++q) {
+        size_t qq = (size_t)k * nxy + q;
+        phi[qq] = start[qq] + (tmp[qq] - gb[k] - gv[q] + dm);
+      }
+    rr = residual_norm(c, rhs, phi, tmp);
   }
   double mp = fsum(c, phi) / (double)n;
   for (size_t q = 0; q < n; ++q) phi[q] -= mp;
@@ -825,6 +952,7 @@ static int poisson_solve(const ocfg *c, const double *rhs_in, double *phi, int32
     st->guess_sweeps = first;
   }
   free(rhs); free(tmp); free(prev); free(zero); free(rb); free(pb); free(gb);
+  free(rv); free(pv); free(gv); free(start);
   return status < 0 ? status : 0;
 }
 

@@ -25,8 +25,9 @@ typedef struct ocfg {
   int32_t advection;           /* 0 QUICK, 1 WENO3 with Lax-Friedrichs flux */
   int32_t wall;                /* u, v at z = 0, H: 0 no-slip (odd mirror), 1 free-slip (even) */
   int32_t phase;               /* condensate partition: 0 Heaviside at T_f, 1 linear ramp T_ice..T_f */
-  int32_t mean_mode;           /* horizontally uniform part of each solve: 0 swept with the
-                                  rest, 1 solved exactly first (see oracle_poisson) */
+  int32_t mean_mode;           /* parts of each solve solved exactly first (see
+                                  oracle_poisson): 0 none, 1 the horizontally uniform
+                                  part, 2 also the vertically uniform part */
   int32_t reserved;
   double dx, dy, dz, dt;
   double poisson_tol;          /* ||rhs - L phi||_2 <= tol * ||rhs||_2 */
@@ -89,10 +90,11 @@ int oracle_divergence(const ocfg *c, const double *U, const double *V, const dou
 int oracle_radiation(const ocfg *c, const double *ql, const double *cpm_pi, double *out);
 
 /* Poisson solve (Sec. 2.4): phi in = guess, out = zero-mean solution.
- * fixed_sweeps > 0 performs exactly that many sweeps.  With mean_mode = 1
+ * fixed_sweeps > 0 performs exactly that many sweeps.  With mean_mode >= 1
  * the horizontal mean of the equation, a one-dimensional Neumann problem in
- * z, is solved exactly first and the sweeps start from that solution plus
- * the guess with its horizontal mean per level removed. */
+ * z, is solved exactly first; with mean_mode 2 also its vertical mean, a
+ * two-dimensional periodic problem (oracle_vertical_mode_solve); the sweeps
+ * start from those solutions plus the guess with the same parts removed. */
 int oracle_poisson(const ocfg *c, const double *rhs, double *phi, int32_t fixed_sweeps,
                    osolve *st);
 /* The same solve as the time step runs it for a guess: the guess is kept
@@ -102,7 +104,12 @@ int oracle_poisson(const ocfg *c, const double *rhs, double *phi, int32_t fixed_
  * start (no fixed count); st->guess as in oracle_step's records. */
 int oracle_poisson_gated(const ocfg *c, const double *rhs, double *phi, int32_t fixed_sweeps,
                          int32_t budget, osolve *st);
-/* Closed-form extreme eigenvalues of -D^{-1} L on zero-mean fields. */
+/* The two-dimensional periodic problem of the vertical mean (mean_mode 2):
+ * Lh pv = rv on nx x ny, Lh the x and y part of the compact Laplacian, rv
+ * with zero mean; pv with zero mean. */
+int oracle_vertical_mode_solve(const ocfg *c, const double *rv, double *pv);
+/* Closed-form extreme eigenvalues of -D^{-1} L on zero-mean fields (with
+ * mean_mode 2, on the modes the sweeps act on). */
 int oracle_jacobi_bounds(const ocfg *c, double *mu_min, double *mu_max);
 
 /* Debug intermediates of the last sub-iteration of the last step (optional). */

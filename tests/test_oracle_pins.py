@@ -472,9 +472,83 @@ def test_jacobi_bounds_brute_force(oracle_lib):
         d = 2 / p["dx"] ** 2 + 2 / p["dy"] ** 2 + 2 / p["dz"] ** 2
         ev = np.sort(np.linalg.eigvalsh(-A / d))
         assert abs(ev[0]) < 1e-12 and ev[1] > 1e-6
-        lo, hi = oracle_lib.jacobi_bounds(p)
+        lo, hi = oracle_lib.jacobi_bounds(dict(p, mean_mode="level"))
         assert lo == pytest.approx(ev[1], rel=1e-10)
         assert hi == pytest.approx(ev[-1], rel=1e-10)
+        # With both uniform parts solved exactly the sweeps act on the fields
+        # with zero horizontal mean on every level and zero vertical mean in
+        # every column: the operator restricted there (an orthonormal basis
+        # of that subspace, from the projector's eigenvectors) has the
+        # smallest eigenvalue the closed form gives.
+        k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        k, j, i = k.ravel(), j.ravel(), i.ravel()
+        col = j * nx + i
+        Pm = (np.eye(n) - (k[:, None] == k[None, :]) / (nx * ny)
+              - (col[:, None] == col[None, :]) / nz + 1.0 / n)
+        w, Q = np.linalg.eigh(Pm)
+        B = Q[:, w > 0.5]
+        evs = np.sort(np.linalg.eigvalsh(B.T @ (-A / d) @ B))
+        lo2, hi2 = oracle_lib.jacobi_bounds(dict(p, mean_mode="exact"))
+        assert lo2 == pytest.approx(evs[0], rel=1e-10)
+        assert hi2 == pytest.approx(evs[-1], rel=1e-10)
+        assert lo2 > 2 * lo
+
+
+def test_vertical_mode_solve_matches_fft(oracle_lib):
+    """The vertically uniform part's exact solution (real Fourier basis)
+    against numpy's complex FFT solution of the 2D periodic problem, on
+    even and odd sizes and a one-row (x-z) grid."""
+    for (ny, nx) in [(8, 8), (6, 10), (7, 5), (1, 12)]:
+        p = small(nx=nx, ny=ny, nz=4, dx=40.0, dy=30.0)
+        rv = li.random_field((1, ny, nx), seed=17)[0]
+        pv = oracle_lib.vertical_mode_solve(p, rv)
+        F = np.fft.fft2(rv)
+        ky = 2 * np.pi * np.fft.fftfreq(ny)
+        kx = 2 * np.pi * np.fft.fftfreq(nx)
+        lam = -((2 - 2 * np.cos(ky))[:, None] / p["dy"] ** 2
+                + (2 - 2 * np.cos(kx))[None, :] / p["dx"] ** 2)
+        lam[0, 0] = 1.0
+        F = F / lam
+        F[0, 0] = 0.0
+        exact = np.real(np.fft.ifft2(F))
+        np.testing.assert_allclose(pv, exact, rtol=0, atol=1e-12 * np.abs(exact).max())
+
+
+def test_vertically_uniform_rhs_needs_no_sweep(oracle_lib):
+    """A right-hand side constant in z is the vertically uniform part only:
+    with both uniform parts exact it is solved with no sweep, every level
+    equal to the 2D solution."""
+    nz, ny, nx = 6, 10, 12
+    p = small(nx=nx, ny=ny, nz=nz, poisson_tol=1e-12, mean_mode="exact")
+    r2 = li.random_field((1, ny, nx), seed=19)
+    rhs = np.repeat(r2, nz, axis=0)
+    phi, st = oracle_lib.poisson(p, rhs)
+    assert st["status"] == 0 and st["sweeps"] == 0
+    pv = oracle_lib.vertical_mode_solve(p, r2[0])
+    np.testing.assert_allclose(phi, np.broadcast_to(pv, phi.shape), rtol=0,
+                               atol=1e-12 * np.abs(pv).max())
+
+
+def test_exact_uniform_parts_cut_the_sweeps(oracle_lib):
+    """On the benchmark's spacing (35 m x 35 m x 5 m), with the horizontal
+    scales far larger than the vertical ones, the slowest modes are the
+    vertically uniform ones; solving them exactly raises the smallest
+    eigenvalue the sweeps see from lambda_h(1) to lambda_h(1) + lambda_z(1)
+    and the sweeps to the same tolerance fall about sqrt of that ratio."""
+    shape = (32, 64, 64)
+    base = dict(nx=64, ny=64, nz=32, precision="fp64", poisson_tol=1e-8)
+    rhs = li.random_field(shape, seed=3)
+    out = {}
+    for mm in ("level", "exact"):
+        p = li.workload("C2", mean_mode=mm, **base)
+        phi, st = oracle_lib.poisson(p, rhs)
+        assert st["status"] == 0
+        out[mm] = (phi, st["sweeps"], oracle_lib.jacobi_bounds(p)[0])
+    ratio = out["exact"][2] / out["level"][2]
+    assert ratio > 40
+    assert out["exact"][1] * 5 < out["level"][1]
+    np.testing.assert_allclose(out["exact"][0], out["level"][0], rtol=0,
+                               atol=1e-6 * np.abs(out["level"][0]).max())
 
 
 # ------------------------------------------------------ P7 Poisson exact
@@ -500,7 +574,7 @@ def fft_poisson(p, rhs):
 
 @pytest.mark.parametrize("shape", [(8, 8, 8), (10, 12, 16)])
 @pytest.mark.parametrize("scheme", ["jacobi", "chebyshev"])
-@pytest.mark.parametrize("mean_mode", ["exact", "swept"])
+@pytest.mark.parametrize("mean_mode", ["exact", "level", "swept"])
 def test_poisson_matches_fft(oracle_lib, shape, scheme, mean_mode):
     nz, ny, nx = shape
     p = small(nx=nx, ny=ny, nz=nz, dx=40.0, dy=30.0, dz=10.0, poisson_tol=1e-12,
@@ -556,30 +630,34 @@ def test_mean_mode_of_a_horizontally_uniform_rhs(oracle_lib):
 
 
 def test_mean_mode_ignores_level_means_of_a_guess(oracle_lib):
-    """With the horizontally uniform part solved exactly, a guess's
-    horizontal means per level play no part: adding any profile of z to it
-    changes neither the sweeps nor the solution."""
+    """With both uniform parts solved exactly, a guess's horizontal means per
+    level and vertical means per column play no part: adding any profile of
+    z and any field of (x, y) to it changes neither the sweeps nor the
+    solution."""
     shape = (12, 10, 14)
     p = small(nx=14, ny=10, nz=12, poisson_tol=1e-10, poisson_scheme="chebyshev",
               mean_mode="exact")
     rhs = li.random_field(shape, seed=12)
     g = li.random_field(shape, seed=13) * 40.0
     prof = np.linspace(-300.0, 500.0, 12)[:, None, None]
+    plane = 200.0 * li.random_field((1, 10, 14), seed=14)
     a, sa = oracle_lib.poisson(p, rhs, guess=g)
-    b, sb = oracle_lib.poisson(p, rhs, guess=g + prof)
+    b, sb = oracle_lib.poisson(p, rhs, guess=g + prof + plane)
     assert sa["sweeps"] == sb["sweeps"] and sa["status"] == 0
     np.testing.assert_allclose(a, b, rtol=0, atol=1e-12 * np.abs(a).max())
 
 
 def _mid_spectrum_case():
     """rhs = L of an eigenmode with Jacobi eigenvalue 1 (the fixed-weight
-    sweep removes it at once) and the slowest horizontal mode v."""
+    sweep removes it at once) and v, the slowest mode with horizontal and
+    vertical structure (the slowest the sweeps see when both uniform parts
+    start exact)."""
     p = small(nx=16, ny=16, nz=16, dx=40.0, dy=40.0, dz=10.0, poisson_scheme="jacobi",
               poisson_tol=1e-10, poisson_check_every=5)
     k, j, i = np.meshgrid(np.arange(16), np.arange(16), np.arange(16), indexing="ij")
     mode = (np.cos(2 * np.pi * 4 * i / 16) * np.cos(2 * np.pi * 4 * j / 16)
             * np.cos(np.pi * 8 * (k + 0.5) / 16))
-    v = np.cos(2 * np.pi * (i + 0.5) / 16)
+    v = np.cos(2 * np.pi * (i + 0.5) / 16) * np.cos(np.pi * (k + 0.5) / 16)
     return p, mode, v
 
 
@@ -591,7 +669,8 @@ def test_gated_guess_kept_rejected_and_capped(oracle_lib):
     meets the tolerance and returns the zero start's solution, with both
     passes counted.  Here the right-hand side is one eigenmode that the
     fixed-weight sweep removes in a few sweeps, and the kept guess errs by
-    the slowest mode, which decays by 1 - omega mu_min per sweep."""
+    the slowest mode the sweeps see, which decays by 1 - omega mu_min per
+    sweep."""
     p, mode, v = _mid_spectrum_case()
     rhs = oracle_lib.laplacian(p, mode)
     phi0, s0 = oracle_lib.poisson(p, rhs)

@@ -57,18 +57,27 @@ enum { LES_NO_SLIP = 0, LES_FREE_SLIP = 1 };  /* u, v at the walls z = 0, H */
  * sublimation heat Ls0; the saturation humidity of a partition is the
  * liquid-share-weighted mean of the two. */
 enum { LES_PHASE_HEAVISIDE = 0, LES_PHASE_RAMP = 1 };
-/* Horizontally uniform part of each pressure-correction solve.  The compact
- * Laplacian maps a function of z alone to its second difference in z and
- * commutes with horizontal averaging, so the horizontal mean of the
- * equation is a one-dimensional Neumann problem that decouples from the
- * other modes:
- *   LES_MEAN_SWEPT  the sweeps solve it with the rest (the paper's method
- *                   as written)
- *   LES_MEAN_EXACT  it is solved exactly in FP64 (two running sums) and the
- *                   sweeps start from that solution; its part of phi and of
- *                   the pressure is kept as FP64 profiles (see les_buffers.p)
- * Both meet the same residual test. */
-enum { LES_MEAN_SWEPT = 0, LES_MEAN_EXACT = 1 };
+/* Uniform parts of each pressure-correction solve.  The compact Laplacian
+ * maps a function of z alone to its second difference in z and commutes
+ * with horizontal averaging, so the horizontal mean of the equation is a
+ * one-dimensional Neumann problem; with mirror walls the z second
+ * differences of a column sum to zero and vanish on a field constant in z,
+ * so its vertical mean is the two-dimensional periodic x-y problem.  Both
+ * decouple exactly from the other modes:
+ *   LES_MEAN_SWEPT  the sweeps solve every mode (the paper's method as
+ *                   written)
+ *   LES_MEAN_LEVEL  the horizontally uniform part is solved exactly in FP64
+ *                   (two running sums), its parts of phi and of the pressure
+ *                   kept as FP64 profiles (see les_buffers.p); the sweeps
+ *                   solve the rest from zero
+ *   LES_MEAN_EXACT  as LES_MEAN_LEVEL, and the vertically uniform part is
+ *                   solved exactly in FP64 too (a real Fourier transform of
+ *                   each horizontal direction); the sweeps solve only the
+ *                   modes with both horizontal and vertical structure, with
+ *                   Chebyshev bounds for those (the slowest modes of these
+ *                   grids are vertically uniform, so far fewer sweeps)
+ * All meet the same residual test. */
+enum { LES_MEAN_SWEPT = 0, LES_MEAN_LEVEL = 1, LES_MEAN_EXACT = 2 };
 /* Initial guess of the pressure-correction solves:
  *   LES_GUESS_ZERO         phi_0 = 0 for every solve (the plain method)
  *   LES_GUESS_EXTRAPOLATE  first solve of a step: phi_0 = alpha0 (p^n -
@@ -126,16 +135,16 @@ typedef struct les_config {
                                    nu/Pr and nu/Sc.  0: Smagorinsky */
   double T_ice;                 /* LES_PHASE_RAMP: all condensate is ice at
                                    and below T_ice (K), 0 < T_ice < Tf */
-  int32_t mean_mode;            /* LES_MEAN_SWEPT or LES_MEAN_EXACT */
+  int32_t mean_mode;            /* LES_MEAN_SWEPT, LES_MEAN_LEVEL or LES_MEAN_EXACT */
   int32_t reserved;             /* 0 */
 } les_config;
 
 /* Caller-owned device buffers.  u, v, w: velocity (m/s); thl: liquid-ice
  * potential temperature (K) stored at the half step; qt: total water
  * specific humidity (kg/kg) at the half step; p: pressure perturbation p'
- * (Pa) less the horizontally uniform pressure that LES_MEAN_EXACT keeps in
- * the workspace as an FP64 profile (starts at zero with les_init; with
- * LES_MEAN_SWEPT it stays zero and p is p').  les_pressure returns the
+ * (Pa) less the horizontally uniform pressure that LES_MEAN_LEVEL and
+ * LES_MEAN_EXACT keep in the workspace as an FP64 profile (starts at zero
+ * with les_init; with LES_MEAN_SWEPT it stays zero and p is p').  les_pressure returns the
  * whole p'.  workspace: at least les_workspace_bytes(cfg) bytes, 256-byte
  * aligned, not shared with another handle. */
 typedef struct les_buffers {
@@ -162,8 +171,8 @@ typedef struct les_solve_stats {
                          missed the tolerance, and the sweeps were repeated
                          from the zero start (sweeps and seconds count both
                          passes); les_poisson_solve: opts->use_guess.
-                         "Zero start": phi = 0, or with LES_MEAN_EXACT the
-                         exact horizontally uniform part.  For a kept guess
+                         "Zero start": phi = 0, or the exact uniform parts
+                         (LES_MEAN_LEVEL, LES_MEAN_EXACT).  For a kept guess
                          res_norm is the residual of the returned iterate
                          (guess plus correction, as stored) */
   int32_t guess_sweeps; /* guess 3: the sweeps of the dropped guess's pass */
@@ -194,23 +203,23 @@ typedef struct les_step_opts {
                                    right-hand sides the sweeps of the call's
                                    last step solved, sub-iteration k at
                                    offset k*n: centred, and with
-                                   LES_MEAN_EXACT also without their
-                                   horizontal mean per level */
+                                   LES_MEAN_LEVEL or LES_MEAN_EXACT also
+                                   without their horizontal mean per level */
   void *dump_phi;               /* device, n_subiter*n elements or NULL:
                                    those solves' zero-mean solutions, with
-                                   LES_MEAN_EXACT without their horizontally
-                                   uniform part */
+                                   LES_MEAN_LEVEL or LES_MEAN_EXACT without
+                                   their horizontally uniform part */
   double *dump_mean;            /* host, n_subiter*(2*nz+1) doubles or NULL:
                                    per solve of the last step, the values the
                                    centring subtracted per level (the mean of
-                                   the raw rhs, or with LES_MEAN_EXACT its
-                                   horizontal mean per level), the
+                                   the raw rhs, or with LES_MEAN_LEVEL and
+                                   LES_MEAN_EXACT its horizontal mean per
+                                   level), the
                                    horizontally uniform part of the solution
                                    (zero with LES_MEAN_SWEPT), and the mean
-                                   of the raw rhs.  With LES_MEAN_EXACT the
-                                   whole centred rhs is dump_rhs + (first
-                                   profile - mean) and the whole solution
-                                   dump_phi + second profile */
+                                   of the raw rhs.  The whole centred rhs is
+                                   dump_rhs + (first profile - mean) and the
+                                   whole solution dump_phi + second profile */
 } les_step_opts;
 
 typedef struct les_step_stats {
@@ -265,8 +274,8 @@ int les_step(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step_
  * the pressure-correction equation of Sec. 2.4) by the configured sweeps.
  * rhs: device, n elements, read only (its mean is removed internally).
  * phi: device, n elements; in = guess if opts->use_guess, out = zero-mean
- * solution (with LES_MEAN_EXACT its horizontally uniform part, solved
- * exactly in FP64, is added before rounding once).  The sweeps solve for a
+ * solution (with LES_MEAN_LEVEL or LES_MEAN_EXACT its horizontally
+ * uniform part, solved exactly in FP64, is added before rounding once).  The sweeps solve for a
  * guess's correction from zero.  Uses the handle's workspace.
  * Synchronizes the stream. */
 int les_poisson_solve(les_handle *h, const void *rhs, void *phi, const les_poisson_opts *opts,
@@ -275,14 +284,15 @@ int les_poisson_solve(les_handle *h, const void *rhs, void *phi, const les_poiss
 /* The whole pressure perturbation p' (Sec. 2.4: the sum of the pressure
  * corrections rho0 phi of the solves): p_out (device, n elements of the
  * storage type, nullable) = p + pbar(z), rounded once; pbar_host (host, nz
- * doubles, nullable) = the FP64 profile pbar kept by LES_MEAN_EXACT (zero
- * with LES_MEAN_SWEPT).  Synchronizes the stream. */
+ * doubles, nullable) = the FP64 profile pbar kept by LES_MEAN_LEVEL and
+ * LES_MEAN_EXACT (zero with LES_MEAN_SWEPT).  Synchronizes the stream. */
 int les_pressure(les_handle *h, void *p_out, double *pbar_host);
 
-/* Restart with LES_MEAN_EXACT: sets the FP64 horizontally uniform pressure
- * pbar (host, nz doubles, finite) that p is taken relative to, e.g. the
- * pbar_host of les_pressure on an earlier run (les_init starts it at
- * zero).  LES_ERR_STATE with LES_MEAN_SWEPT.  Synchronizes the stream. */
+/* Restart with LES_MEAN_LEVEL or LES_MEAN_EXACT: sets the FP64
+ * horizontally uniform pressure pbar (host, nz doubles, finite) that p is
+ * taken relative to, e.g. the pbar_host of les_pressure on an earlier run
+ * (les_init starts it at zero).  LES_ERR_STATE with LES_MEAN_SWEPT.
+ * Synchronizes the stream. */
 int les_set_pressure_profile(les_handle *h, const double *pbar_host);
 
 /* Thermodynamic state of arbitrary fields (Sec. 2.1-2.2): temperature T,
@@ -301,7 +311,8 @@ int les_thermo(les_handle *h, const void *thl, const void *qt, void *T, void *ql
 int les_diagnostics(les_handle *h, les_diag *out, double *profiles);
 
 /* State the library keeps between les_step calls, beyond the caller's
- * fields: the FP64 horizontally uniform pressure of LES_MEAN_EXACT, the
+ * fields: the FP64 horizontally uniform pressure of LES_MEAN_LEVEL and
+ * LES_MEAN_EXACT, the
  * previous step's pressure (LES_GUESS_EXTRAPOLATE), the previous step's
  * solutions of each sub-iteration and which of them are held
  * (LES_GUESS_PREVIOUS, LES_GUESS_LEARNED), and the count of steps taken.

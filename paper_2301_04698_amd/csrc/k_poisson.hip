@@ -155,7 +155,8 @@ __global__ __launch_bounds__(kBlock) void center_kernel(Grid g, int lp, const T 
   if (threadIdx.x == 0) partials[(int64_t)k * lp + blockIdx.x] = s;
 }
 
-// gbar[k] = level mean from the level partials (exact mode), else 0.
+// gbar[k] = level mean from the level partials (exact mode), else 0; and
+// gbar[nz] = the overall mean (the mean of the level means).
 __global__ __launch_bounds__(256) void level_mean_kernel(const double *__restrict__ part, int lp,
                                                          int nz, double nxy, int exact,
                                                          double *__restrict__ gbar) {
@@ -164,6 +165,12 @@ __global__ __launch_bounds__(256) void level_mean_kernel(const double *__restric
     if (exact)
       for (int q = 0; q < lp; ++q) s += part[(int64_t)k * lp + q];
     gbar[k] = s / nxy;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < nz; ++k) t += gbar[k];
+    gbar[nz] = t / nz;
   }
 }
 
@@ -196,6 +203,113 @@ __global__ __launch_bounds__(256) void mean_profiles_kernel(int nz, double dz,
     const int kp = zmirror(k + 1, nz), km = zmirror(k - 1, nz);
     pgz[k] = (T)((alpha0[kp] * pbar[kp] - alpha0[km] * pbar[km]) / (2.0 * dz));
   }
+}
+
+// ------------------------------------------------ vertically uniform part
+
+// Vertical mean of every column: out[i + nx j] = mean over k of f (FP64,
+// fixed order).  One thread per column; consecutive threads read
+// consecutive cells of a level.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void column_mean_kernel(Grid g, const T *__restrict__ f,
+                                                             double *__restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.nxy) return;
+  double s = 0.0;
+  for (int k = 0; k < g.nz; ++k) s += (double)f[q + g.nxy * k];
+  out[q] = s / g.nz;
+}
+
+// One direction of the separable real Fourier (Hartley) transform of an
+// ny x nx FP64 array a[j][i] (i fastest): along y (axis 1),
+// out[ky][i] = sum_j cas(2 pi ky j / ny) a[j][i]; along x (axis 0),
+// out[j][kx] = sum_i a[j][i] cas(2 pi i kx / nx).  cas values come from
+// the table tab[m] = cas(2 pi m / n), m = 0 .. n-1, indexed by (k j) mod n,
+// advanced incrementally.  out may subtract a constant first (sub, the
+// mean of a; nullable).
+template <int AXIS>
+__global__ __launch_bounds__(kBlock) void hartley_kernel(int nx, int ny,
+                                                         const double *__restrict__ a,
+                                                         const double *__restrict__ tab,
+                                                         const double *__restrict__ sub,
+                                                         double *__restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)nx * ny) return;
+  const int row = (int)(q / nx), col = (int)(q - (int64_t)row * nx);
+  const double c0 = sub ? *sub : 0.0;
+  double s = 0.0;
+  if (AXIS == 1) {  // row = ky, col = i
+    int m = 0;
+    for (int j = 0; j < ny; ++j) {
+      s += tab[m] * (a[(int64_t)j * nx + col] - c0);
+      m += row;
+      if (m >= ny) m -= ny;
+    }
+  } else {  // row = j, col = kx
+    int m = 0;
+    const double *ar = a + (int64_t)row * nx;
+    for (int i = 0; i < nx; ++i) {
+      s += (ar[i] - c0) * tab[m];
+      m += col;
+      if (m >= nx) m -= nx;
+    }
+  }
+  out[q] = s;
+}
+
+// Divide the transform of the vertical-mean right-hand side by the
+// eigenvalue of mode (kx, ky) of the x-y compact Laplacian (and by nx ny,
+// the scale of the inverse transform); mode (0, 0) to zero.
+__global__ __launch_bounds__(kBlock) void hartley_divide_kernel(int nx, int ny, double idx2,
+                                                                double idy2,
+                                                                double *__restrict__ b) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)nx * ny) return;
+  const int ky = (int)(q / nx), kx = (int)(q - (int64_t)ky * nx);
+  const double lam = -(2.0 - 2.0 * cospi(2.0 * kx / nx)) * idx2 -
+                     (2.0 - 2.0 * cospi(2.0 * ky / ny)) * idy2;
+  b[q] = (kx == 0 && ky == 0) ? 0.0 : b[q] / (lam * ((double)nx * ny));
+}
+
+// The sweeps' right-hand side with both uniform parts removed:
+// out = rhs_level - (cmean[i,j] - mean), rhs_level the right-hand side
+// without its level means, cmean the raw right-hand side's column means,
+// mean its overall mean; FP64, rounded once.  out may alias rhs_level.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void remove_columns_kernel(Grid g, const T *rhs_level,
+                                                                const double *__restrict__ cmean,
+                                                                const SolveCtl *__restrict__ ctl,
+                                                                T *out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.n) return;
+  const int64_t c = q % g.nxy;
+  out[q] = (T)((double)rhs_level[q] - (cmean[c] - ctl->rhs_mean));
+}
+
+// The returned iterate of an exact-mode solve: the sweeps' correction d
+// with its level means dbar[k], column means dv and overall mean dbar[nz]
+// added back removed (each zero in exact arithmetic: it removes what
+// rounding put there), plus the vertically uniform part pv, plus (when
+// ctl->guess_kept and gs) the guess with its level means gbar[k] and
+// column means gv removed and its overall mean gbar[nz] added back; FP64
+// sum rounded once, in place.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void combine_kernel(Grid g, T *phi,
+                                                         const double *__restrict__ dbar,
+                                                         const double *__restrict__ dv,
+                                                         const double *__restrict__ pv,
+                                                         const T *__restrict__ gs,
+                                                         const double *__restrict__ gbar,
+                                                         const double *__restrict__ gv,
+                                                         const SolveCtl *__restrict__ ctl) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.n) return;
+  const int k = (int)(q / g.nxy);
+  const int64_t c = q - g.nxy * k;
+  // dbar[nz], gbar[nz]: the overall means
+  double v = (double)phi[q] - dbar[k] - dv[c] + dbar[g.nz] + pv[c];
+  if (gs && ctl->guess_kept) v += (double)gs[q] - gbar[k] - gv[c] + gbar[g.nz];
+  phi[q] = (T)v;
 }
 
 // out = in - ctl->phi_mean (if ctl) + prof[k], in FP64, rounded once.
@@ -328,18 +442,23 @@ __global__ __launch_bounds__(1024) void final_kernel(const double *__restrict__ 
 }
 
 // Defect right-hand side of a starting iterate: rhs_d = rhs - L (phi0 -
-// gbar) in FP64 (gbar: per-level means to remove, nullable), with FP64
-// partial sums of rhs_d^2 (partials[b]) and of rhs^2 (partials[gridDim.x +
-// b]); L the compact Laplacian, periodic x, y and mirror z.  rhs_d nullable
-// (only the sums: the residual of a returned iterate).
+// gbar - gv) in FP64 (gbar: per-level means, gv: per-column means to
+// remove, nullable; a constant drops out of L), with FP64 partial sums of
+// rhs_d^2 (partials[b]) and of rhs^2 (partials[gridDim.x + b]); L the
+// compact Laplacian, periodic x, y and mirror z.  rhs_d nullable (only the
+// sums: the residual of a returned iterate); rhs_d may alias rhs.  With
+// `when`, only if when->guess_kept (and then the partial sums are not
+// written either).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void guess_residual_kernel(Grid g, double ix2, double iy2,
-                                                                double iz2,
-                                                                const T *__restrict__ rhs,
+                                                                double iz2, const T *rhs,
                                                                 const T *__restrict__ phi0,
                                                                 const double *__restrict__ gbar,
-                                                                T *__restrict__ rhs_d,
-                                                                double *__restrict__ partials) {
+                                                                const double *__restrict__ gv,
+                                                                T *rhs_d,
+                                                                double *__restrict__ partials,
+                                                                const SolveCtl *__restrict__ when) {
+  if (when && !when->guess_kept) return;
   double rr = 0.0, bb = 0.0;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < g.n;
        q += (int64_t)gridDim.x * blockDim.x) {
@@ -357,6 +476,13 @@ __global__ __launch_bounds__(kBlock) void guess_residual_kernel(Grid g, double i
          2.0 * c) * iz2;
     if (gbar)
       lap -= (pload(gbar, k + 1, g.nz) - 2.0 * gbar[k] + pload(gbar, k - 1, g.nz)) * iz2;
+    if (gv) {  // the x-y second differences of the guess's column means
+      const double gc = gv[(int64_t)i + g.sy * j];
+      const int ip = pwrap(i + 1, g.nx), im = pwrap(i - 1, g.nx);
+      const int jp = pwrap(j + 1, g.ny), jm = pwrap(j - 1, g.ny);
+      lap -= (gv[ip + g.sy * j] + gv[im + g.sy * j] - 2.0 * gc) * ix2 +
+             (gv[i + g.sy * jp] + gv[i + g.sy * jm] - 2.0 * gc) * iy2;
+    }
     const double b = rhs[q];
     const double d = b - lap;
     if (rhs_d) rhs_d[q] = (T)d;
@@ -499,6 +625,38 @@ void launch_rhs_center(const Grid &g, const T *rhs_in, T *rhs_out, T *phi0, cons
                                                      partials);
 }
 
+template <typename T>
+void launch_column_mean(const Grid &g, const T *f, double *out, hipStream_t s) {
+  column_mean_kernel<T><<<blocks_for(g.nxy), kBlock, 0, s>>>(g, f, out);
+}
+
+void launch_vertical_solve(const Grid &g, const double *cmean, const SolveCtl *ctl,
+                           const double *tab_x, const double *tab_y, double *work, double *pv,
+                           hipStream_t s) {
+  const int nx = g.nx, ny = g.ny;
+  const unsigned nb = blocks_for((int64_t)nx * ny);
+  // rv = cmean - mean; a = Hy rv; b = a Hx / lambda; a = Hy b; pv = a Hx
+  hartley_kernel<1><<<nb, kBlock, 0, s>>>(nx, ny, cmean, tab_y, &ctl->rhs_mean, work);
+  hartley_kernel<0><<<nb, kBlock, 0, s>>>(nx, ny, work, tab_x, nullptr, pv);
+  hartley_divide_kernel<<<nb, kBlock, 0, s>>>(nx, ny, 1.0 / (g.dx * g.dx), 1.0 / (g.dy * g.dy),
+                                              pv);
+  hartley_kernel<1><<<nb, kBlock, 0, s>>>(nx, ny, pv, tab_y, nullptr, work);
+  hartley_kernel<0><<<nb, kBlock, 0, s>>>(nx, ny, work, tab_x, nullptr, pv);
+}
+
+template <typename T>
+void launch_remove_columns(const Grid &g, const T *rhs_level, const double *cmean,
+                           const SolveCtl *ctl, T *out, hipStream_t s) {
+  remove_columns_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g, rhs_level, cmean, ctl, out);
+}
+
+template <typename T>
+void launch_combine(const Grid &g, T *phi, const double *dbar, const double *dv, const double *pv,
+                    const T *guess, const double *gbar, const double *gv, const SolveCtl *ctl,
+                    hipStream_t s) {
+  combine_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g, phi, dbar, dv, pv, guess, gbar, gv, ctl);
+}
+
 void launch_ctl_restart(SolveCtl *ctl, int max_sweeps, hipStream_t s) {
   ctl_restart_kernel<<<1, 64, 0, s>>>(ctl, max_sweeps);
 }
@@ -535,13 +693,22 @@ void launch_extrapolate(const Grid &g, const Profiles<T> &P, const T *p, const T
 }
 
 template <typename T>
-void launch_guess_gate(const Grid &g, const T *rhs, const T *phi0, const double *gbar, T *rhs_d,
-                       double *partials, SolveCtl *ctl, int always_keep, hipStream_t s) {
-  guess_residual_kernel<T><<<kReduceBlocks, kBlock, 0, s>>>(
-      g, 1.0 / (g.dx * g.dx), 1.0 / (g.dy * g.dy), 1.0 / (g.dz * g.dz), rhs, phi0, gbar, rhs_d,
-      partials);
-  guess_gate_kernel<<<1, 1024, 0, s>>>(partials, kReduceBlocks, always_keep, ctl);
-  guess_clear_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g.n, ctl, rhs, rhs_d);
+void launch_guess_gate(const Grid &g, const T *rhs, const T *phi0, const double *gbar,
+                       const double *gv, T *rhs_d, double *partials, SolveCtl *ctl,
+                       int always_keep, hipStream_t s) {
+  const double ix2 = 1.0 / (g.dx * g.dx), iy2 = 1.0 / (g.dy * g.dy), iz2 = 1.0 / (g.dz * g.dz);
+  if (rhs != rhs_d) {
+    guess_residual_kernel<T><<<kReduceBlocks, kBlock, 0, s>>>(g, ix2, iy2, iz2, rhs, phi0, gbar,
+                                                              gv, rhs_d, partials, nullptr);
+    guess_gate_kernel<<<1, 1024, 0, s>>>(partials, kReduceBlocks, always_keep, ctl);
+    guess_clear_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g.n, ctl, rhs, rhs_d);
+  } else {  // in place: the sums, the gate, then the defect if the guess is kept
+    guess_residual_kernel<T><<<kReduceBlocks, kBlock, 0, s>>>(g, ix2, iy2, iz2, rhs, phi0, gbar,
+                                                              gv, nullptr, partials, nullptr);
+    guess_gate_kernel<<<1, 1024, 0, s>>>(partials, kReduceBlocks, always_keep, ctl);
+    guess_residual_kernel<T><<<kReduceBlocks, kBlock, 0, s>>>(g, ix2, iy2, iz2, rhs, phi0, gbar,
+                                                              gv, rhs_d, partials, ctl);
+  }
 }
 
 template <typename T>
@@ -549,7 +716,7 @@ void launch_returned_residual(const Grid &g, const T *rhs, const T *phi, double 
                               SolveCtl *ctl, hipStream_t s) {
   guess_residual_kernel<T><<<kReduceBlocks, kBlock, 0, s>>>(
       g, 1.0 / (g.dx * g.dx), 1.0 / (g.dy * g.dy), 1.0 / (g.dz * g.dz), rhs, phi, nullptr,
-      nullptr, partials);
+      nullptr, nullptr, partials, nullptr);
   final_kernel<<<1, 1024, 0, s>>>(partials, kReduceBlocks, kFinalReturned, ctl, 0.0, 0.0, 0,
                                   nullptr);
 }
@@ -582,6 +749,12 @@ void launch_ctl_reset(SolveCtl *ctl, int max_sweeps, int fixed, hipStream_t s) {
                                      const SolveCtl *, double *, hipStream_t);                   \
   template void launch_level_sum<T>(const Grid &, const T *, double *, hipStream_t);           \
   template void launch_zero<T>(const Grid &, T *, hipStream_t);                                 \
+  template void launch_column_mean<T>(const Grid &, const T *, double *, hipStream_t);          \
+  template void launch_remove_columns<T>(const Grid &, const T *, const double *,               \
+                                         const SolveCtl *, T *, hipStream_t);                   \
+  template void launch_combine<T>(const Grid &, T *, const double *, const double *,            \
+                                  const double *, const T *, const double *, const double *,    \
+                                  const SolveCtl *, hipStream_t);                               \
   template void launch_mean_profiles<T>(const Grid &, const double *, const double *,          \
                                         const double *, int, double *, T *, T *, T *,          \
                                         hipStream_t);                                          \
@@ -593,8 +766,9 @@ void launch_ctl_reset(SolveCtl *ctl, int max_sweeps, int fixed, hipStream_t s) {
                                   const SolveCtl *, T *, T *, T *, T *, hipStream_t);            \
   template void launch_sub_mean<T>(const Grid &, const T *, const SolveCtl *, T *, hipStream_t); \
   template void launch_block_sum<T>(const T *, int64_t, int, double *, hipStream_t);            \
-  template void launch_guess_gate<T>(const Grid &, const T *, const T *, const double *, T *,   \
-                                     double *, SolveCtl *, int, hipStream_t);                    \
+  template void launch_guess_gate<T>(const Grid &, const T *, const T *, const double *,        \
+                                     const double *, T *, double *, SolveCtl *, int,             \
+                                     hipStream_t);                                               \
   template void launch_add_guess<T>(const Grid &, const T *, const double *, const SolveCtl *,   \
                                     T *, hipStream_t);                                           \
   template void launch_extrapolate<T>(const Grid &, const Profiles<T> &, const T *, const T *,   \

@@ -35,13 +35,19 @@ constexpr int kProfT = 7;  // storage-type profiles
 constexpr int kPartialCap = kPartials + 1024;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+size_t mean_d_count(size_t nz) { return 5 * nz + 2; }
+size_t pbar_index(size_t nz) { return 2 * nz; }
 
 struct Layout {
   size_t field[F_COUNT];
   size_t prof_d;    // 4 x nz doubles: p0, lnp, alpha0, rho0
   size_t prof_t;    // 7 x nz elems: rho0, alpha0, beta, wsub, pgz, cbar, phigz
   size_t lvl_part;  // kPartials doubles: per-level partial sums
-  size_t mean_d;    // 4 x nz doubles: rsub, phibar, gbar, pbar (the FP64 mean-mode state)
+  size_t mean_d;    // kMeanD(nz) doubles: rsub, phibar, pbar (nz each), gbar, dbar (nz + 1
+                    // each: level means and their mean), the FP64 mean-mode state
+  size_t vert;      // LES_MEAN_EXACT: 5 nx ny + nx + ny doubles (column means of the
+                    // rhs, of a guess and of a correction; the vertically uniform part;
+                    // transform work; cas tables along x and y)
   size_t partials;  // kPartialCap doubles
   size_t partials2; // kPartials doubles: every other residual check's partials
   size_t ctl;       // SolveCtl
@@ -98,7 +104,8 @@ int validate(const les_config *c) {
     return fail(LES_ERR_ARG, "T_ice must be in (0, Tf) for LES_PHASE_RAMP");
   if (c->guess < LES_GUESS_ZERO || c->guess > LES_GUESS_LEARNED)
     return fail(LES_ERR_ARG, "unknown guess mode %d", c->guess);
-  if (c->mean_mode != LES_MEAN_SWEPT && c->mean_mode != LES_MEAN_EXACT)
+  if (c->mean_mode != LES_MEAN_SWEPT && c->mean_mode != LES_MEAN_LEVEL &&
+      c->mean_mode != LES_MEAN_EXACT)
     return fail(LES_ERR_ARG, "unknown mean mode %d", c->mean_mode);
   if (c->reserved != 0) return fail(LES_ERR_ARG, "reserved must be 0");
   return LES_OK;
@@ -122,7 +129,10 @@ Layout layout_of(const les_config *c) {
   L.lvl_part = off;
   off = align_up(off + kPartials * sizeof(double));
   L.mean_d = off;
-  off = align_up(off + 4 * (size_t)c->nz * sizeof(double));
+  off = align_up(off + mean_d_count(c->nz) * sizeof(double));
+  L.vert = off;
+  if (c->mean_mode == LES_MEAN_EXACT)
+    off = align_up(off + (5 * (size_t)c->nx * c->ny + c->nx + c->ny) * sizeof(double));
   L.partials = off;
   off = align_up(off + kPartialCap * sizeof(double));
   L.partials2 = off;
@@ -183,7 +193,10 @@ namespace {
 char *ws(const les_handle *h, size_t off) { return (char *)h->buf.workspace + off; }
 
 // Extreme nonzero eigenvalues of -D^{-1} L (compact Laplacian, periodic x/y,
-// mirror-Neumann z): sums of (2 - 2 cos theta)/Delta^2 per axis over D.
+// mirror-Neumann z) on the modes the sweeps act on: sums of
+// (2 - 2 cos theta)/Delta^2 per axis over D.  With LES_MEAN_EXACT those
+// modes have both horizontal and vertical structure, so the smallest is
+// the smallest horizontal eigenvalue plus the smallest vertical one.
 void jacobi_spectrum(const les_config *c, double *lo, double *hi) {
   const double pi = 3.14159265358979323846;
   const double ax = 1.0 / (c->dx * c->dx), ay = 1.0 / (c->dy * c->dy), az = 1.0 / (c->dz * c->dz);
@@ -191,10 +204,10 @@ void jacobi_spectrum(const les_config *c, double *lo, double *hi) {
   auto per = [&](int n, int m) { return 2.0 - 2.0 * std::cos(2.0 * pi * m / n); };
   auto mir = [&](int n, int m) { return 2.0 - 2.0 * std::cos(pi * m / n); };
   // a periodic axis of one cell has only its constant mode
-  double s = mir(c->nz, 1) * az;
-  if (c->nx > 1) s = std::min(s, per(c->nx, 1) * ax);
-  if (c->ny > 1) s = std::min(s, per(c->ny, 1) * ay);
-  *lo = s / D;
+  double h = per(c->nx, 1) * ax;  // nx >= 2
+  if (c->ny > 1) h = std::min(h, per(c->ny, 1) * ay);
+  const double z1 = mir(c->nz, 1) * az;
+  *lo = (c->mean_mode == LES_MEAN_EXACT ? h + z1 : std::min(h, z1)) / D;
   *hi = (per(c->nx, c->nx / 2) * ax + per(c->ny, c->ny / 2) * ay + mir(c->nz, c->nz - 1) * az) / D;
 }
 
@@ -208,10 +221,16 @@ struct View {
   double *diag;
   T *u, *v, *w, *thl, *qt, *p;
   // mean-mode state: level partials, per-level centring values, the
-  // horizontally uniform part of the current solution, of a guess, and of p'
-  double *lvl_part, *rsub, *phibar, *gbar, *pbar;
+  // horizontally uniform part of the current solution, of a guess, of p' and
+  // of a correction (gbar, dbar: nz level means and their mean)
+  double *lvl_part, *rsub, *phibar, *gbar, *pbar, *dbar;
+  // vertically uniform part (LES_MEAN_EXACT): column means of the rhs
+  // (cmean), of a guess (gv), of a correction (dv); the part itself (pv);
+  // transform work; cas tables
+  double *cmean, *gv, *dv, *pv, *work, *tab_x, *tab_y;
   T *pgz_w, *cbar_w, *phigz_w;  // writable views of the profile terms
-  int exact;                    // LES_MEAN_EXACT
+  int exact;                    // the horizontally uniform part solved exactly
+  int vert;                     // the vertically uniform part too (LES_MEAN_EXACT)
 };
 
 template <typename T>
@@ -236,9 +255,20 @@ View<T> view_of(const les_handle *h) {
   double *md = (double *)ws(h, h->lay.mean_d);
   V.rsub = md;
   V.phibar = md + nz;
-  V.gbar = md + 2 * nz;
-  V.pbar = md + 3 * nz;
-  V.exact = h->cfg.mean_mode == LES_MEAN_EXACT;
+  V.pbar = md + pbar_index(nz);
+  V.gbar = md + 3 * nz;
+  V.dbar = md + 4 * nz + 1;
+  V.exact = h->cfg.mean_mode != LES_MEAN_SWEPT;
+  V.vert = h->cfg.mean_mode == LES_MEAN_EXACT;
+  const size_t nxy = (size_t)h->cfg.nx * h->cfg.ny;
+  double *vd = (double *)ws(h, h->lay.vert);
+  V.cmean = vd;
+  V.gv = vd + nxy;
+  V.dv = vd + 2 * nxy;
+  V.pv = vd + 3 * nxy;
+  V.work = vd + 4 * nxy;
+  V.tab_x = vd + 5 * nxy;
+  V.tab_y = V.tab_x + h->cfg.nx;
   V.partials = (double *)ws(h, h->lay.partials);
   V.partials2 = (double *)ws(h, h->lay.partials2);
   V.ctl = (SolveCtl *)ws(h, h->lay.ctl);
@@ -283,7 +313,7 @@ int upload_profiles(les_handle *h) {
   const int nz = c.nz;
   std::vector<double> pd(4 * (size_t)nz);
   std::vector<T> pt(kProfT * (size_t)nz, T(0));
-  const std::vector<double> md(4 * (size_t)nz, 0.0);  // no mean-mode part yet
+  const std::vector<double> md(mean_d_count(nz), 0.0);  // no mean-mode part yet
   const double H = nz * c.dz, zs = (1.0 - c.sponge_frac) * H;
   const double pi = 3.14159265358979323846;
   for (int k = 0; k < nz; ++k) {
@@ -313,6 +343,19 @@ int upload_profiles(les_handle *h) {
                          hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipMemcpyAsync(ws(h, h->lay.mean_d), md.data(), md.size() * sizeof(double),
                          hipMemcpyHostToDevice, h->stream));
+  // cas(2 pi m / n) = cos + sin, m < n, for the transforms of the
+  // vertically uniform part
+  std::vector<double> tab;
+  if (c.mean_mode == LES_MEAN_EXACT) {
+    for (int n : {c.nx, c.ny})
+      for (int m = 0; m < n; ++m) {
+        const double t = 2.0 * pi * m / n;
+        tab.push_back(std::cos(t) + std::sin(t));
+      }
+    const size_t nxy = (size_t)c.nx * c.ny;
+    HIP_TRY(hipMemcpyAsync((double *)ws(h, h->lay.vert) + 5 * nxy, tab.data(),
+                           tab.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  }
   HIP_TRY(hipStreamSynchronize(h->stream));
   return LES_OK;
 }
@@ -328,9 +371,12 @@ struct SweepTiming {
 // Centred right-hand side of a solve into F_RHS (rhs_in may be F_RHS
 // itself): the mean removed and, with the horizontally uniform part solved
 // exactly, the horizontal mean of every level, whose part of the solution
-// goes to V.phibar (zero otherwise).  Resets the control block; the
-// stopping test is relative to ||rhs_in - mean||, the norm of the whole
-// centred right-hand side.
+// goes to V.phibar (zero otherwise).  With the vertically uniform part
+// solved exactly too (V.vert), that part V.pv from the column means of the
+// right-hand side, and the sweeps' right-hand side F_RHSD = F_RHS without
+// them (Sec. 2.3 with the uniform modes split off; Eq. 7's operator).
+// Resets the control block; the stopping test is relative to
+// ||rhs_in - mean||, the norm of the whole centred right-hand side.
 template <typename T>
 int prepare_rhs(les_handle *h, View<T> &V, const T *rhs_in, int max_sweeps, bool fixed) {
   const Grid &g = h->grid;
@@ -339,27 +385,41 @@ int prepare_rhs(les_handle *h, View<T> &V, const T *rhs_in, int max_sweeps, bool
   launch_ctl_reset(V.ctl, max_sweeps, fixed ? 1 : 0, s);
   launch_level_sum<T>(g, rhs_in, V.lvl_part, s);
   launch_mean_mode(g, V.lvl_part, V.exact, V.ctl, V.rsub, V.phibar, s);
+  if (V.vert) {
+    launch_column_mean<T>(g, rhs_in, V.cmean, s);
+    launch_vertical_solve(g, V.cmean, V.ctl, V.tab_x, V.tab_y, V.work, V.pv, s);
+  }
   // the sweeps start from zero in F_PHI0
   launch_rhs_center<T>(g, rhs_in, V.f[F_RHS], V.f[F_PHI0], V.rsub, V.ctl, V.partials, s);
   launch_final(V.partials, level_parts(g) * g.nz, kFinalRhsNorm, V.ctl, (double)g.n, tol * tol,
                0, nullptr, s);
+  if (V.vert) launch_remove_columns<T>(g, V.f[F_RHS], V.cmean, V.ctl, V.f[F_RHSD], s);
   LAUNCH_TRY();
   return LES_OK;
 }
 
+// The right-hand side the sweeps take from the zero start.
+template <typename T>
+T *sweep_rhs(View<T> &V) {
+  return V.vert ? V.f[F_RHSD] : V.f[F_RHS];
+}
+
 // Starting iterate `guess` of the solve prepared by prepare_rhs, in defect
-// form: F_RHSD = F_RHS - L(guess - gbar), gbar its horizontal means per
-// level when those are solved exactly (already part of V.phibar).  The
-// guess is kept if always_keep or its residual is below the zero start's;
-// a dropped guess leaves F_RHSD = F_RHS.
+// form: F_RHSD = (zero start's rhs) - L(guess - gbar - gv), gbar its
+// horizontal means per level when those are solved exactly (already part
+// of V.phibar), gv its column means when those are (already part of V.pv).
+// The guess is kept if always_keep or its residual is below the zero
+// start's; a dropped guess leaves F_RHSD the zero start's right-hand side.
 template <typename T>
 int prepare_guess(les_handle *h, View<T> &V, const T *guess, bool always_keep) {
   const Grid &g = h->grid;
   hipStream_t s = h->stream;
   launch_level_sum<T>(g, guess, V.lvl_part, s);
   launch_level_mean(g, V.lvl_part, V.exact, V.gbar, s);
-  launch_guess_gate<T>(g, V.f[F_RHS], guess, V.exact ? V.gbar : nullptr, V.f[F_RHSD], V.partials,
-                       V.ctl, always_keep ? 1 : 0, s);
+  if (V.vert) launch_column_mean<T>(g, guess, V.gv, s);
+  launch_guess_gate<T>(g, sweep_rhs(V), guess, V.exact ? V.gbar : nullptr,
+                       V.vert ? V.gv : nullptr, V.f[F_RHSD], V.partials, V.ctl,
+                       always_keep ? 1 : 0, s);
   LAUNCH_TRY();
   return LES_OK;
 }
@@ -566,8 +626,10 @@ int run_sweeps(les_handle *h, View<T> &V, const T *rhs, int fixed, int cap, Solv
 }
 
 // A whole solve after prepare_rhs (and prepare_guess if `guess`): the
-// sweeps, then for a kept guess phi = guess - gbar + correction and the FP64
-// residual of that returned iterate.  gated: a kept guess whose solve
+// sweeps, then for a kept guess phi = guess - gbar + correction (with
+// V.vert: the correction without its level and column means, plus pv, plus
+// the guess without its level and column means) and the FP64 residual of
+// that returned iterate.  gated: a kept guess whose solve
 // reaches the cap, or (budget > 0) the first residual check at or beyond
 // `budget` sweeps, or whose returned iterate misses the tolerance, is
 // dropped and the sweeps repeated from the zero start (unless the sweep
@@ -595,30 +657,56 @@ int solve_prepared(les_handle *h, View<T> &V, const T *guess, bool gated, int fi
       LAUNCH_TRY();
     }
   }
-  int rc = run_sweeps<T>(h, V, guess ? V.f[F_RHSD] : V.f[F_RHS], fixed, cap, &r, &phi, timing);
+  // With the vertically uniform part exact, every returned iterate is
+  // assembled (the correction projected, plus pv and the guess) and its
+  // residual taken against F_RHS.
+  auto assemble = [&](T *x) -> int {
+    launch_level_sum<T>(g, x, V.lvl_part, s);
+    launch_level_mean(g, V.lvl_part, 1, V.dbar, s);
+    launch_column_mean<T>(g, x, V.dv, s);
+    launch_combine<T>(g, x, V.dbar, V.dv, V.pv, guess, V.gbar, V.gv, V.ctl, s);
+    launch_returned_residual<T>(g, V.f[F_RHS], x, V.partials, V.ctl, s);
+    LAUNCH_TRY();
+    HIP_TRY(hipMemcpyAsync(&h->ctl_host[0], V.ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return LES_OK;
+  };
+  int rc = run_sweeps<T>(h, V, guess ? V.f[F_RHSD] : sweep_rhs(V), fixed, cap, &r, &phi, timing);
   if (rc) return rc;
   int sweeps = r.stop_m, first = 0;
   int flag = guess ? (r.guess_kept ? 1 : 2) : 0;
   double res2 = r.res_norm2;
-  if (guess && r.guess_kept) {
-    launch_add_guess<T>(g, guess, V.exact ? V.gbar : nullptr, V.ctl, phi, s);
-    launch_returned_residual<T>(g, V.f[F_RHS], phi, V.partials, V.ctl, s);
-    LAUNCH_TRY();
-    HIP_TRY(hipMemcpyAsync(&h->ctl_host[0], V.ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+  if (V.vert || (guess && r.guess_kept)) {
+    if (V.vert) {
+      if ((rc = assemble(phi))) return rc;
+    } else {
+      launch_add_guess<T>(g, guess, V.exact ? V.gbar : nullptr, V.ctl, phi, s);
+      launch_returned_residual<T>(g, V.f[F_RHS], phi, V.partials, V.ctl, s);
+      LAUNCH_TRY();
+      HIP_TRY(hipMemcpyAsync(&h->ctl_host[0], V.ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+    }
     r = h->ctl_host[0];
     res2 = r.res_out2;
     const bool missed = r.done == 3 || !(res2 <= r.tol2);
-    if (gated && fixed == 0 && missed) {
+    if (guess && r.guess_kept && gated && fixed == 0 && missed) {
       launch_ctl_restart(V.ctl, c.poisson_max_sweeps, s);
       launch_zero<T>(g, V.f[F_PHI0], s);
+      // the zero start's right-hand side again (the defect overwrote it)
+      if (V.vert) launch_remove_columns<T>(g, V.f[F_RHS], V.cmean, V.ctl, V.f[F_RHSD], s);
       LAUNCH_TRY();
-      rc = run_sweeps<T>(h, V, V.f[F_RHS], 0, 0, &r, &phi, timing);
+      rc = run_sweeps<T>(h, V, sweep_rhs(V), 0, 0, &r, &phi, timing);
       if (rc) return rc;
       first = sweeps;
       sweeps += r.stop_m;
       res2 = r.res_norm2;
       flag = 3;
+      if (V.vert) {  // guess_kept is 0 now: pv and the projected correction
+        if ((rc = assemble(phi))) return rc;
+        r = h->ctl_host[0];
+        res2 = r.res_out2;
+        if (r.done == 1 && !(res2 <= r.tol2)) r.done = 3;
+      }
     } else if (r.done == 1 && !(res2 <= r.tol2)) {
       r.done = 3;  // the returned iterate misses the tolerance
     }
@@ -1213,7 +1301,7 @@ int les_export_state(les_handle *h, void *dst) {
     e = copy(d + S.zsw, h->zero_sweeps.data(), (size_t)c.n_subiter * sizeof(int32_t),
              hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = copy(d + S.pbar, ws(h, h->lay.mean_d) + 3 * (size_t)c.nz * sizeof(double),
+    e = copy(d + S.pbar, ws(h, h->lay.mean_d) + pbar_index(c.nz) * sizeof(double),
              (size_t)c.nz * sizeof(double), hipMemcpyDeviceToDevice);
   if (e == hipSuccess && c.guess == LES_GUESS_EXTRAPOLATE)
     e = copy(d + S.pm2, ws(h, h->lay.field[F_PM2]), n * es, hipMemcpyDeviceToDevice);
@@ -1253,7 +1341,7 @@ int les_import_state(les_handle *h, const void *src) {
   auto copy = [&](void *to, const void *from, size_t bytes) {
     return hipMemcpyAsync(to, from, bytes, hipMemcpyDeviceToDevice, h->stream);
   };
-  hipError_t e = copy(ws(h, h->lay.mean_d) + 3 * (size_t)c.nz * sizeof(double), d + S.pbar,
+  hipError_t e = copy(ws(h, h->lay.mean_d) + pbar_index(c.nz) * sizeof(double), d + S.pbar,
                       (size_t)c.nz * sizeof(double));
   if (e == hipSuccess && c.guess == LES_GUESS_EXTRAPOLATE)
     e = copy(ws(h, h->lay.field[F_PM2]), d + S.pm2, n * es);
@@ -1289,8 +1377,8 @@ int les_set_pressure_profile(les_handle *h, const double *pbar_host) {
   int rc = check_handle(h);
   if (rc) return rc;
   if (!pbar_host) return fail(LES_ERR_ARG, "pbar_host is NULL");
-  if (h->cfg.mean_mode != LES_MEAN_EXACT)
-    return fail(LES_ERR_STATE, "les_set_pressure_profile needs LES_MEAN_EXACT");
+  if (h->cfg.mean_mode == LES_MEAN_SWEPT)
+    return fail(LES_ERR_STATE, "les_set_pressure_profile needs LES_MEAN_LEVEL or LES_MEAN_EXACT");
   for (int k = 0; k < h->cfg.nz; ++k)
     if (!std::isfinite(pbar_host[k])) return fail(LES_ERR_ARG, "pbar_host[%d] is not finite", k);
   rc = h->cfg.precision == LES_FP64 ? set_pressure_profile_impl<double>(h, pbar_host)

@@ -132,8 +132,29 @@ void launch_level_sum(const Grid &g, const T *f, double *part, hipStream_t s);
 // part (zero otherwise).
 void launch_mean_mode(const Grid &g, const double *part, int exact, SolveCtl *ctl, double *rsub,
                       double *pb, hipStream_t s);
-// gbar[k] = level mean from the level sums if exact, else 0.
+// gbar[k] = level mean from the level sums if exact, else 0; gbar[nz] =
+// the overall mean (gbar holds nz + 1 values).
 void launch_level_mean(const Grid &g, const double *part, int exact, double *gbar, hipStream_t s);
+// out[i + nx j] = vertical mean of column (i, j) of f (FP64).
+template <typename T>
+void launch_column_mean(const Grid &g, const T *f, double *out, hipStream_t s);
+// The vertically uniform part: pv solves the x-y compact Laplacian
+// Lh pv = cmean - ctl->rhs_mean exactly (separable real Fourier transforms,
+// tab_x[m] = cas(2 pi m / nx), tab_y alike; work: nx ny doubles), mean zero.
+void launch_vertical_solve(const Grid &g, const double *cmean, const SolveCtl *ctl,
+                           const double *tab_x, const double *tab_y, double *work, double *pv,
+                           hipStream_t s);
+// out = rhs_level - (cmean[i, j] - ctl->rhs_mean), FP64 rounded once (out
+// may alias rhs_level).
+template <typename T>
+void launch_remove_columns(const Grid &g, const T *rhs_level, const double *cmean,
+                           const SolveCtl *ctl, T *out, hipStream_t s);
+// phi = (phi - dbar[k] - dv[i, j] + dbar[nz]) + pv[i, j] + (guess kept:
+// guess - gbar[k] - gv[i, j] + gbar[nz]), FP64 rounded once, in place.
+template <typename T>
+void launch_combine(const Grid &g, T *phi, const double *dbar, const double *dv, const double *pv,
+                    const T *guess, const double *gbar, const double *gv, const SolveCtl *ctl,
+                    hipStream_t s);
 // Storage-type profiles of a solution's horizontally uniform part pb
 // (nullable): phigz = d_c pb/dz, cbar = App. A fourth difference in z, and
 // with add_p pbar += rho0 pb; then pgz = d_c(alpha0 pbar)/dz.
@@ -186,15 +207,16 @@ template <typename T>
 void launch_extrapolate(const Grid &g, const Profiles<T> &P, const T *p, const T *p_prev, T *phi0,
                         hipStream_t s);
 
-// Starting iterate phi0 - gbar (gbar: per-level means to remove, nullable)
-// of a solve of L phi = rhs (rhs centred), in defect form: rhs_d = rhs -
-// L(phi0 - gbar) (FP64 arithmetic), so the sweeps solve L delta = rhs_d from
-// zero and phi = phi0 - gbar + delta.  The iterate is kept if always_keep
+// Starting iterate phi0 - gbar - gv (gbar: per-level means, gv: per-column
+// means to remove, each nullable) of a solve of L phi = rhs (rhs centred),
+// in defect form: rhs_d = rhs - L(phi0 - gbar - gv) (FP64 arithmetic; rhs_d
+// may alias rhs), so the sweeps solve L delta = rhs_d from zero.  The iterate is kept if always_keep
 // or ||rhs_d||_2 < ||rhs||_2 (the zero start's residual); otherwise rhs_d =
 // rhs.  Sets ctl->guess_kept.
 template <typename T>
-void launch_guess_gate(const Grid &g, const T *rhs, const T *phi0, const double *gbar, T *rhs_d,
-                       double *partials, SolveCtl *ctl, int always_keep, hipStream_t s);
+void launch_guess_gate(const Grid &g, const T *rhs, const T *phi0, const double *gbar,
+                       const double *gv, T *rhs_d, double *partials, SolveCtl *ctl,
+                       int always_keep, hipStream_t s);
 // phi += phi0 - gbar (FP64 sum, rounded once) when ctl->guess_kept.
 template <typename T>
 void launch_add_guess(const Grid &g, const T *phi0, const double *gbar, const SolveCtl *ctl,

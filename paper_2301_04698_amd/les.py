@@ -25,8 +25,8 @@ LES_NO_SLIP, LES_FREE_SLIP = 0, 1
 WALLS = {"no_slip": LES_NO_SLIP, "free_slip": LES_FREE_SLIP}
 LES_PHASE_HEAVISIDE, LES_PHASE_RAMP = 0, 1
 PHASES = {"heaviside": LES_PHASE_HEAVISIDE, "ramp": LES_PHASE_RAMP}
-LES_MEAN_SWEPT, LES_MEAN_EXACT = 0, 1
-MEAN_MODES = {"swept": LES_MEAN_SWEPT, "exact": LES_MEAN_EXACT}
+LES_MEAN_SWEPT, LES_MEAN_LEVEL, LES_MEAN_EXACT = 0, 1, 2
+MEAN_MODES = {"swept": LES_MEAN_SWEPT, "level": LES_MEAN_LEVEL, "exact": LES_MEAN_EXACT}
 LES_GUESS_ZERO, LES_GUESS_EXTRAPOLATE, LES_GUESS_PREVIOUS, LES_GUESS_LEARNED = 0, 1, 2, 3
 GUESS_MODES = {"zero": LES_GUESS_ZERO, "extrapolate": LES_GUESS_EXTRAPOLATE,
                "previous": LES_GUESS_PREVIOUS, "learned": LES_GUESS_LEARNED}

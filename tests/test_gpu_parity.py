@@ -98,6 +98,32 @@ def test_poisson_degenerate_grids_match_oracle(gpu, oracle_lib, shape):
     assert e <= 1e-11, e
 
 
+@pytest.mark.parametrize("mean_mode", ["exact", "level", "swept"])
+@pytest.mark.parametrize("shape", [(12, 9, 15), (33, 1, 7), (10, 14, 2)])
+def test_poisson_mean_modes_match_oracle(gpu, oracle_lib, shape, mean_mode):
+    """Every split of the uniform parts (none, the horizontally uniform part
+    exact, both uniform parts exact) at odd and degenerate horizontal sizes
+    (transforms over 15 x 9, 7 x 1 and 2 x 14 points): the same sweep count
+    as the oracle and the same solution.  The right-hand side carries large
+    uniform parts of both kinds."""
+    import torch
+    nz, ny, nx = shape
+    p = li.workload("C1", nx=nx, ny=ny, nz=nz, dx=40.0, dy=30.0, dz=10.0, poisson_tol=1e-10,
+                    poisson_scheme="chebyshev", mean_mode=mean_mode)
+    rng = np.random.default_rng(25)
+    rhs = (li.random_field(shape, seed=25) + 3.0 * rng.standard_normal((nz, 1, 1))
+           + 2.0 * rng.standard_normal((1, ny, nx)))
+    phi_o, st_o = oracle_lib.poisson(p, rhs)
+    sim = gpu.LES(p)
+    phi_g, st_g, rc = sim.poisson_solve(torch.from_numpy(rhs))
+    print(f"{mean_mode} {shape}: {st_o['sweeps']} sweeps", flush=True)
+    assert rc == 0 and st_o["status"] == 0 and st_g["status"] == 0
+    assert st_g["sweeps"] == st_o["sweeps"]
+    assert st_g["res_norm"] <= 1e-10 * st_g["rhs_norm"]
+    assert rel(phi_g.cpu().numpy(), phi_o) <= 1e-11
+    sim.close()
+
+
 @pytest.mark.parametrize("every,spl", [(1, 1), (3, 1), (1, 2), (4, 2), (25, 2)])
 def test_poisson_check_intervals_match_oracle(gpu, oracle_lib, every, spl):
     """Residual checks every 1, 3, 4 or 25 sweeps with one- and two-sweep
@@ -126,14 +152,14 @@ def test_gated_guess_kept_rejected_and_capped(gpu, oracle_lib):
     whose sweeps reach the cap is dropped and the sweeps repeated from the
     zero start, so the solve still ends converged.  The right-hand side is
     one eigenmode the fixed-weight sweep removes in a few sweeps; the guesses
-    err by the slowest horizontal mode."""
+    err by the slowest mode with horizontal and vertical structure."""
     import torch
     base = li.workload("C1", nx=16, ny=16, nz=16, dx=40.0, dy=40.0, dz=10.0,
                        poisson_scheme="jacobi", poisson_tol=1e-10, poisson_check_every=5)
     k, j, i = np.meshgrid(np.arange(16), np.arange(16), np.arange(16), indexing="ij")
     mode = (np.cos(2 * np.pi * 4 * i / 16) * np.cos(2 * np.pi * 4 * j / 16)
             * np.cos(np.pi * 8 * (k + 0.5) / 16))
-    v = np.cos(2 * np.pi * (i + 0.5) / 16)
+    v = np.cos(2 * np.pi * (i + 0.5) / 16) * np.cos(np.pi * (k + 0.5) / 16)
     rhs = oracle_lib.laplacian(base, mode)
     phi0, s0 = oracle_lib.poisson(base, rhs)
     a = 0.5 * np.linalg.norm(rhs) / np.linalg.norm(oracle_lib.laplacian(base, v))
@@ -339,7 +365,7 @@ def test_step_c1_fp64_one_step(gpu, oracle_lib):
         assert b["rhs_norm"] == pytest.approx(a["rhs_norm"], rel=1e-10)
 
 
-@pytest.mark.parametrize("mean_mode", ["exact", "swept"])
+@pytest.mark.parametrize("mean_mode", ["exact", "level", "swept"])
 def test_step_c1m_fp64_all_physics(gpu, oracle_lib, mean_mode):
     """Saturated cells, surface fluxes, radiation, sponge, Coriolis, SGS with
     a perturbed velocity field; 2 steps, K = 2; the horizontally uniform

@@ -87,12 +87,18 @@ enum { LES_MEAN_SWEPT = 0, LES_MEAN_LEVEL = 1, LES_MEAN_EXACT = 2 };
  *                          previous step's solution of the same
  *                          sub-iteration (zero on the first step)
  *   LES_GUESS_LEARNED      as LES_GUESS_PREVIOUS, plus the correction of
- *                          the guess network of les_cnn.h (parameters
- *                          bound with les_bind_cnn before the second step)
+ *                          the one-input guess network of les_cnn.h
+ *                          (parameters bound with les_bind_cnn before the
+ *                          second step)
+ *   LES_GUESS_LEARNED3     first solve of a step: the three-input guess
+ *                          network's guess from the previous pressures and
+ *                          the divergence (base alpha0 (p^n - p^{n-1}) as
+ *                          with LES_GUESS_EXTRAPOLATE, plus the network's
+ *                          correction); later solves start from 0
  * The solve always runs to the same residual tolerance: a guess only
  * changes the number of sweeps, never the acceptance test. */
 enum { LES_GUESS_ZERO = 0, LES_GUESS_EXTRAPOLATE = 1, LES_GUESS_PREVIOUS = 2,
-       LES_GUESS_LEARNED = 3 };
+       LES_GUESS_LEARNED = 3, LES_GUESS_LEARNED3 = 4 };
 
 /* Run configuration.  nx >= 2, ny >= 1 (ny = 1: a two-dimensional x-z run)
  * and nz >= 4; one z plane of a field at most 2 GiB (nx*ny <= 2^29 in FP32,
@@ -220,6 +226,12 @@ typedef struct les_step_opts {
                                    of the raw rhs.  The whole centred rhs is
                                    dump_rhs + (first profile - mean) and the
                                    whole solution dump_phi + second profile */
+  void *dump_base;              /* device, n_subiter*n elements or NULL: the
+                                   field each solve of the last step started
+                                   its guess from (the previous solution, or
+                                   the extrapolated pressure change before
+                                   any network correction; zero where the
+                                   solve had no guess) */
 } les_step_opts;
 
 typedef struct les_step_stats {

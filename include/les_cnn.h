@@ -12,20 +12,28 @@
  *     phi_0 = base + (s / d) CNN(r / s),
  * base = the previous step's solution of the same sub-iteration (a previous
  * pressure correction), r = rhs - L base its residual for the new
- * right-hand side, s = RMS(r), d = 2/dx^2 + 2/dy^2 + 2/dz^2.
+ * right-hand side, s = RMS(r), d = 2/dx^2 + 2/dy^2 + 2/dz^2 (the one-input
+ * network).  With LES_GUESS_LEARNED3 the first solve of each step starts
+ * from
+ *     phi_0 = base + (s / d) CNN(r / s, base d / s, rhs / s),
+ * base = alpha0 (p^n - p^{n-1}) (the previous pressures), r and s as above
+ * (the three-input network: the previous pressures and the divergence
+ * right-hand side, their differences formed in FP64 before any rounding,
+ * so the step-to-step change is not lost to bfloat16).
  *
- * Network.  Four 3x3x3 convolutions with biases, channels 1 -> 16 -> 16 ->
- * 16 -> 1, leaky ReLU of slope alpha after the first three.  Weights and
- * every layer input are rounded to bfloat16 (nearest even); sums are FP32
- * (the 16 -> 16 layers on the matrix cores); the output is FP32.
+ * Network.  Four 3x3x3 convolutions with biases, channels C -> 16 -> 16 ->
+ * 16 -> 1 (C = 1 or 3 inputs), leaky ReLU of slope alpha after the first
+ * three.  Weights and every layer input are rounded to bfloat16 (nearest
+ * even); sums are FP32 (the first three layers on the matrix cores); the
+ * output is FP32.
  * x and y wrap on whole fields (periodic = 1) or are "valid" on training
  * crops (periodic = 0: each layer trims one cell per side, 8 in total);
  * every layer reads the even mirror of its input in z.
  *
- * Parameters.  One FP32 vector of les_cnn_param_count() values in device
+ * Parameters.  One FP32 vector of les_cnn_param_count(C) values in device
  * memory: per layer l = 0..3, W_l[tap][cout][cin] then b_l[cout], with
  * tap = 9 (dz+1) + 3 (dy+1) + (dx+1).  "packed" is its bfloat16 copy
- * (les_cnn_param_count() uint16 values) made by les_cnn_pack.
+ * (les_cnn_param_count(C) uint16 values) made by les_cnn_pack.
  *
  * Training loss.  On output crops (nz, ny, nx): e = out - target,
  * q = (L e)/d on interior cells (one-cell ring in x and y excluded, mirror
@@ -51,21 +59,23 @@ typedef struct les_cnn_dims {
   int32_t batch;     /* number of fields / crops, >= 1 */
   int32_t nz, ny, nx; /* network input size of each (valid: ny, nx >= 11) */
   int32_t periodic;  /* 1: whole periodic fields; 0: valid crops */
-  int32_t reserved;  /* 0 */
+  int32_t inputs;    /* input channels C: 1 or 3 */
   double alpha;      /* leaky ReLU slope, >= 0 */
 } les_cnn_dims;
 
-/* Number of FP32 parameters (14737). */
-int32_t les_cnn_param_count(void);
+/* Number of FP32 parameters of the network with `inputs` input channels
+ * (14737 for 1, 15601 for 3); LES_ERR_ARG for another count. */
+int32_t les_cnn_param_count(int32_t inputs);
 
 /* Bytes of the work buffer of les_cnn_forward / _loss / _backward /
  * _train_step for these dims (stored layer inputs, gradients, partial sums). */
 size_t les_cnn_work_bytes(const les_cnn_dims *d);
 
-/* packed[q] = bfloat16(params[q]). */
-int les_cnn_pack(const float *params, uint16_t *packed, void *stream);
+/* packed[q] = bfloat16(params[q]) for the les_cnn_param_count(inputs)
+ * parameters. */
+int les_cnn_pack(int32_t inputs, const float *params, uint16_t *packed, void *stream);
 
-/* Forward pass on a batch: x (batch, nz, ny, nx) FP32 (rounded to
+/* Forward pass on a batch: x (batch, inputs, nz, ny, nx) FP32 (rounded to
  * bfloat16 on entry), out (batch, nz, ny - 8, nx - 8) for valid crops or
  * (batch, nz, ny, nx) for periodic fields.  Keeps the layer inputs in work
  * for les_cnn_backward. */
@@ -132,23 +142,33 @@ int les_cnn_pair_noalloc(const les_config *cfg, const void *rhs, const void *bas
                          const void *phi, float *x, float *target, double *scale,
                          void *stream);
 
-/* Crops of npairs stored pairs x_pairs, t_pairs (each npairs x nz x ny x nx,
- * FP32).  crops: batch triples (pair, j0, i0), each taken modulo its range.
- * xb gets (batch, nz, cy + 8, cx + 8) from (j0 - 4, i0 - 4), tb (batch, nz,
- * cy, cx) from (j0, i0), both wrapping in x and y. */
-int les_cnn_gather(const float *x_pairs, const float *t_pairs, int32_t npairs, int32_t nz,
-                   int32_t ny, int32_t nx, const int32_t *crops, int32_t batch, int32_t cy,
-                   int32_t cx, float *xb, float *tb, void *stream);
+/* Training pair of the three-input network from one solve: r = rhs - L
+ * base, s = RMS(r), x (3, nz, ny, nx) FP32 = (r/s, base d/s, rhs/s) and
+ * target = (phi - base) d/s; base the extrapolated pressure change the
+ * solve started from (les_step_opts.dump_base).  phi and target nullable
+ * together (the inputs only).  scratch and scale as in les_cnn_pair. */
+int les_cnn_pair3(const les_config *cfg, const void *rhs, const void *base, const void *phi,
+                  float *x, float *target, void *scratch, double *scale, void *stream);
 
-/* Bind the network used by LES_GUESS_LEARNED: copies params (device FP32)
- * into the handle's workspace and packs them.  The caller's buffer may be
- * freed afterwards.  Error if the handle was not created with
- * LES_GUESS_LEARNED. */
+/* Crops of npairs stored pairs: x_pairs (npairs, inputs, nz, ny, nx) and
+ * t_pairs (npairs, nz, ny, nx), FP32.  crops: batch triples (pair, j0, i0),
+ * each taken modulo its range.  xb gets (batch, inputs, nz, cy + 8, cx + 8)
+ * from (j0 - 4, i0 - 4), tb (batch, nz, cy, cx) from (j0, i0), both
+ * wrapping in x and y. */
+int les_cnn_gather(int32_t inputs, const float *x_pairs, const float *t_pairs, int32_t npairs,
+                   int32_t nz, int32_t ny, int32_t nx, const int32_t *crops, int32_t batch,
+                   int32_t cy, int32_t cx, float *xb, float *tb, void *stream);
+
+/* Bind the network used by LES_GUESS_LEARNED (one input) or
+ * LES_GUESS_LEARNED3 (three inputs): copies params (device FP32, that
+ * network's count) into the handle's workspace and packs them.  The
+ * caller's buffer may be freed afterwards.  Error if the handle was created
+ * with another guess mode. */
 int les_bind_cnn(les_handle *h, const float *params, double alpha);
 
-/* The learned guess on caller fields of the handle's grid and storage
- * type: guess = base + (s/d) CNN(r/s), r = rhs - L base (rhs is used as
- * given).  scale (host, nullable): synchronizes and stores s. */
+/* The learned guess of the handle's network on caller fields of its grid
+ * and storage type: guess = base + (s/d) CNN(...), r = rhs - L base (rhs
+ * is used as given).  scale (host, nullable): synchronizes and stores s. */
 int les_cnn_guess(les_handle *h, const void *rhs, const void *base, void *guess, double *scale);
 
 #ifdef __cplusplus

@@ -1,7 +1,8 @@
 """Python access to the oracle of the guess network (oracle/cnn_oracle.c).
 
 TEST INFRASTRUCTURE ONLY, like the rest of oracle/.  Arrays are float64;
-a batch of single-channel fields has shape (batch, nz, ny, nx).
+a batch of single-channel fields has shape (batch, nz, ny, nx), a batch of
+network inputs with C = 3 channels (batch, 3, nz, ny, nx).
 """
 from __future__ import annotations
 
@@ -13,7 +14,7 @@ from . import lib as _oracle_lib
 
 LAYERS = 4
 TAPS = 27
-CIN = (1, 16, 16, 16)
+CIN = (1, 16, 16, 16)     # the one-input network; cin(inputs, l) in general
 COUT = (16, 16, 16, 1)
 
 _DP = C.POINTER(C.c_double)
@@ -21,7 +22,8 @@ _DP = C.POINTER(C.c_double)
 
 class Dims(C.Structure):
     _fields_ = [("batch", C.c_int32), ("nz", C.c_int32), ("ny", C.c_int32), ("nx", C.c_int32),
-                ("periodic", C.c_int32), ("bf16", C.c_int32), ("alpha", C.c_double)]
+                ("periodic", C.c_int32), ("bf16", C.c_int32), ("inputs", C.c_int32),
+                ("reserved", C.c_int32), ("alpha", C.c_double)]
 
 
 _ready = False
@@ -32,9 +34,12 @@ def lib():
     L = _oracle_lib()
     if not _ready:
         dp = C.POINTER(Dims)
-        for f in ("ocnn_cin", "ocnn_cout", "ocnn_weight_offset", "ocnn_bias_offset"):
-            getattr(L, f).argtypes = [C.c_int]
+        for f in ("ocnn_cin", "ocnn_weight_offset", "ocnn_bias_offset"):
+            getattr(L, f).argtypes = [C.c_int, C.c_int]
             getattr(L, f).restype = C.c_int
+        L.ocnn_cout.argtypes = [C.c_int]
+        L.ocnn_cout.restype = C.c_int
+        L.ocnn_param_count.argtypes = [C.c_int]
         L.ocnn_param_count.restype = C.c_int
         L.ocnn_bf16.argtypes = [C.c_double]
         L.ocnn_bf16.restype = C.c_double
@@ -46,16 +51,20 @@ def lib():
     return L
 
 
-def param_count() -> int:
-    return lib().ocnn_param_count()
+def param_count(inputs: int = 1) -> int:
+    return lib().ocnn_param_count(inputs)
 
 
-def weight_offset(l: int) -> int:
-    return lib().ocnn_weight_offset(l)
+def cin(l: int, inputs: int = 1) -> int:
+    return lib().ocnn_cin(inputs, l)
 
 
-def bias_offset(l: int) -> int:
-    return lib().ocnn_bias_offset(l)
+def weight_offset(l: int, inputs: int = 1) -> int:
+    return lib().ocnn_weight_offset(inputs, l)
+
+
+def bias_offset(l: int, inputs: int = 1) -> int:
+    return lib().ocnn_bias_offset(inputs, l)
 
 
 def bf16(a):
@@ -70,9 +79,16 @@ def _p(a):
     return a.ctypes.data_as(_DP)
 
 
+def _inputs(x):
+    """Input channel count of x: (batch, nz, ny, nx) is one channel,
+    (batch, C, nz, ny, nx) C."""
+    return 1 if x.ndim == 4 else x.shape[1]
+
+
 def _dims(x, periodic, alpha, bf16_):
-    b, nz, ny, nx = x.shape
-    return Dims(b, nz, ny, nx, 1 if periodic else 0, 1 if bf16_ else 0, float(alpha))
+    b, nz, ny, nx = x.shape[0], x.shape[-3], x.shape[-2], x.shape[-1]
+    return Dims(b, nz, ny, nx, 1 if periodic else 0, 1 if bf16_ else 0, _inputs(x), 0,
+                float(alpha))
 
 
 def layer_size(ny, nx, l, periodic):
@@ -85,13 +101,13 @@ def forward(params, x, periodic=False, alpha=0.1, bf16=True):
     rounded input of layer l and pre[l] the pre-activation of layer l < 3."""
     params = np.ascontiguousarray(params, dtype=np.float64)
     x = np.ascontiguousarray(x, dtype=np.float64)
-    assert params.size == param_count() and x.ndim == 4
+    assert x.ndim in (4, 5) and params.size == param_count(_inputs(x))
     d = _dims(x, periodic, alpha, bf16)
-    b, nz, ny, nx = x.shape
+    b, nz, ny, nx = d.batch, d.nz, d.ny, d.nx
     acts, pre = [], []
     for l in range(LAYERS):
         yi, xi = layer_size(ny, nx, l, periodic)
-        acts.append(np.zeros((b, CIN[l], nz, yi, xi)))
+        acts.append(np.zeros((b, cin(l, d.inputs), nz, yi, xi)))
         if l < LAYERS - 1:
             yo, xo = layer_size(ny, nx, l + 1, periodic)
             pre.append(np.zeros((b, COUT[l], nz, yo, xo)))
@@ -111,7 +127,7 @@ def backward(params, x, acts, pre, gout, periodic=False, alpha=0.1, bf16=True):
     x = np.ascontiguousarray(x, dtype=np.float64)
     gout = np.ascontiguousarray(gout, dtype=np.float64)
     d = _dims(x, periodic, alpha, bf16)
-    grad = np.zeros(param_count())
+    grad = np.zeros(param_count(d.inputs))
     ap = (_DP * LAYERS)(*[_p(a) for a in acts])
     pp = (_DP * LAYERS)(*([_p(a) for a in pre] + [None]))
     rc = lib().ocnn_backward(C.byref(d), _p(params), ap, pp, _p(gout), _p(grad))

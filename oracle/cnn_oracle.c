@@ -8,19 +8,26 @@
 #include <stdlib.h>
 #include <string.h>
 
-static const int CIN[OCNN_LAYERS] = {1, 16, 16, 16};
 static const int COUT[OCNN_LAYERS] = {16, 16, 16, 1};
 
-int ocnn_cin(int l) { return l >= 0 && l < OCNN_LAYERS ? CIN[l] : -1; }
+static int inputs_ok(int inputs) { return inputs == 1 || inputs == 3; }
+int ocnn_cin(int inputs, int l) {
+  if (!inputs_ok(inputs) || l < 0 || l >= OCNN_LAYERS) return -1;
+  return l == 0 ? inputs : COUT[l - 1];
+}
 int ocnn_cout(int l) { return l >= 0 && l < OCNN_LAYERS ? COUT[l] : -1; }
 
-int ocnn_weight_offset(int l) {
+int ocnn_weight_offset(int inputs, int l) {
+  if (!inputs_ok(inputs) || l < 0 || l > OCNN_LAYERS) return -1;
   int off = 0;
-  for (int q = 0; q < l; ++q) off += OCNN_TAPS * CIN[q] * COUT[q] + COUT[q];
+  for (int q = 0; q < l; ++q) off += OCNN_TAPS * ocnn_cin(inputs, q) * COUT[q] + COUT[q];
   return off;
 }
-int ocnn_bias_offset(int l) { return ocnn_weight_offset(l) + OCNN_TAPS * CIN[l] * COUT[l]; }
-int ocnn_param_count(void) { return ocnn_weight_offset(OCNN_LAYERS); }
+int ocnn_bias_offset(int inputs, int l) {
+  if (!inputs_ok(inputs) || l < 0 || l >= OCNN_LAYERS) return -1;
+  return ocnn_weight_offset(inputs, l) + OCNN_TAPS * ocnn_cin(inputs, l) * COUT[l];
+}
+int ocnn_param_count(int inputs) { return ocnn_weight_offset(inputs, OCNN_LAYERS); }
 
 void ocnn_layer_size(const ocnn_dims *d, int l, int *ny, int *nx) {
   int trim = d->periodic ? 0 : 2 * l;
@@ -41,7 +48,8 @@ double ocnn_bf16(double v) {
 }
 
 static int check_dims(const ocnn_dims *d) {
-  if (!d || d->batch < 1 || d->nz < 1 || d->alpha < 0.0) return -1;
+  if (!d || d->batch < 1 || d->nz < 1 || d->alpha < 0.0 || !inputs_ok(d->inputs) || d->reserved)
+    return -1;
   int ny, nx;
   ocnn_layer_size(d, OCNN_LAYERS, &ny, &nx);
   return ny >= 1 && nx >= 1 ? 0 : -1;
@@ -60,10 +68,10 @@ static size_t src_index(const ocnn_dims *d, int nyi, int nxi, int k, int j, int 
 }
 
 static double *rounded_weights(const ocnn_dims *d, const double *params, int l) {
-  int nw = OCNN_TAPS * CIN[l] * COUT[l];
+  int nw = OCNN_TAPS * ocnn_cin(d->inputs, l) * COUT[l];
   double *w = malloc(nw * sizeof(double));
   if (!w) return NULL;
-  const double *src = params + ocnn_weight_offset(l);
+  const double *src = params + ocnn_weight_offset(d->inputs, l);
   for (int q = 0; q < nw; ++q) w[q] = d->bf16 ? ocnn_bf16(src[q]) : src[q];
   return w;
 }
@@ -73,11 +81,11 @@ static int conv_layer(const ocnn_dims *d, int l, const double *params, const dou
   int nyi, nxi, nyo, nxo;
   ocnn_layer_size(d, l, &nyi, &nxi);
   ocnn_layer_size(d, l + 1, &nyo, &nxo);
-  const int ci = CIN[l], co = COUT[l];
+  const int ci = ocnn_cin(d->inputs, l), co = COUT[l];
   const size_t ni = (size_t)d->nz * nyi * nxi, no = (size_t)d->nz * nyo * nxo;
   double *w = rounded_weights(d, params, l);
   if (!w) return -1;
-  const double *bias = params + ocnn_bias_offset(l);
+  const double *bias = params + ocnn_bias_offset(d->inputs, l);
   for (int b = 0; b < d->batch; ++b)
     for (int o = 0; o < co; ++o)
       for (int k = 0; k < d->nz; ++k)
@@ -110,14 +118,14 @@ int ocnn_forward(const ocnn_dims *d, const double *params, const double *x, doub
   double *a[OCNN_LAYERS] = {0}, *y[OCNN_LAYERS] = {0};
   int rc = 0;
   for (int l = 0; l < OCNN_LAYERS && rc == 0; ++l) {
-    a[l] = acts ? acts[l] : malloc(act_len(d, l, CIN[l]) * sizeof(double));
+    a[l] = acts ? acts[l] : malloc(act_len(d, l, ocnn_cin(d->inputs, l)) * sizeof(double));
     y[l] = l == OCNN_LAYERS - 1 ? out
            : pre                ? pre[l]
                                 : malloc(act_len(d, l + 1, COUT[l]) * sizeof(double));
     if (!a[l] || !y[l]) rc = -1;
   }
   if (rc == 0) {
-    size_t n0 = act_len(d, 0, 1);
+    size_t n0 = act_len(d, 0, d->inputs);
     for (size_t q = 0; q < n0; ++q) a[0][q] = d->bf16 ? ocnn_bf16(x[q]) : x[q];
     for (int l = 0; l < OCNN_LAYERS; ++l) {
       if ((rc = conv_layer(d, l, params, a[l], y[l]))) break;
@@ -139,7 +147,7 @@ int ocnn_forward(const ocnn_dims *d, const double *params, const double *x, doub
 int ocnn_backward(const ocnn_dims *d, const double *params, double *const *acts,
                   double *const *pre, const double *gout, double *grad) {
   if (check_dims(d) || !params || !acts || !pre || !gout || !grad) return -1;
-  memset(grad, 0, (size_t)ocnn_param_count() * sizeof(double));
+  memset(grad, 0, (size_t)ocnn_param_count(d->inputs) * sizeof(double));
   /* gy: gradient with respect to the current layer's output (pre-activation) */
   double *gy = malloc(act_len(d, OCNN_LAYERS, 1) * sizeof(double));
   if (!gy) return -1;
@@ -148,12 +156,12 @@ int ocnn_backward(const ocnn_dims *d, const double *params, double *const *acts,
     int nyi, nxi, nyo, nxo;
     ocnn_layer_size(d, l, &nyi, &nxi);
     ocnn_layer_size(d, l + 1, &nyo, &nxo);
-    const int ci = CIN[l], co = COUT[l];
+    const int ci = ocnn_cin(d->inputs, l), co = COUT[l];
     const size_t ni = (size_t)d->nz * nyi * nxi, no = (size_t)d->nz * nyo * nxo;
     double *w = rounded_weights(d, params, l);
     double *ga = l > 0 ? calloc(act_len(d, l, ci), sizeof(double)) : NULL;
     if (!w || (l > 0 && !ga)) { free(w); free(ga); free(gy); return -1; }
-    double *gw = grad + ocnn_weight_offset(l), *gb = grad + ocnn_bias_offset(l);
+    double *gw = grad + ocnn_weight_offset(d->inputs, l), *gb = grad + ocnn_bias_offset(d->inputs, l);
     const double *a = acts[l];
     for (int b = 0; b < d->batch; ++b)
       for (int o = 0; o < co; ++o)

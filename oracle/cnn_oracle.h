@@ -6,10 +6,12 @@
  * baseline of the benchmark call this code; the library never does.
  *
  * Network (the guess network of the learned Poisson initial guess):
- *   four 3x3x3 convolutions, channels 1 -> 16 -> 16 -> 16 -> 1, biases,
- *   leaky ReLU with slope alpha after the first three.
- *   Input: the residual of the base guess, divided by its RMS.
- *   Output: the correction to the base guess in units of RMS/d, with
+ *   four 3x3x3 convolutions, channels C -> 16 -> 16 -> 16 -> 1, biases,
+ *   leaky ReLU with slope alpha after the first three; C = 1 or 3 inputs.
+ *   Inputs (C = 1): the residual of the base guess, divided by its RMS s;
+ *   (C = 3): that residual, the base guess times d/s and the right-hand
+ *   side divided by s (the previous pressures and the divergence).
+ *   Output: the correction to the base guess in units of s/d, with
  *   d = 2/dx^2 + 2/dy^2 + 2/dz^2 the diagonal of the compact Laplacian.
  * Geometry per batch item, arrays (nz, ny, nx), x fastest:
  *   periodic = 1: x and y wrap; output has the input's size;
@@ -35,25 +37,28 @@ typedef struct ocnn_dims {
   int32_t batch, nz, ny, nx; /* input size per batch item */
   int32_t periodic;          /* 1 periodic x,y; 0 valid x,y */
   int32_t bf16;              /* 1 emulate bfloat16 rounding */
+  int32_t inputs;            /* input channels C: 1 or 3 */
+  int32_t reserved;          /* 0 */
   double alpha;              /* leaky ReLU slope */
 } ocnn_dims;
 
-/* Channel counts and parameter offsets. */
-int ocnn_cin(int l);
+/* Channel counts and parameter offsets of the network with `inputs` input
+ * channels (-1 for an invalid layer or input count). */
+int ocnn_cin(int inputs, int l);
 int ocnn_cout(int l);
-int ocnn_weight_offset(int l);
-int ocnn_bias_offset(int l);
-int ocnn_param_count(void);
+int ocnn_weight_offset(int inputs, int l);
+int ocnn_bias_offset(int inputs, int l);
+int ocnn_param_count(int inputs);
 /* Per-item size of the input of layer l (l = 4: the output). */
 void ocnn_layer_size(const ocnn_dims *d, int l, int *ny, int *nx);
 
 /* bfloat16 round to nearest even of a double. */
 double ocnn_bf16(double v);
 
-/* Forward pass.  acts (nullable) receives, for l = 0..3, the rounded input
- * of layer l (channels-first [b][c][z][y][x]) and pre (nullable) the
- * pre-activation y_l of layers 0..2 (needed by the backward pass); out gets
- * y_3 [b][z][y][x]. */
+/* Forward pass on x [b][c][z][y][x] (C input channels).  acts (nullable)
+ * receives, for l = 0..3, the rounded input of layer l (channels-first
+ * [b][c][z][y][x]) and pre (nullable) the pre-activation y_l of layers
+ * 0..2 (needed by the backward pass); out gets y_3 [b][z][y][x]. */
 int ocnn_forward(const ocnn_dims *d, const double *params, const double *x, double *out,
                  double *const *acts, double *const *pre);
 

@@ -23,6 +23,7 @@ int check_dims(const les_cnn_dims *d) {
     return fail(LES_ERR_ARG, "dims %d x %d x %d x %d: every size must be >= 1", d->batch, d->nz,
                 d->ny, d->nx);
   if (d->periodic != 0 && d->periodic != 1) return fail(LES_ERR_ARG, "periodic must be 0 or 1");
+  if (!cnn_inputs_ok(d->inputs)) return fail(LES_ERR_ARG, "inputs must be 1 or 3, got %d", d->inputs);
   if (!d->periodic && (d->ny < 11 || d->nx < 11))
     return fail(LES_ERR_ARG, "valid crops need ny, nx >= 11 (output >= 3), got %d x %d", d->ny,
                 d->nx);
@@ -36,7 +37,7 @@ int check_dims(const les_cnn_dims *d) {
 void counts(const les_cnn_dims *d, int64_t n[kCnnLayers + 1]) {
   for (int l = 0; l <= kCnnLayers; ++l) {
     const CnnGeom G = cnn_geom(d->batch, d->nz, d->ny, d->nx, d->periodic,
-                               l < kCnnLayers ? l : kCnnLayers - 1);
+                               l < kCnnLayers ? l : kCnnLayers - 1, d->inputs);
     n[l] = l < kCnnLayers ? G.n_in : G.n_out;
   }
 }
@@ -57,7 +58,7 @@ Work work_layout(const les_cnn_dims *d) {
   size_t off = 0;
   for (int l = 0; l < kCnnLayers; ++l) {
     W.a[l] = off;
-    off = align_up(off + (size_t)n[l] * cnn_cin(l) * sizeof(uint16_t));
+    off = align_up(off + (size_t)n[l] * cnn_cin(d->inputs, l) * sizeof(uint16_t));
   }
   W.g1 = off;
   off = align_up(off + (size_t)n[1] * kCnnCh * sizeof(float));
@@ -86,9 +87,10 @@ int forward_impl(const les_cnn_dims *d, const float *params, const uint16_t *pac
   const Work W = work_layout(d);
   int64_t n[kCnnLayers + 1];
   counts(d, n);
-  launch_cnn_round(n[0], x, nullptr, at<uint16_t>(work, W.a[0]), s);
+  launch_cnn_round(n[0], d->inputs, (int64_t)d->nz * d->ny * d->nx, x, nullptr,
+                   at<uint16_t>(work, W.a[0]), s);
   for (int l = 0; l < kCnnLayers; ++l) {
-    const CnnGeom G = cnn_geom(d->batch, d->nz, d->ny, d->nx, d->periodic, l);
+    const CnnGeom G = cnn_geom(d->batch, d->nz, d->ny, d->nx, d->periodic, l, d->inputs);
     launch_cnn_conv(l, G, at<uint16_t>(work, W.a[l]), params, packed, (float)d->alpha,
                     l + 1 < kCnnLayers ? at<uint16_t>(work, W.a[l + 1]) : nullptr,
                     l + 1 < kCnnLayers ? nullptr : out, s);
@@ -100,7 +102,7 @@ int forward_impl(const les_cnn_dims *d, const float *params, const uint16_t *pac
 int loss_impl(const les_cnn_dims *d, double dx, double dy, double dz, const float *out,
               const float *target, void *work, float *gout, double *loss, hipStream_t s) {
   const Work W = work_layout(d);
-  const CnnGeom G = cnn_geom(d->batch, d->nz, d->ny, d->nx, 0, kCnnLayers - 1);
+  const CnnGeom G = cnn_geom(d->batch, d->nz, d->ny, d->nx, 0, kCnnLayers - 1, d->inputs);
   const double D = 2.0 / (dx * dx) + 2.0 / (dy * dy) + 2.0 / (dz * dz);
   launch_cnn_loss(d->batch, d->nz, G.nyo, G.nxo, 1.0 / (dx * dx * D), 1.0 / (dy * dy * D),
                   1.0 / (dz * dz * D), out, target, at<float>(work, W.q),
@@ -127,7 +129,7 @@ int backward_impl(const les_cnn_dims *d, const uint16_t *packed, void *work, con
   const float *gy = gout;
   float *next[kCnnLayers] = {nullptr, g1, g2, g1};
   for (int l = kCnnLayers - 1; l >= 0; --l) {
-    const CnnGeom G = cnn_geom(d->batch, d->nz, d->ny, d->nx, 0, l);
+    const CnnGeom G = cnn_geom(d->batch, d->nz, d->ny, d->nx, 0, l, d->inputs);
     const uint16_t *ain = at<uint16_t>(work, W.a[l]);
     launch_cnn_wgrad(l, G, gy, ain, partials, grad, s);
     if (l > 0) {
@@ -145,20 +147,49 @@ bool grid_ok(const les_config *c) {
          (double)c->nx * c->ny * c->nz < 4.0e9;
 }
 
+Grid pair_grid(const les_config *cfg) {
+  Grid g;
+  g.nx = cfg->nx;
+  g.ny = cfg->ny;
+  g.nz = cfg->nz;
+  g.nxy = (int64_t)g.nx * g.ny;
+  g.sy = g.ny == 1 ? 0 : g.nx;
+  g.n = g.nxy * g.nz;
+  g.dx = cfg->dx;
+  g.dy = cfg->dy;
+  g.dz = cfg->dz;
+  g.dt = cfg->dt;
+  return g;
+}
+
+// Pair of the three-input network (les_cnn_pair3).
+template <typename T>
+void pair3_impl(const Grid &g, const T *rhs, const T *base, const T *phi, float *r,
+                double *partials, double *sc, float *x, float *t, hipStream_t s) {
+  const double D = 2.0 / (g.dx * g.dx) + 2.0 / (g.dy * g.dy) + 2.0 / (g.dz * g.dz);
+  launch_cnn_residual<T>(g, rhs, base, r, partials, s);
+  launch_cnn_scale(partials, (double)g.n, D, sc, s);
+  launch_cnn_pair3<T>(g, r, base, rhs, phi, sc, D, x, t, s);
+}
+
 }  // namespace
 
 extern "C" {
 
-int32_t les_cnn_param_count(void) { return cnn_param_count(); }
+int32_t les_cnn_param_count(int32_t inputs) {
+  if (!cnn_inputs_ok(inputs)) return fail(LES_ERR_ARG, "inputs must be 1 or 3, got %d", inputs);
+  return cnn_param_count(inputs);
+}
 
 size_t les_cnn_work_bytes(const les_cnn_dims *d) {
   if (check_dims(d)) return 0;
   return work_layout(d).total;
 }
 
-int les_cnn_pack(const float *params, uint16_t *packed, void *stream) {
+int les_cnn_pack(int32_t inputs, const float *params, uint16_t *packed, void *stream) {
+  if (!cnn_inputs_ok(inputs)) return fail(LES_ERR_ARG, "inputs must be 1 or 3, got %d", inputs);
   if (!params || !packed) return fail(LES_ERR_ARG, "params and packed must be non-NULL");
-  launch_cnn_pack(params, packed, (hipStream_t)stream);
+  launch_cnn_pack(params, cnn_param_count(inputs), packed, (hipStream_t)stream);
   LAUNCH_TRY();
   return LES_OK;
 }
@@ -193,8 +224,9 @@ int les_cnn_stored_input(const les_cnn_dims *d, const void *work, int32_t layer,
   if (layer < 0 || layer >= kCnnLayers) return fail(LES_ERR_ARG, "layer %d out of range", layer);
   if (!work || !out) return fail(LES_ERR_ARG, "NULL argument");
   const Work W = work_layout(d);
-  const CnnGeom G = cnn_geom(d->batch, d->nz, d->ny, d->nx, d->periodic, layer);
-  launch_cnn_unpack(G, cnn_cin(layer), at<uint16_t>(const_cast<void *>(work), W.a[layer]), out,
+  const CnnGeom G = cnn_geom(d->batch, d->nz, d->ny, d->nx, d->periodic, layer, d->inputs);
+  launch_cnn_unpack(G, cnn_cin(d->inputs, layer),
+                    at<uint16_t>(const_cast<void *>(work), W.a[layer]), out,
                     (hipStream_t)stream);
   LAUNCH_TRY();
   return LES_OK;
@@ -237,9 +269,9 @@ int les_cnn_train_step(const les_cnn_dims *d, double dx, double dy, double dz, f
   HIP_TRY(hipMemcpyAsync(at<float>(work, W.q), gout, (size_t)n[4] * sizeof(float),
                          hipMemcpyDeviceToDevice, s));
   if (int rc = backward_impl(d, packed, work, at<float>(work, W.q), grad, s)) return rc;
-  if (int rc = les_cnn_adam(cnn_param_count(), params, grad, m, v, step, lr, beta1, beta2, eps, s))
-    return rc;
-  launch_cnn_pack(params, packed, s);
+  const int np = cnn_param_count(d->inputs);
+  if (int rc = les_cnn_adam(np, params, grad, m, v, step, lr, beta1, beta2, eps, s)) return rc;
+  launch_cnn_pack(params, np, packed, s);
   LAUNCH_TRY();
   if (loss) {
     double st[2];
@@ -262,17 +294,7 @@ int les_cnn_pair(const les_config *cfg, const void *rhs, const void *base, const
   if (!grid_ok(cfg)) return fail(LES_ERR_ARG, "invalid grid in config");
   if (!rhs || !phi || !x || !target || !scratch) return fail(LES_ERR_ARG, "NULL argument");
   hipStream_t s = (hipStream_t)stream;
-  Grid g;
-  g.nx = cfg->nx;
-  g.ny = cfg->ny;
-  g.nz = cfg->nz;
-  g.nxy = (int64_t)g.nx * g.ny;
-  g.sy = g.ny == 1 ? 0 : g.nx;
-  g.n = g.nxy * g.nz;
-  g.dx = cfg->dx;
-  g.dy = cfg->dy;
-  g.dz = cfg->dz;
-  g.dt = cfg->dt;
+  const Grid g = pair_grid(cfg);
   const double D = 2.0 / (g.dx * g.dx) + 2.0 / (g.dy * g.dy) + 2.0 / (g.dz * g.dz);
   float *r = (float *)scratch;
   double *partials = at<double>(scratch, align_up((size_t)g.n * sizeof(float)));
@@ -295,15 +317,41 @@ int les_cnn_pair(const les_config *cfg, const void *rhs, const void *base, const
   return LES_OK;
 }
 
-int les_cnn_gather(const float *x_pairs, const float *t_pairs, int32_t npairs, int32_t nz,
-                   int32_t ny, int32_t nx, const int32_t *crops, int32_t batch, int32_t cy,
-                   int32_t cx, float *xb, float *tb, void *stream) {
+int les_cnn_pair3(const les_config *cfg, const void *rhs, const void *base, const void *phi,
+                  float *x, float *target, void *scratch, double *scale, void *stream) {
+  if (!grid_ok(cfg)) return fail(LES_ERR_ARG, "invalid grid in config");
+  if (!rhs || !base || !x || !scratch || (phi && !target) || (!phi && target))
+    return fail(LES_ERR_ARG, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  const Grid g = pair_grid(cfg);
+  float *r = (float *)scratch;
+  double *partials = at<double>(scratch, align_up((size_t)g.n * sizeof(float)));
+  double *sc = at<double>(scratch, align_up((size_t)g.n * sizeof(float)) +
+                                       align_up(kReduceBlocks * sizeof(double)));
+  if (cfg->precision == LES_FP64)
+    pair3_impl<double>(g, (const double *)rhs, (const double *)base, (const double *)phi, r,
+                       partials, sc, x, target, s);
+  else
+    pair3_impl<float>(g, (const float *)rhs, (const float *)base, (const float *)phi, r, partials,
+                      sc, x, target, s);
+  LAUNCH_TRY();
+  if (scale) {
+    HIP_TRY(hipMemcpyAsync(scale, sc, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  return LES_OK;
+}
+
+int les_cnn_gather(int32_t inputs, const float *x_pairs, const float *t_pairs, int32_t npairs,
+                   int32_t nz, int32_t ny, int32_t nx, const int32_t *crops, int32_t batch,
+                   int32_t cy, int32_t cx, float *xb, float *tb, void *stream) {
+  if (!cnn_inputs_ok(inputs)) return fail(LES_ERR_ARG, "inputs must be 1 or 3, got %d", inputs);
   if (!x_pairs || !t_pairs || !crops || !xb || !tb) return fail(LES_ERR_ARG, "NULL argument");
   if (npairs < 1 || nz < 1 || ny < 5 || nx < 5 || batch < 1 || cy < 1 || cx < 1)
     return fail(LES_ERR_ARG, "gather: invalid sizes");
   // crop entries live in device memory: the kernel reduces each modulo its
   // range, so every read stays inside the stored pairs
-  launch_cnn_gather(x_pairs, t_pairs, npairs, nz, ny, nx, crops, batch, cy, cx, xb, tb,
+  launch_cnn_gather(x_pairs, t_pairs, npairs, inputs, nz, ny, nx, crops, batch, cy, cx, xb, tb,
                     (hipStream_t)stream);
   LAUNCH_TRY();
   return LES_OK;

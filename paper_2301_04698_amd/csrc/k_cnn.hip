@@ -3,12 +3,15 @@
 // pairs.
 //
 // Layouts: single-channel fields are (batch, nz, ny, nx) with x fastest;
-// 16-channel activations are channels-last bfloat16 (cell * 16 + c), so
-// one cell's channels are one 32-byte line.  The two 16 -> 16 layers run on
-// the matrix cores as an implicit GEMM per tap: D(out ch x 16 cells) +=
-// W_tap(out x in) * X_tap(in x 16 cells), FP32 accumulation, one wave per
-// 16 consecutive output cells.  The 1 -> 16 and 16 -> 1 layers and the
-// backward pass are FP32 vector code (FP64 sums in the weight gradient).
+// network inputs of C channels are (batch, C, nz, ny, nx) in FP32 and
+// channels-last bfloat16 (cell * C + c) once rounded; 16-channel
+// activations are channels-last bfloat16 (cell * 16 + c), so one cell's
+// channels are one 32-byte line.  The two 16 -> 16 layers run on the matrix
+// cores as an implicit GEMM per tap: D(out ch x 16 cells) += W_tap(out x
+// in) * X_tap(in x 16 cells), FP32 accumulation, one wave per 16
+// consecutive output cells; the C -> 16 layer as one GEMM over (tap,
+// channel) pairs.  The 16 -> 1 layer and the backward pass are FP32 vector
+// code (FP64 sums in the weight gradient).
 #include <cmath>
 
 #include "cnn_internal.h"
@@ -16,8 +19,9 @@
 
 namespace lesmi {
 
-CnnGeom cnn_geom(int batch, int nz, int ny, int nx, int periodic, int layer) {
+CnnGeom cnn_geom(int batch, int nz, int ny, int nx, int periodic, int layer, int inputs) {
   CnnGeom G;
+  G.inputs = inputs;
   const int ti = periodic ? 0 : 2 * layer, to = periodic ? 0 : 2 * (layer + 1);
   G.batch = batch;
   G.nz = nz;
@@ -87,12 +91,17 @@ __global__ __launch_bounds__(kBlock) void pack_kernel(const float *__restrict__ 
   if (q < n) wbf[q] = f2bf(params[q]);
 }
 
-__global__ __launch_bounds__(kBlock) void round_kernel(int64_t n, const float *__restrict__ x,
+// One thread per (cell, channel) of the channels-last output.
+__global__ __launch_bounds__(kBlock) void round_kernel(int64_t n, int C, int64_t cells,
+                                                       const float *__restrict__ x,
                                                        const double *__restrict__ scale,
                                                        uint16_t *__restrict__ a0) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n) return;
-  const float v = scale ? (float)((double)x[q] * *scale) : x[q];
+  if (q >= n * C) return;
+  const int c = (int)(q % C);
+  const int64_t cell = q / C, b = cell / cells, r = cell - b * cells;
+  const float xv = x[(b * C + c) * cells + r];
+  const float v = scale ? (float)((double)xv * *scale) : xv;
   a0[q] = f2bf(v);
 }
 
@@ -229,34 +238,39 @@ __global__ __launch_bounds__(256) void conv_mid_kernel(CnnGeom G, const uint16_t
   }
 }
 
-// Layer 0 (1 -> 16) on the matrix cores: D(out ch x 16 cells) = W(out ch x
-// 32 taps, 27 used) X(32 taps x 16 cells), the im2col operand gathered from
-// a three-plane LDS ring of bfloat16 inputs; two MFMAs per 16 cells.
+// Layer 0 (CI -> 16) on the matrix cores: D(out ch x 16 cells) = W(out ch x
+// K) X(K x 16 cells) over the K = 27 CI (tap, channel) pairs, k = tap CI +
+// c, padded to a multiple of 16; the im2col operand is gathered from a
+// three-plane LDS ring of bfloat16 inputs (channel planes side by side);
+// 27 CI / 16 MFMAs (rounded up) per 16 cells.
+template <int CI>
 __global__ __launch_bounds__(256) void conv_in_kernel(CnnGeom G, const uint16_t *__restrict__ ain,
                                                       const float *__restrict__ params,
                                                       const uint16_t *__restrict__ wbf,
                                                       float alpha, uint16_t *__restrict__ aout,
                                                       int tiles_x, int tiles_y, int chunks) {
-  __shared__ uint16_t lds[3][kCnnPlane];
+  constexpr int K = kCnnTaps * CI, KM = (K + 15) / 16;
+  __shared__ uint16_t lds[3][CI][kCnnPlane];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int row = lane & 15, quad = lane >> 4;
   const CnnTile T = cnn_tile(G, tiles_x, tiles_y, chunks);
-  // A operands: W0[tap][o = row][0] for taps 4 quad + r (+16 for the second)
-  bf16x4 wa[2];
+  // A operands: W0[tap][o = row][c] for k = 16 m + 4 quad + r
+  bf16x4 wa[KM];
 #pragma unroll
-  for (int m = 0; m < 2; ++m)
+  for (int m = 0; m < KM; ++m)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int tap = 16 * m + 4 * quad + r;
-      wa[m][r] = tap < kCnnTaps ? (short)wbf[tap * kCnnCh + row] : (short)0;
+      const int kk = 16 * m + 4 * quad + r;
+      wa[m][r] = kk < K ? (short)wbf[((kk / CI) * kCnnCh + row) * CI + kk % CI] : (short)0;
     }
   float bq[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) bq[r] = params[cnn_bias_offset(0) + 4 * quad + r];
+  for (int r = 0; r < 4; ++r) bq[r] = params[cnn_bias_offset(CI, 0) + 4 * quad + r];
   auto load_plane = [&](int kk, int slot) {
-    for (int e = threadIdx.x; e < kCnnPlane; e += 256) {
-      const int ly = e / kCnnPX, lx = e - ly * kCnnPX;
-      lds[slot][e] = ain[cnn_src(G, T, kk, ly, lx)];
+    for (int e = threadIdx.x; e < kCnnPlane * CI; e += 256) {
+      const int cell = e / CI, c = e - cell * CI;
+      const int ly = cell / kCnnPX, lx = cell - ly * kCnnPX;
+      lds[slot][c][cell] = ain[cnn_src(G, T, kk, ly, lx) * CI + c];
     }
   };
   load_plane(T.k0 - 1, (T.k0 + 2) % 3);
@@ -270,15 +284,16 @@ __global__ __launch_bounds__(256) void conv_in_kernel(CnnGeom G, const uint16_t 
     for (int t4 = 0; t4 < 4; ++t4) {
       floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int m = 0; m < 2; ++m) {
+      for (int m = 0; m < KM; ++m) {
         bf16x4 xb;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int tap = 16 * m + 4 * quad + r;
+          const int kk = 16 * m + 4 * quad + r;
           short v = 0;
-          if (tap < kCnnTaps) {
+          if (kk < K) {
+            const int tap = kk / CI, c = kk % CI;
             const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-            v = (short)lds[(k + dz + 3) % 3][(wv + 1 + dy) * kCnnPX + 16 * t4 + row + 1 + dx];
+            v = (short)lds[(k + dz + 3) % 3][c][(wv + 1 + dy) * kCnnPX + 16 * t4 + row + 1 + dx];
           }
           xb[r] = v;
         }
@@ -312,9 +327,9 @@ __global__ __launch_bounds__(256) void conv_out_kernel(CnnGeom G, const uint16_t
   __shared__ uint2 lds[3][kCnnPlane * 4];
   __shared__ float w[kCnnTaps * kCnnCh];
   for (int e = threadIdx.x; e < kCnnTaps * kCnnCh; e += 256)
-    w[e] = bf2f(wbf[cnn_weight_offset(3) + e]);
+    w[e] = bf2f(wbf[cnn_weight_offset(G.inputs, 3) + e]);
   const CnnTile Tl = cnn_tile(G, tiles_x, tiles_y, chunks);
-  const float b3 = params[cnn_bias_offset(3)];
+  const float b3 = params[cnn_bias_offset(G.inputs, 3)];
   auto load_plane = [&](int kk, int slot) {
     for (int e = threadIdx.x; e < kCnnPlane * 2; e += 256) {
       const int cell = e >> 1, h = e & 1;
@@ -505,7 +520,8 @@ __global__ __launch_bounds__(kBlock) void wgrad_kernel(CnnGeom G, const float *_
   for (int t = 0; t <= kCnnTaps; ++t) acc[t] = 0.0;
   const int64_t c0 = (int64_t)blockIdx.x * chunk;
   const int64_t c1 = c0 + chunk < G.n_out ? c0 + chunk : G.n_out;
-  for (int64_t q = c0 + grp; q < c1; q += GROUPS) {
+  // threads beyond GROUPS * PAIRS (PAIRS not dividing the block) stay idle
+  for (int64_t q = c0 + grp; grp < GROUPS && q < c1; q += GROUPS) {
     const Cell c = decode(q, G.nz, G.nyo, G.nxo);
     const double g = gy[q * CO + o];
     acc[kCnnTaps] += g;
@@ -623,6 +639,51 @@ __global__ __launch_bounds__(kBlock) void pair_kernel(int64_t n, const float *__
   t[q] = (float)(((double)phi[q] - (base ? (double)base[q] : 0.0)) * d * inv);
 }
 
+// Three-input network inputs at cell q: (r/s, base d/s, rhs/s), FP64
+// products rounded once.
+template <typename T>
+__device__ __forceinline__ void inputs3(int64_t q, const float *__restrict__ r,
+                                        const T *__restrict__ base, const T *__restrict__ rhs,
+                                        double inv, double d, float v[3]) {
+  v[0] = (float)((double)r[q] * inv);
+  v[1] = (float)((double)base[q] * d * inv);
+  v[2] = (float)((double)rhs[q] * inv);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void input3_kernel(int64_t n, const float *__restrict__ r,
+                                                        const T *__restrict__ base,
+                                                        const T *__restrict__ rhs,
+                                                        const double *__restrict__ sc, double d,
+                                                        uint16_t *__restrict__ a0) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  float v[3];
+  inputs3(q, r, base, rhs, sc[1], d, v);
+  a0[3 * q] = f2bf(v[0]);
+  a0[3 * q + 1] = f2bf(v[1]);
+  a0[3 * q + 2] = f2bf(v[2]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void pair3_kernel(int64_t n, const float *__restrict__ r,
+                                                       const T *__restrict__ base,
+                                                       const T *__restrict__ rhs,
+                                                       const T *__restrict__ phi,
+                                                       const double *__restrict__ sc, double d,
+                                                       float *__restrict__ x,
+                                                       float *__restrict__ t) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const double inv = sc[1];
+  float v[3];
+  inputs3(q, r, base, rhs, inv, d, v);
+  x[q] = v[0];
+  x[n + q] = v[1];
+  x[2 * n + q] = v[2];
+  if (phi) t[q] = (float)(((double)phi[q] - (double)base[q]) * d * inv);
+}
+
 // Stored layer input (channels-last bfloat16, C channels, `cells` cells per
 // batch entry) to FP32 in (batch, C, cells) order.
 __global__ __launch_bounds__(kBlock) void unpack_kernel(int64_t n, int C, int64_t cells,
@@ -650,10 +711,12 @@ __global__ __launch_bounds__(kBlock) void pair_inplace_kernel(int64_t n, const T
   t[q] = (float)(((double)phi[q] - (base ? (double)base[q] : 0.0)) * d * inv);
 }
 
+// Input crops (batch, C, nz, cy + 8, cx + 8) read as C nz levels per item
+// (channel-major, so level index c nz + k); targets (batch, nz, cy, cx).
 __global__ __launch_bounds__(kBlock) void gather_kernel(const float *__restrict__ X,
                                                         const float *__restrict__ Tt,
-                                                        int64_t pair_stride, int nz, int ny, int nx,
-                                                        const int32_t *__restrict__ crops,
+                                                        int64_t field, int C, int nz, int ny,
+                                                        int nx, const int32_t *__restrict__ crops,
                                                         int npairs, int cy, int cx, int64_t n_in,
                                                         int64_t n_t,
                                                         float *__restrict__ xb,
@@ -663,7 +726,8 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(const float *__restrict_
   if (q >= n_in + n_t) return;
   const int64_t qq = is_x ? q : q - n_in;
   const int h = is_x ? 4 : 0;
-  const Cell c = decode(qq, nz, cy + 2 * h, cx + 2 * h);
+  const int lv = is_x ? C * nz : nz;  // levels per item
+  const Cell c = decode(qq, lv, cy + 2 * h, cx + 2 * h);
   // every index is reduced modulo its range, so any crop entry reads in bounds
   const int32_t *cr = crops + 3 * c.b;
   int p = cr[0] % npairs, j = (int)(((int64_t)cr[1] - h + c.j) % ny),
@@ -671,7 +735,8 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(const float *__restrict_
   p += p < 0 ? npairs : 0;
   j += j < 0 ? ny : 0;
   i += i < 0 ? nx : 0;
-  const int64_t src = (int64_t)p * pair_stride + ((int64_t)c.k * ny + j) * nx + i;
+  const int64_t stride = is_x ? field * C : field;  // one pair
+  const int64_t src = (int64_t)p * stride + ((int64_t)c.k * ny + j) * nx + i;
   if (is_x)
     xb[qq] = X[src];
   else
@@ -682,13 +747,13 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(const float *__restrict_
 
 // ----------------------------------------------------------- launchers
 
-void launch_cnn_pack(const float *params, uint16_t *wbf, hipStream_t s) {
-  const int n = cnn_param_count();
+void launch_cnn_pack(const float *params, int n, uint16_t *wbf, hipStream_t s) {
   pack_kernel<<<blocks_for(n), kBlock, 0, s>>>(params, wbf, n);
 }
 
-void launch_cnn_round(int64_t n, const float *x, const double *scale, uint16_t *a0, hipStream_t s) {
-  round_kernel<<<blocks_for(n), kBlock, 0, s>>>(n, x, scale, a0);
+void launch_cnn_round(int64_t n, int C, int64_t cells, const float *x, const double *scale,
+                      uint16_t *a0, hipStream_t s) {
+  round_kernel<<<blocks_for(n * C), kBlock, 0, s>>>(n, C, cells, x, scale, a0);
 }
 
 void launch_cnn_conv(int layer, const CnnGeom &G, const uint16_t *ain, const float *params,
@@ -697,12 +762,16 @@ void launch_cnn_conv(int layer, const CnnGeom &G, const uint16_t *ain, const flo
   const int chunks = (G.nz + kCnnKC - 1) / kCnnKC;
   const unsigned blocks = (unsigned)((int64_t)G.batch * tiles_x * tiles_y * chunks);
   if (layer == 0) {
-    conv_in_kernel<<<blocks, 256, 0, s>>>(G, ain, params, wbf, alpha, aout, tiles_x, tiles_y,
-                                          chunks);
+    if (G.inputs == 3)
+      conv_in_kernel<3><<<blocks, 256, 0, s>>>(G, ain, params, wbf, alpha, aout, tiles_x, tiles_y,
+                                               chunks);
+    else
+      conv_in_kernel<1><<<blocks, 256, 0, s>>>(G, ain, params, wbf, alpha, aout, tiles_x, tiles_y,
+                                               chunks);
   } else if (layer < kCnnLayers - 1) {
-    conv_mid_kernel<<<blocks, 256, 0, s>>>(G, ain, params + cnn_bias_offset(layer),
-                                           wbf + cnn_weight_offset(layer), alpha, aout, tiles_x,
-                                           tiles_y, chunks);
+    conv_mid_kernel<<<blocks, 256, 0, s>>>(G, ain, params + cnn_bias_offset(G.inputs, layer),
+                                           wbf + cnn_weight_offset(G.inputs, layer), alpha, aout,
+                                           tiles_x, tiles_y, chunks);
   } else {
     conv_out_kernel<float, false><<<blocks, 256, 0, s>>>(G, ain, params, wbf, yout, nullptr,
                                                          nullptr, nullptr, tiles_x, tiles_y,
@@ -732,7 +801,7 @@ void launch_cnn_loss(int batch, int nz, int ny, int nx, double wx, double wy, do
 
 void launch_cnn_dgrad(int layer, const CnnGeom &G, const float *gy, const uint16_t *wbf,
                       const uint16_t *ain, float alpha, float *gprev, hipStream_t s) {
-  const uint16_t *wl = wbf + cnn_weight_offset(layer);
+  const uint16_t *wl = wbf + cnn_weight_offset(G.inputs, layer);
   if (layer == kCnnLayers - 1)
     dgrad_kernel<kCnnCh, 1><<<blocks_for(G.n_in), kBlock, 0, s>>>(G, gy, wl, ain, alpha, gprev);
   else
@@ -742,19 +811,21 @@ void launch_cnn_dgrad(int layer, const CnnGeom &G, const float *gy, const uint16
 
 void launch_cnn_wgrad(int layer, const CnnGeom &G, const float *gy, const uint16_t *ain,
                       double *partials, float *grad, hipStream_t s) {
-  const int ci = cnn_cin(layer), co = cnn_cout(layer);
+  const int ci = cnn_cin(G.inputs, layer), co = cnn_cout(layer);
   const int E = kCnnTaps * ci * co + co;
   const int64_t chunk = (G.n_out + kCnnWgradBlocks - 1) / kCnnWgradBlocks;
   if (ci == 1)
     wgrad_kernel<1, kCnnCh><<<kCnnWgradBlocks, kBlock, 0, s>>>(G, gy, ain, chunk, partials);
+  else if (ci == 3)
+    wgrad_kernel<3, kCnnCh><<<kCnnWgradBlocks, kBlock, 0, s>>>(G, gy, ain, chunk, partials);
   else if (co == 1)
     wgrad_kernel<kCnnCh, 1><<<kCnnWgradBlocks, kBlock, 0, s>>>(G, gy, ain, chunk, partials);
   else
     wgrad_kernel<kCnnCh, kCnnCh><<<kCnnWgradBlocks, kBlock, 0, s>>>(G, gy, ain, chunk, partials);
   wgrad_final_kernel<<<blocks_for(E), kBlock, 0, s>>>(partials, kCnnWgradBlocks, E,
                                                       kCnnTaps * ci * co,
-                                                      grad + cnn_weight_offset(layer),
-                                                      grad + cnn_bias_offset(layer));
+                                                      grad + cnn_weight_offset(G.inputs, layer),
+                                                      grad + cnn_bias_offset(G.inputs, layer));
 }
 
 void launch_cnn_adam(int n, float *params, const float *grad, float *m, float *v, int step,
@@ -784,6 +855,18 @@ void launch_cnn_pair(const Grid &g, const float *r, const T *phi, const T *base,
   pair_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g.n, r, phi, base, sc, d, x, t);
 }
 
+template <typename T>
+void launch_cnn_input3(const Grid &g, const float *r, const T *base, const T *rhs,
+                       const double *sc, double d, uint16_t *a0, hipStream_t s) {
+  input3_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g.n, r, base, rhs, sc, d, a0);
+}
+
+template <typename T>
+void launch_cnn_pair3(const Grid &g, const float *r, const T *base, const T *rhs, const T *phi,
+                      const double *sc, double d, float *x, float *t, hipStream_t s) {
+  pair3_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g.n, r, base, rhs, phi, sc, d, x, t);
+}
+
 void launch_cnn_unpack(const CnnGeom &G, int C, const uint16_t *a, float *out, hipStream_t s) {
   const int64_t n = G.n_in * C;
   unpack_kernel<<<blocks_for(n), kBlock, 0, s>>>(n, C, (int64_t)G.nz * G.nyi * G.nxi, a, out);
@@ -795,12 +878,12 @@ void launch_cnn_pair_inplace(const Grid &g, const T *phi, const T *base, const d
   pair_inplace_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g.n, phi, base, sc, d, x, t);
 }
 
-void launch_cnn_gather(const float *X, const float *Tt, int npairs, int nz, int ny, int nx,
+void launch_cnn_gather(const float *X, const float *Tt, int npairs, int C, int nz, int ny, int nx,
                        const int32_t *crops, int batch, int cy, int cx, float *xb, float *tb,
                        hipStream_t s) {
-  const int64_t n_in = (int64_t)batch * nz * (cy + 8) * (cx + 8);
+  const int64_t n_in = (int64_t)batch * C * nz * (cy + 8) * (cx + 8);
   const int64_t n_t = (int64_t)batch * nz * cy * cx;
-  gather_kernel<<<blocks_for(n_in + n_t), kBlock, 0, s>>>(X, Tt, (int64_t)nz * ny * nx, nz, ny,
+  gather_kernel<<<blocks_for(n_in + n_t), kBlock, 0, s>>>(X, Tt, (int64_t)nz * ny * nx, C, nz, ny,
                                                           nx, crops, npairs, cy, cx, n_in, n_t,
                                                           xb, tb);
 }
@@ -814,7 +897,11 @@ void launch_cnn_gather(const float *X, const float *Tt, int npairs, int nz, int 
   template void launch_cnn_pair<T>(const Grid &, const float *, const T *, const T *,            \
                                    const double *, double, float *, float *, hipStream_t);        \
   template void launch_cnn_pair_inplace<T>(const Grid &, const T *, const T *, const double *,   \
-                                           double, float *, float *, hipStream_t);
+                                           double, float *, float *, hipStream_t);              \
+  template void launch_cnn_input3<T>(const Grid &, const float *, const T *, const T *,          \
+                                     const double *, double, uint16_t *, hipStream_t);           \
+  template void launch_cnn_pair3<T>(const Grid &, const float *, const T *, const T *, const T *, \
+                                    const double *, double, float *, float *, hipStream_t);
 CNN_INST(float)
 CNN_INST(double)
 #undef CNN_INST

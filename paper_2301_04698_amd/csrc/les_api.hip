@@ -102,7 +102,7 @@ int validate(const les_config *c) {
     return fail(LES_ERR_ARG, "unknown phase partition %d", c->phase);
   if (c->phase == LES_PHASE_RAMP && !(c->T_ice > 0 && c->T_ice < c->Tf))
     return fail(LES_ERR_ARG, "T_ice must be in (0, Tf) for LES_PHASE_RAMP");
-  if (c->guess < LES_GUESS_ZERO || c->guess > LES_GUESS_LEARNED)
+  if (c->guess < LES_GUESS_ZERO || c->guess > LES_GUESS_LEARNED3)
     return fail(LES_ERR_ARG, "unknown guess mode %d", c->guess);
   if (c->mean_mode != LES_MEAN_SWEPT && c->mean_mode != LES_MEAN_LEVEL &&
       c->mean_mode != LES_MEAN_EXACT)
@@ -112,6 +112,19 @@ int validate(const les_config *c) {
 }
 
 size_t elem_size(const les_config *c) { return c->precision == LES_FP64 ? 8 : 4; }
+
+// Guess modes that keep each sub-iteration's previous solution; that keep
+// the previous step's pressure; the input channels of the guess network (0:
+// none).
+bool uses_hist(const les_config *c) {
+  return c->guess == LES_GUESS_PREVIOUS || c->guess == LES_GUESS_LEARNED;
+}
+bool uses_pm2(const les_config *c) {
+  return c->guess == LES_GUESS_EXTRAPOLATE || c->guess == LES_GUESS_LEARNED3;
+}
+int cnn_inputs_of(const les_config *c) {
+  return c->guess == LES_GUESS_LEARNED ? 1 : c->guess == LES_GUESS_LEARNED3 ? 3 : 0;
+}
 
 Layout layout_of(const les_config *c) {
   Layout L;
@@ -141,22 +154,23 @@ Layout layout_of(const les_config *c) {
   off = align_up(off + sizeof(SolveCtl));
   L.diag = off;
   off = align_up(off + (size_t)c->nz * kDiagStride * sizeof(double));
-  L.hist = off;
-  const bool hist = c->guess == LES_GUESS_PREVIOUS || c->guess == LES_GUESS_LEARNED;
-  if (hist) off = align_up(off + (size_t)c->n_subiter * n * es);
-  const bool cnn = c->guess == LES_GUESS_LEARNED;
+  L.hist = off;  // LES_GUESS_LEARNED3: one field, the extrapolated base
+  if (uses_hist(c)) off = align_up(off + (size_t)c->n_subiter * n * es);
+  else if (c->guess == LES_GUESS_LEARNED3) off = align_up(off + n * es);
+  const int ci = cnn_inputs_of(c);
+  const bool cnn = ci > 0;
   L.cnn_r = off;
   if (cnn) off = align_up(off + n * sizeof(float));
   L.cnn_a0 = off;
-  if (cnn) off = align_up(off + n * sizeof(uint16_t));
+  if (cnn) off = align_up(off + n * ci * sizeof(uint16_t));
   for (int q = 0; q < 2; ++q) {
     L.cnn_act[q] = off;
     if (cnn) off = align_up(off + n * kCnnCh * sizeof(uint16_t));
   }
   L.cnn_params = off;
-  if (cnn) off = align_up(off + (size_t)cnn_param_count() * sizeof(float));
+  if (cnn) off = align_up(off + (size_t)cnn_param_count(ci) * sizeof(float));
   L.cnn_packed = off;
-  if (cnn) off = align_up(off + (size_t)cnn_param_count() * sizeof(uint16_t));
+  if (cnn) off = align_up(off + (size_t)cnn_param_count(ci) * sizeof(uint16_t));
   L.cnn_sc = off;
   if (cnn) off = align_up(off + 4 * sizeof(double));
   L.total = off;
@@ -797,12 +811,15 @@ int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step
       // Starting iterate: the previous step's solution of this sub-iteration
       // (corrected by the network in the learned form, whose input is the
       // residual of that solution for the centred right-hand side), or at
-      // k = 0 the extrapolated pressure change: p holds p^n and the
-      // workspace p^{n-1}, then p^{n-1} <- p^n.
+      // k = 0 the extrapolated pressure change alpha0 (p^n - p^{n-1}): p
+      // holds p^n and the workspace p^{n-1}, then p^{n-1} <- p^n (corrected
+      // by the three-input network in LES_GUESS_LEARNED3).  `base`: the
+      // field a guess starts from (dumped for training pairs).
       T *hist = (T *)ws(h, h->lay.hist) + (size_t)k * g.n;
-      const T *guess = nullptr;
-      if (c.guess == LES_GUESS_PREVIOUS || c.guess == LES_GUESS_LEARNED) {
+      const T *guess = nullptr, *base = nullptr;
+      if (uses_hist(&c)) {
         if (h->hist_valid[k]) {
+          base = hist;
           if (c.guess == LES_GUESS_PREVIOUS) {
             guess = hist;
           } else {
@@ -811,11 +828,24 @@ int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step
             guess = V.f[F_GUESS];
           }
         }
-      } else if (k == 0 && c.guess == LES_GUESS_EXTRAPOLATE) {
-        launch_extrapolate<T>(g, V.P, V.p, V.f[F_PM2], V.f[F_GUESS], s);
+      } else if (k == 0 && uses_pm2(&c)) {
+        T *ext = c.guess == LES_GUESS_EXTRAPOLATE ? V.f[F_GUESS] : hist;
+        launch_extrapolate<T>(g, V.P, V.p, V.f[F_PM2], ext, s);
         HIP_TRY(hipMemcpyAsync(V.f[F_PM2], V.p, bytes, hipMemcpyDeviceToDevice, s));
         LAUNCH_TRY();
-        guess = V.f[F_GUESS];
+        base = guess = ext;
+        if (c.guess == LES_GUESS_LEARNED3) {
+          const int grc = cnn_guess<T>(h, V, V.f[F_RHS], ext, V.f[F_GUESS]);
+          if (grc) return grc;
+          guess = V.f[F_GUESS];
+        }
+      }
+      if (step == nsteps - 1 && opts && opts->dump_base) {
+        T *db = (T *)opts->dump_base + (size_t)k * g.n;
+        if (base)
+          HIP_TRY(hipMemcpyAsync(db, base, bytes, hipMemcpyDeviceToDevice, s));
+        else
+          launch_zero<T>(g, db, s);
       }
       // Defect form: the sweeps solve for the correction from zero, so FP32
       // rounding acts at the correction's size, not the guess's.  A guess
@@ -851,7 +881,7 @@ int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step
       launch_final(V.partials, kReduceBlocks, kFinalPhiMean, V.ctl, (double)g.n, 0.0, 0, nullptr, s);
       launch_mean_profiles<T>(g, V.phibar, V.P.rho0, V.P.alpha0, 1, V.pbar, V.phigz_w, V.cbar_w,
                               V.pgz_w, s);
-      if (c.guess == LES_GUESS_PREVIOUS || c.guess == LES_GUESS_LEARNED) {
+      if (uses_hist(&c)) {
         launch_sub_mean<T>(g, phi, V.ctl, hist, s);
         h->hist_valid[k] = 1;
       }
@@ -1004,7 +1034,8 @@ int diag_impl(les_handle *h, les_diag *out, double *profiles) {
 }
 
 // Learned guess: r = rhs - L base, s = RMS(r) (FP64 sums), network on
-// bf16(r / s) over the periodic field, guess = base + (s/d) out.
+// bf16(r / s) (three inputs: and bf16(base d / s), bf16(rhs / s)) over the
+// periodic field, guess = base + (s/d) out.
 template <typename T>
 int cnn_guess(les_handle *h, View<T> &V, const T *rhs, const T *base, T *guess) {
   if (!h->cnn_bound)
@@ -1019,18 +1050,19 @@ int cnn_guess(les_handle *h, View<T> &V, const T *rhs, const T *base, T *guess) 
   const uint16_t *packed = (const uint16_t *)ws(h, L.cnn_packed);
   double *sc = (double *)ws(h, L.cnn_sc);
   const double D = 2.0 / (g.dx * g.dx) + 2.0 / (g.dy * g.dy) + 2.0 / (g.dz * g.dz);
+  const int ci = cnn_inputs_of(&h->cfg);
   launch_cnn_residual<T>(g, rhs, base, r, V.partials, s);
   launch_cnn_scale(V.partials, (double)g.n, D, sc, s);
-  launch_cnn_round(g.n, r, sc + 1, a0, s);
+  if (ci == 3)
+    launch_cnn_input3<T>(g, r, base, rhs, sc, D, a0, s);
+  else
+    launch_cnn_round(g.n, 1, g.n, r, sc + 1, a0, s);
   // one periodic field: batch 1, (nz, ny, nx)
-  const CnnGeom G0 = cnn_geom(1, g.nz, g.ny, g.nx, 1, 0);
-  launch_cnn_conv(0, G0, a0, params, packed, h->cnn_alpha, act[0], nullptr, s);
-  launch_cnn_conv(1, cnn_geom(1, g.nz, g.ny, g.nx, 1, 1), act[0], params, packed, h->cnn_alpha,
-                  act[1], nullptr, s);
-  launch_cnn_conv(2, cnn_geom(1, g.nz, g.ny, g.nx, 1, 2), act[1], params, packed, h->cnn_alpha,
-                  act[0], nullptr, s);
-  launch_cnn_guess<T>(cnn_geom(1, g.nz, g.ny, g.nx, 1, 3), act[0], params, packed, base, sc + 2,
-                      guess, s);
+  auto geom = [&](int l) { return cnn_geom(1, g.nz, g.ny, g.nx, 1, l, ci); };
+  launch_cnn_conv(0, geom(0), a0, params, packed, h->cnn_alpha, act[0], nullptr, s);
+  launch_cnn_conv(1, geom(1), act[0], params, packed, h->cnn_alpha, act[1], nullptr, s);
+  launch_cnn_conv(2, geom(2), act[1], params, packed, h->cnn_alpha, act[0], nullptr, s);
+  launch_cnn_guess<T>(geom(3), act[0], params, packed, base, sc + 2, guess, s);
   LAUNCH_TRY();
   return LES_OK;
 }
@@ -1059,10 +1091,9 @@ StateLayout state_layout(const les_config &c) {
   S.pbar = off;
   off = align_up(off + (size_t)c.nz * sizeof(double));
   S.pm2 = off;
-  if (c.guess == LES_GUESS_EXTRAPOLATE) off = align_up(off + n * es);
+  if (uses_pm2(&c)) off = align_up(off + n * es);
   S.hist = off;
-  if (c.guess == LES_GUESS_PREVIOUS || c.guess == LES_GUESS_LEARNED)
-    off = align_up(off + (size_t)c.n_subiter * n * es);
+  if (uses_hist(&c)) off = align_up(off + (size_t)c.n_subiter * n * es);
   S.total = off;
   return S;
 }
@@ -1303,9 +1334,9 @@ int les_export_state(les_handle *h, void *dst) {
   if (e == hipSuccess)
     e = copy(d + S.pbar, ws(h, h->lay.mean_d) + pbar_index(c.nz) * sizeof(double),
              (size_t)c.nz * sizeof(double), hipMemcpyDeviceToDevice);
-  if (e == hipSuccess && c.guess == LES_GUESS_EXTRAPOLATE)
+  if (e == hipSuccess && uses_pm2(&c))
     e = copy(d + S.pm2, ws(h, h->lay.field[F_PM2]), n * es, hipMemcpyDeviceToDevice);
-  if (e == hipSuccess && (c.guess == LES_GUESS_PREVIOUS || c.guess == LES_GUESS_LEARNED))
+  if (e == hipSuccess && uses_hist(&c))
     e = copy(d + S.hist, ws(h, h->lay.hist), (size_t)c.n_subiter * n * es,
              hipMemcpyDeviceToDevice);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -1343,9 +1374,9 @@ int les_import_state(les_handle *h, const void *src) {
   };
   hipError_t e = copy(ws(h, h->lay.mean_d) + pbar_index(c.nz) * sizeof(double), d + S.pbar,
                       (size_t)c.nz * sizeof(double));
-  if (e == hipSuccess && c.guess == LES_GUESS_EXTRAPOLATE)
+  if (e == hipSuccess && uses_pm2(&c))
     e = copy(ws(h, h->lay.field[F_PM2]), d + S.pm2, n * es);
-  if (e == hipSuccess && (c.guess == LES_GUESS_PREVIOUS || c.guess == LES_GUESS_LEARNED))
+  if (e == hipSuccess && uses_hist(&c))
     e = copy(ws(h, h->lay.hist), d + S.hist, (size_t)c.n_subiter * n * es);
   if (e != hipSuccess) {
     h->broken = true;
@@ -1433,17 +1464,19 @@ void les_destroy(les_handle *h) {
 int les_bind_cnn(les_handle *h, const float *params, double alpha) {
   int rc = check_handle(h);
   if (rc) return rc;
-  if (h->cfg.guess != LES_GUESS_LEARNED)
-    return fail(LES_ERR_STATE, "les_bind_cnn: the handle was not created with LES_GUESS_LEARNED");
+  const int ci = cnn_inputs_of(&h->cfg);
+  if (!ci)
+    return fail(LES_ERR_STATE,
+                "les_bind_cnn: the handle was not created with LES_GUESS_LEARNED or _LEARNED3");
   if (!params) return fail(LES_ERR_ARG, "params is NULL");
   if (!(alpha >= 0.0)) return fail(LES_ERR_ARG, "alpha must be >= 0");
   float *dst = (float *)ws(h, h->lay.cnn_params);
-  if (hipMemcpyAsync(dst, params, (size_t)cnn_param_count() * sizeof(float),
+  if (hipMemcpyAsync(dst, params, (size_t)cnn_param_count(ci) * sizeof(float),
                      hipMemcpyDeviceToDevice, h->stream) != hipSuccess) {
     h->broken = true;
     return fail(LES_ERR_HIP, "copy of the network parameters failed");
   }
-  launch_cnn_pack(dst, (uint16_t *)ws(h, h->lay.cnn_packed), h->stream);
+  launch_cnn_pack(dst, cnn_param_count(ci), (uint16_t *)ws(h, h->lay.cnn_packed), h->stream);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) {
     h->broken = true;
     return fail(LES_ERR_HIP, "packing the network parameters failed");
@@ -1456,8 +1489,9 @@ int les_bind_cnn(les_handle *h, const float *params, double alpha) {
 int les_cnn_guess(les_handle *h, const void *rhs, const void *base, void *guess, double *scale) {
   int rc = check_handle(h);
   if (rc) return rc;
-  if (h->cfg.guess != LES_GUESS_LEARNED)
-    return fail(LES_ERR_STATE, "les_cnn_guess: the handle was not created with LES_GUESS_LEARNED");
+  if (!cnn_inputs_of(&h->cfg))
+    return fail(LES_ERR_STATE,
+                "les_cnn_guess: the handle was not created with LES_GUESS_LEARNED or _LEARNED3");
   if (!rhs || !base || !guess) return fail(LES_ERR_ARG, "rhs, base and guess must be non-NULL");
   if (h->cfg.precision == LES_FP64) {
     View<double> V = view_of<double>(h);

@@ -4,12 +4,16 @@ Pairs come from the solver itself: runs with the previous-solution guess
 dump, every step, the right-hand side and solution of each sub-iteration's
 solve; consecutive steps give (base = last step's solution, rhs, phi*)
 triples, stored as normalised network inputs and targets (les_cnn_pair).
+The three-input network (--inputs 3) learns the first solve of a step from
+runs with the extrapolated-pressure guess: (base = alpha0 (p^n - p^{n-1}),
+rhs, phi*) of every step's first solve (les_cnn_pair3).
 Training draws random crops (les_cnn_gather) and runs the library's own
 forward, loss, backward and Adam kernels (les_cnn_train_step).  Every
 arithmetic step runs in the HIP library; this module only drives it.
 
 Command line:
     python -m paper_2301_04698_amd.guess_train --workload C4 --out weights.npy
+    python -m paper_2301_04698_amd.guess_train --workload C4 --inputs 3 --out weights3.npy
 """
 from __future__ import annotations
 
@@ -30,6 +34,7 @@ import les_inputs as li  # noqa: E402
 from . import cnn, les  # noqa: E402
 
 BLOCKS = [(27 * ci * co, 27 * ci, co) for ci, co in zip(cnn.CIN, cnn.COUT)]
+BLOCKS3 = [(27 * cnn.cin(l, 3) * co, 27 * cnn.cin(l, 3), co) for l, co in enumerate(cnn.COUT)]
 DEFAULT_ALPHA = 0.1
 
 
@@ -77,18 +82,57 @@ def collect(p, seeds, windows, window_len, device="cuda"):
     return X, T
 
 
+def collect3(p, seeds, windows, window_len, device="cuda"):
+    """Pairs of the three-input network: each of window_len consecutive
+    steps from every window start gives the (inputs, target) of its first
+    solve, from runs with the extrapolated guess.  Returns (X, T) float32
+    tensors of shapes (npairs, 3, nz, ny, nx) and (npairs, nz, ny, nx)."""
+    import torch
+    K = p["n_subiter"]
+    shape = (p["nz"], p["ny"], p["nx"])
+    n = int(np.prod(shape))
+    npairs = len(seeds) * len(windows) * window_len
+    X = torch.empty((npairs, 3) + shape, dtype=torch.float32, device=device)
+    T = torch.empty((npairs,) + shape, dtype=torch.float32, device=device)
+    q = 0
+    for seed in seeds:
+        ps = dict(p, seed=int(seed), guess="extrapolate")
+        sim = les.LES(ps, li.initial_state(ps), device=device)
+        rhs = torch.empty(K * n, dtype=sim.dtype, device=device)
+        phi, base = torch.empty_like(rhs), torch.empty_like(rhs)
+        scratch = None
+        done = 0
+        for w0 in windows:
+            if w0 > done:
+                sim.step(w0 - done)
+                done = w0
+            for m in range(window_len):
+                sim.step(1, dump=(rhs, phi), dump_base=base)
+                done += 1
+                cnn.pair3(sim, rhs[:n], base[:n], phi[:n], X[q], T[q], scratch)
+                q += 1
+            log(f"collect: seed {seed} steps {done} pairs {q}/{npairs}")
+        sim.close()
+    assert q == npairs
+    return X, T
+
+
 def train(X, T, p, iters=4000, batch=16, crop=32, lr=2e-3, seed=0, alpha=DEFAULT_ALPHA,
           log_every=200, init=None):
     """Adam on random crops with a cosine learning-rate decay.  The loss is
     evaluated on crop x crop interior cells (output crop + 2).  Returns
     (params float32 tensor, loss history [(iteration, loss)])."""
     import torch
-    npairs, nz, ny, nx = X.shape
-    p0 = torch.from_numpy(init if init is not None else li.cnn_init(seed, BLOCKS)).float()
+    inputs = 1 if X.dim() == 4 else X.shape[1]
+    npairs, nz, ny, nx = X.shape[0], X.shape[-3], X.shape[-2], X.shape[-1]
+    blocks = BLOCKS if inputs == 1 else BLOCKS3
+    p0 = torch.from_numpy(init if init is not None else li.cnn_init(seed, blocks)).float()
     tr = cnn.Trainer(p0, batch, nz, crop + 2, crop + 2, p["dx"], p["dy"], p["dz"], alpha=alpha,
                      lr=lr, device=X.device)
     rng = np.random.default_rng(seed)
-    xb = torch.empty((batch, nz, crop + 10, crop + 10), dtype=torch.float32, device=X.device)
+    xshape = (batch, nz, crop + 10, crop + 10) if inputs == 1 else \
+        (batch, inputs, nz, crop + 10, crop + 10)
+    xb = torch.empty(xshape, dtype=torch.float32, device=X.device)
     tb = torch.empty((batch, nz, crop + 2, crop + 2), dtype=torch.float32, device=X.device)
     hist = []
     for it in range(iters):
@@ -111,7 +155,7 @@ def run_mode(p, state, mode, nsteps, params=None, alpha=DEFAULT_ALPHA, device="c
     import torch
     ps = dict(p, guess=mode)
     sim = les.LES(ps, state, device=device, pbar=pbar)
-    if mode == "learned":
+    if mode in ("learned", "learned3"):
         cnn.bind(sim, params, alpha)
     sim.step(1)
     torch.cuda.synchronize()
@@ -177,6 +221,9 @@ def evaluate(p, params, seed, spinup, nsteps, alpha=DEFAULT_ALPHA, modes=("zero"
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="C4")
+    ap.add_argument("--inputs", type=int, default=1, choices=(1, 3),
+                    help="1: residual input, every solve; 3: previous pressures and the "
+                         "divergence, first solve of a step")
     ap.add_argument("--seeds", default="1000,1001,1002")
     ap.add_argument("--windows", default="40,150,300")
     ap.add_argument("--window-len", type=int, default=3)
@@ -197,10 +244,12 @@ def main():
     import torch
     torch.cuda.set_device(0)
     p = li.workload(a.workload)
+    modes = ("zero", "previous", "learned") if a.inputs == 1 else ("zero", "extrapolate",
+                                                                   "learned3")
     if a.eval_only:
         params = torch.from_numpy(np.load(a.out)).cuda()
         t0 = time.perf_counter()
-        res = evaluate(p, params, a.eval_seed, a.eval_spinup, a.eval_steps, a.alpha)
+        res = evaluate(p, params, a.eval_seed, a.eval_spinup, a.eval_steps, a.alpha, modes)
         summary = dict(workload=a.workload, weights=os.path.basename(a.out), eval_seed=a.eval_seed,
                        eval_spinup=a.eval_spinup, eval_steps=a.eval_steps,
                        eval_s=time.perf_counter() - t0, eval=res)
@@ -209,8 +258,9 @@ def main():
         log(json.dumps(summary))
         return
     t0 = time.perf_counter()
-    X, T = collect(p, [int(s) for s in a.seeds.split(",")], [int(w) for w in a.windows.split(",")],
-                   a.window_len)
+    gather_pairs = collect if a.inputs == 1 else collect3
+    X, T = gather_pairs(p, [int(s) for s in a.seeds.split(",")],
+                        [int(w) for w in a.windows.split(",")], a.window_len)
     t1 = time.perf_counter()
     params, hist = train(X, T, p, a.iters, a.batch, a.crop, a.lr, alpha=a.alpha)
     torch.cuda.synchronize()
@@ -218,10 +268,12 @@ def main():
     del X, T
     np.save(a.out, params.cpu().numpy().astype(np.float32))
     res = None if a.no_eval else evaluate(p, params, a.eval_seed, a.eval_spinup, a.eval_steps,
-                                          a.alpha)
-    npairs = len(a.seeds.split(",")) * len(a.windows.split(",")) * a.window_len * p["n_subiter"]
+                                          a.alpha, modes)
+    npairs = len(a.seeds.split(",")) * len(a.windows.split(",")) * a.window_len * \
+        (p["n_subiter"] if a.inputs == 1 else 1)
     summary = dict(command="python -m paper_2301_04698_amd.guess_train " + " ".join(sys.argv[1:]),
-                   workload=a.workload, seeds=[int(x) for x in a.seeds.split(",")],
+                   workload=a.workload, inputs=a.inputs,
+                   seeds=[int(x) for x in a.seeds.split(",")],
                    windows=[int(x) for x in a.windows.split(",")], window_len=a.window_len,
                    pairs=npairs, crop_samples=a.iters * a.batch, collect_s=t1 - t0,
                    train_s=t2 - t1, loss=hist, alpha=a.alpha, iters=a.iters, batch=a.batch,

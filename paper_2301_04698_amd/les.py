@@ -28,8 +28,10 @@ PHASES = {"heaviside": LES_PHASE_HEAVISIDE, "ramp": LES_PHASE_RAMP}
 LES_MEAN_SWEPT, LES_MEAN_LEVEL, LES_MEAN_EXACT = 0, 1, 2
 MEAN_MODES = {"swept": LES_MEAN_SWEPT, "level": LES_MEAN_LEVEL, "exact": LES_MEAN_EXACT}
 LES_GUESS_ZERO, LES_GUESS_EXTRAPOLATE, LES_GUESS_PREVIOUS, LES_GUESS_LEARNED = 0, 1, 2, 3
+LES_GUESS_LEARNED3 = 4
 GUESS_MODES = {"zero": LES_GUESS_ZERO, "extrapolate": LES_GUESS_EXTRAPOLATE,
-               "previous": LES_GUESS_PREVIOUS, "learned": LES_GUESS_LEARNED}
+               "previous": LES_GUESS_PREVIOUS, "learned": LES_GUESS_LEARNED,
+               "learned3": LES_GUESS_LEARNED3}
 NPROFILES = 9
 PROFILE_NAMES = ("thl", "qt", "ql", "u", "v", "w", "w2", "w3", "b")
 
@@ -90,7 +92,7 @@ class LesStepOpts(C.Structure):
     _fields_ = [("replay_sweeps", C.POINTER(C.c_int32)), ("records", C.POINTER(LesSolveStats)),
                 ("time_sweeps", C.c_int32), ("reserved", C.c_int32),
                 ("dump_rhs", C.c_void_p), ("dump_phi", C.c_void_p),
-                ("dump_mean", C.POINTER(C.c_double))]
+                ("dump_mean", C.POINTER(C.c_double)), ("dump_base", C.c_void_p)]
 
 
 class LesStepStats(C.Structure):
@@ -276,7 +278,7 @@ class LES:
         return self.cfg.nx * self.cfg.ny * self.cfg.nz
 
     def step(self, nsteps=1, replay=None, records=False, time_sweeps=False, dump=None,
-             dump_mean=None):
+             dump_mean=None, dump_base=None):
         """Advance nsteps; returns (rc, stats dict, per-solve records or None).
 
         dump: optional (rhs, phi) device tensors of n_subiter * n elements
@@ -285,7 +287,9 @@ class LES:
         exact mean mode both lack their horizontally uniform parts, which
         dump_mean (a float64 numpy array of n_subiter * (2 nz + 1) values)
         receives: per solve the per-level values the centring subtracted,
-        the solution's horizontally uniform part, and the rhs mean."""
+        the solution's horizontally uniform part, and the rhs mean.
+        dump_base: device tensor of n_subiter * n elements receiving the
+        field each of the last step's solves started its guess from."""
         K = self.cfg.n_subiter
         opts = LesStepOpts()
         opts.time_sweeps = 1 if time_sweeps else 0
@@ -294,6 +298,10 @@ class LES:
                 assert t.is_contiguous() and t.dtype == self.dtype and t.numel() == K * self._n()
             opts.dump_rhs = dump[0].data_ptr()
             opts.dump_phi = dump[1].data_ptr()
+        if dump_base is not None:
+            assert (dump_base.is_contiguous() and dump_base.dtype == self.dtype
+                    and dump_base.numel() == K * self._n())
+            opts.dump_base = dump_base.data_ptr()
         if dump_mean is not None:
             assert dump_mean.dtype == np.float64 and dump_mean.flags.c_contiguous
             assert dump_mean.size == K * (2 * self.cfg.nz + 1)

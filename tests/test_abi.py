@@ -18,7 +18,7 @@ def declared_functions():
     for h in ("les.h", "les_cnn.h"):
         src = open(os.path.join(ROOT, "include", h)).read()
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-        names |= set(re.findall(r"\b(les_[a-z_]+)\s*\(", src))
+        names |= set(re.findall(r"\b(les_[a-z0-9_]+)\s*\(", src))
     return sorted(names)
 
 
@@ -165,17 +165,24 @@ int main(void) {
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     assert got == [C.sizeof(cnn.CnnDims), cnn.CnnDims.alpha.offset]
     assert cnn.param_count() == ocnn.param_count() == 14737
-    for l in range(4):
-        assert cnn.weight_offset(l) == ocnn.weight_offset(l)
-        assert cnn.bias_offset(l) == ocnn.bias_offset(l)
+    assert cnn.param_count(3) == ocnn.param_count(3) == 15601
+    for inputs in (1, 3):
+        for l in range(4):
+            assert cnn.weight_offset(l, inputs) == ocnn.weight_offset(l, inputs)
+            assert cnn.bias_offset(l, inputs) == ocnn.bias_offset(l, inputs)
+    with pytest.raises(lib.LesError):
+        cnn.param_count(2)
 
 
 def test_cnn_work_bytes_validation(lib):
     from paper_2301_04698_amd import cnn
     ok = cnn.dims((2, 16, 20, 21), periodic=False)
     assert cnn.work_bytes(ok) > 2 * 16 * 20 * 21 * (2 + 3 * 32)
+    three = cnn.dims((2, 3, 16, 20, 21), periodic=False)
+    assert three.inputs == 3
+    assert cnn.work_bytes(three) - cnn.work_bytes(ok) >= 2 * 16 * 20 * 21 * 2 * 2
     for bad in (cnn.dims((0, 16, 20, 20)), cnn.dims((1, 16, 10, 20)),
-                cnn.dims((1, 16, 20, 20), alpha=-1.0)):
+                cnn.dims((1, 16, 20, 20), alpha=-1.0), cnn.dims((1, 2, 16, 20, 20))):
         with pytest.raises(lib.LesError):
             cnn.work_bytes(bad)
     assert cnn.work_bytes(cnn.dims((1, 8, 5, 5), periodic=True)) > 0
@@ -190,3 +197,7 @@ def test_learned_guess_workspace(lib):
     assert prev >= base + p["n_subiter"] * n * 8
     # residual, network input, two 16-channel activations and the parameters
     assert learned >= prev + n * (4 + 2 + 2 * 32) + 14737 * 6
+    # the three-input form: the previous pressure, the extrapolated base,
+    # three input channels and the larger parameter vector
+    learned3 = lib.workspace_bytes(lib.make_config(dict(p, guess="learned3")))
+    assert learned3 >= base + n * 8 + n * (4 + 6 + 2 * 32) + 15601 * 6

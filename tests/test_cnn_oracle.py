@@ -246,3 +246,96 @@ def test_adam_matches_torch():
         opt.step()
         cnn.adam(p, g.copy(), m, v, s, lr=2e-3, beta1=0.9, beta2=0.99, eps=1e-8)
     np.testing.assert_allclose(p, w.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+# ------------------------------------------- three inputs (p_{n-1}, p_{n-2}, rhs)
+
+BLOCKS3 = [(27 * cnn.cin(l, 3) * co, 27 * cnn.cin(l, 3), co) for l, co in enumerate(cnn.COUT)]
+
+
+def test_layout_three_inputs():
+    assert cnn.cin(0, 3) == 3 and cnn.cin(1, 3) == 16
+    assert cnn.param_count(3) == sum(nw + nb for nw, _, nb in BLOCKS3) == 14737 + 27 * 16 * 2
+    assert cnn.weight_offset(1, 3) == 27 * 3 * 16 + 16
+    assert cnn.bias_offset(0, 3) == 27 * 3 * 16
+    assert cnn.bias_offset(3, 3) == cnn.param_count(3) - 1
+    assert cnn.param_count(2) == -1
+
+
+def _three_from_one(p1, rng):
+    """Three-input parameters: p1's layers, layer 0 widened with random
+    weights for input channels 1 and 2 (W[tap][cout][cin])."""
+    W1 = p1[:cnn.bias_offset(0)].reshape(27, 16, 1)
+    W3 = np.concatenate([W1, rng.standard_normal((27, 16, 2))], axis=2)
+    return np.concatenate([W3.ravel(), p1[cnn.bias_offset(0):]])
+
+
+@pytest.mark.parametrize("c_out", [0, 9])
+def test_three_input_layer_is_sum_of_correlations(c_out):
+    """Layer 0 of the three-input network: output channel o is the sum over
+    input channels of scipy correlations with W[:, o, c] plus the bias;
+    layers 1-3 pass channel o through their centre taps (slope 1)."""
+    rng = np.random.default_rng(11)
+    p1 = _select(params(9, bias=0.4), 0, 0, c_out)
+    p = _three_from_one(p1, rng)
+    x = rng.standard_normal((2, 3, 6, 9, 10))
+    out, acts, _ = cnn.forward(p, x, periodic=True, alpha=1.0, bf16=False)
+    assert acts[0].shape == (2, 3, 6, 9, 10)
+    W = p[:cnn.bias_offset(0, 3)].reshape(27, 16, 3)
+    for s in range(2):
+        ref = sum(correlate(x[s, c], W[:, c_out, c].reshape(3, 3, 3)) for c in range(3))
+        ref = ref + p[cnn.bias_offset(0, 3) + c_out]
+        np.testing.assert_allclose(out[s], ref, rtol=0, atol=1e-12)
+
+
+def test_three_inputs_with_zero_extra_weights_equal_one_input():
+    """Zero weights on input channels 1 and 2 give the one-input network
+    bit for bit, bfloat16 rounding on, whatever those channels hold."""
+    rng = np.random.default_rng(12)
+    p1 = params(10, bias=0.2)
+    p3 = _three_from_one(p1, rng)
+    W3 = p3[:cnn.bias_offset(0, 3)].reshape(27, 16, 3)
+    W3[:, :, 1:] = 0.0
+    p3[:cnn.bias_offset(0, 3)] = W3.ravel()
+    x1 = rng.standard_normal((1, 5, 12, 12))
+    x3 = np.concatenate([x1[:, None], rng.standard_normal((1, 2, 5, 12, 12))], axis=1)
+    o1, _, _ = cnn.forward(p1, x1, periodic=False)
+    o3, _, _ = cnn.forward(p3, x3, periodic=False)
+    assert np.array_equal(o1, o3)
+
+
+def test_three_input_backward_finite_difference():
+    """Gradient of loss(forward(params)) of the three-input network against
+    central differences (FP64 network, valid crops), layer-0 weights of every
+    input channel included."""
+    rng = np.random.default_rng(13)
+    p = li.cnn_init(14, BLOCKS3)
+    for l in range(cnn.LAYERS):
+        o = cnn.bias_offset(l, 3)
+        p[o:o + cnn.COUT[l]] = 0.2 * rng.standard_normal(cnn.COUT[l])
+    x = rng.standard_normal((2, 3, 4, 11, 12))
+    t = rng.standard_normal((2, 4, 3, 4))
+    dx, dy, dz = 35.0, 35.0, 5.0
+
+    def f(q):
+        out, _, _ = cnn.forward(q, x, periodic=False, alpha=0.1, bf16=False)
+        return cnn.loss(out, t, dx, dy, dz)[0]
+
+    out, acts, pre = cnn.forward(p, x, periodic=False, alpha=0.1, bf16=False)
+    _, gy = cnn.loss(out, t, dx, dy, dz)
+    grad = cnn.backward(p, x, acts, pre, gy, periodic=False, alpha=0.1, bf16=False)
+    scale = np.abs(grad).max()
+    W0 = np.arange(cnn.bias_offset(0, 3)).reshape(27, 16, 3)
+    picks = [int(W0[t_, o, c]) for t_, o, c in ((0, 0, 0), (13, 5, 1), (26, 15, 2), (4, 8, 2),
+                                                 (20, 3, 1))]
+    for l in range(1, cnn.LAYERS):
+        picks += list(rng.integers(cnn.weight_offset(l, 3), cnn.bias_offset(l, 3), 4))
+    picks += [cnn.bias_offset(0, 3), cnn.bias_offset(3, 3)]
+    for q in picks:
+        # a leaky-ReLU kink lies within 1e-5 of one of these weights: 1e-6 steps
+        h = 1e-6 * max(1.0, abs(p[q]))
+        pp, pm = p.copy(), p.copy()
+        pp[q] += h
+        pm[q] -= h
+        fd = (f(pp) - f(pm)) / (2 * h)
+        assert abs(grad[q] - fd) <= 1e-7 * scale + 1e-7 * abs(fd), (q, grad[q], fd)

@@ -276,3 +276,171 @@ def test_learned_step_converges(gpu):
     for k in ("u", "v", "w", "thl", "qt", "p"):
         d = out["zero"][k] - out["zero"][k].mean(axis=(1, 2), keepdims=True)
         assert np.linalg.norm(out["learned"][k] - out["zero"][k]) <= 1e-3 * np.linalg.norm(d)
+
+
+# ------------------------------------------- three inputs (p_{n-1}, p_{n-2}, rhs)
+
+BLOCKS3 = [(27 * ci * co, 27 * ci, co) for ci, co in zip((3, 16, 16, 16), (16, 16, 16, 1))]
+
+
+def params3(seed, bias=0.2):
+    from oracle import cnn as ocnn
+    p = li.cnn_init(seed, BLOCKS3)
+    rng = np.random.default_rng(seed)
+    for l in range(4):
+        o = ocnn.bias_offset(l, 3)
+        p[o:o + (16 if l < 3 else 1)] = np.float32(bias * rng.standard_normal(16 if l < 3 else 1))
+    return p
+
+
+@pytest.mark.parametrize("periodic,shape", [(False, (2, 3, 6, 21, 19)), (True, (1, 3, 5, 12, 40))])
+def test_forward_three_inputs_matches_oracle(gpu, periodic, shape):
+    from oracle import cnn as ocnn
+    p = params3(21)
+    x = np.random.default_rng(22).standard_normal(shape).astype(np.float32).astype(np.float64)
+    ref, _, _ = ocnn.forward(p, x, periodic=periodic, alpha=0.1)
+    P = _t(p)
+    out, _ = gpu.forward(P, gpu.pack(P), _t(x), periodic=periodic, alpha=0.1)
+    got = _np(out)
+    assert got.shape == ref.shape
+    assert rel(got, ref) <= 2e-4, rel(got, ref)
+
+
+@pytest.mark.parametrize("c_out", [0, 6, 15])
+def test_three_input_layer_routing(gpu, c_out):
+    """Layer 0 of the three-input network with random weights on every input
+    channel, later layers passing channel c_out through: the (tap, channel)
+    order of the matrix-core operand against the oracle."""
+    from oracle import cnn as ocnn
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from test_cnn_oracle import _select, _three_from_one
+    rng = np.random.default_rng(23)
+    p = _three_from_one(_select(params(3), 0, 0, c_out), rng)
+    p = p.astype(np.float32).astype(np.float64)
+    x = rng.standard_normal((2, 3, 4, 19, 23)).astype(np.float32).astype(float)
+    ref, _, _ = ocnn.forward(p, x, periodic=False, alpha=0.1)
+    P = _t(p)
+    out, _ = gpu.forward(P, gpu.pack(P), _t(x), periodic=False, alpha=0.1)
+    got = _np(out)
+    diff = np.abs(got - ref) > 1e-6 * np.abs(ref).max()
+    assert diff.mean() <= 1e-3, diff.mean()
+    assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3)) <= 2.0 ** -7
+
+
+def test_three_input_backward_on_identical_operands(gpu):
+    """As the one-input test: the oracle's backward on the GPU's stored
+    bfloat16 layer inputs (three channels into layer 0), <= 1e-5 per layer."""
+    from oracle import cnn as ocnn
+    p = params3(24)
+    rng = np.random.default_rng(25)
+    x = rng.standard_normal((2, 3, 5, 18, 20)).astype(np.float32).astype(float)
+    P = _t(p)
+    packed = gpu.pack(P)
+    out, work = gpu.forward(P, packed, _t(x), periodic=False, alpha=0.1)
+    acts = [np.ascontiguousarray(_np(gpu.stored_input(x.shape, work, l, alpha=0.1)))
+            for l in range(4)]
+    assert acts[0].shape == x.shape and np.array_equal(acts[0], ocnn.bf16(x))
+    gout = rng.standard_normal(_np(out).shape).astype(np.float32).astype(float)
+    ref = ocnn.backward(p, x, acts, [acts[1], acts[2], acts[3]], gout, periodic=False, alpha=0.1)
+    got = _np(gpu.backward(x.shape, packed, work, _t(gout), alpha=0.1))
+    for l in range(4):
+        a, b = ocnn.weight_offset(l, 3), ocnn.bias_offset(l, 3)
+        e = b + (16 if l < 3 else 1)
+        print(f"layer {l}: weight gradient {rel(got[a:b], ref[a:b]):.2e}, "
+              f"bias gradient {rel(got[b:e], ref[b:e]):.2e}")
+        assert rel(got[a:b], ref[a:b]) <= 1e-5, (l, rel(got[a:b], ref[a:b]))
+        assert rel(got[b:e], ref[b:e]) <= 1e-5, (l, "bias")
+
+
+def test_pair3_and_gather3(gpu, oracle_lib):
+    """Three-input pair: (r/s, base d/s, rhs/s) and the target, against the
+    formulas with the oracle's Laplacian; crops of three-channel pairs."""
+    import torch
+    from paper_2301_04698_amd import les
+    p = li.workload("C1", nx=24, ny=20, nz=16, precision="fp32")
+    sim = les.LES(p)
+    shape = (16, 20, 24)
+    rhs = li.random_field(shape, seed=31)
+    base = li.random_field(shape, seed=32) * 50.0
+    phi = base + li.random_field(shape, seed=33) * 5.0
+    cast = lambda a: torch.from_numpy(a.astype(np.float32)).cuda()
+    x = torch.empty((3,) + shape, device="cuda")
+    t = torch.empty(shape, device="cuda")
+    s = gpu.pair3(sim, cast(rhs), cast(base), cast(phi), x, t)
+    r32, b32 = rhs.astype(np.float32).astype(float), base.astype(np.float32).astype(float)
+    r = r32 - oracle_lib.laplacian(p, b32)
+    d = 2 / p["dx"] ** 2 + 2 / p["dy"] ** 2 + 2 / p["dz"] ** 2
+    s_ref = np.sqrt(np.mean(r ** 2))
+    assert s == pytest.approx(s_ref, rel=1e-6)
+    xg = _np(x)
+    assert rel(xg[0], r / s_ref) <= 1e-6
+    assert rel(xg[1], b32 * d / s_ref) <= 1e-6
+    assert rel(xg[2], r32 / s_ref) <= 1e-6
+    tref = (phi.astype(np.float32).astype(float) - b32) * d / s_ref
+    assert rel(_np(t), tref) <= 1e-6
+    X = torch.stack([x, 2 * x]).contiguous()
+    T = torch.stack([t, -t]).contiguous()
+    crops = torch.tensor([[1, 18, 22], [0, 0, 3]], dtype=torch.int32)
+    xb, tb = gpu.gather(X, T, crops.reshape(-1), 6, 5)
+    assert xb.shape == (2, 3, 16, 14, 13)
+    Xn, Tn = _np(X), _np(T)
+    for b, (pp, j0, i0) in enumerate([(1, 18, 22), (0, 0, 3)]):
+        jj = (j0 - 4 + np.arange(14)) % 20
+        ii = (i0 - 4 + np.arange(13)) % 24
+        assert np.array_equal(_np(xb)[b], Xn[pp][:, :, jj][:, :, :, ii])
+        jj = (j0 + np.arange(6)) % 20
+        ii = (i0 + np.arange(5)) % 24
+        assert np.array_equal(_np(tb)[b], Tn[pp][:, jj][:, :, ii])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_learned3_guess_matches_oracle(gpu, oracle_lib, precision):
+    """The three-input guess of a bound network on a whole periodic field
+    against the oracle's network on the same inputs."""
+    import torch
+    from oracle import cnn as ocnn
+    from paper_2301_04698_amd import les
+    p = li.workload("C1", nx=32, ny=24, nz=16, precision=precision, guess="learned3")
+    sim = les.LES(p)
+    prm = params3(34, bias=0.05)
+    gpu.bind(sim, _t(prm), alpha=0.1)
+    shape = (16, 24, 32)
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    R = torch.from_numpy(li.random_field(shape, seed=35)).to("cuda", dt)
+    B = torch.from_numpy(li.random_field(shape, seed=36) * 30.0).to("cuda", dt)
+    g, s = gpu.guess(sim, R, B)
+    rb, bb = _np(R), _np(B)
+    r = rb - oracle_lib.laplacian(dict(p, guess="zero"), bb)
+    s_ref = np.sqrt(np.mean(r ** 2))
+    assert s == pytest.approx(s_ref, rel=1e-6)
+    d = 2 / p["dx"] ** 2 + 2 / p["dy"] ** 2 + 2 / p["dz"] ** 2
+    x = np.stack([r, bb * d, rb]) / s_ref
+    x = x.astype(np.float32).astype(float)
+    out, _, _ = ocnn.forward(prm, x[None], periodic=True, alpha=0.1)
+    assert rel(_np(g) - bb, s_ref / d * out[0]) <= 5e-4
+
+
+def test_learned3_step_converges(gpu):
+    """A run with the three-input guess (random network) stops every solve
+    at the tolerance, starts only the first solve of a step from a guess,
+    and stays within tolerance-level distance of the plain run."""
+    from paper_2301_04698_amd import les
+    base = li.workload("C1m", nx=40, ny=24, nz=32, precision="fp32", poisson_tol=1e-5,
+                       poisson_scheme="chebyshev")
+    out = {}
+    for g in ("zero", "learned3"):
+        p = dict(base, guess=g)
+        sim = les.LES(p, li.initial_state(p))
+        if g == "learned3":
+            gpu.bind(sim, _t(params3(37, bias=0.0)) * 0.1, alpha=0.1)
+        rc, stats, recs = sim.step(5, records=True)
+        assert stats["not_converged"] == 0
+        for i, r in enumerate(recs):
+            assert r["res_norm"] <= p["poisson_tol"] * r["rhs_norm"]
+            if g == "learned3":
+                assert (r["guess"] != 0) == (i % p["n_subiter"] == 0), (i, r["guess"])
+        out[g] = sim.state_numpy()
+    for k in ("u", "v", "w", "thl", "qt", "p"):
+        d = out["zero"][k] - out["zero"][k].mean(axis=(1, 2), keepdims=True)
+        assert np.linalg.norm(out["learned3"][k] - out["zero"][k]) <= 1e-3 * np.linalg.norm(d)

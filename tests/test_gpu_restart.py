@@ -31,12 +31,16 @@ def _sim(gpu, p, state):
     if p["guess"] == "learned":
         prm, meta = cnn.load_weights()
         cnn.bind(sim, torch.from_numpy(prm).cuda(), alpha=meta["alpha"])
+    elif p["guess"] == "learned3":  # a seeded untrained three-input network, scaled down
+        blocks = [(27 * ci * co, 27 * ci, co) for ci, co in zip((3, 16, 16, 16), (16, 16, 16, 1))]
+        prm = 0.1 * li.cnn_init(5, blocks)
+        cnn.bind(sim, torch.from_numpy(prm.astype(np.float32)).cuda(), alpha=0.1)
     return sim
 
 
 @pytest.mark.parametrize("precision,guess", [("fp32", "zero"), ("fp32", "extrapolate"),
                                              ("fp32", "previous"), ("fp32", "learned"),
-                                             ("fp64", "previous")])
+                                             ("fp32", "learned3"), ("fp64", "previous")])
 def test_split_run_is_bitwise_the_whole_run(gpu, precision, guess):
     import torch
     p = li.workload("C1m", nx=40, ny=24, nz=32, precision=precision, poisson_scheme="chebyshev",

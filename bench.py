@@ -78,10 +78,10 @@ def parse():
     ap.add_argument("--guess-weights", default=GUESS_WEIGHTS,
                     help="trained guess network for the learned form ('' to skip it)")
     ap.add_argument("--guess-alpha", type=float, default=0.1)
-    ap.add_argument("--c5-warmup", type=int, default=2,
+    ap.add_argument("--c5-warmup", type=int, default=3,
                     help="largest-domain leg (1024x1024x256): untimed steps from the initial "
                          "state (learned form; its first step starts from zero)")
-    ap.add_argument("--c5-steps", type=int, default=1,
+    ap.add_argument("--c5-steps", type=int, default=5,
                     help="largest-domain leg: timed steps of each form from the same state "
                          "(0 skips the leg)")
     ap.add_argument("--advection", choices=("quick", "weno3"), default="quick",

@@ -183,24 +183,45 @@ __global__ __launch_bounds__(256) void conv_mid_kernel(CnnGeom G, const uint16_t
 #pragma unroll
   for (int r = 0; r < 4; ++r) bq[r] = bias[4 * quad + r];
 
-  // plane kk (mirror-clamped) into a slot: 2 x 16-B halves per cell
-  auto load_plane = [&](int kk, int slot) {
-    for (int e = threadIdx.x; e < kCnnPlane * 2; e += 256) {
-      const int cell = e >> 1, h = e & 1;
-      const int ly = cell / kCnnPX, lx = cell - ly * kCnnPX;
-      const uint4 v = *(const uint4 *)(ain + cnn_src(G, T, kk, ly, lx) * kCnnCh + 8 * h);
-      lds[slot][cell * 4 + cnn_swz(cell, 2 * h)] = make_uint2(v.x, v.y);
-      lds[slot][cell * 4 + cnn_swz(cell, 2 * h + 1)] = make_uint2(v.z, v.w);
+  // plane kk (mirror-clamped): 2 x 16-B halves per cell, kLoads per thread,
+  // fetched into registers first (the next plane's fetch overlaps this
+  // plane's products), then stored to a slot
+  constexpr int kLoads = (kCnnPlane * 2 + 255) / 256;
+  uint4 pre[kLoads];
+  auto fetch = [&](int kk) {
+#pragma unroll
+    for (int u = 0; u < kLoads; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      if (e < kCnnPlane * 2) {
+        const int cell = e >> 1, h = e & 1;
+        const int ly = cell / kCnnPX, lx = cell - ly * kCnnPX;
+        pre[u] = *(const uint4 *)(ain + cnn_src(G, T, kk, ly, lx) * kCnnCh + 8 * h);
+      }
+    }
+  };
+  auto store = [&](int slot) {
+#pragma unroll
+    for (int u = 0; u < kLoads; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      if (e < kCnnPlane * 2) {
+        const int cell = e >> 1, h = e & 1;
+        lds[slot][cell * 4 + cnn_swz(cell, 2 * h)] = make_uint2(pre[u].x, pre[u].y);
+        lds[slot][cell * 4 + cnn_swz(cell, 2 * h + 1)] = make_uint2(pre[u].z, pre[u].w);
+      }
     }
   };
 
-  load_plane(T.k0 - 1, (T.k0 + 2) % 3);
-  load_plane(T.k0, T.k0 % 3);
+  fetch(T.k0 - 1);
+  store((T.k0 + 2) % 3);
+  fetch(T.k0);
+  store(T.k0 % 3);
+  fetch(T.k0 + 1);
   const int oy = T.oy0 + wv;
   for (int k = T.k0; k < T.k1; ++k) {
     __syncthreads();  // slot (k+1)%3 is no longer read
-    load_plane(k + 1, (k + 1) % 3);
+    store((k + 1) % 3);
     __syncthreads();
+    if (k + 1 < T.k1) fetch(k + 2);  // in flight during this level's products
     floatx4 acc[4];
 #pragma unroll
     for (int t4 = 0; t4 < 4; ++t4) acc[t4] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -266,20 +287,41 @@ __global__ __launch_bounds__(256) void conv_in_kernel(CnnGeom G, const uint16_t 
   float bq[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) bq[r] = params[cnn_bias_offset(CI, 0) + 4 * quad + r];
-  auto load_plane = [&](int kk, int slot) {
-    for (int e = threadIdx.x; e < kCnnPlane * CI; e += 256) {
-      const int cell = e / CI, c = e - cell * CI;
-      const int ly = cell / kCnnPX, lx = cell - ly * kCnnPX;
-      lds[slot][c][cell] = ain[cnn_src(G, T, kk, ly, lx) * CI + c];
+  // plane kk (mirror-clamped) fetched into registers one plane ahead
+  constexpr int kLoads = (kCnnPlane * CI + 255) / 256;
+  uint16_t pre[kLoads];
+  auto fetch = [&](int kk) {
+#pragma unroll
+    for (int u = 0; u < kLoads; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      if (e < kCnnPlane * CI) {
+        const int cell = e / CI, c = e - cell * CI;
+        const int ly = cell / kCnnPX, lx = cell - ly * kCnnPX;
+        pre[u] = ain[cnn_src(G, T, kk, ly, lx) * CI + c];
+      }
     }
   };
-  load_plane(T.k0 - 1, (T.k0 + 2) % 3);
-  load_plane(T.k0, T.k0 % 3);
+  auto store = [&](int slot) {
+#pragma unroll
+    for (int u = 0; u < kLoads; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      if (e < kCnnPlane * CI) {
+        const int cell = e / CI, c = e - cell * CI;
+        lds[slot][c][cell] = pre[u];
+      }
+    }
+  };
+  fetch(T.k0 - 1);
+  store((T.k0 + 2) % 3);
+  fetch(T.k0);
+  store(T.k0 % 3);
+  fetch(T.k0 + 1);
   const int oy = T.oy0 + wv;
   for (int k = T.k0; k < T.k1; ++k) {
     __syncthreads();
-    load_plane(k + 1, (k + 1) % 3);
+    store((k + 1) % 3);
     __syncthreads();
+    if (k + 1 < T.k1) fetch(k + 2);
 #pragma unroll
     for (int t4 = 0; t4 < 4; ++t4) {
       floatx4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -312,8 +354,17 @@ __global__ __launch_bounds__(256) void conv_in_kernel(CnnGeom G, const uint16_t 
   }
 }
 
-// Layer 3 (16 -> 1): one thread per output cell of the 64 x 4 tile, inputs
-// from the same swizzled three-plane LDS ring as the 16 -> 16 layers.
+// Layer 3 (16 -> 1) as a matrix-core product per input plane, then a
+// gather.  For every cell of an input plane (the tile plus its one-cell
+// ring) D[t][cell] = sum_c W3[t][c] a[cell][c] for the 27 taps t: two
+// MFMAs per 16 cells (taps padded to 32 rows of A), kept in LDS.  Output
+// cell o then adds, per plane, the D of its 9 neighbours there for the taps
+// pointing back at o.  Marching the input planes k0-1 .. k1 (each read as
+// its mirror-clamped level, as every layer reads z), plane p completes
+// output level p - 1 (planes p - 2, p - 1, p); each thread keeps its output
+// cell's three open levels p - 1, p, p + 1 in registers rotated per plane.  LDS bank use: D rows are
+// kCnnPlane = 396 floats apart, so the four quads of a wave's D store land
+// in disjoint banks; the gather reads consecutive cells per lane.
 // GUESS: the output becomes the guess base + s_over_d * y.
 template <typename T, bool GUESS>
 __global__ __launch_bounds__(256) void conv_out_kernel(CnnGeom G, const uint16_t *__restrict__ ain,
@@ -324,52 +375,100 @@ __global__ __launch_bounds__(256) void conv_out_kernel(CnnGeom G, const uint16_t
                                                        const double *__restrict__ s_over_d,
                                                        T *__restrict__ guess, int tiles_x,
                                                        int tiles_y, int chunks) {
-  __shared__ uint2 lds[3][kCnnPlane * 4];
-  __shared__ float w[kCnnTaps * kCnnCh];
-  for (int e = threadIdx.x; e < kCnnTaps * kCnnCh; e += 256)
-    w[e] = bf2f(wbf[cnn_weight_offset(G.inputs, 3) + e]);
+  __shared__ uint2 lds[kCnnPlane * 4];        // one input plane: 16 channels per cell
+  __shared__ float dl[kCnnTaps][kCnnPlane];   // its per-tap products
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int row = lane & 15, quad = lane >> 4;
   const CnnTile Tl = cnn_tile(G, tiles_x, tiles_y, chunks);
-  const float b3 = params[cnn_bias_offset(G.inputs, 3)];
-  auto load_plane = [&](int kk, int slot) {
-    for (int e = threadIdx.x; e < kCnnPlane * 2; e += 256) {
-      const int cell = e >> 1, h = e & 1;
-      const int ly = cell / kCnnPX, lx = cell - ly * kCnnPX;
-      const uint4 v = *(const uint4 *)(ain + cnn_src(G, Tl, kk, ly, lx) * kCnnCh + 8 * h);
-      lds[slot][cell * 4 + cnn_swz(cell, 2 * h)] = make_uint2(v.x, v.y);
-      lds[slot][cell * 4 + cnn_swz(cell, 2 * h + 1)] = make_uint2(v.z, v.w);
-    }
-  };
-  load_plane(Tl.k0 - 1, (Tl.k0 + 2) % 3);
-  load_plane(Tl.k0, Tl.k0 % 3);
-  const int lx0 = threadIdx.x & 63, ly0 = threadIdx.x >> 6;
-  const int oy = Tl.oy0 + ly0, ox = Tl.ox0 + lx0;
-  for (int k = Tl.k0; k < Tl.k1; ++k) {
-    __syncthreads();
-    load_plane(k + 1, (k + 1) % 3);
-    __syncthreads();
-    float acc = b3;
-#pragma unroll 3
-    for (int t = 0; t < kCnnTaps; ++t) {
-      const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-      const uint2 *plane = lds[(k + dz + 3) % 3];
-      const int cell = (ly0 + 1 + dy) * kCnnPX + lx0 + 1 + dx;
+  // A operands: W3[t = 16 m + row][c = 4 quad + r] (one output channel)
+  const uint16_t *w3 = wbf + cnn_weight_offset(G.inputs, 3);
+  bf16x4 wa[2];
 #pragma unroll
-      for (int qd = 0; qd < 4; ++qd) {
-        const uint2 v = plane[cell * 4 + cnn_swz(cell, qd)];
-        const float *wr = w + t * kCnnCh + 4 * qd;
-        acc += wr[0] * __uint_as_float(v.x << 16);
-        acc += wr[1] * __uint_as_float(v.x & 0xFFFF0000u);
-        acc += wr[2] * __uint_as_float(v.y << 16);
-        acc += wr[3] * __uint_as_float(v.y & 0xFFFF0000u);
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int t = 16 * m + row;
+      wa[m][r] = t < kCnnTaps ? (short)w3[t * kCnnCh + 4 * quad + r] : (short)0;
+    }
+  const float b3 = params[cnn_bias_offset(G.inputs, 3)];
+  const int lx0 = threadIdx.x & 63, ly0 = threadIdx.x >> 6;  // this thread's output cell
+  const int oy = Tl.oy0 + ly0, ox = Tl.ox0 + lx0;
+  // plane kk (mirror-clamped) fetched into registers one plane ahead, so
+  // the fetch overlaps the previous plane's products and gather
+  constexpr int kLoads = (kCnnPlane * 2 + 255) / 256;
+  uint4 pre[kLoads];
+  auto fetch = [&](int kk) {
+#pragma unroll
+    for (int u = 0; u < kLoads; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      if (e < kCnnPlane * 2) {
+        const int cell = e >> 1, h = e & 1;
+        const int ly = cell / kCnnPX, lx = cell - ly * kCnnPX;
+        pre[u] = *(const uint4 *)(ain + cnn_src(G, Tl, kk, ly, lx) * kCnnCh + 8 * h);
       }
     }
-    if (oy < G.nyo && ox < G.nxo) {
-      const int64_t q = (((int64_t)Tl.b * G.nz + k) * G.nyo + oy) * G.nxo + ox;
-      if (GUESS)
-        guess[q] = (T)((double)base[q] + *s_over_d * (double)acc);
-      else
-        y[q] = acc;
+  };
+  float am = 0.f, a0 = 0.f, ap = 0.f;  // output levels p - 1, p, p + 1
+  fetch(Tl.k0 - 1);
+  for (int p = Tl.k0 - 1; p <= Tl.k1; ++p) {
+    __syncthreads();  // the previous plane and its products are no longer read
+#pragma unroll
+    for (int u = 0; u < kLoads; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      if (e < kCnnPlane * 2) {
+        const int cell = e >> 1, h = e & 1;
+        lds[cell * 4 + cnn_swz(cell, 2 * h)] = make_uint2(pre[u].x, pre[u].y);
+        lds[cell * 4 + cnn_swz(cell, 2 * h + 1)] = make_uint2(pre[u].z, pre[u].w);
+      }
     }
+    if (p < Tl.k1) fetch(p + 1);
+    __syncthreads();
+    for (int gi = wv; gi < (kCnnPlane + 15) / 16; gi += 4) {
+      const int cell = gi * 16 + row;
+      const int cl = cell < kCnnPlane ? cell : kCnnPlane - 1;
+      const uint2 v = lds[cl * 4 + cnn_swz(cl, quad)];
+      bf16x4 xb;
+      xb[0] = (short)(v.x & 0xFFFFu);
+      xb[1] = (short)(v.x >> 16);
+      xb[2] = (short)(v.y & 0xFFFFu);
+      xb[3] = (short)(v.y >> 16);
+      const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+      const floatx4 d0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[0], xb, zero, 0, 0, 0);
+      const floatx4 d1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[1], xb, zero, 0, 0, 0);
+      if (cell < kCnnPlane) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          dl[4 * quad + r][cell] = d0[r];
+          if (16 + 4 * quad + r < kCnnTaps) dl[16 + 4 * quad + r][cell] = d1[r];
+        }
+      }
+    }
+    __syncthreads();
+    // output level p - dz reads plane p at tap row dz
+    auto gather = [&](int dz) {
+      float sum = 0.f;
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx)
+          sum += dl[9 * (dz + 1) + 3 * (dy + 1) + (dx + 1)][(ly0 + 1 + dy) * kCnnPX + lx0 + 1 + dx];
+      return sum;
+    };
+    if (p - 1 >= Tl.k0 && p - 1 < Tl.k1) am += gather(1);
+    if (p >= Tl.k0 && p < Tl.k1) a0 += gather(0);
+    if (p + 1 >= Tl.k0 && p + 1 < Tl.k1) ap += gather(-1);
+    const int oc = p - 1;  // complete now
+    if (oc >= Tl.k0 && oc < Tl.k1 && oy < G.nyo && ox < G.nxo) {
+      const float out = am + b3;
+      const int64_t q = (((int64_t)Tl.b * G.nz + oc) * G.nyo + oy) * G.nxo + ox;
+      if (GUESS)
+        guess[q] = (T)((double)base[q] + *s_over_d * (double)out);
+      else
+        y[q] = out;
+    }
+    am = a0;
+    a0 = ap;
+    ap = 0.f;
   }
 }
 
@@ -588,26 +687,29 @@ __global__ __launch_bounds__(kBlock) void residual_kernel(Grid g, double ix2, do
                                                           float *__restrict__ r,
                                                           double *__restrict__ partials) {
   double acc = 0.0;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < g.n;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    double v = (double)rhs[q];
-    if (base) {
-      const int k = (int)(q / g.nxy);
-      const int64_t rr = q - g.nxy * k;
-      const int j = (int)(rr / g.nx);
-      const int i = (int)(rr - (int64_t)g.nx * j);
-      const double c = base[q];
-      const double lap =
-          ((double)gload(base, g, i + 1, j, k, T(1)) + (double)gload(base, g, i - 1, j, k, T(1)) -
-           2.0 * c) * ix2 +
-          ((double)gload(base, g, i, j + 1, k, T(1)) + (double)gload(base, g, i, j - 1, k, T(1)) -
-           2.0 * c) * iy2 +
-          ((double)gload(base, g, i, j, k + 1, T(1)) + (double)gload(base, g, i, j, k - 1, T(1)) -
-           2.0 * c) * iz2;
-      v -= lap;
+  // block b takes the x rows b, b + gridDim.x, ... (level and y index uniform)
+  const int64_t rows = (int64_t)g.ny * g.nz;
+  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const int k = (int)(row / g.ny), j = (int)(row - (int64_t)k * g.ny);
+    const T *c0 = base ? base + row * g.nx : nullptr;
+    const T *yp = base ? base + ((int64_t)k * g.ny + pwrap(j + 1, g.ny)) * g.nx : nullptr;
+    const T *ym = base ? base + ((int64_t)k * g.ny + pwrap(j - 1, g.ny)) * g.nx : nullptr;
+    const T *zp = base ? base + ((int64_t)zmirror(k + 1, g.nz) * g.ny + j) * g.nx : nullptr;
+    const T *zm = base ? base + ((int64_t)zmirror(k - 1, g.nz) * g.ny + j) * g.nx : nullptr;
+    for (int i = threadIdx.x; i < g.nx; i += blockDim.x) {
+      const int64_t q = row * g.nx + i;
+      double v = (double)rhs[q];
+      if (base) {
+        const int ip = i + 1 < g.nx ? i + 1 : 0, im = i > 0 ? i - 1 : g.nx - 1;
+        const double c = c0[i];
+        const double lap = ((double)c0[ip] + (double)c0[im] - 2.0 * c) * ix2 +
+                           ((double)yp[i] + (double)ym[i] - 2.0 * c) * iy2 +
+                           ((double)zp[i] + (double)zm[i] - 2.0 * c) * iz2;
+        v -= lap;
+      }
+      r[q] = (float)v;
+      acc += v * v;
     }
-    r[q] = (float)v;
-    acc += v * v;
   }
   const double s = block_sum(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;

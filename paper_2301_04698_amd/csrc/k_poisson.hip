@@ -97,38 +97,63 @@ __global__ __launch_bounds__(kBlock) void level_sum_kernel(Grid g, const T *__re
 // solves that part, (pb_{k+1} - 2 pb_k + pb_{k-1}) / dz^2 = rb_k with
 // rb_k = level mean - m and mirror ghosts: the face gradient is zero at the
 // bottom wall and grows by dz rb_k across level k; pb has zero mean.  One
-// block; the running sums are sequential in a fixed order.
+// block; the level sums are one wave per level, the running sums
+// sequential in a fixed order over LDS chunks of kScan levels.
+constexpr int kScan = 2048;
 __global__ __launch_bounds__(256) void mean_mode_kernel(const double *__restrict__ part, int lp,
                                                         int nz, double nxy, double dz, int exact,
                                                         SolveCtl *ctl, double *__restrict__ rsub,
                                                         double *__restrict__ pb) {
-  for (int k = threadIdx.x; k < nz; k += blockDim.x) {
+  __shared__ double buf[kScan];
+  __shared__ double bcast;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int k = wv; k < nz; k += 4) {
     double s = 0.0;
-    for (int q = 0; q < lp; ++q) s += part[(int64_t)k * lp + q];
-    rsub[k] = s / nxy;
+    for (int q = lane; q < lp; q += 64) s += part[(int64_t)k * lp + q];
+    s = wave_sum(s);
+    if (lane == 0) rsub[k] = s / nxy;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  double tot = 0.0;
-  for (int k = 0; k < nz; ++k) tot += rsub[k];
-  const double m = tot / nz;
-  ctl->rhs_mean = m;
-  if (exact) {
-    double G = 0.0, acc = 0.0;
-    pb[0] = 0.0;
-    for (int k = 0; k + 1 < nz; ++k) {
-      G += dz * (rsub[k] - m);
-      pb[k + 1] = pb[k] + dz * G;
-    }
-    for (int k = 0; k < nz; ++k) acc += pb[k];
-    const double mp = acc / nz;
-    for (int k = 0; k < nz; ++k) pb[k] -= mp;
-  } else {
-    for (int k = 0; k < nz; ++k) {
+  double t = 0.0;
+  for (int k = threadIdx.x; k < nz; k += blockDim.x) t += rsub[k];
+  t = block_sum(t);
+  if (threadIdx.x == 0) {
+    bcast = t / nz;
+    ctl->rhs_mean = bcast;
+  }
+  __syncthreads();
+  const double m = bcast;
+  if (!exact) {
+    for (int k = threadIdx.x; k < nz; k += blockDim.x) {
       rsub[k] = m;
       pb[k] = 0.0;
     }
+    return;
   }
+  double G = 0.0, p = 0.0, acc = 0.0;  // G, p: thread 0's running sums
+  for (int c0 = 0; c0 < nz; c0 += kScan) {
+    const int c1 = c0 + kScan < nz ? c0 + kScan : nz;
+    for (int k = c0 + threadIdx.x; k < c1; k += blockDim.x) buf[k - c0] = rsub[k] - m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int k = c0; k < c1; ++k) {  // buf: rb_k in, pb_k out
+        const double r = buf[k - c0];
+        buf[k - c0] = p;
+        G += dz * r;
+        p += dz * G;
+      }
+    __syncthreads();
+    for (int k = c0 + threadIdx.x; k < c1; k += blockDim.x) {
+      pb[k] = buf[k - c0];
+      acc += buf[k - c0];
+    }
+    __syncthreads();
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) bcast = acc / nz;
+  __syncthreads();
+  const double mp = bcast;
+  for (int k = threadIdx.x; k < nz; k += blockDim.x) pb[k] -= mp;
 }
 
 // rhs_out = rhs_in - rsub[k], rounded once (in and out may alias); FP64
@@ -160,18 +185,19 @@ __global__ __launch_bounds__(kBlock) void center_kernel(Grid g, int lp, const T 
 __global__ __launch_bounds__(256) void level_mean_kernel(const double *__restrict__ part, int lp,
                                                          int nz, double nxy, int exact,
                                                          double *__restrict__ gbar) {
-  for (int k = threadIdx.x; k < nz; k += blockDim.x) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int k = wv; k < nz; k += 4) {
     double s = 0.0;
     if (exact)
-      for (int q = 0; q < lp; ++q) s += part[(int64_t)k * lp + q];
-    gbar[k] = s / nxy;
+      for (int q = lane; q < lp; q += 64) s += part[(int64_t)k * lp + q];
+    s = wave_sum(s);
+    if (lane == 0) gbar[k] = s / nxy;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int k = 0; k < nz; ++k) t += gbar[k];
-    gbar[nz] = t / nz;
-  }
+  double t = 0.0;
+  for (int k = threadIdx.x; k < nz; k += blockDim.x) t += gbar[k];
+  t = block_sum(t);
+  if (threadIdx.x == 0) gbar[nz] = t / nz;
 }
 
 // Profiles of the horizontally uniform part pb of a solution (FP64 in,
@@ -208,16 +234,22 @@ __global__ __launch_bounds__(256) void mean_profiles_kernel(int nz, double dz,
 // ------------------------------------------------ vertically uniform part
 
 // Vertical mean of every column: out[i + nx j] = mean over k of f (FP64,
-// fixed order).  One thread per column; consecutive threads read
-// consecutive cells of a level.
+// fixed order).  A block takes 64 consecutive columns; its four waves sum
+// a quarter of the levels each (consecutive lanes read consecutive cells
+// of a level), then the quarters are added in order.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void column_mean_kernel(Grid g, const T *__restrict__ f,
-                                                             double *__restrict__ out) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= g.nxy) return;
+__global__ __launch_bounds__(256) void column_mean_kernel(Grid g, const T *__restrict__ f,
+                                                          double *__restrict__ out) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
+  const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+  const int k0 = (int)((int64_t)part * g.nz / 4), k1 = (int)((int64_t)(part + 1) * g.nz / 4);
   double s = 0.0;
-  for (int k = 0; k < g.nz; ++k) s += (double)f[q + g.nxy * k];
-  out[q] = s / g.nz;
+  if (q < g.nxy)
+    for (int k = k0; k < k1; ++k) s += (double)f[q + g.nxy * k];
+  red[part][lane] = s;
+  __syncthreads();
+  if (part == 0 && q < g.nxy) out[q] = (((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]) / g.nz;
 }
 
 // One direction of the separable real Fourier (Hartley) transform of an
@@ -226,35 +258,46 @@ __global__ __launch_bounds__(kBlock) void column_mean_kernel(Grid g, const T *__
 // out[j][kx] = sum_i a[j][i] cas(2 pi i kx / nx).  cas values come from
 // the table tab[m] = cas(2 pi m / n), m = 0 .. n-1, indexed by (k j) mod n,
 // advanced incrementally.  out may subtract a constant first (sub, the
-// mean of a; nullable).
+// mean of a; nullable).  A block takes 64 consecutive outputs; its four
+// waves sum a quarter of the terms each, added in order at the end.
 template <int AXIS>
-__global__ __launch_bounds__(kBlock) void hartley_kernel(int nx, int ny,
-                                                         const double *__restrict__ a,
-                                                         const double *__restrict__ tab,
-                                                         const double *__restrict__ sub,
-                                                         double *__restrict__ out) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= (int64_t)nx * ny) return;
-  const int row = (int)(q / nx), col = (int)(q - (int64_t)row * nx);
+__global__ __launch_bounds__(256) void hartley_kernel(int nx, int ny,
+                                                      const double *__restrict__ a,
+                                                      const double *__restrict__ tab,
+                                                      const double *__restrict__ sub,
+                                                      double *__restrict__ out) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
+  const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+  const bool ok = q < (int64_t)nx * ny;
+  const int row = ok ? (int)(q / nx) : 0, col = ok ? (int)(q - (int64_t)row * nx) : 0;
   const double c0 = sub ? *sub : 0.0;
+  const int n = AXIS == 1 ? ny : nx;
+  const int t0 = (int)((int64_t)part * n / 4), t1 = (int)((int64_t)(part + 1) * n / 4);
   double s = 0.0;
-  if (AXIS == 1) {  // row = ky, col = i
-    int m = 0;
-    for (int j = 0; j < ny; ++j) {
-      s += tab[m] * (a[(int64_t)j * nx + col] - c0);
-      m += row;
-      if (m >= ny) m -= ny;
-    }
-  } else {  // row = j, col = kx
-    int m = 0;
-    const double *ar = a + (int64_t)row * nx;
-    for (int i = 0; i < nx; ++i) {
-      s += (ar[i] - c0) * tab[m];
-      m += col;
-      if (m >= nx) m -= nx;
+  if (ok) {
+    if (AXIS == 1) {  // row = ky, col = i
+      int m = (int)((int64_t)row * t0 % ny);
+#pragma unroll 4
+      for (int j = t0; j < t1; ++j) {
+        s += tab[m] * (a[(int64_t)j * nx + col] - c0);
+        m += row;
+        if (m >= ny) m -= ny;
+      }
+    } else {  // row = j, col = kx
+      int m = (int)((int64_t)col * t0 % nx);
+      const double *ar = a + (int64_t)row * nx;
+#pragma unroll 4
+      for (int i = t0; i < t1; ++i) {
+        s += (ar[i] - c0) * tab[m];
+        m += col;
+        if (m >= nx) m -= nx;
+      }
     }
   }
-  out[q] = s;
+  red[part][lane] = s;
+  __syncthreads();
+  if (part == 0 && ok) out[q] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
 // Divide the transform of the vertical-mean right-hand side by the
@@ -460,34 +503,36 @@ __global__ __launch_bounds__(kBlock) void guess_residual_kernel(Grid g, double i
                                                                 const SolveCtl *__restrict__ when) {
   if (when && !when->guess_kept) return;
   double rr = 0.0, bb = 0.0;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < g.n;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    const int k = (int)(q / g.nxy);
-    const int64_t r2 = q - g.nxy * k;
-    const int j = (int)(r2 / g.nx);
-    const int i = (int)(r2 - (int64_t)g.nx * j);
-    const double c = phi0[q];
-    double lap =
-        ((double)gload(phi0, g, i + 1, j, k, T(1)) + (double)gload(phi0, g, i - 1, j, k, T(1)) -
-         2.0 * c) * ix2 +
-        ((double)gload(phi0, g, i, j + 1, k, T(1)) + (double)gload(phi0, g, i, j - 1, k, T(1)) -
-         2.0 * c) * iy2 +
-        ((double)gload(phi0, g, i, j, k + 1, T(1)) + (double)gload(phi0, g, i, j, k - 1, T(1)) -
-         2.0 * c) * iz2;
-    if (gbar)
-      lap -= (pload(gbar, k + 1, g.nz) - 2.0 * gbar[k] + pload(gbar, k - 1, g.nz)) * iz2;
-    if (gv) {  // the x-y second differences of the guess's column means
-      const double gc = gv[(int64_t)i + g.sy * j];
-      const int ip = pwrap(i + 1, g.nx), im = pwrap(i - 1, g.nx);
-      const int jp = pwrap(j + 1, g.ny), jm = pwrap(j - 1, g.ny);
-      lap -= (gv[ip + g.sy * j] + gv[im + g.sy * j] - 2.0 * gc) * ix2 +
-             (gv[i + g.sy * jp] + gv[i + g.sy * jm] - 2.0 * gc) * iy2;
+  // block b takes the x rows b, b + gridDim.x, ...: the row's level and y
+  // index (and its neighbour rows) are uniform over the block
+  const int64_t rows = (int64_t)g.ny * g.nz;
+  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const int k = (int)(row / g.ny), j = (int)(row - (int64_t)k * g.ny);
+    const int jp = pwrap(j + 1, g.ny), jm = pwrap(j - 1, g.ny);
+    const int kp = zmirror(k + 1, g.nz), km = zmirror(k - 1, g.nz);
+    const T *c0 = phi0 + row * g.nx;
+    const T *yp = phi0 + ((int64_t)k * g.ny + jp) * g.nx, *ym = phi0 + ((int64_t)k * g.ny + jm) * g.nx;
+    const T *zp = phi0 + ((int64_t)kp * g.ny + j) * g.nx, *zm = phi0 + ((int64_t)km * g.ny + j) * g.nx;
+    const double gz = gbar ? (gbar[kp] - 2.0 * gbar[k] + gbar[km]) * iz2 : 0.0;
+    for (int i = threadIdx.x; i < g.nx; i += blockDim.x) {
+      const int ip = i + 1 < g.nx ? i + 1 : 0, im = i > 0 ? i - 1 : g.nx - 1;
+      const double c = c0[i];
+      double lap = ((double)c0[ip] + (double)c0[im] - 2.0 * c) * ix2 +
+                   ((double)yp[i] + (double)ym[i] - 2.0 * c) * iy2 +
+                   ((double)zp[i] + (double)zm[i] - 2.0 * c) * iz2;
+      lap -= gz;
+      if (gv) {  // the x-y second differences of the guess's column means
+        const double gc = gv[(int64_t)i + g.sy * j];
+        lap -= (gv[ip + g.sy * j] + gv[im + g.sy * j] - 2.0 * gc) * ix2 +
+               (gv[i + g.sy * jp] + gv[i + g.sy * jm] - 2.0 * gc) * iy2;
+      }
+      const int64_t q = row * g.nx + i;
+      const double b = rhs[q];
+      const double d = b - lap;
+      if (rhs_d) rhs_d[q] = (T)d;
+      rr += d * d;
+      bb += b * b;
     }
-    const double b = rhs[q];
-    const double d = b - lap;
-    if (rhs_d) rhs_d[q] = (T)d;
-    rr += d * d;
-    bb += b * b;
   }
   const double sr = block_sum(rr);
   const double sb = block_sum(bb);
@@ -627,7 +672,7 @@ void launch_rhs_center(const Grid &g, const T *rhs_in, T *rhs_out, T *phi0, cons
 
 template <typename T>
 void launch_column_mean(const Grid &g, const T *f, double *out, hipStream_t s) {
-  column_mean_kernel<T><<<blocks_for(g.nxy), kBlock, 0, s>>>(g, f, out);
+  column_mean_kernel<T><<<(unsigned)((g.nxy + 63) / 64), 256, 0, s>>>(g, f, out);
 }
 
 void launch_vertical_solve(const Grid &g, const double *cmean, const SolveCtl *ctl,
@@ -635,13 +680,14 @@ void launch_vertical_solve(const Grid &g, const double *cmean, const SolveCtl *c
                            hipStream_t s) {
   const int nx = g.nx, ny = g.ny;
   const unsigned nb = blocks_for((int64_t)nx * ny);
+  const unsigned nb64 = (unsigned)(((int64_t)nx * ny + 63) / 64);
   // rv = cmean - mean; a = Hy rv; b = a Hx / lambda; a = Hy b; pv = a Hx
-  hartley_kernel<1><<<nb, kBlock, 0, s>>>(nx, ny, cmean, tab_y, &ctl->rhs_mean, work);
-  hartley_kernel<0><<<nb, kBlock, 0, s>>>(nx, ny, work, tab_x, nullptr, pv);
+  hartley_kernel<1><<<nb64, 256, 0, s>>>(nx, ny, cmean, tab_y, &ctl->rhs_mean, work);
+  hartley_kernel<0><<<nb64, 256, 0, s>>>(nx, ny, work, tab_x, nullptr, pv);
   hartley_divide_kernel<<<nb, kBlock, 0, s>>>(nx, ny, 1.0 / (g.dx * g.dx), 1.0 / (g.dy * g.dy),
                                               pv);
-  hartley_kernel<1><<<nb, kBlock, 0, s>>>(nx, ny, pv, tab_y, nullptr, work);
-  hartley_kernel<0><<<nb, kBlock, 0, s>>>(nx, ny, work, tab_x, nullptr, pv);
+  hartley_kernel<1><<<nb64, 256, 0, s>>>(nx, ny, pv, tab_y, nullptr, work);
+  hartley_kernel<0><<<nb64, 256, 0, s>>>(nx, ny, work, tab_x, nullptr, pv);
 }
 
 template <typename T>
@@ -692,21 +738,27 @@ void launch_extrapolate(const Grid &g, const Profiles<T> &P, const T *p, const T
   extrapolate_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g, P, p, p_prev, phi0);
 }
 
+// Blocks of the guess/returned-residual kernel: one x row each at a time,
+// enough of them to keep every CU's memory pipes busy; 2 x 4096 partials fit
+// the partial buffer.
+constexpr int kResidualBlocks = 4096;
+static_assert(2 * kResidualBlocks <= kPartials, "residual partials exceed the buffer");
+
 template <typename T>
 void launch_guess_gate(const Grid &g, const T *rhs, const T *phi0, const double *gbar,
                        const double *gv, T *rhs_d, double *partials, SolveCtl *ctl,
                        int always_keep, hipStream_t s) {
   const double ix2 = 1.0 / (g.dx * g.dx), iy2 = 1.0 / (g.dy * g.dy), iz2 = 1.0 / (g.dz * g.dz);
   if (rhs != rhs_d) {
-    guess_residual_kernel<T><<<kReduceBlocks, kBlock, 0, s>>>(g, ix2, iy2, iz2, rhs, phi0, gbar,
+    guess_residual_kernel<T><<<kResidualBlocks, kBlock, 0, s>>>(g, ix2, iy2, iz2, rhs, phi0, gbar,
                                                               gv, rhs_d, partials, nullptr);
-    guess_gate_kernel<<<1, 1024, 0, s>>>(partials, kReduceBlocks, always_keep, ctl);
+    guess_gate_kernel<<<1, 1024, 0, s>>>(partials, kResidualBlocks, always_keep, ctl);
     guess_clear_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g.n, ctl, rhs, rhs_d);
   } else {  // in place: the sums, the gate, then the defect if the guess is kept
-    guess_residual_kernel<T><<<kReduceBlocks, kBlock, 0, s>>>(g, ix2, iy2, iz2, rhs, phi0, gbar,
+    guess_residual_kernel<T><<<kResidualBlocks, kBlock, 0, s>>>(g, ix2, iy2, iz2, rhs, phi0, gbar,
                                                               gv, nullptr, partials, nullptr);
-    guess_gate_kernel<<<1, 1024, 0, s>>>(partials, kReduceBlocks, always_keep, ctl);
-    guess_residual_kernel<T><<<kReduceBlocks, kBlock, 0, s>>>(g, ix2, iy2, iz2, rhs, phi0, gbar,
+    guess_gate_kernel<<<1, 1024, 0, s>>>(partials, kResidualBlocks, always_keep, ctl);
+    guess_residual_kernel<T><<<kResidualBlocks, kBlock, 0, s>>>(g, ix2, iy2, iz2, rhs, phi0, gbar,
                                                               gv, rhs_d, partials, ctl);
   }
 }
@@ -714,10 +766,10 @@ void launch_guess_gate(const Grid &g, const T *rhs, const T *phi0, const double 
 template <typename T>
 void launch_returned_residual(const Grid &g, const T *rhs, const T *phi, double *partials,
                               SolveCtl *ctl, hipStream_t s) {
-  guess_residual_kernel<T><<<kReduceBlocks, kBlock, 0, s>>>(
+  guess_residual_kernel<T><<<kResidualBlocks, kBlock, 0, s>>>(
       g, 1.0 / (g.dx * g.dx), 1.0 / (g.dy * g.dy), 1.0 / (g.dz * g.dz), rhs, phi, nullptr,
       nullptr, nullptr, partials, nullptr);
-  final_kernel<<<1, 1024, 0, s>>>(partials, kReduceBlocks, kFinalReturned, ctl, 0.0, 0.0, 0,
+  final_kernel<<<1, 1024, 0, s>>>(partials, kResidualBlocks, kFinalReturned, ctl, 0.0, 0.0, 0,
                                   nullptr);
 }
 

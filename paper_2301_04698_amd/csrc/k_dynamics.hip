@@ -149,9 +149,13 @@ __device__ __forceinline__ FaceFlux<T> face_mass(const L &at, const Profiles<T> 
 }
 
 // Flux-form advective tendency -div(U s) of a field s with parity par.
-template <typename T, bool WENO, class L>
+// The flux through the bottom face is the one the level below computed for
+// its top face when `have` (the same operands in the same order, so the
+// same value): zin (HAVE); the top face's flux goes to zout for the level
+// above.
+template <typename T, bool WENO, bool HAVE, class L>
 __device__ __forceinline__ T advect(const L &at, const Dyn<T> &d, const FaceFlux<T> &f,
-                                    const T *__restrict__ s, T par) {
+                                    const T *__restrict__ s, T par, T zin, T &zout) {
   T sx[5], sy[5], sz[5];
 #pragma unroll
   for (int o = -2; o <= 2; ++o) {
@@ -164,7 +168,12 @@ __device__ __forceinline__ T advect(const L &at, const Dyn<T> &d, const FaceFlux
   const T fyp = face_flux<T, WENO>(f.yp, sy[1], sy[2], sy[3], sy[4]);
   const T fym = face_flux<T, WENO>(f.ym, sy[0], sy[1], sy[2], sy[3]);
   const T fzp = face_flux<T, WENO>(f.zp, sz[1], sz[2], sz[3], sz[4]);
-  const T fzm = face_flux<T, WENO>(f.zm, sz[0], sz[1], sz[2], sz[3]);
+  T fzm;
+  if constexpr (HAVE)
+    fzm = zin;
+  else
+    fzm = face_flux<T, WENO>(f.zm, sz[0], sz[1], sz[2], sz[3]);
+  zout = fzp;
   return -((fxp - fxm) * d.inv_dx + (fyp - fym) * d.inv_dy + (fzp - fzm) * d.inv_dz);
 }
 
@@ -190,10 +199,11 @@ __device__ __forceinline__ FaceVisc<T> face_visc(const L &at, const Profiles<T> 
   return f;
 }
 
-// div(rho0 nu / Pr grad s), compact face differences.
-template <typename T, class L>
+// div(rho0 nu / Pr grad s), compact face differences; the bottom face's
+// flux carried from the level below as in advect.
+template <typename T, bool HAVE, class L>
 __device__ __forceinline__ T diffuse(const L &at, const Dyn<T> &d, const FaceVisc<T> &f, T inv_pr,
-                                     const T *__restrict__ s) {
+                                     const T *__restrict__ s, T zin, T &zout) {
   const T s0 = at(s, 0, 0, 0, T(1));
   const T gx = (f.xp * inv_pr * ((at(s, 1, 0, 0, T(1)) - s0) * d.inv_dx) -
                 f.xm * inv_pr * ((s0 - at(s, -1, 0, 0, T(1))) * d.inv_dx)) *
@@ -201,21 +211,32 @@ __device__ __forceinline__ T diffuse(const L &at, const Dyn<T> &d, const FaceVis
   const T gy = (f.yp * inv_pr * ((at(s, 0, 1, 0, T(1)) - s0) * d.inv_dy) -
                 f.ym * inv_pr * ((s0 - at(s, 0, -1, 0, T(1))) * d.inv_dy)) *
                d.inv_dy;
-  const T gz = (f.zp * inv_pr * ((at(s, 0, 0, 1, T(1)) - s0) * d.inv_dz) -
-                f.zm * inv_pr * ((s0 - at(s, 0, 0, -1, T(1))) * d.inv_dz)) *
-               d.inv_dz;
+  const T fzp = f.zp * inv_pr * ((at(s, 0, 0, 1, T(1)) - s0) * d.inv_dz);
+  T fzm;
+  if constexpr (HAVE)
+    fzm = zin;
+  else
+    fzm = f.zm * inv_pr * ((s0 - at(s, 0, 0, -1, T(1))) * d.inv_dz);
+  zout = fzp;
+  const T gz = (fzp - fzm) * d.inv_dz;
   return gx + gy + gz;
 }
 
+// Bottom-face fluxes a level hands to the level above in a z march.
+template <typename T, int N>
+struct ZCarry {
+  T f[N];
+};
+
 // Phi^{k+1} = Phi^{n+1/2} + dt/rho0 [ -div(U^k Phi_mid) + div(rho0 nu/Pr grad Phi_mid)
 //            + rho0 w_sub dPhi_mid/dz + radiative heating (theta_l) + surface flux ]
-template <typename T, bool WENO, bool EDGE>
+template <typename T, bool WENO, bool EDGE, bool HAVE>
 __device__ __forceinline__ void scalar_level(
     const Grid &g, const Dyn<T> &d, const Profiles<T> &P, const ColPts<T> &pts, int k,
     bool active, const T *__restrict__ u, const T *__restrict__ v, const T *__restrict__ w,
     const T *__restrict__ thm, const T *__restrict__ qtm, const T *__restrict__ thh,
     const T *__restrict__ qth, const T *__restrict__ nu, const T *__restrict__ rad,
-    T *__restrict__ tho, T *__restrict__ qto) {
+    T *__restrict__ tho, T *__restrict__ qto, ZCarry<T, 4> &zc) {
   const Lvl<T, EDGE> at(g, pts, k);
   const FaceFlux<T> mf = face_mass(at, P, u, v, w);
   const FaceVisc<T> fv = face_visc(at, P, nu);
@@ -223,15 +244,18 @@ __device__ __forceinline__ void scalar_level(
   const T sub = r0 * at.prof(P.wsub_t, 0);
   const T scale = d.dt / r0;
   T th_new, qt_new;
+  ZCarry<T, 4> out;
   {
-    T tend = advect<T, WENO>(at, d, mf, thm, T(1)) + diffuse(at, d, fv, d.inv_pr, thm);
+    T tend = advect<T, WENO, HAVE>(at, d, mf, thm, T(1), zc.f[0], out.f[0]) +
+             diffuse<T, HAVE>(at, d, fv, d.inv_pr, thm, zc.f[1], out.f[1]);
     tend += at(rad, 0, 0, 0, T(1));
     tend += sub * ((at(thm, 0, 0, 1, T(1)) - at(thm, 0, 0, -1, T(1))) * d.inv_2dz);
     if (k == 0) tend += d.sfc_thl * d.inv_dz;
     th_new = at(thh, 0, 0, 0, T(1)) + scale * tend;
   }
   {
-    T tend = advect<T, WENO>(at, d, mf, qtm, T(1)) + diffuse(at, d, fv, d.inv_sc, qtm);
+    T tend = advect<T, WENO, HAVE>(at, d, mf, qtm, T(1), zc.f[2], out.f[2]) +
+             diffuse<T, HAVE>(at, d, fv, d.inv_sc, qtm, zc.f[3], out.f[3]);
     tend += sub * ((at(qtm, 0, 0, 1, T(1)) - at(qtm, 0, 0, -1, T(1))) * d.inv_2dz);
     if (k == 0) tend += d.sfc_qt * d.inv_dz;
     qt_new = at(qth, 0, 0, 0, T(1)) + scale * tend;
@@ -239,6 +263,7 @@ __device__ __forceinline__ void scalar_level(
   // Stores after all loads (the two scalars share the face fluxes' loads).
   at.store(tho, th_new, active);
   at.store(qto, qt_new, active);
+  zc = out;
 }
 
 template <typename T, bool WENO>
@@ -250,13 +275,18 @@ __global__ __launch_bounds__(kBlock) void scalar_kernel(
   const ColWave c = col_wave(g, m);
   if (!c.valid) return;
   const ColPts<T> pts = col_pts<T>(g, c.i, c.j);
-  for (int k = c.k0; k < c.k1; ++k) {
+  // the chunk's first level computes its bottom faces; the others take
+  // them from the level below
+  ZCarry<T, 4> zc = {};
+  scalar_level<T, WENO, true, false>(g, d, P, pts, c.k0, c.active, u, v, w, thm, qtm, thh, qth,
+                                     nu, rad, tho, qto, zc);
+  for (int k = c.k0 + 1; k < c.k1; ++k) {
     if (k >= 2 && k + 2 < g.nz)
-      scalar_level<T, WENO, false>(g, d, P, pts, k, c.active, u, v, w, thm, qtm, thh, qth, nu,
-                                   rad, tho, qto);
+      scalar_level<T, WENO, false, true>(g, d, P, pts, k, c.active, u, v, w, thm, qtm, thh, qth,
+                                         nu, rad, tho, qto, zc);
     else
-      scalar_level<T, WENO, true>(g, d, P, pts, k, c.active, u, v, w, thm, qtm, thh, qth, nu,
-                                  rad, tho, qto);
+      scalar_level<T, WENO, true, true>(g, d, P, pts, k, c.active, u, v, w, thm, qtm, thh, qth, nu,
+                                        rad, tho, qto, zc);
   }
 }
 
@@ -282,13 +312,13 @@ __device__ __forceinline__ T sgs_face(const L &at, const Dyn<T> &d, const T *con
 // U_hat = U^n + dt [ -rho0 grad_c(alpha0 p^k) + R^{n+1/2} ] with
 // R = -div(U_h (x) u_h) + div(rho0 sigma) + rho0 b e_z - f e_z x (U_h - rho0 u_g)
 //     - beta(z) (U_h - rho0 (u_g, v_g, 0)); stored as u_hat = U_hat / rho0.
-template <typename T, bool WENO, bool FS, bool EDGE>
+template <typename T, bool WENO, bool FS, bool EDGE, bool HAVE>
 __device__ __forceinline__ void momentum_level(
     const Grid &g, const Dyn<T> &d, const Profiles<T> &P, const ColPts<T> &pts, int k,
     bool active, const T *__restrict__ uh, const T *__restrict__ vh, const T *__restrict__ wh,
     const T *__restrict__ un, const T *__restrict__ vn, const T *__restrict__ wn,
     const T *__restrict__ p, const T *__restrict__ b, const T *__restrict__ nu,
-    T *__restrict__ uo, T *__restrict__ vo, T *__restrict__ wo) {
+    T *__restrict__ uo, T *__restrict__ vo, T *__restrict__ wo, ZCarry<T, 6> &zc) {
   const Lvl<T, EDGE> at(g, pts, k);
   const T *const vel[3] = {uh, vh, wh};
   const FaceFlux<T> mf = face_mass(at, P, uh, vh, wh);
@@ -311,20 +341,27 @@ __device__ __forceinline__ void momentum_level(
   const T Un[3] = {r0 * at(un, 0, 0, 0, T(1)), r0 * at(vn, 0, 0, 0, T(1)),
                    r0 * at(wn, 0, 0, 0, T(1))};
   const T geo[3] = {d.ug, d.vg, T(0)};
-  T *const out[3] = {uo, vo, wo};
+  T *const outf[3] = {uo, vo, wo};
   const T rnu_m[3] = {fv.xm, fv.ym, fv.zm};
   const T rnu_p[3] = {fv.xp, fv.yp, fv.zp};
   const T invd[3] = {d.inv_dx, d.inv_dy, d.inv_dz};
   const T bq = at(b, 0, 0, 0, T(1));
   T res[3];
+  ZCarry<T, 6> out;  // per component: advective, then SGS flux of the top face
 #pragma unroll
   for (int cmp = 0; cmp < 3; ++cmp) {
-    T R = advect<T, WENO>(at, d, mf, vel[cmp], vpar<T, FS>(cmp));
+    T R = advect<T, WENO, HAVE>(at, d, mf, vel[cmp], vpar<T, FS>(cmp), zc.f[cmp], out.f[cmp]);
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const int di = ax == 0, dj = ax == 1, dk = ax == 2;
       const T fp = sgs_face<T, FS>(at, d, vel, rnu_p[ax], ax, cmp, 0, 0, 0);
-      const T fm = sgs_face<T, FS>(at, d, vel, rnu_m[ax], ax, cmp, -di, -dj, -dk);
+      // the z face below: the level below's top face when it was computed
+      T fm;
+      if (HAVE && ax == 2)
+        fm = zc.f[3 + cmp];
+      else
+        fm = sgs_face<T, FS>(at, d, vel, rnu_m[ax], ax, cmp, -di, -dj, -dk);
+      if (ax == 2) out.f[3 + cmp] = fp;
       R += (fp - fm) * invd[ax];
     }
     if (cmp == 2) R += r0 * bq;
@@ -337,7 +374,8 @@ __device__ __forceinline__ void momentum_level(
   // Stores after all loads: the loads of the three components share their
   // common points and differences.
 #pragma unroll
-  for (int cmp = 0; cmp < 3; ++cmp) at.store(out[cmp], res[cmp], active);
+  for (int cmp = 0; cmp < 3; ++cmp) at.store(outf[cmp], res[cmp], active);
+  zc = out;
 }
 
 template <typename T, bool WENO, bool FS>
@@ -349,13 +387,18 @@ __global__ __launch_bounds__(kBlock) void momentum_kernel(
   const ColWave c = col_wave(g, m);
   if (!c.valid) return;
   const ColPts<T> pts = col_pts<T>(g, c.i, c.j);
-  for (int k = c.k0; k < c.k1; ++k) {
+  // the chunk's first level computes its bottom faces; the others take
+  // them from the level below
+  ZCarry<T, 6> zc = {};
+  momentum_level<T, WENO, FS, true, false>(g, d, P, pts, c.k0, c.active, uh, vh, wh, un, vn, wn, p,
+                                           b, nu, uo, vo, wo, zc);
+  for (int k = c.k0 + 1; k < c.k1; ++k) {
     if (k >= 2 && k + 2 < g.nz)
-      momentum_level<T, WENO, FS, false>(g, d, P, pts, k, c.active, uh, vh, wh, un, vn, wn, p, b,
-                                         nu, uo, vo, wo);
+      momentum_level<T, WENO, FS, false, true>(g, d, P, pts, k, c.active, uh, vh, wh, un, vn, wn,
+                                               p, b, nu, uo, vo, wo, zc);
     else
-      momentum_level<T, WENO, FS, true>(g, d, P, pts, k, c.active, uh, vh, wh, un, vn, wn, p, b,
-                                        nu, uo, vo, wo);
+      momentum_level<T, WENO, FS, true, true>(g, d, P, pts, k, c.active, uh, vh, wh, un, vn, wn, p,
+                                              b, nu, uo, vo, wo, zc);
   }
 }
 

@@ -94,7 +94,8 @@ enum { LES_MEAN_SWEPT = 0, LES_MEAN_LEVEL = 1, LES_MEAN_EXACT = 2 };
  *                          network's guess from the previous pressures and
  *                          the divergence (base alpha0 (p^n - p^{n-1}) as
  *                          with LES_GUESS_EXTRAPOLATE, plus the network's
- *                          correction); later solves start from 0
+ *                          correction; parameters bound with les_bind_cnn
+ *                          before the first step); later solves start from 0
  * The solve always runs to the same residual tolerance: a guess only
  * changes the number of sweeps, never the acceptance test. */
 enum { LES_GUESS_ZERO = 0, LES_GUESS_EXTRAPOLATE = 1, LES_GUESS_PREVIOUS = 2,

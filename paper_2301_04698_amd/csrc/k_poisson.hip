@@ -784,6 +784,16 @@ void launch_block_sum(const T *a, int64_t n, int mode, double *partials, hipStre
   block_sum_kernel<T><<<kReduceBlocks, kBlock, 0, s>>>(a, n, mode, partials);
 }
 
+__global__ void snap_kernel(const SolveCtl *__restrict__ ctl, int64_t *snap, int seq) {
+  if (threadIdx.x == 0) *(volatile int64_t *)snap = ((int64_t)seq << 32) | (uint32_t)ctl->done;
+}
+
+void launch_final_check(const double *partials, int np, SolveCtl *ctl, double n, int m,
+                        int64_t *snap, int snap_seq, hipStream_t s) {
+  final_kernel<<<1, 1024, 0, s>>>(partials, np, kFinalCheck, ctl, n, 0.0, m, nullptr);
+  if (snap) snap_kernel<<<1, 64, 0, s>>>(ctl, snap, snap_seq);
+}
+
 void launch_final(const double *partials, int np, int op, SolveCtl *ctl, double n, double tol2_scale,
                   int m, double *out, hipStream_t s) {
   final_kernel<<<1, 1024, 0, s>>>(partials, np, op, ctl, n, tol2_scale, m, out);

@@ -82,6 +82,11 @@ struct SweepArgs {
   // earlier launch whose dec_np block partials block 0 reduces and decides
   const double *dec_partials;
   int dec_np, dec_m;
+  // host-visible word written after that decision (device view of pinned
+  // host memory; nullable): decision number snap_seq in the high half, the
+  // control block's `done` in the low half, one 64-bit store
+  int64_t *snap;
+  int snap_seq;
 };
 
 struct TileIdx {
@@ -193,7 +198,11 @@ __device__ __forceinline__ double march_row(const SweepArgs<T> &a, const TileIdx
 // per CU) measured faster with loaded x neighbours.
 template <typename T, int WX, int TY, bool CHEB, bool CHECK, bool NT>
 __global__ __launch_bounds__(64 * WX * TY) void sweep1_kernel(SweepArgs<T> a) {
-  if (a.ctl->done) return;
+  if (a.ctl->done) {  // stopped: a deciding launch still leaves its word
+    if (a.snap && blockIdx.x == 0 && threadIdx.x == 0)
+      *(volatile int64_t *)a.snap = ((int64_t)a.snap_seq << 32) | (uint32_t)a.ctl->done;
+    return;
+  }
   const Grid &g = a.g;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   double acc = 0.0;
@@ -224,7 +233,11 @@ __global__ __launch_bounds__(64 * WX * TY) void sweep1_kernel(SweepArgs<T> a) {
 #pragma unroll 16
     for (int q = (int)threadIdx.x; q < a.dec_np; q += 64) t += a.dec_partials[q];
     t = wave_sum(t);
-    if (threadIdx.x == 0) check_decision(a.ctl, t, a.dec_m);
+    if (threadIdx.x == 0) {
+      check_decision(a.ctl, t, a.dec_m);
+      if (a.snap)
+        *(volatile int64_t *)a.snap = ((int64_t)a.snap_seq << 32) | (uint32_t)a.ctl->done;
+    }
   }
   if (CHECK) {
     const double s = block_sum(acc);
@@ -475,7 +488,8 @@ template <typename T>
 void launch_tsweep(const Grid &g, int S, bool chebyshev, bool check, bool first,
                    double omega_jacobi, const double *omega_cheb, const T *cur, const T *prev,
                    T *out_last, T *out_prev, const T *rhs, SolveCtl *ctl, double *partials,
-                   const double *dec_partials, int dec_np, int dec_m, hipStream_t s) {
+                   const double *dec_partials, int dec_np, int dec_m, int64_t *snap,
+                   int snap_seq, hipStream_t s) {
   const Shape sh = shape_of(g, S, sizeof(T) == 8);
   SweepArgs<T> a;
   a.g = g;
@@ -503,6 +517,8 @@ void launch_tsweep(const Grid &g, int S, bool chebyshev, bool check, bool first,
   a.dec_partials = dec_partials;
   a.dec_np = dec_np;
   a.dec_m = S == 1 ? dec_m : -1;
+  a.snap = a.dec_m >= 0 ? snap : nullptr;
+  a.snap_seq = snap_seq;
   const dim3 grid(sh.blocks);
 #define LES_PICK(WX, TY, NT)                                                          \
   do {                                                                                \
@@ -545,10 +561,11 @@ void launch_tsweep(const Grid &g, int S, bool chebyshev, bool check, bool first,
 
 template void launch_tsweep<float>(const Grid &, int, bool, bool, bool, double, const double *,
                                    const float *, const float *, float *, float *, const float *,
-                                   SolveCtl *, double *, const double *, int, int, hipStream_t);
+                                   SolveCtl *, double *, const double *, int, int, int64_t *, int,
+                                   hipStream_t);
 template void launch_tsweep<double>(const Grid &, int, bool, bool, bool, double, const double *,
                                     const double *, const double *, double *, double *,
                                     const double *, SolveCtl *, double *, const double *, int, int,
-                                    hipStream_t);
+                                    int64_t *, int, hipStream_t);
 
 }  // namespace lesmi

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "api_util.h"
@@ -32,6 +33,7 @@ enum Field {
 
 constexpr size_t kAlign = 256;
 constexpr int kProfT = 7;  // storage-type profiles
+constexpr int kTimeEvery = 4;  // time_sweeps: every 4th run of plain sweeps is timed
 constexpr int kPartialCap = kPartials + 1024;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -189,9 +191,11 @@ struct les_handle {
   double mu_min, mu_max;
   int sweeps_per_launch;  // temporal blocking depth of the Poisson sweeps
   SolveCtl *ctl_host;  // pinned mirror for the final read-back
+  int64_t *poll_word;      // pinned, coherent: (decision number << 32) | done, written
+                           // by the kernel deciding each residual test
+  int64_t *poll_word_dev;  // device view of poll_word
   double *diag_host;   // pinned, nz x kDiagStride
   hipEvent_t ev_a, ev_b, ev_s0, ev_s1;
-  std::vector<hipEvent_t> ev_check;
   std::vector<hipEvent_t> ev_sweep;  // pool bracketing runs of plain sweeps
   bool broken;
   std::vector<char> hist_valid;  // per sub-iteration: history holds a solution
@@ -485,36 +489,51 @@ int run_sweeps(les_handle *h, View<T> &V, const T *rhs, int fixed, int cap, Solv
   int recent_m[kRecent], recent_buf[kRecent], nrecent = 0;
 
   // Queue launches; the device stops applying them once a check succeeds.
-  // The host polls a pinned copy of the control block after a bounded lag.
+  // The kernel deciding test number c writes (c << 32) | done into a pinned,
+  // coherent host word; before queueing past test c the host waits for the
+  // word of test c - lag (so it stays a bounded number of tests ahead) and
+  // stops once a decided test says done.  No event or copy per test: each
+  // of those cost the stream several microseconds.
   const int lag = 2;
-  size_t npending = 0, next_wait = 0;
+  size_t npending = 0;
   struct Run {
     int first, last;
   };
   constexpr size_t kMaxRuns = 4096;  // timed runs per solve (a sample)
   std::vector<Run> runs;
   const bool timed = timing && timing->enabled;
-  int run_first = -1;
+  int run_first = -1, run_seen = 0;
+  bool prev_plain = false;  // the previous launch was a full plain one
   double wc_prev = 1.0;  // Chebyshev weight recurrence
   // pending residual check (decided by the next launch) and the host poll:
   // a copy of the control block after each decision, read `lag` checks later
   int pend_m = -1, pend_np = 0, nchecks = 0;
   const double *pend_parts = nullptr;
+  volatile int64_t *word = h->poll_word;
+  *word = 0;  // the previous solve's launches are complete (it ended synchronized)
+  // the number the next decision writes
+  auto next_seq = [&]() { return (int)npending + 1; };
   auto poll = [&](bool &done) -> hipError_t {
-    const size_t slot = npending % h->ev_check.size();
-    hipError_t e = hipMemcpyAsync(&h->ctl_host[slot], V.ctl, sizeof(SolveCtl),
-                                  hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipEventRecord(h->ev_check[slot], s);
-    if (e != hipSuccess) return e;
-    ++npending;
-    if (npending - next_wait > (size_t)lag) {
-      const size_t w = next_wait % h->ev_check.size();
-      e = hipEventSynchronize(h->ev_check[w]);
-      if (e != hipSuccess) return e;
-      ++next_wait;
-      done = h->ctl_host[w].done != 0;
+    ++npending;  // decision npending is queued
+    if (npending <= (size_t)lag) return hipSuccess;
+    const int64_t want = (int64_t)(npending - lag);
+    for (uint64_t it = 1;; ++it) {
+      const int64_t v = *word;
+      if ((v >> 32) >= want || (v & 0xffffffff) != 0) {
+        done = (v & 0xffffffff) != 0;
+        return hipSuccess;
+      }
+      if (it % 256 == 0) {  // an idle stream has run every queued launch
+        const hipError_t q = hipStreamQuery(s);
+        if (q != hipErrorNotReady) {
+          if (q != hipSuccess) return q;
+          const int64_t v2 = *word;
+          done = (v2 & 0xffffffff) != 0;
+          return hipSuccess;
+        }
+      }
+      std::this_thread::yield();
     }
-    return hipSuccess;
   };
   Launch L = launch_at(0);
   int last_m = 0;
@@ -523,7 +542,12 @@ int run_sweeps(les_handle *h, View<T> &V, const T *rhs, int fixed, int cap, Solv
     const bool has_next = nextL.m >= 0;
     last_m = L.m;
     const bool plain_full = !L.check && L.S == smax;
-    if (timed && plain_full && run_first < 0 && runs.size() < kMaxRuns) {
+    // a run starts at a plain launch after a check; every kTimeEvery-th run
+    // is bracketed by events (each event costs the stream a few us)
+    const bool run_start = plain_full && !prev_plain;
+    if (run_start) ++run_seen;
+    if (timed && run_start && run_first < 0 && (run_seen - 1) % kTimeEvery == 0 &&
+        runs.size() < kMaxRuns) {
       const size_t e = 2 * runs.size();
       while (h->ev_sweep.size() < e + 2) {
         hipEvent_t ev;
@@ -566,7 +590,7 @@ int run_sweeps(les_handle *h, View<T> &V, const T *rhs, int fixed, int cap, Solv
                      prev >= 0 ? buf[prev] : nullptr, buf[out_last],
                      out_prev >= 0 ? buf[out_prev] : nullptr, rhs, V.ctl, parts,
                      decides ? pend_parts : nullptr, decides ? pend_np : 0, decides ? pend_m : -1,
-                     s);
+                     decides ? h->poll_word_dev : nullptr, next_seq(), s);
     if (L.S == 1) {
       prev = cur;
     } else {
@@ -595,18 +619,19 @@ int run_sweeps(les_handle *h, View<T> &V, const T *rhs, int fixed, int cap, Solv
         pend_parts = parts;
         pend_np = np;
       } else {
-        launch_final(parts, np, kFinalCheck, V.ctl, (double)g.n, 0.0, L.m, nullptr, s);
+        launch_final_check(parts, np, V.ctl, (double)g.n, L.m, h->poll_word_dev, next_seq(), s);
         LAUNCH_TRY();
         bool stop2 = false;
         HIP_TRY(poll(stop2));
         stop = stop || stop2;
       }
     }
+    prev_plain = plain_full;
     more = !stop && has_next;
     if (more) L = nextL;
   }
   if (pend_m >= 0) {  // a check no later launch decided (the loop stopped early)
-    launch_final(pend_parts, pend_np, kFinalCheck, V.ctl, (double)g.n, 0.0, pend_m, nullptr, s);
+    launch_final_check(pend_parts, pend_np, V.ctl, (double)g.n, pend_m, nullptr, 0, s);
     LAUNCH_TRY();
   }
   LAUNCH_TRY();
@@ -1248,12 +1273,17 @@ int init_impl(const les_config *cfg, const les_buffers *bufs, void *stream, les_
   };
   if (hipHostMalloc((void **)&h->ctl_host, 8 * sizeof(SolveCtl), hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(LES_ERR_HIP, "hipHostMalloc failed"));
+  // residual-test word: written by kernels, read by the host while they run,
+  // so coherent, mapped host memory seen through its device pointer
+  if (hipHostMalloc((void **)&h->poll_word, 256, hipHostMallocMapped | hipHostMallocCoherent) !=
+      hipSuccess)
+    return cleanup(fail(LES_ERR_HIP, "hipHostMalloc (coherent) failed"));
+  std::memset(h->poll_word, 0, 256);
+  if (hipHostGetDevicePointer((void **)&h->poll_word_dev, h->poll_word, 0) != hipSuccess)
+    return cleanup(fail(LES_ERR_HIP, "hipHostGetDevicePointer failed"));
   if (hipHostMalloc((void **)&h->diag_host, (size_t)cfg->nz * kDiagStride * sizeof(double),
                     hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(LES_ERR_HIP, "hipHostMalloc failed"));
-  h->ev_check.resize(8);
-  for (auto &e : h->ev_check)
-    if (hipEventCreate(&e) != hipSuccess) return cleanup(fail(LES_ERR_HIP, "hipEventCreate failed"));
   if (hipEventCreate(&h->ev_s0) != hipSuccess || hipEventCreate(&h->ev_s1) != hipSuccess ||
       hipEventCreate(&h->ev_a) != hipSuccess || hipEventCreate(&h->ev_b) != hipSuccess)
     return cleanup(fail(LES_ERR_HIP, "hipEventCreate failed"));
@@ -1449,14 +1479,13 @@ int les_diagnostics(les_handle *h, les_diag *out, double *profiles) {
 void les_destroy(les_handle *h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
-  for (auto &e : h->ev_check)
-    if (e) (void)hipEventDestroy(e);
   if (h->ev_s0) (void)hipEventDestroy(h->ev_s0);
   if (h->ev_s1) (void)hipEventDestroy(h->ev_s1);
   if (h->ev_a) (void)hipEventDestroy(h->ev_a);
   if (h->ev_b) (void)hipEventDestroy(h->ev_b);
   for (auto &e : h->ev_sweep) (void)hipEventDestroy(e);
   if (h->ctl_host) (void)hipHostFree(h->ctl_host);
+  if (h->poll_word) (void)hipHostFree(h->poll_word);
   if (h->diag_host) (void)hipHostFree(h->diag_host);
   delete h;
 }

@@ -193,7 +193,8 @@ template <typename T>
 void launch_tsweep(const Grid &g, int S, bool chebyshev, bool check, bool first,
                    double omega_jacobi, const double *omega_cheb, const T *cur, const T *prev,
                    T *out_last, T *out_prev, const T *rhs, SolveCtl *ctl, double *partials,
-                   const double *dec_partials, int dec_np, int dec_m, hipStream_t s);
+                   const double *dec_partials, int dec_np, int dec_m, int64_t *snap,
+                   int snap_seq, hipStream_t s);
 
 template <typename T>
 void launch_project(const Grid &g, const Dyn<T> &d, const Profiles<T> &P, const T *phi,
@@ -240,6 +241,11 @@ enum FinalOp {
   kFinalStore = 4,     // out[slot] = sum
   kFinalReturned = 5   // ctl->res_out2 = sum
 };
+// The residual test of sweep m from its partials (kFinalCheck); snap (a
+// device view of pinned host memory, nullable) receives (snap_seq << 32) |
+// done after the decision, one 64-bit store.
+void launch_final_check(const double *partials, int np, SolveCtl *ctl, double n, int m,
+                        int64_t *snap, int snap_seq, hipStream_t s);
 void launch_final(const double *partials, int np, int op, SolveCtl *ctl, double n, double tol2_scale,
                   int m, double *out, hipStream_t s);
 

@@ -30,6 +30,10 @@ int check_dims(const les_cnn_dims *d) {
   if (!(d->alpha >= 0.0)) return fail(LES_ERR_ARG, "alpha must be >= 0");
   if ((double)d->batch * d->nz * d->ny * d->nx * 64.0 > 1.0e12)
     return fail(LES_ERR_ARG, "dims too large");
+  // the tiled layers address a z plane of 16-channel activations with
+  // 32-bit element offsets
+  if ((int64_t)d->ny * d->nx * kCnnCh >= (int64_t)1 << 31)
+    return fail(LES_ERR_ARG, "at most 2^27 cells per z plane");
   return LES_OK;
 }
 

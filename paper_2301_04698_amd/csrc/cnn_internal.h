@@ -4,7 +4,7 @@
 // Network: four 3x3x3 convolutions, channels C -> 16 -> 16 -> 16 -> 1 (C = 1
 // or 3 inputs), with biases and a leaky ReLU after the first three.
 // Weights and layer inputs are bfloat16 (round to nearest even), sums FP32
-// (the first three layers on the matrix cores), the output FP32.
+// (inference on the matrix cores), the output FP32.
 // Activations are stored channels-last: element (cell, c) at cell * C + c.
 #pragma once
 
@@ -60,6 +60,13 @@ void launch_cnn_round(int64_t n, int C, int64_t cells, const float *x, const dou
 // Layers 0..2: aout = bf16(leaky(conv(ain) + b)).  Layer 3: yout = conv(ain) + b.
 void launch_cnn_conv(int layer, const CnnGeom &G, const uint16_t *ain, const float *params,
                      const uint16_t *wbf, float alpha, uint16_t *aout, float *yout, hipStream_t s);
+// Layers 0 and 1 of the one-input network on a periodic field in one pass
+// (G: layer 1's geometry, batch items of (nz, ny, nx)): the input is the
+// FP32 residual r (batch, nz, ny, nx) times *scale, rounded to bfloat16 as
+// launch_cnn_round does; aout = layer 1's output, as launch_cnn_conv
+// writes it.  Layer 0's activations stay on chip.
+void launch_cnn_in_mid(const CnnGeom &G, const float *r, const double *scale, const float *params,
+                       const uint16_t *wbf, float alpha, uint16_t *aout, hipStream_t s);
 // Layer 3 fused with the guess: guess = base + s_over_d * (conv(ain) + b).
 template <typename T>
 void launch_cnn_guess(const CnnGeom &G, const uint16_t *ain, const float *params,

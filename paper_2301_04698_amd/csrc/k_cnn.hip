@@ -6,13 +6,13 @@
 // network inputs of C channels are (batch, C, nz, ny, nx) in FP32 and
 // channels-last bfloat16 (cell * C + c) once rounded; 16-channel
 // activations are channels-last bfloat16 (cell * 16 + c), so one cell's
-// channels are one 32-byte line.  The two 16 -> 16 layers run on the matrix
-// cores as an implicit GEMM per tap: D(out ch x 16 cells) += W_tap(out x
-// in) * X_tap(in x 16 cells), FP32 accumulation, one wave per 16
-// consecutive output cells; the C -> 16 layer as one GEMM over (tap,
-// channel) pairs.  The 16 -> 1 layer and the backward pass are FP32 vector
-// code (FP64 sums in the weight gradient).
+// channels are one 32-byte line.  Inference runs on the matrix cores with
+// FP32 accumulation: the 16 -> 16 and 16 -> 1 layers as implicit GEMMs
+// over pairs of in-plane taps (16 consecutive output cells per product),
+// the C -> 16 layer as one GEMM over (tap, channel) pairs.  The backward
+// pass is FP32 vector code (FP64 sums in the weight gradient).
 #include <cmath>
+#include <type_traits>
 
 #include "cnn_internal.h"
 #include "les_device.h"
@@ -105,33 +105,48 @@ __global__ __launch_bounds__(kBlock) void round_kernel(int64_t n, int C, int64_t
   a0[q] = f2bf(v);
 }
 
-// Layers 1, 2 (16 -> 16) on the matrix cores, as an implicit GEMM per tap:
-// D(out ch x 16 cells) += W_tap(out ch x in ch) X_tap(in ch x 16 cells).
-// A block owns a 64 x 4 output tile of one batch item and marches up z
-// over kCnnKC levels; the input planes k-1, k, k+1 (tile plus a one-cell
-// ring, 16 channels, 32 B per cell) sit in a three-plane LDS ring, each
-// loaded once with coalesced 16-B loads.  Wave w computes output row w as
-// four 16-cell MFMA chains interleaved tap by tap.  Lane l: row = l % 16 is
-// its cell (B operand, result) and its output channel (A operand); quad =
-// l / 16 selects input channels 4 quad .. 4 quad + 3 (A, B) and output
-// channels 4 quad .. 4 quad + 3 of the result.  The 8-B quads of a cell are
-// stored at quad ^ ((cell >> 2) & 3) so the 16 lanes reading one quad of 16
-// consecutive cells hit distinct LDS banks.
+// Layers 1, 2 (16 -> 16) and 3 (16 -> 1) on the matrix cores as implicit
+// GEMMs over pairs of in-plane taps (K = 32: two taps x 16 input channels).
+// A block owns a 64 x 4 output tile of one batch item and marches the input
+// planes k0 - 1 .. k1 of its z chunk [k0, k1) (each read as its
+// mirror-clamped level, as every layer reads z).  Input plane p feeds
+// output levels p + 1, p and p - 1 through the tap rows dz = -1, 0, +1, so
+// each operand read from LDS serves three products and level p - 1 is
+// complete once plane p is done.  A plane (the tile plus a one-cell ring,
+// 16 channels, 32 B per cell) is loaded once with coalesced 16-B loads into
+// one slot of a two-slot LDS ring while the other slot is read, one
+// barrier per plane.  Wave w computes output row w as four 16-cell chains.
 constexpr int kCnnTX = 64, kCnnTY = 4, kCnnKC = 16;
 constexpr int kCnnPX = kCnnTX + 2, kCnnPY = kCnnTY + 2;
 constexpr int kCnnPlane = kCnnPX * kCnnPY;  // cells per LDS plane
-
-__device__ __forceinline__ int cnn_swz(int cell, int quad) { return quad ^ ((cell >> 2) & 3); }
+// In-plane tap pairs: pair m joins the taps 2m and 2m + 1 of the 3 x 3
+// plane stencil (t = 3 (dy + 1) + (dx + 1)); the second tap of pair 4 has
+// zero weights and reads tap 8 again.
+constexpr int kCnnPairs = 5;
+// LDS cell stride: the two 16-B channel halves, unpadded.  Measured on
+// gfx950, 16-B operand reads of this layout (lanes l % 16 on consecutive
+// cells, the two halves on alternate lane groups) run at the rate of fully
+// contiguous reads, while a 48-B stride costs 1.8x.
+constexpr int kCnnCellB = 32;
 
 // Block geometry shared by the tiled layers: a 64 x 4 output tile of batch
-// item b over z levels [k0, k1).
+// item b over z levels [k0, k1).  The grid is a multiple of 8 blocks and
+// XCD x (the blocks b with b % 8 = x) takes the x-th contiguous range of
+// tiles in the order x tile, y tile, z chunk, batch item, so that tiles
+// next to each other in y run on one XCD and share their halo rows in its
+// L2.  Blocks past the last tile are not valid.
 struct CnnTile {
   int b, ox0, oy0, ix0, iy0, k0, k1;
+  bool valid;
 };
+inline unsigned cnn_blocks(int64_t tiles) { return (unsigned)((tiles + 7) / 8 * 8); }
 __device__ __forceinline__ CnnTile cnn_tile(const CnnGeom &G, int tiles_x, int tiles_y,
                                             int chunks) {
-  int blk = blockIdx.x;
+  const int per = (int)(gridDim.x >> 3);
+  int blk = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
   CnnTile T;
+  T.valid = blk < G.batch * tiles_x * tiles_y * chunks;
+  if (!T.valid) blk = 0;
   const int tx = blk % tiles_x;
   blk /= tiles_x;
   const int ty = blk % tiles_y;
@@ -165,97 +180,307 @@ __device__ __forceinline__ int64_t cnn_src(const CnnGeom &G, const CnnTile &T, i
   return (((int64_t)T.b * G.nz + kk) * G.nyi + jj) * G.nxi + ii;
 }
 
-__global__ __launch_bounds__(256) void conv_mid_kernel(CnnGeom G, const uint16_t *__restrict__ ain,
-                                                       const float *__restrict__ bias,
-                                                       const uint16_t *__restrict__ w,
-                                                       float alpha, uint16_t *__restrict__ aout,
-                                                       int tiles_x, int tiles_y, int chunks) {
-  __shared__ uint2 lds[3][kCnnPlane * 4];  // [slot][cell * 4 + swizzled quad]
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int row = lane & 15, quad = lane >> 4;
-  const CnnTile T = cnn_tile(G, tiles_x, tiles_y, chunks);
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-  bf16x4 wa[kCnnTaps];
+__device__ __forceinline__ floatx4 mfma32(bf16x8 a, bf16x8 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Eight bfloat16 weights w[0..7] (8-B aligned) as one K = 32 operand half.
+__device__ __forceinline__ bf16x8 load_w8(const uint16_t *__restrict__ w) {
+  typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+  const u32x2 lo = *(const u32x2 *)w, hi = *(const u32x2 *)(w + 4);
+  return __builtin_bit_cast(bf16x8, u32x4{lo.x, lo.y, hi.x, hi.y});
+}
+
+// Operand register layout of a K = 32 product (v_mfma_f32_16x16x32_bf16):
+// lane l holds row / column l % 16 and k = 8 (l / 16) .. 8 (l / 16) + 7,
+// i.e. side = l / 32 picks the tap of the pair and half = (l / 16) % 2 the
+// input channels 8 half .. 8 half + 7.  The activation operand of lane l
+// is cell l % 16 of its chain, shifted by its tap: the byte offset of that
+// cell's channel half within an LDS plane, for pair m and chain 0 of wave
+// wv (chain c adds 16 c cells).
+__device__ __forceinline__ uint32_t pair_offset(int wv, int row, int side, int half, int m) {
+  const int t = min(2 * m + side, 8);
+  const int dy = t / 3 - 1, dx = t % 3 - 1;
+  return (uint32_t)(((wv + 1 + dy) * kCnnPX + row + 1 + dx) * kCnnCellB + 16 * half);
+}
+
+// Plane streaming of the tiled 16-channel layers: 2 x 16-B halves per cell
+// of the plane (tile plus ring), kPlaneLoads per thread.  The in-plane
+// source cell of each load (wrap or clamp) is fixed per thread; a plane
+// adds its level's offset.
+constexpr int kPlaneLoads = (kCnnPlane * 2 + 255) / 256;
+
+__device__ __forceinline__ void plane_sources(const CnnGeom &G, const CnnTile &T,
+                                              int32_t (&src)[kPlaneLoads]) {
 #pragma unroll
-  for (int t = 0; t < kCnnTaps; ++t)
-    wa[t] = *(const bf16x4 *)(w + (t * kCnnCh + row) * kCnnCh + 4 * quad);
+  for (int u = 0; u < kPlaneLoads; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    const int cell = min(e >> 1, kCnnPlane - 1);
+    const int ly = cell / kCnnPX, lx = cell - ly * kCnnPX;
+    // in-plane part of cnn_src: level 0 of batch item 0
+    const CnnTile T0 = {0, T.ox0, T.oy0, T.ix0, T.iy0, 0, 0, true};
+    src[u] = (int32_t)cnn_src(G, T0, 0, ly, lx) * kCnnCh + 8 * (e & 1);
+  }
+}
+
+// Element offset of level kk (mirror-clamped) of batch item b.
+__device__ __forceinline__ int64_t plane_base(const CnnGeom &G, int b, int kk) {
+  kk = kk < 0 ? 0 : (kk >= G.nz ? G.nz - 1 : kk);
+  return ((int64_t)b * G.nz + kk) * G.nyi * G.nxi * kCnnCh;
+}
+
+// Layers 1, 2: aout = bf16(leaky(conv(ain) + b)).  Lane l: row = l % 16 is
+// its output channel in the weight operand and its cell in the activation
+// operand and the result, which holds output channels 4 (l / 16) .. + 3.
+// FUSED (inference of the one-input network on a periodic field): layer 0
+// runs inside the block.  Each plane of layer 0's output is computed on
+// the tile plus its ring (bias, leaky ReLU, bfloat16) straight into the
+// LDS slot that layer 1 reads, from the network input: the FP32 residual r
+// times *in_scale, rounded to bfloat16 as the separate input pass does,
+// three planes of the tile plus a two-cell ring staged in LDS.  Layer 0's
+// activations never reach HBM.
+constexpr int kInPX = kCnnPX + 2, kInPY = kCnnPY + 2;
+constexpr int kInPlane = kInPX * kInPY;        // input cells per plane
+constexpr int kInSet = 3 * kInPlane;           // the three planes of one layer-0 plane
+constexpr int kInLoads = (kInSet + 255) / 256;  // per thread
+constexpr int kL0Chains = (kCnnPlane + 15) / 16;
+
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+template <bool FUSED>
+__global__ __launch_bounds__(256, 2) void conv_mid_kernel(
+    CnnGeom G, const uint16_t *__restrict__ ain, const float *__restrict__ rin,
+    const double *__restrict__ in_scale, const float *__restrict__ bias0,
+    const uint16_t *__restrict__ w0, const float *__restrict__ bias,
+    const uint16_t *__restrict__ w, float alpha, uint16_t *__restrict__ aout, int tiles_x,
+    int tiles_y, int chunks) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2][kCnnPlane * kCnnCellB];
+  // fused: the staged input set, one bfloat16 value per 32-bit word so that
+  // every operand read is an aligned word
+  __shared__ uint32_t inp[FUSED ? 2 : 1][FUSED ? kInSet : 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int row = lane & 15, quad = lane >> 4, side = quad >> 1, half = quad & 1;
+  const CnnTile T = cnn_tile(G, tiles_x, tiles_y, chunks);
+  if (!T.valid) return;  // the whole block
+  auto slot = [&](int p) { return (p - T.k0 + 1) & 1; };  // LDS slot of plane p
+
+  // weights W[9 (dz + 1) + t][o = row][8 half .. + 7], t = 2 m + side
+  bf16x8 wa[3][kCnnPairs];
+  uint32_t poff[kCnnPairs];
+#pragma unroll
+  for (int m = 0; m < kCnnPairs; ++m) {
+    const int t = 2 * m + side;
+#pragma unroll
+    for (int z = 0; z < 3; ++z)
+      wa[z][m] = t < 9 ? load_w8(w + ((9 * z + t) * kCnnCh + row) * kCnnCh + 8 * half)
+                       : bf16x8{};
+    poff[m] = pair_offset(wv, row, side, half, m);
+  }
   float bq[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) bq[r] = bias[4 * quad + r];
-
-  // plane kk (mirror-clamped): 2 x 16-B halves per cell, kLoads per thread,
-  // fetched into registers first (the next plane's fetch overlaps this
-  // plane's products), then stored to a slot
-  constexpr int kLoads = (kCnnPlane * 2 + 255) / 256;
-  uint4 pre[kLoads];
-  auto fetch = [&](int kk) {
-#pragma unroll
-    for (int u = 0; u < kLoads; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      if (e < kCnnPlane * 2) {
-        const int cell = e >> 1, h = e & 1;
-        const int ly = cell / kCnnPX, lx = cell - ly * kCnnPX;
-        pre[u] = *(const uint4 *)(ain + cnn_src(G, T, kk, ly, lx) * kCnnCh + 8 * h);
-      }
-    }
-  };
-  auto store = [&](int slot) {
-#pragma unroll
-    for (int u = 0; u < kLoads; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      if (e < kCnnPlane * 2) {
-        const int cell = e >> 1, h = e & 1;
-        lds[slot][cell * 4 + cnn_swz(cell, 2 * h)] = make_uint2(pre[u].x, pre[u].y);
-        lds[slot][cell * 4 + cnn_swz(cell, 2 * h + 1)] = make_uint2(pre[u].z, pre[u].w);
-      }
-    }
-  };
-
-  fetch(T.k0 - 1);
-  store((T.k0 + 2) % 3);
-  fetch(T.k0);
-  store(T.k0 % 3);
-  fetch(T.k0 + 1);
   const int oy = T.oy0 + wv;
-  for (int k = T.k0; k < T.k1; ++k) {
-    __syncthreads();  // slot (k+1)%3 is no longer read
-    store((k + 1) % 3);
-    __syncthreads();
-    if (k + 1 < T.k1) fetch(k + 2);  // in flight during this level's products
-    floatx4 acc[4];
+
+  // ---- how a plane reaches its LDS slot
+  // (a) layer-1 input from HBM: plane kk fetched into registers one plane
+  // ahead (the loads past the plane repeat its last cell and are not
+  // stored), then stored to a slot
+  int32_t src[FUSED ? 1 : kPlaneLoads];
+  u32x4 pre[FUSED ? 1 : kPlaneLoads];
+  // (b) fused layer 0: the input set of layer-0 plane P (levels L - 1, L,
+  // L + 1 of L = P, each mirror-clamped) fetched one set ahead as FP32
+  // (set element e = plane d * kInPlane + cell), rounded when stored
+  int32_t gof[FUSED ? kInLoads : 1];
+  float rpre[FUSED ? kInLoads : 1];
+  bf16x8 w0a[2];
+  float b0q[4];
+  double scale = 0.0;
+  if constexpr (FUSED) {
 #pragma unroll
-    for (int t4 = 0; t4 < 4; ++t4) acc[t4] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int u = 0; u < kInLoads; ++u) {
+      const int e = min((int)threadIdx.x + 256 * u, kInSet - 1);
+      const int cell = e % kInPlane, iy = cell / kInPX, ix = cell - iy * kInPX;
+      const int jj = pwrap(T.oy0 - 2 + iy, G.nyi), ii = pwrap(T.ox0 - 2 + ix, G.nxi);
+      gof[u] = jj * G.nxi + ii;
+    }
+    // layer-0 weight operand: k = 8 quad + e of product m is tap 9 quad +
+    // (8 m + e) (dz = quad - 1; in-plane taps 0..8), zero past them
 #pragma unroll
-    for (int t = 0; t < kCnnTaps; ++t) {
-      const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-      const uint2 *plane = lds[(k + dz + 3) % 3];
-      const int cbase = (wv + 1 + dy) * kCnnPX + row + 1 + dx;
+    for (int m = 0; m < 2; ++m) {
+      u16x8 v;
 #pragma unroll
-      for (int t4 = 0; t4 < 4; ++t4) {
-        const int cell = cbase + 16 * t4;
-        const uint2 v = plane[cell * 4 + cnn_swz(cell, quad)];
-        bf16x4 xb;
-        xb[0] = (short)(v.x & 0xFFFFu);
-        xb[1] = (short)(v.x >> 16);
-        xb[2] = (short)(v.y & 0xFFFFu);
-        xb[3] = (short)(v.y >> 16);
-        acc[t4] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[t], xb, acc[t4], 0, 0, 0);
+      for (int e = 0; e < 8; ++e) {
+        const int cb = 8 * m + e;
+        v[e] = quad < 3 && cb < 9 ? w0[(9 * quad + cb) * kCnnCh + row] : (uint16_t)0;
+      }
+      w0a[m] = __builtin_bit_cast(bf16x8, v);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) b0q[r] = bias0[4 * quad + r];
+    scale = *in_scale;
+  } else {
+    plane_sources(G, T, src);
+  }
+  const int64_t in_plane = (int64_t)G.nyi * G.nxi;
+  auto fetch_set = [&](int P) __attribute__((always_inline)) {
+    const int L = P < 0 ? 0 : (P >= G.nz ? G.nz - 1 : P);
+#pragma unroll
+    for (int u = 0; u < kInLoads; ++u) {
+      const int e = min((int)threadIdx.x + 256 * u, kInSet - 1);
+      int lev = L + e / kInPlane - 1;
+      lev = lev < 0 ? 0 : (lev >= G.nz ? G.nz - 1 : lev);
+      rpre[u] = rin[((int64_t)T.b * G.nz + lev) * in_plane + gof[u]];
+    }
+  };
+  auto store_set = [&](uint32_t *dst) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < kInLoads; ++u) {
+      const int e = (int)threadIdx.x + 256 * u;
+      if (e < kInSet) dst[e] = f2bf((float)((double)rpre[u] * scale));
+    }
+  };
+  // chain k of layer-0 plane P (input set in LDS) into slot(P): wave w
+  // takes the 16-cell chains w + 4 k, k = 0..6, of the tile-plus-ring plane
+  // (k = 6 only for wave 0: 25 chains)
+  auto layer0_chain = [&](int k, int P) __attribute__((always_inline)) {
+    const uint32_t *in = inp[slot(P)];
+    unsigned char *dst = lds[slot(P)];
+    {
+      const int ch = wv + 4 * k;
+      const int cell = ch * 16 + row, cc = min(cell, kCnnPlane - 1);
+      const int ay = cc / kCnnPX, ax = cc - ay * kCnnPX;
+      const uint32_t *pl = in + min(quad, 2) * kInPlane + (ay + 1) * kInPX + ax + 1;
+      u16x8 v0, v1 = {};
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v0[e] = (uint16_t)pl[(e / 3 - 1) * kInPX + (e % 3 - 1)];
+      v1[0] = (uint16_t)pl[kInPX + 1];  // in-plane tap 8
+      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+      acc = mfma32(w0a[0], __builtin_bit_cast(bf16x8, v0), acc);
+      acc = mfma32(w0a[1], __builtin_bit_cast(bf16x8, v1), acc);
+      if (cell < kCnnPlane) {
+        const uint32_t l2 = (uint32_t)f2bf(leaky(acc[0] + b0q[0], alpha)) |
+                            ((uint32_t)f2bf(leaky(acc[1] + b0q[1], alpha)) << 16);
+        const uint32_t h2 = (uint32_t)f2bf(leaky(acc[2] + b0q[2], alpha)) |
+                            ((uint32_t)f2bf(leaky(acc[3] + b0q[3], alpha)) << 16);
+        *(uint2 *)(dst + cell * kCnnCellB + 8 * quad) = make_uint2(l2, h2);
       }
     }
-    if (oy < G.nyo) {
+  };
+  auto layer0 = [&](int P) __attribute__((always_inline)) {
 #pragma unroll
-      for (int t4 = 0; t4 < 4; ++t4) {
-        const int ox = T.ox0 + 16 * t4 + row;
+    for (int k = 0; k < 6; ++k) layer0_chain(k, P);
+    if (wv == 0) layer0_chain(6, P);
+  };
+  auto fetch = [&](int kk) __attribute__((always_inline)) {
+    const uint16_t *pl = ain + plane_base(G, T.b, kk);
+#pragma unroll
+    for (int u = 0; u < kPlaneLoads; ++u) pre[u] = *(const u32x4 *)(pl + src[u]);
+  };
+  auto store = [&](unsigned char *dst) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < kPlaneLoads; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      if (e < kCnnPlane * 2) *(u32x4 *)(dst + (e >> 1) * kCnnCellB + 16 * (e & 1)) = pre[u];
+    }
+  };
+  // plane P into slot(P) (all waves finished reading that slot before the
+  // last barrier); the one after it prepared.  Fused: layer 0 of plane P
+  // itself runs among the products of the plane before.
+  auto produce = [&](int P) __attribute__((always_inline)) {
+    if constexpr (FUSED) {
+      if (P + 1 <= T.k1) {
+        store_set(inp[slot(P + 1)]);
+        if (P + 2 <= T.k1) fetch_set(P + 2);
+      }
+    } else {
+      store(lds[slot(P)]);
+      if (P + 1 <= T.k1) fetch(P + 1);
+    }
+  };
+  if constexpr (FUSED) {
+    fetch_set(T.k0 - 1);
+    store_set(inp[slot(T.k0 - 1)]);
+    fetch_set(T.k0);
+    store_set(inp[slot(T.k0)]);
+    fetch_set(T.k0 + 1);
+    __syncthreads();
+    layer0(T.k0 - 1);
+  } else {
+    fetch(T.k0 - 1);
+    store(lds[slot(T.k0 - 1)]);
+    fetch(T.k0);
+  }
+  __syncthreads();
+
+  // Plane p with the accumulators of levels p - 1 (lo), p (mid), p + 1
+  // (hi); MODE 1: hi only.  Produces plane p + 1, emits level p - 1 and
+  // clears lo (the next plane's hi).  Fused: the layer-0 chains of plane
+  // p + 1 are spread over the pairs so that their latency overlaps the
+  // products; at p = k1 they fill a slot nobody reads (the stale input set
+  // there is a finite earlier one).
+  auto plane = [&](auto mode, int p, floatx4(&lo)[4], floatx4(&mid)[4],
+                   floatx4(&hi)[4]) __attribute__((always_inline)) {
+    constexpr int MODE = decltype(mode)::value;
+    const unsigned char *cur = lds[slot(p)];
+#pragma unroll
+    for (int m = 0; m < kCnnPairs; ++m) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const bf16x8 b = *(const bf16x8 *)(cur + poff[m] + c * 16 * kCnnCellB);
+        if constexpr (MODE == 0) {
+          lo[c] = mfma32(wa[2][m], b, lo[c]);
+          mid[c] = mfma32(wa[1][m], b, mid[c]);
+        }
+        hi[c] = mfma32(wa[0][m], b, hi[c]);
+      }
+      if constexpr (FUSED) {
+        layer0_chain(m, p + 1);
+        if (m == 0) layer0_chain(5, p + 1);
+        if (m == 1 && wv == 0) layer0_chain(6, p + 1);
+      }
+    }
+    if (p < T.k1) produce(p + 1);
+    const int o = p - 1;
+    if (o >= T.k0 && oy < G.nyo) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int ox = T.ox0 + 16 * c + row;
         if (ox < G.nxo) {
-          const uint32_t lo = (uint32_t)f2bf(leaky(acc[t4][0] + bq[0], alpha)) |
-                              ((uint32_t)f2bf(leaky(acc[t4][1] + bq[1], alpha)) << 16);
-          const uint32_t hi = (uint32_t)f2bf(leaky(acc[t4][2] + bq[2], alpha)) |
-                              ((uint32_t)f2bf(leaky(acc[t4][3] + bq[3], alpha)) << 16);
-          const int64_t q = (((int64_t)T.b * G.nz + k) * G.nyo + oy) * G.nxo + ox;
-          *(uint2 *)(aout + q * kCnnCh + 4 * quad) = make_uint2(lo, hi);
+          const uint32_t l2 = (uint32_t)f2bf(leaky(lo[c][0] + bq[0], alpha)) |
+                              ((uint32_t)f2bf(leaky(lo[c][1] + bq[1], alpha)) << 16);
+          const uint32_t h2 = (uint32_t)f2bf(leaky(lo[c][2] + bq[2], alpha)) |
+                              ((uint32_t)f2bf(leaky(lo[c][3] + bq[3], alpha)) << 16);
+          const int64_t q = (((int64_t)T.b * G.nz + o) * G.nyo + oy) * G.nxo + ox;
+          *(uint2 *)(aout + q * kCnnCh + 4 * quad) = make_uint2(l2, h2);
         }
       }
     }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) lo[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    __syncthreads();
+  };
+  floatx4 a0[4], a1[4], a2[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    a0[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    a1[c] = a0[c];
+    a2[c] = a0[c];
+  }
+  // plane k0 - 1 feeds level k0 only; the later planes run all three
+  // products (at planes k0 and k1 one or two of them belong to levels
+  // outside the chunk and are dropped), the accumulators rotating roles
+  // every plane: three planes per trip
+  plane(std::integral_constant<int, 1>{}, T.k0 - 1, a0, a1, a2);
+  for (int p = T.k0;; p += 3) {
+    plane(std::integral_constant<int, 0>{}, p, a1, a2, a0);
+    if (p + 1 > T.k1) break;
+    plane(std::integral_constant<int, 0>{}, p + 1, a2, a0, a1);
+    if (p + 2 > T.k1) break;
+    plane(std::integral_constant<int, 0>{}, p + 2, a0, a1, a2);
+    if (p + 3 > T.k1) break;
   }
 }
 
@@ -275,6 +500,7 @@ __global__ __launch_bounds__(256) void conv_in_kernel(CnnGeom G, const uint16_t 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int row = lane & 15, quad = lane >> 4;
   const CnnTile T = cnn_tile(G, tiles_x, tiles_y, chunks);
+  if (!T.valid) return;  // the whole block
   // A operands: W0[tap][o = row][c] for k = 16 m + 4 quad + r
   bf16x4 wa[KM];
 #pragma unroll
@@ -354,17 +580,14 @@ __global__ __launch_bounds__(256) void conv_in_kernel(CnnGeom G, const uint16_t 
   }
 }
 
-// Layer 3 (16 -> 1) as a matrix-core product per input plane, then a
-// gather.  For every cell of an input plane (the tile plus its one-cell
-// ring) D[t][cell] = sum_c W3[t][c] a[cell][c] for the 27 taps t: two
-// MFMAs per 16 cells (taps padded to 32 rows of A), kept in LDS.  Output
-// cell o then adds, per plane, the D of its 9 neighbours there for the taps
-// pointing back at o.  Marching the input planes k0-1 .. k1 (each read as
-// its mirror-clamped level, as every layer reads z), plane p completes
-// output level p - 1 (planes p - 2, p - 1, p); each thread keeps its output
-// cell's three open levels p - 1, p, p + 1 in registers rotated per plane.  LDS bank use: D rows are
-// kCnnPlane = 396 floats apart, so the four quads of a wave's D store land
-// in disjoint banks; the gather reads consecutive cells per lane.
+// Layer 3 (16 -> 1): y = conv(ain) + b.  The activations are the row operand
+// (lane l % 16 = cell, as in the layers before) and the weights the column
+// operand, whose columns 0..2 carry the three open output levels: with the
+// plane counter q = p - (k0 - 1), column j accumulates the levels u = o -
+// (k0 - 1) with u = j (mod 3), so at plane q column j takes the tap row dz
+// = q - u.  Level p - 1 (column (q + 2) mod 3) is complete after plane p:
+// its lanes hold 4 consecutive cells each; they pass them on and clear the
+// column.
 // GUESS: the output becomes the guess base + s_over_d * y.
 template <typename T, bool GUESS>
 __global__ __launch_bounds__(256) void conv_out_kernel(CnnGeom G, const uint16_t *__restrict__ ain,
@@ -375,100 +598,102 @@ __global__ __launch_bounds__(256) void conv_out_kernel(CnnGeom G, const uint16_t
                                                        const double *__restrict__ s_over_d,
                                                        T *__restrict__ guess, int tiles_x,
                                                        int tiles_y, int chunks) {
-  __shared__ uint2 lds[kCnnPlane * 4];        // one input plane: 16 channels per cell
-  __shared__ float dl[kCnnTaps][kCnnPlane];   // its per-tap products
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2][kCnnPlane * kCnnCellB];
+  __shared__ __attribute__((aligned(16))) float res[4][kCnnTX];  // a finished level per wave
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int row = lane & 15, quad = lane >> 4;
+  const int row = lane & 15, quad = lane >> 4, side = quad >> 1, half = quad & 1;
   const CnnTile Tl = cnn_tile(G, tiles_x, tiles_y, chunks);
-  // A operands: W3[t = 16 m + row][c = 4 quad + r] (one output channel)
+  if (!Tl.valid) return;  // the whole block
   const uint16_t *w3 = wbf + cnn_weight_offset(G.inputs, 3);
-  bf16x4 wa[2];
+
+  // weights of phase f = q mod 3: column j = row < 3 holds W3[9 (dz + 1) +
+  // t][8 half .. + 7], t = 2 m + side, dz = +1, 0, -1 for (f - j) mod 3 =
+  // 1, 0, 2
+  bf16x8 wb[3][kCnnPairs];
+  uint32_t poff[kCnnPairs];
 #pragma unroll
-  for (int m = 0; m < 2; ++m)
+  for (int m = 0; m < kCnnPairs; ++m) {
+    const int t = 2 * m + side;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int t = 16 * m + row;
-      wa[m][r] = t < kCnnTaps ? (short)w3[t * kCnnCh + 4 * quad + r] : (short)0;
+    for (int f = 0; f < 3; ++f) {
+      const int d = (f - row + 3) % 3;
+      const int z = d == 0 ? 1 : (d == 1 ? 2 : 0);  // dz + 1
+      wb[f][m] = row < 3 && t < 9 ? load_w8(w3 + (9 * z + t) * kCnnCh + 8 * half) : bf16x8{};
     }
+    poff[m] = pair_offset(wv, row, side, half, m);
+  }
   const float b3 = params[cnn_bias_offset(G.inputs, 3)];
-  const int lx0 = threadIdx.x & 63, ly0 = threadIdx.x >> 6;  // this thread's output cell
-  const int oy = Tl.oy0 + ly0, ox = Tl.ox0 + lx0;
-  // plane kk (mirror-clamped) fetched into registers one plane ahead, so
-  // the fetch overlaps the previous plane's products and gather
-  constexpr int kLoads = (kCnnPlane * 2 + 255) / 256;
-  uint4 pre[kLoads];
-  auto fetch = [&](int kk) {
+  const double sd = GUESS ? *s_over_d : 0.0;
+  const int oy = Tl.oy0 + wv;
+
+  // plane kk fetched into registers one plane ahead (the loads past the
+  // plane repeat its last cell and are not stored), then stored to a slot
+  int32_t src[kPlaneLoads];
+  plane_sources(G, Tl, src);
+  u32x4 pre[kPlaneLoads];
+  auto fetch = [&](int kk) __attribute__((always_inline)) {
+    const uint16_t *pl = ain + plane_base(G, Tl.b, kk);
 #pragma unroll
-    for (int u = 0; u < kLoads; ++u) {
+    for (int u = 0; u < kPlaneLoads; ++u) pre[u] = *(const u32x4 *)(pl + src[u]);
+  };
+  auto store = [&](unsigned char *slot) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < kPlaneLoads; ++u) {
       const int e = threadIdx.x + 256 * u;
-      if (e < kCnnPlane * 2) {
-        const int cell = e >> 1, h = e & 1;
-        const int ly = cell / kCnnPX, lx = cell - ly * kCnnPX;
-        pre[u] = *(const uint4 *)(ain + cnn_src(G, Tl, kk, ly, lx) * kCnnCh + 8 * h);
-      }
+      if (e < kCnnPlane * 2) *(u32x4 *)(slot + (e >> 1) * kCnnCellB + 16 * (e & 1)) = pre[u];
     }
   };
-  float am = 0.f, a0 = 0.f, ap = 0.f;  // output levels p - 1, p, p + 1
   fetch(Tl.k0 - 1);
-  for (int p = Tl.k0 - 1; p <= Tl.k1; ++p) {
-    __syncthreads();  // the previous plane and its products are no longer read
+  store(lds[0]);
+  fetch(Tl.k0);
+  __syncthreads();
+
+  floatx4 acc[4];
 #pragma unroll
-    for (int u = 0; u < kLoads; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      if (e < kCnnPlane * 2) {
-        const int cell = e >> 1, h = e & 1;
-        lds[cell * 4 + cnn_swz(cell, 2 * h)] = make_uint2(pre[u].x, pre[u].y);
-        lds[cell * 4 + cnn_swz(cell, 2 * h + 1)] = make_uint2(pre[u].z, pre[u].w);
+  for (int c = 0; c < 4; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  auto plane = [&](auto phase, int p) __attribute__((always_inline)) {
+    constexpr int F = decltype(phase)::value;
+    const unsigned char *cur = lds[(p - Tl.k0 + 1) & 1];
+#pragma unroll
+    for (int m = 0; m < kCnnPairs; ++m)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const bf16x8 a = *(const bf16x8 *)(cur + poff[m] + c * 16 * kCnnCellB);
+        acc[c] = mfma32(a, wb[F][m], acc[c]);
+      }
+    if (p < Tl.k1) {
+      store(lds[(p - Tl.k0) & 1]);
+      if (p + 1 < Tl.k1) fetch(p + 2);
+    }
+    // level p - 1 (column J) through the wave's LDS row, so that lane l
+    // writes cell ox0 + l (LDS operations of one wave complete in order)
+    constexpr int J = (F + 2) % 3;
+    if (row == J) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        *(floatx4 *)&res[wv][16 * c + 4 * quad] = acc[c];
+        acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
       }
     }
-    if (p < Tl.k1) fetch(p + 1);
-    __syncthreads();
-    for (int gi = wv; gi < (kCnnPlane + 15) / 16; gi += 4) {
-      const int cell = gi * 16 + row;
-      const int cl = cell < kCnnPlane ? cell : kCnnPlane - 1;
-      const uint2 v = lds[cl * 4 + cnn_swz(cl, quad)];
-      bf16x4 xb;
-      xb[0] = (short)(v.x & 0xFFFFu);
-      xb[1] = (short)(v.x >> 16);
-      xb[2] = (short)(v.y & 0xFFFFu);
-      xb[3] = (short)(v.y >> 16);
-      const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
-      const floatx4 d0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[0], xb, zero, 0, 0, 0);
-      const floatx4 d1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[1], xb, zero, 0, 0, 0);
-      if (cell < kCnnPlane) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          dl[4 * quad + r][cell] = d0[r];
-          if (16 + 4 * quad + r < kCnnTaps) dl[16 + 4 * quad + r][cell] = d1[r];
-        }
-      }
-    }
-    __syncthreads();
-    // output level p - dz reads plane p at tap row dz
-    auto gather = [&](int dz) {
-      float sum = 0.f;
-#pragma unroll
-      for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx)
-          sum += dl[9 * (dz + 1) + 3 * (dy + 1) + (dx + 1)][(ly0 + 1 + dy) * kCnnPX + lx0 + 1 + dx];
-      return sum;
-    };
-    if (p - 1 >= Tl.k0 && p - 1 < Tl.k1) am += gather(1);
-    if (p >= Tl.k0 && p < Tl.k1) a0 += gather(0);
-    if (p + 1 >= Tl.k0 && p + 1 < Tl.k1) ap += gather(-1);
-    const int oc = p - 1;  // complete now
-    if (oc >= Tl.k0 && oc < Tl.k1 && oy < G.nyo && ox < G.nxo) {
-      const float out = am + b3;
-      const int64_t q = (((int64_t)Tl.b * G.nz + oc) * G.nyo + oy) * G.nxo + ox;
+    __builtin_amdgcn_wave_barrier();
+    const int o = p - 1, ox = Tl.ox0 + lane;
+    if (o >= Tl.k0 && oy < G.nyo && ox < G.nxo) {
+      const float out = res[wv][lane] + b3;
+      const int64_t q = (((int64_t)Tl.b * G.nz + o) * G.nyo + oy) * G.nxo + ox;
       if (GUESS)
-        guess[q] = (T)((double)base[q] + *s_over_d * (double)out);
+        guess[q] = (T)((double)base[q] + sd * (double)out);
       else
         y[q] = out;
     }
-    am = a0;
-    a0 = ap;
-    ap = 0.f;
+    __syncthreads();
+  };
+  for (int p = Tl.k0 - 1;; p += 3) {
+    plane(std::integral_constant<int, 0>{}, p);
+    if (p + 1 > Tl.k1) break;
+    plane(std::integral_constant<int, 1>{}, p + 1);
+    if (p + 2 > Tl.k1) break;
+    plane(std::integral_constant<int, 2>{}, p + 2);
+    if (p + 3 > Tl.k1) break;
   }
 }
 
@@ -687,28 +912,42 @@ __global__ __launch_bounds__(kBlock) void residual_kernel(Grid g, double ix2, do
                                                           float *__restrict__ r,
                                                           double *__restrict__ partials) {
   double acc = 0.0;
-  // block b takes the x rows b, b + gridDim.x, ... (level and y index uniform)
-  const int64_t rows = (int64_t)g.ny * g.nz;
-  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
-    const int k = (int)(row / g.ny), j = (int)(row - (int64_t)k * g.ny);
-    const T *c0 = base ? base + row * g.nx : nullptr;
-    const T *yp = base ? base + ((int64_t)k * g.ny + pwrap(j + 1, g.ny)) * g.nx : nullptr;
-    const T *ym = base ? base + ((int64_t)k * g.ny + pwrap(j - 1, g.ny)) * g.nx : nullptr;
-    const T *zp = base ? base + ((int64_t)zmirror(k + 1, g.nz) * g.ny + j) * g.nx : nullptr;
-    const T *zm = base ? base + ((int64_t)zmirror(k - 1, g.nz) * g.ny + j) * g.nx : nullptr;
+  // block b takes the x rows b, b + gridDim.x, ..., four at a time (rows
+  // past the end repeat the last row and are not counted) so that their
+  // loads are in flight together; level and y index uniform over the block
+  const int64_t rows = (int64_t)g.ny * g.nz, stride = gridDim.x;
+  constexpr int R = 4;
+  for (int64_t r0 = blockIdx.x; r0 < rows; r0 += R * stride) {
     for (int i = threadIdx.x; i < g.nx; i += blockDim.x) {
-      const int64_t q = row * g.nx + i;
-      double v = (double)rhs[q];
-      if (base) {
-        const int ip = i + 1 < g.nx ? i + 1 : 0, im = i > 0 ? i - 1 : g.nx - 1;
-        const double c = c0[i];
-        const double lap = ((double)c0[ip] + (double)c0[im] - 2.0 * c) * ix2 +
-                           ((double)yp[i] + (double)ym[i] - 2.0 * c) * iy2 +
-                           ((double)zp[i] + (double)zm[i] - 2.0 * c) * iz2;
-        v -= lap;
+      const int ip = i + 1 < g.nx ? i + 1 : 0, im = i > 0 ? i - 1 : g.nx - 1;
+      double rv[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int64_t row = min(r0 + u * stride, rows - 1);
+        const int k = (int)(row / g.ny), j = (int)(row - (int64_t)k * g.ny);
+        double v = (double)rhs[row * g.nx + i];
+        if (base) {
+          const T *c0 = base + row * g.nx;
+          const T *yp = base + ((int64_t)k * g.ny + pwrap(j + 1, g.ny)) * g.nx;
+          const T *ym = base + ((int64_t)k * g.ny + pwrap(j - 1, g.ny)) * g.nx;
+          const T *zp = base + ((int64_t)zmirror(k + 1, g.nz) * g.ny + j) * g.nx;
+          const T *zm = base + ((int64_t)zmirror(k - 1, g.nz) * g.ny + j) * g.nx;
+          const double c = c0[i];
+          const double lap = ((double)c0[ip] + (double)c0[im] - 2.0 * c) * ix2 +
+                             ((double)yp[i] + (double)ym[i] - 2.0 * c) * iy2 +
+                             ((double)zp[i] + (double)zm[i] - 2.0 * c) * iz2;
+          v -= lap;
+        }
+        rv[u] = v;
       }
-      r[q] = (float)v;
-      acc += v * v;
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int64_t row = r0 + u * stride;
+        if (row < rows) {
+          r[row * g.nx + i] = (float)rv[u];
+          acc += rv[u] * rv[u];
+        }
+      }
     }
   }
   const double s = block_sum(acc);
@@ -862,7 +1101,7 @@ void launch_cnn_conv(int layer, const CnnGeom &G, const uint16_t *ain, const flo
                      const uint16_t *wbf, float alpha, uint16_t *aout, float *yout, hipStream_t s) {
   const int tiles_x = (G.nxo + kCnnTX - 1) / kCnnTX, tiles_y = (G.nyo + kCnnTY - 1) / kCnnTY;
   const int chunks = (G.nz + kCnnKC - 1) / kCnnKC;
-  const unsigned blocks = (unsigned)((int64_t)G.batch * tiles_x * tiles_y * chunks);
+  const unsigned blocks = cnn_blocks((int64_t)G.batch * tiles_x * tiles_y * chunks);
   if (layer == 0) {
     if (G.inputs == 3)
       conv_in_kernel<3><<<blocks, 256, 0, s>>>(G, ain, params, wbf, alpha, aout, tiles_x, tiles_y,
@@ -871,14 +1110,25 @@ void launch_cnn_conv(int layer, const CnnGeom &G, const uint16_t *ain, const flo
       conv_in_kernel<1><<<blocks, 256, 0, s>>>(G, ain, params, wbf, alpha, aout, tiles_x, tiles_y,
                                                chunks);
   } else if (layer < kCnnLayers - 1) {
-    conv_mid_kernel<<<blocks, 256, 0, s>>>(G, ain, params + cnn_bias_offset(G.inputs, layer),
-                                           wbf + cnn_weight_offset(G.inputs, layer), alpha, aout,
-                                           tiles_x, tiles_y, chunks);
+    conv_mid_kernel<false><<<blocks, 256, 0, s>>>(
+        G, ain, nullptr, nullptr, nullptr, nullptr, params + cnn_bias_offset(G.inputs, layer),
+        wbf + cnn_weight_offset(G.inputs, layer), alpha, aout, tiles_x, tiles_y, chunks);
   } else {
     conv_out_kernel<float, false><<<blocks, 256, 0, s>>>(G, ain, params, wbf, yout, nullptr,
                                                          nullptr, nullptr, tiles_x, tiles_y,
                                                          chunks);
   }
+}
+
+void launch_cnn_in_mid(const CnnGeom &G, const float *r, const double *scale, const float *params,
+                       const uint16_t *wbf, float alpha, uint16_t *aout, hipStream_t s) {
+  const int tiles_x = (G.nxo + kCnnTX - 1) / kCnnTX, tiles_y = (G.nyo + kCnnTY - 1) / kCnnTY;
+  const int chunks = (G.nz + kCnnKC - 1) / kCnnKC;
+  const unsigned blocks = cnn_blocks((int64_t)G.batch * tiles_x * tiles_y * chunks);
+  conv_mid_kernel<true><<<blocks, 256, 0, s>>>(
+      G, nullptr, r, scale, params + cnn_bias_offset(1, 0), wbf + cnn_weight_offset(1, 0),
+      params + cnn_bias_offset(1, 1), wbf + cnn_weight_offset(1, 1), alpha, aout, tiles_x, tiles_y,
+      chunks);
 }
 
 template <typename T>
@@ -887,7 +1137,7 @@ void launch_cnn_guess(const CnnGeom &G, const uint16_t *ain, const float *params
                       hipStream_t s) {
   const int tiles_x = (G.nxo + kCnnTX - 1) / kCnnTX, tiles_y = (G.nyo + kCnnTY - 1) / kCnnTY;
   const int chunks = (G.nz + kCnnKC - 1) / kCnnKC;
-  const unsigned blocks = (unsigned)((int64_t)G.batch * tiles_x * tiles_y * chunks);
+  const unsigned blocks = cnn_blocks((int64_t)G.batch * tiles_x * tiles_y * chunks);
   conv_out_kernel<T, true><<<blocks, 256, 0, s>>>(G, ain, params, wbf, nullptr, base, s_over_d,
                                                   guess, tiles_x, tiles_y, chunks);
 }

@@ -503,35 +503,50 @@ __global__ __launch_bounds__(kBlock) void guess_residual_kernel(Grid g, double i
                                                                 const SolveCtl *__restrict__ when) {
   if (when && !when->guess_kept) return;
   double rr = 0.0, bb = 0.0;
-  // block b takes the x rows b, b + gridDim.x, ...: the row's level and y
-  // index (and its neighbour rows) are uniform over the block
-  const int64_t rows = (int64_t)g.ny * g.nz;
-  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
-    const int k = (int)(row / g.ny), j = (int)(row - (int64_t)k * g.ny);
-    const int jp = pwrap(j + 1, g.ny), jm = pwrap(j - 1, g.ny);
-    const int kp = zmirror(k + 1, g.nz), km = zmirror(k - 1, g.nz);
-    const T *c0 = phi0 + row * g.nx;
-    const T *yp = phi0 + ((int64_t)k * g.ny + jp) * g.nx, *ym = phi0 + ((int64_t)k * g.ny + jm) * g.nx;
-    const T *zp = phi0 + ((int64_t)kp * g.ny + j) * g.nx, *zm = phi0 + ((int64_t)km * g.ny + j) * g.nx;
-    const double gz = gbar ? (gbar[kp] - 2.0 * gbar[k] + gbar[km]) * iz2 : 0.0;
+  // block b takes the x rows b, b + gridDim.x, ..., four at a time (rows
+  // past the end repeat the last row and are not counted) so that their
+  // loads are in flight together; a row's level and y index (and its
+  // neighbour rows) are uniform over the block
+  const int64_t rows = (int64_t)g.ny * g.nz, stride = gridDim.x;
+  constexpr int R = 4;
+  for (int64_t r0 = blockIdx.x; r0 < rows; r0 += R * stride) {
     for (int i = threadIdx.x; i < g.nx; i += blockDim.x) {
       const int ip = i + 1 < g.nx ? i + 1 : 0, im = i > 0 ? i - 1 : g.nx - 1;
-      const double c = c0[i];
-      double lap = ((double)c0[ip] + (double)c0[im] - 2.0 * c) * ix2 +
-                   ((double)yp[i] + (double)ym[i] - 2.0 * c) * iy2 +
-                   ((double)zp[i] + (double)zm[i] - 2.0 * c) * iz2;
-      lap -= gz;
-      if (gv) {  // the x-y second differences of the guess's column means
-        const double gc = gv[(int64_t)i + g.sy * j];
-        lap -= (gv[ip + g.sy * j] + gv[im + g.sy * j] - 2.0 * gc) * ix2 +
-               (gv[i + g.sy * jp] + gv[i + g.sy * jm] - 2.0 * gc) * iy2;
+      double dv[R], bv[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int64_t row = min(r0 + u * stride, rows - 1);
+        const int k = (int)(row / g.ny), j = (int)(row - (int64_t)k * g.ny);
+        const int jp = pwrap(j + 1, g.ny), jm = pwrap(j - 1, g.ny);
+        const int kp = zmirror(k + 1, g.nz), km = zmirror(k - 1, g.nz);
+        const T *c0 = phi0 + row * g.nx;
+        const T *yp = phi0 + ((int64_t)k * g.ny + jp) * g.nx;
+        const T *ym = phi0 + ((int64_t)k * g.ny + jm) * g.nx;
+        const T *zp = phi0 + ((int64_t)kp * g.ny + j) * g.nx;
+        const T *zm = phi0 + ((int64_t)km * g.ny + j) * g.nx;
+        const double gz = gbar ? (gbar[kp] - 2.0 * gbar[k] + gbar[km]) * iz2 : 0.0;
+        const double c = c0[i];
+        double lap = ((double)c0[ip] + (double)c0[im] - 2.0 * c) * ix2 +
+                     ((double)yp[i] + (double)ym[i] - 2.0 * c) * iy2 +
+                     ((double)zp[i] + (double)zm[i] - 2.0 * c) * iz2;
+        lap -= gz;
+        if (gv) {  // the x-y second differences of the guess's column means
+          const double gc = gv[(int64_t)i + g.sy * j];
+          lap -= (gv[ip + g.sy * j] + gv[im + g.sy * j] - 2.0 * gc) * ix2 +
+                 (gv[i + g.sy * jp] + gv[i + g.sy * jm] - 2.0 * gc) * iy2;
+        }
+        bv[u] = rhs[row * g.nx + i];
+        dv[u] = bv[u] - lap;
       }
-      const int64_t q = row * g.nx + i;
-      const double b = rhs[q];
-      const double d = b - lap;
-      if (rhs_d) rhs_d[q] = (T)d;
-      rr += d * d;
-      bb += b * b;
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int64_t row = r0 + u * stride;
+        if (row < rows) {
+          if (rhs_d) rhs_d[row * g.nx + i] = (T)dv[u];
+          rr += dv[u] * dv[u];
+          bb += bv[u] * bv[u];
+        }
+      }
     }
   }
   const double sr = block_sum(rr);

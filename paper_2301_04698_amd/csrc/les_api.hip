@@ -106,6 +106,11 @@ int validate(const les_config *c) {
     return fail(LES_ERR_ARG, "T_ice must be in (0, Tf) for LES_PHASE_RAMP");
   if (c->guess < LES_GUESS_ZERO || c->guess > LES_GUESS_LEARNED3)
     return fail(LES_ERR_ARG, "unknown guess mode %d", c->guess);
+  // the guess network addresses a z plane of 16-channel activations with
+  // 32-bit element offsets
+  if ((c->guess == LES_GUESS_LEARNED || c->guess == LES_GUESS_LEARNED3) &&
+      (int64_t)c->nx * c->ny * 16 >= (int64_t)1 << 31)
+    return fail(LES_ERR_ARG, "learned guess: at most 2^27 cells per z plane");
   if (c->mean_mode != LES_MEAN_SWEPT && c->mean_mode != LES_MEAN_LEVEL &&
       c->mean_mode != LES_MEAN_EXACT)
     return fail(LES_ERR_ARG, "unknown mean mode %d", c->mean_mode);
@@ -1078,14 +1083,15 @@ int cnn_guess(les_handle *h, View<T> &V, const T *rhs, const T *base, T *guess) 
   const int ci = cnn_inputs_of(&h->cfg);
   launch_cnn_residual<T>(g, rhs, base, r, V.partials, s);
   launch_cnn_scale(V.partials, (double)g.n, D, sc, s);
-  if (ci == 3)
-    launch_cnn_input3<T>(g, r, base, rhs, sc, D, a0, s);
-  else
-    launch_cnn_round(g.n, 1, g.n, r, sc + 1, a0, s);
   // one periodic field: batch 1, (nz, ny, nx)
   auto geom = [&](int l) { return cnn_geom(1, g.nz, g.ny, g.nx, 1, l, ci); };
-  launch_cnn_conv(0, geom(0), a0, params, packed, h->cnn_alpha, act[0], nullptr, s);
-  launch_cnn_conv(1, geom(1), act[0], params, packed, h->cnn_alpha, act[1], nullptr, s);
+  if (ci == 3) {
+    launch_cnn_input3<T>(g, r, base, rhs, sc, D, a0, s);
+    launch_cnn_conv(0, geom(0), a0, params, packed, h->cnn_alpha, act[0], nullptr, s);
+    launch_cnn_conv(1, geom(1), act[0], params, packed, h->cnn_alpha, act[1], nullptr, s);
+  } else {  // the input r / s is rounded inside the fused first two layers
+    launch_cnn_in_mid(geom(1), r, sc + 1, params, packed, h->cnn_alpha, act[1], s);
+  }
   launch_cnn_conv(2, geom(2), act[1], params, packed, h->cnn_alpha, act[0], nullptr, s);
   launch_cnn_guess<T>(geom(3), act[0], params, packed, base, sc + 2, guess, s);
   LAUNCH_TRY();

@@ -54,8 +54,11 @@ def _np(t):
     return t.detach().cpu().double().numpy()
 
 
+# z spans several 16-level chunks of the tiled layers, with a one-level and
+# a four-level last chunk
 @pytest.mark.parametrize("periodic,shape", [(False, (2, 6, 21, 19)), (True, (1, 5, 12, 40)),
-                                            (False, (1, 3, 11, 11))])
+                                            (False, (1, 3, 11, 11)), (True, (1, 33, 9, 70)),
+                                            (False, (2, 20, 12, 14))])
 def test_forward_matches_oracle(gpu, periodic, shape):
     from oracle import cnn as ocnn
     p = params(1)
@@ -223,18 +226,21 @@ def test_pair_and_gather(gpu, oracle_lib):
         assert np.array_equal(_np(tb)[b], Tn[pp][:, jj][:, :, ii])
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_learned_guess_matches_oracle(gpu, oracle_lib, precision):
+# (nz, ny, nx): one z chunk of the tiled layers and a partial x tile; three
+# z chunks (the last of five levels), partial x and y tiles
+@pytest.mark.parametrize("precision,shape", [("fp32", (16, 24, 32)), ("fp64", (16, 24, 32)),
+                                             ("fp32", (37, 10, 70))])
+def test_learned_guess_matches_oracle(gpu, oracle_lib, precision, shape):
     """The guess of a bound network on a whole periodic field: residual,
     scale, network and combination against the oracle."""
     import torch
     from oracle import cnn as ocnn
     from paper_2301_04698_amd import les
-    p = li.workload("C1", nx=32, ny=24, nz=16, precision=precision, guess="learned")
+    p = li.workload("C1", nx=shape[2], ny=shape[1], nz=shape[0], precision=precision,
+                    guess="learned")
     sim = les.LES(p)
     prm = params(14, bias=0.05)
     gpu.bind(sim, _t(prm), alpha=0.1)
-    shape = (16, 24, 32)
     dt = torch.float32 if precision == "fp32" else torch.float64
     rhs = li.random_field(shape, seed=15)
     base = li.random_field(shape, seed=16) * 30.0
@@ -293,7 +299,8 @@ def params3(seed, bias=0.2):
     return p
 
 
-@pytest.mark.parametrize("periodic,shape", [(False, (2, 3, 6, 21, 19)), (True, (1, 3, 5, 12, 40))])
+@pytest.mark.parametrize("periodic,shape", [(False, (2, 3, 6, 21, 19)), (True, (1, 3, 5, 12, 40)),
+                                            (True, (1, 3, 17, 6, 66))])
 def test_forward_three_inputs_matches_oracle(gpu, periodic, shape):
     from oracle import cnn as ocnn
     p = params3(21)

@@ -42,12 +42,16 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-// FP32 -> bfloat16, round to nearest, ties to even (finite values): add
-// 0x7FFF plus the lowest kept bit, then truncate to the high half.
+// FP32 -> bfloat16, round to nearest, ties to even: the conversion
+// instruction of gfx950 (v_cvt_pk_bf16_f32, two values per instruction).
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float floatx2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  return __builtin_bit_cast(uint16_t, (__bf16)f);
+}
+// bf16(a) in the low half, bf16(b) in the high half.
+__device__ __forceinline__ uint32_t f2bf2(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(floatx2_t{a, b}, bf16x2_t));
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ float leaky(float v, float alpha) { return v >= 0.f ? v : alpha * v; }
@@ -361,10 +365,10 @@ __global__ __launch_bounds__(256, 2) void conv_mid_kernel(
       acc = mfma32(w0a[0], __builtin_bit_cast(bf16x8, v0), acc);
       acc = mfma32(w0a[1], __builtin_bit_cast(bf16x8, v1), acc);
       if (cell < kCnnPlane) {
-        const uint32_t l2 = (uint32_t)f2bf(leaky(acc[0] + b0q[0], alpha)) |
-                            ((uint32_t)f2bf(leaky(acc[1] + b0q[1], alpha)) << 16);
-        const uint32_t h2 = (uint32_t)f2bf(leaky(acc[2] + b0q[2], alpha)) |
-                            ((uint32_t)f2bf(leaky(acc[3] + b0q[3], alpha)) << 16);
+        const uint32_t l2 = f2bf2(leaky(acc[0] + b0q[0], alpha),
+                                  leaky(acc[1] + b0q[1], alpha));
+        const uint32_t h2 = f2bf2(leaky(acc[2] + b0q[2], alpha),
+                                  leaky(acc[3] + b0q[3], alpha));
         *(uint2 *)(dst + cell * kCnnCellB + 8 * quad) = make_uint2(l2, h2);
       }
     }
@@ -449,10 +453,10 @@ __global__ __launch_bounds__(256, 2) void conv_mid_kernel(
       for (int c = 0; c < 4; ++c) {
         const int ox = T.ox0 + 16 * c + row;
         if (ox < G.nxo) {
-          const uint32_t l2 = (uint32_t)f2bf(leaky(lo[c][0] + bq[0], alpha)) |
-                              ((uint32_t)f2bf(leaky(lo[c][1] + bq[1], alpha)) << 16);
-          const uint32_t h2 = (uint32_t)f2bf(leaky(lo[c][2] + bq[2], alpha)) |
-                              ((uint32_t)f2bf(leaky(lo[c][3] + bq[3], alpha)) << 16);
+          const uint32_t l2 = f2bf2(leaky(lo[c][0] + bq[0], alpha),
+                                    leaky(lo[c][1] + bq[1], alpha));
+          const uint32_t h2 = f2bf2(leaky(lo[c][2] + bq[2], alpha),
+                                    leaky(lo[c][3] + bq[3], alpha));
           const int64_t q = (((int64_t)T.b * G.nz + o) * G.nyo + oy) * G.nxo + ox;
           *(uint2 *)(aout + q * kCnnCh + 4 * quad) = make_uint2(l2, h2);
         }
@@ -569,10 +573,10 @@ __global__ __launch_bounds__(256) void conv_in_kernel(CnnGeom G, const uint16_t 
       }
       const int ox = T.ox0 + 16 * t4 + row;
       if (oy < G.nyo && ox < G.nxo) {
-        const uint32_t lo = (uint32_t)f2bf(leaky(acc[0] + bq[0], alpha)) |
-                            ((uint32_t)f2bf(leaky(acc[1] + bq[1], alpha)) << 16);
-        const uint32_t hi = (uint32_t)f2bf(leaky(acc[2] + bq[2], alpha)) |
-                            ((uint32_t)f2bf(leaky(acc[3] + bq[3], alpha)) << 16);
+        const uint32_t lo = f2bf2(leaky(acc[0] + bq[0], alpha),
+                                  leaky(acc[1] + bq[1], alpha));
+        const uint32_t hi = f2bf2(leaky(acc[2] + bq[2], alpha),
+                                  leaky(acc[3] + bq[3], alpha));
         const int64_t q = (((int64_t)T.b * G.nz + k) * G.nyo + oy) * G.nxo + ox;
         *(uint2 *)(aout + q * kCnnCh + 4 * quad) = make_uint2(lo, hi);
       }
@@ -654,6 +658,14 @@ __global__ __launch_bounds__(256) void conv_out_kernel(CnnGeom G, const uint16_t
   auto plane = [&](auto phase, int p) __attribute__((always_inline)) {
     constexpr int F = decltype(phase)::value;
     const unsigned char *cur = lds[(p - Tl.k0 + 1) & 1];
+    // the lane's output cell of level p - 1 (finished by this plane); its
+    // base value is loaded before the products
+    const int o = p - 1, ox = Tl.ox0 + lane;
+    const bool emit = o >= Tl.k0 && oy < G.nyo && ox < G.nxo;
+    const int64_t q = (((int64_t)Tl.b * G.nz + (emit ? o : 0)) * G.nyo + (emit ? oy : 0)) * G.nxo +
+                      (emit ? ox : 0);
+    T bval = T(0);
+    if (GUESS && emit) bval = base[q];
 #pragma unroll
     for (int m = 0; m < kCnnPairs; ++m)
 #pragma unroll
@@ -676,12 +688,10 @@ __global__ __launch_bounds__(256) void conv_out_kernel(CnnGeom G, const uint16_t
       }
     }
     __builtin_amdgcn_wave_barrier();
-    const int o = p - 1, ox = Tl.ox0 + lane;
-    if (o >= Tl.k0 && oy < G.nyo && ox < G.nxo) {
+    if (emit) {
       const float out = res[wv][lane] + b3;
-      const int64_t q = (((int64_t)Tl.b * G.nz + o) * G.nyo + oy) * G.nxo + ox;
       if (GUESS)
-        guess[q] = (T)((double)base[q] + sd * (double)out);
+        guess[q] = (T)((double)bval + sd * (double)out);
       else
         y[q] = out;
     }
@@ -905,28 +915,39 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(int n, float *__restrict__
 
 // ------------------------------------------------- inputs and datasets
 
-template <typename T>
+template <typename T, bool BASE>
 __global__ __launch_bounds__(kBlock) void residual_kernel(Grid g, double ix2, double iy2,
                                                           double iz2, const T *__restrict__ rhs,
                                                           const T *__restrict__ base,
                                                           float *__restrict__ r,
                                                           double *__restrict__ partials) {
   double acc = 0.0;
-  // block b takes the x rows b, b + gridDim.x, ..., four at a time (rows
-  // past the end repeat the last row and are not counted) so that their
-  // loads are in flight together; level and y index uniform over the block
-  const int64_t rows = (int64_t)g.ny * g.nz, stride = gridDim.x;
+  // each block takes a run of x rows (xcd_rows), four at a time so that
+  // their loads are in flight together (rows past the run repeat its first
+  // row and are not counted); level and y index uniform over the block
+  const int64_t rows = (int64_t)g.ny * g.nz;
   constexpr int R = 4;
-  for (int64_t r0 = blockIdx.x; r0 < rows; r0 += R * stride) {
+  const RowRange rr = xcd_rows(rows);
+  // (level, y row) of row r0 + u, stepped without divisions
+  const RowStep rs(g.ny, 1);
+  RowPos p0 = rs.at(rr.r0);
+  for (int64_t r0 = rr.r0; r0 < rr.r1; r0 += R) {
+    RowPos pu[R];
+    pu[0] = p0;
+#pragma unroll
+    for (int u = 1; u < R; ++u) pu[u] = rs.next(pu[u - 1]);
+    p0 = rs.next(pu[R - 1]);
     for (int i = threadIdx.x; i < g.nx; i += blockDim.x) {
       const int ip = i + 1 < g.nx ? i + 1 : 0, im = i > 0 ? i - 1 : g.nx - 1;
       double rv[R];
 #pragma unroll
       for (int u = 0; u < R; ++u) {
-        const int64_t row = min(r0 + u * stride, rows - 1);
-        const int k = (int)(row / g.ny), j = (int)(row - (int64_t)k * g.ny);
+        const bool in = r0 + u < rr.r1;
+        const int64_t row = in ? r0 + u : r0;
+        const RowPos q = in ? pu[u] : pu[0];
+        const int k = q.k, j = q.j;
         double v = (double)rhs[row * g.nx + i];
-        if (base) {
+        if constexpr (BASE) {
           const T *c0 = base + row * g.nx;
           const T *yp = base + ((int64_t)k * g.ny + pwrap(j + 1, g.ny)) * g.nx;
           const T *ym = base + ((int64_t)k * g.ny + pwrap(j - 1, g.ny)) * g.nx;
@@ -942,8 +963,8 @@ __global__ __launch_bounds__(kBlock) void residual_kernel(Grid g, double ix2, do
       }
 #pragma unroll
       for (int u = 0; u < R; ++u) {
-        const int64_t row = r0 + u * stride;
-        if (row < rows) {
+        const int64_t row = r0 + u;
+        if (row < rr.r1) {
           r[row * g.nx + i] = (float)rv[u];
           acc += rv[u] * rv[u];
         }
@@ -1193,8 +1214,13 @@ void launch_cnn_adam(int n, float *params, const float *grad, float *m, float *v
 template <typename T>
 void launch_cnn_residual(const Grid &g, const T *rhs, const T *base, float *r, double *partials,
                          hipStream_t s) {
-  residual_kernel<T><<<kReduceBlocks, kBlock, 0, s>>>(g, 1.0 / (g.dx * g.dx), 1.0 / (g.dy * g.dy),
-                                                      1.0 / (g.dz * g.dz), rhs, base, r, partials);
+  const double ix2 = 1.0 / (g.dx * g.dx), iy2 = 1.0 / (g.dy * g.dy), iz2 = 1.0 / (g.dz * g.dz);
+  if (base)
+    residual_kernel<T, true><<<kReduceBlocks, kBlock, 0, s>>>(g, ix2, iy2, iz2, rhs, base, r,
+                                                              partials);
+  else
+    residual_kernel<T, false><<<kReduceBlocks, kBlock, 0, s>>>(g, ix2, iy2, iz2, rhs, base, r,
+                                                               partials);
 }
 
 void launch_cnn_scale(const double *partials, double n, double d, double *sc, hipStream_t s) {

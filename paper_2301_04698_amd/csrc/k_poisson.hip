@@ -491,8 +491,9 @@ __global__ __launch_bounds__(1024) void final_kernel(const double *__restrict__ 
 // compact Laplacian, periodic x, y and mirror z.  rhs_d nullable (only the
 // sums: the residual of a returned iterate); rhs_d may alias rhs.  With
 // `when`, only if when->guess_kept (and then the partial sums are not
-// written either).
-template <typename T>
+// written either).  GBAR, GV: gbar, gv are given (compile-time, so that
+// the loads of several rows are in flight together).
+template <typename T, bool GBAR, bool GV>
 __global__ __launch_bounds__(kBlock) void guess_residual_kernel(Grid g, double ix2, double iy2,
                                                                 double iz2, const T *rhs,
                                                                 const T *__restrict__ phi0,
@@ -503,20 +504,31 @@ __global__ __launch_bounds__(kBlock) void guess_residual_kernel(Grid g, double i
                                                                 const SolveCtl *__restrict__ when) {
   if (when && !when->guess_kept) return;
   double rr = 0.0, bb = 0.0;
-  // block b takes the x rows b, b + gridDim.x, ..., four at a time (rows
-  // past the end repeat the last row and are not counted) so that their
-  // loads are in flight together; a row's level and y index (and its
-  // neighbour rows) are uniform over the block
-  const int64_t rows = (int64_t)g.ny * g.nz, stride = gridDim.x;
+  // each block takes a run of x rows (xcd_rows), four at a time so that
+  // their loads are in flight together (rows past the run repeat its first
+  // row and are not counted); a row's level and y index (and its neighbour
+  // rows) are uniform over the block
+  const int64_t rows = (int64_t)g.ny * g.nz;
   constexpr int R = 4;
-  for (int64_t r0 = blockIdx.x; r0 < rows; r0 += R * stride) {
+  const RowRange run = xcd_rows(rows);
+  // (level, y row) of row r0 + u, stepped without divisions
+  const RowStep rs(g.ny, 1);
+  RowPos p0 = rs.at(run.r0);
+  for (int64_t r0 = run.r0; r0 < run.r1; r0 += R) {
+    RowPos pu[R];
+    pu[0] = p0;
+#pragma unroll
+    for (int u = 1; u < R; ++u) pu[u] = rs.next(pu[u - 1]);
+    p0 = rs.next(pu[R - 1]);
     for (int i = threadIdx.x; i < g.nx; i += blockDim.x) {
       const int ip = i + 1 < g.nx ? i + 1 : 0, im = i > 0 ? i - 1 : g.nx - 1;
       double dv[R], bv[R];
 #pragma unroll
       for (int u = 0; u < R; ++u) {
-        const int64_t row = min(r0 + u * stride, rows - 1);
-        const int k = (int)(row / g.ny), j = (int)(row - (int64_t)k * g.ny);
+        const bool in = r0 + u < run.r1;
+        const int64_t row = in ? r0 + u : r0;
+        const RowPos q = in ? pu[u] : pu[0];
+        const int k = q.k, j = q.j;
         const int jp = pwrap(j + 1, g.ny), jm = pwrap(j - 1, g.ny);
         const int kp = zmirror(k + 1, g.nz), km = zmirror(k - 1, g.nz);
         const T *c0 = phi0 + row * g.nx;
@@ -524,13 +536,13 @@ __global__ __launch_bounds__(kBlock) void guess_residual_kernel(Grid g, double i
         const T *ym = phi0 + ((int64_t)k * g.ny + jm) * g.nx;
         const T *zp = phi0 + ((int64_t)kp * g.ny + j) * g.nx;
         const T *zm = phi0 + ((int64_t)km * g.ny + j) * g.nx;
-        const double gz = gbar ? (gbar[kp] - 2.0 * gbar[k] + gbar[km]) * iz2 : 0.0;
+        const double gz = GBAR ? (gbar[kp] - 2.0 * gbar[k] + gbar[km]) * iz2 : 0.0;
         const double c = c0[i];
         double lap = ((double)c0[ip] + (double)c0[im] - 2.0 * c) * ix2 +
                      ((double)yp[i] + (double)ym[i] - 2.0 * c) * iy2 +
                      ((double)zp[i] + (double)zm[i] - 2.0 * c) * iz2;
         lap -= gz;
-        if (gv) {  // the x-y second differences of the guess's column means
+        if constexpr (GV) {  // the x-y second differences of the guess's column means
           const double gc = gv[(int64_t)i + g.sy * j];
           lap -= (gv[ip + g.sy * j] + gv[im + g.sy * j] - 2.0 * gc) * ix2 +
                  (gv[i + g.sy * jp] + gv[i + g.sy * jm] - 2.0 * gc) * iy2;
@@ -540,8 +552,8 @@ __global__ __launch_bounds__(kBlock) void guess_residual_kernel(Grid g, double i
       }
 #pragma unroll
       for (int u = 0; u < R; ++u) {
-        const int64_t row = r0 + u * stride;
-        if (row < rows) {
+        const int64_t row = r0 + u;
+        if (row < run.r1) {
           if (rhs_d) rhs_d[row * g.nx + i] = (T)dv[u];
           rr += dv[u] * dv[u];
           bb += bv[u] * bv[u];
@@ -759,31 +771,42 @@ void launch_extrapolate(const Grid &g, const Profiles<T> &P, const T *p, const T
 constexpr int kResidualBlocks = 4096;
 static_assert(2 * kResidualBlocks <= kPartials, "residual partials exceed the buffer");
 
+// guess_residual_kernel with its GBAR, GV variant picked from gbar, gv.
+template <typename T>
+void launch_residual_pass(const Grid &g, const T *rhs, const T *phi0, const double *gbar,
+                          const double *gv, T *rhs_d, double *partials, const SolveCtl *when,
+                          hipStream_t s) {
+  const double ix2 = 1.0 / (g.dx * g.dx), iy2 = 1.0 / (g.dy * g.dy), iz2 = 1.0 / (g.dz * g.dz);
+#define LES_RES(GB, GV)                                                            \
+  guess_residual_kernel<T, GB, GV><<<kResidualBlocks, kBlock, 0, s>>>(g, ix2, iy2, iz2, rhs, \
+                                                                      phi0, gbar, gv, rhs_d, \
+                                                                      partials, when)
+  if (gbar && gv) LES_RES(true, true);
+  else if (gbar) LES_RES(true, false);
+  else if (gv) LES_RES(false, true);
+  else LES_RES(false, false);
+#undef LES_RES
+}
+
 template <typename T>
 void launch_guess_gate(const Grid &g, const T *rhs, const T *phi0, const double *gbar,
                        const double *gv, T *rhs_d, double *partials, SolveCtl *ctl,
                        int always_keep, hipStream_t s) {
-  const double ix2 = 1.0 / (g.dx * g.dx), iy2 = 1.0 / (g.dy * g.dy), iz2 = 1.0 / (g.dz * g.dz);
   if (rhs != rhs_d) {
-    guess_residual_kernel<T><<<kResidualBlocks, kBlock, 0, s>>>(g, ix2, iy2, iz2, rhs, phi0, gbar,
-                                                              gv, rhs_d, partials, nullptr);
+    launch_residual_pass<T>(g, rhs, phi0, gbar, gv, rhs_d, partials, nullptr, s);
     guess_gate_kernel<<<1, 1024, 0, s>>>(partials, kResidualBlocks, always_keep, ctl);
     guess_clear_kernel<T><<<blocks_for(g.n), kBlock, 0, s>>>(g.n, ctl, rhs, rhs_d);
   } else {  // in place: the sums, the gate, then the defect if the guess is kept
-    guess_residual_kernel<T><<<kResidualBlocks, kBlock, 0, s>>>(g, ix2, iy2, iz2, rhs, phi0, gbar,
-                                                              gv, nullptr, partials, nullptr);
+    launch_residual_pass<T>(g, rhs, phi0, gbar, gv, nullptr, partials, nullptr, s);
     guess_gate_kernel<<<1, 1024, 0, s>>>(partials, kResidualBlocks, always_keep, ctl);
-    guess_residual_kernel<T><<<kResidualBlocks, kBlock, 0, s>>>(g, ix2, iy2, iz2, rhs, phi0, gbar,
-                                                              gv, rhs_d, partials, ctl);
+    launch_residual_pass<T>(g, rhs, phi0, gbar, gv, rhs_d, partials, ctl, s);
   }
 }
 
 template <typename T>
 void launch_returned_residual(const Grid &g, const T *rhs, const T *phi, double *partials,
                               SolveCtl *ctl, hipStream_t s) {
-  guess_residual_kernel<T><<<kResidualBlocks, kBlock, 0, s>>>(
-      g, 1.0 / (g.dx * g.dx), 1.0 / (g.dy * g.dy), 1.0 / (g.dz * g.dz), rhs, phi, nullptr,
-      nullptr, nullptr, partials, nullptr);
+  launch_residual_pass<T>(g, rhs, phi, nullptr, nullptr, nullptr, partials, nullptr, s);
   final_kernel<<<1, 1024, 0, s>>>(partials, kResidualBlocks, kFinalReturned, ctl, 0.0, 0.0, 0,
                                   nullptr);
 }

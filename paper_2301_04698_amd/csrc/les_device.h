@@ -34,6 +34,52 @@ __device__ __forceinline__ T pload(const T *__restrict__ a, int k, int nz) {
   return a[zmirror(k, nz)];
 }
 
+// Rows of a row-wise pass over a grid of a multiple of 8 blocks: XCD x
+// (the blocks b with b % 8 = x) takes the x-th contiguous eighth of the
+// rows and each of its blocks a consecutive run of them, so that the rows
+// beside a row (y +- 1 in the same run, z +- 1 one level of rows away) are
+// read on one XCD close in time and come from its L2.
+struct RowRange {
+  int64_t r0, r1;
+};
+__device__ __forceinline__ RowRange xcd_rows(int64_t rows) {
+  const int64_t per = gridDim.x >> 3, rpx = (rows + 7) / 8, rpb = (rpx + per - 1) / per;
+  const int64_t x = blockIdx.x & 7, lb = blockIdx.x >> 3;
+  const int64_t lo = x * rpx + lb * rpb;
+  RowRange r;
+  r.r0 = lo < rows ? lo : rows;
+  r.r1 = min(min(lo + rpb, (x + 1) * rpx), rows);
+  if (r.r1 < r.r0) r.r1 = r.r0;
+  return r;
+}
+
+// Level k and y row j of the x row r = k ny + j, and stepping r by a
+// fixed stride without divisions (the stride's quotient and remainder by
+// ny are formed once).
+struct RowPos {
+  int k, j;
+};
+struct RowStep {
+  int ny, sk, sj;
+  __device__ __forceinline__ RowStep(int ny_, int64_t stride)
+      : ny(ny_), sk((int)(stride / ny_)), sj((int)(stride - (stride / ny_) * ny_)) {}
+  __device__ __forceinline__ RowPos at(int64_t r) const {
+    RowPos p;
+    p.k = (int)(r / ny);
+    p.j = (int)(r - (int64_t)p.k * ny);
+    return p;
+  }
+  __device__ __forceinline__ RowPos next(RowPos p) const {
+    p.k += sk;
+    p.j += sj;
+    if (p.j >= ny) {
+      p.j -= ny;
+      ++p.k;
+    }
+    return p;
+  }
+};
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -3,8 +3,11 @@
 // prediction equation) on the collocated grid.  Column-marching kernels
 // (one lane per column, a chunk of levels per wave); the stencil
 // neighbourhoods are served by the L1/L2 caches.
+#include <type_traits>
+
 #include "les.h"
 #include "les_column.h"
+#include "les_tile.h"
 
 namespace lesmi {
 
@@ -69,54 +72,94 @@ __device__ __forceinline__ T dcentral(const T *__restrict__ f, const L &at, cons
 // nu_t = (c_s Delta)^2 f_B S with S = sqrt(2 S_ij S_ij) and the buoyancy
 // factor f_B = sqrt(clamp(1 - N^2/(Pr S^2), 0, 1)), N^2 = db/dz (central);
 // or the uniform viscosity of the validation cases (Sec. 3) when set.
-template <typename T, bool FS, bool EDGE>
-__device__ __forceinline__ void sgs_nu_level(const Grid &g, const Dyn<T> &d, const ColPts<T> &pts,
-                                             int k, bool active, const T *__restrict__ u,
-                                             const T *__restrict__ v, const T *__restrict__ w,
-                                             const T *__restrict__ b, T *__restrict__ nu) {
-  const Lvl<T, EDGE> at(g, pts, k);
-  const T *vel[3] = {u, v, w};
-  T G[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int e = 0; e < 3; ++e) G[a][e] = dcentral<T, FS>(vel[a], at, d, a, e, 0, 0, 0);
-  T s2 = T(0);
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-      const T sij = T(0.5) * (G[a][e] + G[e][a]);
-      s2 += T(2) * sij * sij;
-    }
-  const T n2 = (at(b, 0, 0, 1, T(1)) - at(b, 0, 0, -1, T(1))) * d.inv_2dz;
-  T val = T(0);
-  if (s2 > T(0)) {
-    T r = T(1) - n2 / (d.pr * s2);
-    r = r < T(0) ? T(0) : (r > T(1) ? T(1) : r);
-    val = d.smag_l2 * sqrt(s2) * sqrt(r);
-  }
-  at.store(nu, val, active);
-}
-
+// Tiled z march (les_tile.h): the x and y differences of u, v, w from their
+// LDS planes, the z differences (and N^2) from the column's values below
+// and above carried in registers.
 template <typename T, bool FS>
-__global__ __launch_bounds__(kBlock) void sgs_nu_kernel(Grid g, ColMap m, Dyn<T> d,
-                                                        const T *__restrict__ u,
-                                                        const T *__restrict__ v,
-                                                        const T *__restrict__ w,
-                                                        const T *__restrict__ b,
-                                                        T *__restrict__ nu) {
-  const ColWave c = col_wave(g, m);
-  if (!c.valid) return;
-  const ColPts<T> pts = col_pts<T>(g, c.i, c.j);
-  for (int k = c.k0; k < c.k1; ++k) {
-    if (d.nu_const > T(0)) {
-      Lvl<T, false>(g, pts, k).store(nu, d.nu_const, c.active);
-    } else if (k >= 2 && k + 2 < g.nz) {
-      sgs_nu_level<T, FS, false>(g, d, pts, k, c.active, u, v, w, b, nu);
-    } else {
-      sgs_nu_level<T, FS, true>(g, d, pts, k, c.active, u, v, w, b, nu);
+__global__ __launch_bounds__(kTileThreads) void sgs_nu_kernel(Grid g, TileMap m, Dyn<T> d,
+                                                              const T *__restrict__ u,
+                                                              const T *__restrict__ v,
+                                                              const T *__restrict__ w,
+                                                              const T *__restrict__ b,
+                                                              T *__restrict__ nu) {
+  __shared__ TilePlane<T, 1, 1> pl[2][3];  // u, v, w at the level, two slots
+  const Tile tl = tile_of(g, m);
+  if (!tl.valid) return;
+  const TileCol c = tile_col(g, tl);
+  if (d.nu_const > T(0)) {
+    for (int k = tl.k0; k < tl.k1; ++k)
+      if (c.active) nu[(int64_t)k * g.nxy + c.off] = d.nu_const;
+    return;
+  }
+  const RingCells<1, 1> rc = ring_cells<1, 1>(g, tl);
+  constexpr int PER = RingCells<1, 1>::PER;
+  const T *const fld[4] = {u, v, w, b};
+  const T fpar[4] = {vpar<T, FS>(0), vpar<T, FS>(1), vpar<T, FS>(2), T(1)};
+  // Loads run ahead of the march in register FIFOs of depth D indexed by
+  // the level's place i = k - k0 in the chunk: the ring cells of level k in
+  // slot i % D (fetched D levels ahead), the column's u, v, w, b at level k
+  // in slot (i + 1) % D (levels k - 1 .. k + D - 2 held; fetched D - 1
+  // levels ahead, up to level k1, the last one the march reads).
+  constexpr int D = kTileDepth;
+  T hq[D][3][PER], zq[D][4];
+  auto fetch_ring = [&](T(&h)[3][PER], int kk) __attribute__((always_inline)) {
+    if (kk < tl.k1) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+          if (rc.dst[q] >= 0) h[a][q] = fld[a][(int64_t)kk * g.nxy + rc.src[q]];
     }
+  };
+  auto fetch_col = [&](T(&z)[4], int kk) __attribute__((always_inline)) {
+    kk = min(kk, tl.k1);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) z[f] = col_value(g, fld[f], c.off, kk, fpar[f]);
+  };
+#pragma unroll
+  for (int s = 0; s < D; ++s) {
+    fetch_ring(hq[s], tl.k0 + s);
+    fetch_col(zq[s], tl.k0 - 1 + s);
+  }
+  const int x = c.lx + 1, y = c.ly + 1;
+  // level k = k0 + i, i = PH (mod 4)
+  auto level = [&](auto ph, int k) __attribute__((always_inline)) {
+    constexpr int PH = decltype(ph)::value;
+    T(&zm)[4] = zq[PH];
+    T(&z0)[4] = zq[(PH + 1) % D];
+    T(&zp)[4] = zq[(PH + 2) % D];
+    TilePlane<T, 1, 1> *P = pl[PH & 1];
+    // this slot was last read two levels ago, before the last barrier
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      P[a].v[y][x] = z0[a];
+#pragma unroll
+      for (int q = 0; q < PER; ++q)
+        if (rc.dst[q] >= 0) (&P[a].v[0][0])[rc.dst[q]] = hq[PH][a][q];
+    }
+    fetch_ring(hq[PH], k + D);
+    __syncthreads();
+    T G[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      G[a][0] = (P[a].v[y][x + 1] - P[a].v[y][x - 1]) * d.inv_2dx;
+      G[a][1] = (P[a].v[y + 1][x] - P[a].v[y - 1][x]) * d.inv_2dy;
+      G[a][2] = (zp[a] - zm[a]) * d.inv_2dz;
+    }
+    // S^2 = 2 S_ij S_ij: the diagonal terms plus the three distinct
+    // off-diagonal pairs (S_ij = S_ji)
+    const T o01 = G[0][1] + G[1][0], o02 = G[0][2] + G[2][0], o12 = G[1][2] + G[2][1];
+    const T s2 = T(2) * (G[0][0] * G[0][0] + G[1][1] * G[1][1] + G[2][2] * G[2][2]) +
+                 (o01 * o01 + o02 * o02 + o12 * o12);
+    const T n2 = (zp[3] - zm[3]) * d.inv_2dz;
+    // S^2 f_B^2 = S^2 clamp(1 - N^2/(Pr S^2), 0, 1) = clamp(S^2 - N^2/Pr, 0, S^2)
+    T e2 = s2 - n2 * d.inv_pr;
+    e2 = e2 < T(0) ? T(0) : (e2 > s2 ? s2 : e2);
+    const T val = d.smag_l2 * sqrt(e2);
+    if (c.active) nu[(int64_t)k * g.nxy + c.off] = val;
+    fetch_col(zq[PH], k - 1 + D);  // the slot of level k - 1, used for the last time
+  };
+  for (int k = tl.k0; march_trip(level, k, tl.k1, std::make_integer_sequence<int, D>{}); k += D) {
   }
 }
 
@@ -407,11 +450,11 @@ __global__ __launch_bounds__(kBlock) void momentum_kernel(
 template <typename T>
 void launch_sgs_nu(const Grid &g, const Dyn<T> &d, const T *u, const T *v, const T *w, const T *b,
                    T *nu, hipStream_t s) {
-  const ColMap m = col_map(g);
+  const TileMap m = tile_map(g);
   if (d.uv_par > T(0))
-    sgs_nu_kernel<T, true><<<m.blocks, kBlock, 0, s>>>(g, m, d, u, v, w, b, nu);
+    sgs_nu_kernel<T, true><<<m.blocks, kTileThreads, 0, s>>>(g, m, d, u, v, w, b, nu);
   else
-    sgs_nu_kernel<T, false><<<m.blocks, kBlock, 0, s>>>(g, m, d, u, v, w, b, nu);
+    sgs_nu_kernel<T, false><<<m.blocks, kTileThreads, 0, s>>>(g, m, d, u, v, w, b, nu);
 }
 
 template <typename T>

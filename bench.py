@@ -78,6 +78,9 @@ def parse():
     ap.add_argument("--guess-weights", default=GUESS_WEIGHTS,
                     help="trained guess network for the learned form ('' to skip it)")
     ap.add_argument("--guess-alpha", type=float, default=0.1)
+    ap.add_argument("--guess-passes", type=int, default=2,
+                    help="network passes per guessed solve in the learned form (each pass "
+                         "after the first corrects the last one's guess from its residual)")
     ap.add_argument("--c5-warmup", type=int, default=3,
                     help="largest-domain leg (1024x1024x256): untimed steps from the initial "
                          "state (learned form; its first step starts from zero)")
@@ -266,7 +269,7 @@ def learned_form(p, args, plain_sweeps, plain_poisson, plain_value):
     import les_inputs as li
     from paper_2301_04698_amd import cnn, les
 
-    pl = dict(p, guess="learned")
+    pl = dict(p, guess="learned", guess_passes=args.guess_passes)
     sim = les.LES(pl, li.initial_state(pl), device="cuda:0")
     cnn.bind(sim, torch.from_numpy(np.load(args.guess_weights)), args.guess_alpha)
     if args.warmup > 0:
@@ -297,9 +300,12 @@ def learned_form(p, args, plain_sweeps, plain_poisson, plain_value):
         "not_converged": st["not_converged"],
         "res_rel_max": st["res_rel_max"],
         "weights": os.path.relpath(args.guess_weights, ROOT),
+        "guess_passes": args.guess_passes,
         "note": ("each solve after the first step starts from the previous step's solution of the "
-                 "same sub-iteration plus the network's correction; the network's inference time "
-                 "is inside poisson_s_per_step; same residual test as the plain form"),
+                 "same sub-iteration plus the network's correction (guess_passes passes, each "
+                 "after the first correcting the last one's guess from its residual); the "
+                 "network's inference time is inside poisson_s_per_step; same residual test as "
+                 "the plain form"),
     }
 
 
@@ -348,7 +354,8 @@ def largest_domain(args):
         }, st
 
     t0 = time.perf_counter()
-    sim = les.LES(dict(p, guess="learned"), li.initial_state(p), device="cuda:0")
+    sim = les.LES(dict(p, guess="learned", guess_passes=args.guess_passes), li.initial_state(p),
+                  device="cuda:0")
     cnn.bind(sim, prm, args.guess_alpha)
     t_init = time.perf_counter() - t0
     progress(f"1024x1024x256: set up in {t_init:.0f} s")
@@ -380,6 +387,7 @@ def largest_domain(args):
     avg = st["sweep_seconds"] / max(st["sweeps_timed"], 1)
     bytes_launch = sweep_bytes_per_cell(p) * ncell
     achieved = bytes_launch / avg / 1e9
+    learned["guess_passes"] = args.guess_passes
     learned["speedup"] = learned["value"] / plain["value"]
     learned["poisson_speedup"] = plain["poisson_s_per_step"] / learned["poisson_s_per_step"]
     learned["iterations_saved_per_step"] = plain["sweeps_per_step"] - learned["sweeps_per_step"]

@@ -143,7 +143,11 @@ typedef struct les_config {
   double T_ice;                 /* LES_PHASE_RAMP: all condensate is ice at
                                    and below T_ice (K), 0 < T_ice < Tf */
   int32_t mean_mode;            /* LES_MEAN_SWEPT, LES_MEAN_LEVEL or LES_MEAN_EXACT */
-  int32_t reserved;             /* 0 */
+  int32_t guess_passes;         /* LES_GUESS_LEARNED: network passes per guessed
+                                   solve, 1..4 (0 means 1); pass 2 onward feeds
+                                   the previous pass's guess back as the base,
+                                   so each pass corrects the residual the last
+                                   one left.  Other guess modes: 0 or 1 */
 } les_config;
 
 /* Caller-owned device buffers.  u, v, w: velocity (m/s); thl: liquid-ice

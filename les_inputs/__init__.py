@@ -77,6 +77,7 @@ _BASE = dict(
     jacobi_omega=0.0,          # 0 selects the closed-form optimum
     sweeps_per_launch=0,       # library launch shape only (0: its default)
     guess="zero",              # initial guess of the solves
+    guess_passes=0,            # learned guess: network passes per solve (0 or 1: one)
     mean_mode="exact",         # parts of each solve solved exactly before the sweeps:
                                # "exact" (the horizontally uniform part, a 1D problem, and
                                # the vertically uniform part, a 2D one), "level" (the 1D

@@ -114,7 +114,9 @@ int validate(const les_config *c) {
   if (c->mean_mode != LES_MEAN_SWEPT && c->mean_mode != LES_MEAN_LEVEL &&
       c->mean_mode != LES_MEAN_EXACT)
     return fail(LES_ERR_ARG, "unknown mean mode %d", c->mean_mode);
-  if (c->reserved != 0) return fail(LES_ERR_ARG, "reserved must be 0");
+  if (c->guess_passes < 0 || c->guess_passes > 4 ||
+      (c->guess_passes > 1 && c->guess != LES_GUESS_LEARNED))
+    return fail(LES_ERR_ARG, "guess_passes must be in [0, 4], above 1 only with LES_GUESS_LEARNED");
   return LES_OK;
 }
 
@@ -853,7 +855,11 @@ int step_impl(les_handle *h, int32_t nsteps, const les_step_opts *opts, les_step
           if (c.guess == LES_GUESS_PREVIOUS) {
             guess = hist;
           } else {
-            const int grc = cnn_guess<T>(h, V, V.f[F_RHS], hist, V.f[F_GUESS]);
+            int grc = cnn_guess<T>(h, V, V.f[F_RHS], hist, V.f[F_GUESS]);
+            // further passes correct the guess from its own residual (in
+            // place: each output cell reads only its own base value)
+            for (int pass = 1; grc == 0 && pass < c.guess_passes; ++pass)
+              grc = cnn_guess<T>(h, V, V.f[F_RHS], V.f[F_GUESS], V.f[F_GUESS]);
             if (grc) return grc;
             guess = V.f[F_GUESS];
           }

@@ -148,12 +148,14 @@ def train(X, T, p, iters=4000, batch=16, crop=32, lr=2e-3, seed=0, alpha=DEFAULT
     return tr.params.detach().clone(), hist
 
 
-def run_mode(p, state, mode, nsteps, params=None, alpha=DEFAULT_ALPHA, device="cuda", pbar=None):
+def run_mode(p, state, mode, nsteps, params=None, alpha=DEFAULT_ALPHA, device="cuda", pbar=None,
+             passes=1):
     """nsteps timed steps after one untimed step (which fills the history)
     from `state` (p relative to the FP64 profile pbar) with the given guess
-    mode; returns per-step figures."""
+    mode (and network passes per solve in the learned form); returns
+    per-step figures."""
     import torch
-    ps = dict(p, guess=mode)
+    ps = dict(p, guess=mode, guess_passes=passes if mode == "learned" else 0)
     sim = les.LES(ps, state, device=device, pbar=pbar)
     if mode in ("learned", "learned3"):
         cnn.bind(sim, params, alpha)
@@ -180,6 +182,7 @@ def run_mode(p, state, mode, nsteps, params=None, alpha=DEFAULT_ALPHA, device="c
     K = p["n_subiter"]
     out = dict(
         mode=mode,
+        passes=passes if mode == "learned" else None,
         ms_per_step=wall / nsteps * 1e3,
         mcell_steps_per_s=p["nx"] * p["ny"] * p["nz"] * nsteps / wall / 1e6,
         poisson_s_per_step=st["poisson_seconds"] / nsteps,
@@ -198,9 +201,10 @@ def run_mode(p, state, mode, nsteps, params=None, alpha=DEFAULT_ALPHA, device="c
 
 def evaluate(p, params, seed, spinup, nsteps, alpha=DEFAULT_ALPHA, modes=("zero", "previous",
                                                                              "learned"),
-             device="cuda"):
+             device="cuda", passes=(1,)):
     """Spin up a held-out run with the plain solver, then run each guess
-    mode from the same state."""
+    mode from the same state (the learned form once per pass count; keys
+    "learned", "learned_2passes", ...)."""
     ps = dict(p, seed=int(seed), guess="zero")
     sim = les.LES(ps, li.initial_state(ps), device=device)
     done = 0
@@ -213,8 +217,11 @@ def evaluate(p, params, seed, spinup, nsteps, alpha=DEFAULT_ALPHA, modes=("zero"
     sim.close()
     res = {}
     for mode in modes:
-        res[mode] = run_mode(ps, state, mode, nsteps, params, alpha, device, pbar=pbar)
-        log(f"evaluate: {json.dumps(res[mode])}")
+        for np_ in (passes if mode == "learned" else (1,)):
+            key = mode if np_ == 1 else f"{mode}_{np_}passes"
+            res[key] = run_mode(ps, state, mode, nsteps, params, alpha, device, pbar=pbar,
+                                passes=np_)
+            log(f"evaluate: {json.dumps(res[key])}")
     return res
 
 
@@ -237,6 +244,9 @@ def main():
     ap.add_argument("--eval-steps", type=int, default=40)
     ap.add_argument("--out", required=True,
                     help="weights file to write (or, with --eval-only, to evaluate)")
+    ap.add_argument("--passes", default="1",
+                    help="network passes per solve evaluated for the one-input network "
+                         "(comma list)")
     ap.add_argument("--eval-only", action="store_true",
                     help="evaluate the weights in --out on the held-out run; write <out>.eval.json")
     ap.add_argument("--no-eval", action="store_true")
@@ -244,12 +254,14 @@ def main():
     import torch
     torch.cuda.set_device(0)
     p = li.workload(a.workload)
+    passes = tuple(int(x) for x in a.passes.split(","))
     modes = ("zero", "previous", "learned") if a.inputs == 1 else ("zero", "extrapolate",
                                                                    "learned3")
     if a.eval_only:
         params = torch.from_numpy(np.load(a.out)).cuda()
         t0 = time.perf_counter()
-        res = evaluate(p, params, a.eval_seed, a.eval_spinup, a.eval_steps, a.alpha, modes)
+        res = evaluate(p, params, a.eval_seed, a.eval_spinup, a.eval_steps, a.alpha, modes,
+                       passes=passes)
         summary = dict(workload=a.workload, weights=os.path.basename(a.out), eval_seed=a.eval_seed,
                        eval_spinup=a.eval_spinup, eval_steps=a.eval_steps,
                        eval_s=time.perf_counter() - t0, eval=res)
@@ -268,7 +280,7 @@ def main():
     del X, T
     np.save(a.out, params.cpu().numpy().astype(np.float32))
     res = None if a.no_eval else evaluate(p, params, a.eval_seed, a.eval_spinup, a.eval_steps,
-                                          a.alpha, modes)
+                                          a.alpha, modes, passes=passes)
     npairs = len(a.seeds.split(",")) * len(a.windows.split(",")) * a.window_len * \
         (p["n_subiter"] if a.inputs == 1 else 1)
     summary = dict(command="python -m paper_2301_04698_amd.guess_train " + " ".join(sys.argv[1:]),

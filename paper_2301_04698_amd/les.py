@@ -64,7 +64,7 @@ class LesConfig(C.Structure):
         ("e_tr", C.c_double), ("T_tr", C.c_double), ("satadj_tol", C.c_double),
         ("guess", C.c_int32), ("advection", C.c_int32),
         ("wall", C.c_int32), ("phase", C.c_int32), ("nu_const", C.c_double),
-        ("T_ice", C.c_double), ("mean_mode", C.c_int32), ("reserved", C.c_int32),
+        ("T_ice", C.c_double), ("mean_mode", C.c_int32), ("guess_passes", C.c_int32),
     ]
 
 
@@ -193,8 +193,8 @@ def make_config(p: dict) -> LesConfig:
         elif name == "mean_mode":
             v = p.get("mean_mode", "exact")
             c.mean_mode = MEAN_MODES[v] if isinstance(v, str) else int(v)
-        elif name == "reserved":
-            c.reserved = 0
+        elif name == "guess_passes":
+            c.guess_passes = int(p.get("guess_passes", 0))
         elif name == "precision":
             v = p.get("precision", "fp64")
             c.precision = {"fp64": LES_FP64, "fp32": LES_FP32}[v] if isinstance(v, str) else int(v)

@@ -76,7 +76,7 @@ def test_make_config_carries_every_parameter(lib, oracle_lib):
         c = lib.make_config(p)
         o = oracle_lib.make_cfg(p)
         for name, _ in oracle_lib.OCfg._fields_:
-            if name != "reserved":
+            if name not in ("reserved", "guess_passes"):
                 assert getattr(c, name) == getattr(o, name), name
         assert c.precision == lib.LES_FP32 and c.poisson_scheme == lib.LES_CHEBYSHEV
 
@@ -85,6 +85,9 @@ def test_make_config_carries_every_parameter(lib, oracle_lib):
     (dict(nz=3), "4 <= nz <= 65535"),
     (dict(nz=65536, nx=2, ny=1), "4 <= nz <= 65535"),
     (dict(mean_mode=5), "mean mode"),
+    (dict(guess="learned", guess_passes=5), "guess_passes"),
+    (dict(guess="previous", guess_passes=2), "guess_passes"),
+    (dict(guess_passes=-1), "guess_passes"),
     (dict(ny=0), "nx must be >= 2, ny >= 1"),
     (dict(nx=1), "nx must be >= 2, ny >= 1"),
     (dict(wall=7), "wall condition"),

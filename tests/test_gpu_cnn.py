@@ -258,6 +258,85 @@ def test_learned_guess_matches_oracle(gpu, oracle_lib, precision, shape):
     assert rel(corr, s_ref / d * out[0]) <= 5e-4
 
 
+def _guess_into(sim, rhs, base, out):
+    """les_cnn_guess writing into `out` (which may be `base` itself)."""
+    import ctypes as C
+    from paper_2301_04698_amd import cnn, les
+    s = C.c_double()
+    les.check(cnn.lib().les_cnn_guess(sim.handle, cnn._ptr(rhs), cnn._ptr(base), cnn._ptr(out),
+                                      C.byref(s)))
+    return s.value
+
+
+def test_guess_in_place_equals_out_of_place(gpu):
+    """A guess written over its own base (the passes after the first do
+    this) equals the guess written elsewhere, bit for bit: each output cell
+    reads only its own base value once the residual pass is done."""
+    import torch
+    from paper_2301_04698_amd import les
+    p = li.workload("C1", nx=70, ny=10, nz=37, precision="fp32", guess="learned")
+    sim = les.LES(p)
+    gpu.bind(sim, _t(params(14, bias=0.05)), alpha=0.1)
+    shape = (37, 10, 70)
+    R = torch.from_numpy(li.random_field(shape, seed=31)).to("cuda", torch.float32)
+    B = torch.from_numpy(li.random_field(shape, seed=32) * 30.0).to("cuda", torch.float32)
+    g, s = gpu.guess(sim, R, B)
+    Bi = B.clone()
+    si = _guess_into(sim, R, Bi, Bi)
+    torch.cuda.synchronize()
+    assert si == s
+    assert torch.equal(Bi, g)
+
+
+def test_second_pass_matches_oracle(gpu, oracle_lib):
+    """A second pass is one pass on the first pass's guess: the network's
+    correction from the residual that guess leaves, against the oracle on
+    the same operands."""
+    import torch
+    from oracle import cnn as ocnn
+    from paper_2301_04698_amd import les
+    shape = (16, 24, 32)
+    p = li.workload("C1", nx=32, ny=24, nz=16, precision="fp64", guess="learned")
+    sim = les.LES(p)
+    prm = params(14, bias=0.05)
+    gpu.bind(sim, _t(prm), alpha=0.1)
+    R = torch.from_numpy(li.random_field(shape, seed=15)).to("cuda", torch.float64)
+    B = torch.from_numpy(li.random_field(shape, seed=16) * 30.0).to("cuda", torch.float64)
+    g1, _ = gpu.guess(sim, R, B)
+    g2, s2 = gpu.guess(sim, R, g1)
+    rb, b1 = _np(R), _np(g1)
+    r = rb - oracle_lib.laplacian(dict(p, guess="zero"), b1)
+    s_ref = np.sqrt(np.mean(r ** 2))
+    assert s2 == pytest.approx(s_ref, rel=1e-6)
+    d = 2 / p["dx"] ** 2 + 2 / p["dy"] ** 2 + 2 / p["dz"] ** 2
+    x = (r.astype(np.float32) / np.float32(1.0)).astype(float) / s_ref
+    out, _, _ = ocnn.forward(prm, x[None], periodic=True, alpha=0.1)
+    assert rel(_np(g2) - b1, s_ref / d * out[0]) <= 5e-4
+
+
+def test_learned_step_two_passes_converges(gpu):
+    """The learned form with two network passes per solve stops every solve
+    at the tolerance and stays within tolerance-level distance of the plain
+    run."""
+    from paper_2301_04698_amd import les
+    base = li.workload("C1m", nx=40, ny=24, nz=32, precision="fp32", poisson_tol=1e-5,
+                       poisson_scheme="chebyshev")
+    out = {}
+    for g, passes in (("zero", 0), ("learned", 2)):
+        p = dict(base, guess=g, guess_passes=passes)
+        sim = les.LES(p, li.initial_state(p))
+        if g == "learned":
+            gpu.bind(sim, _t(params(17, bias=0.0)) * 0.1, alpha=0.1)
+        rc, stats, recs = sim.step(5, records=True)
+        assert stats["not_converged"] == 0
+        for r in recs:
+            assert r["res_norm"] <= p["poisson_tol"] * r["rhs_norm"]
+        out[g] = sim.state_numpy()
+    for k in ("u", "v", "w", "thl", "qt", "p"):
+        d = out["zero"][k] - out["zero"][k].mean(axis=(1, 2), keepdims=True)
+        assert np.linalg.norm(out["learned"][k] - out["zero"][k]) <= 1e-3 * np.linalg.norm(d)
+
+
 def test_learned_step_converges(gpu):
     """A learned-guess run (random network) still stops every solve at the
     tolerance and stays within tolerance-level distance of the plain run."""

@@ -181,12 +181,18 @@ typedef struct les_solve_stats {
                          ran from the zero start), or its returned iterate
                          missed the tolerance, and the sweeps were repeated
                          from the zero start (sweeps and seconds count both
-                         passes); les_poisson_solve: opts->use_guess.
+                         passes), 4 its kept guess's sweeps met the test but
+                         the returned iterate missed the tolerance, and the
+                         solve continued once from that iterate as a new
+                         guess (under the same budget, with none under the
+                         first pass's count; should that miss again, it is
+                         repeated from the zero start: 3);
+                         les_poisson_solve: opts->use_guess.
                          "Zero start": phi = 0, or the exact uniform parts
                          (LES_MEAN_LEVEL, LES_MEAN_EXACT).  For a kept guess
                          res_norm is the residual of the returned iterate
                          (guess plus correction, as stored) */
-  int32_t guess_sweeps; /* guess 3: the sweeps of the dropped guess's pass */
+  int32_t guess_sweeps; /* guess 3 and 4: the sweeps before the last pass */
 } les_solve_stats;
 
 typedef struct les_poisson_opts {

@@ -1,6 +1,8 @@
 // Per-cell moist thermodynamics (paper Sec. 2.1-2.2) and the radiative
 // flux column (Sec. 2.1, theta_l equation).  The saturation adjustment
 // always iterates in FP64, whatever the storage precision.
+#include <algorithm>
+
 #include "les.h"
 #include "les_device.h"
 
@@ -128,10 +130,12 @@ __global__ __launch_bounds__(kBlock) void thermo_kernel(Grid g, Thermo c, Profil
   if (Tout) Tout[q] = (T)s.T;
 }
 
-// One thread per (i, j) column, marching down from the lid: net upward
-// flux F(z_f) = F0 exp(-kappa * sum_{cells above} rho0 q_l dz) and the
-// heating -(c_pm Pi)^{-1} dF/dz of each cell.  Consecutive threads take
-// consecutive x, so every level is a coalesced row access.
+// Net upward flux F(z_f) = F0 exp(-kappa * sum_{cells above} rho0 q_l dz)
+// and the heating -(c_pm Pi)^{-1} dF/dz of each cell, two launch forms.
+//
+// Many columns: one thread per (i, j) column marching down from the lid;
+// consecutive threads take consecutive x, so every level is a coalesced row
+// access.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void radiation_kernel(Grid g, Profiles<T> P, double F0,
                                                            double kappa, const T *__restrict__ ql,
@@ -148,6 +152,72 @@ __global__ __launch_bounds__(kBlock) void radiation_kernel(Grid g, Profiles<T> P
     out[q] = (T)(-(f_above - f_below) / (g.dz * (double)cpmpi[q]));
     f_above = f_below;
   }
+}
+
+// Few columns (too few threads to hide the march's latency): a block owns
+// the columns of one 64-wide x segment of a y row and its nw waves split
+// their levels into chunks (wave w below wave w + 1).  Each wave sums the
+// path of its chunk, the sums cross through LDS, and each wave then marches
+// its chunk down from the path of the chunks above it; the top kRadRegs
+// levels of a chunk stay in registers between the two passes, the rest are
+// read again.
+constexpr int kRadMaxWaves = 16, kRadRegs = 16;
+
+// Below 4096 row segments (16 waves per CU marching whole columns) the
+// chunked form, with chunks of about kRadRegs levels.
+inline int rad_waves(const Grid &g) {
+  const int64_t segs = (int64_t)((g.nx + 63) / 64) * g.ny;
+  if (segs >= 4096) return 1;
+  return std::min(kRadMaxWaves, std::max(1, (g.nz + kRadRegs - 1) / kRadRegs));
+}
+
+template <typename T>
+__global__ __launch_bounds__(64 * kRadMaxWaves) void radiation_chunk_kernel(
+    Grid g, Profiles<T> P, double F0, double kappa, const T *__restrict__ ql,
+    const T *__restrict__ cpmpi, T *__restrict__ out) {
+  __shared__ double part[kRadMaxWaves][64];
+  const int lane = (int)(threadIdx.x & 63);
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int nw = (int)(blockDim.x >> 6);
+  const int ntx = (g.nx + 63) / 64;
+  const int tx = (int)(blockIdx.x % (unsigned)ntx);
+  const int j = (int)(blockIdx.x / (unsigned)ntx);
+  const int i = tx * 64 + lane;
+  const bool active = i < g.nx;
+  const int64_t col = (int64_t)(active ? i : g.nx - 1) + (int64_t)g.nx * j;
+  const int len = (g.nz + nw - 1) / nw;
+  const int k0 = min(g.nz, w * len), k1 = min(g.nz, k0 + len);
+  const int n = k1 - k0;  // levels k1 - 1 - t, t = 0 .. n - 1, top down
+  T v[kRadRegs];
+  double sum = 0.0;
+#pragma unroll
+  for (int t = 0; t < kRadRegs; ++t) {
+    if (t < n) {
+      const int k = k1 - 1 - t;
+      v[t] = ql[col + g.nxy * k];
+      sum += P.rho0[k] * (double)v[t] * g.dz;
+    }
+  }
+  for (int t = kRadRegs; t < n; ++t) {
+    const int k = k1 - 1 - t;
+    sum += P.rho0[k] * (double)ql[col + g.nxy * k] * g.dz;
+  }
+  part[w][lane] = sum;
+  __syncthreads();
+  double path = 0.0;
+  for (int u = nw - 1; u > w; --u) path += part[u][lane];
+  double f_above = F0 * exp(-kappa * path);
+  auto level = [&](int k, T q_l) __attribute__((always_inline)) {
+    const int64_t q = col + g.nxy * k;
+    path += P.rho0[k] * (double)q_l * g.dz;
+    const double f_below = F0 * exp(-kappa * path);
+    if (active) out[q] = (T)(-(f_above - f_below) / (g.dz * (double)cpmpi[q]));
+    f_above = f_below;
+  };
+#pragma unroll
+  for (int t = 0; t < kRadRegs; ++t)
+    if (t < n) level(k1 - 1 - t, v[t]);
+  for (int t = kRadRegs; t < n; ++t) level(k1 - 1 - t, ql[col + g.nxy * (k1 - 1 - t)]);
 }
 
 template <typename T>
@@ -182,7 +252,13 @@ void launch_thermo(const Grid &g, const Thermo &c, const Profiles<T> &P, const T
 template <typename T>
 void launch_radiation(const Grid &g, const Profiles<T> &P, double F0, double kappa, const T *ql,
                       const T *cpmpi, T *out, hipStream_t s) {
-  radiation_kernel<T><<<blocks_for(g.nxy), kBlock, 0, s>>>(g, P, F0, kappa, ql, cpmpi, out);
+  const int nw = rad_waves(g);
+  if (nw == 1) {
+    radiation_kernel<T><<<blocks_for(g.nxy), kBlock, 0, s>>>(g, P, F0, kappa, ql, cpmpi, out);
+  } else {
+    const unsigned segs = (unsigned)(((g.nx + 63) / 64) * (int64_t)g.ny);
+    radiation_chunk_kernel<T><<<segs, 64 * nw, 0, s>>>(g, P, F0, kappa, ql, cpmpi, out);
+  }
 }
 
 template <typename T>

@@ -59,6 +59,29 @@ def test_full_size_step_matches_oracle(les, oracle_lib):
         assert e <= 1e-5, (k, e)
 
 
+def test_many_columns_step_matches_oracle(les, oracle_lib):
+    """A grid of 2049 rows of two 64-wide x segments (the second one column):
+    4098 row segments, so the radiative flux takes its one-thread-per-column
+    form (the chunked form below 4096); cloud in the upper levels.  One FP64
+    step, all physics, 20 sweeps per solve on both sides."""
+    p = li.workload("C1m", nx=65, ny=2049, nz=5, dz=200.0, poisson_scheme="chebyshev")
+    st0 = li.initial_state(p)
+    assert oracle_lib.thermo(p, st0["thl"], st0["qt"])["ql"].max() > 1e-4
+    rng = np.random.default_rng(5)
+    for k in ("u", "v", "w"):
+        st0[k] = st0[k] + 0.3 * rng.standard_normal(st0[k].shape)
+    replay = [20] * p["n_subiter"]
+    ost = {k: v.copy() for k, v in st0.items()}
+    oracle_lib.step(p, ost, nsteps=1, replay=replay)
+    sim = les.LES(p, st0)
+    sim.step(1, replay=replay)
+    gst = sim.state_numpy()
+    errs = {k: rel(gst[k], ost[k]) for k in FIELDS}
+    print("many-column step rel errors", errs)
+    for k, e in errs.items():
+        assert e <= 1e-11, (k, e)
+
+
 def test_full_size_sweeps_match_oracle(les, oracle_lib):
     import torch
     p = c2()

@@ -397,6 +397,24 @@ def test_step_column_kernel_shapes_match_oracle(gpu, oracle_lib, shape, advectio
         assert e <= 1e-11, (k, e, errs)
 
 
+@pytest.mark.parametrize("shape,dz", [
+    ((300, 2, 5), 25.0),  # 16 waves of 19 levels: the levels past the 16 held in registers read again
+    ((17, 3, 70), 50.0),  # two waves of 9 and 8 levels; a ragged second x segment
+])
+def test_step_radiation_columns_match_oracle(gpu, oracle_lib, shape, dz):
+    """The radiative flux column (path sums per z chunk exchanged between the
+    waves of a block, then each chunk marched from the path above it) on
+    tall and short columns with a cloud layer: two FP64 steps."""
+    nz, ny, nx = shape
+    p = li.workload("C1m", nx=nx, ny=ny, nz=nz, dz=dz, poisson_tol=1e-9,
+                    poisson_scheme="chebyshev")
+    st0 = with_velocity_noise(p, li.initial_state(p), 0.3, 17)
+    assert oracle_lib.thermo(p, st0["thl"], st0["qt"])["ql"].max() > 1e-4  # a cloud to absorb
+    errs, *_ = _compare_step(gpu, oracle_lib, p, st0, 2, 1e-11)
+    for k, e in errs.items():
+        assert e <= 1e-11, (k, e, errs)
+
+
 def test_step_c1_fp64_ten_steps(gpu, oracle_lib):
     """The configuration of the small parity case: 32^3, dt 0.5 s, tol 1e-8,
     fixed-weight Jacobi, 10 steps."""

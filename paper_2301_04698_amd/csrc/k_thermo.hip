@@ -60,17 +60,23 @@ __device__ __forceinline__ double exner(const Thermo &c, double lnp, double qt, 
   return exp(r_moist(c, qt, ql, qi) / cp_moist(c, qt, ql, qi) * lnp);
 }
 
-// theta_l*(T) - theta_l at saturation partition.
-__device__ __forceinline__ double thl_residual(const Thermo &c, double T, double thl, double qt,
-                                               double p0, double lnp) {
+// theta_l*(T) - theta_l at saturation partition (f), with that partition
+// and its Exner function.
+struct ThlResidual {
+  double f, pi;
+  Phase ph;
+};
+__device__ __forceinline__ ThlResidual thl_residual(const Thermo &c, double T, double thl,
+                                                    double qt, double p0, double lnp) {
   const Phase ph = partition(c, T, qt, p0);
   const double cpm = cp_moist(c, qt, ph.ql, ph.qi);
   const double pi = exner(c, lnp, qt, ph.ql, ph.qi);
-  return T / pi * (1.0 - (c.Lv0 * ph.ql + c.Ls0 * ph.qi) / (cpm * T)) - thl;
+  return ThlResidual{T / pi * (1.0 - (c.Lv0 * ph.ql + c.Ls0 * ph.qi) / (cpm * T)) - thl, pi, ph};
 }
 
+// The adjusted state and the Exner function of its partition.
 struct CellState {
-  double T, ql, qi;
+  double T, ql, qi, pi;
 };
 
 // Saturation adjustment by the secant method (Sec. 2.2).  Unsaturated test
@@ -78,23 +84,23 @@ struct CellState {
 // stopping at |dT| <= tol, equal residuals or the iteration cap.
 __device__ CellState saturation_adjust(const Thermo &c, double thl, double qt, double p0,
                                        double lnp) {
-  const double tu = thl * exner(c, lnp, qt, 0.0, 0.0);
+  const double pu = exner(c, lnp, qt, 0.0, 0.0);
+  const double tu = thl * pu;
   const double qs = qstar(c, liquid_fraction(c, tu), tu, p0);
-  if (qt <= qs) return CellState{tu, 0.0, 0.0};
+  if (qt <= qs) return CellState{tu, 0.0, 0.0, pu};
   double ta = tu, tb = tu + c.Lv0 * (qt - qs) / c.cpd;
-  double fa = thl_residual(c, ta, thl, qt, p0, lnp);
-  double fb = thl_residual(c, tb, thl, qt, p0, lnp);
+  double fa = thl_residual(c, ta, thl, qt, p0, lnp).f;
+  ThlResidual rb = thl_residual(c, tb, thl, qt, p0, lnp);  // always that of the last tb
   for (int it = 0; it < c.satadj_maxit; ++it) {
-    if (fb == fa) break;
-    const double tn = tb - fb * (tb - ta) / (fb - fa);
+    if (rb.f == fa) break;
+    const double tn = tb - rb.f * (tb - ta) / (rb.f - fa);
     ta = tb;
-    fa = fb;
+    fa = rb.f;
     tb = tn;
-    fb = thl_residual(c, tb, thl, qt, p0, lnp);
+    rb = thl_residual(c, tb, thl, qt, p0, lnp);
     if (fabs(tb - ta) <= c.satadj_tol) break;
   }
-  const Phase ph = partition(c, tb, qt, p0);
-  return CellState{tb, ph.ql, ph.qi};
+  return CellState{tb, rb.ph.ql, rb.ph.qi, rb.pi};
 }
 
 template <typename T>
@@ -126,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void thermo_kernel(Grid g, Thermo c, Profil
     b[q] = (T)(c.g * (alpha - a0) / a0);
   }
   if (ql) ql[q] = (T)s.ql;
-  if (cpmpi) cpmpi[q] = (T)(cp_moist(c, qtd, s.ql, s.qi) * exner(c, lnp, qtd, s.ql, s.qi));
+  if (cpmpi) cpmpi[q] = (T)(cp_moist(c, qtd, s.ql, s.qi) * s.pi);
   if (Tout) Tout[q] = (T)s.T;
 }
 

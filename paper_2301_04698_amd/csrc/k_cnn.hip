@@ -610,20 +610,14 @@ __global__ __launch_bounds__(256) void conv_out_kernel(CnnGeom G, const uint16_t
   if (!Tl.valid) return;  // the whole block
   const uint16_t *w3 = wbf + cnn_weight_offset(G.inputs, 3);
 
-  // weights of phase f = q mod 3: column j = row < 3 holds W3[9 (dz + 1) +
-  // t][8 half .. + 7], t = 2 m + side, dz = +1, 0, -1 for (f - j) mod 3 =
-  // 1, 0, 2
-  bf16x8 wb[3][kCnnPairs];
+  // weights: column j = row < 3 holds W3[9 j + t][8 half .. + 7] (dz = j -
+  // 1), t = 2 m + side; the other columns are zero
+  bf16x8 wb[kCnnPairs];
   uint32_t poff[kCnnPairs];
 #pragma unroll
   for (int m = 0; m < kCnnPairs; ++m) {
     const int t = 2 * m + side;
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-      const int d = (f - row + 3) % 3;
-      const int z = d == 0 ? 1 : (d == 1 ? 2 : 0);  // dz + 1
-      wb[f][m] = row < 3 && t < 9 ? load_w8(w3 + (9 * z + t) * kCnnCh + 8 * half) : bf16x8{};
-    }
+    wb[m] = row < 3 && t < 9 ? load_w8(w3 + (9 * row + t) * kCnnCh + 8 * half) : bf16x8{};
     poff[m] = pair_offset(wv, row, side, half, m);
   }
   const float b3 = params[cnn_bias_offset(G.inputs, 3)];
@@ -652,11 +646,15 @@ __global__ __launch_bounds__(256) void conv_out_kernel(CnnGeom G, const uint16_t
   fetch(Tl.k0);
   __syncthreads();
 
+  // Column j of the accumulators holds level p + 1 - j while plane p is
+  // applied: plane p adds its dz = j - 1 taps to column j, then level p - 1
+  // (column 2) is emitted and every column moves one to the right (lane l
+  // takes lane l - 1 of its 16-lane row, column 0 starts from zero), so
+  // each level collects its three planes in order with one weight set.
   floatx4 acc[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
-  auto plane = [&](auto phase, int p) __attribute__((always_inline)) {
-    constexpr int F = decltype(phase)::value;
+  auto plane = [&](int p) __attribute__((always_inline)) {
     const unsigned char *cur = lds[(p - Tl.k0 + 1) & 1];
     // the lane's output cell of level p - 1 (finished by this plane); its
     // base value is loaded before the products
@@ -671,22 +669,24 @@ __global__ __launch_bounds__(256) void conv_out_kernel(CnnGeom G, const uint16_t
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const bf16x8 a = *(const bf16x8 *)(cur + poff[m] + c * 16 * kCnnCellB);
-        acc[c] = mfma32(a, wb[F][m], acc[c]);
+        acc[c] = mfma32(a, wb[m], acc[c]);
       }
     if (p < Tl.k1) {
       store(lds[(p - Tl.k0) & 1]);
       if (p + 1 < Tl.k1) fetch(p + 2);
     }
-    // level p - 1 (column J) through the wave's LDS row, so that lane l
+    // level p - 1 (column 2) through the wave's LDS row, so that lane l
     // writes cell ox0 + l (LDS operations of one wave complete in order)
-    constexpr int J = (F + 2) % 3;
-    if (row == J) {
+    if (row == 2) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        *(floatx4 *)&res[wv][16 * c + 4 * quad] = acc[c];
-        acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
-      }
+      for (int c = 0; c < 4; ++c) *(floatx4 *)&res[wv][16 * c + 4 * quad] = acc[c];
     }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)  // DPP row_shr:1, zero into lane 0 of each row
+        acc[c][r] = __int_as_float(
+            __builtin_amdgcn_update_dpp(0, __float_as_int(acc[c][r]), 0x111, 0xF, 0xF, true));
     __builtin_amdgcn_wave_barrier();
     if (emit) {
       const float out = res[wv][lane] + b3;
@@ -697,14 +697,7 @@ __global__ __launch_bounds__(256) void conv_out_kernel(CnnGeom G, const uint16_t
     }
     __syncthreads();
   };
-  for (int p = Tl.k0 - 1;; p += 3) {
-    plane(std::integral_constant<int, 0>{}, p);
-    if (p + 1 > Tl.k1) break;
-    plane(std::integral_constant<int, 1>{}, p + 1);
-    if (p + 2 > Tl.k1) break;
-    plane(std::integral_constant<int, 2>{}, p + 2);
-    if (p + 3 > Tl.k1) break;
-  }
+  for (int p = Tl.k0 - 1; p <= Tl.k1; ++p) plane(p);
 }
 
 // ---------------------------------------------------------------- loss

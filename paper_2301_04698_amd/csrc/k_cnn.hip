@@ -243,13 +243,15 @@ __device__ __forceinline__ int64_t plane_base(const CnnGeom &G, int b, int kk) {
 // runs inside the block.  Each plane of layer 0's output is computed on
 // the tile plus its ring (bias, leaky ReLU, bfloat16) straight into the
 // LDS slot that layer 1 reads, from the network input: the FP32 residual r
-// times *in_scale, rounded to bfloat16 as the separate input pass does,
-// three planes of the tile plus a two-cell ring staged in LDS.  Layer 0's
-// activations never reach HBM.
+// times *in_scale, rounded to bfloat16 as the separate input pass does.
+// The input levels (the tile plus a two-cell ring) are staged once each in
+// a four-slot LDS ring: layer-0 plane P reads levels c - 1, c, c + 1 of c =
+// P clamped to the grid (each again clamped; virtual level u sits in slot
+// (u + 4) mod 4), and each plane step stages the one level the next plane
+// adds.  Layer 0's activations never reach HBM.
 constexpr int kInPX = kCnnPX + 2, kInPY = kCnnPY + 2;
-constexpr int kInPlane = kInPX * kInPY;        // input cells per plane
-constexpr int kInSet = 3 * kInPlane;           // the three planes of one layer-0 plane
-constexpr int kInLoads = (kInSet + 255) / 256;  // per thread
+constexpr int kInPlane = kInPX * kInPY;           // input cells per plane
+constexpr int kInLoads = (kInPlane + 255) / 256;  // per thread and level
 constexpr int kL0Chains = (kCnnPlane + 15) / 16;
 
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
@@ -262,9 +264,9 @@ __global__ __launch_bounds__(256, 2) void conv_mid_kernel(
     const uint16_t *__restrict__ w, float alpha, uint16_t *__restrict__ aout, int tiles_x,
     int tiles_y, int chunks) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[2][kCnnPlane * kCnnCellB];
-  // fused: the staged input set, one bfloat16 value per 32-bit word so that
-  // every operand read is an aligned word
-  __shared__ uint32_t inp[FUSED ? 2 : 1][FUSED ? kInSet : 1];
+  // fused: the ring of staged input levels, one bfloat16 value per 32-bit
+  // word so that every operand read is an aligned word
+  __shared__ uint32_t inr[FUSED ? 4 : 1][FUSED ? kInPlane : 1];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int row = lane & 15, quad = lane >> 4, side = quad >> 1, half = quad & 1;
   const CnnTile T = cnn_tile(G, tiles_x, tiles_y, chunks);
@@ -294,9 +296,8 @@ __global__ __launch_bounds__(256, 2) void conv_mid_kernel(
   // stored), then stored to a slot
   int32_t src[FUSED ? 1 : kPlaneLoads];
   u32x4 pre[FUSED ? 1 : kPlaneLoads];
-  // (b) fused layer 0: the input set of layer-0 plane P (levels L - 1, L,
-  // L + 1 of L = P, each mirror-clamped) fetched one set ahead as FP32
-  // (set element e = plane d * kInPlane + cell), rounded when stored
+  // (b) fused layer 0: the one input level a plane step adds to the ring,
+  // fetched a step ahead as FP32 and rounded when stored
   int32_t gof[FUSED ? kInLoads : 1];
   float rpre[FUSED ? kInLoads : 1];
   bf16x8 w0a[2];
@@ -305,8 +306,8 @@ __global__ __launch_bounds__(256, 2) void conv_mid_kernel(
   if constexpr (FUSED) {
 #pragma unroll
     for (int u = 0; u < kInLoads; ++u) {
-      const int e = min((int)threadIdx.x + 256 * u, kInSet - 1);
-      const int cell = e % kInPlane, iy = cell / kInPX, ix = cell - iy * kInPX;
+      const int cell = min((int)threadIdx.x + 256 * u, kInPlane - 1);
+      const int iy = cell / kInPX, ix = cell - iy * kInPX;
       const int jj = pwrap(T.oy0 - 2 + iy, G.nyi), ii = pwrap(T.ox0 - 2 + ix, G.nxi);
       gof[u] = jj * G.nxi + ii;
     }
@@ -329,34 +330,33 @@ __global__ __launch_bounds__(256, 2) void conv_mid_kernel(
     plane_sources(G, T, src);
   }
   const int64_t in_plane = (int64_t)G.nyi * G.nxi;
-  auto fetch_set = [&](int P) __attribute__((always_inline)) {
-    const int L = P < 0 ? 0 : (P >= G.nz ? G.nz - 1 : P);
+  auto clampz = [&](int P) { return P < 0 ? 0 : (P >= G.nz ? G.nz - 1 : P); };
+  // virtual input level u (content: level u clamped) into registers, then
+  // into ring slot (u + 4) mod 4
+  auto fetch_level = [&](int u) __attribute__((always_inline)) {
+    const int64_t base = ((int64_t)T.b * G.nz + clampz(u)) * in_plane;
 #pragma unroll
-    for (int u = 0; u < kInLoads; ++u) {
-      const int e = min((int)threadIdx.x + 256 * u, kInSet - 1);
-      int lev = L + e / kInPlane - 1;
-      lev = lev < 0 ? 0 : (lev >= G.nz ? G.nz - 1 : lev);
-      rpre[u] = rin[((int64_t)T.b * G.nz + lev) * in_plane + gof[u]];
+    for (int i = 0; i < kInLoads; ++i) rpre[i] = rin[base + gof[i]];
+  };
+  auto store_level = [&](int u) __attribute__((always_inline)) {
+    uint32_t *dst = inr[(u + 4) & 3];
+#pragma unroll
+    for (int i = 0; i < kInLoads; ++i) {
+      const int e = (int)threadIdx.x + 256 * i;
+      if (e < kInPlane) dst[e] = f2bf((float)((double)rpre[i] * scale));
     }
   };
-  auto store_set = [&](uint32_t *dst) __attribute__((always_inline)) {
-#pragma unroll
-    for (int u = 0; u < kInLoads; ++u) {
-      const int e = (int)threadIdx.x + 256 * u;
-      if (e < kInSet) dst[e] = f2bf((float)((double)rpre[u] * scale));
-    }
-  };
-  // chain k of layer-0 plane P (input set in LDS) into slot(P): wave w
-  // takes the 16-cell chains w + 4 k, k = 0..6, of the tile-plus-ring plane
-  // (k = 6 only for wave 0: 25 chains)
+  // chain k of layer-0 plane P (its three input levels in the ring) into
+  // slot(P): wave w takes the 16-cell chains w + 4 k, k = 0..6, of the
+  // tile-plus-ring plane (k = 6 only for wave 0: 25 chains)
   auto layer0_chain = [&](int k, int P) __attribute__((always_inline)) {
-    const uint32_t *in = inp[slot(P)];
+    const uint32_t *in = inr[(clampz(P) - 1 + min(quad, 2) + 4) & 3];
     unsigned char *dst = lds[slot(P)];
     {
       const int ch = wv + 4 * k;
       const int cell = ch * 16 + row, cc = min(cell, kCnnPlane - 1);
       const int ay = cc / kCnnPX, ax = cc - ay * kCnnPX;
-      const uint32_t *pl = in + min(quad, 2) * kInPlane + (ay + 1) * kInPX + ax + 1;
+      const uint32_t *pl = in + (ay + 1) * kInPX + ax + 1;
       u16x8 v0, v1 = {};
 #pragma unroll
       for (int e = 0; e < 8; ++e) v0[e] = (uint16_t)pl[(e / 3 - 1) * kInPX + (e % 3 - 1)];
@@ -392,12 +392,15 @@ __global__ __launch_bounds__(256, 2) void conv_mid_kernel(
   };
   // plane P into slot(P) (all waves finished reading that slot before the
   // last barrier); the one after it prepared.  Fused: layer 0 of plane P
-  // itself runs among the products of the plane before.
+  // itself runs among the products of the plane before; here the level
+  // that layer-0 plane P + 1 adds to the ring (read in the next step) is
+  // stored, into the slot of the level two below the ones read in this
+  // step, and the level plane P + 2 adds is fetched.
   auto produce = [&](int P) __attribute__((always_inline)) {
     if constexpr (FUSED) {
       if (P + 1 <= T.k1) {
-        store_set(inp[slot(P + 1)]);
-        if (P + 2 <= T.k1) fetch_set(P + 2);
+        if (clampz(P + 1) > clampz(P)) store_level(clampz(P + 1) + 1);
+        if (P + 2 <= T.k1 && clampz(P + 2) > clampz(P + 1)) fetch_level(clampz(P + 2) + 1);
       }
     } else {
       store(lds[slot(P)]);
@@ -405,11 +408,13 @@ __global__ __launch_bounds__(256, 2) void conv_mid_kernel(
     }
   };
   if constexpr (FUSED) {
-    fetch_set(T.k0 - 1);
-    store_set(inp[slot(T.k0 - 1)]);
-    fetch_set(T.k0);
-    store_set(inp[slot(T.k0)]);
-    fetch_set(T.k0 + 1);
+    // the levels of layer-0 planes k0 - 1 and k0; the one plane k0 + 1 adds
+    const int c0 = clampz(T.k0 - 1);
+    for (int u = c0 - 1; u <= clampz(T.k0) + 1; ++u) {
+      fetch_level(u);
+      store_level(u);
+    }
+    if (T.k0 + 1 <= T.k1 && clampz(T.k0 + 1) > clampz(T.k0)) fetch_level(clampz(T.k0 + 1) + 1);
     __syncthreads();
     layer0(T.k0 - 1);
   } else {

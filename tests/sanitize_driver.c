@@ -1,6 +1,7 @@
 /* Standalone driver of the FP64 oracle for a host sanitizer build
  * (AddressSanitizer and UndefinedBehaviorSanitizer): time steps of the LES
- * oracle and a forward, loss and backward pass of the guess network, on
+ * oracle, the diagnostics of the final state, and a forward, loss and
+ * backward pass of the guess network, on
  * inputs and sizes read from a file, results written to another.  Built and
  * run by tests/test_oracle_sanitizers.py; the oracle is test
  * infrastructure and so is this program.
@@ -10,6 +11,7 @@
  *   ocnn_dims; params; x (batch C nz ny nx); target (batch nz ny_out nx_out)
  * Output:
  *   u, v, w, thl, qt, p; nsteps * n_subiter osolve records;
+ *   6 diagnostic scalars and 9 x nz profiles of the final state;
  *   out (batch nz ny_out nx_out); loss; grad (params). */
 #include <stdio.h>
 #include <stdlib.h>
@@ -64,6 +66,15 @@ int main(int argc, char **argv) {
     return 11;
   }
 
+  /* diagnostics of the final state */
+  double scalars[6];
+  double *profiles = alloc_doubles((size_t)9 * c.nz);
+  if (!profiles) return 19;
+  if ((rc = oracle_diagnostics(&c, f[0], f[1], f[2], f[3], f[4], scalars, profiles))) {
+    fprintf(stderr, "oracle_diagnostics failed (%d)\n", rc);
+    return 20;
+  }
+
   /* the network: forward with the activations kept, loss, backward */
   double *acts[OCNN_LAYERS], *pre[OCNN_LAYERS] = {NULL, NULL, NULL, NULL};
   for (int l = 0; l < OCNN_LAYERS; ++l) {
@@ -98,6 +109,8 @@ int main(int argc, char **argv) {
   int ok = 1;
   for (int k = 0; k < 6; ++k) ok = ok && write_all(o, f[k], n * sizeof(double));
   ok = ok && write_all(o, rec, nsolve * sizeof(osolve));
+  ok = ok && write_all(o, scalars, sizeof scalars);
+  ok = ok && write_all(o, profiles, (size_t)9 * c.nz * sizeof(double));
   ok = ok && write_all(o, out, n_out * sizeof(double));
   ok = ok && write_all(o, &loss, sizeof loss);
   ok = ok && write_all(o, grad, (size_t)np * sizeof(double));
@@ -108,6 +121,6 @@ int main(int argc, char **argv) {
     free(acts[l]);
     free(pre[l]);
   }
-  free(params); free(x); free(target); free(rec); free(out); free(gy); free(grad);
+  free(params); free(x); free(target); free(rec); free(out); free(gy); free(grad); free(profiles);
   return 0;
 }

@@ -4,9 +4,9 @@ standalone driver (tests/sanitize_driver.c) compiled with AddressSanitizer
 The driver runs full-physics time steps (two configurations: warm cloud with
 QUICK, no-slip walls, the exact mean modes and the previous-solution guess;
 mixed-phase ice with WENO3, free slip, the level mode and the extrapolated
-guess) and a forward, loss and backward pass of the guess network (one- and
-three-input, valid and periodic padding); the results must equal those of
-the ordinary build."""
+guess), the diagnostics of the final state, and a forward, loss and backward
+pass of the guess network (one- and three-input, valid and periodic
+padding); the results must equal those of the ordinary build."""
 import os
 import shutil
 import subprocess
@@ -72,13 +72,15 @@ def _run(driver, p, st, nsteps, params, x, target, periodic, alpha=0.1):
     rb = C.sizeof(oracle.OSolve) * nrec
     recs = (oracle.OSolve * nrec).from_buffer_copy(raw[off: off + rb].tobytes())
     off += rb
+    diag = raw[off: off + 8 * (6 + 9 * p["nz"])].view(np.float64)
+    off += 8 * (6 + 9 * p["nz"])
     m = target.size
     y = raw[off: off + 8 * m].view(np.float64).reshape(target.shape)
     off += 8 * m
     loss = float(raw[off: off + 8].view(np.float64)[0])
     off += 8
     grad = raw[off:].view(np.float64)
-    return out, [(r.sweeps, r.status, r.guess) for r in recs], y, loss, grad
+    return out, [(r.sweeps, r.status, r.guess) for r in recs], diag, y, loss, grad
 
 
 CASES = [
@@ -105,13 +107,18 @@ def test_sanitized_oracle_equals_ordinary_build(driver, case, inputs, periodic, 
     ys, xs = cnn.layer_size(xshape[-2], xshape[-1], cnn.LAYERS, periodic)
     target = rng.standard_normal((xshape[0], xshape[-3], ys, xs))
 
-    got, grecs, y, loss, grad = _run(driver, p, st0, 2, params, x, target, periodic)
+    got, grecs, diag, y, loss, grad = _run(driver, p, st0, 2, params, x, target, periodic)
 
     ref = {k: v.copy() for k, v in st0.items()}
     recs, _ = oracle.step(p, ref, nsteps=2)
     assert grecs == [(r["sweeps"], r["status"], r["guess"]) for r in recs]
     for k in FIELDS:
         assert np.array_equal(got[k], ref[k]), k
+    d = oracle.diagnostics(p, ref)
+    want = [d[k] for k in ("mass_thl", "mass_qt", "div_l2", "div_max", "cfl", "ke")]
+    assert np.array_equal(diag[:6], np.array(want))
+    prof = np.stack([d["profiles"][k] for k in ("thl", "qt", "ql", "u", "v", "w", "w2", "w3", "b")])
+    assert np.array_equal(diag[6:].reshape(9, p["nz"]), prof)
     out, acts, pre = cnn.forward(params, x, periodic=periodic)
     l_ref, gy = cnn.loss(out, target, p["dx"], p["dy"], p["dz"])
     g_ref = cnn.backward(params, x, acts, pre, gy, periodic=periodic)
